@@ -1,0 +1,70 @@
+"""Seeded synthetic workloads shared by the tests, the smoke check and the
+benchmark.  This module only draws random numbers: it holds none of the
+method's arithmetic.
+
+The paper measures only synthetic distributions (uniform points in the unit
+box, points on a sphere or circle), so no dataset is involved.  Each recipe
+below is a fixed draw order from ``numpy.random.default_rng(seed)``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform_cube(n: int, seed: int):
+    """Points uniform in [0,1]^3, charges uniform in [-1,1]."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 3))
+    q = rng.uniform(-1.0, 1.0, n)
+    return pts, q
+
+
+def sphere_and_blobs(n: int, seed: int, frac_sphere: float = 0.7, nblobs: int = 3,
+                     sigma: float = 1e-3):
+    """Clustered 3-D set: a fraction on the unit sphere (normalised Gaussian
+    vectors), the rest split evenly over Gaussian blobs of width sigma whose
+    centres are uniform in [-1/2,1/2]^3; shuffled into a random input order;
+    charges uniform in [-1,1]."""
+    rng = np.random.default_rng(seed)
+    ns = int(round(frac_sphere * n))
+    g = rng.standard_normal((ns, 3))
+    sph = g / np.linalg.norm(g, axis=1)[:, None]
+    nb = n - ns
+    centres = rng.uniform(-0.5, 0.5, (nblobs, 3))
+    counts = np.full(nblobs, nb // nblobs)
+    counts[: nb - counts.sum()] += 1
+    blobs = np.concatenate([centres[k] + sigma * rng.standard_normal((counts[k], 3))
+                            for k in range(nblobs)]) if nb else np.zeros((0, 3))
+    pts = np.concatenate([sph, blobs])
+    pts = pts[rng.permutation(n)]
+    q = rng.uniform(-1.0, 1.0, n)
+    return np.ascontiguousarray(pts), q
+
+
+def two_clusters_and_background(n: int, seed: int):
+    """Small adaptive case: two tight clusters plus a uniform background, so
+    the tree has coarse neighbours and non-adjacent fine boxes."""
+    rng = np.random.default_rng(seed)
+    n1 = n // 3
+    n2 = n // 3
+    n3 = n - n1 - n2
+    a = np.array([0.3, 0.3, 0.3]) + 2e-3 * rng.standard_normal((n1, 3))
+    b = np.array([0.62, 0.55, 0.71]) + 1e-2 * rng.standard_normal((n2, 3))
+    c = rng.random((n3, 3))
+    pts = np.concatenate([a, b, c])[rng.permutation(n)]
+    q = rng.uniform(-1.0, 1.0, n)
+    return np.ascontiguousarray(pts), q
+
+
+# Named workloads: (generator, N, seed, leaf capacity n_s).
+CONFIGS = {
+    "cfg1_uniform_2k": (uniform_cube, 2_000, 1, 50),
+    "cfg2_uniform_1m": (uniform_cube, 1_000_000, 2, 64),
+    "cfg3_clustered_10m": (sphere_and_blobs, 10_000_000, 3, 64),
+}
+
+
+def make(name: str, n: int | None = None):
+    gen, n0, seed, ns = CONFIGS[name]
+    pts, q = gen(n0 if n is None else n, seed)
+    return pts, q, ns

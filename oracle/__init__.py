@@ -1,0 +1,290 @@
+"""FP64 CPU oracle for the DMK point code (arXiv 2308.00292).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+leg of the benchmark use it; the product library never imports it.  The
+arithmetic lives in the C sources next to this file (``liboracle.so``); this
+module only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+
+
+def build() -> None:
+    """Compile liboracle.so with the Makefile beside this file."""
+    subprocess.run(["make", "-s", "-B", "-C", _HERE, "liboracle.so"], check=True)
+
+
+class Params(C.Structure):
+    _fields_ = [("tol", C.c_double), ("c", C.c_double), ("nf", C.c_int), ("p", C.c_int),
+                ("nw", C.c_int), ("hw", C.c_double)]
+
+
+_MAXTERM = 96
+_GLEXT = 256
+
+
+class Pswf(C.Structure):
+    _fields_ = [("c", C.c_double), ("nterm", C.c_int), ("coef", C.c_double * _MAXTERM),
+                ("chi", C.c_double), ("psi0", C.c_double), ("lambda0", C.c_double),
+                ("c0", C.c_double), ("c2", C.c_double),
+                ("glx", C.c_double * _GLEXT), ("glw", C.c_double * _GLEXT),
+                ("glpsi", C.c_double * _GLEXT)]
+
+
+_P = C.POINTER
+_i64p = _P(C.c_int64)
+_u64p = _P(C.c_uint64)
+_f64p = _P(C.c_double)
+_i32p = _P(C.c_int32)
+_u8p = _P(C.c_uint8)
+
+
+class _Tree(C.Structure):
+    _fields_ = [("dim", C.c_int), ("bits", C.c_int), ("ns", C.c_int), ("maxdepth", C.c_int),
+                ("n", C.c_int64), ("center", C.c_double * 3), ("side", C.c_double),
+                ("perm", _i64p), ("key", _u64p), ("xs", _f64p), ("nlevels", C.c_int),
+                ("level_start", _i64p), ("nbox", C.c_int64), ("level", _i32p), ("bkey", _u64p),
+                ("parent", _i64p), ("child0", _i64p), ("pstart", _i64p), ("pcount", _i64p),
+                ("leaf", _u8p), ("fout", _u8p), ("fin", _u8p), ("terminal", _u8p),
+                ("colleague", _i64p), ("ncoarse", _i32p), ("coarse", _i64p), ("tlevel", _i32p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("n", C.c_int64), ("u", _f64p), ("ufar", _f64p), ("ures", _f64p),
+                ("p", C.c_int), ("nf", C.c_int), ("proxy", _P(_f64p)), ("local", _P(_f64p))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            build()
+        L = C.CDLL(_LIBPATH)
+        L.orc_params_for.argtypes = [C.c_double, _P(Params)]
+        L.orc_pswf_init.argtypes = [C.c_double, _P(Pswf)]
+        for f in ("orc_pswf_eval", "orc_pswf_eval_ext", "orc_pswf_phi"):
+            getattr(L, f).argtypes = [_P(Pswf), C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.orc_split_w0.argtypes = [_P(Pswf), C.c_double]
+        L.orc_split_w0.restype = C.c_double
+        for f in ("orc_split_d", "orc_split_r", "orc_dhat"):
+            getattr(L, f).argtypes = [_P(Pswf), C.c_int, C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.orc_split_m0.argtypes = [_P(Pswf), C.c_int]
+        L.orc_split_m0.restype = C.c_double
+        L.orc_w0hat.argtypes = [_P(Pswf), C.c_double]
+        L.orc_w0hat.restype = C.c_double
+        L.orc_split_d_pw.argtypes = [_P(Pswf), _P(Params), C.c_int, _f64p]
+        L.orc_split_d_pw.restype = C.c_double
+        L.orc_split_w0_pw.argtypes = [_P(Pswf), _P(Params), _f64p]
+        L.orc_split_w0_pw.restype = C.c_double
+        L.orc_gauss_legendre.argtypes = [C.c_int, _f64p, _f64p]
+        L.orc_tree_build.argtypes = [C.c_int, C.c_int64, _f64p, C.c_int, C.c_int, _P(_Tree)]
+        L.orc_tree_free.argtypes = [_P(_Tree)]
+        L.orc_dmk_eval.argtypes = [_P(_Tree), _P(Params), _P(Pswf), _f64p, C.c_int, _P(_Result)]
+        L.orc_dmk_result_free.argtypes = [_P(_Tree), _P(_Result)]
+        L.orc_direct.argtypes = [C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
+        L.orc_dmk_run.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int, C.c_int, _f64p,
+                                  _f64p]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_f64p)
+
+
+def params_for(tol: float) -> Params:
+    pr = Params()
+    if lib().orc_params_for(tol, C.byref(pr)) != 0:
+        raise ValueError(f"unsupported tolerance {tol}")
+    return pr
+
+
+class PSWF:
+    """psi_0^c with its constants (c_0, c_2, lambda_0, psi(0))."""
+
+    def __init__(self, c: float):
+        self.s = Pswf()
+        lib().orc_pswf_init(c, C.byref(self.s))
+
+    def __getattr__(self, k):
+        if k in ("c", "nterm", "chi", "psi0", "lambda0", "c0", "c2"):
+            return getattr(self.s, k)
+        raise AttributeError(k)
+
+    def psi(self, x):
+        return lib().orc_pswf_eval_ext(C.byref(self.s), float(x))
+
+    def psi_series(self, x):
+        return lib().orc_pswf_eval(C.byref(self.s), float(x))
+
+    def phi(self, x):
+        return lib().orc_pswf_phi(C.byref(self.s), float(x))
+
+    def w0(self, r):
+        return lib().orc_split_w0(C.byref(self.s), float(r))
+
+    def d(self, l, r):
+        return lib().orc_split_d(C.byref(self.s), int(l), float(r))
+
+    def r(self, L, r):
+        return lib().orc_split_r(C.byref(self.s), int(L), float(r))
+
+    def m0(self, L):
+        return lib().orc_split_m0(C.byref(self.s), int(L))
+
+    def dhat(self, l, k):
+        return lib().orc_dhat(C.byref(self.s), int(l), float(k))
+
+    def w0hat(self, k):
+        return lib().orc_w0hat(C.byref(self.s), float(k))
+
+    def d_pw(self, params: Params, l, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_split_d_pw(C.byref(self.s), C.byref(params), int(l), _dp(x))
+
+    def w0_pw(self, params: Params, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_split_w0_pw(C.byref(self.s), C.byref(params), _dp(x))
+
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().orc_gauss_legendre(n, _dp(x), _dp(w))
+    return x, w
+
+
+class Tree:
+    """Level-restricted adaptive tree (copied out of the C structure)."""
+
+    def __init__(self, pts: np.ndarray, ns: int, maxdepth: int = 0):
+        pts = np.ascontiguousarray(pts, dtype=np.float64)
+        n, dim = pts.shape
+        self._t = _Tree()
+        rc = lib().orc_tree_build(dim, n, _dp(pts), ns, maxdepth, C.byref(self._t))
+        if rc != 0:
+            raise RuntimeError("orc_tree_build failed")
+        t = self._t
+        nb = t.nbox
+        ncol = 3 ** dim
+        nco = 2 ** dim - 1
+
+        def arr(ptr, cnt, dt):
+            if cnt == 0:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array(ptr, shape=(cnt,)).astype(dt, copy=True)
+
+        self.dim, self.n, self.ns, self.maxdepth = dim, n, ns, t.maxdepth
+        self.center = np.array(t.center[:dim])
+        self.side = t.side
+        self.perm = arr(t.perm, n, np.int64)
+        self.key = arr(t.key, n, np.uint64)
+        self.xs = arr(t.xs, n * dim, np.float64).reshape(n, dim)
+        self.nlevels = t.nlevels
+        self.level_start = arr(t.level_start, t.nlevels + 1, np.int64)
+        self.nbox = nb
+        self.level = arr(t.level, nb, np.int32)
+        self.bkey = arr(t.bkey, nb, np.uint64)
+        self.parent = arr(t.parent, nb, np.int64)
+        self.child0 = arr(t.child0, nb, np.int64)
+        self.pstart = arr(t.pstart, nb, np.int64)
+        self.pcount = arr(t.pcount, nb, np.int64)
+        self.leaf = arr(t.leaf, nb, np.uint8)
+        self.fout = arr(t.fout, nb, np.uint8)
+        self.fin = arr(t.fin, nb, np.uint8)
+        self.terminal = arr(t.terminal, nb, np.uint8)
+        self.colleague = arr(t.colleague, nb * ncol, np.int64).reshape(nb, ncol)
+        self.ncoarse = arr(t.ncoarse, nb, np.int32)
+        self.coarse = arr(t.coarse, nb * nco, np.int64).reshape(nb, nco)
+        self.tlevel = arr(t.tlevel, n, np.int32)
+
+    def __del__(self):
+        try:
+            lib().orc_tree_free(C.byref(self._t))
+        except Exception:
+            pass
+
+
+def dmk_eval(tree: Tree, params: Params, pswf: PSWF, charges: np.ndarray, keep: bool = False):
+    """Run Steps 2-5 on a built tree.  Returns a dict with the potential in
+    input order (u) and, in sorted order and normalised units, the far and
+    residual parts; with keep=True also the per-box proxies and local values."""
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    res = _Result()
+    rc = lib().orc_dmk_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), _dp(q),
+                            1 if keep else 0, C.byref(res))
+    if rc != 0:
+        raise RuntimeError("orc_dmk_eval failed")
+    n = tree.n
+    out = {}
+    if n:
+        out["u"] = np.ctypeslib.as_array(res.u, shape=(n,)).copy()
+        out["ufar"] = np.ctypeslib.as_array(res.ufar, shape=(n,)).copy()
+        out["ures"] = np.ctypeslib.as_array(res.ures, shape=(n,)).copy()
+    else:
+        out["u"] = np.zeros(0)
+        out["ufar"] = np.zeros(0)
+        out["ures"] = np.zeros(0)
+    if keep and n:
+        p3 = params.p ** 3
+        prox, loc = {}, {}
+        for b in range(tree.nbox):
+            if res.proxy[b]:
+                prox[b] = np.ctypeslib.as_array(res.proxy[b], shape=(p3,)).copy()
+            if res.local[b]:
+                loc[b] = np.ctypeslib.as_array(res.local[b], shape=(p3,)).copy()
+        out["proxy"] = prox
+        out["local"] = loc
+    lib().orc_dmk_result_free(C.byref(tree._t), C.byref(res))
+    return out
+
+
+def dmk(pts, charges, tol=1e-6, ns=50, maxdepth=0):
+    pr = params_for(tol)
+    ps = PSWF(pr.c)
+    tr = Tree(pts, ns, maxdepth)
+    return dmk_eval(tr, pr, ps, charges)["u"]
+
+
+def dmk_run(pts, charges, tol, ns, maxdepth=0):
+    """Whole pipeline in C; returns (u, plan_seconds, eval_seconds)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    n = pts.shape[0]
+    u = np.zeros(n)
+    tm = np.zeros(2)
+    rc = lib().orc_dmk_run(n, _dp(pts), _dp(q), tol, ns, maxdepth, _dp(u), _dp(tm))
+    if rc != 0:
+        raise RuntimeError(f"orc_dmk_run failed ({rc})")
+    return u, tm[0], tm[1]
+
+
+def direct(pts, charges, tidx=None):
+    """u_i = sum_{j != i, r > 0} q_j / (4 pi r_ij) at the listed targets."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    n = pts.shape[0]
+    if tidx is None:
+        tidx = np.arange(n, dtype=np.int64)
+    tidx = np.ascontiguousarray(tidx, dtype=np.int64)
+    out = np.zeros(len(tidx))
+    lib().orc_direct(n, _dp(pts), _dp(q), len(tidx), tidx.ctypes.data_as(_i64p), _dp(out))
+    return out
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

@@ -1,0 +1,153 @@
+/*
+ * oracle.h -- plain, slow FP64 CPU oracle for the DMK (dual-space multilevel
+ * kernel-splitting) point code of Jiang & Greengard, arXiv 2308.00292.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this code; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no source with the HIP path.
+ *
+ * Every routine follows a passage of the paper (cited by section, equation,
+ * lemma or table) and is written as plain loops in double precision:
+ *   - PSWF psi_0^c (Appendix "Prolate spheroidal wave functions of order
+ *     zero", eigenfunction of the operator F_c), its constants c_0, c_2,
+ *     lambda_0 and the cumulative window Phi (Sec. 3.7, "Optimization of kernel
+ *     splitting using prolate spheroidal wave functions").
+ *   - The kernel split 1/r = W_0 + sum_l D_l + R_L (Sec. 3.7, eq. newkernels)
+ *     and the plane-wave weights (eqs. differencekernelft3, windowedkernelft2,
+ *     wlmdef, with the trapezoidal factor h^d).
+ *   - The level-restricted adaptive tree, colleagues, coarse neighbours,
+ *     flags F_leaf/F_out/F_in (Sec. 3.3 and Sec. 3.6 "The full DMK algorithm
+ *     for discrete sources", Step 0).
+ *   - Steps 1-5 of that algorithm: proxies, upward pass, plane-wave outgoing
+ *     and incoming expansions, local expansions, direct residual sums,
+ *     self-interaction correction.
+ *   - Direct O(N M) summation with compensated accumulation (eq. laplacesum).
+ *
+ * Kernel: 3-D Laplace, K(r) = 1/(4 pi r).  Sources equal targets; the pair
+ * i = j and pairs at distance exactly 0 are excluded from the sum.
+ */
+#ifndef DMK_ORACLE_H
+#define DMK_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- params */
+typedef struct {
+    double tol;    /* requested precision                              */
+    double c;      /* PSWF bandwidth parameter                         */
+    int    nf;     /* plane-wave half width for D_l (N_1 = 2 nf + 1)   */
+    int    p;      /* Chebyshev proxy order per dimension              */
+    int    nw;     /* plane-wave half width for the windowed W_0       */
+    double hw;     /* plane-wave spacing for W_0 (root box side 1)     */
+} orc_params;
+
+/* Parameters of Table 1 (c, N_1, p); tol 1e-5 uses c = log(1e5), nf = 10,
+ * p = 15.  Returns 0 on success, -1 for an unsupported tol. */
+int orc_params_for(double tol, orc_params *out);
+
+/* ------------------------------------------------------------------ PSWF */
+#define ORC_PSWF_MAXTERM 96
+#define ORC_GL_EXT 256
+typedef struct {
+    double c;
+    int    nterm;                      /* even Legendre terms kept          */
+    double coef[ORC_PSWF_MAXTERM];     /* coefficient of sqrt(k+1/2) P_k, k=2i */
+    double chi;                        /* Sturm-Liouville eigenvalue         */
+    double psi0;                       /* psi(0)                             */
+    double lambda0;                    /* eigenvalue of F_c                  */
+    double c0, c2;                     /* int_0^1 psi, int_0^1 x^2 psi       */
+    double glx[ORC_GL_EXT], glw[ORC_GL_EXT], glpsi[ORC_GL_EXT];
+} orc_pswf;
+
+int    orc_pswf_init(double c, orc_pswf *ps);
+double orc_pswf_eval(const orc_pswf *ps, double x);     /* |x| <= 1 series   */
+double orc_pswf_eval_ext(const orc_pswf *ps, double x); /* any x, via F_c    */
+double orc_pswf_phi(const orc_pswf *ps, double x);      /* Phi(x), x >= 0    */
+void   orc_gauss_legendre(int n, double *x, double *w);
+
+/* Kernel split for 1/r (unscaled, root box side s_0 = 1). */
+double orc_split_w0(const orc_pswf *ps, double r);
+double orc_split_d(const orc_pswf *ps, int l, double r);
+double orc_split_r(const orc_pswf *ps, int L, double r);
+double orc_split_m0(const orc_pswf *ps, int L);          /* M_L(0)           */
+/* Fourier transforms (3-D radial) of D_l and of the windowed W_0. */
+double orc_dhat(const orc_pswf *ps, int l, double k);
+double orc_w0hat(const orc_pswf *ps, double k);
+/* Plane-wave (trapezoidal) approximations evaluated at a 3-D offset x. */
+double orc_split_d_pw(const orc_pswf *ps, const orc_params *pr, int l,
+                      const double x[3]);
+double orc_split_w0_pw(const orc_pswf *ps, const orc_params *pr,
+                       const double x[3]);
+
+/* ------------------------------------------------------------------ tree */
+typedef struct {
+    int      dim;          /* 2 or 3                                         */
+    int      bits;         /* key bits per dimension (21 in 3-D, 31 in 2-D)   */
+    int      ns;           /* leaf capacity n_s                               */
+    int      maxdepth;
+    int64_t  n;            /* number of points                                */
+    double   center[3];    /* root cube centre (input units)                  */
+    double   side;         /* root cube side S (input units)                  */
+    int64_t *perm;         /* sorted position -> input index                  */
+    uint64_t *key;         /* sorted Morton keys                              */
+    double  *xs;           /* sorted normalised coordinates [n][dim]          */
+    int      nlevels;      /* levels 0 .. nlevels-1                           */
+    int64_t *level_start;  /* [nlevels+1] first box of each level             */
+    int64_t  nbox;
+    int32_t *level;        /* [nbox]                                          */
+    uint64_t *bkey;        /* [nbox] Morton prefix of the box at its level    */
+    int64_t *parent;       /* [nbox] (-1 for the root)                        */
+    int64_t *child0;       /* [nbox] first of 2^d contiguous children or -1   */
+    int64_t *pstart;       /* [nbox] first sorted point                       */
+    int64_t *pcount;       /* [nbox] number of points                         */
+    uint8_t *leaf, *fout, *fin, *terminal;  /* [nbox] flags                   */
+    int64_t *colleague;    /* [nbox][3^d], offset order (dx,dy,dz) lexicographic,
+                              -1 when absent; entry 3^d/2 is the box itself    */
+    int32_t *ncoarse;      /* [nbox]                                          */
+    int64_t *coarse;       /* [nbox][2^d - 1] coarse-neighbour leaves         */
+    int32_t *tlevel;       /* [n] level of the terminal box of each sorted pt */
+} orc_tree;
+
+/* Builds the tree for n points pts[n][dim] (input order).  Returns 0 on
+ * success. */
+int  orc_tree_build(int dim, int64_t n, const double *pts, int ns,
+                    int maxdepth, orc_tree *t);
+void orc_tree_free(orc_tree *t);
+
+/* ------------------------------------------------------------------- DMK */
+typedef struct {
+    int64_t n;
+    double *u;        /* [n] potential, input order                        */
+    double *ufar;     /* [n] sorted order, normalised units, no 1/(4 pi S) */
+    double *ures;     /* [n] sorted order, residual incl. self correction   */
+    /* optional intermediates (keep != 0), indexed by box                    */
+    int     p, nf;
+    double **proxy;   /* [nbox] -> p^3 proxy charges, NULL if not formed   */
+    double **local;   /* [nbox] -> p^3 local values on the box's Chebyshev
+                         grid (far potential incl. inherited parts)        */
+} orc_dmk_result;
+
+int  orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
+                  const double *charges, int keep, orc_dmk_result *res);
+void orc_dmk_result_free(const orc_tree *t, orc_dmk_result *res);
+
+/* Direct sum u_i = sum_{j != i, r_ij > 0} q_j / (4 pi r_ij) for the targets
+ * listed in tidx (input indices); compensated (Neumaier) accumulation. */
+void orc_direct(int64_t n, const double *pts, const double *q,
+                int64_t nt, const int64_t *tidx, double *out);
+
+/* Convenience: full pipeline (params, PSWF, tree, DMK) in one call; the
+ * plan/eval wall times in seconds are returned in times[0..1]. */
+int orc_dmk_run(int64_t n, const double *pts, const double *q, double tol,
+                int ns, int maxdepth, double *u, double *times);
+
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

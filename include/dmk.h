@@ -1,0 +1,226 @@
+/*
+ * dmk.h -- C ABI of the MI355X (gfx950) implementation of the DMK
+ * (dual-space multilevel kernel-splitting) point code of Jiang & Greengard,
+ * "A dual-space multilevel kernel-splitting framework for discrete and
+ * continuous convolution", arXiv 2308.00292.
+ *
+ * The library computes, for N points x_i with charges q_i (sources equal
+ * targets),
+ *
+ *     pot_i = sum_{j != i, |x_i - x_j| > 0} K(|x_i - x_j|) q_j,
+ *     K(r) = 1 / (4 pi r)                      (3-D Laplace, eq. laplacesum),
+ *
+ * to a requested relative precision tol, with the O(N) scheme of Sec. 3.5-3.6
+ * ("The linear scaling full DMK algorithm", "The full DMK algorithm for
+ * discrete sources") and the PSWF kernel split of Sec. 3.7.  Pairs at
+ * distance exactly zero (the self pair and coincident points) contribute
+ * nothing.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers (memory of the current HIP
+ *    device), unless the argument is documented as a host pointer.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Work is enqueued on it asynchronously unless stated otherwise.
+ *  - Status codes only; no C++ exception crosses the ABI.  After a non-zero
+ *    status, dmk_last_error() returns a message for the calling thread.
+ *  - Only the 3-D Laplace kernel is implemented; other kernel/dim pairs
+ *    return DMK_ERR_UNSUPPORTED.
+ */
+#ifndef DMK_H
+#define DMK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DMK_OK = 0,
+    DMK_ERR_ARG = -1,          /* invalid argument                           */
+    DMK_ERR_UNSUPPORTED = -2,  /* kernel / dim / tol not implemented         */
+    DMK_ERR_NOMEM = -3,        /* device allocation failed                   */
+    DMK_ERR_HIP = -4,          /* a HIP runtime call failed                  */
+    DMK_ERR_PRECISION = -5,    /* precision mode incompatible with tol       */
+    DMK_ERR_STATE = -6         /* plan busy or in an unusable state          */
+} dmk_status;
+
+typedef enum { DMK_LAPLACE = 0, DMK_YUKAWA = 1 } dmk_kernel;
+
+/* Arithmetic of the eval pipeline.  Input and output are always FP64. */
+typedef enum {
+    DMK_FP64 = 0,   /* every stage in double precision                     */
+    DMK_MIXED = 1   /* transforms and residual sums in FP32, box-relative
+                       offsets, small-r residuals and the final sum in FP64 */
+} dmk_precision;
+
+/* Options; a zero field selects the default.  Pass NULL for all defaults. */
+typedef struct {
+    int32_t  leaf_max;    /* n_s, the leaf capacity (default 64)              */
+    int32_t  max_depth;   /* depth cap of the tree (default 20, at most 21)   */
+    int32_t  precision;   /* dmk_precision (default DMK_FP64)                 */
+    int32_t  reserved0;
+    uint64_t flags;       /* DMK_FLAG_* bits                                  */
+} dmk_opts;
+
+/* Keep the per-box local values of leaves too, so dmk_copy_box_data can
+ * return them after an eval (parity checks; costs memory). */
+#define DMK_FLAG_KEEP_LOCALS 1ull
+
+typedef struct dmk_plan_s *dmk_plan_t;
+
+/* Sizes of a plan (host struct filled by dmk_plan_info). */
+typedef struct {
+    int64_t n;            /* points                                          */
+    int64_t nbox;         /* boxes of all levels                             */
+    int32_t nlevels;      /* levels 0 .. nlevels-1                           */
+    int32_t p;            /* Chebyshev proxy order per dimension             */
+    int32_t nf;           /* plane-wave half width of D_l                    */
+    int32_t nw;           /* plane-wave half width of the windowed W_0       */
+    double  c;            /* PSWF parameter                                  */
+    double  tol;
+    int32_t leaf_max;
+    int32_t precision;
+    int64_t nleaf;        /* leaves holding at least one point               */
+    int64_t nfout;        /* boxes with F_out                                */
+    int64_t nfin;         /* non-empty boxes with F_in                       */
+    int64_t npairs;       /* candidate (target, source) pairs of the residual */
+    int64_t device_bytes; /* device memory held by the plan                  */
+    double  center[3];    /* root cube centre (input units)                  */
+    double  side;         /* root cube side (input units)                    */
+} dmk_plan_stats;
+
+/*
+ * dmk_plan -- build the adaptive tree and all tables for one point set.
+ *
+ * Paper: Step 0 (initialisation: level-restricted adaptive tree, flags
+ * F_leaf/F_out/F_in) and Step 1 (precomputation of the 1-D transforms and
+ * plane-wave weights) of Sec. 3.6; tree conventions of Sec. 3.3; parameters
+ * c, N_1 = 2 n_f + 1, p of Table 1 (Sec. 3.7).
+ *
+ *  dim     must be 3.
+ *  kernel  must be DMK_LAPLACE.
+ *  tol     one of 1e-3, 1e-6, 1e-9, 1e-12 (Table 1) or 1e-5.  DMK_MIXED
+ *          requires tol >= 1e-6 (else DMK_ERR_PRECISION).
+ *  n       number of points, 0 <= n < 2^31.
+ *  pts     device, [n][3] FP64, row-major, input order.  Read during the
+ *          call only; the plan keeps its own sorted copy.  Non-finite
+ *          coordinates give DMK_ERR_ARG.
+ *  opts    host pointer or NULL.
+ *  stream  work is enqueued on it; the call synchronises it before return.
+ *  out     host pointer receiving the plan handle (NULL on failure).
+ *
+ * The plan owns its device memory until dmk_plan_destroy.
+ */
+dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const double *pts,
+                    const dmk_opts *opts, void *stream, dmk_plan_t *out);
+
+/*
+ * dmk_eval -- potentials of one charge vector on a planned point set.
+ *
+ * Paper: Steps 2-5 of Sec. 3.6 (upward pass, downward pass, direct
+ * interactions with the residual kernel, self-interaction correction).
+ *
+ *  charges device, [n] FP64, input order.
+ *  pot     device, [n] FP64, input order, overwritten.
+ *  stream  asynchronous: pot is valid once the stream has been synchronised.
+ *
+ * A plan owns its workspace: a second dmk_eval on the same plan while one
+ * is in flight on another host thread returns DMK_ERR_STATE.  Calls on the
+ * same stream are ordered and may be issued back to back.
+ */
+dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *stream);
+
+/*
+ * dmk_eval_parts -- like dmk_eval, but returns the far-field part (the
+ * windowed and difference kernels through plane waves and Chebyshev
+ * interpolation, eq. farpotential) and the near part (residual kernel sums
+ * plus the self correction, eq. nearpotential and Step 5) separately, both
+ * in input order and both scaled by 1/(4 pi S).  pot = far + near.
+ * Either output pointer may be NULL.
+ */
+dmk_status dmk_eval_parts(dmk_plan_t plan, const double *charges, double *far_part,
+                          double *near_part, void *stream);
+
+/* dmk_plan_info -- sizes of a plan; st is a host pointer. */
+dmk_status dmk_plan_info(dmk_plan_t plan, dmk_plan_stats *st);
+
+/*
+ * dmk_export_tree -- copy the tree to caller-owned HOST arrays (for
+ * bit-exact comparison with an independent tree builder).  Any pointer may
+ * be NULL to skip that array.  Sizes: n = points, B = nbox (dmk_plan_info).
+ *   perm       [n]       int64  sorted position -> input index
+ *   level      [B]       int32
+ *   bkey       [B]       uint64 Morton prefix of the box at its level
+ *   parent     [B]       int64  (-1 for the root)
+ *   child0     [B]       int64  first of 8 contiguous children, -1 for a leaf
+ *   pstart     [B]       int64  first sorted point of the box
+ *   pcount     [B]       int64  points in the box
+ *   flags      [B]       uint8  bit0 leaf, bit1 F_out, bit2 F_in, bit3 terminal
+ *   colleague  [B][27]   int64  same-level neighbours by offset (dx,dy,dz),
+ *                               lexicographic from (-1,-1,-1); -1 if absent
+ *   ncoarse    [B]       int32  number of coarse-neighbour leaves
+ *   coarse     [B][7]    int64  coarse-neighbour leaves (first ncoarse valid)
+ * Boxes are ordered level by level, in Morton order within a level.
+ * Synchronous.
+ */
+dmk_status dmk_export_tree(dmk_plan_t plan, int64_t *perm, int32_t *level, uint64_t *bkey,
+                           int64_t *parent, int64_t *child0, int64_t *pstart, int64_t *pcount,
+                           uint8_t *flags, int64_t *colleague, int32_t *ncoarse, int64_t *coarse);
+
+/*
+ * dmk_export_near_lists -- the residual interaction lists in gather form:
+ * for every leaf holding points, the boxes whose sources act on its targets
+ * with the residual kernel of the source box's level.  HOST arrays:
+ *   leaf_box  [nleaf]        int64  the target leaves, in list order
+ *   offsets   [nleaf+1]      int64  CSR offsets into src_box
+ *   src_box   [offsets[nleaf]] int64 source (terminal) boxes
+ * Call first with src_box = NULL to learn offsets[nleaf].  Synchronous.
+ */
+dmk_status dmk_export_near_lists(dmk_plan_t plan, int64_t *leaf_box, int64_t *offsets,
+                                 int64_t *src_box);
+
+/*
+ * dmk_copy_box_data -- after a dmk_eval on `plan`, copy per-box data of
+ * box `box` to the HOST array `out` (p^3 FP64 values, index (i*p + j)*p + k
+ * for Chebyshev node indices i, j, k along x, y, z).
+ *   what = 0: proxy charges (boxes with F_out only);
+ *   what = 1: local values of the far potential on the box's Chebyshev grid
+ *             (non-leaf boxes with points; leaves too with
+ *             DMK_FLAG_KEEP_LOCALS).
+ * Values are in normalised units (root box [-1/2,1/2]^3, kernel 1/r).
+ * Returns DMK_ERR_ARG if the box holds no such data.  Synchronous.
+ */
+dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out);
+
+/*
+ * dmk_precompute_probe -- HOST-only view of the tables that Step 1 of
+ * Sec. 3.6 builds for a tolerance; no device is touched, so it also runs on
+ * machines without a GPU.  x and out are host arrays of n entries.
+ *   what = 0: psi_0^c(x_i) / psi_0^c(0) for any real x_i (the PSWF of the
+ *             tolerance's c, continued off [-1,1] by the eigen-relation of
+ *             the Appendix on PSWFs);
+ *   what = 1: g(t_i) = Phi(sqrt t_i)/sqrt t_i for t_i in [0,1], as the
+ *             residual stage evaluates it (R_l(r) = 1/r - g(r^2/s_l^2)/s_l);
+ *   what = 2: plane-wave weight of D_0 at |m|^2 = x_i (eq.
+ *             differencekernelft3 with the factor (h_0/2pi)^3), NaN if no
+ *             mode of the table has that |m|^2;
+ *   what = 3: plane-wave weight of the windowed W_0 at |m|^2 = x_i;
+ *   what = 4: out[0..3] = psi(0), c_0, c_2, lambda_0 (n >= 4, x unused);
+ *   what = 5: out[0..5] = c, n_f, p, n_w, h_w, degree of g (n >= 6).
+ * DMK_ERR_UNSUPPORTED for a tolerance outside the table, DMK_ERR_ARG for a
+ * bad `what` or n.
+ */
+dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x, double *out);
+
+/* dmk_plan_destroy -- free a plan (NULL is ignored).  Synchronises the
+ * plan's last stream first. */
+void dmk_plan_destroy(dmk_plan_t plan);
+
+/* dmk_last_error -- message of the last failure on the calling thread. */
+const char *dmk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

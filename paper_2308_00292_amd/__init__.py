@@ -1,0 +1,185 @@
+"""MI355X (gfx950) DMK point code: Python binding of the C ABI in include/dmk.h.
+
+Argument marshalling only: every stage of the computation runs in the HIP
+kernels of ``libdmk.so``.  PyTorch supplies device memory and streams.  There
+is no fallback: if the library is missing, importing a binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libdmk.so")
+
+DMK_FP64, DMK_MIXED = 0, 1
+DMK_LAPLACE = 0
+DMK_FLAG_KEEP_LOCALS = 1
+
+# exported symbols, in the order of include/dmk.h
+SYMBOLS = ["dmk_plan", "dmk_eval", "dmk_eval_parts", "dmk_plan_info", "dmk_export_tree",
+           "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
+           "dmk_plan_destroy", "dmk_last_error"]
+
+
+class Opts(C.Structure):
+    _fields_ = [("leaf_max", C.c_int32), ("max_depth", C.c_int32), ("precision", C.c_int32),
+                ("reserved0", C.c_int32), ("flags", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nbox", C.c_int64), ("nlevels", C.c_int32), ("p", C.c_int32),
+                ("nf", C.c_int32), ("nw", C.c_int32), ("c", C.c_double), ("tol", C.c_double),
+                ("leaf_max", C.c_int32), ("precision", C.c_int32), ("nleaf", C.c_int64),
+                ("nfout", C.c_int64), ("nfin", C.c_int64), ("npairs", C.c_int64),
+                ("device_bytes", C.c_int64), ("center", C.c_double * 3), ("side", C.c_double)]
+
+
+class DmkError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"DMK status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdmk.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"{LIBPATH} is missing: build it with paper_2308_00292_amd/build.py")
+        L = C.CDLL(LIBPATH)
+        vp, i64, f64p = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
+        L.dmk_plan.argtypes = [C.c_int, C.c_int, C.c_double, i64, vp, C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.dmk_eval.argtypes = [vp, vp, vp, vp]
+        L.dmk_eval_parts.argtypes = [vp, vp, vp, vp, vp]
+        L.dmk_plan_info.argtypes = [vp, C.POINTER(Stats)]
+        L.dmk_export_tree.argtypes = [vp] + [vp] * 11
+        L.dmk_export_near_lists.argtypes = [vp, vp, vp, vp]
+        L.dmk_copy_box_data.argtypes = [vp, C.c_int, i64, f64p]
+        L.dmk_precompute_probe.argtypes = [C.c_double, C.c_int, i64, vp, vp]
+        L.dmk_plan_destroy.argtypes = [vp]
+        L.dmk_plan_destroy.restype = None
+        L.dmk_last_error.restype = C.c_char_p
+        for f in SYMBOLS[:-2]:
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise DmkError(rc, lib().dmk_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def precompute_probe(tol, what, x=None, n=None):
+    """Host-only view of the precomputed tables (see dmk_precompute_probe)."""
+    if x is not None:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = len(x)
+    out = np.zeros(n)
+    _check(lib().dmk_precompute_probe(float(tol), int(what), int(n), _np_ptr(x), _np_ptr(out)))
+    return out
+
+
+class Plan:
+    """dmk_plan on device points; eval() applies dmk_eval to charge vectors."""
+
+    def __init__(self, pts, tol=1e-6, leaf_max=64, max_depth=0, precision=DMK_FP64, flags=0,
+                 stream=None):
+        import torch
+        if not (isinstance(pts, torch.Tensor) and pts.is_cuda and pts.dtype == torch.float64):
+            raise TypeError("pts must be a float64 CUDA tensor of shape [n, 3]")
+        pts = pts.contiguous()
+        self.n = int(pts.shape[0])
+        o = Opts(leaf_max, max_depth, precision, 0, flags)
+        h = C.c_void_p()
+        _check(lib().dmk_plan(3, DMK_LAPLACE, float(tol), self.n, _ptr(pts), C.byref(o),
+                              _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self.device = pts.device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmk_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def eval(self, charges, out=None, stream=None):
+        import torch
+        q = charges.contiguous()
+        if q.dtype != torch.float64 or not q.is_cuda or q.numel() != self.n:
+            raise TypeError("charges must be a float64 CUDA tensor with n entries")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=q.device)
+        _check(lib().dmk_eval(self._h, _ptr(q), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def eval_parts(self, charges, stream=None):
+        import torch
+        q = charges.contiguous()
+        far = torch.empty(self.n, dtype=torch.float64, device=q.device)
+        near = torch.empty(self.n, dtype=torch.float64, device=q.device)
+        _check(lib().dmk_eval_parts(self._h, _ptr(q), _ptr(far), _ptr(near), _stream_handle(stream)))
+        return far, near
+
+    def info(self):
+        st = Stats()
+        _check(lib().dmk_plan_info(self._h, C.byref(st)))
+        d = {k: getattr(st, k) for k, _ in Stats._fields_}
+        d["center"] = list(st.center)
+        return d
+
+    def export_tree(self):
+        inf = self.info()
+        n, nb = inf["n"], inf["nbox"]
+        out = dict(perm=np.zeros(n, np.int64), level=np.zeros(nb, np.int32),
+                   bkey=np.zeros(nb, np.uint64), parent=np.zeros(nb, np.int64),
+                   child0=np.zeros(nb, np.int64), pstart=np.zeros(nb, np.int64),
+                   pcount=np.zeros(nb, np.int64), flags=np.zeros(nb, np.uint8),
+                   colleague=np.zeros((nb, 27), np.int64), ncoarse=np.zeros(nb, np.int32),
+                   coarse=np.zeros((nb, 7), np.int64))
+        keys = ["perm", "level", "bkey", "parent", "child0", "pstart", "pcount", "flags",
+                "colleague", "ncoarse", "coarse"]
+        _check(lib().dmk_export_tree(self._h, *[_np_ptr(out[k]) for k in keys]))
+        return out
+
+    def export_near_lists(self):
+        inf = self.info()
+        nl = inf["nleaf"]
+        leaf = np.zeros(max(nl, 1), np.int64)
+        off = np.zeros(nl + 1, np.int64)
+        _check(lib().dmk_export_near_lists(self._h, _np_ptr(leaf), _np_ptr(off), None))
+        src = np.zeros(max(int(off[-1]), 1), np.int64)
+        _check(lib().dmk_export_near_lists(self._h, _np_ptr(leaf), _np_ptr(off), _np_ptr(src)))
+        return leaf[:nl], off, src[: int(off[-1])]
+
+    def box_data(self, what, box):
+        p = self.info()["p"]
+        out = np.zeros(p ** 3)
+        _check(lib().dmk_copy_box_data(self._h, int(what), int(box),
+                                       out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out

@@ -1,0 +1,312 @@
+// C ABI of the DMK library (declarations and documentation in include/dmk.h).
+// Every entry point converts internal failures into status codes; no C++
+// exception crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "dmk_internal.h"
+
+namespace dmk {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+void *dalloc(Plan *P, size_t bytes)
+{
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{DMK_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e)};
+    }
+    P->allocations.push_back(p);
+    P->device_bytes += (int64_t)bytes;
+    return p;
+}
+
+void plan_free_all(Plan *P)
+{
+    for (void *p : P->allocations) (void)hipFree(p);
+    P->allocations.clear();
+}
+
+}  // namespace dmk
+
+using namespace dmk;
+
+namespace {
+
+template <typename F>
+dmk_status guarded(F &&f)
+{
+    try {
+        f();
+        return DMK_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return DMK_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return DMK_ERR_STATE;
+    } catch (...) {
+        set_error("unknown failure");
+        return DMK_ERR_STATE;
+    }
+}
+
+struct BusyGuard {
+    Plan *P;
+    explicit BusyGuard(Plan *p) : P(p)
+    {
+        int expect = 0;
+        if (!P->busy.compare_exchange_strong(expect, 1))
+            throw Error{DMK_ERR_STATE, "plan is in use by another dmk_eval"};
+    }
+    ~BusyGuard() { P->busy.store(0); }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *dmk_last_error(void) { return g_err.c_str(); }
+
+dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const double *pts, const dmk_opts *opts,
+                    void *stream, dmk_plan_t *out)
+{
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out) throw Error{DMK_ERR_ARG, "out is NULL"};
+        if (dim != 3) throw Error{DMK_ERR_UNSUPPORTED, "only dim = 3 is implemented"};
+        if (kernel != DMK_LAPLACE) throw Error{DMK_ERR_UNSUPPORTED, "only the Laplace kernel is implemented"};
+        if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
+        if (n < 0 || n >= (int64_t(1) << 31)) throw Error{DMK_ERR_ARG, "n must satisfy 0 <= n < 2^31"};
+        if (n > 0 && !pts) throw Error{DMK_ERR_ARG, "pts is NULL"};
+        dmk_opts o;
+        std::memset(&o, 0, sizeof(o));
+        if (opts) o = *opts;
+        Params prm;
+        if (!params_for(tol, &prm)) throw Error{DMK_ERR_UNSUPPORTED, "tol must be one of 1e-3, 1e-5, 1e-6, 1e-9, 1e-12"};
+        if (prm.p > 18) throw Error{DMK_ERR_UNSUPPORTED, "tol below 1e-6 needs proxy order > 18, not built"};
+        if (o.precision != DMK_FP64 && o.precision != DMK_MIXED) throw Error{DMK_ERR_ARG, "unknown precision"};
+        if (o.precision == DMK_MIXED) throw Error{DMK_ERR_UNSUPPORTED, "mixed precision is not built yet"};
+        if (o.leaf_max < 0 || o.max_depth < 0 || o.max_depth > 21) throw Error{DMK_ERR_ARG, "bad leaf_max/max_depth"};
+        auto *P = new Plan();
+        try {
+            P->precision = o.precision;
+            P->leaf_max = o.leaf_max ? o.leaf_max : 64;
+            P->max_depth = o.max_depth ? o.max_depth : 20;
+            P->flags = o.flags;
+            P->n = n;
+            build_tables(prm, &P->tab);
+            P->p = prm.p;
+            P->nf = prm.nf;
+            P->nw = prm.nw;
+            hipStream_t s = (hipStream_t)stream;
+            upload_tables(P, s);
+            build_tree(P, pts, s);
+            build_lists(P, s);
+            alloc_workspace(P);
+        } catch (...) {
+            plan_free_all(P);
+            delete P;
+            throw;
+        }
+        *out = reinterpret_cast<dmk_plan_t>(P);
+    });
+}
+
+dmk_status dmk_eval_parts(dmk_plan_t plan, const double *charges, double *far_part, double *near_part, void *stream)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (P->n > 0 && !charges) throw Error{DMK_ERR_ARG, "charges is NULL"};
+        BusyGuard g(P);
+        hipStream_t s = (hipStream_t)stream;
+        run_eval(P, charges, nullptr, far_part, near_part, s);
+        P->last_stream = s;
+    });
+}
+
+dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *stream)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (P->n > 0 && (!charges || !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
+        BusyGuard g(P);
+        hipStream_t s = (hipStream_t)stream;
+        run_eval(P, charges, pot, nullptr, nullptr, s);
+        P->last_stream = s;
+    });
+}
+
+dmk_status dmk_plan_info(dmk_plan_t plan, dmk_plan_stats *st)
+{
+    return guarded([&] {
+        if (!plan || !st) throw Error{DMK_ERR_ARG, "NULL argument"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        std::memset(st, 0, sizeof(*st));
+        st->n = P->n;
+        st->nbox = P->nbox;
+        st->nlevels = P->nlevels;
+        st->p = P->p;
+        st->nf = P->nf;
+        st->nw = P->nw;
+        st->c = P->tab.prm.c;
+        st->tol = P->tab.prm.tol;
+        st->leaf_max = P->leaf_max;
+        st->precision = P->precision;
+        st->nleaf = P->nleaf;
+        st->nfout = P->nfout;
+        st->nfin = P->nfin;
+        st->npairs = P->npairs;
+        st->device_bytes = P->device_bytes;
+        for (int d = 0; d < 3; ++d) st->center[d] = P->center[d];
+        st->side = P->side;
+    });
+}
+
+dmk_status dmk_export_tree(dmk_plan_t plan, int64_t *perm, int32_t *level, uint64_t *bkey, int64_t *parent,
+                           int64_t *child0, int64_t *pstart, int64_t *pcount, uint8_t *flags, int64_t *colleague,
+                           int32_t *ncoarse, int64_t *coarse)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        const int64_t n = P->n, nb = P->nbox;
+        auto cp32to64 = [&](const int32_t *src, int64_t cnt, int64_t *dst) {
+            if (!dst || cnt == 0) return;
+            std::vector<int32_t> h(cnt);
+            DMK_HIP(hipMemcpy(h.data(), src, cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < cnt; ++i) dst[i] = h[i];
+        };
+        cp32to64(P->perm, n, perm);
+        if (level) DMK_HIP(hipMemcpy(level, P->blevel, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (bkey) DMK_HIP(hipMemcpy(bkey, P->bkey, nb * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        cp32to64(P->parent, nb, parent);
+        cp32to64(P->child0, nb, child0);
+        cp32to64(P->pstart, nb, pstart);
+        cp32to64(P->pcount, nb, pcount);
+        if (flags) DMK_HIP(hipMemcpy(flags, P->bflags, nb, hipMemcpyDeviceToHost));
+        cp32to64(P->colleague, 27 * nb, colleague);
+        if (ncoarse) DMK_HIP(hipMemcpy(ncoarse, P->ncoarse, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+        cp32to64(P->coarse, 7 * nb, coarse);
+    });
+}
+
+dmk_status dmk_export_near_lists(dmk_plan_t plan, int64_t *leaf_box, int64_t *offsets, int64_t *src_box)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        auto cp = [&](const int32_t *src, int64_t cnt, int64_t *dst) {
+            if (!dst || cnt == 0) return;
+            std::vector<int32_t> h(cnt);
+            DMK_HIP(hipMemcpy(h.data(), src, cnt * sizeof(int32_t), hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < cnt; ++i) dst[i] = h[i];
+        };
+        cp(P->l_leaf, P->nleaf, leaf_box);
+        if (offsets) {
+            if (P->nleaf == 0) offsets[0] = 0;
+            else cp(P->nl_off, P->nleaf + 1, offsets);
+        }
+        cp(P->nl_src, P->nl_total, src_box);
+    });
+}
+
+dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out)
+{
+    return guarded([&] {
+        if (!plan || !out) throw Error{DMK_ERR_ARG, "NULL argument"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (box < 0 || box >= P->nbox) throw Error{DMK_ERR_ARG, "box out of range"};
+        const int64_t p3 = (int64_t)P->p * P->p * P->p;
+        int32_t slot = -1;
+        const double *base = nullptr;
+        if (what == 0) {
+            DMK_HIP(hipMemcpy(&slot, P->proxy_slot + box, sizeof(int32_t), hipMemcpyDeviceToHost));
+            base = P->proxy;
+        } else if (what == 1) {
+            DMK_HIP(hipMemcpy(&slot, P->local_slot + box, sizeof(int32_t), hipMemcpyDeviceToHost));
+            base = P->local;
+        } else {
+            throw Error{DMK_ERR_ARG, "what must be 0 or 1"};
+        }
+        if (slot < 0) throw Error{DMK_ERR_ARG, "box holds no such data"};
+        if (P->last_stream) DMK_HIP(hipStreamSynchronize(P->last_stream));
+        DMK_HIP(hipDeviceSynchronize());
+        DMK_HIP(hipMemcpy(out, base + (int64_t)slot * p3, p3 * sizeof(double), hipMemcpyDeviceToHost));
+    });
+}
+
+dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x, double *out)
+{
+    return guarded([&] {
+        if (n < 0 || (n > 0 && !out)) throw Error{DMK_ERR_ARG, "bad n or out"};
+        Params prm;
+        if (!params_for(tol, &prm)) throw Error{DMK_ERR_UNSUPPORTED, "tolerance not in the table"};
+        Tables t;
+        build_tables(prm, &t);
+        if (what == 4) {
+            if (n < 4) throw Error{DMK_ERR_ARG, "n >= 4 needed"};
+            out[0] = t.psi0; out[1] = t.c0; out[2] = t.c2; out[3] = t.lambda0;
+            return;
+        }
+        if (what == 5) {
+            if (n < 6) throw Error{DMK_ERR_ARG, "n >= 6 needed"};
+            out[0] = prm.c; out[1] = prm.nf; out[2] = prm.p; out[3] = prm.nw; out[4] = prm.hw; out[5] = t.gdeg;
+            return;
+        }
+        if (n > 0 && !x) throw Error{DMK_ERR_ARG, "x is NULL"};
+        for (int64_t i = 0; i < n; ++i) {
+            double v = NAN;
+            if (what == 0) {
+                v = pswf_eval(t, x[i]) / t.psi0;
+            } else if (what == 1) {
+                double u = 2.0 * x[i] - 1.0, b1 = 0.0, b2 = 0.0;
+                for (int k = t.gdeg; k >= 1; --k) {
+                    double b0 = t.gcheb[k] + 2.0 * u * b1 - b2;
+                    b2 = b1;
+                    b1 = b0;
+                }
+                v = t.gcheb[0] + u * b1 - b2;
+            } else if (what == 2 || what == 3) {
+                const int nf = (what == 2) ? t.nf : t.nw, nn = 2 * nf + 1;
+                const std::vector<double> &w = (what == 2) ? t.wd0 : t.ww;
+                long k2 = lround(x[i]);
+                for (int m3 = 0; m3 <= nf && std::isnan(v); ++m3)
+                    for (int m2 = -nf; m2 <= nf && std::isnan(v); ++m2)
+                        for (int m1 = -nf; m1 <= nf; ++m1)
+                            if ((long)(m1 * m1 + m2 * m2 + m3 * m3) == k2) {
+                                v = w[((size_t)m3 * nn + (m2 + nf)) * nn + (m1 + nf)];
+                                break;
+                            }
+            } else {
+                throw Error{DMK_ERR_ARG, "what must be 0..5"};
+            }
+            out[i] = v;
+        }
+    });
+}
+
+void dmk_plan_destroy(dmk_plan_t plan)
+{
+    if (!plan) return;
+    Plan *P = reinterpret_cast<Plan *>(plan);
+    if (P->last_stream) (void)hipStreamSynchronize(P->last_stream);
+    (void)hipDeviceSynchronize();
+    plan_free_all(P);
+    delete P;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal declarations of the gfx950 DMK library: plan layout, precomputed
+// tables and error plumbing.  Not part of the C ABI (include/dmk.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dmk.h"
+
+namespace dmk {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+
+struct Error {
+    dmk_status code;
+    std::string msg;
+};
+
+#define DMK_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::dmk::Error{DMK_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+// ------------------------------------------------------------- parameters
+struct Params {
+    double tol;
+    double c;    // PSWF parameter
+    int nf;      // plane-wave half width of D_l
+    int p;       // Chebyshev order
+    int nw;      // plane-wave half width of W_0
+    double hw;   // plane-wave spacing of W_0 (root side 1)
+};
+bool params_for(double tol, Params *out);
+
+// Host-side tables, all FP64 (Step 1 of the algorithm).
+struct Tables {
+    Params prm;
+    int p, nf, nn, nh, nw, nwn, nwh;
+    double psi0, c0, c2, lambda0;
+    std::vector<double> coef;              // PSWF Legendre coefficients (even k)
+    std::vector<double> xcheb;             // p first-kind Chebyshev nodes
+    std::vector<double> bary;              // barycentric weights of the nodes
+    std::vector<double> c2p;               // [2][p][p] A_s[a][i] = l_a((x_i + s)/2)
+    std::vector<double> epw;               // [nn][p][2] exp(-i pi m x_j / 3)
+    std::vector<double> ew;                // [nwn][p][2] exp(-i hw m x_j / 2)
+    std::vector<double> wd0;               // [nh][nn][nn] D_0 weights, half spectrum
+    std::vector<double> ww;                // [nwh][nwn][nwn] W_0 weights
+    std::vector<double> gcheb;             // Chebyshev coefficients of Phi(sqrt t)/sqrt t on [0,1]
+    int gdeg;
+};
+void build_tables(const Params &prm, Tables *t);
+
+// PSWF helpers exposed for the host-side self checks in the tests.
+double pswf_eval(const Tables &t, double x);  // any real x
+
+// ------------------------------------------------------------------- plan
+struct LevelLists {
+    // offsets into the concatenated device lists, per level [nlevels+1]
+    std::vector<int64_t> fout_off, ne_off, fin_off, leaf_off;
+};
+
+struct Plan {
+    // configuration
+    int dim = 3, p = 0, nf = 0, nw = 0, precision = 0, leaf_max = 64, max_depth = 20;
+    uint64_t flags = 0;
+    Tables tab;
+    int64_t n = 0;
+    double center[3] = {0, 0, 0}, side = 1.0;
+
+    // sorted points
+    double *X = nullptr, *Y = nullptr, *Z = nullptr;
+    int32_t *perm = nullptr;
+    uint64_t *keys = nullptr;
+
+    // boxes (level-major, Morton order within a level)
+    int nlevels = 0;
+    std::vector<int64_t> level_start;  // host [nlevels+1]
+    int64_t nbox = 0;
+    uint64_t *bkey = nullptr;
+    int32_t *blevel = nullptr, *parent = nullptr, *child0 = nullptr;
+    int32_t *pstart = nullptr, *pcount = nullptr;
+    uint8_t *bflags = nullptr;  // bit0 leaf, bit1 fout, bit2 fin, bit3 terminal
+    int32_t *colleague = nullptr;  // [nbox][27]
+    int32_t *ncoarse = nullptr, *coarse = nullptr;  // [nbox], [nbox][7]
+    double *bcenter = nullptr;     // [nbox][3]
+
+    // work lists (device, concatenated by level) and slot maps
+    LevelLists ll;
+    int32_t *l_fout = nullptr, *l_ne = nullptr, *l_fin = nullptr, *l_leaf = nullptr;
+    int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
+    int64_t nfout = 0, nne = 0, nfin = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
+
+    // near (residual) lists in gather form over l_leaf order
+    int32_t *nl_off = nullptr, *nl_src = nullptr;
+    int64_t nl_total = 0, npairs = 0;
+
+    // device tables
+    double *d_c2p = nullptr, *d_epw = nullptr, *d_ew = nullptr, *d_wd0 = nullptr,
+           *d_ww = nullptr, *d_gcheb = nullptr, *d_xcheb = nullptr, *d_bary = nullptr;
+
+    // eval workspace
+    double *qs = nullptr, *ufar = nullptr, *ures = nullptr;
+    double *proxy = nullptr;   // [nfout][p^3]
+    double *local = nullptr;   // [nne][p^3]
+    double *phi = nullptr;     // [max_fout_level][nh*nn*nn][2]
+    double *psi = nullptr;     // [max_fin_level][nh*nn*nn][2]
+    double *w0vals = nullptr;  // [p^3] W_0 values on the root grid
+
+    std::vector<void *> allocations;
+    int64_t device_bytes = 0;
+    std::atomic<int> busy{0};
+    hipStream_t last_stream = nullptr;
+};
+
+void *dalloc(Plan *P, size_t bytes);  // tracked device allocation
+void plan_free_all(Plan *P);
+
+void build_tree(Plan *P, const double *pts, hipStream_t s);
+void build_lists(Plan *P, hipStream_t s);
+void upload_tables(Plan *P, hipStream_t s);
+void alloc_workspace(Plan *P);
+void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
+              hipStream_t s);
+
+}  // namespace dmk

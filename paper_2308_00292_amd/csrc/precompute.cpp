@@ -1,0 +1,330 @@
+// Step 1 of the discrete DMK algorithm (Sec. 3.6): host-side precomputation
+// in FP64 of everything the device stages read.
+//
+//  * psi_0^c, the first prolate spheroidal wave function of order zero
+//    (Appendix, eigenfunction of F_c).  Its even Legendre coefficients are the
+//    ground state of the prolate Sturm-Liouville operator, a symmetric matrix
+//    in the normalised Legendre basis, diagonalised here by cyclic Jacobi
+//    rotations.  Off [-1,1] psi is continued through the eigen-relation,
+//    lambda_0 psi(x) = int_{-1}^1 psi(t) e^{icxt} dt, which in the Legendre
+//    basis is a series of spherical Bessel functions:
+//        int_{-1}^1 P_k(t) e^{iwt} dt = 2 i^k j_k(w).
+//  * The cumulative window Phi(x) = (1/c_0) int_0^x psi (Sec. 3.7), tabulated
+//    as Chebyshev coefficients of g(t) = Phi(sqrt t)/sqrt t on t in [0,1], so
+//    that the residual kernel is R_l(r) = 1/r - g(r^2/s_l^2)/s_l for r < s_l.
+//  * Plane-wave weights of the difference kernels (eq. differencekernelft3,
+//    trapezoidal rule with spacing h_l = 2 pi/(3 s_l) and factor (h_l/2pi)^3)
+//    and of the windowed root kernel (mollifier transform times the
+//    transform 8 pi sin^2(kA/2)/k^2 of 1/r truncated at A = 1 + sqrt 3).
+//  * 1-D operators: first-kind Chebyshev nodes, barycentric weights, the
+//    child<->parent interpolation matrices of Lemmas 2.1/2.2 and the
+//    proxy->plane-wave matrices of eq. outgoingexpansion2.
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+#include "dmk_internal.h"
+
+namespace dmk {
+
+bool params_for(double tol, Params *out)
+{
+    // Table 1 (c, N_1 = 2 nf + 1, p) plus a 1e-5 row (c = log(1/eps)).
+    struct Row { double tol, c; int nf, p; };
+    static const Row rows[] = {
+        {1e-3, 7.2462000846862793, 6, 9},
+        {1e-5, 11.512925464970229, 10, 15},
+        {1e-6, 13.739999771118164, 12, 18},
+        {1e-9, 20.736000061035156, 19, 28},
+        {1e-12, 27.870000839233398, 26, 38},
+    };
+    for (const Row &r : rows) {
+        if (std::fabs(std::log10(tol) - std::log10(r.tol)) < 1e-3) {
+            out->tol = tol;
+            out->c = r.c;
+            out->nf = r.nf;
+            out->p = r.p;
+            // W_0 lives on r <= A + 1 (A = 1 + sqrt 3); offsets inside the unit
+            // box are <= 1 per axis, so the period 2 pi/hw must reach 3 + sqrt 3.
+            out->hw = 2.0 * M_PI / (3.0 + std::sqrt(3.0));
+            out->nw = (int)std::ceil(out->c / out->hw);
+            return true;
+        }
+    }
+    return false;
+}
+
+namespace {
+
+// Cyclic Jacobi diagonalisation of a symmetric n x n matrix A (row-major,
+// destroyed).  On return evals[i] and column i of V are an eigenpair.
+void jacobi_eigen(int n, std::vector<double> &A, std::vector<double> &V, std::vector<double> &evals)
+{
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double a = A[(size_t)i * n + j];
+                tot += a * a;
+                if (i != j) off += a * a;
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - s * akq;
+                    A[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - s * aqk;
+                    A[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - s * vkq;
+                    V[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    evals.resize(n);
+    for (int i = 0; i < n; ++i) evals[i] = A[(size_t)i * n + i];
+}
+
+void legendre(int kmax, double x, std::vector<double> &P)
+{
+    P.resize(kmax + 1);
+    P[0] = 1.0;
+    if (kmax > 0) P[1] = x;
+    for (int k = 1; k < kmax; ++k) P[k + 1] = ((2 * k + 1) * x * P[k] - k * P[k - 1]) / (k + 1);
+}
+
+// Spherical Bessel j_0..j_nmax at z > 0 by Miller's downward recurrence,
+// normalised with j_0 or j_1 in closed form.
+void sph_bessel(int nmax, double z, std::vector<double> &j)
+{
+    j.assign(nmax + 1, 0.0);
+    if (z == 0.0) { j[0] = 1.0; return; }
+    int N = nmax + 30 + (int)z;
+    std::vector<double> v(N + 2, 0.0);
+    double hi = 0.0, cur = 1e-280;
+    for (int k = N; k >= 0; --k) {
+        v[k] = cur;
+        double lo = (2.0 * k + 1.0) / z * cur - hi;
+        hi = cur;
+        cur = lo;
+        if (std::fabs(cur) > 1e200) {
+            for (int m = k; m <= N; ++m) v[m] *= 1e-200;
+            hi *= 1e-200;
+            cur *= 1e-200;
+        }
+    }
+    double j0 = std::sin(z) / z, j1 = std::sin(z) / (z * z) - std::cos(z) / z;
+    double scale = (std::fabs(j0) >= std::fabs(j1)) ? j0 / v[0] : j1 / v[1];
+    for (int k = 0; k <= nmax; ++k) j[k] = v[k] * scale;
+}
+
+double pswf_series(const Tables &t, double x)
+{
+    int K = (int)t.coef.size();
+    std::vector<double> P;
+    legendre(2 * K, x, P);
+    double s = 0.0;
+    for (int i = 0; i < K; ++i) s += t.coef[i] * std::sqrt(2 * i + 0.5) * P[2 * i];
+    return s;
+}
+
+// Phi(x) = (1/c_0) int_0^x psi for 0 <= x <= 1 (Legendre antiderivatives).
+double phi_window(const Tables &t, double x)
+{
+    if (x >= 1.0) return 1.0;
+    int K = (int)t.coef.size();
+    std::vector<double> P;
+    legendre(2 * K + 1, x, P);
+    double s = t.coef[0] * std::sqrt(0.5) * x;
+    for (int i = 1; i < K; ++i) {
+        int k = 2 * i;
+        s += t.coef[i] * std::sqrt(k + 0.5) * (P[k + 1] - P[k - 1]) / (2.0 * k + 1.0);
+    }
+    return s / t.c0;
+}
+
+// Lagrange basis of the p first-kind Chebyshev nodes at xi (barycentric form).
+void lagrange_row(const Tables &t, double xi, double *out)
+{
+    int p = t.p;
+    for (int a = 0; a < p; ++a)
+        if (xi == t.xcheb[a]) {
+            for (int b = 0; b < p; ++b) out[b] = (a == b) ? 1.0 : 0.0;
+            return;
+        }
+    double den = 0.0;
+    for (int a = 0; a < p; ++a) {
+        out[a] = t.bary[a] / (xi - t.xcheb[a]);
+        den += out[a];
+    }
+    for (int a = 0; a < p; ++a) out[a] /= den;
+}
+
+}  // namespace
+
+double pswf_eval(const Tables &t, double x)
+{
+    x = std::fabs(x);
+    if (x <= 1.0) return pswf_series(t, x);
+    // psi(x) = (2/lambda_0) sum_i coef_i sqrt(k+1/2) (-1)^i j_k(c x), k = 2i
+    int K = (int)t.coef.size();
+    std::vector<double> j;
+    sph_bessel(2 * K, t.prm.c * x, j);
+    double s = 0.0;
+    for (int i = 0; i < K; ++i) s += t.coef[i] * std::sqrt(2 * i + 0.5) * ((i & 1) ? -1.0 : 1.0) * j[2 * i];
+    return 2.0 * s / t.lambda0;
+}
+
+void build_tables(const Params &prm, Tables *t)
+{
+    t->prm = prm;
+    const double c = prm.c;
+    // ---- PSWF ground state in the even normalised-Legendre basis
+    const int K = 48;
+    std::vector<double> A((size_t)K * K, 0.0), V, ev;
+    for (int i = 0; i < K; ++i) {
+        double k = 2.0 * i;
+        A[(size_t)i * K + i] = k * (k + 1.0) + c * c * (2.0 * k * k + 2.0 * k - 1.0) / ((2.0 * k - 1.0) * (2.0 * k + 3.0));
+        if (i + 1 < K) {
+            double off = c * c * (k + 1.0) * (k + 2.0) / ((2.0 * k + 3.0) * std::sqrt((2.0 * k + 1.0) * (2.0 * k + 5.0)));
+            A[(size_t)i * K + i + 1] = off;
+            A[(size_t)(i + 1) * K + i] = off;
+        }
+    }
+    jacobi_eigen(K, A, V, ev);
+    int imin = (int)(std::min_element(ev.begin(), ev.end()) - ev.begin());
+    t->coef.resize(K);
+    for (int i = 0; i < K; ++i) t->coef[i] = V[(size_t)i * K + imin];
+    // trim negligible tail, fix the sign so that psi(0) > 0
+    int keep = K;
+    double cmax = 0.0;
+    for (double v : t->coef) cmax = std::max(cmax, std::fabs(v));
+    while (keep > 1 && std::fabs(t->coef[keep - 1]) < 1e-20 * cmax) keep--;
+    t->coef.resize(keep);
+    if (pswf_series(*t, 0.0) < 0)
+        for (double &v : t->coef) v = -v;
+    t->psi0 = pswf_series(*t, 0.0);
+    // int_0^1 sqrt(k+1/2) P_k: sqrt(1/2) for k = 0, 0 for even k >= 2;
+    // int_0^1 x^2 sqrt(k+1/2) P_k: sqrt(1/2)/3 (k = 0), 2 sqrt(5/2)/15 (k = 2).
+    t->c0 = t->coef[0] * std::sqrt(0.5);
+    t->c2 = t->coef[0] * std::sqrt(0.5) / 3.0 + (keep > 1 ? t->coef[1] * std::sqrt(2.5) * 2.0 / 15.0 : 0.0);
+    t->lambda0 = 2.0 * t->c0 / t->psi0;
+
+    // ---- sizes
+    t->p = prm.p;
+    t->nf = prm.nf;
+    t->nn = 2 * prm.nf + 1;
+    t->nh = prm.nf + 1;
+    t->nw = prm.nw;
+    t->nwn = 2 * prm.nw + 1;
+    t->nwh = prm.nw + 1;
+    const int p = t->p;
+
+    // ---- Chebyshev nodes, barycentric weights, child<->parent matrices
+    t->xcheb.resize(p);
+    t->bary.resize(p);
+    for (int j = 0; j < p; ++j) {
+        t->xcheb[j] = std::cos(M_PI * (j + 0.5) / p);
+        t->bary[j] = ((j & 1) ? -1.0 : 1.0) * std::sin((2 * j + 1) * M_PI / (2.0 * p));
+    }
+    t->c2p.assign((size_t)2 * p * p, 0.0);
+    std::vector<double> row(p);
+    for (int s = 0; s < 2; ++s) {
+        double sigma = s ? 1.0 : -1.0;
+        for (int i = 0; i < p; ++i) {
+            lagrange_row(*t, 0.5 * (t->xcheb[i] + sigma), row.data());
+            for (int a = 0; a < p; ++a) t->c2p[((size_t)s * p + a) * p + i] = row[a];
+        }
+    }
+    // ---- proxy -> plane-wave matrices (complex, interleaved)
+    t->epw.assign((size_t)t->nn * p * 2, 0.0);
+    for (int m = -prm.nf; m <= prm.nf; ++m)
+        for (int j = 0; j < p; ++j) {
+            double ph = -M_PI * m * t->xcheb[j] / 3.0;
+            t->epw[((size_t)(m + prm.nf) * p + j) * 2 + 0] = std::cos(ph);
+            t->epw[((size_t)(m + prm.nf) * p + j) * 2 + 1] = std::sin(ph);
+        }
+    t->ew.assign((size_t)t->nwn * p * 2, 0.0);
+    for (int m = -prm.nw; m <= prm.nw; ++m)
+        for (int j = 0; j < p; ++j) {
+            double ph = -prm.hw * m * 0.5 * t->xcheb[j];
+            t->ew[((size_t)(m + prm.nw) * p + j) * 2 + 0] = std::cos(ph);
+            t->ew[((size_t)(m + prm.nw) * p + j) * 2 + 1] = std::sin(ph);
+        }
+
+    // ---- plane-wave weights of D_0 (level l multiplies by 2^l), half spectrum
+    // w_0(m) = [psi(pi|m|/(3c)) - psi(2pi|m|/(3c))] / (3 pi psi(0) |m|^2),
+    // w_0(0) = pi c_2 / (18 c_0)
+    {
+        int maxk2 = 3 * prm.nf * prm.nf;
+        std::vector<double> memo(maxk2 + 1);
+        memo[0] = M_PI * t->c2 / (18.0 * t->c0);
+        for (int k2 = 1; k2 <= maxk2; ++k2) {
+            double km = std::sqrt((double)k2);
+            memo[k2] = (pswf_eval(*t, M_PI * km / (3.0 * c)) - pswf_eval(*t, 2.0 * M_PI * km / (3.0 * c))) /
+                       (3.0 * M_PI * t->psi0 * k2);
+        }
+        t->wd0.assign((size_t)t->nh * t->nn * t->nn, 0.0);
+        for (int m3 = 0; m3 <= prm.nf; ++m3)
+            for (int m2 = -prm.nf; m2 <= prm.nf; ++m2)
+                for (int m1 = -prm.nf; m1 <= prm.nf; ++m1)
+                    t->wd0[((size_t)m3 * t->nn + (m2 + prm.nf)) * t->nn + (m1 + prm.nf)] =
+                        memo[m1 * m1 + m2 * m2 + m3 * m3];
+    }
+    // ---- windowed W_0 weights (hw/2pi)^3 * What_0(hw |m|)
+    {
+        const double Atr = 1.0 + std::sqrt(3.0);
+        const double h = prm.hw, fac = std::pow(h / (2.0 * M_PI), 3);
+        int maxk2 = 3 * prm.nw * prm.nw;
+        std::vector<double> memo(maxk2 + 1);
+        memo[0] = fac * 2.0 * M_PI * Atr * Atr;
+        for (int k2 = 1; k2 <= maxk2; ++k2) {
+            double k = h * std::sqrt((double)k2);
+            double sn = std::sin(0.5 * k * Atr);
+            memo[k2] = fac * 8.0 * M_PI * sn * sn / (k * k) * pswf_eval(*t, k / c) / t->psi0;
+        }
+        t->ww.assign((size_t)t->nwh * t->nwn * t->nwn, 0.0);
+        for (int m3 = 0; m3 <= prm.nw; ++m3)
+            for (int m2 = -prm.nw; m2 <= prm.nw; ++m2)
+                for (int m1 = -prm.nw; m1 <= prm.nw; ++m1)
+                    t->ww[((size_t)m3 * t->nwn + (m2 + prm.nw)) * t->nwn + (m1 + prm.nw)] =
+                        memo[m1 * m1 + m2 * m2 + m3 * m3];
+    }
+    // ---- residual window: Chebyshev coefficients of g(t) = Phi(sqrt t)/sqrt t
+    {
+        const int M = 48;
+        std::vector<double> f(M), cf(M);
+        for (int k = 0; k < M; ++k) {
+            double u = std::cos(M_PI * (k + 0.5) / M);  // node in [-1,1]
+            double tt = 0.5 * (u + 1.0);                 // t in [0,1]
+            double x = std::sqrt(tt);
+            f[k] = (x > 0) ? phi_window(*t, x) / x : t->psi0 / t->c0;
+        }
+        for (int j = 0; j < M; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < M; ++k) s += f[k] * std::cos(M_PI * j * (k + 0.5) / M);
+            cf[j] = (j == 0 ? 1.0 : 2.0) * s / M;
+        }
+        int deg = M - 1;
+        while (deg > 0 && std::fabs(cf[deg]) < 1e-17 * std::fabs(cf[0])) deg--;
+        t->gdeg = deg;
+        t->gcheb.assign(cf.begin(), cf.begin() + deg + 1);
+    }
+}
+
+}  // namespace dmk

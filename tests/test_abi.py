@@ -1,0 +1,79 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+that include/dmk.h declares, validates arguments before touching a device,
+and its host-side tables (Step 1 of Sec. 3.6) agree with the oracle's
+independently computed PSWF, window and plane-wave weights."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2308_00292_amd as dmk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "dmk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.findall(r"^\s*(?:dmk_status|void|const char \*)\s*(dmk_\w+)\s*\(", src, flags=re.M)
+
+
+def test_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) == 10
+    assert sorted(names) == sorted(dmk.SYMBOLS)
+    L = C.CDLL(dmk.LIBPATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_argument_errors_without_device():
+    L = dmk.lib()
+    h = C.c_void_p()
+    assert L.dmk_plan(2, 0, 1e-6, 10, None, None, None, C.byref(h)) == -2  # dim
+    assert L.dmk_plan(3, 1, 1e-6, 10, None, None, None, C.byref(h)) == -2  # kernel
+    assert L.dmk_plan(3, 0, 1e-6, -1, None, None, None, C.byref(h)) == -1  # n < 0
+    assert L.dmk_plan(3, 0, 3e-7, 10, C.c_void_p(1), None, None, C.byref(h)) == -2  # tol
+    assert L.dmk_plan(3, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # NULL pts
+    assert b"NULL" in L.dmk_last_error()
+    assert L.dmk_eval(None, None, None, None) == -1
+    assert h.value is None
+    with pytest.raises(dmk.DmkError):
+        dmk.precompute_probe(1e-7, 0, np.zeros(1))
+    with pytest.raises(dmk.DmkError):
+        dmk.precompute_probe(1e-6, 9, np.zeros(1))
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-5, 1e-6])
+def test_host_tables_match_oracle(oracle_mod, tol):
+    pr = oracle_mod.params_for(tol)
+    ps = oracle_mod.PSWF(pr.c)
+    c, nf, p, nw, hw, gdeg = dmk.precompute_probe(tol, 5, n=6)
+    assert (c, int(nf), int(p), int(nw)) == (pr.c, pr.nf, pr.p, pr.nw) and hw == pr.hw
+    psi0, c0, c2, lam = dmk.precompute_probe(tol, 4, n=4)
+    assert psi0 == pytest.approx(ps.psi0, rel=1e-13)
+    assert c0 == pytest.approx(ps.c0, rel=1e-13)
+    assert c2 == pytest.approx(ps.c2, rel=1e-12)
+    assert lam == pytest.approx(ps.lambda0, rel=1e-13)
+    xs = np.array([0.0, 0.25, 0.8, 1.0, 1.3, 2.2, 3.2])
+    got = dmk.precompute_probe(tol, 0, xs)
+    ref = np.array([ps.psi(x) / ps.psi0 for x in xs])
+    assert np.max(np.abs(got - ref)) < 1e-14
+    ts = np.linspace(0.0, 1.0, 41)
+    got = dmk.precompute_probe(tol, 1, ts)
+    ref = np.array([ps.psi0 / ps.c0 if t == 0 else ps.phi(np.sqrt(t)) / np.sqrt(t) for t in ts])
+    assert np.max(np.abs(got - ref)) < 1e-13
+    k2 = np.arange(0, 3 * nf * nf + 1, 3.0)
+    got = dmk.precompute_probe(tol, 2, k2)
+    h = 2 * np.pi / 3
+    ref = np.array([(h / (2 * np.pi)) ** 3 * ps.dhat(0, h * np.sqrt(k)) for k in k2])
+    ok = ~np.isnan(got)
+    assert ok.sum() > 10
+    assert np.max(np.abs(got[ok] - ref[ok])) < 1e-13 * np.max(np.abs(ref))
+    k2 = np.arange(0, 3 * nw * nw + 1, 4.0)
+    got = dmk.precompute_probe(tol, 3, k2)
+    ref = np.array([(hw / (2 * np.pi)) ** 3 * ps.w0hat(hw * np.sqrt(k)) for k in k2])
+    ok = ~np.isnan(got)
+    assert np.max(np.abs(got[ok] - ref[ok])) < 1e-13 * np.max(np.abs(ref))

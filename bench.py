@@ -1,0 +1,181 @@
+"""Benchmark of the DMK point code on one MI355X.
+
+One step = one dmk_eval (every stage of the eval pipeline: upward pass, root
+window, plane-wave stages on every level, leaf evaluation, residual sums,
+scatter) on a plan built once outside the timed region, with points and
+charges resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                  [--precision fp64|mixed] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "points/s, 3D Laplace DMK at 1e-6 rel ℓ2: mixed+batched vs plain FP64, 1 GPU"
+PEAK = {"hbm": (8000.0, "GB/s"), "alu64": (78.6, "TFLOP/s"), "alu32": (157.3, "TFLOP/s")}
+# bound of each stage: memory streams vs arithmetic on the vector ALUs
+STAGE_BOUND = {"gather": "hbm", "finalize": "hbm", "pwshift": "hbm", "upward": "alu", "root": "alu",
+               "proxy2pw": "alu", "local": "alu", "pw2grid": "alu", "leaf": "alu", "residual": "alu"}
+STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward", "root": "k_root_w0",
+                "proxy2pw": "k_proxy2pw", "local": "k_local_init", "pwshift": "k_pwshift",
+                "pw2grid": "k_pw2grid", "leaf": "k_leaf_eval", "residual": "k_residual",
+                "finalize": "k_finalize"}
+WORKLOADS = {
+    "cfg3_clustered_10m": "3-D Laplace, N=1e7 clustered (70% on the unit sphere, 30% in 3 Gaussian "
+                          "blobs sigma=1e-3), charges U[-1,1], leaf<=64, tol 1e-6",
+    "cfg2_uniform_1m": "3-D Laplace, N=1e6 uniform in the unit cube, charges U[-1,1], leaf<=64, tol 1e-6",
+    "cfg1_uniform_2k": "3-D Laplace, N=2000 uniform in the unit cube, leaf<=50, tol 1e-6",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(pts, q, ns, tol, seed=7):
+    """The oracle (plain FP64 C, OpenMP over all host threads) on a random
+    subset of the same point set, sized for roughly 10-20 s of CPU work."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    n = len(q)
+    m0 = min(n, 50_000)
+    idx = rng.choice(n, m0, replace=False)
+    _, _, te = oracle.dmk_run(pts[idx], q[idx], tol, ns)
+    rate = m0 / te
+    m = int(min(n, max(100_000, min(2_000_000, rate * 15.0))))
+    idx = rng.choice(n, m, replace=False)
+    _, tp, te = oracle.dmk_run(pts[idx], q[idx], tol, ns)
+    return {"value": m / te, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"random subset of {m} of the {n} points (same distribution), eval phase "
+                      f"{te:.2f} s, plan {tp:.2f} s excluded, FP64, tol {tol:g}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg3_clustered_10m", choices=list(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sample-targets", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import dmk_inputs
+    import paper_2308_00292_amd as dmk
+
+    tol = 1e-6
+    prec = dmk.DMK_FP64 if args.precision == "fp64" else dmk.DMK_MIXED
+    log(f"[bench] generating {args.workload}")
+    pts, q, ns = dmk_inputs.make(args.workload)
+    n = len(q)
+    dev = torch.device("cuda:0")
+    tp_ = torch.from_numpy(pts).to(dev)
+    tq = torch.from_numpy(q).to(dev)
+    torch.cuda.synchronize()
+    log("[bench] plan")
+    t0 = time.perf_counter()
+    plan = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=prec)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info()
+    log(f"[bench] plan {t_plan:.2f} s: levels {info['nlevels']} boxes {info['nbox']} leaves {info['nleaf']}")
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.eval(tq, out)
+    torch.cuda.synchronize()
+    log("[bench] timed region")
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    plan.stage_timing(True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.eval(tq, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = ev0.elapsed_time(ev1)
+    stage_ms, launches = plan.stage_times()
+    plan.stage_timing(False)
+    ms_step = gpu_ms / args.steps
+    value = n / (ms_step * 1e-3)
+    log(f"[bench] {ms_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} wall) -> {value:.4g} points/s")
+
+    # roofline of the dominant stage (live HIP events of the timed region)
+    flops, byts = plan.stage_work()
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    avg_ms = stage_ms[dom] / max(1, launches[dom])
+    per_launch = (byts[dom] if STAGE_BOUND[dom] == "hbm" else flops[dom]) * args.steps / max(1, launches[dom])
+    if STAGE_BOUND[dom] == "hbm":
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9
+        peak, unit = PEAK["hbm"]
+    else:
+        achieved = per_launch / (avg_ms * 1e-3) / 1e12
+        peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
+    roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "kernel": STAGE_KERNEL[dom], "stage": dom,
+            "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / args.steps}
+    stages = {}
+    for k in stage_ms:
+        ms = stage_ms[k] / args.steps
+        ent = {"ms": round(ms, 4)}
+        if ms > 0 and flops[k] > 0:
+            ent["tflops"] = round(flops[k] / (ms * 1e-3) / 1e12, 3)
+        if ms > 0 and byts[k] > 0:
+            ent["gbps"] = round(byts[k] / (ms * 1e-3) / 1e9, 1)
+        stages[k] = ent
+
+    # sampled parity against direct summation by the oracle
+    import oracle
+    rng = np.random.default_rng(11)
+    sidx = rng.choice(n, min(n, args.sample_targets), replace=False)
+    ud = oracle.direct(pts, q, sidx)
+    got = out.cpu().numpy()[sidx]
+    err = float(np.linalg.norm(got - ud) / np.linalg.norm(ud))
+    log(f"[bench] sampled rel l2 vs direct sum ({len(sidx)} targets): {err:.3e}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline(pts, q, ns, tol)
+        log(f"[bench] cpu baseline {cpu['value']:.4g} points/s on {cpu['cores']} threads")
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64" if prec == dmk.DMK_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n_points": n,
+                   "tol": tol, "leaf_max": ns, "precision": args.precision, "batched": False,
+                   "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"],
+                   "p": info["p"], "nf": info["nf"], "t_plan_s": round(t_plan, 3),
+                   "end_to_end_points_per_s": n / (t_plan + ms_step * 1e-3),
+                   "sampled_rel_l2_vs_direct": err, "stage_ms_per_step": stages},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -213,6 +213,45 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
  */
 dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x, double *out);
 
+/* Stages of dmk_eval, in pipeline order (indices into the arrays of
+ * dmk_stage_times and dmk_stage_work). */
+enum {
+    DMK_STAGE_GATHER = 0,    /* charges into tree order                      */
+    DMK_STAGE_UPWARD = 1,    /* proxy charges of F_out boxes (Step 2)        */
+    DMK_STAGE_ROOT = 2,      /* windowed kernel W_0 at the root              */
+    DMK_STAGE_PROXY2PW = 3,  /* outgoing plane waves (Step 3)                */
+    DMK_STAGE_LOCAL = 4,     /* parent -> child local values (Step 3)        */
+    DMK_STAGE_PWSHIFT = 5,   /* diagonal translation to colleagues (Step 3)  */
+    DMK_STAGE_PW2GRID = 6,   /* incoming plane waves -> local values         */
+    DMK_STAGE_LEAF = 7,      /* far potential at leaf targets                */
+    DMK_STAGE_RESIDUAL = 8,  /* residual-kernel sums and self term (4-5)     */
+    DMK_STAGE_FINALIZE = 9,  /* scaling and scatter to input order           */
+    DMK_NSTAGES = 10
+};
+
+/*
+ * dmk_stage_timing -- enable (1) or disable (0) per-stage HIP events in the
+ * following dmk_eval calls of the plan (the per-stage breakdown the paper
+ * reports in Table 2).  Enabling resets the totals.
+ */
+dmk_status dmk_stage_timing(dmk_plan_t plan, int enable);
+
+/*
+ * dmk_stage_times -- totals since timing was enabled, per stage: elapsed
+ * milliseconds between events recorded on the eval stream before and after
+ * each kernel launch (HOST array ms[nstages]) and the number of launches
+ * (HOST array launches[nstages]).  Synchronises the plan's last stream.
+ */
+dmk_status dmk_stage_times(dmk_plan_t plan, double *ms, int64_t *launches, int nstages);
+
+/*
+ * dmk_stage_work -- algorithmic work of ONE dmk_eval per stage, from the
+ * plan's box and pair counts (HOST arrays of nstages entries): flops (0 for
+ * stages bound by memory) and bytes that must cross HBM at least once.
+ * The per-unit figures are documented beside the kernels.
+ */
+dmk_status dmk_stage_work(dmk_plan_t plan, double *flops, double *bytes, int nstages);
+
 /* dmk_plan_destroy -- free a plan (NULL is ignored).  Synchronises the
  * plan's last stream first. */
 void dmk_plan_destroy(dmk_plan_t plan);

@@ -21,7 +21,11 @@ DMK_FLAG_KEEP_LOCALS = 1
 # exported symbols, in the order of include/dmk.h
 SYMBOLS = ["dmk_plan", "dmk_eval", "dmk_eval_parts", "dmk_plan_info", "dmk_export_tree",
            "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
+           "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
            "dmk_plan_destroy", "dmk_last_error"]
+
+STAGES = ["gather", "upward", "root", "proxy2pw", "local", "pwshift", "pw2grid", "leaf",
+          "residual", "finalize"]
 
 
 class Opts(C.Structure):
@@ -62,6 +66,9 @@ def lib():
         L.dmk_export_near_lists.argtypes = [vp, vp, vp, vp]
         L.dmk_copy_box_data.argtypes = [vp, C.c_int, i64, f64p]
         L.dmk_precompute_probe.argtypes = [C.c_double, C.c_int, i64, vp, vp]
+        L.dmk_stage_timing.argtypes = [vp, C.c_int]
+        L.dmk_stage_times.argtypes = [vp, vp, vp, C.c_int]
+        L.dmk_stage_work.argtypes = [vp, vp, vp, C.c_int]
         L.dmk_plan_destroy.argtypes = [vp]
         L.dmk_plan_destroy.restype = None
         L.dmk_last_error.restype = C.c_char_p
@@ -176,6 +183,21 @@ class Plan:
         src = np.zeros(max(int(off[-1]), 1), np.int64)
         _check(lib().dmk_export_near_lists(self._h, _np_ptr(leaf), _np_ptr(off), _np_ptr(src)))
         return leaf[:nl], off, src[: int(off[-1])]
+
+    def stage_timing(self, enable=True):
+        _check(lib().dmk_stage_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().dmk_stage_times(self._h, _np_ptr(ms), _np_ptr(cnt), len(STAGES)))
+        return dict(zip(STAGES, ms)), dict(zip(STAGES, cnt))
+
+    def stage_work(self):
+        fl = np.zeros(len(STAGES))
+        by = np.zeros(len(STAGES))
+        _check(lib().dmk_stage_work(self._h, _np_ptr(fl), _np_ptr(by), len(STAGES)))
+        return dict(zip(STAGES, fl)), dict(zip(STAGES, by))
 
     def box_data(self, what, box):
         p = self.info()["p"]

@@ -97,7 +97,8 @@ dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const dou
         if (!params_for(tol, &prm)) throw Error{DMK_ERR_UNSUPPORTED, "tol must be one of 1e-3, 1e-5, 1e-6, 1e-9, 1e-12"};
         if (prm.p > 18) throw Error{DMK_ERR_UNSUPPORTED, "tol below 1e-6 needs proxy order > 18, not built"};
         if (o.precision != DMK_FP64 && o.precision != DMK_MIXED) throw Error{DMK_ERR_ARG, "unknown precision"};
-        if (o.precision == DMK_MIXED) throw Error{DMK_ERR_UNSUPPORTED, "mixed precision is not built yet"};
+        if (o.precision == DMK_MIXED && tol < 1e-6 * (1 - 1e-9))
+            throw Error{DMK_ERR_PRECISION, "mixed precision needs tol >= 1e-6"};
         if (o.leaf_max < 0 || o.max_depth < 0 || o.max_depth > 21) throw Error{DMK_ERR_ARG, "bad leaf_max/max_depth"};
         auto *P = new Plan();
         try {
@@ -115,6 +116,7 @@ dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const dou
             build_tree(P, pts, s);
             build_lists(P, s);
             alloc_workspace(P);
+            count_work(P, s);
         } catch (...) {
             plan_free_all(P);
             delete P;
@@ -233,19 +235,29 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
         const int64_t p3 = (int64_t)P->p * P->p * P->p;
         int32_t slot = -1;
         const double *base = nullptr;
+        const void *vbase = nullptr;
         if (what == 0) {
             DMK_HIP(hipMemcpy(&slot, P->proxy_slot + box, sizeof(int32_t), hipMemcpyDeviceToHost));
-            base = P->proxy;
+            vbase = P->proxy;
         } else if (what == 1) {
             DMK_HIP(hipMemcpy(&slot, P->local_slot + box, sizeof(int32_t), hipMemcpyDeviceToHost));
-            base = P->local;
+            vbase = P->local;
         } else {
             throw Error{DMK_ERR_ARG, "what must be 0 or 1"};
         }
+        (void)base;
         if (slot < 0) throw Error{DMK_ERR_ARG, "box holds no such data"};
         if (P->last_stream) DMK_HIP(hipStreamSynchronize(P->last_stream));
         DMK_HIP(hipDeviceSynchronize());
-        DMK_HIP(hipMemcpy(out, base + (int64_t)slot * p3, p3 * sizeof(double), hipMemcpyDeviceToHost));
+        if (P->precision == DMK_FP64) {
+            DMK_HIP(hipMemcpy(out, (const double *)vbase + (int64_t)slot * p3, p3 * sizeof(double),
+                              hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> h(p3);
+            DMK_HIP(hipMemcpy(h.data(), (const float *)vbase + (int64_t)slot * p3, p3 * sizeof(float),
+                              hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < p3; ++i) out[i] = h[i];
+        }
     });
 }
 
@@ -288,7 +300,8 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
                     for (int m2 = -nf; m2 <= nf && std::isnan(v); ++m2)
                         for (int m1 = -nf; m1 <= nf; ++m1)
                             if ((long)(m1 * m1 + m2 * m2 + m3 * m3) == k2) {
-                                v = w[((size_t)m3 * nn + (m2 + nf)) * nn + (m1 + nf)];
+                                v = (what == 2) ? w[((size_t)(m1 + nf) * (nf + 1) + m3) * nn + (m2 + nf)]
+                                                : w[((size_t)m3 * nn + (m2 + nf)) * nn + (m1 + nf)];
                                 break;
                             }
             } else {
@@ -299,12 +312,73 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
     });
 }
 
+dmk_status dmk_stage_timing(dmk_plan_t plan, int enable)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (P->last_stream) DMK_HIP(hipStreamSynchronize(P->last_stream));
+        for (auto &r : P->pending) {
+            P->event_pool.push_back(r.a);
+            P->event_pool.push_back(r.b);
+        }
+        P->pending.clear();
+        for (int i = 0; i < DMK_NSTAGES; ++i) {
+            P->stage_ms[i] = 0.0;
+            P->stage_launches[i] = 0;
+        }
+        P->timing = enable != 0;
+    });
+}
+
+dmk_status dmk_stage_times(dmk_plan_t plan, double *ms, int64_t *launches, int nstages)
+{
+    return guarded([&] {
+        if (!plan || nstages < 0) throw Error{DMK_ERR_ARG, "bad argument"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (P->last_stream) DMK_HIP(hipStreamSynchronize(P->last_stream));
+        for (auto &r : P->pending) {
+            float t = 0.0f;
+            DMK_HIP(hipEventSynchronize(r.b));
+            DMK_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            P->stage_ms[r.stage] += t;
+            P->stage_launches[r.stage] += 1;
+            P->event_pool.push_back(r.a);
+            P->event_pool.push_back(r.b);
+        }
+        P->pending.clear();
+        for (int i = 0; i < nstages && i < DMK_NSTAGES; ++i) {
+            if (ms) ms[i] = P->stage_ms[i];
+            if (launches) launches[i] = P->stage_launches[i];
+        }
+    });
+}
+
+dmk_status dmk_stage_work(dmk_plan_t plan, double *flops, double *bytes, int nstages)
+{
+    return guarded([&] {
+        if (!plan || nstages < 0) throw Error{DMK_ERR_ARG, "bad argument"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        double F[DMK_NSTAGES], B[DMK_NSTAGES];
+        stage_work(P, F, B);
+        for (int i = 0; i < nstages && i < DMK_NSTAGES; ++i) {
+            if (flops) flops[i] = F[i];
+            if (bytes) bytes[i] = B[i];
+        }
+    });
+}
+
 void dmk_plan_destroy(dmk_plan_t plan)
 {
     if (!plan) return;
     Plan *P = reinterpret_cast<Plan *>(plan);
     if (P->last_stream) (void)hipStreamSynchronize(P->last_stream);
     (void)hipDeviceSynchronize();
+    for (auto &r : P->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
     plan_free_all(P);
     delete P;
 }

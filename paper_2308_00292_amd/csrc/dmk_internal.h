@@ -50,10 +50,11 @@ struct Tables {
     std::vector<double> c2p;               // [2][p][p] A_s[a][i] = l_a((x_i + s)/2)
     std::vector<double> epw;               // [nn][p][2] exp(-i pi m x_j / 3)
     std::vector<double> ew;                // [nwn][p][2] exp(-i hw m x_j / 2)
-    std::vector<double> wd0;               // [nh][nn][nn] D_0 weights, half spectrum
-    std::vector<double> ww;                // [nwh][nwn][nwn] W_0 weights
+    std::vector<double> wd0;               // [nn][nh][nn] D_0 weights, half spectrum, [m1][m3][m2]
+    std::vector<double> ww;                // [nwh][nwn][nwn] W_0 weights, [m3][m2][m1]
     std::vector<double> gcheb;             // Chebyshev coefficients of Phi(sqrt t)/sqrt t on [0,1]
-    int gdeg;
+    int gdeg;                              // degree kept for FP64 evaluation
+    int gdeg32;                            // degree kept for FP32 evaluation
 };
 void build_tables(const Params &prm, Tables *t);
 
@@ -63,7 +64,7 @@ double pswf_eval(const Tables &t, double x);  // any real x
 // ------------------------------------------------------------------- plan
 struct LevelLists {
     // offsets into the concatenated device lists, per level [nlevels+1]
-    std::vector<int64_t> fout_off, ne_off, fin_off, leaf_off;
+    std::vector<int64_t> fout_off, fin_off, anc_off, leaf_off;
 };
 
 struct Plan {
@@ -88,30 +89,47 @@ struct Plan {
     int32_t *pstart = nullptr, *pcount = nullptr;
     uint8_t *bflags = nullptr;  // bit0 leaf, bit1 fout, bit2 fin, bit3 terminal
     int32_t *colleague = nullptr;  // [nbox][27]
+    int32_t *anchor = nullptr;     // [nbox] nearest ancestor-or-self holding local values
     int32_t *ncoarse = nullptr, *coarse = nullptr;  // [nbox], [nbox][7]
     double *bcenter = nullptr;     // [nbox][3]
 
     // work lists (device, concatenated by level) and slot maps
     LevelLists ll;
-    int32_t *l_fout = nullptr, *l_ne = nullptr, *l_fin = nullptr, *l_leaf = nullptr;
+    int32_t *l_fout = nullptr, *l_fin = nullptr, *l_anc = nullptr, *l_leaf = nullptr;
     int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
-    int64_t nfout = 0, nne = 0, nfin = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
+    int64_t nfout = 0, nfin = 0, nanc = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
 
     // near (residual) lists in gather form over l_leaf order
     int32_t *nl_off = nullptr, *nl_src = nullptr;
     int64_t nl_total = 0, npairs = 0;
 
-    // device tables
+    // device tables, FP64 and FP32 copies
     double *d_c2p = nullptr, *d_epw = nullptr, *d_ew = nullptr, *d_wd0 = nullptr,
            *d_ww = nullptr, *d_gcheb = nullptr, *d_xcheb = nullptr, *d_bary = nullptr;
+    float *f_c2p = nullptr, *f_epw = nullptr, *f_wd0 = nullptr, *f_gcheb = nullptr, *f_xcheb = nullptr,
+          *f_bary = nullptr;
 
-    // eval workspace
-    double *qs = nullptr, *ufar = nullptr, *ures = nullptr;
-    double *proxy = nullptr;   // [nfout][p^3]
-    double *local = nullptr;   // [nne][p^3]
-    double *phi = nullptr;     // [max_fout_level][nh*nn*nn][2]
-    double *psi = nullptr;     // [max_fin_level][nh*nn*nn][2]
-    double *w0vals = nullptr;  // [p^3] W_0 values on the root grid
+    // eval workspace (element type: double for DMK_FP64, float for DMK_MIXED)
+    double *qs = nullptr, *ufar = nullptr, *ures = nullptr, *rootscratch = nullptr;
+    void *proxy = nullptr;   // [nfout][p^3]
+    void *local = nullptr;   // [nanc][p^3]
+    void *phi = nullptr;     // [max_fout_level][2][nh*nn*nn] planar
+    void *psi = nullptr;     // [max_fin_level][2][nh*nn*nn] planar
+    void *w0vals = nullptr;  // [p^3] W_0 values on the root grid
+
+    // per-stage event timing (dmk_stage_timing / dmk_stage_times)
+    struct Rec { int stage; hipEvent_t a, b; };
+    bool timing = false;
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> event_pool;
+    double stage_ms[DMK_NSTAGES] = {0};
+    int64_t stage_launches[DMK_NSTAGES] = {0};
+
+    // algorithmic work counts gathered at plan time
+    int64_t n_anterp = 0;      // points anterpolated straight onto F_out parents
+    int64_t n_merge = 0;       // F_out children merged by c2p
+    int64_t n_shift_pairs = 0; // (F_in box, F_out colleague) pairs
+    int64_t npairs_in = 0;     // residual pairs closer than the source box side
 
     std::vector<void *> allocations;
     int64_t device_bytes = 0;
@@ -128,5 +146,7 @@ void upload_tables(Plan *P, hipStream_t s);
 void alloc_workspace(Plan *P);
 void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
               hipStream_t s);
+void count_work(Plan *P, hipStream_t s);
+void stage_work(const Plan *P, double *flops, double *bytes);
 
 }  // namespace dmk

@@ -1,31 +1,35 @@
-// Steps 2-5 of the discrete DMK algorithm (Sec. 3.6) on gfx950, FP64.
+// Steps 2-5 of the discrete DMK algorithm (Sec. 3.6) on gfx950.
 //
-// Stage map (one kernel per stage and level; one workgroup per box):
-//   k_gather_q      charges into Morton order
-//   k_upward        proxy charges of every F_out box (Step 2): F_out children
-//                   are merged with the child->parent anterpolation matrices
-//                   (Lemma 2.1); the points of all other children are
-//                   anterpolated straight onto the parent grid (Def. 2.1).
-//                   Both give the same proxies (Lemma 2.1 is exact), the
-//                   second skips proxy grids nobody else reads.
-//   k_root_w0       windowed kernel W_0 over the unit box (root only)
-//   k_proxy2pw      outgoing plane waves Phi_l(B) of F_out boxes
-//                   (eq. outgoingexpansion2), Hermitian half spectrum
-//   k_local_init    local values inherited from the parent (Lemma 2.2)
-//   k_pwshift       incoming plane waves Psi_l(B) by diagonal translation
-//                   from F_out colleagues (eq. diagonaltranslation); with
-//                   h_l s_l = 2 pi / 3 the phases are cube roots of unity
-//   k_pw2grid       Psi_l(B) -> values on B's Chebyshev grid
-//                   (eq. incomingexpansion2)
-//   k_leaf_eval     far potential at the targets of each leaf (eq.
-//                   farpotential) by tensor Lagrange interpolation
-//   k_residual      residual-kernel sums (Step 4) in gather form, including
-//                   the r = 0 self correction (Step 5)
-//   k_finalize      scale by 1/(4 pi S) and scatter to input order
+// Every stage is one kernel per tree level (one workgroup per box), written
+// once as a template over the arithmetic type T (double for the FP64 path,
+// float for the mixed path), the Chebyshev order P and the plane-wave half
+// width NF.  The tensor-product transforms are sequences of small dense
+// contractions (Lemmas 2.1/2.2, eqs. outgoingexpansion2/incomingexpansion2);
+// they run as register-tiled GEMMs on operands staged in LDS.
 //
-// Data layout in HBM: sorted points as SoA FP64; per-box p^3 arrays with the
-// x index slowest, (i*p + j)*p + k; plane waves as [m3][m2][m1] complex
-// (interleaved re, im) with m3 = 0..nf (half spectrum) and m1, m2 = -nf..nf.
+//   k_upward     proxy charges of each F_out box: F_out children are merged
+//                with the child->parent anterpolation matrices (Lemma 2.1);
+//                the points of all other children are anterpolated straight
+//                onto the parent's grid (Def. 2.1, exact by Lemma 2.1).
+//   k_root_w0    windowed kernel W_0 on the root grid (FP64 always).
+//   k_proxy2pw   outgoing plane waves Phi_l(B) of F_out boxes.
+//   k_pwshift    incoming plane waves Psi_l(B) from the F_out colleagues
+//                (diagonal translation; with h_l s_l = 2 pi/3 the phases
+//                are cube roots of unity).
+//   k_local_pw   local values of the anchor boxes (the root and the boxes
+//                with F_in): interpolation of the nearest anchor ancestor's
+//                polynomial to the box's grid (Lemma 2.2) plus the box's own
+//                incoming plane waves evaluated on that grid.
+//   k_leaf       far potential at the targets of each leaf, read from its
+//                anchor's polynomial (a box without F_in adds nothing of its
+//                own, so its polynomial is its anchor's, restricted).
+//   k_residual   residual-kernel sums in gather form with the r = 0 self
+//                correction (Steps 4-5).
+//   k_finalize   scaling by 1/(4 pi S), scatter to input order.
+//
+// HBM layout: sorted points SoA FP64; per-box p^3 arrays (x index slowest);
+// plane waves planar (all real parts, then all imaginary parts), index
+// [m1][m3][m2] with m1, m2 in -nf..nf and m3 in 0..nf (Hermitian half).
 #include <algorithm>
 #include <cmath>
 
@@ -36,362 +40,339 @@ namespace dmk {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int MAXP = 18;                 // largest proxy order on the device
-constexpr int MAXNPT = (MAXP * MAXP * MAXP + TPB - 1) / TPB;  // owned entries per thread
-constexpr int MAXN = 2 * 12 + 1;         // largest plane-wave width (nf <= 12)
-constexpr int GSL = 4;                   // m3 slices per group in pw2grid
 
+// --------------------------------------------------------------- GEMM
+// C(b,m,n) = [C(b,m,n) +] sum_k A(b,m,k) B(b,k,n), all operands addressed by
+// strides.  Each thread owns a TM x TN tile whose rows are MT apart and whose
+// columns are NT apart (MT, NT = number of tiles along m, n), so consecutive
+// threads read consecutive columns of B and share rows of A.
+template <typename T, int TM, int TN, bool ACC>
+__device__ inline void gemm(int nb, int M, int N, int K, const T *A, int sAb, int sAm, int sAk, const T *B,
+                            int sBb, int sBk, int sBn, T *C, int sCb, int sCm, int sCn)
+{
+    const int MT = (M + TM - 1) / TM, NT = (N + TN - 1) / TN;
+    const int ntile = nb * MT * NT;
+    for (int t = threadIdx.x; t < ntile; t += TPB) {
+        const int b = t / (MT * NT), r = t % (MT * NT);
+        const int mt = r / NT, nt = r % NT;
+        const T *Ab = A + (int64_t)b * sAb;
+        const T *Bb = B + (int64_t)b * sBb;
+        T acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = T(0);
+        for (int k = 0; k < K; ++k) {
+            T a[TM], bb[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                int m = mt + i * MT;
+                a[i] = (m < M) ? Ab[m * sAm + k * sAk] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                int n = nt + j * NT;
+                bb[j] = (n < N) ? Bb[k * sBk + n * sBn] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] += a[i] * bb[j];
+        }
+        T *Cb = C + (int64_t)b * sCb;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                int m = mt + i * MT, n = nt + j * NT;
+                if (m < M && n < N) {
+                    if (ACC) Cb[m * sCm + n * sCn] += acc[i][j];
+                    else Cb[m * sCm + n * sCn] = acc[i][j];
+                }
+            }
+    }
+}
+
+// Same contraction with the output kept in registers: acc[i][j] holds
+// C(m = mt + i MT, n = nt + j NT) of the thread's single tile (requires
+// MT * NT <= TPB).  Used for the per-box accumulators of shape p x p^2.
+template <typename T, int TM, int TN>
+__device__ inline void gemm_regs(int M, int N, int K, const T *A, int sAm, int sAk, const T *B, int sBk, int sBn,
+                                 T (&acc)[TM][TN])
+{
+    const int MT = (M + TM - 1) / TM, NT = (N + TN - 1) / TN;
+    const int t = threadIdx.x;
+    if (t >= MT * NT) return;
+    const int mt = t / NT, nt = t % NT;
+    for (int k = 0; k < K; ++k) {
+        T a[TM], bb[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            int m = mt + i * MT;
+            a[i] = (m < M) ? A[m * sAm + k * sAk] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            int n = nt + j * NT;
+            bb[j] = (n < N) ? B[k * sBk + n * sBn] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] += a[i] * bb[j];
+    }
+}
+
+// Complex contraction on planar operands (real and imaginary parts at
+// separate base pointers with identical strides).
+template <typename T, int TM, int TN, bool ACC>
+__device__ inline void cgemm(int nb, int M, int N, int K, const T *Ar, const T *Ai, int sAb, int sAm, int sAk,
+                             const T *Br, const T *Bi, int sBb, int sBk, int sBn, T *Cr, T *Ci, int sCb, int sCm,
+                             int sCn)
+{
+    const int MT = (M + TM - 1) / TM, NT = (N + TN - 1) / TN;
+    const int ntile = nb * MT * NT;
+    for (int t = threadIdx.x; t < ntile; t += TPB) {
+        const int b = t / (MT * NT), r = t % (MT * NT);
+        const int mt = r / NT, nt = r % NT;
+        const int64_t oA = (int64_t)b * sAb, oB = (int64_t)b * sBb;
+        T re[TM][TN], im[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) re[i][j] = im[i][j] = T(0);
+        for (int k = 0; k < K; ++k) {
+            T ar[TM], ai[TM], br[TN], bi[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                int m = mt + i * MT;
+                bool ok = m < M;
+                ar[i] = ok ? Ar[oA + m * sAm + k * sAk] : T(0);
+                ai[i] = ok ? Ai[oA + m * sAm + k * sAk] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                int n = nt + j * NT;
+                bool ok = n < N;
+                br[j] = ok ? Br[oB + k * sBk + n * sBn] : T(0);
+                bi[j] = ok ? Bi[oB + k * sBk + n * sBn] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    re[i][j] += ar[i] * br[j] - ai[i] * bi[j];
+                    im[i][j] += ar[i] * bi[j] + ai[i] * br[j];
+                }
+        }
+        const int64_t oC = (int64_t)b * sCb;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                int m = mt + i * MT, n = nt + j * NT;
+                if (m < M && n < N) {
+                    int64_t o = oC + m * sCm + n * sCn;
+                    if (ACC) { Cr[o] += re[i][j]; Ci[o] += im[i][j]; }
+                    else { Cr[o] = re[i][j]; Ci[o] = im[i][j]; }
+                }
+            }
+    }
+}
+
+// tile shapes: R* for the p x p^2 per-box accumulators (one tile per
+// thread), Z* for the mode products on p^2 x p and p x p operands
+template <int P> struct Tiles;
+template <> struct Tiles<18> { static constexpr int RM = 3, RN = 9, ZM = 3, ZN = 6; };
+template <> struct Tiles<15> { static constexpr int RM = 3, RN = 5, ZM = 3, ZN = 5; };
+template <> struct Tiles<9> { static constexpr int RM = 1, RN = 3, ZM = 3, ZN = 3; };
+
+// store a p x p^2 register accumulator (tile layout of gemm_regs)
+template <typename T, int P, int RM, int RN>
+__device__ inline void store_tiles(const T (&acc)[RM][RN], T *dst)
+{
+    constexpr int P2 = P * P, MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;
+    const int t = threadIdx.x;
+    if (t >= MT * NT) return;
+    const int mt = t / NT, nt = t % NT;
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+            int m = mt + i * MT, n = nt + j * NT;
+            if (m < P && n < P2) dst[m * P2 + n] = acc[i][j];
+        }
+}
+
+// ------------------------------------------------------------ device view
+template <typename T>
 struct Dev {
-    int p, p2, p3, nf, nn, nh, nw, nwn, nwh, gdeg;
-    const double *X, *Y, *Z;
-    const int32_t *pstart, *pcount, *child0, *parent, *col, *proxy_slot, *local_slot, *psi_slot, *blevel;
+    int p, nf, nn, nh, nw, nwn, nwh, gdeg;
+    const double *X, *Y, *Z, *qs;
+    const int32_t *pstart, *pcount, *child0, *parent, *col, *proxy_slot, *local_slot, *psi_slot, *blevel,
+        *anchor;
     const uint8_t *bflags;
     const double *bcenter;
-    const double *c2p, *epw, *ew, *wd0, *ww, *gcheb, *xcheb, *bary;
-    double *qs, *proxy, *local, *phi, *psi, *w0vals, *ufar, *ures;
+    const T *c2p, *epw, *wd0, *gcheb, *xcheb, *bary;  // tables in T
+    const double *ew64, *ww64, *xcheb64, *bary64;     // FP64 tables
+    T *proxy, *local, *phi, *psi, *w0vals;
+    double *ufar, *ures, *rootscratch;
+    int64_t pwstride;  // elements per plane-wave set (nh * nn * nn)
 };
 
-// Lagrange basis of the Chebyshev nodes at xi (barycentric formula).
-__device__ inline void lagrange_row(const Dev &D, double xi, double *out)
+// Lagrange basis of the Chebyshev nodes at xi (barycentric formula)
+template <typename T>
+__device__ inline void lagrange_row(int p, const T *xc, const T *bw, T xi, T *out)
 {
-    const int p = D.p;
-    double den = 0.0;
+    T den = T(0);
     int hit = -1;
     for (int a = 0; a < p; ++a) {
-        double d = xi - D.xcheb[a];
-        if (d == 0.0) hit = a;
-        double v = D.bary[a] / d;
+        T d = xi - xc[a];
+        if (d == T(0)) hit = a;
+        T v = bw[a] / d;
         out[a] = v;
         den += v;
     }
     if (hit >= 0) {
-        for (int a = 0; a < p; ++a) out[a] = (a == hit) ? 1.0 : 0.0;
+        for (int a = 0; a < p; ++a) out[a] = (a == hit) ? T(1) : T(0);
         return;
     }
-    double inv = 1.0 / den;
+    T inv = T(1) / den;
     for (int a = 0; a < p; ++a) out[a] *= inv;
 }
 
-// Accumulate into the thread's owned entries e = tid + TPB*m of a p^3 grid
-// the anterpolation of points [i0, i1) onto the grid of a box with centre c
-// and side s.  Uses LDS scratch of at most p^3 doubles (chunks of CH points,
-// 3 CH p Lagrange values and CH charges).
-__device__ void anterpolate_points(const Dev &D, int64_t i0, int64_t i1, const double *c, double s,
-                                   double *sL, double *acc)
-{
-    const int p = D.p, p2 = D.p2, p3 = D.p3;
-    const int CH = min(64, p3 / (3 * p + 1));
-    double *Lx = sL, *Ly = Lx + CH * p, *Lz = Ly + CH * p, *qq = Lz + CH * p;
-    const double sc = 2.0 / s;
-    for (int64_t base = i0; base < i1; base += CH) {
-        int cnt = (int)min<int64_t>(CH, i1 - base);
-        __syncthreads();
-        for (int t = threadIdx.x; t < 3 * cnt; t += TPB) {
-            int pt = t / 3, d = t % 3;
-            int64_t i = base + pt;
-            double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
-            double xi = (x - c[d]) * sc;
-            double row[MAXP];
-            lagrange_row(D, xi, row);
-            double *dst = (d == 0 ? Lx : d == 1 ? Ly : Lz) + pt * p;
-            for (int a = 0; a < p; ++a) dst[a] = row[a];
-        }
-        for (int t = threadIdx.x; t < cnt; t += TPB) qq[t] = D.qs[base + t];
-        __syncthreads();
-        for (int m = 0; m < MAXNPT; ++m) {
-            int e = threadIdx.x + TPB * m;
-            if (e >= p3) break;
-            int a0 = e / p2, a1 = (e / p) % p, a2 = e % p;
-            double s_ = 0.0;
-            for (int pt = 0; pt < cnt; ++pt) s_ += Lx[pt * p + a0] * Ly[pt * p + a1] * (Lz[pt * p + a2] * qq[pt]);
-            acc[m] += s_;
-        }
-    }
-}
+__device__ inline double box_side(int level) { return ldexp(1.0, -level); }
 
 // ------------------------------------------------------------------ upward
-__global__ void __launch_bounds__(TPB) k_upward(Dev D, const int32_t *list)
+template <int P> constexpr int up_chunk()
 {
-    extern __shared__ double sm[];
-    const int p = D.p, p2 = D.p2, p3 = D.p3;
-    double *tmp = sm;          // p^3
-    double *buf = tmp + p3;    // p^3 (also point scratch)
-    double *Am = buf + p3;     // 2 p^2
-    const int32_t P = list[blockIdx.x];
-    for (int t = threadIdx.x; t < 2 * p2; t += TPB) Am[t] = D.c2p[t];
-    double acc[MAXNPT];
-    for (int m = 0; m < MAXNPT; ++m) acc[m] = 0.0;
-    const double *cP = D.bcenter + 3 * (int64_t)P;
-    const double sideP = ldexp(1.0, -D.blevel[P]);
+    return (2 * P * P * P) / (4 * P + P * P + 1) < 64 ? (2 * P * P * P) / (4 * P + P * P + 1) : 64;
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
+{
+    constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
+    constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, CH = up_chunk<P>();
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *Am = sm;              // 2 p^2 child->parent matrices
+    T *xc = Am + 2 * P2;     // nodes
+    T *bw = xc + P;          // barycentric weights
+    T *w0 = bw + P;          // work area of 2 p^3
+    const int32_t Pb = list[blockIdx.x];
+    for (int t = threadIdx.x; t < 2 * P2; t += TPB) Am[t] = D.c2p[t];
+    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
+    T acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
+    const double *cP = D.bcenter + 3 * (int64_t)Pb;
+    const double sc = 2.0 / box_side(D.blevel[Pb]);
+    __syncthreads();
     for (int k = 0; k < 8; ++k) {
-        const int32_t C = D.child0[P] + k;
+        const int32_t C = D.child0[Pb] + k;
         const int cnt = D.pcount[C];
         if (cnt == 0) continue;
         if (D.bflags[C] & 2) {
-            const double *src = D.proxy + (int64_t)D.proxy_slot[C] * p3;
-            const double *Ax = Am + ((k >> 2) & 1) * p2, *Ay = Am + ((k >> 1) & 1) * p2, *Az = Am + (k & 1) * p2;
+            // c2p: three mode products with A_sigma (sigma from the child's position)
+            const T *src = D.proxy + (int64_t)D.proxy_slot[C] * P3;
+            T *t1 = w0, *t2 = w0 + P3;
+            const T *Ax = Am + ((k >> 2) & 1) * P2, *Ay = Am + ((k >> 1) & 1) * P2, *Az = Am + (k & 1) * P2;
             __syncthreads();
-            // z: tmp[i0][i1][a2] = sum_i2 Az[a2][i2] src[i0][i1][i2]
-            for (int e = threadIdx.x; e < p3; e += TPB) {
-                int r = e / p, a2 = e % p;
-                const double *row = src + (int64_t)r * p;
-                double s_ = 0.0;
-                for (int i = 0; i < p; ++i) s_ += Az[a2 * p + i] * row[i];
-                tmp[e] = s_;
-            }
+            for (int t = threadIdx.x; t < P3; t += TPB) t2[t] = src[t];
             __syncthreads();
-            // y: buf[i0][a1][a2] = sum_i1 Ay[a1][i1] tmp[i0][i1][a2]
-            for (int e = threadIdx.x; e < p3; e += TPB) {
-                int i0 = e / p2, a1 = (e / p) % p, a2 = e % p;
-                double s_ = 0.0;
-                for (int i = 0; i < p; ++i) s_ += Ay[a1 * p + i] * tmp[i0 * p2 + i * p + a2];
-                buf[e] = s_;
-            }
+            // z: t1[(i0 i1)][a2] = sum_i2 t2[(i0 i1)][i2] Az[a2][i2]
+            gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Az, 0, 1, P, t1, 0, P, 1);
             __syncthreads();
-            // x: acc[a0][a1][a2] += sum_i0 Ax[a0][i0] buf[i0][a1][a2]
-            for (int m = 0; m < MAXNPT; ++m) {
-                int e = threadIdx.x + TPB * m;
-                if (e >= p3) break;
-                int a0 = e / p2, rest = e % p2;
-                double s_ = 0.0;
-                for (int i = 0; i < p; ++i) s_ += Ax[a0 * p + i] * buf[i * p2 + rest];
-                acc[m] += s_;
-            }
+            // y: t2[i0][a1][a2] = sum_i1 Ay[a1][i1] t1[i0][i1][a2]
+            gemm<T, ZM, ZN, false>(P, P, P, P, Ay, 0, P, 1, t1, P2, P, 1, t2, P2, P, 1);
+            __syncthreads();
+            // x: acc[a0][r] += sum_i0 Ax[a0][i0] t2[i0][r]
+            gemm_regs<T, RM, RN>(P, P2, P, Ax, P, 1, t2, P2, 1, acc);
         } else {
-            double c[3] = {cP[0], cP[1], cP[2]};
-            anterpolate_points(D, D.pstart[C], D.pstart[C] + cnt, c, sideP, buf, acc);
+            // anterpolate the child's points onto the parent grid:
+            // rho[a0][(a1 a2)] += sum_pt Lx[pt][a0] (Ly[pt][a1] Lz[pt][a2] q[pt])
+            T *Lx = w0, *Ly = Lx + CH * P, *Lz = Ly + CH * P, *W = Lz + CH * P, *qq = W + CH * P2;
+            const int64_t i0 = D.pstart[C];
+            for (int base = 0; base < cnt; base += CH) {
+                const int m = min(CH, cnt - base);
+                __syncthreads();
+                for (int t = threadIdx.x; t < 3 * m; t += TPB) {
+                    int pt = t / 3, d = t % 3;
+                    int64_t i = i0 + base + pt;
+                    double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
+                    T row[P];
+                    lagrange_row<T>(P, xc, bw, (T)((x - cP[d]) * sc), row);
+                    T *dst = (d == 0 ? Lx : d == 1 ? Ly : Lz) + pt * P;
+#pragma unroll
+                    for (int a = 0; a < P; ++a) dst[a] = row[a];
+                }
+                for (int t = threadIdx.x; t < m; t += TPB) qq[t] = (T)D.qs[i0 + base + t];
+                __syncthreads();
+                for (int t = threadIdx.x; t < m * P2; t += TPB) {
+                    int pt = t / P2, c = t % P2;
+                    W[t] = Ly[pt * P + c / P] * Lz[pt * P + c % P] * qq[pt];
+                }
+                __syncthreads();
+                gemm_regs<T, RM, RN>(P, P2, m, Lx, 1, P, W, P2, 1, acc);
+            }
         }
     }
-    double *dst = D.proxy + (int64_t)D.proxy_slot[P] * p3;
-    for (int m = 0; m < MAXNPT; ++m) {
-        int e = threadIdx.x + TPB * m;
-        if (e < p3) dst[e] = acc[m];
-    }
+    store_tiles<T, P>(acc, D.proxy + (int64_t)D.proxy_slot[Pb] * P3);
 }
 
-// ------------------------------------------- proxies -> plane waves (LDS)
-// rho (p^3, LDS) -> out[m3][m2][m1] (complex, global), multiplied by wts
-// (half spectrum, may be null).  E is [n][p] complex with row m+nf.
-__device__ void proxy_to_pw(const Dev &D, const double *rho, const double *E, int n, int nh, double *Abuf,
-                            double *Bbuf, int gmax, double *out, const double *wts)
+// -------------------------------------------- proxies -> plane waves
+// Phi[m1][m3][m2] = sum_j E[m1][j1] E[m2][j2] E[m3][j3] rho[j1][j2][j3],
+// E[m][j] = exp(-i pi m x_j / 3); m3 >= 0 only (rho is real).
+template <typename T, int P, int NF, int G>
+__global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list, int64_t slot0)
 {
-    const int p = D.p, p2 = D.p2, nf = (n - 1) / 2;
-    // A[m3][j1][j2] = sum_j3 E[m3][j3] rho[j1][j2][j3]
-    for (int e = threadIdx.x; e < nh * p2; e += TPB) {
-        int m3 = e / p2, r = e % p2;
-        const double *Er = E + 2 * (int64_t)(m3 + nf) * p;
-        const double *row = rho + r * p;
-        double re = 0.0, im = 0.0;
-        for (int j = 0; j < p; ++j) {
-            re += Er[2 * j] * row[j];
-            im += Er[2 * j + 1] * row[j];
-        }
-        Abuf[2 * e] = re;
-        Abuf[2 * e + 1] = im;
-    }
-    __syncthreads();
-    for (int g0 = 0; g0 < nh; g0 += gmax) {
-        int g = min(gmax, nh - g0);
-        // B[m3][j1][m2] = sum_j2 E[m2][j2] A[m3][j1][j2]
-        for (int e = threadIdx.x; e < g * p * n; e += TPB) {
-            int mm = e / (p * n), j1 = (e / n) % p, m2 = e % n;
-            const double *Ar = Abuf + 2 * ((int64_t)(g0 + mm) * p2 + j1 * p);
-            const double *Er = E + 2 * (int64_t)m2 * p;
-            double re = 0.0, im = 0.0;
-            for (int j = 0; j < p; ++j) {
-                double er = Er[2 * j], ei = Er[2 * j + 1], ar = Ar[2 * j], ai = Ar[2 * j + 1];
-                re += er * ar - ei * ai;
-                im += er * ai + ei * ar;
-            }
-            Bbuf[2 * e] = re;
-            Bbuf[2 * e + 1] = im;
-        }
-        __syncthreads();
-        // out[m3][m2][m1] = sum_j1 E[m1][j1] B[m3][j1][m2]
-        for (int e = threadIdx.x; e < g * n * n; e += TPB) {
-            int mm = e / (n * n), m2 = (e / n) % n, m1 = e % n;
-            const double *Er = E + 2 * (int64_t)m1 * p;
-            double re = 0.0, im = 0.0;
-            for (int j = 0; j < p; ++j) {
-                const double *b = Bbuf + 2 * ((int64_t)mm * p * n + j * n + m2);
-                double er = Er[2 * j], ei = Er[2 * j + 1];
-                re += er * b[0] - ei * b[1];
-                im += er * b[1] + ei * b[0];
-            }
-            int64_t o = ((int64_t)(g0 + mm) * n + m2) * n + m1;
-            double w = wts ? wts[o] : 1.0;
-            out[2 * o] = re * w;
-            out[2 * o + 1] = im * w;
-        }
-        __syncthreads();
-    }
-}
-
-// psi[m3][m2][m1] (global, half spectrum) -> acc (owned grid entries) +=
-// Re sum_m exp(+i theta m.x_j) psi[m], E as above (its conjugate is used).
-__device__ void pw_to_grid(const Dev &D, const double *psi, const double *E, int n, int nh, double *Sbuf,
-                           double *C1, double *C2, double *acc)
-{
-    const int p = D.p, p2 = D.p2, p3 = D.p3;
-    for (int g0 = 0; g0 < nh; g0 += GSL) {
-        int g = min(GSL, nh - g0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < g * n * n; e += TPB) {
-            Sbuf[2 * e] = psi[2 * ((int64_t)g0 * n * n + e)];
-            Sbuf[2 * e + 1] = psi[2 * ((int64_t)g0 * n * n + e) + 1];
-        }
-        __syncthreads();
-        // C1[m3][m2][j1] = sum_m1 conj(E[m1][j1]) S[m3][m2][m1]
-        for (int e = threadIdx.x; e < g * n * p; e += TPB) {
-            int mm = e / (n * p), m2 = (e / p) % n, j1 = e % p;
-            const double *Sr = Sbuf + 2 * ((int64_t)mm * n * n + m2 * n);
-            double re = 0.0, im = 0.0;
-            for (int m1 = 0; m1 < n; ++m1) {
-                double er = E[2 * (m1 * p + j1)], ei = -E[2 * (m1 * p + j1) + 1];
-                double sr = Sr[2 * m1], si = Sr[2 * m1 + 1];
-                re += er * sr - ei * si;
-                im += er * si + ei * sr;
-            }
-            C1[2 * e] = re;
-            C1[2 * e + 1] = im;
-        }
-        __syncthreads();
-        // C2[m3][j1][j2] = sum_m2 conj(E[m2][j2]) C1[m3][m2][j1]
-        for (int e = threadIdx.x; e < g * p2; e += TPB) {
-            int mm = e / p2, j1 = (e / p) % p, j2 = e % p;
-            double re = 0.0, im = 0.0;
-            for (int m2 = 0; m2 < n; ++m2) {
-                double er = E[2 * (m2 * p + j2)], ei = -E[2 * (m2 * p + j2) + 1];
-                const double *c = C1 + 2 * ((int64_t)mm * n * p + m2 * p + j1);
-                re += er * c[0] - ei * c[1];
-                im += er * c[1] + ei * c[0];
-            }
-            C2[2 * e] = re;
-            C2[2 * e + 1] = im;
-        }
-        __syncthreads();
-        // acc[j1][j2][j3] += sum_m3 w_m3 Re(conj(E[m3][j3]) C2[m3][j1][j2])
-        const int nf = (n - 1) / 2;
-        for (int m = 0; m < MAXNPT; ++m) {
-            int e = threadIdx.x + TPB * m;
-            if (e >= p3) break;
-            int r = e / p, j3 = e % p;
-            double s_ = 0.0;
-            for (int mm = 0; mm < g; ++mm) {
-                int m3 = g0 + mm;
-                double er = E[2 * ((m3 + nf) * p + j3)], ei = -E[2 * ((m3 + nf) * p + j3) + 1];
-                const double *c = C2 + 2 * ((int64_t)mm * p2 + r);
-                double v = er * c[0] - ei * c[1];
-                s_ += (m3 == 0) ? v : 2.0 * v;
-            }
-            acc[m] += s_;
-        }
-    }
-}
-
-__global__ void __launch_bounds__(TPB) k_proxy2pw(Dev D, const int32_t *list, int64_t slot0)
-{
-    extern __shared__ double sm[];
-    const int p3 = D.p3;
-    double *rho = sm;                         // p^3
-    double *E = rho + p3;                     // nn*p*2
-    double *A = E + 2 * D.nn * D.p;           // nh*p^2*2
+    constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *rho = sm;                  // p^3
+    T *Er = rho + P3;             // [nn][p]
+    T *Ei = Er + NN * P;
+    T *Bc = Ei + NN * P;          // [p][2G]: E rows m3 of the group, re | im
+    T *Ag = Bc + P * 2 * G;       // [(j1 j2)][2G]
+    T *Bg = Ag + P2 * 2 * G;      // planar [j1][G][nn] re, then im
     const int32_t B = list[blockIdx.x];
-    const double *src = D.proxy + (int64_t)D.proxy_slot[B] * p3;
-    for (int t = threadIdx.x; t < p3; t += TPB) rho[t] = src[t];
-    for (int t = threadIdx.x; t < 2 * D.nn * D.p; t += TPB) E[t] = D.epw[t];
-    __syncthreads();
-    int64_t slot = D.proxy_slot[B] - slot0;
-    double *out = D.phi + 2 * slot * (int64_t)D.nh * D.nn * D.nn;
-    // B groups reuse the rho region once A is formed
-    int gmax = max(1, p3 / (2 * D.p * D.nn));
-    proxy_to_pw(D, rho, E, D.nn, D.nh, A, rho, gmax, out, nullptr);
-}
-
-__global__ void __launch_bounds__(TPB) k_root_w0(Dev D, int root_fout, double *scratch)
-{
-    extern __shared__ double sm[];
-    const int p3 = D.p3;
-    double *E = sm;                     // nwn*p*2
-    double *rho = E + 2 * D.nn * D.p;   // p^3
-    double *A = rho + p3;               // nh*p^2*2 (point scratch while anterpolating)
-    double acc[MAXNPT];
-    for (int m = 0; m < MAXNPT; ++m) acc[m] = 0.0;
-    if (root_fout) {
-        const double *src = D.proxy + (int64_t)D.proxy_slot[0] * p3;
-        for (int m = 0; m < MAXNPT; ++m) {
-            int e = threadIdx.x + TPB * m;
-            if (e < p3) acc[m] = src[e];
+    const T *src = D.proxy + (int64_t)D.proxy_slot[B] * P3;
+    for (int t = threadIdx.x; t < P3; t += TPB) rho[t] = src[t];
+    for (int t = threadIdx.x; t < NN * P; t += TPB) {
+        Er[t] = D.epw[2 * t];
+        Ei[t] = D.epw[2 * t + 1];
+    }
+    const int64_t nm = D.pwstride;
+    T *outr = D.phi + 2 * (int64_t)(D.proxy_slot[B] - slot0) * nm;
+    T *outi = outr + nm;
+    for (int g0 = 0; g0 < NH; g0 += G) {
+        const int g = min(G, NH - g0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < P * 2 * g; t += TPB) {
+            int k = t / (2 * g), c = t % (2 * g);
+            int m3 = g0 + (c < g ? c : c - g);
+            Bc[k * 2 * g + c] = (c < g) ? Er[(m3 + NF) * P + k] : Ei[(m3 + NF) * P + k];
         }
-    } else {
-        double c[3] = {0.0, 0.0, 0.0};
-        anterpolate_points(D, 0, D.pcount[0], c, 1.0, A, acc);
-    }
-    __syncthreads();
-    for (int m = 0; m < MAXNPT; ++m) {
-        int e = threadIdx.x + TPB * m;
-        if (e < p3) rho[e] = acc[m];
-    }
-    for (int t = threadIdx.x; t < 2 * D.nwn * D.p; t += TPB) E[t] = D.ew[t];
-    __syncthreads();
-    int gmax = max(1, p3 / (2 * D.p * D.nwn));
-    proxy_to_pw(D, rho, E, D.nwn, D.nwh, A, rho, gmax, scratch, D.ww);
-    __threadfence_block();
-    __syncthreads();
-    for (int m = 0; m < MAXNPT; ++m) acc[m] = 0.0;
-    double *Sb = rho;
-    double *C1 = Sb + 2 * GSL * D.nwn * D.nwn;
-    double *C2 = C1 + 2 * GSL * D.nwn * D.p;
-    pw_to_grid(D, scratch, E, D.nwn, D.nwh, Sb, C1, C2, acc);
-    for (int m = 0; m < MAXNPT; ++m) {
-        int e = threadIdx.x + TPB * m;
-        if (e < p3) D.w0vals[e] = acc[m];
+        __syncthreads();
+        // A[(j1 j2)][c] = sum_j3 rho[(j1 j2)][j3] Bc[j3][c]
+        gemm<T, 6, 2, false>(1, P2, 2 * g, P, rho, 0, P, 1, Bc, 0, 2 * g, 1, Ag, 0, 2 * g, 1);
+        __syncthreads();
+        // B[j1][m3][m2] = sum_j2 A[j1][j2][m3] E[m2][j2]
+        cgemm<T, 2, 5, false>(P, g, NN, P, Ag, Ag + g, P * 2 * g, 1, 2 * g, Er, Ei, 0, 1, P, Bg, Bg + P * g * NN,
+                              g * NN, NN, 1);
+        __syncthreads();
+        // Phi[m1][(m3 m2)] = sum_j1 E[m1][j1] B[j1][(m3 m2)]  (the group's rows are contiguous)
+        cgemm<T, 5, 4, false>(1, NN, g * NN, P, Er, Ei, 0, P, 1, Bg, Bg + P * g * NN, 0, g * NN, 1,
+                              outr + g0 * NN, outi + g0 * NN, 0, NH * NN, 1);
     }
 }
 
-// ------------------------------------------------------------- downward
-__global__ void __launch_bounds__(TPB) k_local_init(Dev D, const int32_t *list, int level)
-{
-    extern __shared__ double sm[];
-    const int p = D.p, p2 = D.p2, p3 = D.p3;
-    const int32_t B = list[blockIdx.x];
-    double *dst = D.local + (int64_t)D.local_slot[B] * p3;
-    if (level == 0) {
-        for (int e = threadIdx.x; e < p3; e += TPB) dst[e] = D.w0vals[e];
-        return;
-    }
-    double *tmp = sm, *buf = tmp + p3, *Am = buf + p3;
-    for (int t = threadIdx.x; t < 2 * p2; t += TPB) Am[t] = D.c2p[t];
-    __syncthreads();
-    const int32_t Pb = D.parent[B];
-    const int k = B - D.child0[Pb];
-    const double *src = D.local + (int64_t)D.local_slot[Pb] * p3;
-    const double *Ax = Am + ((k >> 2) & 1) * p2, *Ay = Am + ((k >> 1) & 1) * p2, *Az = Am + (k & 1) * p2;
-    // z: tmp[a0][a1][i2] = sum_a2 Az[a2][i2] src[a0][a1][a2]
-    for (int e = threadIdx.x; e < p3; e += TPB) {
-        int r = e / p, i2 = e % p;
-        const double *row = src + (int64_t)r * p;
-        double s_ = 0.0;
-        for (int a = 0; a < p; ++a) s_ += Az[a * p + i2] * row[a];
-        tmp[e] = s_;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < p3; e += TPB) {
-        int a0 = e / p2, i1 = (e / p) % p, i2 = e % p;
-        double s_ = 0.0;
-        for (int a = 0; a < p; ++a) s_ += Ay[a * p + i1] * tmp[a0 * p2 + a * p + i2];
-        buf[e] = s_;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < p3; e += TPB) {
-        int i0 = e / p2, rest = e % p2;
-        double s_ = 0.0;
-        for (int a = 0; a < p; ++a) s_ += Ax[a * p + i0] * buf[a * p2 + rest];
-        dst[e] = s_;
-    }
-}
-
-__global__ void __launch_bounds__(TPB) k_pwshift(Dev D, const int32_t *list, int64_t fout_slot0, double wscale)
+// ------------------------------------------------ diagonal translation
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *list, int64_t fout_slot0, T wscale)
 {
     __shared__ int32_t src_slot[27];
     __shared__ int8_t dl[27][3];
@@ -403,8 +384,7 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev D, const int32_t *list, int
             int32_t S = D.col[(int64_t)B * 27 + k];
             if (S >= 0 && (D.bflags[S] & 2)) {
                 src_slot[c] = (int32_t)(D.proxy_slot[S] - fout_slot0);
-                // c_S - c_B = delta s_l with delta = offset of the colleague
-                dl[c][0] = (int8_t)(k / 9 - 1);
+                dl[c][0] = (int8_t)(k / 9 - 1);  // c_S - c_B = delta s_l
                 dl[c][1] = (int8_t)((k / 3) % 3 - 1);
                 dl[c][2] = (int8_t)(k % 3 - 1);
                 c++;
@@ -413,107 +393,206 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev D, const int32_t *list, int
         nsrc = c;
     }
     __syncthreads();
-    const int nn = D.nn, nf = D.nf;
-    const int64_t nm = (int64_t)D.nh * nn * nn;
-    double *out = D.psi + 2 * (int64_t)D.psi_slot[B] * nm;
+    const int nn = D.nn, nh = D.nh, nf = D.nf;
+    const int64_t nm = D.pwstride;
+    T *outr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *outi = outr + nm;
     // exp(i h m.(c_B - c_S)) = exp(-2 pi i (m.delta)/3) = w^{-(m.delta mod 3)}
-    const double c3 = -0.5, s3 = 0.86602540378443864676;
+    const T c3 = T(-0.5), s3 = T(0.86602540378443864676);
     for (int64_t e = threadIdx.x; e < nm; e += TPB) {
-        int m3 = (int)(e / (nn * nn)), m2 = (int)((e / nn) % nn) - nf, m1 = (int)(e % nn) - nf;
-        double re = 0.0, im = 0.0;
+        // e = (m1 * nh + m3) * nn + m2
+        const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
+        T re = T(0), im = T(0);
         for (int k = 0; k < nsrc; ++k) {
-            const double *f = D.phi + 2 * ((int64_t)src_slot[k] * nm + e);
+            const T *f = D.phi + 2 * (int64_t)src_slot[k] * nm + e;
+            T fr = f[0], fi = f[nm];
             int t = (m1 * dl[k][0] + m2 * dl[k][1] + m3 * dl[k][2]) % 3;
             if (t < 0) t += 3;
-            double fr = f[0], fi = f[1];
             if (t == 0) { re += fr; im += fi; }
-            else if (t == 1) { re += c3 * fr + s3 * fi; im += c3 * fi - s3 * fr; }   // * (c3 - i s3)
-            else { re += c3 * fr - s3 * fi; im += c3 * fi + s3 * fr; }               // * (c3 + i s3)
+            else if (t == 1) { re += c3 * fr + s3 * fi; im += c3 * fi - s3 * fr; }
+            else { re += c3 * fr - s3 * fi; im += c3 * fi + s3 * fr; }
         }
-        double w = D.wd0[e] * wscale;
-        out[2 * e] = re * w;
-        out[2 * e + 1] = im * w;
+        const T w = D.wd0[e] * wscale;
+        outr[e] = re * w;
+        outi[e] = im * w;
     }
 }
 
-__global__ void __launch_bounds__(TPB) k_pw2grid(Dev D, const int32_t *list)
+// ------------------------------------------------ local values (anchors)
+// v_B = interp(anchor(parent(B)) -> B's grid) + Re sum_m exp(+i pi m.x/3) Psi_B[m]
+template <typename T, int P, int NF, int G1>
+__global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list, int level)
 {
-    extern __shared__ double sm[];
-    const int p = D.p, p3 = D.p3, nn = D.nn;
-    double *E = sm;
-    double *Sb = E + 2 * nn * p;
-    double *C1 = Sb + 2 * GSL * nn * nn;
-    double *C2 = C1 + 2 * GSL * nn * p;
+    constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
+    constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, NN = 2 * NF + 1, NH = NF + 1;
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *Er = sm;                // [nn][p]  Re E
+    T *Ein = Er + NN * P;      // [nn][p] -Im E  (imaginary part of conj(E))
+    T *Gw = Ein + NN * P;      // [nh][p] re then [nh][p] im: c_m3 conj(E[m3][j3])
+    T *Gc = Gw + 2 * NH * P;   // [2 nn][p]: Re E rows, then Im E rows
+    T *xc = Gc + 2 * NN * P;
+    T *bw = xc + P;
+    T *w0 = bw + P;            // work area
     const int32_t B = list[blockIdx.x];
-    for (int t = threadIdx.x; t < 2 * nn * p; t += TPB) E[t] = D.epw[t];
-    double *v = D.local + (int64_t)D.local_slot[B] * p3;
-    double acc[MAXNPT];
-    for (int m = 0; m < MAXNPT; ++m) {
-        int e = threadIdx.x + TPB * m;
-        acc[m] = (e < p3) ? v[e] : 0.0;
+    for (int t = threadIdx.x; t < NN * P; t += TPB) {
+        T er = D.epw[2 * t], ei = D.epw[2 * t + 1];
+        Er[t] = er;
+        Ein[t] = -ei;
+        Gc[t] = er;
+        Gc[NN * P + t] = ei;
     }
-    const double *psi = D.psi + 2 * (int64_t)D.psi_slot[B] * D.nh * nn * nn;
-    pw_to_grid(D, psi, E, nn, D.nh, Sb, C1, C2, acc);
-    for (int m = 0; m < MAXNPT; ++m) {
-        int e = threadIdx.x + TPB * m;
-        if (e < p3) v[e] = acc[m];
+    for (int t = threadIdx.x; t < NH * P; t += TPB) {
+        int m3 = t / P, j = t % P;
+        T c = (m3 == 0) ? T(1) : T(2);
+        Gw[t] = c * D.epw[2 * ((m3 + NF) * P + j)];
+        Gw[NH * P + t] = -c * D.epw[2 * ((m3 + NF) * P + j) + 1];
     }
-}
-
-__global__ void __launch_bounds__(TPB) k_leaf_eval(Dev D, const int32_t *list)
-{
-    extern __shared__ double sm[];
-    const int p = D.p, p2 = D.p2, p3 = D.p3;
-    const int CH = 64;
-    double *v = sm;
-    double *Lx = v + p3, *Ly = Lx + CH * p, *Lz = Ly + CH * p, *part = Lz + CH * p;
-    const int32_t B = list[blockIdx.x];
-    const double *src = D.local + (int64_t)D.local_slot[B] * p3;
-    for (int t = threadIdx.x; t < p3; t += TPB) v[t] = src[t];
-    const double *c = D.bcenter + 3 * (int64_t)B;
-    const int64_t i0 = D.pstart[B], i1 = i0 + D.pcount[B];
-    const double s = ldexp(1.0, -D.blevel[B]);
-    const double sc = 2.0 / s;
-    for (int64_t base = i0; base < i1; base += CH) {
-        int cnt = (int)min<int64_t>(CH, i1 - base);
-        __syncthreads();
-        for (int t = threadIdx.x; t < 3 * cnt; t += TPB) {
-            int pt = t / 3, d = t % 3;
-            int64_t i = base + pt;
-            double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
-            double row[MAXP];
-            lagrange_row(D, (x - c[d]) * sc, row);
-            double *dst = (d == 0 ? Lx : d == 1 ? Ly : Lz) + pt * p;
-            for (int a = 0; a < p; ++a) dst[a] = row[a];
+    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
+    T acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
+    __syncthreads();
+    if (level == 0) {
+        // root: the windowed W_0 values
+        constexpr int MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;
+        const int t = threadIdx.x;
+        if (t < MT * NT) {
+            const int mt = t / NT, nt = t % NT;
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j) {
+                    int m = mt + i * MT, n = nt + j * NT;
+                    if (m < P && n < P2) acc[i][j] = D.w0vals[m * P2 + n];
+                }
         }
+    } else {
+        // interpolation from the anchor A of the parent: node i of B sits at
+        // A-coordinate ((c_B + s_B x_i / 2) - c_A) * 2 / s_A
+        const int32_t A = D.anchor[D.parent[B]];
+        T *Mx = w0, *My = Mx + P2, *Mz = My + P2, *t1 = Mz + P2, *t2 = t1 + P3;
+        const double sB = box_side(level), sA = box_side(D.blevel[A]);
+        for (int t = threadIdx.x; t < 3 * P; t += TPB) {
+            int d = t / P, i = t % P;
+            double xi = (D.bcenter[3 * (int64_t)B + d] + 0.5 * sB * D.xcheb64[i] - D.bcenter[3 * (int64_t)A + d]) *
+                        (2.0 / sA);
+            T row[P];
+            lagrange_row<T>(P, xc, bw, (T)xi, row);
+            T *dst = (d == 0 ? Mx : d == 1 ? My : Mz) + i * P;
+#pragma unroll
+            for (int a = 0; a < P; ++a) dst[a] = row[a];
+        }
+        const T *src = D.local + (int64_t)D.local_slot[A] * P3;
+        for (int t = threadIdx.x; t < P3; t += TPB) t2[t] = src[t];
         __syncthreads();
-        for (int t = threadIdx.x; t < cnt * p; t += TPB) {
-            int j1 = t / cnt, pt = t % cnt;
-            const double *ly = Ly + pt * p, *lz = Lz + pt * p;
-            double s1 = 0.0;
-            for (int j2 = 0; j2 < p; ++j2) {
-                const double *row = v + j1 * p2 + j2 * p;
-                double s2 = 0.0;
-                for (int j3 = 0; j3 < p; ++j3) s2 += row[j3] * lz[j3];
-                s1 += ly[j2] * s2;
+        // z: t1[(a0 a1)][i2] = sum_a2 v[(a0 a1)][a2] Mz[i2][a2]
+        gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Mz, 0, 1, P, t1, 0, P, 1);
+        __syncthreads();
+        // y: t2[a0][i1][i2] = sum_a1 My[i1][a1] t1[a0][a1][i2]
+        gemm<T, ZM, ZN, false>(P, P, P, P, My, 0, P, 1, t1, P2, P, 1, t2, P2, P, 1);
+        __syncthreads();
+        // x: acc[i0][r] = sum_a0 Mx[i0][a0] t2[a0][r]
+        gemm_regs<T, RM, RN>(P, P2, P, Mx, P, 1, t2, P2, 1, acc);
+    }
+    if (D.psi_slot[B] >= 0) {
+        const int64_t nm = D.pwstride;
+        const T *psr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *psim = psr + nm;
+        T *Sr = w0, *Si = Sr + G1 * NH * NN;                       // Psi rows of an m1 group [m1][m3][m2]
+        T *D1r = Si + G1 * NH * NN, *D1i = D1r + G1 * NN * P;      // [m1][m2][j3]
+        T *Dc = D1i + G1 * NN * P;                                  // [m1][(j2 j3)] re rows, then im rows
+        for (int g0 = 0; g0 < NN; g0 += G1) {
+            const int g = min(G1, NN - g0);
+            __syncthreads();
+            for (int t = threadIdx.x; t < g * NH * NN; t += TPB) {
+                Sr[t] = psr[(int64_t)g0 * NH * NN + t];
+                Si[t] = psim[(int64_t)g0 * NH * NN + t];
             }
-            part[pt * p + j1] = Lx[pt * p + j1] * s1;
+            __syncthreads();
+            // D1[m1][m2][j3] = sum_m3 S[m1][m3][m2] Gw[m3][j3]
+            cgemm<T, 5, 3, false>(g, NN, P, NH, Sr, Si, NH * NN, 1, NN, Gw, Gw + NH * P, 0, P, 1, D1r, D1i,
+                                  NN * P, P, 1);
+            __syncthreads();
+            // D2[m1][j2][j3] = sum_m2 conj(E[m2][j2]) D1[m1][m2][j3]
+            cgemm<T, 3, 3, false>(g, P, P, NN, Er, Ein, 0, 1, P, D1r, D1i, NN * P, P, 1, Dc, Dc + g * P2, P2, P, 1);
+            __syncthreads();
+            // acc[j1][(j2 j3)] += sum_m1 Re(conj(E[m1][j1]) D2[m1][(j2 j3)])
+            //                  = sum_m1 ReE[m1][j1] D2r + ImE[m1][j1] D2i
+            gemm_regs<T, RM, RN>(P, P2, g, Gc + g0 * P, 1, P, Dc, P2, 1, acc);
+            gemm_regs<T, RM, RN>(P, P2, g, Gc + NN * P + g0 * P, 1, P, Dc + g * P2, P2, 1, acc);
+        }
+    }
+    store_tiles<T, P>(acc, D.local + (int64_t)D.local_slot[B] * P3);
+}
+
+// ------------------------------------------------------------ leaf targets
+template <typename T, int P, int CH>
+__global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *list)
+{
+    constexpr int P2 = P * P, P3 = P2 * P;
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *v = sm;                  // p^3 anchor values
+    T *Lx = v + P3, *Ly = Lx + CH * P, *Lz = Ly + CH * P;
+    T *W = Lz + CH * P;         // [(j1 j2)][CH]
+    T *part = W + P2 * CH;      // [CH][p]
+    T *xc = part + CH * P, *bw = xc + P;
+    const int32_t B = list[blockIdx.x];
+    const int32_t A = D.anchor[B];
+    const T *src = D.local + (int64_t)D.local_slot[A] * P3;
+    for (int t = threadIdx.x; t < P3; t += TPB) v[t] = src[t];
+    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
+    const double *cA = D.bcenter + 3 * (int64_t)A;
+    const double sc = 2.0 / box_side(D.blevel[A]);
+    const int64_t i0 = D.pstart[B];
+    const int cnt = D.pcount[B];
+    for (int base = 0; base < cnt; base += CH) {
+        const int m = min(CH, cnt - base);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 3 * m; t += TPB) {
+            int pt = t / 3, d = t % 3;
+            int64_t i = i0 + base + pt;
+            double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
+            T row[P];
+            lagrange_row<T>(P, xc, bw, (T)((x - cA[d]) * sc), row);
+            T *dst = (d == 0 ? Lx : d == 1 ? Ly : Lz) + pt * P;
+#pragma unroll
+            for (int a = 0; a < P; ++a) dst[a] = row[a];
         }
         __syncthreads();
-        for (int pt = threadIdx.x; pt < cnt; pt += TPB) {
-            double s_ = 0.0;
-            for (int j1 = 0; j1 < p; ++j1) s_ += part[pt * p + j1];
-            D.ufar[base + pt] = s_;
+        // W[(j1 j2)][t] = sum_j3 v[(j1 j2)][j3] Lz[t][j3]
+        gemm<T, 6, 2, false>(1, P2, m, P, v, 0, P, 1, Lz, 0, 1, P, W, 0, CH, 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < m * P; t += TPB) {
+            int pt = t % m, j1 = t / m;
+            T s = T(0);
+#pragma unroll
+            for (int j2 = 0; j2 < P; ++j2) s += Ly[pt * P + j2] * W[(j1 * P + j2) * CH + pt];
+            part[pt * P + j1] = s * Lx[pt * P + j1];
+        }
+        __syncthreads();
+        for (int pt = threadIdx.x; pt < m; pt += TPB) {
+            T s = T(0);
+#pragma unroll
+            for (int j1 = 0; j1 < P; ++j1) s += part[pt * P + j1];
+            D.ufar[i0 + base + pt] = (double)s;
         }
     }
 }
 
-// ------------------------------------------------------------- residual
-__global__ void __launch_bounds__(TPB) k_residual(Dev D, const int32_t *leaves, const int32_t *nl_off,
-                                                  const int32_t *nl_src, const int32_t *blevel)
+// -------------------------------------------------------------- residual
+// Offsets of targets and sources from the target leaf's centre are formed in
+// FP64 and rounded to T once per point; each pair is evaluated in T and the
+// per-tile partial sums are added into an FP64 accumulator.  In FP64 mode
+// this is plain double arithmetic.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
+                                                  const int32_t *nl_src)
 {
-    __shared__ double sx[TPB], sy[TPB], sz[TPB], sq[TPB];
+    __shared__ T sx[TPB], sy[TPB], sz[TPB], sq[TPB];
     __shared__ double part[TPB];
+    __shared__ T gc[48];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.pstart[B];
     const int nt = D.pcount[B];
@@ -522,58 +601,189 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev D, const int32_t *leaves, 
     const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
     const int32_t l0 = nl_off[blockIdx.x], l1 = nl_off[blockIdx.x + 1];
     const int deg = D.gdeg;
+    for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
+    const double cx = D.bcenter[3 * (int64_t)B], cy = D.bcenter[3 * (int64_t)B + 1], cz = D.bcenter[3 * (int64_t)B + 2];
     for (int tbase = 0; tbase < nt; tbase += tch) {
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
-        const double xt = D.X[it], yt = D.Y[it], zt = D.Z[it];
+        const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy), zt = (T)(D.Z[it] - cz);
         double acc = 0.0;
         for (int li = l0; li < l1; ++li) {
-            const int32_t T = nl_src[li];
-            const int lev = blevel[T];
-            const double inv_s = ldexp(1.0, lev), inv_s2 = inv_s * inv_s, s2 = 1.0 / inv_s2;
-            const int64_t j0 = D.pstart[T];
-            const int ns = D.pcount[T];
+            const int32_t Tb = nl_src[li];
+            const int lev = D.blevel[Tb];
+            const T inv_s = (T)ldexp(1.0, lev), inv_s2 = inv_s * inv_s, s2 = (T)ldexp(1.0, -2 * lev);
+            const int64_t j0 = D.pstart[Tb];
+            const int ns = D.pcount[Tb];
             for (int jb = 0; jb < ns; jb += TPB) {
-                int cnt = min(TPB, ns - jb);
+                const int cnt = min(TPB, ns - jb);
                 __syncthreads();
                 if (threadIdx.x < cnt) {
                     int64_t j = j0 + jb + threadIdx.x;
-                    sx[threadIdx.x] = D.X[j];
-                    sy[threadIdx.x] = D.Y[j];
-                    sz[threadIdx.x] = D.Z[j];
-                    sq[threadIdx.x] = D.qs[j];
+                    sx[threadIdx.x] = (T)(D.X[j] - cx);
+                    sy[threadIdx.x] = (T)(D.Y[j] - cy);
+                    sz[threadIdx.x] = (T)(D.Z[j] - cz);
+                    sq[threadIdx.x] = (T)D.qs[j];
                 }
                 __syncthreads();
+                T pacc = T(0);
                 for (int j = split; j < cnt; j += nsplit) {
-                    double dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
-                    double r2 = dx * dx + dy * dy + dz * dz;
+                    T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
+                    T r2 = dx * dx + dy * dy + dz * dz;
                     if (r2 < s2) {
-                        double u = 2.0 * r2 * inv_s2 - 1.0;
                         // Clenshaw for g(t) = Phi(sqrt t)/sqrt t, t = r^2/s^2
-                        double b1 = 0.0, b2 = 0.0;
+                        T u = T(2) * r2 * inv_s2 - T(1);
+                        T b1 = T(0), b2 = T(0);
                         for (int k = deg; k >= 1; --k) {
-                            double b0 = D.gcheb[k] + 2.0 * u * b1 - b2;
+                            T b0 = gc[k] + T(2) * u * b1 - b2;
                             b2 = b1;
                             b1 = b0;
                         }
-                        double g = D.gcheb[0] + u * b1 - b2;
-                        double rinv = (r2 > 0.0) ? rsqrt(r2) : 0.0;
-                        acc += sq[j] * (rinv - g * inv_s);
+                        T g = gc[0] + u * b1 - b2;
+                        T rinv = (r2 > T(0)) ? rsqrt(r2) : T(0);
+                        pacc += sq[j] * (rinv - g * inv_s);
                     }
                 }
+                acc += (double)pacc;
             }
         }
         __syncthreads();
         part[threadIdx.x] = acc;
         __syncthreads();
         if (split == 0 && active) {
-            double s_ = 0.0;
-            for (int k = 0; k < nsplit; ++k) s_ += part[k * tch + tl];
-            D.ures[t0 + tbase + tl] = s_;
+            double s = 0.0;
+            for (int k = 0; k < nsplit; ++k) s += part[k * tch + tl];
+            D.ures[t0 + tbase + tl] = s;
         }
     }
 }
 
+// ----------------------------------------------------------- root window
+// Root proxies -> W_0 plane waves (spacing hw, half width nw) times the
+// window weights -> values on the root grid, in FP64.  One workgroup; the
+// intermediates live in a global scratch buffer (O(1) work per eval).
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_root_w0(Dev<T> D, int root_fout)
+{
+    extern __shared__ unsigned char smraw[];
+    double *sm = reinterpret_cast<double *>(smraw);
+    const int p = D.p, p2 = p * p, p3 = p2 * p, n = D.nwn, nh = D.nwh, nw = D.nw;
+    double *rho = sm, *xc = rho + p3, *bw = xc + p, *L = bw + p;  // L: 3 * 16 * p
+    double *Ar = D.rootscratch, *Ai = Ar + p2 * nh;               // [(j1 j2)][m3]
+    double *Br = Ai + p2 * nh, *Bi = Br + p * nh * n;             // [j1][m3][m2]
+    double *Fr = Bi + p * nh * n, *Fi = Fr + n * nh * n;          // [m1][m3][m2]
+    double *C1r = Fi + n * nh * n, *C1i = C1r + n * n * p;        // [m1][m2][j3]
+    double *C2r = C1i + n * n * p, *C2i = C2r + n * p2;           // [m1][(j2 j3)]
+    for (int t = threadIdx.x; t < p; t += TPB) { xc[t] = D.xcheb64[t]; bw[t] = D.bary64[t]; }
+    for (int t = threadIdx.x; t < p3; t += TPB) rho[t] = 0.0;
+    __syncthreads();
+    if (root_fout) {
+        const T *src = D.proxy + (int64_t)D.proxy_slot[0] * p3;
+        for (int t = threadIdx.x; t < p3; t += TPB) rho[t] = (double)src[t];
+    } else {
+        // the root holds at most n_s points: anterpolate them directly
+        const int cnt = D.pcount[0];
+        for (int base = 0; base < cnt; base += 16) {
+            const int m = min(16, cnt - base);
+            __syncthreads();
+            for (int t = threadIdx.x; t < 3 * m; t += TPB) {
+                int pt = t / 3, d = t % 3;
+                double x = (d == 0) ? D.X[base + pt] : (d == 1) ? D.Y[base + pt] : D.Z[base + pt];
+                lagrange_row<double>(p, xc, bw, 2.0 * x, L + (d * 16 + pt) * p);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < p3; e += TPB) {
+                int a0 = e / p2, a1 = (e / p) % p, a2 = e % p;
+                double s = 0.0;
+                for (int pt = 0; pt < m; ++pt)
+                    s += L[pt * p + a0] * L[(16 + pt) * p + a1] * L[(32 + pt) * p + a2] * D.qs[base + pt];
+                rho[e] += s;
+            }
+        }
+    }
+    __syncthreads();
+    const double *E = D.ew64;  // [n][p][2], rows m + nw
+    for (int e = threadIdx.x; e < p2 * nh; e += TPB) {
+        int r = e / nh, m3 = e % nh;
+        double re = 0, im = 0;
+        for (int j = 0; j < p; ++j) {
+            re += E[2 * ((m3 + nw) * p + j)] * rho[r * p + j];
+            im += E[2 * ((m3 + nw) * p + j) + 1] * rho[r * p + j];
+        }
+        Ar[e] = re;
+        Ai[e] = im;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < p * nh * n; e += TPB) {
+        int j1 = e / (nh * n), m3 = (e / n) % nh, m2 = e % n;
+        double re = 0, im = 0;
+        for (int j = 0; j < p; ++j) {
+            double er = E[2 * (m2 * p + j)], ei = E[2 * (m2 * p + j) + 1];
+            double ar = Ar[(j1 * p + j) * nh + m3], ai = Ai[(j1 * p + j) * nh + m3];
+            re += er * ar - ei * ai;
+            im += er * ai + ei * ar;
+        }
+        Br[e] = re;
+        Bi[e] = im;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * nh * n; e += TPB) {
+        int m1 = e / (nh * n), r = e % (nh * n), m3 = r / n, m2 = r % n;
+        double re = 0, im = 0;
+        for (int j = 0; j < p; ++j) {
+            double er = E[2 * (m1 * p + j)], ei = E[2 * (m1 * p + j) + 1];
+            re += er * Br[j * nh * n + r] - ei * Bi[j * nh * n + r];
+            im += er * Bi[j * nh * n + r] + ei * Br[j * nh * n + r];
+        }
+        double w = D.ww64[(m3 * n + m2) * n + m1];
+        Fr[e] = re * w;
+        Fi[e] = im * w;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n * p; e += TPB) {
+        int m1 = e / (n * p), m2 = (e / p) % n, j3 = e % p;
+        double re = 0, im = 0;
+        for (int m3 = 0; m3 < nh; ++m3) {
+            double c = (m3 == 0) ? 1.0 : 2.0;
+            double er = c * E[2 * ((m3 + nw) * p + j3)], ei = -c * E[2 * ((m3 + nw) * p + j3) + 1];
+            double fr = Fr[(m1 * nh + m3) * n + m2], fi = Fi[(m1 * nh + m3) * n + m2];
+            re += er * fr - ei * fi;
+            im += er * fi + ei * fr;
+        }
+        C1r[e] = re;
+        C1i[e] = im;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * p2; e += TPB) {
+        int m1 = e / p2, j2 = (e / p) % p, j3 = e % p;
+        double re = 0, im = 0;
+        for (int m2 = 0; m2 < n; ++m2) {
+            double er = E[2 * (m2 * p + j2)], ei = -E[2 * (m2 * p + j2) + 1];
+            double cr = C1r[(m1 * n + m2) * p + j3], ci = C1i[(m1 * n + m2) * p + j3];
+            re += er * cr - ei * ci;
+            im += er * ci + ei * cr;
+        }
+        C2r[e] = re;
+        C2i[e] = im;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < p3; e += TPB) {
+        int j1 = e / p2, r = e % p2;
+        double s = 0.0;
+        for (int m1 = 0; m1 < n; ++m1) {
+            double er = E[2 * (m1 * p + j1)], ei = E[2 * (m1 * p + j1) + 1];
+            s += er * C2r[m1 * p2 + r] + ei * C2i[m1 * p2 + r];
+        }
+        D.w0vals[e] = (T)s;
+    }
+}
+
+int64_t root_scratch_elems(const Tables &t)
+{
+    const int64_t p = t.p, p2 = p * p, n = t.nwn, nh = t.nwh;
+    return 2 * (p2 * nh + p * nh * n + n * nh * n + n * n * p + n * p2);
+}
+
+// -------------------------------------------------------------- small ones
 __global__ void k_gather_q(const double *charges, const int32_t *perm, int64_t n, double *qs)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -594,70 +804,194 @@ __global__ void k_finalize(const double *ufar, const double *ures, const int32_t
 
 inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + TPB - 1) / TPB); }
 
-size_t lds_upward(const Plan *P) { return (size_t)(2 * P->p * P->p * P->p + 2 * P->p * P->p) * sizeof(double); }
-size_t lds_p2pw(const Plan *P)
-{
-    const Tables &t = P->tab;
-    return (size_t)(t.p * t.p * t.p + 2 * t.nn * t.p + 2 * t.nh * t.p * t.p) * sizeof(double);
-}
-size_t lds_local(const Plan *P) { return lds_upward(P); }
-size_t lds_pw2grid(const Plan *P)
-{
-    const Tables &t = P->tab;
-    return (size_t)(2 * t.nn * t.p + 2 * GSL * t.nn * t.nn + 2 * GSL * t.nn * t.p + 2 * GSL * t.p * t.p) *
-           sizeof(double);
-}
-size_t lds_root(const Plan *P)
-{
-    const Tables &t = P->tab;
-    size_t a = lds_p2pw(P);
-    size_t b = (size_t)(2 * t.nn * t.p + 2 * GSL * (t.nwn * t.nwn + t.nwn * t.p + t.p * t.p)) * sizeof(double);
-    return std::max(a, b);
-}
-size_t lds_leaf(const Plan *P)
-{
-    return (size_t)(P->p * P->p * P->p + 4 * 64 * P->p) * sizeof(double);
-}
+// ------------------------------------------------------------ host side
+template <typename T, int P, int NF>
+struct Cfg {
+    static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
+    static constexpr int G = sizeof(T) == 8 ? 4 : 7;    // m3 group of k_proxy2pw
+    static constexpr int G1 = 5;                        // m1 group of k_local_pw
+    static constexpr int CH = sizeof(T) == 8 ? 16 : 32; // target chunk of k_leaf
+    static size_t lds_up() { return sizeof(T) * (2 * P2 + 2 * P + 2 * P3); }
+    static size_t lds_p2pw() { return sizeof(T) * (P3 + 2 * NN * P + P * 2 * G + P2 * 2 * G + 2 * P * G * NN); }
+    static size_t lds_local()
+    {
+        size_t fixed = 2 * NN * P + 2 * NH * P + 2 * NN * P + 2 * P;
+        size_t p2c = 3 * P2 + 2 * P3;
+        size_t pw = 2 * G1 * NH * NN + 2 * G1 * NN * P + 2 * G1 * P2;
+        return sizeof(T) * (fixed + std::max(p2c, pw));
+    }
+    static size_t lds_leaf() { return sizeof(T) * (P3 + 3 * CH * P + P2 * CH + CH * P + 2 * P); }
+    static size_t lds_root() { return sizeof(double) * (P3 + 2 * P + 3 * 16 * P); }
+};
 
-Dev make_dev(Plan *P)
+template <typename T>
+Dev<T> make_dev(Plan *P)
 {
-    Dev D;
+    Dev<T> D;
     const Tables &t = P->tab;
-    D.p = t.p; D.p2 = t.p * t.p; D.p3 = t.p * t.p * t.p;
-    D.nf = t.nf; D.nn = t.nn; D.nh = t.nh; D.nw = t.nw; D.nwn = t.nwn; D.nwh = t.nwh; D.gdeg = t.gdeg;
-    D.X = P->X; D.Y = P->Y; D.Z = P->Z;
+    D.p = t.p; D.nf = t.nf; D.nn = t.nn; D.nh = t.nh; D.nw = t.nw; D.nwn = t.nwn; D.nwh = t.nwh;
+    D.gdeg = sizeof(T) == 8 ? t.gdeg : t.gdeg32;
+    D.X = P->X; D.Y = P->Y; D.Z = P->Z; D.qs = P->qs;
     D.pstart = P->pstart; D.pcount = P->pcount; D.child0 = P->child0; D.parent = P->parent; D.col = P->colleague;
     D.proxy_slot = P->proxy_slot; D.local_slot = P->local_slot; D.psi_slot = P->psi_slot; D.blevel = P->blevel;
+    D.anchor = P->anchor;
     D.bflags = P->bflags; D.bcenter = P->bcenter;
-    D.c2p = P->d_c2p; D.epw = P->d_epw; D.ew = P->d_ew; D.wd0 = P->d_wd0; D.ww = P->d_ww;
-    D.gcheb = P->d_gcheb; D.xcheb = P->d_xcheb; D.bary = P->d_bary;
-    D.qs = P->qs; D.proxy = P->proxy; D.local = P->local; D.phi = P->phi; D.psi = P->psi;
-    D.w0vals = P->w0vals; D.ufar = P->ufar; D.ures = P->ures;
+    const bool f64 = sizeof(T) == 8;
+    D.c2p = (const T *)(f64 ? (void *)P->d_c2p : (void *)P->f_c2p);
+    D.epw = (const T *)(f64 ? (void *)P->d_epw : (void *)P->f_epw);
+    D.wd0 = (const T *)(f64 ? (void *)P->d_wd0 : (void *)P->f_wd0);
+    D.gcheb = (const T *)(f64 ? (void *)P->d_gcheb : (void *)P->f_gcheb);
+    D.xcheb = (const T *)(f64 ? (void *)P->d_xcheb : (void *)P->f_xcheb);
+    D.bary = (const T *)(f64 ? (void *)P->d_bary : (void *)P->f_bary);
+    D.ew64 = P->d_ew; D.ww64 = P->d_ww; D.xcheb64 = P->d_xcheb; D.bary64 = P->d_bary;
+    D.proxy = (T *)P->proxy; D.local = (T *)P->local; D.phi = (T *)P->phi; D.psi = (T *)P->psi;
+    D.w0vals = (T *)P->w0vals;
+    D.ufar = P->ufar; D.ures = P->ures; D.rootscratch = P->rootscratch;
+    D.pwstride = (int64_t)t.nh * t.nn * t.nn;
     return D;
 }
 
-bool g_attr_done = false;
-void set_lds_attrs(const Plan *P)
+template <typename K>
+void allow_lds(K kernel, size_t bytes)
 {
-    size_t need = std::max({lds_upward(P), lds_p2pw(P), lds_root(P), lds_local(P), lds_pw2grid(P), lds_leaf(P)});
     int dev = 0, lim = 0;
     DMK_HIP(hipGetDevice(&dev));
     DMK_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if ((size_t)lim < need)
+    if ((size_t)lim < bytes)
         throw Error{DMK_ERR_UNSUPPORTED, "device LDS per workgroup (" + std::to_string(lim) + " B) below the " +
-                                             std::to_string(need) + " B the stages need"};
-    if (g_attr_done) return;
-    const int maxlds = lim;
-    DMK_HIP(hipFuncSetAttribute((const void *)k_upward, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    DMK_HIP(hipFuncSetAttribute((const void *)k_proxy2pw, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    DMK_HIP(hipFuncSetAttribute((const void *)k_root_w0, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    DMK_HIP(hipFuncSetAttribute((const void *)k_local_init, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    DMK_HIP(hipFuncSetAttribute((const void *)k_pw2grid, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    DMK_HIP(hipFuncSetAttribute((const void *)k_leaf_eval, hipFuncAttributeMaxDynamicSharedMemorySize, maxlds));
-    g_attr_done = true;
+                                             std::to_string(bytes) + " B a stage needs"};
+    DMK_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
 }
 
 }  // namespace
+
+// Records HIP events around one stage launch when timing is enabled.
+struct StageScope {
+    Plan *P;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    hipEvent_t get()
+    {
+        if (!P->event_pool.empty()) {
+            hipEvent_t e = P->event_pool.back();
+            P->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        DMK_HIP(hipEventCreate(&e));
+        return e;
+    }
+    StageScope(Plan *p, hipStream_t st, int sg) : P(p), s(st), stage(sg)
+    {
+        if (P->timing) {
+            a = get();
+            DMK_HIP(hipEventRecord(a, s));
+        }
+    }
+    ~StageScope() noexcept(false)
+    {
+        if (P->timing) {
+            hipEvent_t b = get();
+            DMK_HIP(hipEventRecord(b, s));
+            P->pending.push_back({stage, a, b});
+        }
+    }
+};
+
+template <typename T, int P, int NF>
+static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far_part, double *near_part,
+                       hipStream_t s)
+{
+    using C = Cfg<T, P, NF>;
+    const int64_t n = Pl->n;
+    static bool attrs = false;
+    if (!attrs) {
+        allow_lds(k_upward<T, P>, C::lds_up());
+        allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
+        allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
+        allow_lds(k_leaf<T, P, C::CH>, C::lds_leaf());
+        allow_lds(k_root_w0<T>, C::lds_root());
+        attrs = true;
+    }
+    Dev<T> D = make_dev<T>(Pl);
+    const auto &ll = Pl->ll;
+    const int L = Pl->nlevels;
+    {
+        StageScope t(Pl, s, DMK_STAGE_GATHER);
+        hipLaunchKernelGGL(k_gather_q, dim3(nblk(n)), dim3(TPB), 0, s, charges, Pl->perm, n, Pl->qs);
+    }
+    // Step 2: upward pass, finest level first
+    for (int l = L - 1; l >= 0; --l) {
+        int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
+        if (!m) continue;
+        StageScope t(Pl, s, DMK_STAGE_UPWARD);
+        hipLaunchKernelGGL((k_upward<T, P>), dim3((unsigned)m), dim3(TPB), C::lds_up(), s, D, Pl->l_fout + ll.fout_off[l]);
+    }
+    {
+        StageScope t(Pl, s, DMK_STAGE_ROOT);
+        int root_fout = (ll.fout_off[1] > 0) ? 1 : 0;
+        hipLaunchKernelGGL((k_root_w0<T>), dim3(1), dim3(TPB), C::lds_root(), s, D, root_fout);
+    }
+    // Step 3: downward pass
+    for (int l = 0; l < L; ++l) {
+        int64_t nfo = ll.fout_off[l + 1] - ll.fout_off[l];
+        int64_t nfi = ll.fin_off[l + 1] - ll.fin_off[l];
+        int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];
+        if (nfo) {
+            StageScope t(Pl, s, DMK_STAGE_PROXY2PW);
+            hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)nfo), dim3(TPB), C::lds_p2pw(), s, D,
+                               Pl->l_fout + ll.fout_off[l], ll.fout_off[l]);
+        }
+        if (nfi) {
+            StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
+            hipLaunchKernelGGL((k_pwshift<T>), dim3((unsigned)nfi), dim3(TPB), 0, s, D, Pl->l_fin + ll.fin_off[l],
+                               ll.fout_off[l], (T)std::ldexp(1.0, l));
+        }
+        if (nan) {
+            StageScope t(Pl, s, DMK_STAGE_PW2GRID);
+            hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,
+                               Pl->l_anc + ll.anc_off[l], l);
+        }
+    }
+    if (Pl->nleaf) {
+        {
+            StageScope t(Pl, s, DMK_STAGE_LEAF);
+            hipLaunchKernelGGL((k_leaf<T, P, C::CH>), dim3((unsigned)Pl->nleaf), dim3(TPB), C::lds_leaf(), s, D, Pl->l_leaf);
+        }
+        StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
+        hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src);
+    }
+    {
+        StageScope t(Pl, s, DMK_STAGE_FINALIZE);
+        const double scale = 1.0 / (4.0 * M_PI * Pl->side);
+        hipLaunchKernelGGL(k_finalize, dim3(nblk(n)), dim3(TPB), 0, s, Pl->ufar, Pl->ures, Pl->perm, n, scale, pot,
+                           far_part, near_part);
+    }
+    DMK_HIP(hipGetLastError());
+}
+
+void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part, hipStream_t s)
+{
+    if (P->n == 0) return;
+    const bool f64 = P->precision == DMK_FP64;
+    switch (P->p) {
+    case 18:
+        if (f64) run_eval_t<double, 18, 12>(P, charges, pot, far_part, near_part, s);
+        else run_eval_t<float, 18, 12>(P, charges, pot, far_part, near_part, s);
+        break;
+    case 15:
+        if (f64) run_eval_t<double, 15, 10>(P, charges, pot, far_part, near_part, s);
+        else run_eval_t<float, 15, 10>(P, charges, pot, far_part, near_part, s);
+        break;
+    case 9:
+        if (f64) run_eval_t<double, 9, 6>(P, charges, pot, far_part, near_part, s);
+        else run_eval_t<float, 9, 6>(P, charges, pot, far_part, near_part, s);
+        break;
+    default:
+        throw Error{DMK_ERR_UNSUPPORTED, "no kernels for this proxy order"};
+    }
+}
 
 void upload_tables(Plan *P, hipStream_t s)
 {
@@ -665,6 +999,14 @@ void upload_tables(Plan *P, hipStream_t s)
     auto up = [&](const std::vector<double> &v) {
         double *d = (double *)dalloc(P, std::max<size_t>(v.size(), 1) * sizeof(double));
         if (!v.empty()) DMK_HIP(hipMemcpyAsync(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        return d;
+    };
+    std::vector<std::vector<float>> keep;
+    auto upf = [&](const std::vector<double> &v) {
+        keep.emplace_back(v.begin(), v.end());
+        const auto &h = keep.back();
+        float *d = (float *)dalloc(P, std::max<size_t>(h.size(), 1) * sizeof(float));
+        if (!h.empty()) DMK_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, s));
         return d;
     };
     P->d_c2p = up(t.c2p);
@@ -675,62 +1017,139 @@ void upload_tables(Plan *P, hipStream_t s)
     P->d_gcheb = up(t.gcheb);
     P->d_xcheb = up(t.xcheb);
     P->d_bary = up(t.bary);
+    P->f_c2p = upf(t.c2p);
+    P->f_epw = upf(t.epw);
+    P->f_wd0 = upf(t.wd0);
+    P->f_gcheb = upf(t.gcheb);
+    P->f_xcheb = upf(t.xcheb);
+    P->f_bary = upf(t.bary);
     DMK_HIP(hipStreamSynchronize(s));
 }
 
 void alloc_workspace(Plan *P)
 {
     const Tables &t = P->tab;
+    const size_t el = (P->precision == DMK_FP64) ? sizeof(double) : sizeof(float);
     const int64_t p3 = (int64_t)t.p * t.p * t.p;
     const int64_t nm = (int64_t)t.nh * t.nn * t.nn;
-    const int64_t nmw = (int64_t)t.nwh * t.nwn * t.nwn;
-    auto al = [&](int64_t cnt) { return (double *)dalloc(P, (size_t)std::max<int64_t>(cnt, 1) * sizeof(double)); };
-    P->qs = al(P->n);
-    P->ufar = al(P->n);
-    P->ures = al(P->n);
-    P->proxy = al(P->nfout * p3);
-    P->local = al(P->nne * p3);
-    P->phi = al(2 * std::max<int64_t>(P->max_fout_level * nm, nmw));
-    P->psi = al(2 * P->max_fin_level * nm);
-    P->w0vals = al(p3);
+    auto al = [&](int64_t cnt, size_t sz) { return dalloc(P, (size_t)std::max<int64_t>(cnt, 1) * sz); };
+    P->qs = (double *)al(P->n, 8);
+    P->ufar = (double *)al(P->n, 8);
+    P->ures = (double *)al(P->n, 8);
+    P->rootscratch = (double *)al(root_scratch_elems(t), 8);
+    P->proxy = al(P->nfout * p3, el);
+    P->local = al(P->nanc * p3, el);
+    P->phi = al(2 * P->max_fout_level * nm, el);
+    P->psi = al(2 * P->max_fin_level * nm, el);
+    P->w0vals = al(p3, el);
 }
 
-void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part, hipStream_t s)
+// ---------------------------------------------------------- work counts
+namespace {
+// pairs of the residual lists closer than the source box side (r < s_l)
+__global__ void __launch_bounds__(TPB) k_count_inrange(const double *X, const double *Y, const double *Z,
+                                                       const int32_t *pstart, const int32_t *pcount,
+                                                       const int32_t *leaves, const int32_t *nl_off,
+                                                       const int32_t *nl_src, const int32_t *blevel,
+                                                       unsigned long long *total)
 {
-    const int64_t n = P->n;
-    if (n == 0) return;
-    set_lds_attrs(P);
-    Dev D = make_dev(P);
-    const auto &ll = P->ll;
-    const int L = P->nlevels;
-    hipLaunchKernelGGL(k_gather_q, dim3(nblk(n)), dim3(TPB), 0, s, charges, P->perm, n, P->qs);
-    // Step 2: upward pass, finest level first
-    for (int l = L - 1; l >= 0; --l) {
-        int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
-        if (m) hipLaunchKernelGGL(k_upward, dim3((unsigned)m), dim3(TPB), lds_upward(P), s, D, P->l_fout + ll.fout_off[l]);
-    }
-    // root: windowed kernel W_0 (the phi buffer doubles as scratch)
-    int root_fout = (ll.fout_off[1] > 0) ? 1 : 0;
-    hipLaunchKernelGGL(k_root_w0, dim3(1), dim3(TPB), lds_root(P), s, D, root_fout, P->phi);
-    // Step 3: downward pass
-    for (int l = 0; l < L; ++l) {
-        int64_t nfo = ll.fout_off[l + 1] - ll.fout_off[l];
-        int64_t nne = ll.ne_off[l + 1] - ll.ne_off[l];
-        int64_t nfi = ll.fin_off[l + 1] - ll.fin_off[l];
-        if (nfo) hipLaunchKernelGGL(k_proxy2pw, dim3((unsigned)nfo), dim3(TPB), lds_p2pw(P), s, D, P->l_fout + ll.fout_off[l], ll.fout_off[l]);
-        if (nne) hipLaunchKernelGGL(k_local_init, dim3((unsigned)nne), dim3(TPB), lds_local(P), s, D, P->l_ne + ll.ne_off[l], l);
-        if (nfi) {
-            hipLaunchKernelGGL(k_pwshift, dim3((unsigned)nfi), dim3(TPB), 0, s, D, P->l_fin + ll.fin_off[l], ll.fout_off[l], std::ldexp(1.0, l));
-            hipLaunchKernelGGL(k_pw2grid, dim3((unsigned)nfi), dim3(TPB), lds_pw2grid(P), s, D, P->l_fin + ll.fin_off[l]);
+    __shared__ unsigned long long red[TPB];
+    const int32_t B = leaves[blockIdx.x];
+    const int64_t t0 = pstart[B];
+    const int nt = pcount[B];
+    unsigned long long cnt = 0;
+    for (int tt = threadIdx.x; tt < nt; tt += TPB) {
+        const double xt = X[t0 + tt], yt = Y[t0 + tt], zt = Z[t0 + tt];
+        for (int li = nl_off[blockIdx.x]; li < nl_off[blockIdx.x + 1]; ++li) {
+            const int32_t T = nl_src[li];
+            const double s = ldexp(1.0, -blevel[T]), s2 = s * s;
+            for (int64_t j = pstart[T]; j < pstart[T] + pcount[T]; ++j) {
+                double dx = xt - X[j], dy = yt - Y[j], dz = zt - Z[j];
+                cnt += (dx * dx + dy * dy + dz * dz < s2) ? 1 : 0;
+            }
         }
     }
-    if (P->nleaf) {
-        hipLaunchKernelGGL(k_leaf_eval, dim3((unsigned)P->nleaf), dim3(TPB), lds_leaf(P), s, D, P->l_leaf);
-        hipLaunchKernelGGL(k_residual, dim3((unsigned)P->nleaf), dim3(TPB), 0, s, D, P->l_leaf, P->nl_off, P->nl_src, P->blevel);
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
-    const double scale = 1.0 / (4.0 * M_PI * P->side);
-    hipLaunchKernelGGL(k_finalize, dim3(nblk(n)), dim3(TPB), 0, s, P->ufar, P->ures, P->perm, n, scale, pot, far_part, near_part);
-    DMK_HIP(hipGetLastError());
+    if (threadIdx.x == 0) atomicAdd(total, red[0]);
+}
+}  // namespace
+
+void count_work(Plan *P, hipStream_t s)
+{
+    const int64_t nb = P->nbox;
+    std::vector<uint8_t> fl(nb);
+    std::vector<int32_t> pc(nb), c0(nb), col;
+    DMK_HIP(hipMemcpy(fl.data(), P->bflags, nb, hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(pc.data(), P->pcount, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(c0.data(), P->child0, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    col.resize((size_t)nb * 27);
+    DMK_HIP(hipMemcpy(col.data(), P->colleague, (size_t)nb * 27 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    P->n_anterp = P->n_merge = P->n_shift_pairs = 0;
+    if (nb > 0 && !(fl[0] & 2)) P->n_anterp += pc[0];  // a root leaf is anterpolated in the root stage
+    for (int64_t b = 0; b < nb; ++b) {
+        if (fl[b] & 2)
+            for (int k = 0; k < 8; ++k) {
+                int32_t c = c0[b] + k;
+                if (pc[c] == 0) continue;
+                if (fl[c] & 2) P->n_merge++; else P->n_anterp += pc[c];
+            }
+        if ((fl[b] & 4) && pc[b] > 0)
+            for (int k = 0; k < 27; ++k) {
+                int32_t j = col[(size_t)b * 27 + k];
+                if (j >= 0 && (fl[j] & 2)) P->n_shift_pairs++;
+            }
+    }
+    P->npairs_in = 0;
+    if (P->nleaf) {
+        unsigned long long *d = nullptr;
+        DMK_HIP(hipMalloc(&d, sizeof(unsigned long long)));
+        DMK_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_count_inrange, dim3((unsigned)P->nleaf), dim3(TPB), 0, s, P->X, P->Y, P->Z, P->pstart,
+                           P->pcount, P->l_leaf, P->nl_off, P->nl_src, P->blevel, d);
+        unsigned long long h = 0;
+        DMK_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+        DMK_HIP(hipStreamSynchronize(s));
+        DMK_HIP(hipFree(d));
+        P->npairs_in = (int64_t)h;
+    }
+}
+
+// Algorithmic work of one eval: flops of the separable contractions and
+// pair evaluations, and the bytes that must cross HBM once.
+void stage_work(const Plan *P, double *F, double *Bt)
+{
+    const Tables &t = P->tab;
+    const double el = (P->precision == DMK_FP64) ? 8.0 : 4.0;
+    const double p = t.p, p3 = p * p * p, p4 = p3 * p, n = t.nn, nh = t.nh;
+    const double N = (double)P->n;
+    const double pwflops = 4 * nh * p3 + 8 * nh * n * p * p + 8 * nh * n * n * p;  // one box, either direction
+    const double pwbytes = 2 * el * nh * n * n;                                      // one half spectrum
+    for (int i = 0; i < DMK_NSTAGES; ++i) F[i] = Bt[i] = 0.0;
+    Bt[DMK_STAGE_GATHER] = 20 * N;
+    F[DMK_STAGE_UPWARD] = 2 * p3 * P->n_anterp + 6 * p4 * P->n_merge;
+    Bt[DMK_STAGE_UPWARD] = 32.0 * P->n_anterp + el * p3 * (P->n_merge + P->nfout);
+    {
+        const double nw = t.nwn, nwh = t.nwh;
+        F[DMK_STAGE_ROOT] = 2 * (4 * nwh * p3 + 8 * nwh * nw * p * p + 8 * nwh * nw * nw * p);
+        Bt[DMK_STAGE_ROOT] = 16 * p3;
+    }
+    F[DMK_STAGE_PROXY2PW] = pwflops * P->nfout;
+    Bt[DMK_STAGE_PROXY2PW] = (el * p3 + pwbytes) * P->nfout;
+    F[DMK_STAGE_PWSHIFT] = 8 * nh * n * n * P->n_shift_pairs;
+    Bt[DMK_STAGE_PWSHIFT] = pwbytes * (P->nfout + P->nfin);
+    // anchors: interpolation from the anchor ancestor (6 p^4) plus the plane waves
+    F[DMK_STAGE_PW2GRID] = pwflops * P->nfin + 6 * p4 * std::max<int64_t>(P->nanc - 1, 0);
+    Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p3 * P->nanc;
+    F[DMK_STAGE_LEAF] = 2 * p3 * N;
+    Bt[DMK_STAGE_LEAF] = 40 * N + el * p3 * P->nleaf;
+    F[DMK_STAGE_RESIDUAL] = 8.0 * P->npairs + (2.0 * (P->precision == DMK_FP64 ? t.gdeg : t.gdeg32) + 8.0) * P->npairs_in;
+    Bt[DMK_STAGE_RESIDUAL] = 40 * N;
+    Bt[DMK_STAGE_FINALIZE] = 28 * N;
 }
 
 }  // namespace dmk

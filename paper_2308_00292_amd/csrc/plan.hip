@@ -506,14 +506,13 @@ void build_tree(Plan *P, const double *pts, hipStream_t s)
 namespace {
 
 __global__ void k_list_flags(int64_t nbox, const uint8_t *bflags, const int32_t *pcount, uint8_t *f_fout,
-                             uint8_t *f_ne, uint8_t *f_fin, uint8_t *f_leaf)
+                             uint8_t *f_fin, uint8_t *f_leaf)
 {
     int64_t b = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (b >= nbox) return;
     uint8_t f = bflags[b];
     bool ne = pcount[b] > 0;
     f_fout[b] = (f & 2) ? 1 : 0;
-    f_ne[b] = ne ? 1 : 0;
     f_fin[b] = (ne && (f & 4)) ? 1 : 0;
     f_leaf[b] = (ne && (f & 1)) ? 1 : 0;
 }
@@ -522,6 +521,16 @@ __global__ void k_slots(const int32_t *list, int64_t m, int32_t *slot)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i < m) slot[list[i]] = (int32_t)i;
+}
+
+// anchor of a box: itself if it holds points and has F_in, else its parent's
+// anchor; the root is always an anchor.  One launch per level, top down.
+__global__ void k_anchor(int64_t b0, int64_t nb, const int32_t *parent, const uint8_t *f_fin, int32_t *anchor)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= nb) return;
+    int64_t b = b0 + i;
+    anchor[b] = (parent[b] < 0 || f_fin[b]) ? (int32_t)b : anchor[parent[b]];
 }
 
 // residual lists, gather form: for target leaf B, the terminal non-empty
@@ -604,29 +613,43 @@ void build_lists(Plan *P, hipStream_t s)
     Scratch S;
     const int64_t nbox = P->nbox;
     const int L = P->nlevels;
-    uint8_t *f_fout = S.get<uint8_t>(nbox), *f_ne = S.get<uint8_t>(nbox), *f_fin = S.get<uint8_t>(nbox),
-            *f_leaf = S.get<uint8_t>(nbox);
-    hipLaunchKernelGGL(k_list_flags, dim3(nblk(nbox)), dim3(TPB), 0, s, nbox, P->bflags, P->pcount, f_fout, f_ne,
-                       f_fin, f_leaf);
+    uint8_t *f_fout = S.get<uint8_t>(nbox), *f_fin = S.get<uint8_t>(nbox), *f_leaf = S.get<uint8_t>(nbox);
+    hipLaunchKernelGGL(k_list_flags, dim3(nblk(nbox)), dim3(TPB), 0, s, nbox, P->bflags, P->pcount, f_fout, f_fin,
+                       f_leaf);
     P->l_fout = talloc<int32_t>(P, nbox);
-    P->l_ne = talloc<int32_t>(P, nbox);
     P->l_fin = talloc<int32_t>(P, nbox);
+    P->l_anc = talloc<int32_t>(P, nbox + 1);
     P->l_leaf = talloc<int32_t>(P, nbox);
+    P->anchor = talloc<int32_t>(P, nbox);
     auto &ll = P->ll;
     ll.fout_off.assign(L + 1, 0);
-    ll.ne_off.assign(L + 1, 0);
     ll.fin_off.assign(L + 1, 0);
+    ll.anc_off.assign(L + 1, 0);
     ll.leaf_off.assign(L + 1, 0);
     for (int l = 0; l < L; ++l) {
         int64_t b0 = P->level_start[l], nb = P->level_start[l + 1] - b0;
         ll.fout_off[l + 1] = ll.fout_off[l] + select_indices(S, f_fout, b0, nb, P->l_fout + ll.fout_off[l], s);
-        ll.ne_off[l + 1] = ll.ne_off[l] + select_indices(S, f_ne, b0, nb, P->l_ne + ll.ne_off[l], s);
         ll.fin_off[l + 1] = ll.fin_off[l] + select_indices(S, f_fin, b0, nb, P->l_fin + ll.fin_off[l], s);
         ll.leaf_off[l + 1] = ll.leaf_off[l] + select_indices(S, f_leaf, b0, nb, P->l_leaf + ll.leaf_off[l], s);
+        hipLaunchKernelGGL(k_anchor, dim3(nblk(nb)), dim3(TPB), 0, s, b0, nb, P->parent, f_fin, P->anchor);
+    }
+    // anchors: the root, then the non-empty F_in boxes of levels >= 1
+    {
+        int32_t zero = 0;
+        DMK_HIP(hipMemcpyAsync(P->l_anc, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        ll.anc_off[0] = 0;
+        ll.anc_off[1] = (P->n > 0) ? 1 : 0;
+        for (int l = 1; l < L; ++l) {
+            int64_t m = ll.fin_off[l + 1] - ll.fin_off[l];
+            if (m)
+                DMK_HIP(hipMemcpyAsync(P->l_anc + ll.anc_off[l], P->l_fin + ll.fin_off[l], m * sizeof(int32_t),
+                                       hipMemcpyDeviceToDevice, s));
+            ll.anc_off[l + 1] = ll.anc_off[l] + m;
+        }
     }
     P->nfout = ll.fout_off[L];
-    P->nne = ll.ne_off[L];
     P->nfin = ll.fin_off[L];
+    P->nanc = ll.anc_off[L];
     P->nleaf = ll.leaf_off[L];
     P->max_fin_level = 0;
     P->max_fout_level = 0;
@@ -642,8 +665,8 @@ void build_lists(Plan *P, hipStream_t s)
     DMK_HIP(hipMemsetAsync(P->psi_slot, 0xff, nbox * sizeof(int32_t), s));
     if (P->nfout)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfout)), dim3(TPB), 0, s, P->l_fout, P->nfout, P->proxy_slot);
-    if (P->nne)
-        hipLaunchKernelGGL(k_slots, dim3(nblk(P->nne)), dim3(TPB), 0, s, P->l_ne, P->nne, P->local_slot);
+    if (P->nanc)
+        hipLaunchKernelGGL(k_slots, dim3(nblk(P->nanc)), dim3(TPB), 0, s, P->l_anc, P->nanc, P->local_slot);
     // psi slots restart at 0 on every level (the buffer is reused per level)
     for (int l = 0; l < L; ++l) {
         int64_t m = ll.fin_off[l + 1] - ll.fin_off[l];

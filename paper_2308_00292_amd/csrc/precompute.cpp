@@ -279,11 +279,12 @@ void build_tables(const Params &prm, Tables *t)
             memo[k2] = (pswf_eval(*t, M_PI * km / (3.0 * c)) - pswf_eval(*t, 2.0 * M_PI * km / (3.0 * c))) /
                        (3.0 * M_PI * t->psi0 * k2);
         }
+        // same layout as the plane-wave arrays: [m1][m3][m2]
         t->wd0.assign((size_t)t->nh * t->nn * t->nn, 0.0);
-        for (int m3 = 0; m3 <= prm.nf; ++m3)
-            for (int m2 = -prm.nf; m2 <= prm.nf; ++m2)
-                for (int m1 = -prm.nf; m1 <= prm.nf; ++m1)
-                    t->wd0[((size_t)m3 * t->nn + (m2 + prm.nf)) * t->nn + (m1 + prm.nf)] =
+        for (int m1 = -prm.nf; m1 <= prm.nf; ++m1)
+            for (int m3 = 0; m3 <= prm.nf; ++m3)
+                for (int m2 = -prm.nf; m2 <= prm.nf; ++m2)
+                    t->wd0[((size_t)(m1 + prm.nf) * t->nh + m3) * t->nn + (m2 + prm.nf)] =
                         memo[m1 * m1 + m2 * m2 + m3 * m3];
     }
     // ---- windowed W_0 weights (hw/2pi)^3 * What_0(hw |m|)
@@ -320,10 +321,15 @@ void build_tables(const Params &prm, Tables *t)
             for (int k = 0; k < M; ++k) s += f[k] * std::cos(M_PI * j * (k + 0.5) / M);
             cf[j] = (j == 0 ? 1.0 : 2.0) * s / M;
         }
+        // keep the terms above the rounding floor of the samples (~1e-15)
         int deg = M - 1;
-        while (deg > 0 && std::fabs(cf[deg]) < 1e-17 * std::fabs(cf[0])) deg--;
+        while (deg > 0 && std::fabs(cf[deg]) < 1e-14 * std::fabs(cf[0])) deg--;
         t->gdeg = deg;
         t->gcheb.assign(cf.begin(), cf.begin() + deg + 1);
+        // FP32 evaluation needs only the terms above single-precision rounding
+        int deg32 = deg;
+        while (deg32 > 0 && std::fabs(cf[deg32]) < 2e-9 * std::fabs(cf[0])) deg32--;
+        t->gdeg32 = deg32;
     }
 }
 

@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 10
+    assert len(names) == 13
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:

@@ -1,14 +1,18 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Bars (FP64 mode; both sides use the same Table 1 parameters, so they agree
-to rounding, far below the 1e-6 relative l2 the method targets):
+FP64 mode (both sides use the same Table 1 parameters, so they agree to
+rounding, far below the 1e-6 relative l2 the method targets):
   * tree, flags, colleagues, coarse neighbours: bit-exact;
   * residual interaction lists: the same (target leaf, source box) pairs;
-  * proxy charges of F_out boxes and local values on Chebyshev grids:
-    max error <= 1e-11 of the box's largest entry;
+  * proxy charges of F_out boxes and local values on the Chebyshev grids of
+    the boxes that hold them: max error <= 1e-11 of the box's largest entry;
   * far and near parts and the potential: relative l2 <= 1e-10;
   * against O(N^2) direct summation: relative l2 <= 1e-6 (2e-6 for deep
     adaptive trees, see the oracle's own pins).
+Mixed mode (FP32 transforms and pair sums, FP64 offsets and final sums),
+same parameters, against the same FP64 oracle: tree and lists bit-exact;
+per-box data <= 2e-5 of the box's largest entry; far, near and potential
+relative l2 <= 1e-5; against direct summation <= 1e-5.
 """
 import sys
 
@@ -39,25 +43,41 @@ CASES = {
 }
 
 
-@pytest.fixture(scope="module", params=list(CASES))
+_ORACLE = {}
+
+
+def _oracle_run(oracle_mod, name):
+    if name not in _ORACLE:
+        pts, q, ns = CASES[name]()
+        pr = oracle_mod.params_for(1e-6)
+        ps = oracle_mod.PSWF(pr.c)
+        otree = oracle_mod.Tree(pts, ns)
+        ores = oracle_mod.dmk_eval(otree, pr, ps, q, keep=True)
+        _ORACLE.clear()
+        _ORACLE[name] = (pts, q, ns, otree, ores)
+    return _ORACLE[name]
+
+
+PARAMS = [(name, prec) for name in CASES for prec in ("fp64", "mixed")]
+BARS = {"fp64": dict(box=1e-11, l2=1e-10), "mixed": dict(box=2e-5, l2=1e-5)}
+
+
+@pytest.fixture(scope="module", params=PARAMS, ids=[f"{a}-{b}" for a, b in PARAMS])
 def case(request, oracle_mod):
     import paper_2308_00292_amd as dmk
-    name = request.param
-    pts, q, ns = CASES[name]()
-    _say(f"[case {name}] n={len(q)} ns={ns}")
-    pr = oracle_mod.params_for(1e-6)
-    ps = oracle_mod.PSWF(pr.c)
-    otree = oracle_mod.Tree(pts, ns)
-    ores = oracle_mod.dmk_eval(otree, pr, ps, q, keep=True)
+    name, prec = request.param
+    pts, q, ns, otree, ores = _oracle_run(oracle_mod, name)
+    _say(f"[case {name} {prec}] n={len(q)} ns={ns}")
     dev = torch.device("cuda:0")
     tp = torch.from_numpy(pts).to(dev)
     tq = torch.from_numpy(q).to(dev)
-    plan = dmk.Plan(tp, tol=1e-6, leaf_max=ns)
+    plan = dmk.Plan(tp, tol=1e-6, leaf_max=ns,
+                    precision=dmk.DMK_FP64 if prec == "fp64" else dmk.DMK_MIXED)
     pot = plan.eval(tq)
     far, near = plan.eval_parts(tq)
     torch.cuda.synchronize()
-    out = dict(name=name, pts=pts, q=q, ns=ns, otree=otree, ores=ores, plan=plan,
-               pot=pot.cpu().numpy(), far=far.cpu().numpy(), near=near.cpu().numpy())
+    out = dict(name=name, prec=prec, bar=BARS[prec], pts=pts, q=q, ns=ns, otree=otree, ores=ores,
+               plan=plan, pot=pot.cpu().numpy(), far=far.cpu().numpy(), near=near.cpu().numpy())
     yield out
     plan.close()
 
@@ -115,17 +135,21 @@ def test_near_lists_match_source_centric_definition(case):
 
 
 def test_proxies_and_locals(case):
-    ot, ores, plan = case["otree"], case["ores"], case["plan"]
+    """Proxies of F_out boxes; local values of the boxes that store them (the
+    root and the non-empty F_in boxes -- every other box's local polynomial
+    is its nearest such ancestor's, by the exactness of Lemma 2.2)."""
+    ot, ores, plan, bar = case["otree"], case["ores"], case["plan"], case["bar"]["box"]
     nchk = 0
     for b in np.nonzero(ot.fout)[0][:200]:
         g = plan.box_data(0, b)
         o = ores["proxy"][int(b)]
-        assert np.max(np.abs(g - o)) <= 1e-11 * np.max(np.abs(o)), b
+        assert np.max(np.abs(g - o)) <= bar * np.max(np.abs(o)), b
         nchk += 1
-    for b in np.nonzero(ot.pcount > 0)[0][:400]:
+    anchors = np.nonzero((ot.pcount > 0) & ((ot.fin == 1) | (ot.parent < 0)))[0]
+    for b in anchors[:400]:
         g = plan.box_data(1, b)
         o = ores["local"][int(b)]
-        assert np.max(np.abs(g - o)) <= 1e-11 * np.max(np.abs(o)), b
+        assert np.max(np.abs(g - o)) <= bar * np.max(np.abs(o)), b
         nchk += 1
     assert nchk > 0
 
@@ -137,9 +161,10 @@ def test_far_near_and_potential(case):
     near_o = np.empty_like(case["near"])
     far_o[ot.perm] = ores["ufar"] * scale
     near_o[ot.perm] = ores["ures"] * scale
-    assert rel_l2(case["far"], far_o) < 1e-10
-    assert rel_l2(case["near"], near_o) < 1e-10
-    assert rel_l2(case["pot"], ores["u"]) < 1e-10
+    bar = case["bar"]["l2"]
+    assert rel_l2(case["far"], far_o) < bar
+    assert rel_l2(case["near"], near_o) < bar
+    assert rel_l2(case["pot"], ores["u"]) < bar
     assert np.array_equal(case["pot"], case["far"] + case["near"]) or \
         rel_l2(case["pot"], case["far"] + case["near"]) < 1e-15
 
@@ -150,6 +175,8 @@ def test_against_direct_sum(case, oracle_mod):
     idx = np.arange(n) if n <= 6000 else np.random.default_rng(0).choice(n, 3000, replace=False)
     ud = oracle_mod.direct(pts, q, idx)
     bar = 1e-6 if case["name"].startswith(("cfg1", "uniform")) else 2e-6
+    if case["prec"] == "mixed":
+        bar = 1e-5
     assert rel_l2(case["pot"][idx], ud) < bar
 
 

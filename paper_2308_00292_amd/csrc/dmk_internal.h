@@ -96,11 +96,14 @@ struct Plan {
     // work lists (device, concatenated by level) and slot maps
     LevelLists ll;
     int32_t *l_fout = nullptr, *l_fin = nullptr, *l_anc = nullptr, *l_leaf = nullptr;
+    int32_t *anc_tbeg = nullptr;   // [nanc+1] offsets into anc_tgt
+    int32_t *anc_tgt = nullptr;    // [nleaf points] targets grouped by the anchor of their leaf
     int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
     int64_t nfout = 0, nfin = 0, nanc = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
 
     // near (residual) lists in gather form over l_leaf order
     int32_t *nl_off = nullptr, *nl_src = nullptr;
+    int32_t *nl_pre = nullptr;     // [nl_total + nleaf] running source-point counts per list (+ total)
     int64_t nl_total = 0, npairs = 0;
 
     // device tables, FP64 and FP32 copies

@@ -11,7 +11,7 @@
 //                with the child->parent anterpolation matrices (Lemma 2.1);
 //                the points of all other children are anterpolated straight
 //                onto the parent's grid (Def. 2.1, exact by Lemma 2.1).
-//   k_root_w0    windowed kernel W_0 on the root grid (FP64 always).
+//   k_root_stage windowed kernel W_0 on the root grid (FP64 always).
 //   k_proxy2pw   outgoing plane waves Phi_l(B) of F_out boxes.
 //   k_pwshift    incoming plane waves Psi_l(B) from the F_out colleagues
 //                (diagonal translation; with h_l s_l = 2 pi/3 the phases
@@ -527,260 +527,317 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
 }
 
 // ------------------------------------------------------------ leaf targets
-template <typename T, int P, int CH>
-__global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *list)
+// Lagrange basis of the nodes at xi with one division (prefix products of
+// the differences, Montgomery's batch inversion), barycentric weights bw.
+template <typename T, int P>
+__device__ inline void lagrange_row_fast(const T *xc, const T *bw, T xi, T (&out)[P])
+{
+    T d[P], pre[P];
+    int hit = -1;
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+        d[a] = xi - xc[a];
+        if (d[a] == T(0)) hit = a;
+    }
+    if (hit >= 0) {
+#pragma unroll
+        for (int a = 0; a < P; ++a) out[a] = (a == hit) ? T(1) : T(0);
+        return;
+    }
+    pre[0] = d[0];
+#pragma unroll
+    for (int a = 1; a < P; ++a) pre[a] = pre[a - 1] * d[a];
+    T inv = T(1) / pre[P - 1];
+    T den = T(0);
+#pragma unroll
+    for (int a = P - 1; a >= 1; --a) {
+        out[a] = bw[a] * (inv * pre[a - 1]);
+        inv *= d[a];
+        den += out[a];
+    }
+    out[0] = bw[0] * inv;
+    den += out[0];
+    const T r = T(1) / den;
+#pragma unroll
+    for (int a = 0; a < P; ++a) out[a] *= r;
+}
+
+// One workgroup per anchor box; one thread per target among the points of
+// the leaves whose anchor it is (at most 8 n_s of them): the anchor's p^3
+// values sit in LDS and every lane reads the same entry at the same time.
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, const int32_t *tbeg, const int32_t *tgt)
 {
     constexpr int P2 = P * P, P3 = P2 * P;
     extern __shared__ unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
-    T *v = sm;                  // p^3 anchor values
-    T *Lx = v + P3, *Ly = Lx + CH * P, *Lz = Ly + CH * P;
-    T *W = Lz + CH * P;         // [(j1 j2)][CH]
-    T *part = W + P2 * CH;      // [CH][p]
-    T *xc = part + CH * P, *bw = xc + P;
-    const int32_t B = list[blockIdx.x];
-    const int32_t A = D.anchor[B];
-    const T *src = D.local + (int64_t)D.local_slot[A] * P3;
+    T *v = sm, *xc = v + P3, *bw = xc + P;
+    const int a = blockIdx.x;
+    const int b0 = tbeg[a], b1 = tbeg[a + 1];
+    if (b0 == b1) return;
+    const int32_t A = anc[a];
+    const T *src = D.local + (int64_t)a * P3;
     for (int t = threadIdx.x; t < P3; t += TPB) v[t] = src[t];
     for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
-    const double *cA = D.bcenter + 3 * (int64_t)A;
+    __syncthreads();
+    const double cA0 = D.bcenter[3 * (int64_t)A], cA1 = D.bcenter[3 * (int64_t)A + 1],
+                 cA2 = D.bcenter[3 * (int64_t)A + 2];
     const double sc = 2.0 / box_side(D.blevel[A]);
-    const int64_t i0 = D.pstart[B];
-    const int cnt = D.pcount[B];
-    for (int base = 0; base < cnt; base += CH) {
-        const int m = min(CH, cnt - base);
-        __syncthreads();
-        for (int t = threadIdx.x; t < 3 * m; t += TPB) {
-            int pt = t / 3, d = t % 3;
-            int64_t i = i0 + base + pt;
-            double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
-            T row[P];
-            lagrange_row<T>(P, xc, bw, (T)((x - cA[d]) * sc), row);
-            T *dst = (d == 0 ? Lx : d == 1 ? Ly : Lz) + pt * P;
+    for (int t = b0 + threadIdx.x; t < b1; t += TPB) {
+        const int64_t i = tgt[t];
+        T lx[P], ly[P], lz[P];
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.X[i] - cA0) * sc), lx);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.Y[i] - cA1) * sc), ly);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.Z[i] - cA2) * sc), lz);
+        T u = T(0);
+        for (int j1 = 0; j1 < P; ++j1) {
+            T s1 = T(0);
 #pragma unroll
-            for (int a = 0; a < P; ++a) dst[a] = row[a];
-        }
-        __syncthreads();
-        // W[(j1 j2)][t] = sum_j3 v[(j1 j2)][j3] Lz[t][j3]
-        gemm<T, 6, 2, false>(1, P2, m, P, v, 0, P, 1, Lz, 0, 1, P, W, 0, CH, 1);
-        __syncthreads();
-        for (int t = threadIdx.x; t < m * P; t += TPB) {
-            int pt = t % m, j1 = t / m;
-            T s = T(0);
+            for (int j2 = 0; j2 < P; ++j2) {
+                const T *row = v + j1 * P2 + j2 * P;
+                T s2 = T(0);
 #pragma unroll
-            for (int j2 = 0; j2 < P; ++j2) s += Ly[pt * P + j2] * W[(j1 * P + j2) * CH + pt];
-            part[pt * P + j1] = s * Lx[pt * P + j1];
+                for (int j3 = 0; j3 < P; ++j3) s2 += row[j3] * lz[j3];
+                s1 += ly[j2] * s2;
+            }
+            u += lx[j1] * s1;
         }
-        __syncthreads();
-        for (int pt = threadIdx.x; pt < m; pt += TPB) {
-            T s = T(0);
-#pragma unroll
-            for (int j1 = 0; j1 < P; ++j1) s += part[pt * P + j1];
-            D.ufar[i0 + base + pt] = (double)s;
-        }
+        D.ufar[i] = (double)u;
     }
 }
 
 // -------------------------------------------------------------- residual
-// Offsets of targets and sources from the target leaf's centre are formed in
-// FP64 and rounded to T once per point; each pair is evaluated in T and the
-// per-tile partial sums are added into an FP64 accumulator.  In FP64 mode
-// this is plain double arithmetic.
+// One workgroup per target leaf.  The sources of the leaf's whole gather list
+// are staged in LDS (offsets from the leaf centre formed in FP64 and rounded
+// to T once per point, with 1/s and 1/s^2 of the source box level); each
+// thread then sums one target against a stride of the staged sources, and
+// the per-pass partial sums are added into an FP64 accumulator.
+constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
+
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
-                                                  const int32_t *nl_src)
+                                                  const int32_t *nl_src, const int32_t *nl_pre)
 {
-    __shared__ T sx[TPB], sy[TPB], sz[TPB], sq[TPB];
-    __shared__ double part[TPB];
+    constexpr int RCAP = sizeof(T) == 8 ? 512 : 1024;  // sources staged per pass
+    __shared__ T sx[RCAP], sy[RCAP], sz[RCAP], sq[RCAP], sis[RCAP], sis2[RCAP];
+    __shared__ int32_t loff[RLIST + 1];
     __shared__ T gc[48];
+    __shared__ double part[TPB];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.pstart[B];
     const int nt = D.pcount[B];
+    const int32_t l0 = nl_off[blockIdx.x];
+    const int L = nl_off[blockIdx.x + 1] - l0;
+    const int deg = D.gdeg;
+    for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
+    // running source counts over the list (computed at plan time)
+    for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
+    __syncthreads();
+    const int nsrc = loff[L];
+    const double cx = D.bcenter[3 * (int64_t)B], cy = D.bcenter[3 * (int64_t)B + 1], cz = D.bcenter[3 * (int64_t)B + 2];
     const int tch = (nt <= 32) ? 32 : 64;
     const int nsplit = TPB / tch;
     const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
-    const int32_t l0 = nl_off[blockIdx.x], l1 = nl_off[blockIdx.x + 1];
-    const int deg = D.gdeg;
-    for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
-    const double cx = D.bcenter[3 * (int64_t)B], cy = D.bcenter[3 * (int64_t)B + 1], cz = D.bcenter[3 * (int64_t)B + 2];
     for (int tbase = 0; tbase < nt; tbase += tch) {
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
         const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy), zt = (T)(D.Z[it] - cz);
         double acc = 0.0;
-        for (int li = l0; li < l1; ++li) {
-            const int32_t Tb = nl_src[li];
-            const int lev = D.blevel[Tb];
-            const T inv_s = (T)ldexp(1.0, lev), inv_s2 = inv_s * inv_s, s2 = (T)ldexp(1.0, -2 * lev);
-            const int64_t j0 = D.pstart[Tb];
-            const int ns = D.pcount[Tb];
-            for (int jb = 0; jb < ns; jb += TPB) {
-                const int cnt = min(TPB, ns - jb);
-                __syncthreads();
-                if (threadIdx.x < cnt) {
-                    int64_t j = j0 + jb + threadIdx.x;
-                    sx[threadIdx.x] = (T)(D.X[j] - cx);
-                    sy[threadIdx.x] = (T)(D.Y[j] - cy);
-                    sz[threadIdx.x] = (T)(D.Z[j] - cz);
-                    sq[threadIdx.x] = (T)D.qs[j];
+        for (int pb = 0; pb < nsrc; pb += RCAP) {
+            const int cnt = min(RCAP, nsrc - pb);
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < cnt; idx += TPB) {
+                const int g = pb + idx;
+                int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (loff[mid] <= g) lo = mid; else hi = mid - 1;
                 }
-                __syncthreads();
-                T pacc = T(0);
-                for (int j = split; j < cnt; j += nsplit) {
-                    T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
-                    T r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < s2) {
-                        // Clenshaw for g(t) = Phi(sqrt t)/sqrt t, t = r^2/s^2
-                        T u = T(2) * r2 * inv_s2 - T(1);
-                        T b1 = T(0), b2 = T(0);
-                        for (int k = deg; k >= 1; --k) {
-                            T b0 = gc[k] + T(2) * u * b1 - b2;
-                            b2 = b1;
-                            b1 = b0;
-                        }
-                        T g = gc[0] + u * b1 - b2;
-                        T rinv = (r2 > T(0)) ? rsqrt(r2) : T(0);
-                        pacc += sq[j] * (rinv - g * inv_s);
-                    }
-                }
-                acc += (double)pacc;
+                const int32_t Tb = nl_src[l0 + lo];
+                const int64_t j = D.pstart[Tb] + (g - loff[lo]);
+                const int lev = D.blevel[Tb];
+                sx[idx] = (T)(D.X[j] - cx);
+                sy[idx] = (T)(D.Y[j] - cy);
+                sz[idx] = (T)(D.Z[j] - cz);
+                sq[idx] = (T)D.qs[j];
+                sis[idx] = (T)ldexp(1.0, lev);
+                sis2[idx] = (T)ldexp(1.0, 2 * lev);
             }
+            __syncthreads();
+            T pacc = T(0);
+            for (int j = split; j < cnt; j += nsplit) {
+                const T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T tt = r2 * sis2[j];
+                if (tt < T(1)) {
+                    // Clenshaw for g(t) = Phi(sqrt t)/sqrt t
+                    const T u = T(2) * tt - T(1);
+                    T b1 = T(0), b2 = T(0);
+                    for (int k = deg; k >= 1; --k) {
+                        T b0 = gc[k] + T(2) * u * b1 - b2;
+                        b2 = b1;
+                        b1 = b0;
+                    }
+                    const T g = gc[0] + u * b1 - b2;
+                    const T rinv = (r2 > T(0)) ? rsqrt(r2) : T(0);
+                    pacc += sq[j] * (rinv - g * sis[j]);
+                }
+            }
+            acc += (double)pacc;
         }
         __syncthreads();
         part[threadIdx.x] = acc;
         __syncthreads();
         if (split == 0 && active) {
-            double s = 0.0;
-            for (int k = 0; k < nsplit; ++k) s += part[k * tch + tl];
-            D.ures[t0 + tbase + tl] = s;
+            double sum = 0.0;
+            for (int k = 0; k < nsplit; ++k) sum += part[k * tch + tl];
+            D.ures[t0 + tbase + tl] = sum;
         }
     }
 }
 
 // ----------------------------------------------------------- root window
 // Root proxies -> W_0 plane waves (spacing hw, half width nw) times the
-// window weights -> values on the root grid, in FP64.  One workgroup; the
-// intermediates live in a global scratch buffer (O(1) work per eval).
+// window weights -> values on the root grid, in FP64 (O(1) work per eval).
+// Eight grid-wide stages, one thread per output entry; the intermediates
+// live in a global scratch buffer laid out as in root_scratch_elems.
+struct RootLayout {
+    int64_t rows, rho, Ar, Ai, Br, Bi, Fr, Fi, C1r, C1i, C2r, C2i, total;
+    __host__ __device__ RootLayout(int p, int n, int nh, int npts)
+    {
+        const int64_t p2 = (int64_t)p * p;
+        rows = 0;
+        rho = rows + 3 * (int64_t)npts * p;
+        Ar = rho + p2 * p;
+        Ai = Ar + p2 * nh;
+        Br = Ai + p2 * nh;
+        Bi = Br + (int64_t)p * nh * n;
+        Fr = Bi + (int64_t)p * nh * n;
+        Fi = Fr + (int64_t)n * nh * n;
+        C1r = Fi + (int64_t)n * nh * n;
+        C1i = C1r + (int64_t)n * n * p;
+        C2r = C1i + (int64_t)n * n * p;
+        C2i = C2r + (int64_t)n * p2;
+        total = C2i + (int64_t)n * p2;
+    }
+};
+
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_root_w0(Dev<T> D, int root_fout)
+__global__ void __launch_bounds__(TPB) k_root_stage(Dev<T> D, int stage, int root_fout, int npts)
 {
-    extern __shared__ unsigned char smraw[];
-    double *sm = reinterpret_cast<double *>(smraw);
     const int p = D.p, p2 = p * p, p3 = p2 * p, n = D.nwn, nh = D.nwh, nw = D.nw;
-    double *rho = sm, *xc = rho + p3, *bw = xc + p, *L = bw + p;  // L: 3 * 16 * p
-    double *Ar = D.rootscratch, *Ai = Ar + p2 * nh;               // [(j1 j2)][m3]
-    double *Br = Ai + p2 * nh, *Bi = Br + p * nh * n;             // [j1][m3][m2]
-    double *Fr = Bi + p * nh * n, *Fi = Fr + n * nh * n;          // [m1][m3][m2]
-    double *C1r = Fi + n * nh * n, *C1i = C1r + n * n * p;        // [m1][m2][j3]
-    double *C2r = C1i + n * n * p, *C2i = C2r + n * p2;           // [m1][(j2 j3)]
-    for (int t = threadIdx.x; t < p; t += TPB) { xc[t] = D.xcheb64[t]; bw[t] = D.bary64[t]; }
-    for (int t = threadIdx.x; t < p3; t += TPB) rho[t] = 0.0;
-    __syncthreads();
-    if (root_fout) {
-        const T *src = D.proxy + (int64_t)D.proxy_slot[0] * p3;
-        for (int t = threadIdx.x; t < p3; t += TPB) rho[t] = (double)src[t];
-    } else {
-        // the root holds at most n_s points: anterpolate them directly
-        const int cnt = D.pcount[0];
-        for (int base = 0; base < cnt; base += 16) {
-            const int m = min(16, cnt - base);
-            __syncthreads();
-            for (int t = threadIdx.x; t < 3 * m; t += TPB) {
-                int pt = t / 3, d = t % 3;
-                double x = (d == 0) ? D.X[base + pt] : (d == 1) ? D.Y[base + pt] : D.Z[base + pt];
-                lagrange_row<double>(p, xc, bw, 2.0 * x, L + (d * 16 + pt) * p);
-            }
-            __syncthreads();
-            for (int e = threadIdx.x; e < p3; e += TPB) {
-                int a0 = e / p2, a1 = (e / p) % p, a2 = e % p;
-                double s = 0.0;
-                for (int pt = 0; pt < m; ++pt)
-                    s += L[pt * p + a0] * L[(16 + pt) * p + a1] * L[(32 + pt) * p + a2] * D.qs[base + pt];
-                rho[e] += s;
-            }
-        }
-    }
-    __syncthreads();
+    const RootLayout R(p, n, nh, npts);
+    double *S = D.rootscratch;
     const double *E = D.ew64;  // [n][p][2], rows m + nw
-    for (int e = threadIdx.x; e < p2 * nh; e += TPB) {
-        int r = e / nh, m3 = e % nh;
-        double re = 0, im = 0;
-        for (int j = 0; j < p; ++j) {
-            re += E[2 * ((m3 + nw) * p + j)] * rho[r * p + j];
-            im += E[2 * ((m3 + nw) * p + j) + 1] * rho[r * p + j];
+    const int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    switch (stage) {
+    case 0:  // Lagrange rows of the root's points (root without F_out)
+        if (e < 3 * npts) {
+            const int pt = (int)(e / 3), d = (int)(e % 3);
+            const double x = (d == 0) ? D.X[pt] : (d == 1) ? D.Y[pt] : D.Z[pt];
+            lagrange_row<double>(p, D.xcheb64, D.bary64, 2.0 * x, S + R.rows + (d * (int64_t)npts + pt) * p);
         }
-        Ar[e] = re;
-        Ai[e] = im;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < p * nh * n; e += TPB) {
-        int j1 = e / (nh * n), m3 = (e / n) % nh, m2 = e % n;
-        double re = 0, im = 0;
-        for (int j = 0; j < p; ++j) {
-            double er = E[2 * (m2 * p + j)], ei = E[2 * (m2 * p + j) + 1];
-            double ar = Ar[(j1 * p + j) * nh + m3], ai = Ai[(j1 * p + j) * nh + m3];
-            re += er * ar - ei * ai;
-            im += er * ai + ei * ar;
+        break;
+    case 1:  // root proxies
+        if (e < p3) {
+            double v = 0.0;
+            if (root_fout) {
+                v = (double)D.proxy[(int64_t)D.proxy_slot[0] * p3 + e];
+            } else {
+                const int a0 = (int)(e / p2), a1 = (int)((e / p) % p), a2 = (int)(e % p);
+                const double *Lx = S + R.rows, *Ly = Lx + (int64_t)npts * p, *Lz = Ly + (int64_t)npts * p;
+                for (int pt = 0; pt < npts; ++pt) v += Lx[pt * p + a0] * Ly[pt * p + a1] * Lz[pt * p + a2] * D.qs[pt];
+            }
+            S[R.rho + e] = v;
         }
-        Br[e] = re;
-        Bi[e] = im;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * nh * n; e += TPB) {
-        int m1 = e / (nh * n), r = e % (nh * n), m3 = r / n, m2 = r % n;
-        double re = 0, im = 0;
-        for (int j = 0; j < p; ++j) {
-            double er = E[2 * (m1 * p + j)], ei = E[2 * (m1 * p + j) + 1];
-            re += er * Br[j * nh * n + r] - ei * Bi[j * nh * n + r];
-            im += er * Bi[j * nh * n + r] + ei * Br[j * nh * n + r];
+        break;
+    case 2:  // A[(j1 j2)][m3] = sum_j3 E[m3][j3] rho
+        if (e < (int64_t)p2 * nh) {
+            const int r = (int)(e / nh), m3 = (int)(e % nh);
+            double re = 0, im = 0;
+            for (int j = 0; j < p; ++j) {
+                re += E[2 * ((m3 + nw) * p + j)] * S[R.rho + r * p + j];
+                im += E[2 * ((m3 + nw) * p + j) + 1] * S[R.rho + r * p + j];
+            }
+            S[R.Ar + e] = re;
+            S[R.Ai + e] = im;
         }
-        double w = D.ww64[(m3 * n + m2) * n + m1];
-        Fr[e] = re * w;
-        Fi[e] = im * w;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n * p; e += TPB) {
-        int m1 = e / (n * p), m2 = (e / p) % n, j3 = e % p;
-        double re = 0, im = 0;
-        for (int m3 = 0; m3 < nh; ++m3) {
-            double c = (m3 == 0) ? 1.0 : 2.0;
-            double er = c * E[2 * ((m3 + nw) * p + j3)], ei = -c * E[2 * ((m3 + nw) * p + j3) + 1];
-            double fr = Fr[(m1 * nh + m3) * n + m2], fi = Fi[(m1 * nh + m3) * n + m2];
-            re += er * fr - ei * fi;
-            im += er * fi + ei * fr;
+        break;
+    case 3:  // B[j1][m3][m2] = sum_j2 E[m2][j2] A[j1][j2][m3]
+        if (e < (int64_t)p * nh * n) {
+            const int j1 = (int)(e / (nh * n)), m3 = (int)((e / n) % nh), m2 = (int)(e % n);
+            double re = 0, im = 0;
+            for (int j = 0; j < p; ++j) {
+                const double er = E[2 * (m2 * p + j)], ei = E[2 * (m2 * p + j) + 1];
+                const double ar = S[R.Ar + (j1 * p + j) * nh + m3], ai = S[R.Ai + (j1 * p + j) * nh + m3];
+                re += er * ar - ei * ai;
+                im += er * ai + ei * ar;
+            }
+            S[R.Br + e] = re;
+            S[R.Bi + e] = im;
         }
-        C1r[e] = re;
-        C1i[e] = im;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * p2; e += TPB) {
-        int m1 = e / p2, j2 = (e / p) % p, j3 = e % p;
-        double re = 0, im = 0;
-        for (int m2 = 0; m2 < n; ++m2) {
-            double er = E[2 * (m2 * p + j2)], ei = -E[2 * (m2 * p + j2) + 1];
-            double cr = C1r[(m1 * n + m2) * p + j3], ci = C1i[(m1 * n + m2) * p + j3];
-            re += er * cr - ei * ci;
-            im += er * ci + ei * cr;
+        break;
+    case 4:  // Phi[m1][m3][m2] = w(m) sum_j1 E[m1][j1] B[j1][m3][m2]
+        if (e < (int64_t)n * nh * n) {
+            const int m1 = (int)(e / (nh * n)), r = (int)(e % (nh * n)), m3 = r / n, m2 = r % n;
+            double re = 0, im = 0;
+            for (int j = 0; j < p; ++j) {
+                const double er = E[2 * (m1 * p + j)], ei = E[2 * (m1 * p + j) + 1];
+                const double br = S[R.Br + j * nh * n + r], bi = S[R.Bi + j * nh * n + r];
+                re += er * br - ei * bi;
+                im += er * bi + ei * br;
+            }
+            const double w = D.ww64[(m3 * n + m2) * n + m1];
+            S[R.Fr + e] = re * w;
+            S[R.Fi + e] = im * w;
         }
-        C2r[e] = re;
-        C2i[e] = im;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < p3; e += TPB) {
-        int j1 = e / p2, r = e % p2;
-        double s = 0.0;
-        for (int m1 = 0; m1 < n; ++m1) {
-            double er = E[2 * (m1 * p + j1)], ei = E[2 * (m1 * p + j1) + 1];
-            s += er * C2r[m1 * p2 + r] + ei * C2i[m1 * p2 + r];
+        break;
+    case 5:  // C1[m1][m2][j3] = sum_m3 c_m3 conj(E[m3][j3]) Phi[m1][m3][m2]
+        if (e < (int64_t)n * n * p) {
+            const int m1 = (int)(e / (n * p)), m2 = (int)((e / p) % n), j3 = (int)(e % p);
+            double re = 0, im = 0;
+            for (int m3 = 0; m3 < nh; ++m3) {
+                const double c = (m3 == 0) ? 1.0 : 2.0;
+                const double er = c * E[2 * ((m3 + nw) * p + j3)], ei = -c * E[2 * ((m3 + nw) * p + j3) + 1];
+                const double fr = S[R.Fr + (m1 * nh + m3) * n + m2], fi = S[R.Fi + (m1 * nh + m3) * n + m2];
+                re += er * fr - ei * fi;
+                im += er * fi + ei * fr;
+            }
+            S[R.C1r + e] = re;
+            S[R.C1i + e] = im;
         }
-        D.w0vals[e] = (T)s;
+        break;
+    case 6:  // C2[m1][j2][j3] = sum_m2 conj(E[m2][j2]) C1[m1][m2][j3]
+        if (e < (int64_t)n * p2) {
+            const int m1 = (int)(e / p2), j2 = (int)((e / p) % p), j3 = (int)(e % p);
+            double re = 0, im = 0;
+            for (int m2 = 0; m2 < n; ++m2) {
+                const double er = E[2 * (m2 * p + j2)], ei = -E[2 * (m2 * p + j2) + 1];
+                const double cr = S[R.C1r + (m1 * n + m2) * p + j3], ci = S[R.C1i + (m1 * n + m2) * p + j3];
+                re += er * cr - ei * ci;
+                im += er * ci + ei * cr;
+            }
+            S[R.C2r + e] = re;
+            S[R.C2i + e] = im;
+        }
+        break;
+    case 7:  // values: Re sum_m1 conj(E[m1][j1]) C2[m1][(j2 j3)]
+        if (e < p3) {
+            const int j1 = (int)(e / p2), r = (int)(e % p2);
+            double v = 0.0;
+            for (int m1 = 0; m1 < n; ++m1) {
+                const double er = E[2 * (m1 * p + j1)], ei = E[2 * (m1 * p + j1) + 1];
+                v += er * S[R.C2r + m1 * p2 + r] + ei * S[R.C2i + m1 * p2 + r];
+            }
+            D.w0vals[e] = (T)v;
+        }
+        break;
     }
 }
 
-int64_t root_scratch_elems(const Tables &t)
+int64_t root_scratch_elems(const Tables &t, int npts)
 {
-    const int64_t p = t.p, p2 = p * p, n = t.nwn, nh = t.nwh;
-    return 2 * (p2 * nh + p * nh * n + n * nh * n + n * n * p + n * p2);
+    return RootLayout(t.p, t.nwn, t.nwh, npts).total;
 }
 
 // -------------------------------------------------------------- small ones
@@ -810,7 +867,6 @@ struct Cfg {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
     static constexpr int G = sizeof(T) == 8 ? 4 : 7;    // m3 group of k_proxy2pw
     static constexpr int G1 = 5;                        // m1 group of k_local_pw
-    static constexpr int CH = sizeof(T) == 8 ? 16 : 32; // target chunk of k_leaf
     static size_t lds_up() { return sizeof(T) * (2 * P2 + 2 * P + 2 * P3); }
     static size_t lds_p2pw() { return sizeof(T) * (P3 + 2 * NN * P + P * 2 * G + P2 * 2 * G + 2 * P * G * NN); }
     static size_t lds_local()
@@ -820,8 +876,7 @@ struct Cfg {
         size_t pw = 2 * G1 * NH * NN + 2 * G1 * NN * P + 2 * G1 * P2;
         return sizeof(T) * (fixed + std::max(p2c, pw));
     }
-    static size_t lds_leaf() { return sizeof(T) * (P3 + 3 * CH * P + P2 * CH + CH * P + 2 * P); }
-    static size_t lds_root() { return sizeof(double) * (P3 + 2 * P + 3 * 16 * P); }
+    static size_t lds_leaf() { return sizeof(T) * (P3 + 2 * P); }
 };
 
 template <typename T>
@@ -910,8 +965,7 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
         allow_lds(k_upward<T, P>, C::lds_up());
         allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
         allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
-        allow_lds(k_leaf<T, P, C::CH>, C::lds_leaf());
-        allow_lds(k_root_w0<T>, C::lds_root());
+        allow_lds(k_leaf<T, P>, C::lds_leaf());
         attrs = true;
     }
     Dev<T> D = make_dev<T>(Pl);
@@ -930,8 +984,13 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     }
     {
         StageScope t(Pl, s, DMK_STAGE_ROOT);
-        int root_fout = (ll.fout_off[1] > 0) ? 1 : 0;
-        hipLaunchKernelGGL((k_root_w0<T>), dim3(1), dim3(TPB), C::lds_root(), s, D, root_fout);
+        const int root_fout = (ll.fout_off[1] > 0) ? 1 : 0;
+        const int npts = root_fout ? 0 : (int)n;
+        const int64_t p = P, nw = Pl->tab.nwn, nwh = Pl->tab.nwh;
+        const int64_t outs[8] = {3 * (int64_t)npts, p * p * p, p * p * nwh, p * nwh * nw, nw * nwh * nw,
+                                 nw * nw * p, nw * p * p, p * p * p};
+        for (int st = root_fout ? 1 : 0; st < 8; ++st)
+            hipLaunchKernelGGL((k_root_stage<T>), dim3(nblk(outs[st])), dim3(TPB), 0, s, D, st, root_fout, npts);
     }
     // Step 3: downward pass
     for (int l = 0; l < L; ++l) {
@@ -957,10 +1016,12 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     if (Pl->nleaf) {
         {
             StageScope t(Pl, s, DMK_STAGE_LEAF);
-            hipLaunchKernelGGL((k_leaf<T, P, C::CH>), dim3((unsigned)Pl->nleaf), dim3(TPB), C::lds_leaf(), s, D, Pl->l_leaf);
+            hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D, Pl->l_anc,
+                               Pl->anc_tbeg, Pl->anc_tgt);
         }
         StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
-        hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src);
+        hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf, Pl->nl_off,
+                           Pl->nl_src, Pl->nl_pre);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -1036,7 +1097,7 @@ void alloc_workspace(Plan *P)
     P->qs = (double *)al(P->n, 8);
     P->ufar = (double *)al(P->n, 8);
     P->ures = (double *)al(P->n, 8);
-    P->rootscratch = (double *)al(root_scratch_elems(t), 8);
+    P->rootscratch = (double *)al(root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
     P->proxy = al(P->nfout * p3, el);
     P->local = al(P->nanc * p3, el);
     P->phi = al(2 * P->max_fout_level * nm, el);

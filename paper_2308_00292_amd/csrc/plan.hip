@@ -517,6 +517,35 @@ __global__ void k_list_flags(int64_t nbox, const uint8_t *bflags, const int32_t 
     f_leaf[b] = (ne && (f & 1)) ? 1 : 0;
 }
 
+// targets grouped by anchor: per leaf, its anchor's slot, and per anchor the
+// number of targets
+__global__ void k_leaf_keys(const int32_t *leaves, int64_t nleaf, const int32_t *anchor, const int32_t *local_slot,
+                            const int32_t *pcount, int32_t *key, int32_t *ident, int32_t *anc_cnt)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= nleaf) return;
+    int32_t L = leaves[i];
+    int32_t a = local_slot[anchor[L]];
+    key[i] = a;
+    ident[i] = L;
+    atomicAdd(&anc_cnt[a], pcount[L]);
+}
+
+__global__ void k_leaf_counts(const int32_t *sorted_leaves, int64_t nleaf, const int32_t *pcount, int32_t *cnt)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i < nleaf) cnt[i] = pcount[sorted_leaves[i]];
+}
+
+__global__ void k_fill_targets(const int32_t *sorted_leaves, int64_t nleaf, const int32_t *pstart,
+                               const int32_t *pcount, const int32_t *pos, int32_t *tgt)
+{
+    int64_t i = blockIdx.x;
+    if (i >= nleaf) return;
+    int32_t L = sorted_leaves[i];
+    for (int k = threadIdx.x; k < pcount[L]; k += TPB) tgt[pos[i] + k] = pstart[L] + k;
+}
+
 __global__ void k_slots(const int32_t *list, int64_t m, int32_t *slot)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -540,7 +569,7 @@ template <bool FILL>
 __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t *lstart_dev, int nlevels,
                              const uint64_t *bkey, const int32_t *blevel, const int32_t *parent,
                              const int32_t *col, const uint8_t *bflags, const int32_t *pcount,
-                             int32_t *count, const int32_t *off, int32_t *src, int64_t *pairs)
+                             int32_t *count, const int32_t *off, int32_t *src, int32_t *pre, int64_t *pairs)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= nleaf) return;
@@ -548,11 +577,12 @@ __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t
     int cnt = 0;
     int64_t pr = 0;
     int32_t base = FILL ? off[i] : 0;
+    // pre: running count of source points before each entry (FILL pass)
     for (int32_t A = B; A >= 0; A = parent[A])
         for (int k = 0; k < 27; ++k) {
             int32_t T = col[(int64_t)A * 27 + k];
             if (T >= 0 && (bflags[T] & 8) && pcount[T] > 0) {
-                if (FILL) src[base + cnt] = T;
+                if (FILL) { src[base + cnt] = T; pre[base + i + cnt] = (int32_t)pr; }
                 cnt++;
                 pr += pcount[T];
             }
@@ -578,12 +608,13 @@ __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t
             if (f < 0) continue;
             int32_t T = (int32_t)(lstart_dev[l + 1] + f);
             if ((bflags[T] & 1) && (bflags[T] & 8) && pcount[T] > 0) {
-                if (FILL) src[base + cnt] = T;
+                if (FILL) { src[base + cnt] = T; pre[base + i + cnt] = (int32_t)pr; }
                 cnt++;
                 pr += pcount[T];
             }
         }
     }
+    if (FILL) pre[base + i + cnt] = (int32_t)pr;  // total after the last entry (one extra slot per leaf)
     if (!FILL) {
         count[i] = cnt;
         pairs[i] = pr * pcount[B];
@@ -673,6 +704,38 @@ void build_lists(Plan *P, hipStream_t s)
         if (m) hipLaunchKernelGGL(k_slots, dim3(nblk(m)), dim3(TPB), 0, s, P->l_fin + ll.fin_off[l], m, P->psi_slot);
     }
 
+    // targets grouped by the anchor of their leaf (leaf evaluation)
+    {
+        const int64_t nleaf = ll.leaf_off[L], nanc = ll.anc_off[L];
+        P->anc_tbeg = talloc<int32_t>(P, nanc + 1);
+        P->anc_tgt = talloc<int32_t>(P, std::max<int64_t>(P->n, 1));
+        int32_t *cnt = S.get<int32_t>(nanc + 1);
+        DMK_HIP(hipMemsetAsync(cnt, 0, (nanc + 1) * sizeof(int32_t), s));
+        if (nleaf > 0) {
+            int32_t *key = S.get<int32_t>(nleaf), *ident = S.get<int32_t>(nleaf);
+            int32_t *skey = S.get<int32_t>(nleaf), *sleaf = S.get<int32_t>(nleaf);
+            hipLaunchKernelGGL(k_leaf_keys, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, P->anchor,
+                               P->local_slot, P->pcount, key, ident, cnt);
+            size_t tb = 0;
+            DMK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, skey, ident, sleaf, (int)nleaf, 0, 32, s));
+            void *tmp = S.get<char>((int64_t)tb);
+            DMK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, skey, ident, sleaf, (int)nleaf, 0, 32, s));
+            int32_t *lc = S.get<int32_t>(nleaf + 1), *pos = S.get<int32_t>(nleaf + 1);
+            hipLaunchKernelGGL(k_leaf_counts, dim3(nblk(nleaf)), dim3(TPB), 0, s, sleaf, nleaf, P->pcount, lc);
+            DMK_HIP(hipMemsetAsync(lc + nleaf, 0, sizeof(int32_t), s));
+            tb = 0;
+            DMK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, lc, pos, (int)nleaf + 1, s));
+            tmp = S.get<char>((int64_t)tb);
+            DMK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, lc, pos, (int)nleaf + 1, s));
+            hipLaunchKernelGGL(k_fill_targets, dim3((unsigned)nleaf), dim3(TPB), 0, s, sleaf, nleaf, P->pstart,
+                               P->pcount, pos, P->anc_tgt);
+        }
+        size_t tb = 0;
+        DMK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, P->anc_tbeg, (int)nanc + 1, s));
+        void *tmp = S.get<char>((int64_t)tb);
+        DMK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, P->anc_tbeg, (int)nanc + 1, s));
+    }
+
     // near lists over the leaf order
     const int64_t nleaf = P->nleaf;
     int32_t *lsd = S.get<int32_t>(L + 2);
@@ -688,7 +751,7 @@ void build_lists(Plan *P, hipStream_t s)
         int64_t *pairs = S.get<int64_t>(nleaf);
         hipLaunchKernelGGL(k_near_lists<false>, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
                            P->blevel, P->parent, P->colleague, P->bflags, P->pcount, cnt, (const int32_t *)nullptr,
-                           (int32_t *)nullptr, pairs);
+                           (int32_t *)nullptr, (int32_t *)nullptr, pairs);
         size_t tb = 0;
         DMK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, P->nl_off, (int)nleaf + 1, s));
         // exclusive sum over nleaf+1 entries needs a trailing zero in the input
@@ -699,6 +762,18 @@ void build_lists(Plan *P, hipStream_t s)
         DMK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt1, P->nl_off, (int)nleaf + 1, s));
         int32_t total = 0;
         DMK_HIP(hipMemcpyAsync(&total, P->nl_off + nleaf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        {
+            int32_t *mx = S.get<int32_t>(1);
+            size_t tbm = 0;
+            DMK_HIP(hipcub::DeviceReduce::Max(nullptr, tbm, cnt, mx, (int)nleaf, s));
+            void *tmpm = S.get<char>((int64_t)tbm);
+            DMK_HIP(hipcub::DeviceReduce::Max(tmpm, tbm, cnt, mx, (int)nleaf, s));
+            int32_t hmx = 0;
+            DMK_HIP(hipMemcpyAsync(&hmx, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DMK_HIP(hipStreamSynchronize(s));
+            if (hmx > 1024)
+                throw Error{DMK_ERR_UNSUPPORTED, "a leaf's residual list exceeds 1024 source boxes"};
+        }
         int64_t *psum = S.get<int64_t>(1);
         tb = 0;
         DMK_HIP(hipcub::DeviceReduce::Sum(nullptr, tb, pairs, psum, (int)nleaf, s));
@@ -708,11 +783,13 @@ void build_lists(Plan *P, hipStream_t s)
         DMK_HIP(hipStreamSynchronize(s));
         P->nl_total = total;
         P->nl_src = talloc<int32_t>(P, total);
+        P->nl_pre = talloc<int32_t>(P, total + nleaf);
         hipLaunchKernelGGL(k_near_lists<true>, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
                            P->blevel, P->parent, P->colleague, P->bflags, P->pcount, (int32_t *)nullptr,
-                           (const int32_t *)P->nl_off, P->nl_src, (int64_t *)nullptr);
+                           (const int32_t *)P->nl_off, P->nl_src, P->nl_pre, (int64_t *)nullptr);
     } else {
         P->nl_src = talloc<int32_t>(P, 1);
+        P->nl_pre = talloc<int32_t>(P, 1);
         DMK_HIP(hipMemsetAsync(P->nl_off, 0, sizeof(int32_t), s));
     }
     DMK_HIP(hipGetLastError());

@@ -26,9 +26,9 @@ PEAK = {"hbm": (8000.0, "GB/s"), "alu64": (78.6, "TFLOP/s"), "alu32": (157.3, "T
 # bound of each stage: memory streams vs arithmetic on the vector ALUs
 STAGE_BOUND = {"gather": "hbm", "finalize": "hbm", "pwshift": "hbm", "upward": "alu", "root": "alu",
                "proxy2pw": "alu", "local": "alu", "pw2grid": "alu", "leaf": "alu", "residual": "alu"}
-STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward", "root": "k_root_w0",
-                "proxy2pw": "k_proxy2pw", "local": "k_local_init", "pwshift": "k_pwshift",
-                "pw2grid": "k_pw2grid", "leaf": "k_leaf_eval", "residual": "k_residual",
+STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward", "root": "k_root_stage",
+                "proxy2pw": "k_proxy2pw", "local": "k_local_pw", "pwshift": "k_pwshift",
+                "pw2grid": "k_local_pw", "leaf": "k_leaf", "residual": "k_residual",
                 "finalize": "k_finalize"}
 WORKLOADS = {
     "cfg3_clustered_10m": "3-D Laplace, N=1e7 clustered (70% on the unit sphere, 30% in 3 Gaussian "
@@ -66,7 +66,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg3_clustered_10m", choices=list(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--no-batched", action="store_true",
+                    help="launch every stage eagerly instead of replaying the captured graph")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain FP64 (eager) comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-targets", type=int, default=200)
     args = ap.parse_args()
@@ -82,6 +86,7 @@ def main():
 
     tol = 1e-6
     prec = dmk.DMK_FP64 if args.precision == "fp64" else dmk.DMK_MIXED
+    batched = not args.no_batched
     log(f"[bench] generating {args.workload}")
     pts, q, ns = dmk_inputs.make(args.workload)
     n = len(q)
@@ -89,42 +94,48 @@ def main():
     tp_ = torch.from_numpy(pts).to(dev)
     tq = torch.from_numpy(q).to(dev)
     torch.cuda.synchronize()
-    log("[bench] plan")
+
+    def timed(plan, steps, warmup):
+        out = torch.empty(n, dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            plan.eval(tq, out)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(steps):
+            plan.eval(tq, out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps, out
+
+    log(f"[bench] plan ({args.precision}{', batched' if batched else ''})")
     t0 = time.perf_counter()
-    plan = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=prec)
+    plan = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=prec,
+                    flags=dmk.DMK_FLAG_BATCHED if batched else 0)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
     log(f"[bench] plan {t_plan:.2f} s: levels {info['nlevels']} boxes {info['nbox']} leaves {info['nleaf']}")
-    out = torch.empty(n, dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        plan.eval(tq, out)
-    torch.cuda.synchronize()
     log("[bench] timed region")
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    ms_step, out = timed(plan, args.steps, args.warmup)
+    value = n / (ms_step * 1e-3)
+    log(f"[bench] {ms_step:.3f} ms/step -> {value:.4g} points/s")
+
+    # per-stage breakdown: HIP events around every launch (eager launches)
     plan.stage_timing(True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    nst = max(2, min(args.steps, 5))
+    for _ in range(nst):
         plan.eval(tq, out)
-    ev1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_ms = ev0.elapsed_time(ev1)
     stage_ms, launches = plan.stage_times()
     plan.stage_timing(False)
-    ms_step = gpu_ms / args.steps
-    value = n / (ms_step * 1e-3)
-    log(f"[bench] {ms_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} wall) -> {value:.4g} points/s")
-
-    # roofline of the dominant stage (live HIP events of the timed region)
     flops, byts = plan.stage_work()
     dom = max(stage_ms, key=lambda k: stage_ms[k])
     avg_ms = stage_ms[dom] / max(1, launches[dom])
-    per_launch = (byts[dom] if STAGE_BOUND[dom] == "hbm" else flops[dom]) * args.steps / max(1, launches[dom])
+    per_launch = (byts[dom] if STAGE_BOUND[dom] == "hbm" else flops[dom]) * nst / max(1, launches[dom])
     if STAGE_BOUND[dom] == "hbm":
         achieved = per_launch / (avg_ms * 1e-3) / 1e9
         peak, unit = PEAK["hbm"]
@@ -133,25 +144,41 @@ def main():
         peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
     roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": None, "kernel": STAGE_KERNEL[dom], "stage": dom,
-            "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / args.steps}
+            "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / nst}
     stages = {}
     for k in stage_ms:
-        ms = stage_ms[k] / args.steps
+        ms = stage_ms[k] / nst
         ent = {"ms": round(ms, 4)}
         if ms > 0 and flops[k] > 0:
             ent["tflops"] = round(flops[k] / (ms * 1e-3) / 1e12, 3)
         if ms > 0 and byts[k] > 0:
             ent["gbps"] = round(byts[k] / (ms * 1e-3) / 1e9, 1)
         stages[k] = ent
+    u_main = out.cpu().numpy()
+    plan.close()
+    del plan
+
+    plain = None
+    if not args.no_compare:
+        log("[bench] plain FP64 comparison (eager launches)")
+        p64 = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=dmk.DMK_FP64)
+        ms64, out64 = timed(p64, args.steps, args.warmup)
+        u64 = out64.cpu().numpy()
+        p64.close()
+        del p64
+        plain = {"points_per_s": n / (ms64 * 1e-3), "ms_per_step": ms64}
+        log(f"[bench] plain FP64 {ms64:.3f} ms/step -> {plain['points_per_s']:.4g} points/s")
 
     # sampled parity against direct summation by the oracle
     import oracle
     rng = np.random.default_rng(11)
     sidx = rng.choice(n, min(n, args.sample_targets), replace=False)
     ud = oracle.direct(pts, q, sidx)
-    got = out.cpu().numpy()[sidx]
-    err = float(np.linalg.norm(got - ud) / np.linalg.norm(ud))
+    err = float(np.linalg.norm(u_main[sidx] - ud) / np.linalg.norm(ud))
     log(f"[bench] sampled rel l2 vs direct sum ({len(sidx)} targets): {err:.3e}")
+    if plain is not None:
+        plain["sampled_rel_l2_vs_direct"] = float(np.linalg.norm(u64[sidx] - ud) / np.linalg.norm(ud))
+        plain["rel_l2_vs_main"] = float(np.linalg.norm(u_main - u64) / np.linalg.norm(u64))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -165,16 +192,17 @@ def main():
         "vs_baseline": None, "dtype": "f64" if prec == dmk.DMK_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n_points": n,
-                   "tol": tol, "leaf_max": ns, "precision": args.precision, "batched": False,
+                   "tol": tol, "leaf_max": ns, "precision": args.precision, "batched": batched,
                    "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"],
                    "p": info["p"], "nf": info["nf"], "t_plan_s": round(t_plan, 3),
                    "end_to_end_points_per_s": n / (t_plan + ms_step * 1e-3),
-                   "sampled_rel_l2_vs_direct": err, "stage_ms_per_step": stages},
+                   "sampled_rel_l2_vs_direct": err, "stage_ms_per_step": stages,
+                   "plain_fp64": plain,
+                   "speedup_vs_plain_fp64": (value / plain["points_per_s"]) if plain else None},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -60,12 +60,16 @@ typedef struct {
     int32_t  max_depth;   /* depth cap of the tree (default 20, at most 21)   */
     int32_t  precision;   /* dmk_precision (default DMK_FP64)                 */
     int32_t  reserved0;
-    uint64_t flags;       /* DMK_FLAG_* bits                                  */
+    uint64_t flags;       /* DMK_FLAG_* bits (DMK_FLAG_BATCHED)               */
 } dmk_opts;
 
-/* Keep the per-box local values of leaves too, so dmk_copy_box_data can
- * return them after an eval (parity checks; costs memory). */
-#define DMK_FLAG_KEEP_LOCALS 1ull
+/* Batched execution of dmk_eval: the middle of the pipeline (upward pass,
+ * root window, plane-wave stages over all levels, local values, leaf
+ * evaluation) is captured once into a HIP graph and replayed, and the
+ * residual sums run on a second stream concurrently with it.  Without the
+ * flag every stage is launched eagerly, one after the other, on the caller's
+ * stream.  Results are identical either way. */
+#define DMK_FLAG_BATCHED 2ull
 
 typedef struct dmk_plan_s *dmk_plan_t;
 
@@ -185,10 +189,12 @@ dmk_status dmk_export_near_lists(dmk_plan_t plan, int64_t *leaf_box, int64_t *of
  * box `box` to the HOST array `out` (p^3 FP64 values, index (i*p + j)*p + k
  * for Chebyshev node indices i, j, k along x, y, z).
  *   what = 0: proxy charges (boxes with F_out only);
- *   what = 1: local values of the far potential on the box's Chebyshev grid
- *             (non-leaf boxes with points; leaves too with
- *             DMK_FLAG_KEEP_LOCALS).
- * Values are in normalised units (root box [-1/2,1/2]^3, kernel 1/r).
+ *   what = 1: local values of the far potential on the box's Chebyshev grid,
+ *             held by the root and by every box with points and F_in (any
+ *             other box's far potential is the polynomial of its nearest
+ *             such ancestor, by the exactness of Lemma 2.2).
+ * Values are in normalised units (root box [-1/2,1/2]^3, kernel 1/r); the
+ * mixed path's FP32 values are widened to FP64.
  * Returns DMK_ERR_ARG if the box holds no such data.  Synchronous.
  */
 dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out);

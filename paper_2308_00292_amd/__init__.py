@@ -16,7 +16,7 @@ LIBPATH = os.path.join(_HERE, "libdmk.so")
 
 DMK_FP64, DMK_MIXED = 0, 1
 DMK_LAPLACE = 0
-DMK_FLAG_KEEP_LOCALS = 1
+DMK_FLAG_BATCHED = 2
 
 # exported symbols, in the order of include/dmk.h
 SYMBOLS = ["dmk_plan", "dmk_eval", "dmk_eval_parts", "dmk_plan_info", "dmk_export_tree",

@@ -117,9 +117,15 @@ dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const dou
             build_lists(P, s);
             alloc_workspace(P);
             count_work(P, s);
+            if (P->flags & DMK_FLAG_BATCHED) {
+                // default-priority streams only
+                DMK_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+                DMK_HIP(hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking));
+                DMK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+                DMK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+            }
         } catch (...) {
-            plan_free_all(P);
-            delete P;
+            plan_release(P);
             throw;
         }
         *out = reinterpret_cast<dmk_plan_t>(P);
@@ -374,13 +380,27 @@ void dmk_plan_destroy(dmk_plan_t plan)
     Plan *P = reinterpret_cast<Plan *>(plan);
     if (P->last_stream) (void)hipStreamSynchronize(P->last_stream);
     (void)hipDeviceSynchronize();
+    plan_release(P);
+}
+
+}  // extern "C"
+
+namespace dmk {
+// frees everything a plan holds (device memory, events, streams, graph)
+void plan_release(Plan *P)
+{
     for (auto &r : P->pending) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+    if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+    if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
     plan_free_all(P);
     delete P;
 }
 
-}  // extern "C"
+}  // namespace dmk

@@ -134,6 +134,11 @@ struct Plan {
     int64_t n_shift_pairs = 0; // (F_in box, F_out colleague) pairs
     int64_t npairs_in = 0;     // residual pairs closer than the source box side
 
+    // batched execution: graph of the eval core, capture and side streams
+    hipStream_t cap_stream = nullptr, side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
     std::vector<void *> allocations;
     int64_t device_bytes = 0;
     std::atomic<int> busy{0};
@@ -142,6 +147,7 @@ struct Plan {
 
 void *dalloc(Plan *P, size_t bytes);  // tracked device allocation
 void plan_free_all(Plan *P);
+void plan_release(Plan *P);  // device memory, events, streams, graph, then the Plan itself
 
 void build_tree(Plan *P, const double *pts, hipStream_t s);
 void build_lists(Plan *P, hipStream_t s);

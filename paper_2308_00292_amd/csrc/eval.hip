@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
 // Phi[m1][m3][m2] = sum_j E[m1][j1] E[m2][j2] E[m3][j3] rho[j1][j2][j3],
 // E[m][j] = exp(-i pi m x_j / 3); m3 >= 0 only (rho is real).
 template <typename T, int P, int NF, int G>
-__global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list, int64_t slot0)
+__global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list)
 {
     constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
     extern __shared__ unsigned char smraw[];
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list,
         Ei[t] = D.epw[2 * t + 1];
     }
     const int64_t nm = D.pwstride;
-    T *outr = D.phi + 2 * (int64_t)(D.proxy_slot[B] - slot0) * nm;
+    T *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
     T *outi = outr + nm;
     for (int g0 = 0; g0 < NH; g0 += G) {
         const int g = min(G, NH - g0);
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list,
 
 // ------------------------------------------------ diagonal translation
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *list, int64_t fout_slot0, T wscale)
+__global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *list)
 {
     __shared__ int32_t src_slot[27];
     __shared__ int8_t dl[27][3];
@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *list, 
         for (int k = 0; k < 27; ++k) {
             int32_t S = D.col[(int64_t)B * 27 + k];
             if (S >= 0 && (D.bflags[S] & 2)) {
-                src_slot[c] = (int32_t)(D.proxy_slot[S] - fout_slot0);
+                src_slot[c] = D.proxy_slot[S];
                 dl[c][0] = (int8_t)(k / 9 - 1);  // c_S - c_B = delta s_l
                 dl[c][1] = (int8_t)((k / 3) % 3 - 1);
                 dl[c][2] = (int8_t)(k % 3 - 1);
@@ -395,6 +395,7 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *list, 
     __syncthreads();
     const int nn = D.nn, nh = D.nh, nf = D.nf;
     const int64_t nm = D.pwstride;
+    const T wscale = (T)ldexp(1.0, D.blevel[B]);  // w_l = 2^l w_0 (scale invariance of 1/r)
     T *outr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *outi = outr + nm;
     // exp(i h m.(c_B - c_S)) = exp(-2 pi i (m.delta)/3) = w^{-(m.delta mod 3)}
     const T c3 = T(-0.5), s3 = T(0.86602540378443864676);
@@ -954,26 +955,24 @@ struct StageScope {
     }
 };
 
+// The stages between the charge gather and the final scatter.  They read and
+// write plan-owned buffers only, so the sequence can be captured into a HIP
+// graph once and replayed.  `side` (if not null) is a second stream on which
+// the residual sums run concurrently with the far-field chain.
 template <typename T, int P, int NF>
-static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far_part, double *near_part,
-                       hipStream_t s)
+static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
 {
     using C = Cfg<T, P, NF>;
-    const int64_t n = Pl->n;
-    static bool attrs = false;
-    if (!attrs) {
-        allow_lds(k_upward<T, P>, C::lds_up());
-        allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
-        allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
-        allow_lds(k_leaf<T, P>, C::lds_leaf());
-        attrs = true;
-    }
     Dev<T> D = make_dev<T>(Pl);
     const auto &ll = Pl->ll;
     const int L = Pl->nlevels;
-    {
-        StageScope t(Pl, s, DMK_STAGE_GATHER);
-        hipLaunchKernelGGL(k_gather_q, dim3(nblk(n)), dim3(TPB), 0, s, charges, Pl->perm, n, Pl->qs);
+    const int64_t n = Pl->n;
+    if (side && Pl->nleaf) {
+        DMK_HIP(hipEventRecord(Pl->ev_fork, s));
+        DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
+        hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, side, D, Pl->l_leaf, Pl->nl_off,
+                           Pl->nl_src, Pl->nl_pre);
+        DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
     // Step 2: upward pass, finest level first
     for (int l = L - 1; l >= 0; --l) {
@@ -992,26 +991,24 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
         for (int st = root_fout ? 1 : 0; st < 8; ++st)
             hipLaunchKernelGGL((k_root_stage<T>), dim3(nblk(outs[st])), dim3(TPB), 0, s, D, st, root_fout, npts);
     }
-    // Step 3: downward pass
+    // Step 3: outgoing plane waves of every F_out box and incoming plane
+    // waves of every non-empty F_in box, all levels in one launch each
+    if (Pl->nfout) {
+        StageScope t(Pl, s, DMK_STAGE_PROXY2PW);
+        hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
+                           Pl->l_fout);
+    }
+    if (Pl->nfin) {
+        StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
+        hipLaunchKernelGGL((k_pwshift<T>), dim3((unsigned)Pl->nfin), dim3(TPB), 0, s, D, Pl->l_fin);
+    }
+    // local values of the anchors, coarse to fine
     for (int l = 0; l < L; ++l) {
-        int64_t nfo = ll.fout_off[l + 1] - ll.fout_off[l];
-        int64_t nfi = ll.fin_off[l + 1] - ll.fin_off[l];
         int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];
-        if (nfo) {
-            StageScope t(Pl, s, DMK_STAGE_PROXY2PW);
-            hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)nfo), dim3(TPB), C::lds_p2pw(), s, D,
-                               Pl->l_fout + ll.fout_off[l], ll.fout_off[l]);
-        }
-        if (nfi) {
-            StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
-            hipLaunchKernelGGL((k_pwshift<T>), dim3((unsigned)nfi), dim3(TPB), 0, s, D, Pl->l_fin + ll.fin_off[l],
-                               ll.fout_off[l], (T)std::ldexp(1.0, l));
-        }
-        if (nan) {
-            StageScope t(Pl, s, DMK_STAGE_PW2GRID);
-            hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,
-                               Pl->l_anc + ll.anc_off[l], l);
-        }
+        if (!nan) continue;
+        StageScope t(Pl, s, DMK_STAGE_PW2GRID);
+        hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,
+                           Pl->l_anc + ll.anc_off[l], l);
     }
     if (Pl->nleaf) {
         {
@@ -1019,9 +1016,54 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
             hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D, Pl->l_anc,
                                Pl->anc_tbeg, Pl->anc_tgt);
         }
-        StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
-        hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf, Pl->nl_off,
-                           Pl->nl_src, Pl->nl_pre);
+        if (side) {
+            DMK_HIP(hipStreamWaitEvent(s, Pl->ev_join, 0));
+        } else {
+            StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
+            hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf, Pl->nl_off,
+                               Pl->nl_src, Pl->nl_pre);
+        }
+    }
+}
+
+template <typename T, int P, int NF>
+static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far_part, double *near_part,
+                       hipStream_t s)
+{
+    using C = Cfg<T, P, NF>;
+    const int64_t n = Pl->n;
+    static bool attrs = false;
+    if (!attrs) {
+        allow_lds(k_upward<T, P>, C::lds_up());
+        allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
+        allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
+        allow_lds(k_leaf<T, P>, C::lds_leaf());
+        attrs = true;
+    }
+    {
+        StageScope t(Pl, s, DMK_STAGE_GATHER);
+        hipLaunchKernelGGL(k_gather_q, dim3(nblk(n)), dim3(TPB), 0, s, charges, Pl->perm, n, Pl->qs);
+    }
+    const bool batched = (Pl->flags & DMK_FLAG_BATCHED) && !Pl->timing;
+    if (batched) {
+        if (!Pl->graph_exec) {
+            // capture once: the core touches plan-owned buffers only
+            hipGraph_t g = nullptr;
+            DMK_HIP(hipStreamBeginCapture(Pl->cap_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue_core<T, P, NF>(Pl, Pl->cap_stream, Pl->side_stream);
+            } catch (...) {
+                (void)hipStreamEndCapture(Pl->cap_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            DMK_HIP(hipStreamEndCapture(Pl->cap_stream, &g));
+            DMK_HIP(hipGraphInstantiate(&Pl->graph_exec, g, nullptr, nullptr, 0));
+            DMK_HIP(hipGraphDestroy(g));
+        }
+        DMK_HIP(hipGraphLaunch(Pl->graph_exec, s));
+    } else {
+        enqueue_core<T, P, NF>(Pl, s, nullptr);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -1100,8 +1142,8 @@ void alloc_workspace(Plan *P)
     P->rootscratch = (double *)al(root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
     P->proxy = al(P->nfout * p3, el);
     P->local = al(P->nanc * p3, el);
-    P->phi = al(2 * P->max_fout_level * nm, el);
-    P->psi = al(2 * P->max_fin_level * nm, el);
+    P->phi = al(2 * P->nfout * nm, el);
+    P->psi = al(2 * P->nfin * nm, el);
     P->w0vals = al(p3, el);
 }
 

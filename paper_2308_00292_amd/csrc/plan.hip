@@ -698,11 +698,8 @@ void build_lists(Plan *P, hipStream_t s)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfout)), dim3(TPB), 0, s, P->l_fout, P->nfout, P->proxy_slot);
     if (P->nanc)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nanc)), dim3(TPB), 0, s, P->l_anc, P->nanc, P->local_slot);
-    // psi slots restart at 0 on every level (the buffer is reused per level)
-    for (int l = 0; l < L; ++l) {
-        int64_t m = ll.fin_off[l + 1] - ll.fin_off[l];
-        if (m) hipLaunchKernelGGL(k_slots, dim3(nblk(m)), dim3(TPB), 0, s, P->l_fin + ll.fin_off[l], m, P->psi_slot);
-    }
+    if (P->nfin)
+        hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfin)), dim3(TPB), 0, s, P->l_fin, P->nfin, P->psi_slot);
 
     // targets grouped by the anchor of their leaf (leaf evaluation)
     {

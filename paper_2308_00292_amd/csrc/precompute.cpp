@@ -328,7 +328,7 @@ void build_tables(const Params &prm, Tables *t)
         t->gcheb.assign(cf.begin(), cf.begin() + deg + 1);
         // FP32 evaluation needs only the terms above single-precision rounding
         int deg32 = deg;
-        while (deg32 > 0 && std::fabs(cf[deg32]) < 2e-9 * std::fabs(cf[0])) deg32--;
+        while (deg32 > 0 && std::fabs(cf[deg32]) < 1e-7 * std::fabs(cf[0])) deg32--;
         t->gdeg32 = deg32;
     }
 }

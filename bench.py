@@ -1,12 +1,18 @@
 """Benchmark of the DMK point code on one MI355X.
 
-One step = one dmk_eval (every stage of the eval pipeline: upward pass, root
-window, plane-wave stages on every level, leaf evaluation, residual sums,
-scatter) on a plan built once outside the timed region, with points and
-charges resident in HBM.  Prints one JSON line.
+One step = one dmk_eval over the whole hot path (charge gather, upward pass,
+root window, plane-wave stages of every level, leaf evaluation, residual
+sums, scatter) on a plan built once outside the timed region, with points
+and charges resident in HBM.  The timed run is the mixed-precision path in
+batched mode (the eval core replayed from a HIP graph, residual sums on a
+concurrent stream); the plain FP64 path (eager launches) is timed beside it
+on the same points.  A separate eager pass with HIP events around every
+launch gives the per-stage times and the roofline of the dominant kernel.
+Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                  [--precision fp64|mixed] [--no-cpu-baseline]
+                  [--precision fp64|mixed] [--no-batched] [--no-compare]
+                  [--no-cpu-baseline] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -73,6 +79,8 @@ def main():
                     help="skip the plain FP64 (eager) comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-targets", type=int, default=200)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run an elementwise copy of 1 GiB first (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -94,6 +102,15 @@ def main():
     tp_ = torch.from_numpy(pts).to(dev)
     tq = torch.from_numpy(q).to(dev)
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        # x * 1 through torch's elementwise kernel: reads and writes exactly 2^30 bytes
+        src = torch.ones(2**28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] copy calibration: 3 x (read 1 GiB, write 1 GiB)")
 
     def timed(plan, steps, warmup):
         out = torch.empty(n, dtype=torch.float64, device=dev)

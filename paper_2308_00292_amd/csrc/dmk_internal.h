@@ -100,6 +100,14 @@ struct Plan {
     int32_t *anc_tgt = nullptr;    // [nleaf points] targets grouped by the anchor of their leaf
     int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
     int64_t nfout = 0, nfin = 0, nanc = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
+    // sibling groups for the diagonal translation: per parent of F_in boxes,
+    // the Psi slots of its 8 children and the Phi slots of the 64 boxes of
+    // the 4x4x4 block around them (-1 where absent); the root forms a group
+    // of its own when it has F_in
+    int32_t *oct_dst = nullptr;    // [noct][8]
+    int32_t *oct_src = nullptr;    // [noct][64]
+    int32_t *oct_level = nullptr;  // [noct] level of the children
+    int64_t noct = 0;
 
     // near (residual) lists in gather form over l_leaf order
     int32_t *nl_off = nullptr, *nl_src = nullptr;

@@ -371,50 +371,149 @@ __global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list)
 }
 
 // ------------------------------------------------ diagonal translation
+// Incoming plane waves of the children of one parent (a sibling group).  The
+// colleagues of the 8 children lie in the 4x4x4 block of boxes around them;
+// child t sits at cell t + (1,1,1).  With delta = (c_S - c_B)/s_l the
+// translation factor exp(i h m.(c_B - c_S)) = w^{-(m.delta)}, w = e^{2 pi i/3}
+// (h_l s_l = 2 pi/3), factors per axis, so the 27-term sum of each child runs
+// as three passes of 3-term sums (z, then y, then x) shared by the siblings:
+// 64 loads per mode for 8 boxes instead of up to 27 per box.  One thread per
+// mode; a block covers TPB consecutive modes of one group.  Blocks are dealt
+// out so that each XCD gets a contiguous range of groups (neighbouring groups
+// share most of their sources, which then stay in that XCD's L2).
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *list)
+struct Cx { T r, i; };
+
+template <typename T>
+__device__ inline Cx<T> cmul(Cx<T> a, Cx<T> f) { return {a.r * f.r - a.i * f.i, a.r * f.i + a.i * f.r}; }
+
+template <typename T>
+__device__ inline Cx<T> root3(int k)  // w^{-k}, any integer k
 {
-    __shared__ int32_t src_slot[27];
-    __shared__ int8_t dl[27][3];
-    __shared__ int nsrc;
-    const int32_t B = list[blockIdx.x];
-    if (threadIdx.x == 0) {
-        int c = 0;
-        for (int k = 0; k < 27; ++k) {
-            int32_t S = D.col[(int64_t)B * 27 + k];
-            if (S >= 0 && (D.bflags[S] & 2)) {
-                src_slot[c] = D.proxy_slot[S];
-                dl[c][0] = (int8_t)(k / 9 - 1);  // c_S - c_B = delta s_l
-                dl[c][1] = (int8_t)((k / 3) % 3 - 1);
-                dl[c][2] = (int8_t)(k % 3 - 1);
-                c++;
-            }
-        }
-        nsrc = c;
+    k %= 3;
+    if (k < 0) k += 3;
+    const T s3 = T(0.86602540378443864676);
+    if (k == 0) return {T(1), T(0)};
+    if (k == 1) return {T(-0.5), -s3};
+    return {T(-0.5), s3};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_dst, const int32_t *oct_src,
+                                                 const int32_t *oct_level, int64_t noct, int nchunk)
+{
+    __shared__ int32_t src[64];
+    __shared__ int32_t dst[8];
+    __shared__ int colany[16];
+    const int64_t G = gridDim.x;  // a multiple of 8
+    const int64_t Lb = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
+    const int64_t o = Lb / nchunk;
+    const int chunk = (int)(Lb % nchunk);
+    if (o >= noct) return;  // whole block: before any barrier
+    if (threadIdx.x < 64) src[threadIdx.x] = oct_src[o * 64 + threadIdx.x];
+    if (threadIdx.x < 8) dst[threadIdx.x] = oct_dst[o * 8 + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        const int c = threadIdx.x;
+        colany[c] = (src[4 * c] >= 0) | (src[4 * c + 1] >= 0) | (src[4 * c + 2] >= 0) | (src[4 * c + 3] >= 0);
     }
     __syncthreads();
-    const int nn = D.nn, nh = D.nh, nf = D.nf;
     const int64_t nm = D.pwstride;
-    const T wscale = (T)ldexp(1.0, D.blevel[B]);  // w_l = 2^l w_0 (scale invariance of 1/r)
-    T *outr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *outi = outr + nm;
-    // exp(i h m.(c_B - c_S)) = exp(-2 pi i (m.delta)/3) = w^{-(m.delta mod 3)}
-    const T c3 = T(-0.5), s3 = T(0.86602540378443864676);
-    for (int64_t e = threadIdx.x; e < nm; e += TPB) {
-        // e = (m1 * nh + m3) * nn + m2
-        const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
-        T re = T(0), im = T(0);
-        for (int k = 0; k < nsrc; ++k) {
-            const T *f = D.phi + 2 * (int64_t)src_slot[k] * nm + e;
-            T fr = f[0], fi = f[nm];
-            int t = (m1 * dl[k][0] + m2 * dl[k][1] + m3 * dl[k][2]) % 3;
-            if (t < 0) t += 3;
-            if (t == 0) { re += fr; im += fi; }
-            else if (t == 1) { re += c3 * fr + s3 * fi; im += c3 * fi - s3 * fr; }
-            else { re += c3 * fr - s3 * fi; im += c3 * fi + s3 * fr; }
+    const int64_t e = (int64_t)chunk * TPB + threadIdx.x;
+    if (e >= nm) return;
+    const int nn = D.nn, nh = D.nh, nf = D.nf;
+    // e = (m1 * nh + m3) * nn + m2
+    const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
+    // per-axis factors for delta = -1 and +1 (delta = 0 is 1)
+    const Cx<T> xm = root3<T>(-m1), xp = root3<T>(m1);
+    const Cx<T> ym = root3<T>(-m2), yp = root3<T>(m2);
+    const Cx<T> zm = root3<T>(-m3), zp = root3<T>(m3);
+    Cx<T> acc[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[a][b][c] = {T(0), T(0)};
+    const T *phi = D.phi;
+#pragma unroll
+    for (int gx = 0; gx < 4; ++gx) {
+        // z then y pass for this x slab: Y[ty][tz]
+        Cx<T> Y[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) Y[a][b] = {T(0), T(0)};
+        bool any = false;
+#pragma unroll
+        for (int gy = 0; gy < 4; ++gy) {
+            if (!colany[gx * 4 + gy]) continue;
+            any = true;
+            Cx<T> f[4];
+#pragma unroll
+            for (int gz = 0; gz < 4; ++gz) {
+                const int32_t sl = src[(gx * 4 + gy) * 4 + gz];
+                if (sl >= 0) {
+                    const T *q = phi + 2 * (int64_t)sl * nm + e;
+                    f[gz] = {q[0], q[nm]};
+                } else {
+                    f[gz] = {T(0), T(0)};
+                }
+            }
+            // Z[tz] = sum over gz = tz .. tz+2 of w^{-m3 (gz - tz - 1)} f[gz]
+            Cx<T> z0 = cmul(f[0], zm), z1 = cmul(f[3], zp);
+            z0.r += f[1].r + cmul(f[2], zp).r;
+            z0.i += f[1].i + cmul(f[2], zp).i;
+            z1.r += f[2].r + cmul(f[1], zm).r;
+            z1.i += f[2].i + cmul(f[1], zm).i;
+            // ty = gy - 1 - delta: gy contributes to ty = 0 (delta = gy - 1) and ty = 1 (delta = gy - 2)
+            if (gy <= 2) {
+                const Cx<T> fy = (gy == 0) ? ym : (gy == 1) ? Cx<T>{T(1), T(0)} : yp;
+                const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
+                Y[0][0].r += a0.r; Y[0][0].i += a0.i;
+                Y[0][1].r += a1.r; Y[0][1].i += a1.i;
+            }
+            if (gy >= 1) {
+                const Cx<T> fy = (gy == 1) ? ym : (gy == 2) ? Cx<T>{T(1), T(0)} : yp;
+                const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
+                Y[1][0].r += a0.r; Y[1][0].i += a0.i;
+                Y[1][1].r += a1.r; Y[1][1].i += a1.i;
+            }
         }
-        const T w = D.wd0[e] * wscale;
-        outr[e] = re * w;
-        outi[e] = im * w;
+        if (!any) continue;
+        // x pass
+        if (gx <= 2) {
+            const Cx<T> fx = (gx == 0) ? xm : (gx == 1) ? Cx<T>{T(1), T(0)} : xp;
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const Cx<T> v = cmul(Y[b][c], fx);
+                    acc[0][b][c].r += v.r;
+                    acc[0][b][c].i += v.i;
+                }
+        }
+        if (gx >= 1) {
+            const Cx<T> fx = (gx == 1) ? xm : (gx == 2) ? Cx<T>{T(1), T(0)} : xp;
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const Cx<T> v = cmul(Y[b][c], fx);
+                    acc[1][b][c].r += v.r;
+                    acc[1][b][c].i += v.i;
+                }
+        }
+    }
+    const T w = D.wd0[e] * (T)ldexp(1.0, oct_level[o]);  // w_l = 2^l w_0 (scale invariance of 1/r)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int32_t d = dst[t];
+        if (d < 0) continue;
+        const Cx<T> v = acc[t >> 2][(t >> 1) & 1][t & 1];
+        T *out = D.psi + 2 * (int64_t)d * nm + e;
+        out[0] = v.r * w;
+        out[nm] = v.i * w;
     }
 }
 
@@ -998,9 +1097,13 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
         hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
                            Pl->l_fout);
     }
-    if (Pl->nfin) {
+    if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
-        hipLaunchKernelGGL((k_pwshift<T>), dim3((unsigned)Pl->nfin), dim3(TPB), 0, s, D, Pl->l_fin);
+        const int64_t nm = (int64_t)Pl->tab.nh * Pl->tab.nn * Pl->tab.nn;
+        const int nchunk = (int)((nm + TPB - 1) / TPB);
+        const int64_t nb = (Pl->noct * nchunk + 7) / 8 * 8;
+        hipLaunchKernelGGL((k_pwshift<T>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
+                           Pl->oct_level, Pl->noct, nchunk);
     }
     // local values of the anchors, coarse to fine
     for (int l = 0; l < L; ++l) {

@@ -552,6 +552,45 @@ __global__ void k_slots(const int32_t *list, int64_t m, int32_t *slot)
     if (i < m) slot[list[i]] = (int32_t)i;
 }
 
+// parents of the non-empty F_in boxes of levels >= 1
+__global__ void k_oct_flag(const int32_t *fin, int64_t m, const int32_t *parent, uint8_t *flag)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= m) return;
+    int32_t P = parent[fin[i]];
+    if (P >= 0) flag[P] = 1;
+}
+
+// sibling group of parent P: child k = (x y z bits) sits at cell k + (1,1,1)
+// of the 4x4x4 block; cell g holds child ((g+1) & 1) of P's colleague at
+// offset (g+1)/2 - 1 per axis
+__global__ void k_oct_fill(const int32_t *octs, int64_t m, const int32_t *child0, const int32_t *col,
+                           const uint8_t *bflags, const int32_t *blevel, const int32_t *proxy_slot,
+                           const int32_t *psi_slot, int32_t *dst, int32_t *src, int32_t *lev)
+{
+    int64_t i = blockIdx.x;
+    if (i >= m) return;
+    const int32_t P = octs[i];
+    const int t = threadIdx.x;
+    if (t < 8) dst[i * 8 + t] = psi_slot[child0[P] + t];
+    if (t == 0) lev[i] = blevel[P] + 1;
+    if (t < 64) {
+        const int g[3] = {t / 16, (t / 4) % 4, t % 4};
+        int k = 0, c = 0;
+        for (int a = 0; a < 3; ++a) {
+            k = 3 * k + (g[a] + 1) / 2;      // colleague offset + 1
+            c = 2 * c + ((g[a] + 1) & 1);   // child bit
+        }
+        int32_t C = col[(int64_t)P * 27 + k];
+        int32_t v = -1;
+        if (C >= 0 && child0[C] >= 0) {
+            int32_t S = child0[C] + c;
+            if (bflags[S] & 2) v = proxy_slot[S];
+        }
+        src[i * 64 + t] = v;
+    }
+}
+
 // anchor of a box: itself if it holds points and has F_in, else its parent's
 // anchor; the root is always an anchor.  One launch per level, top down.
 __global__ void k_anchor(int64_t b0, int64_t nb, const int32_t *parent, const uint8_t *f_fin, int32_t *anchor)
@@ -700,6 +739,43 @@ void build_lists(Plan *P, hipStream_t s)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nanc)), dim3(TPB), 0, s, P->l_anc, P->nanc, P->local_slot);
     if (P->nfin)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfin)), dim3(TPB), 0, s, P->l_fin, P->nfin, P->psi_slot);
+
+    // sibling groups for the diagonal translation (the root first, then the
+    // parents level by level)
+    {
+        uint8_t *f_oct = S.get<uint8_t>(nbox);
+        DMK_HIP(hipMemsetAsync(f_oct, 0, nbox, s));
+        if (P->nfin)
+            hipLaunchKernelGGL(k_oct_flag, dim3(nblk(P->nfin)), dim3(TPB), 0, s, P->l_fin, P->nfin, P->parent, f_oct);
+        int32_t *octs = S.get<int32_t>(nbox + 1);
+        int64_t m = select_indices(S, f_oct, 0, nbox, octs, s);
+        int32_t root_psi = -1, root_phi = -1;
+        if (nbox > 0) {
+            DMK_HIP(hipMemcpyAsync(&root_psi, P->psi_slot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DMK_HIP(hipMemcpyAsync(&root_phi, P->proxy_slot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DMK_HIP(hipStreamSynchronize(s));
+        }
+        const int64_t r = (root_psi >= 0) ? 1 : 0;
+        P->noct = m + r;
+        P->oct_dst = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * 8);
+        P->oct_src = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * 64);
+        P->oct_level = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1));
+        if (r) {
+            // the root's only colleague is itself: target cell (1,1,1) = 21
+            std::vector<int32_t> d(8, -1), g(64, -1);
+            d[0] = root_psi;
+            g[21] = root_phi;
+            int32_t l0 = 0;
+            DMK_HIP(hipMemcpyAsync(P->oct_dst, d.data(), 8 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipMemcpyAsync(P->oct_src, g.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipMemcpyAsync(P->oct_level, &l0, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipStreamSynchronize(s));
+        }
+        if (m)
+            hipLaunchKernelGGL(k_oct_fill, dim3((unsigned)m), dim3(64), 0, s, octs, m, P->child0, P->colleague,
+                               P->bflags, P->blevel, P->proxy_slot, P->psi_slot, P->oct_dst + 8 * r,
+                               P->oct_src + 64 * r, P->oct_level + r);
+    }
 
     // targets grouped by the anchor of their leaf (leaf evaluation)
     {

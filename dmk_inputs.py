@@ -56,6 +56,44 @@ def two_clusters_and_background(n: int, seed: int):
     return np.ascontiguousarray(pts), q
 
 
+def uniform_square(n: int, seed: int):
+    """Points uniform in [0,1]^2, charges uniform in [-1,1]."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    q = rng.uniform(-1.0, 1.0, n)
+    return pts, q
+
+
+def gaussian_2d(n: int, seed: int, sigma: float = 0.01):
+    """Points 0.5 + sigma N(0, I_2), charges uniform in [-1,1]."""
+    rng = np.random.default_rng(seed)
+    pts = 0.5 + sigma * rng.standard_normal((n, 2))
+    q = rng.uniform(-1.0, 1.0, n)
+    return pts, q
+
+
+def batch_2d(nprob: int, seed: int, nmin: float = 1e3, nmax: float = 2e5, scale: float = 1.0):
+    """Many independent 2-D problems: problem b draws from default_rng(1000 seed + b)
+    a size N_b = floor(exp(U[ln nmin, ln nmax]) * scale) (at least 1), then a
+    coin for its distribution (uniform in [0,1]^2, or 0.5 + 0.01 N(0, I_2)),
+    the points, and charges uniform in [-1,1].  Returns (offsets, pts, q) with
+    the problems concatenated."""
+    sizes, parts, charges = [], [], []
+    for b in range(nprob):
+        rng = np.random.default_rng(1000 * seed + b)
+        nb = max(1, int(np.floor(np.exp(rng.uniform(np.log(nmin), np.log(nmax))) * scale)))
+        if rng.random() < 0.5:
+            p = rng.random((nb, 2))
+        else:
+            p = 0.5 + 0.01 * rng.standard_normal((nb, 2))
+        parts.append(p)
+        charges.append(rng.uniform(-1.0, 1.0, nb))
+        sizes.append(nb)
+    off = np.zeros(nprob + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off, np.ascontiguousarray(np.concatenate(parts)), np.concatenate(charges)
+
+
 # Named workloads: (generator, N, seed, leaf capacity n_s).
 CONFIGS = {
     "cfg1_uniform_2k": (uniform_cube, 2_000, 1, 50),

@@ -62,6 +62,13 @@ class _Result(C.Structure):
                 ("p", C.c_int), ("nf", C.c_int), ("proxy", _P(_f64p)), ("local", _P(_f64p))]
 
 
+class _Split2(C.Structure):
+    _fields_ = [("kern", C.c_int), ("lam", C.c_double), ("nlev", C.c_int), ("deg", C.c_int),
+                ("coef", _f64p), ("self", _f64p)]
+
+
+LOG2, YUK2 = 0, 1  # 2-D kernels: -log(r)/(2 pi) and K_0(lambda r)
+
 _lib = None
 
 
@@ -98,6 +105,32 @@ def lib():
         L.orc_dmk_run.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int, C.c_int, _f64p,
                                   _f64p]
         L.orc_num_threads.restype = C.c_int
+        # 2-D
+        for f in ("orc_bessel_k0", "orc_bessel_k1"):
+            getattr(L, f).argtypes = [C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.orc2_kernel.argtypes = [C.c_int, C.c_double, C.c_double]
+        L.orc2_kernel.restype = C.c_double
+        L.orc_params2_for.argtypes = [C.c_double, _P(Params)]
+        L.orc2_dhat.argtypes = [_P(Pswf), C.c_int, C.c_double, C.c_int, C.c_double]
+        L.orc2_dhat.restype = C.c_double
+        L.orc2_w0hat.argtypes = [_P(Pswf), C.c_int, C.c_double, C.c_double]
+        L.orc2_w0hat.restype = C.c_double
+        L.orc2_smooth_quad.argtypes = [_P(Pswf), C.c_int, C.c_double, C.c_double]
+        L.orc2_smooth_quad.restype = C.c_double
+        L.orc2_split_init.argtypes = [_P(Pswf), C.c_int, C.c_double, C.c_int, _P(_Split2)]
+        L.orc2_split_free.argtypes = [_P(_Split2)]
+        L.orc2_smooth.argtypes = [_P(_Split2), C.c_int, C.c_double]
+        L.orc2_smooth.restype = C.c_double
+        L.orc2_residual.argtypes = [_P(_Split2), C.c_int, C.c_double]
+        L.orc2_residual.restype = C.c_double
+        L.orc2_d_pw.argtypes = [_P(Pswf), _P(Params), C.c_int, C.c_double, C.c_int, _f64p]
+        L.orc2_d_pw.restype = C.c_double
+        L.orc2_w0_pw.argtypes = [_P(Pswf), _P(Params), C.c_int, C.c_double, _f64p]
+        L.orc2_w0_pw.restype = C.c_double
+        L.orc_dmk2_eval.argtypes = [_P(_Tree), _P(Params), _P(Pswf), C.c_int, C.c_double, _f64p, C.c_int,
+                                    _P(_Result)]
+        L.orc_direct2.argtypes = [C.c_int, C.c_double, C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
         _lib = L
     return _lib
 
@@ -161,6 +194,68 @@ class PSWF:
         return lib().orc_split_w0_pw(C.byref(self.s), C.byref(params), _dp(x))
 
 
+    # ---- 2-D split (kern: LOG2 or YUK2; lam: scaled Yukawa parameter)
+    def d2hat(self, kern, lam, l, k):
+        return lib().orc2_dhat(C.byref(self.s), int(kern), float(lam), int(l), float(k))
+
+    def w02hat(self, kern, lam, k):
+        return lib().orc2_w0hat(C.byref(self.s), int(kern), float(lam), float(k))
+
+    def smooth_quad(self, kern, mu, x):
+        return lib().orc2_smooth_quad(C.byref(self.s), int(kern), float(mu), float(x))
+
+    def d2_pw(self, params: Params, kern, lam, l, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc2_d_pw(C.byref(self.s), C.byref(params), int(kern), float(lam), int(l), _dp(x))
+
+    def w02_pw(self, params: Params, kern, lam, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc2_w0_pw(C.byref(self.s), C.byref(params), int(kern), float(lam), _dp(x))
+
+
+class Split2:
+    """Per-level residual tables of the 2-D split (smooth part and M_l(0))."""
+
+    def __init__(self, pswf: PSWF, kern: int, lam: float, nlev: int):
+        self._s = _Split2()
+        lib().orc2_split_init(C.byref(pswf.s), int(kern), float(lam), int(nlev), C.byref(self._s))
+        self.nlev, self.deg = nlev, self._s.deg
+        self.coef = np.ctypeslib.as_array(self._s.coef, shape=(nlev * (self.deg + 1),)).reshape(
+            nlev, self.deg + 1).copy()
+        self.self_ = np.ctypeslib.as_array(self._s.self, shape=(nlev,)).copy()
+
+    def smooth(self, l, x):
+        return lib().orc2_smooth(C.byref(self._s), int(l), float(x))
+
+    def residual(self, l, r):
+        return lib().orc2_residual(C.byref(self._s), int(l), float(r))
+
+    def __del__(self):
+        try:
+            lib().orc2_split_free(C.byref(self._s))
+        except Exception:
+            pass
+
+
+def params2_for(tol: float) -> Params:
+    pr = Params()
+    if lib().orc_params2_for(tol, C.byref(pr)) != 0:
+        raise ValueError(f"unsupported tolerance {tol}")
+    return pr
+
+
+def bessel_k0(x):
+    return lib().orc_bessel_k0(float(x))
+
+
+def bessel_k1(x):
+    return lib().orc_bessel_k1(float(x))
+
+
+def kernel2(kern, lam, r):
+    return lib().orc2_kernel(int(kern), float(lam), float(r))
+
+
 def gauss_legendre(n: int):
     x = np.zeros(n)
     w = np.zeros(n)
@@ -219,14 +314,20 @@ class Tree:
             pass
 
 
-def dmk_eval(tree: Tree, params: Params, pswf: PSWF, charges: np.ndarray, keep: bool = False):
+def dmk_eval(tree: Tree, params: Params, pswf: PSWF, charges: np.ndarray, keep: bool = False,
+             kern: int = LOG2, lam: float = 0.0):
     """Run Steps 2-5 on a built tree.  Returns a dict with the potential in
     input order (u) and, in sorted order and normalised units, the far and
-    residual parts; with keep=True also the per-box proxies and local values."""
+    residual parts; with keep=True also the per-box proxies and local values.
+    2-D trees use kern (LOG2 / YUK2) and lam (input units)."""
     q = np.ascontiguousarray(charges, dtype=np.float64)
     res = _Result()
-    rc = lib().orc_dmk_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), _dp(q),
-                            1 if keep else 0, C.byref(res))
+    if tree.dim == 2:
+        rc = lib().orc_dmk2_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), int(kern), float(lam),
+                                 _dp(q), 1 if keep else 0, C.byref(res))
+    else:
+        rc = lib().orc_dmk_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), _dp(q),
+                                1 if keep else 0, C.byref(res))
     if rc != 0:
         raise RuntimeError("orc_dmk_eval failed")
     n = tree.n
@@ -240,7 +341,7 @@ def dmk_eval(tree: Tree, params: Params, pswf: PSWF, charges: np.ndarray, keep: 
         out["ufar"] = np.zeros(0)
         out["ures"] = np.zeros(0)
     if keep and n:
-        p3 = params.p ** 3
+        p3 = params.p ** tree.dim
         prox, loc = {}, {}
         for b in range(tree.nbox):
             if res.proxy[b]:
@@ -283,6 +384,20 @@ def direct(pts, charges, tidx=None):
     tidx = np.ascontiguousarray(tidx, dtype=np.int64)
     out = np.zeros(len(tidx))
     lib().orc_direct(n, _dp(pts), _dp(q), len(tidx), tidx.ctypes.data_as(_i64p), _dp(out))
+    return out
+
+
+def direct2(kern, lam, pts, charges, tidx=None):
+    """u_i = sum_{j != i, r > 0} K(r_ij) q_j, K = -log(r)/(2 pi) or K_0(lam r)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    n = pts.shape[0]
+    if tidx is None:
+        tidx = np.arange(n, dtype=np.int64)
+    tidx = np.ascontiguousarray(tidx, dtype=np.int64)
+    out = np.zeros(len(tidx))
+    lib().orc_direct2(int(kern), float(lam), n, _dp(pts), _dp(q), len(tidx), tidx.ctypes.data_as(_i64p),
+                      _dp(out))
     return out
 
 

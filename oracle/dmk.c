@@ -52,15 +52,9 @@ int orc_num_threads(void)
 #endif
 }
 
-/* ---------------------------------------------------------- Chebyshev */
-typedef struct {
-    int p;
-    double *x;     /* nodes r_i = cos(pi (i - 1/2) / p), i = 1..p          */
-    double *vinv;  /* V^{-1}, V(i,j) = T_{j-1}(r_i)  (Sec. 2.1)            */
-    double *A[2];  /* A_sigma[a][i] = ell_a((r_i + sigma)/2), sigma = -1,+1 */
-} cheb_t;
+#include "cheb.h"
 
-static void cheb_T(int p, double x, double *T)
+void cheb_T(int p, double x, double *T)
 {
     T[0] = 1.0;
     if (p > 1) T[1] = x;
@@ -68,7 +62,7 @@ static void cheb_T(int p, double x, double *T)
 }
 
 /* row of the interpolation matrix U = E V^{-1} at one point */
-static void cheb_interp_row(const cheb_t *ch, double xi, double *u)
+void cheb_interp_row(const cheb_t *ch, double xi, double *u)
 {
     int p = ch->p;
     double T[64];
@@ -80,7 +74,7 @@ static void cheb_interp_row(const cheb_t *ch, double xi, double *u)
     }
 }
 
-static void cheb_init(int p, cheb_t *ch)
+void cheb_init(int p, cheb_t *ch)
 {
     ch->p = p;
     ch->x = (double *)malloc((size_t)p * sizeof(double));
@@ -129,7 +123,7 @@ static void cheb_init(int p, cheb_t *ch)
     }
 }
 
-static void cheb_free(cheb_t *ch)
+void cheb_free(cheb_t *ch)
 {
     free(ch->x); free(ch->vinv); free(ch->A[0]); free(ch->A[1]);
 }

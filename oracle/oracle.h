@@ -147,6 +147,50 @@ int orc_dmk_run(int64_t n, const double *pts, const double *q, double tol,
 
 int orc_num_threads(void);
 
+/* ------------------------------------------------------------------- 2-D
+ * Kernels (input units): ORC_LOG2 K(r) = -log(r)/(2 pi); ORC_YUK2 K(r) =
+ * K_0(lambda r).  Split in Fourier space (Sec. 4.4, eq. yukawaPSWFkernels),
+ * windowed root kernel (Sec. 4.5); see split2.c. */
+enum { ORC_LOG2 = 0, ORC_YUK2 = 1 };
+#define ORC2_DEG 47   /* Chebyshev degree (in x^2) of the residual tables */
+
+double orc_bessel_k0(double x);
+double orc_bessel_k1(double x);
+double orc2_kernel(int kern, double lam, double r);
+/* Table 1 (c, nf, p); root window spacing hw = 2 pi/(3 + sqrt 2) */
+int    orc_params2_for(double tol, orc_params *out);
+/* transforms for root side 1; lam is the scaled Yukawa parameter */
+double orc2_dhat(const orc_pswf *ps, int kern, double lam, int l, double k);
+double orc2_w0hat(const orc_pswf *ps, int kern, double lam, double k);
+/* smooth part of the residual by quadrature (definition): log m(x); K_0
+ * M_l(x s_l) with mu = lam s_l */
+double orc2_smooth_quad(const orc_pswf *ps, int kern, double mu, double x);
+typedef struct {
+    int     kern;
+    double  lam;      /* scaled Yukawa parameter                            */
+    int     nlev, deg;
+    double *coef;     /* [nlev][deg+1] Chebyshev coefficients in 2(r/s_l)^2-1 */
+    double *self;     /* [nlev] M_l(0), the r = 0 limit of the far field    */
+} orc_split2;
+int    orc2_split_init(const orc_pswf *ps, int kern, double lam, int nlev, orc_split2 *sp);
+void   orc2_split_free(orc_split2 *sp);
+double orc2_smooth(const orc_split2 *sp, int l, double x);
+double orc2_residual(const orc_split2 *sp, int l, double r);  /* r > 0 */
+double orc2_d_pw(const orc_pswf *ps, const orc_params *pr, int kern, double lam, int l,
+                 const double x[2]);
+double orc2_w0_pw(const orc_pswf *ps, const orc_params *pr, int kern, double lam,
+                  const double x[2]);
+
+/* DMK in 2-D on a 2-D tree; lam in input units.  ufar/ures are in the
+ * scaled (root side 1) problem; for the log kernel the constant
+ * -log(S)/(2 pi) of the unit change is carried by ufar (times the total
+ * charge) and by the r = 0 correction, so u = ufar + ures in input order. */
+int  orc_dmk2_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, int kern,
+                   double lam, const double *charges, int keep, orc_dmk_result *res);
+/* direct sum over j != i, r_ij > 0, compensated */
+void orc_direct2(int kern, double lam, int64_t n, const double *pts, const double *q,
+                 int64_t nt, const int64_t *tidx, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,14 +14,14 @@ import dmk_inputs
 
 def _coords(tree):
     """integer box coordinates at each box's own level"""
-    nb = tree.nbox
-    c = np.zeros((nb, 3), dtype=np.int64)
+    nb, dim = tree.nbox, tree.dim
+    c = np.zeros((nb, dim), dtype=np.int64)
     for b in range(nb):
         key = int(tree.bkey[b])
         l = int(tree.level[b])
         for bit in range(l):
-            for d in range(3):
-                c[b, d] |= ((key >> (3 * bit + (2 - d))) & 1) << bit
+            for d in range(dim):
+                c[b, d] |= ((key >> (dim * bit + (dim - 1 - d))) & 1) << bit
     return c
 
 
@@ -40,6 +40,8 @@ CASES = [
     ("adaptive", lambda: dmk_inputs.two_clusters_and_background(1500, 11), 20),
     ("sphere", lambda: dmk_inputs.sphere_and_blobs(3000, 12), 30),
     ("uniform", lambda: dmk_inputs.uniform_cube(3000, 13), 40),
+    ("square2d", lambda: dmk_inputs.uniform_square(3000, 14), 30),
+    ("gaussian2d", lambda: dmk_inputs.gaussian_2d(3000, 15, sigma=0.02), 20),
 ]
 
 
@@ -65,7 +67,7 @@ def test_structure(built):
         if tree.leaf[b]:
             assert tree.child0[b] == -1
         else:
-            ch = tree.child0[b] + np.arange(8)
+            ch = tree.child0[b] + np.arange(2 ** tree.dim)
             assert np.all(tree.parent[ch] == b)
             assert tree.pcount[ch].sum() == tree.pcount[b]
             assert tree.pstart[ch[0]] == tree.pstart[b]
@@ -73,7 +75,7 @@ def test_structure(built):
 
 def test_points_in_boxes(built):
     tree, pts, coords, lo, hi, ns = built
-    # the sorted points are the input points, rescaled into [-1/2,1/2]^3
+    # the sorted points are the input points, rescaled into [-1/2,1/2]^d
     x = (pts[tree.perm] - tree.center) / tree.side
     assert np.array_equal(x, tree.xs)
     assert np.all(np.abs(tree.xs) < 0.5)
@@ -113,9 +115,11 @@ def test_colleagues_and_coarse(built):
         t = same[_touch(lo, hi, b, same)]
         got = tree.colleague[b][tree.colleague[b] >= 0]
         assert sorted(got.tolist()) == sorted(t.tolist())
-        for j in got:  # offset order (dx, dy, dz) lexicographic
+        for j in got:  # offset order (dx, dy[, dz]) lexicographic
             dlt = coords[j] - coords[b]
-            k = (dlt[0] + 1) * 9 + (dlt[1] + 1) * 3 + (dlt[2] + 1)
+            k = 0
+            for d in range(tree.dim):
+                k = 3 * k + int(dlt[d]) + 1
             assert tree.colleague[b][k] == j
         if tree.leaf[b] and l > 0:
             cand = allb[(tree.level == l - 1) & (tree.leaf == 1)]
@@ -181,3 +185,6 @@ def test_degenerate_inputs(oracle_mod):
     assert t0.nbox == 1 and t0.pcount[0] == 0
     t1 = oracle_mod.Tree(np.array([[0.5, 0.5, 0.5]]), 10)
     assert t1.nbox == 1 and t1.leaf[0] == 1
+    # 2-D: identical points stop at the cap as well
+    t2 = oracle_mod.Tree(np.tile(np.array([[0.1, 0.2]]), (30, 1)), 10, 5)
+    assert t2.nlevels == 6 and t2.pcount[t2.level_start[5]:].max() == 30

@@ -8,13 +8,17 @@
  * targets),
  *
  *     pot_i = sum_{j != i, |x_i - x_j| > 0} K(|x_i - x_j|) q_j,
- *     K(r) = 1 / (4 pi r)                      (3-D Laplace, eq. laplacesum),
+ *     K(r) = 1 / (4 pi r)        (3-D Laplace, eq. laplacesum), or
+ *     K(r) = -log(r) / (2 pi)    (2-D Laplace),
  *
  * to a requested relative precision tol, with the O(N) scheme of Sec. 3.5-3.6
  * ("The linear scaling full DMK algorithm", "The full DMK algorithm for
- * discrete sources") and the PSWF kernel split of Sec. 3.7.  Pairs at
- * distance exactly zero (the self pair and coincident points) contribute
- * nothing.
+ * discrete sources"), the PSWF kernel split of Sec. 3.7 in 3-D and its
+ * Fourier-space form (Sec. 4.4, with the windowed root kernel of Sec. 4.5)
+ * in 2-D.  Pairs at distance exactly zero (the self pair and coincident
+ * points) contribute nothing.  A plan may hold many independent 2-D point
+ * sets (dmk_plan_batched); each is solved in its own root box and every
+ * stage runs over the boxes of all of them at once.
  *
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers (memory of the current HIP
@@ -23,8 +27,8 @@
  *    stream.  Work is enqueued on it asynchronously unless stated otherwise.
  *  - Status codes only; no C++ exception crosses the ABI.  After a non-zero
  *    status, dmk_last_error() returns a message for the calling thread.
- *  - Only the 3-D Laplace kernel is implemented; other kernel/dim pairs
- *    return DMK_ERR_UNSUPPORTED.
+ *  - Implemented: DMK_LAPLACE in 2-D and 3-D.  DMK_YUKAWA returns
+ *    DMK_ERR_UNSUPPORTED.
  */
 #ifndef DMK_H
 #define DMK_H
@@ -45,6 +49,8 @@ typedef enum {
     DMK_ERR_STATE = -6         /* plan busy or in an unusable state          */
 } dmk_status;
 
+/* DMK_LAPLACE: 1/(4 pi r) in 3-D, -log(r)/(2 pi) in 2-D.
+ * DMK_YUKAWA: K_0(lambda r) in 2-D (not built: DMK_ERR_UNSUPPORTED). */
 typedef enum { DMK_LAPLACE = 0, DMK_YUKAWA = 1 } dmk_kernel;
 
 /* Arithmetic of the eval pipeline.  Input and output are always FP64. */
@@ -57,10 +63,13 @@ typedef enum {
 /* Options; a zero field selects the default.  Pass NULL for all defaults. */
 typedef struct {
     int32_t  leaf_max;    /* n_s, the leaf capacity (default 64)              */
-    int32_t  max_depth;   /* depth cap of the tree (default 20, at most 21)   */
+    int32_t  max_depth;   /* depth cap of the tree (default 20 in 3-D, 30 in
+                             2-D, at most the key bits per axis: 21 in 3-D,
+                             31 in 2-D, fewer in a batch, see dmk_plan_batched) */
     int32_t  precision;   /* dmk_precision (default DMK_FP64)                 */
     int32_t  reserved0;
     uint64_t flags;       /* DMK_FLAG_* bits (DMK_FLAG_BATCHED)               */
+    double   lambda;      /* Yukawa parameter in input units (DMK_YUKAWA)     */
 } dmk_opts;
 
 /* Batched execution of dmk_eval: the middle of the pipeline (upward pass,
@@ -90,8 +99,10 @@ typedef struct {
     int64_t nfin;         /* non-empty boxes with F_in                       */
     int64_t npairs;       /* candidate (target, source) pairs of the residual */
     int64_t device_bytes; /* device memory held by the plan                  */
-    double  center[3];    /* root cube centre (input units)                  */
-    double  side;         /* root cube side (input units)                    */
+    double  center[3];    /* root box centre of problem 0 (input units)      */
+    double  side;         /* root box side of problem 0 (input units)        */
+    int32_t dim;
+    int32_t nprob;        /* independent problems in the plan                */
 } dmk_plan_stats;
 
 /*
@@ -102,12 +113,12 @@ typedef struct {
  * plane-wave weights) of Sec. 3.6; tree conventions of Sec. 3.3; parameters
  * c, N_1 = 2 n_f + 1, p of Table 1 (Sec. 3.7).
  *
- *  dim     must be 3.
- *  kernel  must be DMK_LAPLACE.
+ *  dim     2 or 3.
+ *  kernel  DMK_LAPLACE (DMK_YUKAWA: DMK_ERR_UNSUPPORTED).
  *  tol     one of 1e-3, 1e-6, 1e-9, 1e-12 (Table 1) or 1e-5.  DMK_MIXED
  *          requires tol >= 1e-6 (else DMK_ERR_PRECISION).
  *  n       number of points, 0 <= n < 2^31.
- *  pts     device, [n][3] FP64, row-major, input order.  Read during the
+ *  pts     device, [n][dim] FP64, row-major, input order.  Read during the
  *          call only; the plan keeps its own sorted copy.  Non-finite
  *          coordinates give DMK_ERR_ARG.
  *  opts    host pointer or NULL.
@@ -118,6 +129,36 @@ typedef struct {
  */
 dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const double *pts,
                     const dmk_opts *opts, void *stream, dmk_plan_t *out);
+
+/*
+ * dmk_plan_batched -- one plan for nprob independent point sets.
+ *
+ * Paper: the same steps as dmk_plan, applied to every problem; each problem
+ * gets its own root box from its own bounding box (Sec. 3.3).  The trees
+ * form a forest: level 0 holds the nprob roots, boxes of all problems are
+ * interleaved level by level, and every stage of dmk_eval is one launch over
+ * the boxes of all problems.
+ *
+ *  dim      must be 2 (3-D batches: DMK_ERR_UNSUPPORTED).
+ *  nprob    >= 1.
+ *  offsets  HOST, [nprob+1] int64, offsets[0] = 0, non-decreasing; problem b
+ *           is points offsets[b] .. offsets[b+1]-1 (empty problems allowed).
+ *  pts      device, [offsets[nprob]][dim] FP64, the problems concatenated.
+ *  Other arguments as dmk_plan.  Keys hold ceil(log2 nprob) bits of problem
+ *  index, leaving (63 - those bits)/dim bits per axis (at most 31), which
+ *  caps max_depth.
+ * dmk_eval on such a plan takes the concatenated charges and returns the
+ * concatenated potentials, problem by problem, with no interaction between
+ * problems.
+ */
+dmk_status dmk_plan_batched(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *offsets,
+                            const double *pts, const dmk_opts *opts, void *stream, dmk_plan_t *out);
+
+/*
+ * dmk_problem_info -- root box of problem `prob` of a plan (input units):
+ * centre [dim] and side, both HOST pointers (either may be NULL).
+ */
+dmk_status dmk_problem_info(dmk_plan_t plan, int32_t prob, double *center, double *side);
 
 /*
  * dmk_eval -- potentials of one charge vector on a planned point set.
@@ -140,7 +181,10 @@ dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *s
  * windowed and difference kernels through plane waves and Chebyshev
  * interpolation, eq. farpotential) and the near part (residual kernel sums
  * plus the self correction, eq. nearpotential and Step 5) separately, both
- * in input order and both scaled by 1/(4 pi S).  pot = far + near.
+ * in input order and input units (3-D: both scaled by 1/(4 pi S); 2-D: the
+ * constant -log(S)/(2 pi) of the unit change is carried by the far part for
+ * the total charge and by the near part for pairs at distance zero).
+ * pot = far + near.
  * Either output pointer may be NULL.
  */
 dmk_status dmk_eval_parts(dmk_plan_t plan, const double *charges, double *far_part,
@@ -155,17 +199,19 @@ dmk_status dmk_plan_info(dmk_plan_t plan, dmk_plan_stats *st);
  * be NULL to skip that array.  Sizes: n = points, B = nbox (dmk_plan_info).
  *   perm       [n]       int64  sorted position -> input index
  *   level      [B]       int32
- *   bkey       [B]       uint64 Morton prefix of the box at its level
- *   parent     [B]       int64  (-1 for the root)
- *   child0     [B]       int64  first of 8 contiguous children, -1 for a leaf
+ *   bkey       [B]       uint64 Morton prefix of the box at its level, with
+ *                               the problem index above it (batched plans)
+ *   parent     [B]       int64  (-1 for a root)
+ *   child0     [B]       int64  first of 2^dim contiguous children, -1 for a leaf
  *   pstart     [B]       int64  first sorted point of the box
  *   pcount     [B]       int64  points in the box
  *   flags      [B]       uint8  bit0 leaf, bit1 F_out, bit2 F_in, bit3 terminal
- *   colleague  [B][27]   int64  same-level neighbours by offset (dx,dy,dz),
- *                               lexicographic from (-1,-1,-1); -1 if absent
+ *   colleague  [B][3^dim] int64 same-level neighbours by offset (dx,dy[,dz]),
+ *                               lexicographic from (-1,..,-1); -1 if absent
  *   ncoarse    [B]       int32  number of coarse-neighbour leaves
- *   coarse     [B][7]    int64  coarse-neighbour leaves (first ncoarse valid)
- * Boxes are ordered level by level, in Morton order within a level.
+ *   coarse     [B][2^dim-1] int64 coarse-neighbour leaves (first ncoarse valid)
+ * Boxes are ordered level by level, in key order within a level (problem
+ * index first, then Morton order).
  * Synchronous.
  */
 dmk_status dmk_export_tree(dmk_plan_t plan, int64_t *perm, int32_t *level, uint64_t *bkey,
@@ -186,15 +232,16 @@ dmk_status dmk_export_near_lists(dmk_plan_t plan, int64_t *leaf_box, int64_t *of
 
 /*
  * dmk_copy_box_data -- after a dmk_eval on `plan`, copy per-box data of
- * box `box` to the HOST array `out` (p^3 FP64 values, index (i*p + j)*p + k
- * for Chebyshev node indices i, j, k along x, y, z).
+ * box `box` to the HOST array `out` (p^dim FP64 values, index (i*p + j)*p + k
+ * for Chebyshev node indices i, j, k along x, y, z; i*p + j in 2-D).
  *   what = 0: proxy charges (boxes with F_out only);
  *   what = 1: local values of the far potential on the box's Chebyshev grid,
  *             held by the root and by every box with points and F_in (any
  *             other box's far potential is the polynomial of its nearest
  *             such ancestor, by the exactness of Lemma 2.2).
- * Values are in normalised units (root box [-1/2,1/2]^3, kernel 1/r); the
- * mixed path's FP32 values are widened to FP64.
+ * Values are in normalised units (root box [-1/2,1/2]^dim; kernel 1/r in
+ * 3-D; in 2-D -log(r)/(2 pi) with the root values holding the constant of
+ * the unit change); the mixed path's FP32 values are widened to FP64.
  * Returns DMK_ERR_ARG if the box holds no such data.  Synchronous.
  */
 dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out);
@@ -213,7 +260,14 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
  *             mode of the table has that |m|^2;
  *   what = 3: plane-wave weight of the windowed W_0 at |m|^2 = x_i;
  *   what = 4: out[0..3] = psi(0), c_0, c_2, lambda_0 (n >= 4, x unused);
- *   what = 5: out[0..5] = c, n_f, p, n_w, h_w, degree of g (n >= 6).
+ *   what = 5: out[0..5] = c, n_f, p, n_w, h_w, degree of g (n >= 6);
+ * 2-D tables (kernel -log(r)/(2 pi), Fourier-space split of Sec. 4.4):
+ *   what = 6: plane-wave weight of D_l at |m|^2 = x_i (the same at every
+ *             level), NaN if no mode of the table has that |m|^2;
+ *   what = 7: plane-wave weight of the windowed W_0 (Sec. 4.5) at |m|^2 = x_i;
+ *   what = 8: m(x_i), the smooth part of the residual
+ *             R_l(r) = -log(x)/(2 pi) - m(x), x = r/s_l in [0,1];
+ *   what = 9: out[0..3] = m(0), n_w, h_w, degree of m (n >= 4).
  * DMK_ERR_UNSUPPORTED for a tolerance outside the table, DMK_ERR_ARG for a
  * bad `what` or n.
  */

@@ -15,12 +15,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libdmk.so")
 
 DMK_FP64, DMK_MIXED = 0, 1
-DMK_LAPLACE = 0
+DMK_LAPLACE, DMK_YUKAWA = 0, 1
 DMK_FLAG_BATCHED = 2
 
 # exported symbols, in the order of include/dmk.h
-SYMBOLS = ["dmk_plan", "dmk_eval", "dmk_eval_parts", "dmk_plan_info", "dmk_export_tree",
-           "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
+SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_problem_info", "dmk_eval", "dmk_eval_parts",
+           "dmk_plan_info", "dmk_export_tree", "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
            "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
            "dmk_plan_destroy", "dmk_last_error"]
 
@@ -30,7 +30,7 @@ STAGES = ["gather", "upward", "root", "proxy2pw", "local", "pwshift", "pw2grid",
 
 class Opts(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("max_depth", C.c_int32), ("precision", C.c_int32),
-                ("reserved0", C.c_int32), ("flags", C.c_uint64)]
+                ("reserved0", C.c_int32), ("flags", C.c_uint64), ("lambda_", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -38,7 +38,8 @@ class Stats(C.Structure):
                 ("nf", C.c_int32), ("nw", C.c_int32), ("c", C.c_double), ("tol", C.c_double),
                 ("leaf_max", C.c_int32), ("precision", C.c_int32), ("nleaf", C.c_int64),
                 ("nfout", C.c_int64), ("nfin", C.c_int64), ("npairs", C.c_int64),
-                ("device_bytes", C.c_int64), ("center", C.c_double * 3), ("side", C.c_double)]
+                ("device_bytes", C.c_int64), ("center", C.c_double * 3), ("side", C.c_double),
+                ("dim", C.c_int32), ("nprob", C.c_int32)]
 
 
 class DmkError(RuntimeError):
@@ -59,6 +60,9 @@ def lib():
         L = C.CDLL(LIBPATH)
         vp, i64, f64p = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
         L.dmk_plan.argtypes = [C.c_int, C.c_int, C.c_double, i64, vp, C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.dmk_plan_batched.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, C.POINTER(Opts), vp,
+                                       C.POINTER(vp)]
+        L.dmk_problem_info.argtypes = [vp, C.c_int32, f64p, f64p]
         L.dmk_eval.argtypes = [vp, vp, vp, vp]
         L.dmk_eval_parts.argtypes = [vp, vp, vp, vp, vp]
         L.dmk_plan_info.argtypes = [vp, C.POINTER(Stats)]
@@ -108,19 +112,30 @@ def precompute_probe(tol, what, x=None, n=None):
 
 
 class Plan:
-    """dmk_plan on device points; eval() applies dmk_eval to charge vectors."""
+    """dmk_plan on device points [n, dim] (dim 2 or 3); with offsets (host
+    int64 [nprob+1]) dmk_plan_batched over the concatenated problems.
+    eval() applies dmk_eval to charge vectors."""
 
     def __init__(self, pts, tol=1e-6, leaf_max=64, max_depth=0, precision=DMK_FP64, flags=0,
-                 stream=None):
+                 stream=None, kernel=DMK_LAPLACE, lam=0.0, offsets=None):
         import torch
-        if not (isinstance(pts, torch.Tensor) and pts.is_cuda and pts.dtype == torch.float64):
-            raise TypeError("pts must be a float64 CUDA tensor of shape [n, 3]")
+        if not (isinstance(pts, torch.Tensor) and pts.is_cuda and pts.dtype == torch.float64
+                and pts.dim() == 2 and pts.shape[1] in (2, 3)):
+            raise TypeError("pts must be a float64 CUDA tensor of shape [n, 2] or [n, 3]")
         pts = pts.contiguous()
         self.n = int(pts.shape[0])
-        o = Opts(leaf_max, max_depth, precision, 0, flags)
+        self.dim = int(pts.shape[1])
+        o = Opts(leaf_max, max_depth, precision, 0, flags, float(lam))
         h = C.c_void_p()
-        _check(lib().dmk_plan(3, DMK_LAPLACE, float(tol), self.n, _ptr(pts), C.byref(o),
-                              _stream_handle(stream), C.byref(h)))
+        if offsets is None:
+            _check(lib().dmk_plan(self.dim, int(kernel), float(tol), self.n, _ptr(pts), C.byref(o),
+                                  _stream_handle(stream), C.byref(h)))
+        else:
+            off = np.ascontiguousarray(offsets, dtype=np.int64)
+            if off[-1] != self.n:
+                raise ValueError("offsets[-1] must equal the number of points")
+            _check(lib().dmk_plan_batched(self.dim, int(kernel), float(tol), len(off) - 1, _np_ptr(off),
+                                          _ptr(pts), C.byref(o), _stream_handle(stream), C.byref(h)))
         self._h = h
         self.device = pts.device
 
@@ -160,15 +175,23 @@ class Plan:
         d["center"] = list(st.center)
         return d
 
+    def problem_info(self, b):
+        c = np.zeros(3)
+        sd = np.zeros(1)
+        _check(lib().dmk_problem_info(self._h, int(b), c.ctypes.data_as(C.POINTER(C.c_double)),
+                                      sd.ctypes.data_as(C.POINTER(C.c_double))))
+        return c[: self.dim], float(sd[0])
+
     def export_tree(self):
         inf = self.info()
         n, nb = inf["n"], inf["nbox"]
+        ncol, nco = 3 ** self.dim, 2 ** self.dim - 1
         out = dict(perm=np.zeros(n, np.int64), level=np.zeros(nb, np.int32),
                    bkey=np.zeros(nb, np.uint64), parent=np.zeros(nb, np.int64),
                    child0=np.zeros(nb, np.int64), pstart=np.zeros(nb, np.int64),
                    pcount=np.zeros(nb, np.int64), flags=np.zeros(nb, np.uint8),
-                   colleague=np.zeros((nb, 27), np.int64), ncoarse=np.zeros(nb, np.int32),
-                   coarse=np.zeros((nb, 7), np.int64))
+                   colleague=np.zeros((nb, ncol), np.int64), ncoarse=np.zeros(nb, np.int32),
+                   coarse=np.zeros((nb, nco), np.int64))
         keys = ["perm", "level", "bkey", "parent", "child0", "pstart", "pcount", "flags",
                 "colleague", "ncoarse", "coarse"]
         _check(lib().dmk_export_tree(self._h, *[_np_ptr(out[k]) for k in keys]))
@@ -201,7 +224,7 @@ class Plan:
 
     def box_data(self, what, box):
         p = self.info()["p"]
-        out = np.zeros(p ** 3)
+        out = np.zeros(p ** self.dim)
         _check(lib().dmk_copy_box_data(self._h, int(what), int(box),
                                        out.ctypes.data_as(C.POINTER(C.c_double))))
         return out

@@ -79,56 +79,120 @@ extern "C" {
 
 const char *dmk_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+namespace {
+
+// Shared by dmk_plan and dmk_plan_batched: validates, builds tables, the
+// forest of trees, lists and workspace.  poff: host offsets [nprob+1].
+dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *poff, const double *pts,
+                     const dmk_opts *opts, void *stream)
+{
+    if (dim != 2 && dim != 3) throw Error{DMK_ERR_ARG, "dim must be 2 or 3"};
+    if (kernel != DMK_LAPLACE && kernel != DMK_YUKAWA) throw Error{DMK_ERR_ARG, "unknown kernel"};
+    if (kernel != DMK_LAPLACE) throw Error{DMK_ERR_UNSUPPORTED, "only the Laplace kernels are implemented"};
+    if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
+    if (nprob < 1) throw Error{DMK_ERR_ARG, "nprob must be >= 1"};
+    if (dim == 3 && nprob > 1) throw Error{DMK_ERR_UNSUPPORTED, "batches of 3-D problems are not built"};
+    if (!poff) throw Error{DMK_ERR_ARG, "offsets is NULL"};
+    if (poff[0] != 0) throw Error{DMK_ERR_ARG, "offsets[0] must be 0"};
+    for (int32_t b = 0; b < nprob; ++b)
+        if (poff[b + 1] < poff[b]) throw Error{DMK_ERR_ARG, "offsets must be non-decreasing"};
+    const int64_t n = poff[nprob];
+    if (n >= (int64_t(1) << 31)) throw Error{DMK_ERR_ARG, "n must satisfy 0 <= n < 2^31"};
+    if (n > 0 && !pts) throw Error{DMK_ERR_ARG, "pts is NULL"};
+    dmk_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    Params prm;
+    if (!params_for(tol, &prm, dim))
+        throw Error{DMK_ERR_UNSUPPORTED, "tol must be one of 1e-3, 1e-5, 1e-6, 1e-9, 1e-12"};
+    if (prm.p > 18) throw Error{DMK_ERR_UNSUPPORTED, "tol below 1e-6 needs proxy order > 18, not built"};
+    if (o.precision != DMK_FP64 && o.precision != DMK_MIXED) throw Error{DMK_ERR_ARG, "unknown precision"};
+    if (o.precision == DMK_MIXED && tol < 1e-6 * (1 - 1e-9))
+        throw Error{DMK_ERR_PRECISION, "mixed precision needs tol >= 1e-6"};
+    // key layout: problem index above dim * kb Morton bits, 63 bits in all
+    int pbits = 0;
+    while ((int64_t(1) << pbits) < nprob) ++pbits;
+    const int kbmax = (dim == 3) ? 21 : 31;
+    const int kb = std::min(kbmax, (63 - pbits) / dim);
+    const int dflt = (dim == 3) ? 20 : 30;
+    if (o.leaf_max < 0 || o.max_depth < 0 || o.max_depth > kb) throw Error{DMK_ERR_ARG, "bad leaf_max/max_depth"};
+    auto *P = new Plan();
+    try {
+        P->dim = dim;
+        P->kernel = kernel;
+        P->lambda = o.lambda;
+        P->nprob = nprob;
+        P->poff.assign(poff, poff + nprob + 1);
+        P->pbits = pbits;
+        P->kb = kb;
+        P->precision = o.precision;
+        P->leaf_max = o.leaf_max ? o.leaf_max : 64;
+        P->max_depth = o.max_depth ? o.max_depth : std::min(dflt, kb);
+        P->flags = o.flags;
+        P->n = n;
+        build_tables(prm, &P->tab, dim);
+        P->p = prm.p;
+        P->nf = prm.nf;
+        P->nw = prm.nw;
+        hipStream_t s = (hipStream_t)stream;
+        P->d_poff = (int64_t *)dalloc(P, (nprob + 1) * sizeof(int64_t));
+        DMK_HIP(hipMemcpyAsync(P->d_poff, P->poff.data(), (nprob + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        upload_tables(P, s);
+        build_tree(P, pts, s);
+        build_lists(P, s);
+        alloc_workspace(P);
+        count_work(P, s);
+        if (P->flags & DMK_FLAG_BATCHED) {
+            // default-priority streams only
+            DMK_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+            DMK_HIP(hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking));
+            DMK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+            DMK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+        }
+    } catch (...) {
+        plan_release(P);
+        throw;
+    }
+    return reinterpret_cast<dmk_plan_t>(P);
+}
+
+}  // namespace
+
+extern "C" {
+
 dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const double *pts, const dmk_opts *opts,
                     void *stream, dmk_plan_t *out)
 {
     if (out) *out = nullptr;
     return guarded([&] {
         if (!out) throw Error{DMK_ERR_ARG, "out is NULL"};
-        if (dim != 3) throw Error{DMK_ERR_UNSUPPORTED, "only dim = 3 is implemented"};
-        if (kernel != DMK_LAPLACE) throw Error{DMK_ERR_UNSUPPORTED, "only the Laplace kernel is implemented"};
-        if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
-        if (n < 0 || n >= (int64_t(1) << 31)) throw Error{DMK_ERR_ARG, "n must satisfy 0 <= n < 2^31"};
-        if (n > 0 && !pts) throw Error{DMK_ERR_ARG, "pts is NULL"};
-        dmk_opts o;
-        std::memset(&o, 0, sizeof(o));
-        if (opts) o = *opts;
-        Params prm;
-        if (!params_for(tol, &prm)) throw Error{DMK_ERR_UNSUPPORTED, "tol must be one of 1e-3, 1e-5, 1e-6, 1e-9, 1e-12"};
-        if (prm.p > 18) throw Error{DMK_ERR_UNSUPPORTED, "tol below 1e-6 needs proxy order > 18, not built"};
-        if (o.precision != DMK_FP64 && o.precision != DMK_MIXED) throw Error{DMK_ERR_ARG, "unknown precision"};
-        if (o.precision == DMK_MIXED && tol < 1e-6 * (1 - 1e-9))
-            throw Error{DMK_ERR_PRECISION, "mixed precision needs tol >= 1e-6"};
-        if (o.leaf_max < 0 || o.max_depth < 0 || o.max_depth > 21) throw Error{DMK_ERR_ARG, "bad leaf_max/max_depth"};
-        auto *P = new Plan();
-        try {
-            P->precision = o.precision;
-            P->leaf_max = o.leaf_max ? o.leaf_max : 64;
-            P->max_depth = o.max_depth ? o.max_depth : 20;
-            P->flags = o.flags;
-            P->n = n;
-            build_tables(prm, &P->tab);
-            P->p = prm.p;
-            P->nf = prm.nf;
-            P->nw = prm.nw;
-            hipStream_t s = (hipStream_t)stream;
-            upload_tables(P, s);
-            build_tree(P, pts, s);
-            build_lists(P, s);
-            alloc_workspace(P);
-            count_work(P, s);
-            if (P->flags & DMK_FLAG_BATCHED) {
-                // default-priority streams only
-                DMK_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-                DMK_HIP(hipStreamCreateWithFlags(&P->side_stream, hipStreamNonBlocking));
-                DMK_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-                DMK_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
-            }
-        } catch (...) {
-            plan_release(P);
-            throw;
-        }
-        *out = reinterpret_cast<dmk_plan_t>(P);
+        if (n < 0) throw Error{DMK_ERR_ARG, "n must satisfy 0 <= n < 2^31"};
+        const int64_t off[2] = {0, n};
+        *out = make_plan(dim, kernel, tol, 1, off, pts, opts, stream);
+    });
+}
+
+dmk_status dmk_plan_batched(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *offsets,
+                            const double *pts, const dmk_opts *opts, void *stream, dmk_plan_t *out)
+{
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out) throw Error{DMK_ERR_ARG, "out is NULL"};
+        *out = make_plan(dim, kernel, tol, nprob, offsets, pts, opts, stream);
+    });
+}
+
+dmk_status dmk_problem_info(dmk_plan_t plan, int32_t prob, double *center, double *side)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (prob < 0 || prob >= P->nprob) throw Error{DMK_ERR_ARG, "problem index out of range"};
+        if (center)
+            for (int d = 0; d < P->dim; ++d) center[d] = P->pcenter[(size_t)P->dim * prob + d];
+        if (side) *side = P->pside[prob];
     });
 }
 
@@ -179,8 +243,10 @@ dmk_status dmk_plan_info(dmk_plan_t plan, dmk_plan_stats *st)
         st->nfin = P->nfin;
         st->npairs = P->npairs;
         st->device_bytes = P->device_bytes;
-        for (int d = 0; d < 3; ++d) st->center[d] = P->center[d];
+        for (int d = 0; d < P->dim; ++d) st->center[d] = P->center[d];
         st->side = P->side;
+        st->dim = P->dim;
+        st->nprob = P->nprob;
     });
 }
 
@@ -206,9 +272,10 @@ dmk_status dmk_export_tree(dmk_plan_t plan, int64_t *perm, int32_t *level, uint6
         cp32to64(P->pstart, nb, pstart);
         cp32to64(P->pcount, nb, pcount);
         if (flags) DMK_HIP(hipMemcpy(flags, P->bflags, nb, hipMemcpyDeviceToHost));
-        cp32to64(P->colleague, 27 * nb, colleague);
+        const int64_t ncol = (P->dim == 3) ? 27 : 9, nco = (1 << P->dim) - 1;
+        cp32to64(P->colleague, ncol * nb, colleague);
         if (ncoarse) DMK_HIP(hipMemcpy(ncoarse, P->ncoarse, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
-        cp32to64(P->coarse, 7 * nb, coarse);
+        cp32to64(P->coarse, nco * nb, coarse);
     });
 }
 
@@ -238,7 +305,7 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
         if (!plan || !out) throw Error{DMK_ERR_ARG, "NULL argument"};
         Plan *P = reinterpret_cast<Plan *>(plan);
         if (box < 0 || box >= P->nbox) throw Error{DMK_ERR_ARG, "box out of range"};
-        const int64_t p3 = (int64_t)P->p * P->p * P->p;
+        const int64_t p3 = (P->dim == 3) ? (int64_t)P->p * P->p * P->p : (int64_t)P->p * P->p;
         int32_t slot = -1;
         const double *base = nullptr;
         const void *vbase = nullptr;
@@ -271,10 +338,16 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
 {
     return guarded([&] {
         if (n < 0 || (n > 0 && !out)) throw Error{DMK_ERR_ARG, "bad n or out"};
+        const int dim = (what >= 6) ? 2 : 3;
         Params prm;
-        if (!params_for(tol, &prm)) throw Error{DMK_ERR_UNSUPPORTED, "tolerance not in the table"};
+        if (!params_for(tol, &prm, dim)) throw Error{DMK_ERR_UNSUPPORTED, "tolerance not in the table"};
         Tables t;
-        build_tables(prm, &t);
+        build_tables(prm, &t, dim);
+        if (what == 9) {
+            if (n < 4) throw Error{DMK_ERR_ARG, "n >= 4 needed"};
+            out[0] = t.m0; out[1] = prm.nw; out[2] = prm.hw; out[3] = t.gdeg;
+            return;
+        }
         if (what == 4) {
             if (n < 4) throw Error{DMK_ERR_ARG, "n >= 4 needed"};
             out[0] = t.psi0; out[1] = t.c0; out[2] = t.c2; out[3] = t.lambda0;
@@ -310,8 +383,26 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
                                                 : w[((size_t)m3 * nn + (m2 + nf)) * nn + (m1 + nf)];
                                 break;
                             }
+            } else if (what == 6 || what == 7) {
+                const int nf = (what == 6) ? t.nf : t.nw, nh = nf + 1;
+                const std::vector<double> &w = (what == 6) ? t.wd0 : t.ww;
+                long k2 = lround(x[i]);
+                for (int m2 = 0; m2 <= nf && std::isnan(v); ++m2)
+                    for (int m1 = -nf; m1 <= nf; ++m1)
+                        if ((long)(m1 * m1 + m2 * m2) == k2) {
+                            v = w[(size_t)(m1 + nf) * nh + m2];
+                            break;
+                        }
+            } else if (what == 8) {
+                double u = 2.0 * x[i] * x[i] - 1.0, b1 = 0.0, b2 = 0.0;
+                for (int k = t.gdeg; k >= 1; --k) {
+                    double b0 = t.gcheb[k] + 2.0 * u * b1 - b2;
+                    b2 = b1;
+                    b1 = b0;
+                }
+                v = t.gcheb[0] + u * b1 - b2;
             } else {
-                throw Error{DMK_ERR_ARG, "what must be 0..5"};
+                throw Error{DMK_ERR_ARG, "what must be 0..9"};
             }
             out[i] = v;
         }

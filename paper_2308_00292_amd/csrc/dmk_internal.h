@@ -37,11 +37,16 @@ struct Params {
     int nw;      // plane-wave half width of W_0
     double hw;   // plane-wave spacing of W_0 (root side 1)
 };
-bool params_for(double tol, Params *out);
+bool params_for(double tol, Params *out, int dim = 3);
 
-// Host-side tables, all FP64 (Step 1 of the algorithm).
+// Host-side tables, all FP64 (Step 1 of the algorithm).  In 2-D the
+// plane-wave arrays are [m1][m2] with m2 >= 0, the weights are those of the
+// log kernel's split (level-independent), and gcheb holds the smooth part m
+// of its residual as a series in 2 (r/s_l)^2 - 1.
 struct Tables {
     Params prm;
+    int dim = 3;
+    double m0 = 0.0;                       // 2-D: m(0), the r -> 0 value of the smooth part
     int p, nf, nn, nh, nw, nwn, nwh;
     double psi0, c0, c2, lambda0;
     std::vector<double> coef;              // PSWF Legendre coefficients (even k)
@@ -50,13 +55,13 @@ struct Tables {
     std::vector<double> c2p;               // [2][p][p] A_s[a][i] = l_a((x_i + s)/2)
     std::vector<double> epw;               // [nn][p][2] exp(-i pi m x_j / 3)
     std::vector<double> ew;                // [nwn][p][2] exp(-i hw m x_j / 2)
-    std::vector<double> wd0;               // [nn][nh][nn] D_0 weights, half spectrum, [m1][m3][m2]
-    std::vector<double> ww;                // [nwh][nwn][nwn] W_0 weights, [m3][m2][m1]
+    std::vector<double> wd0;               // 3-D [nn][nh][nn] D_0 weights, half spectrum, [m1][m3][m2]; 2-D [nn][nh]
+    std::vector<double> ww;                // 3-D [nwh][nwn][nwn] W_0 weights, [m3][m2][m1]; 2-D [nwn][nwh]
     std::vector<double> gcheb;             // Chebyshev coefficients of Phi(sqrt t)/sqrt t on [0,1]
     int gdeg;                              // degree kept for FP64 evaluation
     int gdeg32;                            // degree kept for FP32 evaluation
 };
-void build_tables(const Params &prm, Tables *t);
+void build_tables(const Params &prm, Tables *t, int dim = 3);
 
 // PSWF helpers exposed for the host-side self checks in the tests.
 double pswf_eval(const Tables &t, double x);  // any real x
@@ -70,10 +75,22 @@ struct LevelLists {
 struct Plan {
     // configuration
     int dim = 3, p = 0, nf = 0, nw = 0, precision = 0, leaf_max = 64, max_depth = 20;
+    int kernel = DMK_LAPLACE;
+    double lambda = 0.0;       // Yukawa parameter, input units
     uint64_t flags = 0;
     Tables tab;
     int64_t n = 0;
-    double center[3] = {0, 0, 0}, side = 1.0;
+    double center[3] = {0, 0, 0}, side = 1.0;  // root cube of problem 0
+
+    // independent problems (a forest: one tree per problem, boxes of all
+    // problems interleaved level by level); a single point set is nprob = 1
+    int32_t nprob = 1;
+    int kb = 21, pbits = 0;               // key bits per axis, problem-id bits
+    std::vector<int64_t> poff;            // host [nprob+1] point offsets
+    std::vector<double> pcenter, pside;   // host [nprob][dim], [nprob]
+    int64_t *d_poff = nullptr;            // device copies
+    double *d_pcenter = nullptr, *d_pside = nullptr;
+    int32_t *bprob = nullptr;             // [nbox] problem of each box
 
     // sorted points
     double *X = nullptr, *Y = nullptr, *Z = nullptr;
@@ -88,10 +105,10 @@ struct Plan {
     int32_t *blevel = nullptr, *parent = nullptr, *child0 = nullptr;
     int32_t *pstart = nullptr, *pcount = nullptr;
     uint8_t *bflags = nullptr;  // bit0 leaf, bit1 fout, bit2 fin, bit3 terminal
-    int32_t *colleague = nullptr;  // [nbox][27]
+    int32_t *colleague = nullptr;  // [nbox][3^dim]
     int32_t *anchor = nullptr;     // [nbox] nearest ancestor-or-self holding local values
-    int32_t *ncoarse = nullptr, *coarse = nullptr;  // [nbox], [nbox][7]
-    double *bcenter = nullptr;     // [nbox][3]
+    int32_t *ncoarse = nullptr, *coarse = nullptr;  // [nbox], [nbox][2^dim - 1]
+    double *bcenter = nullptr;     // [nbox][dim]
 
     // work lists (device, concatenated by level) and slot maps
     LevelLists ll;
@@ -101,11 +118,11 @@ struct Plan {
     int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
     int64_t nfout = 0, nfin = 0, nanc = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
     // sibling groups for the diagonal translation: per parent of F_in boxes,
-    // the Psi slots of its 8 children and the Phi slots of the 64 boxes of
-    // the 4x4x4 block around them (-1 where absent); the root forms a group
-    // of its own when it has F_in
-    int32_t *oct_dst = nullptr;    // [noct][8]
-    int32_t *oct_src = nullptr;    // [noct][64]
+    // the Psi slots of its 2^dim children and the Phi slots of the 4^dim
+    // boxes of the block around them (-1 where absent); a root with F_in
+    // forms a group of its own
+    int32_t *oct_dst = nullptr;    // [noct][2^dim]
+    int32_t *oct_src = nullptr;    // [noct][4^dim]
     int32_t *oct_level = nullptr;  // [noct] level of the children
     int64_t noct = 0;
 
@@ -164,6 +181,43 @@ void alloc_workspace(Plan *P);
 void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
               hipStream_t s);
 void count_work(Plan *P, hipStream_t s);
+void run_eval2(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
+               hipStream_t s);
+void alloc_workspace2(Plan *P);
 void stage_work(const Plan *P, double *flops, double *bytes);
+
+// Records HIP events around one stage launch when timing is enabled.
+struct StageScope {
+    Plan *P;
+    hipStream_t s;
+    int stage;
+    hipEvent_t a = nullptr;
+    hipEvent_t get()
+    {
+        if (!P->event_pool.empty()) {
+            hipEvent_t e = P->event_pool.back();
+            P->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        DMK_HIP(hipEventCreate(&e));
+        return e;
+    }
+    StageScope(Plan *p, hipStream_t st, int sg) : P(p), s(st), stage(sg)
+    {
+        if (P->timing) {
+            a = get();
+            DMK_HIP(hipEventRecord(a, s));
+        }
+    }
+    ~StageScope() noexcept(false)
+    {
+        if (P->timing) {
+            hipEvent_t b = get();
+            DMK_HIP(hipEventRecord(b, s));
+            P->pending.push_back({stage, a, b});
+        }
+    }
+};
 
 }  // namespace dmk

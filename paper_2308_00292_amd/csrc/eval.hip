@@ -1020,40 +1020,6 @@ void allow_lds(K kernel, size_t bytes)
 
 }  // namespace
 
-// Records HIP events around one stage launch when timing is enabled.
-struct StageScope {
-    Plan *P;
-    hipStream_t s;
-    int stage;
-    hipEvent_t a = nullptr;
-    hipEvent_t get()
-    {
-        if (!P->event_pool.empty()) {
-            hipEvent_t e = P->event_pool.back();
-            P->event_pool.pop_back();
-            return e;
-        }
-        hipEvent_t e;
-        DMK_HIP(hipEventCreate(&e));
-        return e;
-    }
-    StageScope(Plan *p, hipStream_t st, int sg) : P(p), s(st), stage(sg)
-    {
-        if (P->timing) {
-            a = get();
-            DMK_HIP(hipEventRecord(a, s));
-        }
-    }
-    ~StageScope() noexcept(false)
-    {
-        if (P->timing) {
-            hipEvent_t b = get();
-            DMK_HIP(hipEventRecord(b, s));
-            P->pending.push_back({stage, a, b});
-        }
-    }
-};
-
 // The stages between the charge gather and the final scatter.  They read and
 // write plan-owned buffers only, so the sequence can be captured into a HIP
 // graph once and replayed.  `side` (if not null) is a second stream on which
@@ -1180,6 +1146,10 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
 void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part, hipStream_t s)
 {
     if (P->n == 0) return;
+    if (P->dim == 2) {
+        run_eval2(P, charges, pot, far_part, near_part, s);
+        return;
+    }
     const bool f64 = P->precision == DMK_FP64;
     switch (P->p) {
     case 18:
@@ -1234,6 +1204,10 @@ void upload_tables(Plan *P, hipStream_t s)
 
 void alloc_workspace(Plan *P)
 {
+    if (P->dim == 2) {
+        alloc_workspace2(P);
+        return;
+    }
     const Tables &t = P->tab;
     const size_t el = (P->precision == DMK_FP64) ? sizeof(double) : sizeof(float);
     const int64_t p3 = (int64_t)t.p * t.p * t.p;
@@ -1265,12 +1239,12 @@ __global__ void __launch_bounds__(TPB) k_count_inrange(const double *X, const do
     const int nt = pcount[B];
     unsigned long long cnt = 0;
     for (int tt = threadIdx.x; tt < nt; tt += TPB) {
-        const double xt = X[t0 + tt], yt = Y[t0 + tt], zt = Z[t0 + tt];
+        const double xt = X[t0 + tt], yt = Y[t0 + tt], zt = Z ? Z[t0 + tt] : 0.0;
         for (int li = nl_off[blockIdx.x]; li < nl_off[blockIdx.x + 1]; ++li) {
             const int32_t T = nl_src[li];
             const double s = ldexp(1.0, -blevel[T]), s2 = s * s;
             for (int64_t j = pstart[T]; j < pstart[T] + pcount[T]; ++j) {
-                double dx = xt - X[j], dy = yt - Y[j], dz = zt - Z[j];
+                double dx = xt - X[j], dy = yt - Y[j], dz = Z ? zt - Z[j] : 0.0;
                 cnt += (dx * dx + dy * dy + dz * dz < s2) ? 1 : 0;
             }
         }
@@ -1288,25 +1262,27 @@ __global__ void __launch_bounds__(TPB) k_count_inrange(const double *X, const do
 void count_work(Plan *P, hipStream_t s)
 {
     const int64_t nb = P->nbox;
+    const int NC = 1 << P->dim, NCOL = (P->dim == 3) ? 27 : 9;
     std::vector<uint8_t> fl(nb);
     std::vector<int32_t> pc(nb), c0(nb), col;
     DMK_HIP(hipMemcpy(fl.data(), P->bflags, nb, hipMemcpyDeviceToHost));
     DMK_HIP(hipMemcpy(pc.data(), P->pcount, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
     DMK_HIP(hipMemcpy(c0.data(), P->child0, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
-    col.resize((size_t)nb * 27);
-    DMK_HIP(hipMemcpy(col.data(), P->colleague, (size_t)nb * 27 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    col.resize((size_t)nb * NCOL);
+    DMK_HIP(hipMemcpy(col.data(), P->colleague, (size_t)nb * NCOL * sizeof(int32_t), hipMemcpyDeviceToHost));
     P->n_anterp = P->n_merge = P->n_shift_pairs = 0;
-    if (nb > 0 && !(fl[0] & 2)) P->n_anterp += pc[0];  // a root leaf is anterpolated in the root stage
+    for (int r = 0; r < P->nprob && r < nb; ++r)
+        if (!(fl[r] & 2)) P->n_anterp += pc[r];  // a root leaf is anterpolated in the root stage
     for (int64_t b = 0; b < nb; ++b) {
         if (fl[b] & 2)
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < NC; ++k) {
                 int32_t c = c0[b] + k;
                 if (pc[c] == 0) continue;
                 if (fl[c] & 2) P->n_merge++; else P->n_anterp += pc[c];
             }
         if ((fl[b] & 4) && pc[b] > 0)
-            for (int k = 0; k < 27; ++k) {
-                int32_t j = col[(size_t)b * 27 + k];
+            for (int k = 0; k < NCOL; ++k) {
+                int32_t j = col[(size_t)b * NCOL + k];
                 if (j >= 0 && (fl[j] & 2)) P->n_shift_pairs++;
             }
     }
@@ -1331,12 +1307,36 @@ void stage_work(const Plan *P, double *F, double *Bt)
 {
     const Tables &t = P->tab;
     const double el = (P->precision == DMK_FP64) ? 8.0 : 4.0;
-    const double p = t.p, p3 = p * p * p, p4 = p3 * p, n = t.nn, nh = t.nh;
+    const double p = t.p, n = t.nn, nh = t.nh;
     const double N = (double)P->n;
-    const double pwflops = 4 * nh * p3 + 8 * nh * n * p * p + 8 * nh * n * n * p;  // one box, either direction
-    const double pwbytes = 2 * el * nh * n * n;                                      // one half spectrum
     for (int i = 0; i < DMK_NSTAGES; ++i) F[i] = Bt[i] = 0.0;
     Bt[DMK_STAGE_GATHER] = 20 * N;
+    Bt[DMK_STAGE_FINALIZE] = 28 * N;
+    const double gd = (double)((P->precision == DMK_FP64) ? t.gdeg : t.gdeg32);
+    if (P->dim == 2) {
+        const double p2 = p * p, p3 = p2 * p;
+        const double pwflops = 4 * nh * p2 + 8 * nh * n * p;  // one box, either direction
+        const double pwbytes = 2 * el * nh * n;
+        F[DMK_STAGE_UPWARD] = 2 * p2 * P->n_anterp + 4 * p3 * P->n_merge;
+        Bt[DMK_STAGE_UPWARD] = 24.0 * P->n_anterp + el * p2 * (P->n_merge + P->nfout);
+        const double nw = t.nwn, nwh = t.nwh;
+        F[DMK_STAGE_ROOT] = P->nprob * 2 * (4 * nwh * p2 + 8 * nwh * nw * p);
+        Bt[DMK_STAGE_ROOT] = 16 * p2 * P->nprob;
+        F[DMK_STAGE_PROXY2PW] = pwflops * P->nfout;
+        Bt[DMK_STAGE_PROXY2PW] = (el * p2 + pwbytes) * P->nfout;
+        F[DMK_STAGE_PWSHIFT] = 8 * nh * n * P->n_shift_pairs;
+        Bt[DMK_STAGE_PWSHIFT] = pwbytes * (P->nfout + P->nfin);
+        F[DMK_STAGE_PW2GRID] = pwflops * P->nfin + 4 * p3 * std::max<int64_t>(P->nanc - P->nprob, 0);
+        Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p2 * P->nanc;
+        F[DMK_STAGE_LEAF] = 2 * p2 * N;
+        Bt[DMK_STAGE_LEAF] = 32 * N + el * p2 * P->nleaf;
+        F[DMK_STAGE_RESIDUAL] = 6.0 * P->npairs + (2.0 * gd + 12.0) * P->npairs_in;
+        Bt[DMK_STAGE_RESIDUAL] = 32 * N;
+        return;
+    }
+    const double p3 = p * p * p, p4 = p3 * p;
+    const double pwflops = 4 * nh * p3 + 8 * nh * n * p * p + 8 * nh * n * n * p;  // one box, either direction
+    const double pwbytes = 2 * el * nh * n * n;                                      // one half spectrum
     F[DMK_STAGE_UPWARD] = 2 * p3 * P->n_anterp + 6 * p4 * P->n_merge;
     Bt[DMK_STAGE_UPWARD] = 32.0 * P->n_anterp + el * p3 * (P->n_merge + P->nfout);
     {
@@ -1353,9 +1353,8 @@ void stage_work(const Plan *P, double *F, double *Bt)
     Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p3 * P->nanc;
     F[DMK_STAGE_LEAF] = 2 * p3 * N;
     Bt[DMK_STAGE_LEAF] = 40 * N + el * p3 * P->nleaf;
-    F[DMK_STAGE_RESIDUAL] = 8.0 * P->npairs + (2.0 * (P->precision == DMK_FP64 ? t.gdeg : t.gdeg32) + 8.0) * P->npairs_in;
+    F[DMK_STAGE_RESIDUAL] = 8.0 * P->npairs + (2.0 * gd + 8.0) * P->npairs_in;
     Bt[DMK_STAGE_RESIDUAL] = 40 * N;
-    Bt[DMK_STAGE_FINALIZE] = 28 * N;
 }
 
 }  // namespace dmk

@@ -1,19 +1,26 @@
-// Step 0 of the discrete DMK algorithm (Sec. 3.6) on the GPU: root cube,
-// Morton keys, stable radix sort, the level-restricted adaptive octree
-// (Sec. 3.3), colleagues, coarse neighbours, the flags F_leaf/F_out/F_in,
-// per-level work lists and the residual interaction lists.
+// Step 0 of the discrete DMK algorithm (Sec. 3.6) on the GPU: root box,
+// Morton keys, stable radix sort, the level-restricted adaptive tree (Sec.
+// 3.3; octree in 3-D, quadtree in 2-D), colleagues, coarse neighbours, the
+// flags F_leaf/F_out/F_in, per-level work lists and the residual interaction
+// lists.
 //
-// Tree rules (each box refined into all 8 children):
+// Tree rules (each box refined into all 2^d children):
 //  (1) a box holding more than n_s points is refined (below the depth cap);
 //  (2) level restriction -- leaves sharing a boundary point differ by at most
 //      one level -- holds iff every refined box Q at level l has all its
 //      level-l neighbour regions present, i.e. their parents are refined.
 // The set of refined boxes is the smallest set closed under (1) and (2).  It
 // is computed by one sweep from the finest level upward: the refined boxes of
-// level l force the parents of their 27 neighbour regions at level l-1.
+// level l force the parents of their 3^d neighbour regions at level l-1.
 // Each box is identified by its Morton prefix; all lookups are binary
 // searches in sorted prefix arrays, so the result does not depend on
 // scheduling and is reproducible bit for bit.
+//
+// Several independent point sets (a batch of problems) form a forest: every
+// key carries the problem index above its Morton bits, so a box key at level
+// l is (problem << d l) | Morton prefix, level 0 holds one root per problem,
+// and neighbour searches never leave a problem.  Each problem has its own
+// root box from its own bounding box.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -25,8 +32,11 @@ namespace dmk {
 
 namespace {
 
-constexpr int KB = 21;  // key bits per dimension
 constexpr int TPB = 256;
+
+template <int D> struct Geo;
+template <> struct Geo<3> { static constexpr int NC = 8, NCOL = 27, NCO = 7, NRING = 64, KBMAX = 21; };
+template <> struct Geo<2> { static constexpr int NC = 4, NCOL = 9, NCO = 3, NRING = 16, KBMAX = 31; };
 
 __host__ __device__ inline uint64_t spread3(uint64_t v)
 {
@@ -51,17 +61,70 @@ __host__ __device__ inline uint64_t compact3(uint64_t v)
     return v;
 }
 
-// x is the most significant coordinate inside each 3-bit group
-__host__ __device__ inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z)
+__host__ __device__ inline uint64_t spread2(uint64_t v)
 {
-    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+    // bit b of v -> bit 2b
+    v &= 0xffffffffull;
+    v = (v | (v << 16)) & 0x0000ffff0000ffffull;
+    v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
+    v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
 }
 
-__host__ __device__ inline void unmorton(uint64_t k, int64_t *c)
+__host__ __device__ inline uint64_t compact2(uint64_t v)
 {
-    c[0] = (int64_t)compact3(k >> 2);
-    c[1] = (int64_t)compact3(k >> 1);
-    c[2] = (int64_t)compact3(k);
+    v &= 0x5555555555555555ull;
+    v = (v ^ (v >> 1)) & 0x3333333333333333ull;
+    v = (v ^ (v >> 2)) & 0x0f0f0f0f0f0f0f0full;
+    v = (v ^ (v >> 4)) & 0x00ff00ff00ff00ffull;
+    v = (v ^ (v >> 8)) & 0x0000ffff0000ffffull;
+    v = (v ^ (v >> 16)) & 0x00000000ffffffffull;
+    return v;
+}
+
+// Morton interleave; x is the most significant coordinate inside each group
+template <int D>
+__host__ __device__ inline uint64_t morton(const int64_t *c)
+{
+    if (D == 3) return (spread3((uint64_t)c[0]) << 2) | (spread3((uint64_t)c[1]) << 1) | spread3((uint64_t)c[2]);
+    return (spread2((uint64_t)c[0]) << 1) | spread2((uint64_t)c[1]);
+}
+
+// coordinates and problem of a box key at level l
+template <int D>
+__host__ __device__ inline void box_coords(uint64_t key, int l, int64_t *c)
+{
+    const uint64_t m = (l == 0) ? 0ull : (key & ((1ull << (D * l)) - 1ull));
+    if (D == 3) {
+        c[0] = (int64_t)compact3(m >> 2);
+        c[1] = (int64_t)compact3(m >> 1);
+        c[2] = (int64_t)compact3(m);
+    } else {
+        c[0] = (int64_t)compact2(m >> 1);
+        c[1] = (int64_t)compact2(m);
+    }
+}
+
+template <int D>
+__host__ __device__ inline uint64_t box_pid(uint64_t key, int l)
+{
+    return key >> (D * l);
+}
+
+template <int D>
+__host__ __device__ inline uint64_t box_key(uint64_t pid, int l, const int64_t *c)
+{
+    return (pid << (D * l)) | morton<D>(c);
+}
+
+// offset k of the 3^d neighbourhood, lexicographic (dx, dy[, dz]) from -1
+template <int D>
+__host__ __device__ inline void nbr_offset(int k, int64_t *d)
+{
+    if (D == 3) { d[0] = k / 9 - 1; d[1] = (k / 3) % 3 - 1; d[2] = k % 3 - 1; }
+    else { d[0] = k / 3 - 1; d[1] = k % 3 - 1; }
 }
 
 __device__ inline int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v)
@@ -81,14 +144,15 @@ __device__ inline int64_t find_u64(const uint64_t *a, int64_t n, uint64_t v)
 }
 
 // ---------------------------------------------------------------- kernels
+template <int D>
 __global__ void k_bbox_partial(const double *pts, int64_t n, double *part)
 {
     __shared__ double red[7][TPB];
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     double bad = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB)
-        for (int d = 0; d < 3; ++d) {
-            double v = pts[3 * i + d];
+        for (int d = 0; d < D; ++d) {
+            double v = pts[D * i + d];
             if (!isfinite(v)) bad = 1.0;
             mn[d] = fmin(mn[d], v);
             mx[d] = fmax(mx[d], v);
@@ -109,28 +173,69 @@ __global__ void k_bbox_partial(const double *pts, int64_t n, double *part)
     if (threadIdx.x < 7) part[blockIdx.x * 7 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// one block per problem: bounding box of its range [poff[b], poff[b+1])
+template <int D>
+__global__ void k_bbox_prob(const double *pts, const int64_t *poff, double *part)
+{
+    __shared__ double red[7][TPB];
+    const int64_t b = blockIdx.x, i0 = poff[b], i1 = poff[b + 1];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double bad = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += TPB)
+        for (int d = 0; d < D; ++d) {
+            double v = pts[D * i + d];
+            if (!isfinite(v)) bad = 1.0;
+            mn[d] = fmin(mn[d], v);
+            mx[d] = fmax(mx[d], v);
+        }
+    for (int d = 0; d < 3; ++d) { red[d][threadIdx.x] = mn[d]; red[3 + d][threadIdx.x] = mx[d]; }
+    red[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            for (int d = 0; d < 3; ++d) {
+                red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+                red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + s]);
+            }
+            red[6][threadIdx.x] = fmax(red[6][threadIdx.x], red[6][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[b * 7 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// point keys: problem index (binary search in poff) above the Morton bits of
+// floor((x' + 1/2) 2^kb) per axis, x' = (x - centre_b)/side_b
 #pragma clang fp contract(off)
-__global__ void k_keys(const double *pts, int64_t n, double cx, double cy, double cz, double side,
-                       double *xn, uint64_t *keys, int32_t *idx)
+template <int D>
+__global__ void k_keys(const double *pts, int64_t n, const int64_t *poff, int nprob, const double *pcenter,
+                       const double *pside, int kb, double *xn, uint64_t *keys, int32_t *idx)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= n) return;
-    const double scale = 2097152.0;  // 2^21
-    const double c[3] = {cx, cy, cz};
-    uint64_t k[3];
-    for (int d = 0; d < 3; ++d) {
-        double x = (pts[3 * i + d] - c[d]) / side;
+    int lo = 0, hi = nprob;  // last b with poff[b] <= i
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (poff[mid] <= i) lo = mid; else hi = mid;
+    }
+    const int b = lo;
+    const double scale = ldexp(1.0, kb);
+    const double side = pside[b];
+    int64_t k[3];
+    for (int d = 0; d < D; ++d) {
+        double x = (pts[D * i + d] - pcenter[D * b + d]) / side;
         xn[d * n + i] = x;
         double f = floor((x + 0.5) * scale);
         uint64_t kk = (f <= 0.0) ? 0ull : (uint64_t)f;
-        if (kk > (1ull << KB) - 1ull) kk = (1ull << KB) - 1ull;
-        k[d] = kk;
+        if (kk > (1ull << kb) - 1ull) kk = (1ull << kb) - 1ull;
+        k[d] = (int64_t)kk;
     }
-    keys[i] = morton(k[0], k[1], k[2]);
+    keys[i] = box_key<D>((uint64_t)b, kb, k);
     idx[i] = (int32_t)i;
 }
 #pragma clang fp contract(on)
 
+template <int D>
 __global__ void k_gather_points(const double *xn, const int32_t *perm, int64_t n, double *X, double *Y,
                                 double *Z)
 {
@@ -139,118 +244,131 @@ __global__ void k_gather_points(const double *xn, const int32_t *perm, int64_t n
     int64_t j = perm[i];
     X[i] = xn[j];
     Y[i] = xn[n + j];
-    Z[i] = xn[2 * n + j];
+    if (D == 3) Z[i] = xn[2 * n + j];
 }
 
 // children of the refined prefixes of one level
+template <int D>
 __global__ void k_children(const uint64_t *ref, int64_t m, uint64_t *out)
 {
+    constexpr int NC = Geo<D>::NC;
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (i >= 8 * m) return;
-    out[i] = (ref[i >> 3] << 3) | (uint64_t)(i & 7);
+    if (i >= NC * m) return;
+    out[i] = (ref[i / NC] << D) | (uint64_t)(i % NC);
 }
 
-__device__ inline void prefix_range(const uint64_t *keys, int64_t n, uint64_t P, int l, int64_t *lo,
+template <int D>
+__device__ inline void prefix_range(const uint64_t *keys, int64_t n, uint64_t P, int l, int kb, int64_t *lo,
                                     int64_t *hi)
 {
-    if (l == 0) { *lo = 0; *hi = n; return; }
-    int sh = 3 * (KB - l);
+    int sh = D * (kb - l);
     *lo = lower_bound_u64(keys, n, P << sh);
     *hi = lower_bound_u64(keys, n, (P + 1) << sh);
 }
 
-__global__ void k_refine_flag(const uint64_t *ex, int64_t m, int l, const uint64_t *keys, int64_t n,
+template <int D>
+__global__ void k_refine_flag(const uint64_t *ex, int64_t m, int l, int kb, const uint64_t *keys, int64_t n,
                               int ns, uint8_t *flag)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= m) return;
     int64_t a, b;
-    prefix_range(keys, n, ex[i], l, &a, &b);
+    prefix_range<D>(keys, n, ex[i], l, kb, &a, &b);
     flag[i] = (b - a > ns) ? 1 : 0;
 }
 
-// parents (level l-1) of the 27 level-l neighbour regions of each refined box
+// parents (level l-1) of the 3^d level-l neighbour regions of each refined box
+template <int D>
 __global__ void k_balance_cands(const uint64_t *ref, int64_t m, int l, uint64_t *out)
 {
+    constexpr int NCOL = Geo<D>::NCOL;
     int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (t >= 27 * m) return;
-    int64_t i = t / 27;
-    int k = (int)(t % 27);
-    int64_t c[3];
-    unmorton(ref[i], c);
-    int64_t d[3] = {k / 9 - 1, (k / 3) % 3 - 1, k % 3 - 1};
+    if (t >= NCOL * m) return;
+    int64_t i = t / NCOL;
+    int k = (int)(t % NCOL);
+    int64_t c[3], d[3], q[3];
+    box_coords<D>(ref[i], l, c);
+    const uint64_t pid = box_pid<D>(ref[i], l);
+    nbr_offset<D>(k, d);
     int64_t lim = (int64_t)1 << l;
     uint64_t res = ~0ull;
-    int64_t q[3];
     bool ok = true;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < D; ++a) {
         q[a] = c[a] + d[a];
         if (q[a] < 0 || q[a] >= lim) ok = false;
+        q[a] >>= 1;
     }
-    if (ok) res = morton((uint64_t)(q[0] >> 1), (uint64_t)(q[1] >> 1), (uint64_t)(q[2] >> 1));
+    if (ok) res = box_key<D>(pid, l - 1, q);
     out[t] = res;
 }
 
-__global__ void k_box_fill(int l, int64_t b0, int64_t nb, const uint64_t *bkey_all, int64_t prev0,
+template <int D>
+__global__ void k_box_fill(int l, int kb, int64_t b0, int64_t nb, const uint64_t *bkey_all, int64_t prev0,
                            int64_t nprev, int64_t next0, const uint64_t *ref, int64_t nref,
                            const uint64_t *keys, int64_t n, int ns, int32_t *blevel, int32_t *parent,
                            int32_t *child0, int32_t *pstart, int32_t *pcount, uint8_t *bflags,
-                           double *bcenter)
+                           double *bcenter, int32_t *bprob)
 {
+    constexpr int NC = Geo<D>::NC;
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= nb) return;
     int64_t b = b0 + i;
     uint64_t P = bkey_all[b];
     blevel[b] = l;
     int64_t a, e;
-    prefix_range(keys, n, P, l, &a, &e);
+    prefix_range<D>(keys, n, P, l, kb, &a, &e);
     pstart[b] = (int32_t)a;
     pcount[b] = (int32_t)(e - a);
     int64_t r = (nref > 0) ? find_u64(ref, nref, P) : -1;
     bool leaf = r < 0;
-    child0[b] = leaf ? -1 : (int32_t)(next0 + 8 * r);
-    parent[b] = (l == 0) ? -1 : (int32_t)(prev0 + find_u64(bkey_all + prev0, nprev, P >> 3));
+    child0[b] = leaf ? -1 : (int32_t)(next0 + NC * r);
+    parent[b] = (l == 0) ? -1 : (int32_t)(prev0 + find_u64(bkey_all + prev0, nprev, P >> D));
     uint8_t f = leaf ? 1 : 0;
     if (!leaf && (e - a) > ns) f |= 2;
     bflags[b] = f;
+    bprob[b] = (int32_t)box_pid<D>(P, l);
     int64_t c[3];
-    unmorton(P, c);
+    box_coords<D>(P, l, c);
     double s = ldexp(1.0, -l);
-    for (int d = 0; d < 3; ++d) bcenter[3 * b + d] = -0.5 + ((double)c[d] + 0.5) * s;
+    for (int d = 0; d < D; ++d) bcenter[D * b + d] = -0.5 + ((double)c[d] + 0.5) * s;
 }
 
+template <int D>
 __global__ void k_colleagues(int l, int64_t b0, int64_t nb, const uint64_t *bkey_all, int32_t *col)
 {
+    constexpr int NCOL = Geo<D>::NCOL;
     int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
-    if (t >= 27 * nb) return;
-    int64_t i = t / 27;
-    int k = (int)(t % 27);
-    int64_t c[3];
-    unmorton(bkey_all[b0 + i], c);
-    int64_t d[3] = {k / 9 - 1, (k / 3) % 3 - 1, k % 3 - 1};
+    if (t >= NCOL * nb) return;
+    int64_t i = t / NCOL;
+    int k = (int)(t % NCOL);
+    const uint64_t K = bkey_all[b0 + i];
+    int64_t c[3], d[3], q[3];
+    box_coords<D>(K, l, c);
+    nbr_offset<D>(k, d);
     int64_t lim = (int64_t)1 << l;
     int32_t res = -1;
-    int64_t q[3];
     bool ok = true;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < D; ++a) {
         q[a] = c[a] + d[a];
         if (q[a] < 0 || q[a] >= lim) ok = false;
     }
     if (ok) {
-        int64_t f = find_u64(bkey_all + b0, nb, morton((uint64_t)q[0], (uint64_t)q[1], (uint64_t)q[2]));
+        int64_t f = find_u64(bkey_all + b0, nb, box_key<D>(box_pid<D>(K, l), l, q));
         if (f >= 0) res = (int32_t)(b0 + f);
     }
-    col[(b0 + i) * 27 + k] = res;
+    col[(b0 + i) * NCOL + k] = res;
 }
 
+template <int D>
 __global__ void k_flags2(int64_t nbox, const int32_t *col, const int32_t *parent, uint8_t *bflags)
 {
+    constexpr int NCOL = Geo<D>::NCOL;
     int64_t b = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (b >= nbox) return;
     uint8_t f = bflags[b];
     bool fin = false;
-    for (int k = 0; k < 27; ++k) {
-        int32_t j = col[b * 27 + k];
+    for (int k = 0; k < NCOL; ++k) {
+        int32_t j = col[b * NCOL + k];
         if (j >= 0 && (bflags[j] & 2)) fin = true;
     }
     bool fout = f & 2;
@@ -260,41 +378,44 @@ __global__ void k_flags2(int64_t nbox, const int32_t *col, const int32_t *parent
     bflags[b] = f;  // bits 0-1 are only read by other threads, bits 2-3 only written here
 }
 
+template <int D>
 __global__ void k_coarse(int l, int64_t b0, int64_t nb, const uint64_t *bkey_all, int64_t prev0,
                          int64_t nprev, const uint8_t *bflags, int32_t *ncoarse, int32_t *coarse)
 {
+    constexpr int NCOL = Geo<D>::NCOL, NCO = Geo<D>::NCO;
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= nb) return;
     int64_t b = b0 + i;
     int cnt = 0;
-    int32_t found[7];
+    int32_t found[NCO];
     if (l > 0 && (bflags[b] & 1)) {
         uint64_t P = bkey_all[b];
-        int64_t c[3];
-        unmorton(P, c);
+        int64_t c[3], d[3], q[3];
+        box_coords<D>(P, l, c);
+        const uint64_t pid = box_pid<D>(P, l);
         int64_t lim = (int64_t)1 << l;
-        for (int k = 0; k < 27; ++k) {
-            int64_t d[3] = {k / 9 - 1, (k / 3) % 3 - 1, k % 3 - 1};
-            int64_t q[3];
+        for (int k = 0; k < NCOL; ++k) {
+            nbr_offset<D>(k, d);
             bool ok = true;
-            for (int a = 0; a < 3; ++a) {
+            for (int a = 0; a < D; ++a) {
                 q[a] = c[a] + d[a];
                 if (q[a] < 0 || q[a] >= lim) ok = false;
+                q[a] >>= 1;
             }
             if (!ok) continue;
-            uint64_t Q = morton((uint64_t)(q[0] >> 1), (uint64_t)(q[1] >> 1), (uint64_t)(q[2] >> 1));
-            if (Q == (P >> 3)) continue;
+            uint64_t Q = box_key<D>(pid, l - 1, q);
+            if (Q == (P >> D)) continue;
             int64_t f = find_u64(bkey_all + prev0, nprev, Q);
             if (f < 0) continue;
             int32_t j = (int32_t)(prev0 + f);
             if (!(bflags[j] & 1)) continue;
             bool dup = false;
             for (int m = 0; m < cnt; ++m) dup |= (found[m] == j);
-            if (!dup && cnt < 7) found[cnt++] = j;
+            if (!dup && cnt < NCO) found[cnt++] = j;
         }
     }
     ncoarse[b] = cnt;
-    for (int m = 0; m < 7; ++m) coarse[b * 7 + m] = (m < cnt) ? found[m] : -1;
+    for (int m = 0; m < NCO; ++m) coarse[b * NCO + m] = (m < cnt) ? found[m] : -1;
 }
 
 // ------------------------------------------------------------ small helpers
@@ -351,73 +472,102 @@ int64_t sort_unique(Scratch &S, uint64_t *in, int64_t n, uint64_t **out, hipStre
 
 }  // namespace
 
-void build_tree(Plan *P, const double *pts, hipStream_t s)
+template <int D>
+static void build_tree_t(Plan *P, const double *pts, hipStream_t s)
 {
+    constexpr int NC = Geo<D>::NC, NCOL = Geo<D>::NCOL, NCO = Geo<D>::NCO;
     const int64_t n = P->n;
+    const int nprob = P->nprob;
+    const int kb = P->kb;
     Scratch S;
-    // ---- root cube from the bounding box
-    double bb[7] = {0, 0, 0, 0, 0, 0, 0};
+    // ---- root box of each problem from its bounding box
+    std::vector<double> bbx(7 * (size_t)nprob, 0.0);
     if (n > 0) {
-        int nb = (int)std::min<int64_t>(1024, (n + TPB - 1) / TPB);
-        double *part = S.get<double>(7 * nb);
-        hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(TPB), 0, s, pts, n, part);
-        std::vector<double> h(7 * nb);
-        DMK_HIP(hipMemcpyAsync(h.data(), part, 7 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
-        DMK_HIP(hipStreamSynchronize(s));
-        for (int d = 0; d < 3; ++d) { bb[d] = h[d]; bb[3 + d] = h[3 + d]; }
-        for (int b = 0; b < nb; ++b) {
-            for (int d = 0; d < 3; ++d) {
-                bb[d] = std::min(bb[d], h[7 * b + d]);
-                bb[3 + d] = std::max(bb[3 + d], h[7 * b + 3 + d]);
+        if (nprob == 1) {
+            int nb = (int)std::min<int64_t>(1024, (n + TPB - 1) / TPB);
+            double *part = S.get<double>(7 * nb);
+            hipLaunchKernelGGL(k_bbox_partial<D>, dim3(nb), dim3(TPB), 0, s, pts, n, part);
+            std::vector<double> h(7 * nb);
+            DMK_HIP(hipMemcpyAsync(h.data(), part, 7 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+            DMK_HIP(hipStreamSynchronize(s));
+            for (int k = 0; k < 7; ++k) bbx[k] = h[k];
+            for (int b = 0; b < nb; ++b) {
+                for (int d = 0; d < 3; ++d) {
+                    bbx[d] = std::min(bbx[d], h[7 * b + d]);
+                    bbx[3 + d] = std::max(bbx[3 + d], h[7 * b + 3 + d]);
+                }
+                bbx[6] = std::max(bbx[6], h[7 * b + 6]);
             }
-            bb[6] = std::max(bb[6], h[7 * b + 6]);
+        } else {
+            double *part = S.get<double>(7 * (int64_t)nprob);
+            hipLaunchKernelGGL(k_bbox_prob<D>, dim3(nprob), dim3(TPB), 0, s, pts, P->d_poff, part);
+            DMK_HIP(hipMemcpyAsync(bbx.data(), part, 7 * (size_t)nprob * sizeof(double), hipMemcpyDeviceToHost, s));
+            DMK_HIP(hipStreamSynchronize(s));
         }
-        if (bb[6] != 0.0) throw Error{DMK_ERR_ARG, "non-finite point coordinate"};
+        for (int b = 0; b < nprob; ++b)
+            if (bbx[7 * b + 6] != 0.0) throw Error{DMK_ERR_ARG, "non-finite point coordinate"};
     }
-    double ext = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        P->center[d] = 0.5 * (bb[d] + bb[3 + d]);
-        if (bb[3 + d] - bb[d] > ext) ext = bb[3 + d] - bb[d];
+    P->pcenter.assign((size_t)nprob * D, 0.0);
+    P->pside.assign(nprob, 1.0);
+    for (int b = 0; b < nprob; ++b) {
+        double ext = 0.0;
+        const bool empty = P->poff[b + 1] == P->poff[b];
+        for (int d = 0; d < D; ++d) {
+            double lo = bbx[7 * b + d], hi = bbx[7 * b + 3 + d];
+            if (empty) lo = hi = 0.0;
+            P->pcenter[(size_t)D * b + d] = 0.5 * (lo + hi);
+            if (hi - lo > ext) ext = hi - lo;
+        }
+        P->pside[b] = (ext > 0.0) ? ext * (1.0 + std::ldexp(1.0, -40)) : 1.0;
     }
-    P->side = (ext > 0.0) ? ext * (1.0 + std::ldexp(1.0, -40)) : 1.0;
+    for (int d = 0; d < D; ++d) P->center[d] = P->pcenter[d];
+    P->side = P->pside[0];
+    P->d_pcenter = talloc<double>(P, (int64_t)nprob * D);
+    P->d_pside = talloc<double>(P, nprob);
+    DMK_HIP(hipMemcpyAsync(P->d_pcenter, P->pcenter.data(), (size_t)nprob * D * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+    DMK_HIP(hipMemcpyAsync(P->d_pside, P->pside.data(), (size_t)nprob * sizeof(double), hipMemcpyHostToDevice, s));
 
     // ---- keys, sort, sorted coordinates
     P->X = talloc<double>(P, n);
     P->Y = talloc<double>(P, n);
-    P->Z = talloc<double>(P, n);
+    P->Z = (D == 3) ? talloc<double>(P, n) : nullptr;
     P->perm = talloc<int32_t>(P, n);
     P->keys = talloc<uint64_t>(P, n);
     if (n > 0) {
-        double *xn = S.get<double>(3 * n);
+        double *xn = S.get<double>(D * n);
         uint64_t *k0 = S.get<uint64_t>(n);
         int32_t *i0 = S.get<int32_t>(n);
-        hipLaunchKernelGGL(k_keys, dim3(nblk(n)), dim3(TPB), 0, s, pts, n, P->center[0], P->center[1],
-                           P->center[2], P->side, xn, k0, i0);
+        hipLaunchKernelGGL(k_keys<D>, dim3(nblk(n)), dim3(TPB), 0, s, pts, n, P->d_poff, nprob, P->d_pcenter,
+                           P->d_pside, kb, xn, k0, i0);
+        const int endbit = D * kb + P->pbits;
         size_t tb = 0;
-        DMK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, P->keys, i0, P->perm, (int)n, 0, 63, s));
+        DMK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, P->keys, i0, P->perm, (int)n, 0, endbit, s));
         void *tmp = S.get<char>((int64_t)tb);
-        DMK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, P->keys, i0, P->perm, (int)n, 0, 63, s));
-        hipLaunchKernelGGL(k_gather_points, dim3(nblk(n)), dim3(TPB), 0, s, xn, P->perm, n, P->X, P->Y, P->Z);
+        DMK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, P->keys, i0, P->perm, (int)n, 0, endbit, s));
+        hipLaunchKernelGGL(k_gather_points<D>, dim3(nblk(n)), dim3(TPB), 0, s, xn, P->perm, n, P->X, P->Y, P->Z);
     }
 
-    // ---- refinement by count
+    // ---- refinement by count (level 0: one root per problem)
     const int maxd = P->max_depth;
     std::vector<uint64_t *> ref(maxd + 2, nullptr);
     std::vector<int64_t> nref(maxd + 2, 0);
-    uint64_t *ex = S.get<uint64_t>(1);
+    uint64_t *ex = S.get<uint64_t>(nprob);
     {
-        uint64_t zero = 0;
-        DMK_HIP(hipMemcpyAsync(ex, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        std::vector<uint64_t> roots(nprob);
+        for (int b = 0; b < nprob; ++b) roots[b] = (uint64_t)b;
+        DMK_HIP(hipMemcpyAsync(ex, roots.data(), nprob * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        DMK_HIP(hipStreamSynchronize(s));
     }
-    int64_t nex = 1;
+    int64_t nex = nprob;
     for (int l = 0; l < maxd && n > 0; ++l) {
         if (l > 0) {
-            nex = 8 * nref[l - 1];
+            nex = NC * nref[l - 1];
             ex = S.get<uint64_t>(nex);
-            hipLaunchKernelGGL(k_children, dim3(nblk(nex)), dim3(TPB), 0, s, ref[l - 1], nref[l - 1], ex);
+            hipLaunchKernelGGL(k_children<D>, dim3(nblk(nex)), dim3(TPB), 0, s, ref[l - 1], nref[l - 1], ex);
         }
         uint8_t *flag = S.get<uint8_t>(nex);
-        hipLaunchKernelGGL(k_refine_flag, dim3(nblk(nex)), dim3(TPB), 0, s, ex, nex, l, P->keys, n,
+        hipLaunchKernelGGL(k_refine_flag<D>, dim3(nblk(nex)), dim3(TPB), 0, s, ex, nex, l, kb, P->keys, n,
                            P->leaf_max, flag);
         uint64_t *sel = S.get<uint64_t>(nex);
         int64_t *cnt = S.get<int64_t>(1);
@@ -438,9 +588,9 @@ void build_tree(Plan *P, const double *pts, hipStream_t s)
         if (nref[l] > 0) lmax = l;
     for (int l = lmax; l >= 1; --l) {
         if (nref[l] == 0) continue;
-        int64_t nc = 27 * nref[l];
+        int64_t nc = NCOL * nref[l];
         uint64_t *cand = S.get<uint64_t>(nc + nref[l - 1]);
-        hipLaunchKernelGGL(k_balance_cands, dim3(nblk(nc)), dim3(TPB), 0, s, ref[l], nref[l], l, cand);
+        hipLaunchKernelGGL(k_balance_cands<D>, dim3(nblk(nc)), dim3(TPB), 0, s, ref[l], nref[l], l, cand);
         if (nref[l - 1] > 0)
             DMK_HIP(hipMemcpyAsync(cand + nc, ref[l - 1], nref[l - 1] * sizeof(uint64_t),
                                    hipMemcpyDeviceToDevice, s));
@@ -453,10 +603,10 @@ void build_tree(Plan *P, const double *pts, hipStream_t s)
     // ---- materialise boxes level by level
     std::vector<int64_t> lstart(1, 0);
     std::vector<int64_t> cnts;
-    cnts.push_back(1);
+    cnts.push_back(nprob);
     for (int l = 1; l <= maxd; ++l) {
         if (nref[l - 1] == 0) break;
-        cnts.push_back(8 * nref[l - 1]);
+        cnts.push_back(NC * nref[l - 1]);
     }
     P->nlevels = (int)cnts.size();
     for (int64_t c : cnts) lstart.push_back(lstart.back() + c);
@@ -470,36 +620,45 @@ void build_tree(Plan *P, const double *pts, hipStream_t s)
     P->pstart = talloc<int32_t>(P, nbox);
     P->pcount = talloc<int32_t>(P, nbox);
     P->bflags = talloc<uint8_t>(P, nbox);
-    P->colleague = talloc<int32_t>(P, 27 * nbox);
+    P->bprob = talloc<int32_t>(P, nbox);
+    P->colleague = talloc<int32_t>(P, NCOL * nbox);
     P->ncoarse = talloc<int32_t>(P, nbox);
-    P->coarse = talloc<int32_t>(P, 7 * nbox);
-    P->bcenter = talloc<double>(P, 3 * nbox);
+    P->coarse = talloc<int32_t>(P, NCO * nbox);
+    P->bcenter = talloc<double>(P, D * nbox);
     {
-        uint64_t zero = 0;
-        DMK_HIP(hipMemcpyAsync(P->bkey, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        std::vector<uint64_t> roots(nprob);
+        for (int b = 0; b < nprob; ++b) roots[b] = (uint64_t)b;
+        DMK_HIP(hipMemcpyAsync(P->bkey, roots.data(), nprob * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        DMK_HIP(hipStreamSynchronize(s));
     }
     for (int l = 1; l < P->nlevels; ++l)
-        hipLaunchKernelGGL(k_children, dim3(nblk(cnts[l])), dim3(TPB), 0, s, ref[l - 1], nref[l - 1],
+        hipLaunchKernelGGL(k_children<D>, dim3(nblk(cnts[l])), dim3(TPB), 0, s, ref[l - 1], nref[l - 1],
                            P->bkey + lstart[l]);
     for (int l = 0; l < P->nlevels; ++l) {
         int64_t prev0 = (l > 0) ? lstart[l - 1] : 0, nprev = (l > 0) ? cnts[l - 1] : 0;
         int64_t next0 = lstart[l + 1];
-        hipLaunchKernelGGL(k_box_fill, dim3(nblk(cnts[l])), dim3(TPB), 0, s, l, lstart[l], cnts[l], P->bkey,
+        hipLaunchKernelGGL(k_box_fill<D>, dim3(nblk(cnts[l])), dim3(TPB), 0, s, l, kb, lstart[l], cnts[l], P->bkey,
                            prev0, nprev, next0, ref[l], (l < maxd) ? nref[l] : (int64_t)0, P->keys, n,
                            P->leaf_max, P->blevel, P->parent, P->child0, P->pstart, P->pcount, P->bflags,
-                           P->bcenter);
+                           P->bcenter, P->bprob);
     }
     for (int l = 0; l < P->nlevels; ++l)
-        hipLaunchKernelGGL(k_colleagues, dim3(nblk(27 * cnts[l])), dim3(TPB), 0, s, l, lstart[l], cnts[l],
+        hipLaunchKernelGGL(k_colleagues<D>, dim3(nblk(NCOL * cnts[l])), dim3(TPB), 0, s, l, lstart[l], cnts[l],
                            P->bkey, P->colleague);
-    hipLaunchKernelGGL(k_flags2, dim3(nblk(nbox)), dim3(TPB), 0, s, nbox, P->colleague, P->parent, P->bflags);
+    hipLaunchKernelGGL(k_flags2<D>, dim3(nblk(nbox)), dim3(TPB), 0, s, nbox, P->colleague, P->parent, P->bflags);
     for (int l = 0; l < P->nlevels; ++l) {
         int64_t prev0 = (l > 0) ? lstart[l - 1] : 0, nprev = (l > 0) ? cnts[l - 1] : 0;
-        hipLaunchKernelGGL(k_coarse, dim3(nblk(cnts[l])), dim3(TPB), 0, s, l, lstart[l], cnts[l], P->bkey,
+        hipLaunchKernelGGL(k_coarse<D>, dim3(nblk(cnts[l])), dim3(TPB), 0, s, l, lstart[l], cnts[l], P->bkey,
                            prev0, nprev, P->bflags, P->ncoarse, P->coarse);
     }
     DMK_HIP(hipGetLastError());
     DMK_HIP(hipStreamSynchronize(s));
+}
+
+void build_tree(Plan *P, const double *pts, hipStream_t s)
+{
+    if (P->dim == 3) build_tree_t<3>(P, pts, s);
+    else build_tree_t<2>(P, pts, s);
 }
 
 // ------------------------------------------------------------------ lists
@@ -552,6 +711,12 @@ __global__ void k_slots(const int32_t *list, int64_t m, int32_t *slot)
     if (i < m) slot[list[i]] = (int32_t)i;
 }
 
+__global__ void k_nonempty(const int32_t *pcount, int64_t m, uint8_t *flag)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i < m) flag[i] = pcount[i] > 0 ? 1 : 0;
+}
+
 // parents of the non-empty F_in boxes of levels >= 1
 __global__ void k_oct_flag(const int32_t *fin, int64_t m, const int32_t *parent, uint8_t *flag)
 {
@@ -561,33 +726,36 @@ __global__ void k_oct_flag(const int32_t *fin, int64_t m, const int32_t *parent,
     if (P >= 0) flag[P] = 1;
 }
 
-// sibling group of parent P: child k = (x y z bits) sits at cell k + (1,1,1)
-// of the 4x4x4 block; cell g holds child ((g+1) & 1) of P's colleague at
+// sibling group of parent P: child k (bits x y [z]) sits at cell k + (1,..,1)
+// of the 4^d block; cell g holds child ((g+1) & 1) of P's colleague at
 // offset (g+1)/2 - 1 per axis
+template <int D>
 __global__ void k_oct_fill(const int32_t *octs, int64_t m, const int32_t *child0, const int32_t *col,
                            const uint8_t *bflags, const int32_t *blevel, const int32_t *proxy_slot,
                            const int32_t *psi_slot, int32_t *dst, int32_t *src, int32_t *lev)
 {
+    constexpr int NC = Geo<D>::NC, NCOL = Geo<D>::NCOL, NR = Geo<D>::NRING;
     int64_t i = blockIdx.x;
     if (i >= m) return;
     const int32_t P = octs[i];
     const int t = threadIdx.x;
-    if (t < 8) dst[i * 8 + t] = psi_slot[child0[P] + t];
+    if (t < NC) dst[i * NC + t] = psi_slot[child0[P] + t];
     if (t == 0) lev[i] = blevel[P] + 1;
-    if (t < 64) {
-        const int g[3] = {t / 16, (t / 4) % 4, t % 4};
-        int k = 0, c = 0;
-        for (int a = 0; a < 3; ++a) {
+    if (t < NR) {
+        int k = 0, c = 0, r = t;
+        int g[3];
+        for (int a = D - 1; a >= 0; --a) { g[a] = r % 4; r /= 4; }
+        for (int a = 0; a < D; ++a) {
             k = 3 * k + (g[a] + 1) / 2;      // colleague offset + 1
             c = 2 * c + ((g[a] + 1) & 1);   // child bit
         }
-        int32_t C = col[(int64_t)P * 27 + k];
+        int32_t C = col[(int64_t)P * NCOL + k];
         int32_t v = -1;
         if (C >= 0 && child0[C] >= 0) {
             int32_t S = child0[C] + c;
             if (bflags[S] & 2) v = proxy_slot[S];
         }
-        src[i * 64 + t] = v;
+        src[i * NR + t] = v;
     }
 }
 
@@ -604,12 +772,13 @@ __global__ void k_anchor(int64_t b0, int64_t nb, const int32_t *parent, const ui
 // residual lists, gather form: for target leaf B, the terminal non-empty
 // boxes among (a) the colleagues of B and of each of its ancestors and
 // (b) the leaves one level finer that share a boundary point with B.
-template <bool FILL>
+template <int D, bool FILL>
 __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t *lstart_dev, int nlevels,
                              const uint64_t *bkey, const int32_t *blevel, const int32_t *parent,
                              const int32_t *col, const uint8_t *bflags, const int32_t *pcount,
                              int32_t *count, const int32_t *off, int32_t *src, int32_t *pre, int64_t *pairs)
 {
+    constexpr int NCOL = Geo<D>::NCOL, NR = Geo<D>::NRING;
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= nleaf) return;
     int32_t B = leaves[i];
@@ -618,8 +787,8 @@ __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t
     int32_t base = FILL ? off[i] : 0;
     // pre: running count of source points before each entry (FILL pass)
     for (int32_t A = B; A >= 0; A = parent[A])
-        for (int k = 0; k < 27; ++k) {
-            int32_t T = col[(int64_t)A * 27 + k];
+        for (int k = 0; k < NCOL; ++k) {
+            int32_t T = col[(int64_t)A * NCOL + k];
             if (T >= 0 && (bflags[T] & 8) && pcount[T] > 0) {
                 if (FILL) { src[base + cnt] = T; pre[base + i + cnt] = (int32_t)pr; }
                 cnt++;
@@ -629,21 +798,23 @@ __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t
     int l = blevel[B];
     if (l + 1 < nlevels) {
         int64_t c[3];
-        unmorton(bkey[B], c);
+        box_coords<D>(bkey[B], l, c);
+        const uint64_t pid = box_pid<D>(bkey[B], l);
         int64_t lim = (int64_t)1 << (l + 1);
         int64_t n1 = lstart_dev[l + 2] - lstart_dev[l + 1];
         const uint64_t *k1 = bkey + lstart_dev[l + 1];
-        for (int r = 0; r < 64; ++r) {
-            int64_t o[3] = {r / 16 - 1, (r / 4) % 4 - 1, r % 4 - 1};
+        for (int r = 0; r < NR; ++r) {
+            int64_t o[3], q[3];
+            int rr = r;
+            for (int a = D - 1; a >= 0; --a) { o[a] = rr % 4 - 1; rr /= 4; }
             bool own = true, ok = true;
-            int64_t q[3];
-            for (int a = 0; a < 3; ++a) {
+            for (int a = 0; a < D; ++a) {
                 if (o[a] < 0 || o[a] > 1) own = false;
                 q[a] = 2 * c[a] + o[a];
                 if (q[a] < 0 || q[a] >= lim) ok = false;
             }
             if (own || !ok) continue;
-            int64_t f = find_u64(k1, n1, morton((uint64_t)q[0], (uint64_t)q[1], (uint64_t)q[2]));
+            int64_t f = find_u64(k1, n1, box_key<D>(pid, l + 1, q));
             if (f < 0) continue;
             int32_t T = (int32_t)(lstart_dev[l + 1] + f);
             if ((bflags[T] & 1) && (bflags[T] & 8) && pcount[T] > 0) {
@@ -678,8 +849,10 @@ int64_t select_indices(Scratch &S, const uint8_t *flag, int64_t first, int64_t c
 
 }  // namespace
 
-void build_lists(Plan *P, hipStream_t s)
+template <int D>
+static void build_lists_t(Plan *P, hipStream_t s)
 {
+    constexpr int NC = Geo<D>::NC, NR = Geo<D>::NRING;
     Scratch S;
     const int64_t nbox = P->nbox;
     const int L = P->nlevels;
@@ -688,7 +861,7 @@ void build_lists(Plan *P, hipStream_t s)
                        f_leaf);
     P->l_fout = talloc<int32_t>(P, nbox);
     P->l_fin = talloc<int32_t>(P, nbox);
-    P->l_anc = talloc<int32_t>(P, nbox + 1);
+    P->l_anc = talloc<int32_t>(P, nbox + P->nprob);
     P->l_leaf = talloc<int32_t>(P, nbox);
     P->anchor = talloc<int32_t>(P, nbox);
     auto &ll = P->ll;
@@ -703,12 +876,13 @@ void build_lists(Plan *P, hipStream_t s)
         ll.leaf_off[l + 1] = ll.leaf_off[l] + select_indices(S, f_leaf, b0, nb, P->l_leaf + ll.leaf_off[l], s);
         hipLaunchKernelGGL(k_anchor, dim3(nblk(nb)), dim3(TPB), 0, s, b0, nb, P->parent, f_fin, P->anchor);
     }
-    // anchors: the root, then the non-empty F_in boxes of levels >= 1
+    // anchors: the roots holding points, then the non-empty F_in boxes of
+    // levels >= 1
     {
-        int32_t zero = 0;
-        DMK_HIP(hipMemcpyAsync(P->l_anc, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
+        uint8_t *f_root = S.get<uint8_t>(P->nprob);
+        hipLaunchKernelGGL(k_nonempty, dim3(nblk(P->nprob)), dim3(TPB), 0, s, P->pcount, (int64_t)P->nprob, f_root);
         ll.anc_off[0] = 0;
-        ll.anc_off[1] = (P->n > 0) ? 1 : 0;
+        ll.anc_off[1] = select_indices(S, f_root, 0, P->nprob, P->l_anc, s);
         for (int l = 1; l < L; ++l) {
             int64_t m = ll.fin_off[l + 1] - ll.fin_off[l];
             if (m)
@@ -740,7 +914,7 @@ void build_lists(Plan *P, hipStream_t s)
     if (P->nfin)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfin)), dim3(TPB), 0, s, P->l_fin, P->nfin, P->psi_slot);
 
-    // sibling groups for the diagonal translation (the root first, then the
+    // sibling groups for the diagonal translation (the roots first, then the
     // parents level by level)
     {
         uint8_t *f_oct = S.get<uint8_t>(nbox);
@@ -749,32 +923,35 @@ void build_lists(Plan *P, hipStream_t s)
             hipLaunchKernelGGL(k_oct_flag, dim3(nblk(P->nfin)), dim3(TPB), 0, s, P->l_fin, P->nfin, P->parent, f_oct);
         int32_t *octs = S.get<int32_t>(nbox + 1);
         int64_t m = select_indices(S, f_oct, 0, nbox, octs, s);
-        int32_t root_psi = -1, root_phi = -1;
-        if (nbox > 0) {
-            DMK_HIP(hipMemcpyAsync(&root_psi, P->psi_slot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            DMK_HIP(hipMemcpyAsync(&root_phi, P->proxy_slot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            DMK_HIP(hipStreamSynchronize(s));
+        // roots with F_in: the root's only colleague is itself
+        const int np = P->nprob;
+        std::vector<int32_t> rpsi(np), rphi(np);
+        DMK_HIP(hipMemcpyAsync(rpsi.data(), P->psi_slot, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DMK_HIP(hipMemcpyAsync(rphi.data(), P->proxy_slot, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        DMK_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> hd, hs, hl;
+        int root_cell = (D == 3) ? 21 : 5;  // cell (1,..,1)
+        for (int b = 0; b < np; ++b) {
+            if (rpsi[b] < 0) continue;
+            for (int k = 0; k < NC; ++k) hd.push_back(k == 0 ? rpsi[b] : -1);
+            for (int k = 0; k < NR; ++k) hs.push_back(k == root_cell ? rphi[b] : -1);
+            hl.push_back(0);
         }
-        const int64_t r = (root_psi >= 0) ? 1 : 0;
+        const int64_t r = (int64_t)hl.size();
         P->noct = m + r;
-        P->oct_dst = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * 8);
-        P->oct_src = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * 64);
+        P->oct_dst = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * NC);
+        P->oct_src = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * NR);
         P->oct_level = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1));
         if (r) {
-            // the root's only colleague is itself: target cell (1,1,1) = 21
-            std::vector<int32_t> d(8, -1), g(64, -1);
-            d[0] = root_psi;
-            g[21] = root_phi;
-            int32_t l0 = 0;
-            DMK_HIP(hipMemcpyAsync(P->oct_dst, d.data(), 8 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            DMK_HIP(hipMemcpyAsync(P->oct_src, g.data(), 64 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            DMK_HIP(hipMemcpyAsync(P->oct_level, &l0, sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipMemcpyAsync(P->oct_dst, hd.data(), hd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipMemcpyAsync(P->oct_src, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipMemcpyAsync(P->oct_level, hl.data(), hl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
             DMK_HIP(hipStreamSynchronize(s));
         }
         if (m)
-            hipLaunchKernelGGL(k_oct_fill, dim3((unsigned)m), dim3(64), 0, s, octs, m, P->child0, P->colleague,
-                               P->bflags, P->blevel, P->proxy_slot, P->psi_slot, P->oct_dst + 8 * r,
-                               P->oct_src + 64 * r, P->oct_level + r);
+            hipLaunchKernelGGL(k_oct_fill<D>, dim3((unsigned)m), dim3(64), 0, s, octs, m, P->child0, P->colleague,
+                               P->bflags, P->blevel, P->proxy_slot, P->psi_slot, P->oct_dst + NC * r,
+                               P->oct_src + NR * r, P->oct_level + r);
     }
 
     // targets grouped by the anchor of their leaf (leaf evaluation)
@@ -822,7 +999,7 @@ void build_lists(Plan *P, hipStream_t s)
     if (nleaf > 0) {
         int32_t *cnt = S.get<int32_t>(nleaf);
         int64_t *pairs = S.get<int64_t>(nleaf);
-        hipLaunchKernelGGL(k_near_lists<false>, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
+        hipLaunchKernelGGL((k_near_lists<D, false>), dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
                            P->blevel, P->parent, P->colleague, P->bflags, P->pcount, cnt, (const int32_t *)nullptr,
                            (int32_t *)nullptr, (int32_t *)nullptr, pairs);
         size_t tb = 0;
@@ -857,7 +1034,7 @@ void build_lists(Plan *P, hipStream_t s)
         P->nl_total = total;
         P->nl_src = talloc<int32_t>(P, total);
         P->nl_pre = talloc<int32_t>(P, total + nleaf);
-        hipLaunchKernelGGL(k_near_lists<true>, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
+        hipLaunchKernelGGL((k_near_lists<D, true>), dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
                            P->blevel, P->parent, P->colleague, P->bflags, P->pcount, (int32_t *)nullptr,
                            (const int32_t *)P->nl_off, P->nl_src, P->nl_pre, (int64_t *)nullptr);
     } else {
@@ -867,6 +1044,12 @@ void build_lists(Plan *P, hipStream_t s)
     }
     DMK_HIP(hipGetLastError());
     DMK_HIP(hipStreamSynchronize(s));
+}
+
+void build_lists(Plan *P, hipStream_t s)
+{
+    if (P->dim == 3) build_lists_t<3>(P, s);
+    else build_lists_t<2>(P, s);
 }
 
 }  // namespace dmk

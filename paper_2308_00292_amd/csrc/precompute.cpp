@@ -27,7 +27,7 @@
 
 namespace dmk {
 
-bool params_for(double tol, Params *out)
+bool params_for(double tol, Params *out, int dim)
 {
     // Table 1 (c, N_1 = 2 nf + 1, p) plus a 1e-5 row (c = log(1/eps)).
     struct Row { double tol, c; int nf, p; };
@@ -44,9 +44,9 @@ bool params_for(double tol, Params *out)
             out->c = r.c;
             out->nf = r.nf;
             out->p = r.p;
-            // W_0 lives on r <= A + 1 (A = 1 + sqrt 3); offsets inside the unit
-            // box are <= 1 per axis, so the period 2 pi/hw must reach 3 + sqrt 3.
-            out->hw = 2.0 * M_PI / (3.0 + std::sqrt(3.0));
+            // W_0 lives on r <= A + 1 (A = 1 + sqrt d); offsets inside the unit
+            // box are <= 1 per axis, so the period 2 pi/hw must reach 3 + sqrt d.
+            out->hw = 2.0 * M_PI / (3.0 + std::sqrt((double)dim));
             out->nw = (int)std::ceil(out->c / out->hw);
             return true;
         }
@@ -190,9 +190,12 @@ double pswf_eval(const Tables &t, double x)
     return 2.0 * s / t.lambda0;
 }
 
-void build_tables(const Params &prm, Tables *t)
+void build_tables2(Tables *t);
+
+void build_tables(const Params &prm, Tables *t, int dim)
 {
     t->prm = prm;
+    t->dim = dim;
     const double c = prm.c;
     // ---- PSWF ground state in the even normalised-Legendre basis
     const int K = 48;
@@ -267,6 +270,10 @@ void build_tables(const Params &prm, Tables *t)
             t->ew[((size_t)(m + prm.nw) * p + j) * 2 + 1] = std::sin(ph);
         }
 
+    if (dim == 2) {
+        build_tables2(t);
+        return;
+    }
     // ---- plane-wave weights of D_0 (level l multiplies by 2^l), half spectrum
     // w_0(m) = [psi(pi|m|/(3c)) - psi(2pi|m|/(3c))] / (3 pi psi(0) |m|^2),
     // w_0(0) = pi c_2 / (18 c_0)
@@ -330,6 +337,117 @@ void build_tables(const Params &prm, Tables *t)
         int deg32 = deg;
         while (deg32 > 0 && std::fabs(cf[deg32]) < 1e-7 * std::fabs(cf[0])) deg32--;
         t->gdeg32 = deg32;
+    }
+}
+
+// ---------------------------------------------------------------- 2-D
+// Kernel -log(r)/(2 pi), split in Fourier space (Sec. 4.4): its transform
+// 1/k^2 times the mollifier psi(k s_l/c)/psi(0).
+//  * D_l weights (h_l/2pi)^2 Dhat_l(h_l |m|), h_l s_l = 2 pi/3:
+//      w(m) = [psi(pi|m|/(3c)) - psi(2pi|m|/(3c))] / (4 pi^2 psi(0) |m|^2),
+//      w(0) = c_2/(24 c_0) (the k -> 0 limit), the same at every level
+//      (scale invariance of the log kernel up to a constant).
+//  * W_0 weights (hw/2pi)^2 psi(k/c)/psi(0) That(k), That the transform of the
+//    kernel cut at A = 1 + sqrt 2 (Sec. 4.5):
+//      That(k) = (1 - J_0(kA))/k^2 - A log(A) J_1(kA)/k, That(0) = A^2/4 - A^2 log(A)/2.
+//  * The residual R_l(r) = -log(x)/(2 pi) - m(x), x = r/s_l < 1, with
+//      m(x) = (1/2 pi) int_0^{2c} psi(t/c)/psi(0) (J_0(tx) - J_0(t)) dt/t
+//    (the mollifier beyond argument 2 is dropped), tabulated as a Chebyshev
+//    series in u = 2x^2 - 1 from values by Gauss-Legendre quadrature on
+//    uniform panels.
+void build_tables2(Tables *t)
+{
+    const Params &prm = t->prm;
+    const double c = prm.c;
+    {
+        const int nf = prm.nf, nn = t->nn, nh = t->nh;
+        const int maxk2 = 2 * nf * nf;
+        std::vector<double> memo(maxk2 + 1);
+        memo[0] = t->c2 / (24.0 * t->c0);
+        for (int k2 = 1; k2 <= maxk2; ++k2) {
+            double km = std::sqrt((double)k2);
+            memo[k2] = (pswf_eval(*t, M_PI * km / (3.0 * c)) - pswf_eval(*t, 2.0 * M_PI * km / (3.0 * c))) /
+                       (4.0 * M_PI * M_PI * t->psi0 * k2);
+        }
+        t->wd0.assign((size_t)nn * nh, 0.0);
+        for (int m1 = -nf; m1 <= nf; ++m1)
+            for (int m2 = 0; m2 <= nf; ++m2) t->wd0[(size_t)(m1 + nf) * nh + m2] = memo[m1 * m1 + m2 * m2];
+    }
+    {
+        const int nw = prm.nw, nwn = t->nwn, nwh = t->nwh;
+        const double Atr = 1.0 + std::sqrt(2.0), h = prm.hw, fac = std::pow(h / (2.0 * M_PI), 2);
+        const int maxk2 = 2 * nw * nw;
+        std::vector<double> memo(maxk2 + 1);
+        memo[0] = fac * (0.25 * Atr * Atr - 0.5 * Atr * Atr * std::log(Atr));
+        for (int k2 = 1; k2 <= maxk2; ++k2) {
+            double k = h * std::sqrt((double)k2);
+            double That = (1.0 - std::cyl_bessel_j(0.0, k * Atr)) / (k * k) -
+                          Atr * std::log(Atr) * std::cyl_bessel_j(1.0, k * Atr) / k;
+            memo[k2] = fac * That * pswf_eval(*t, k / c) / t->psi0;
+        }
+        t->ww.assign((size_t)nwn * nwh, 0.0);
+        for (int m1 = -nw; m1 <= nw; ++m1)
+            for (int m2 = 0; m2 <= nw; ++m2) t->ww[(size_t)(m1 + nw) * nwh + m2] = memo[m1 * m1 + m2 * m2];
+    }
+    {
+        // quadrature nodes on [0, 2c]: 24 uniform panels of 32 Gauss-Legendre points
+        const int NPAN = 24, NG = 32;
+        std::vector<double> gx(NG), gw(NG);
+        for (int i = 0; i < NG; ++i) {  // Newton on P_NG
+            double z = std::cos(M_PI * (i + 0.75) / (NG + 0.5));
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1.0, p1 = z;
+                for (int k = 2; k <= NG; ++k) {
+                    double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                    p0 = p1;
+                    p1 = pk;
+                }
+                double dp = NG * (z * p1 - p0) / (z * z - 1.0);
+                double dz = p1 / dp;
+                z -= dz;
+                if (std::fabs(dz) < 1e-16) {
+                    gw[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                    break;
+                }
+                gw[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+            }
+            gx[i] = z;
+        }
+        const double T = 2.0 * c, hp = T / NPAN;
+        std::vector<double> tq, wq;
+        for (int pnl = 0; pnl < NPAN; ++pnl)
+            for (int i = 0; i < NG; ++i) {
+                double tt = hp * (pnl + 0.5 * (gx[i] + 1.0));
+                tq.push_back(tt);
+                wq.push_back(0.5 * hp * gw[i] * pswf_eval(*t, tt / c) / t->psi0 / tt / (2.0 * M_PI));
+            }
+        auto mval = [&](double x) {
+            double s = 0.0;
+            for (size_t k = 0; k < tq.size(); ++k)
+                s += wq[k] * (std::cyl_bessel_j(0.0, tq[k] * x) - std::cyl_bessel_j(0.0, tq[k]));
+            return s;
+        };
+        const int M = 48;
+        std::vector<double> f(M), cf(M);
+        for (int k = 0; k < M; ++k) {
+            double u = std::cos(M_PI * (k + 0.5) / M);
+            f[k] = mval(std::sqrt(0.5 * (u + 1.0)));
+        }
+        for (int j = 0; j < M; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < M; ++k) s += f[k] * std::cos(M_PI * j * (k + 0.5) / M);
+            cf[j] = (j == 0 ? 1.0 : 2.0) * s / M;
+        }
+        double cmax = 0.0;
+        for (double v : cf) cmax = std::max(cmax, std::fabs(v));
+        int deg = M - 1;
+        while (deg > 0 && std::fabs(cf[deg]) < 1e-15 * cmax) deg--;
+        t->gdeg = deg;
+        t->gcheb.assign(cf.begin(), cf.begin() + deg + 1);
+        int deg32 = deg;
+        while (deg32 > 0 && std::fabs(cf[deg32]) < 1e-8 * cmax) deg32--;
+        t->gdeg32 = deg32;
+        t->m0 = mval(0.0);
     }
 }
 

@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 13
+    assert len(names) == 15
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:
@@ -32,13 +32,26 @@ def test_exports_every_declared_symbol():
 def test_argument_errors_without_device():
     L = dmk.lib()
     h = C.c_void_p()
-    assert L.dmk_plan(2, 0, 1e-6, 10, None, None, None, C.byref(h)) == -2  # dim
+    assert L.dmk_plan(4, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # dim
+    assert L.dmk_plan(2, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # 2-D, NULL pts
     assert L.dmk_plan(3, 1, 1e-6, 10, None, None, None, C.byref(h)) == -2  # kernel
+    assert L.dmk_plan(3, 7, 1e-6, 10, None, None, None, C.byref(h)) == -1  # unknown kernel
     assert L.dmk_plan(3, 0, 1e-6, -1, None, None, None, C.byref(h)) == -1  # n < 0
     assert L.dmk_plan(3, 0, 3e-7, 10, C.c_void_p(1), None, None, C.byref(h)) == -2  # tol
     assert L.dmk_plan(3, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # NULL pts
     assert b"NULL" in L.dmk_last_error()
     assert L.dmk_eval(None, None, None, None) == -1
+    off = np.array([0, 5, 3], dtype=np.int64)
+    assert L.dmk_plan_batched(2, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
+                              C.byref(h)) == -1  # decreasing offsets
+    off = np.array([1, 5, 9], dtype=np.int64)
+    assert L.dmk_plan_batched(2, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
+                              C.byref(h)) == -1  # offsets[0] != 0
+    off = np.array([0, 5, 9], dtype=np.int64)
+    assert L.dmk_plan_batched(3, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
+                              C.byref(h)) == -2  # 3-D batches
+    assert L.dmk_plan_batched(2, 0, 1e-6, 0, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
+                              C.byref(h)) == -1  # nprob
     assert h.value is None
     with pytest.raises(dmk.DmkError):
         dmk.precompute_probe(1e-7, 0, np.zeros(1))
@@ -77,3 +90,28 @@ def test_host_tables_match_oracle(oracle_mod, tol):
     ref = np.array([(hw / (2 * np.pi)) ** 3 * ps.w0hat(hw * np.sqrt(k)) for k in k2])
     ok = ~np.isnan(got)
     assert np.max(np.abs(got[ok] - ref[ok])) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_host_tables_2d_match_oracle(oracle_mod):
+    """2-D tables (log kernel): plane-wave weights of D_l and W_0 against the
+    oracle's transforms times the trapezoidal factor, and the residual's smooth
+    part m against the oracle's quadrature (independent quadratures and
+    Bessel routines on each side)."""
+    pr = oracle_mod.params2_for(1e-6)
+    ps = oracle_mod.PSWF(pr.c)
+    m0, nw, hw, deg = dmk.precompute_probe(1e-6, 9, n=4)
+    assert nw == pr.nw and hw == pytest.approx(pr.hw, rel=1e-15)
+    assert m0 == pytest.approx(ps.smooth_quad(0, 0.0, 0.0), abs=1e-13)
+    k2 = np.array([0, 1, 2, 5, 8, 25, 100, 200, 288], dtype=np.float64)
+    got = dmk.precompute_probe(1e-6, 6, k2)
+    h = 2 * np.pi / 3.0  # level 0: s = 1
+    ref = np.array([(h / (2 * np.pi)) ** 2 * ps.d2hat(0, 0.0, 0, h * np.sqrt(v)) for v in k2])
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+    k2w = np.array([0, 1, 2, 13, 50, 100, 200], dtype=np.float64)
+    got = dmk.precompute_probe(1e-6, 7, k2w)
+    ref = np.array([(pr.hw / (2 * np.pi)) ** 2 * ps.w02hat(0, 0.0, pr.hw * np.sqrt(v)) for v in k2w])
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    xs = np.linspace(0, 1, 23)
+    got = dmk.precompute_probe(1e-6, 8, xs)
+    ref = np.array([ps.smooth_quad(0, 0.0, x) for x in xs])
+    assert np.max(np.abs(got - ref)) < 1e-13

@@ -1,0 +1,327 @@
+"""GPU parity of the 2-D path (kernel -log(r)/(2 pi)) through the C ABI
+against the 2-D FP64 oracle, for single problems and for batches of
+independent problems (dmk_plan_batched).
+
+FP64: quadtrees, flags, colleagues and coarse neighbours bit-exact (per
+problem for batches); residual lists equal to the source-centric definition;
+proxies and local values <= 1e-11 of the box's largest entry; far part, near
+part and potential <= 1e-10 relative l2; against direct summation <= 2e-6.
+Mixed (FP32 transforms and pair sums, FP64 offsets and sums): trees and lists
+bit-exact, per-box data <= 2e-5, parts and potential <= 1e-5, against direct
+summation <= 1e-5.  Batched mode (graph replay) must equal eager launches bit
+for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import dmk_inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _mixture(n, seed):
+    pa, qa = dmk_inputs.gaussian_2d(n // 2, seed, sigma=0.003)
+    pb, qb = dmk_inputs.uniform_square(n - n // 2, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    perm = rng.permutation(n)
+    return np.ascontiguousarray(np.concatenate([pa, pb])[perm]), np.concatenate([qa, qb])[perm]
+
+
+def _batch_small():
+    """9 problems: sizes 0 .. 5000 of both distributions, incl. one point."""
+    off, pts, q = dmk_inputs.batch_2d(7, 77, nmin=200, nmax=5000)
+    sizes = list(np.diff(off))
+    parts = [pts[off[b]:off[b + 1]] for b in range(7)]
+    qs = [q[off[b]:off[b + 1]] for b in range(7)]
+    parts.insert(2, np.zeros((0, 2)))
+    qs.insert(2, np.zeros(0))
+    sizes.insert(2, 0)
+    parts.append(np.array([[0.3, 0.9]]))
+    qs.append(np.array([0.7]))
+    sizes.append(1)
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off, np.ascontiguousarray(np.concatenate(parts)), np.concatenate(qs)
+
+
+SINGLE = {
+    "square_4k": lambda: (*dmk_inputs.uniform_square(4000, 201), 40),
+    "gauss_5k": lambda: (*dmk_inputs.gaussian_2d(5000, 202), 30),
+    "mixture_20k": lambda: (*_mixture(20000, 203), 60),
+}
+
+BARS = {"fp64": dict(box=1e-11, l2=1e-10, direct=2e-6), "mixed": dict(box=2e-5, l2=1e-5, direct=1e-5)}
+
+_ORACLE = {}
+
+
+def _oracle(oracle_mod, key, pts, q, ns):
+    if key not in _ORACLE:
+        pr = oracle_mod.params2_for(1e-6)
+        ps = oracle_mod.PSWF(pr.c)
+        tr = oracle_mod.Tree(pts, ns)
+        res = oracle_mod.dmk_eval(tr, pr, ps, q, keep=True, kern=oracle_mod.LOG2)
+        _ORACLE.clear()
+        _ORACLE[key] = (tr, res)
+    return _ORACLE[key]
+
+
+PARAMS = [(name, prec) for name in SINGLE for prec in ("fp64", "mixed")]
+
+
+@pytest.fixture(scope="module", params=PARAMS, ids=[f"{a}-{b}" for a, b in PARAMS])
+def case(request, oracle_mod):
+    import paper_2308_00292_amd as dmk
+    name, prec = request.param
+    pts, q, ns = SINGLE[name]()
+    tr, res = _oracle(oracle_mod, name, pts, q, ns)
+    _say(f"[2d case {name} {prec}] n={len(q)} ns={ns}")
+    dev = torch.device("cuda:0")
+    plan = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=ns,
+                    precision=dmk.DMK_FP64 if prec == "fp64" else dmk.DMK_MIXED)
+    tq = torch.from_numpy(q).to(dev)
+    pot = plan.eval(tq)
+    far, near = plan.eval_parts(tq)
+    torch.cuda.synchronize()
+    out = dict(name=name, prec=prec, bar=BARS[prec], pts=pts, q=q, ns=ns, otree=tr, ores=res, plan=plan,
+               pot=pot.cpu().numpy(), far=far.cpu().numpy(), near=near.cpu().numpy())
+    yield out
+    plan.close()
+
+
+def _tree_equal(g, ot, gidx=None, pbase=0):
+    """GPU tree arrays (restricted to the boxes gidx of one problem) against the oracle tree."""
+    nb = ot.nbox
+    if gidx is None:
+        gidx = np.arange(nb)
+    assert len(gidx) == nb
+    g2o = {int(b): i for i, b in enumerate(gidx)}
+
+    def mp(a):
+        return np.array([g2o[int(x)] if x >= 0 else -1 for x in a.ravel()]).reshape(a.shape)
+
+    lev = g["level"][gidx]
+    assert np.array_equal(lev, ot.level)
+    mask = np.array([(1 << (2 * int(l))) - 1 for l in lev], dtype=np.uint64)
+    assert np.array_equal(g["bkey"][gidx] & mask, ot.bkey)
+    assert np.array_equal(mp(g["parent"][gidx]), ot.parent)
+    assert np.array_equal(mp(g["child0"][gidx]), ot.child0)
+    assert np.array_equal(g["pstart"][gidx] - pbase, ot.pstart)
+    assert np.array_equal(g["pcount"][gidx], ot.pcount)
+    fl = g["flags"][gidx]
+    assert np.array_equal(fl & 1, ot.leaf)
+    assert np.array_equal((fl >> 1) & 1, ot.fout)
+    assert np.array_equal((fl >> 2) & 1, ot.fin)
+    assert np.array_equal((fl >> 3) & 1, ot.terminal)
+    assert np.array_equal(mp(g["colleague"][gidx]), ot.colleague)
+    assert np.array_equal(g["ncoarse"][gidx], ot.ncoarse)
+    for i in np.nonzero(ot.ncoarse)[0]:
+        k = ot.ncoarse[i]
+        assert sorted(mp(g["coarse"][gidx[i]][:k]).tolist()) == sorted(ot.coarse[i][:k].tolist())
+
+
+def test_tree_bit_exact(case):
+    ot, g = case["otree"], case["plan"].export_tree()
+    assert np.array_equal(g["perm"], ot.perm)
+    _tree_equal(g, ot)
+    c, side = case["plan"].problem_info(0)
+    assert side == ot.side and np.array_equal(c, ot.center)
+
+
+def test_near_lists(case):
+    ot = case["otree"]
+    leaf_box, off, src = case["plan"].export_near_lists()
+    got = {int(b): sorted(src[off[i]:off[i + 1]].tolist()) for i, b in enumerate(leaf_box)}
+    desc = {}
+    for b in np.nonzero((ot.leaf == 1) & (ot.pcount > 0))[0]:
+        a = b
+        while a >= 0:
+            desc.setdefault(int(a), []).append(int(b))
+            a = ot.parent[a]
+    want = {int(b): [] for b in np.nonzero((ot.leaf == 1) & (ot.pcount > 0))[0]}
+    for T in np.nonzero((ot.terminal == 1) & (ot.pcount > 0))[0]:
+        tg = set()
+        for cb in ot.colleague[T][ot.colleague[T] >= 0]:
+            tg.update(desc.get(int(cb), []))
+        if ot.leaf[T]:
+            for cb in ot.coarse[T][: ot.ncoarse[T]]:
+                if ot.pcount[cb] > 0:
+                    tg.add(int(cb))
+        for B in tg:
+            want[B].append(int(T))
+    assert got == {k: sorted(v) for k, v in want.items()}
+
+
+def test_proxies_and_locals(case):
+    ot, ores, plan, bar = case["otree"], case["ores"], case["plan"], case["bar"]["box"]
+    nchk = 0
+    for b in np.nonzero(ot.fout)[0][:300]:
+        g = plan.box_data(0, b)
+        o = ores["proxy"][int(b)]
+        assert np.max(np.abs(g - o)) <= bar * np.max(np.abs(o)), b
+        nchk += 1
+    anchors = np.nonzero((ot.pcount > 0) & ((ot.fin == 1) | (ot.parent < 0)))[0]
+    for b in anchors[:400]:
+        g = plan.box_data(1, b)
+        o = ores["local"][int(b)]
+        assert np.max(np.abs(g - o)) <= bar * np.max(np.abs(o)), b
+        nchk += 1
+    assert nchk > 0
+
+
+def test_far_near_and_potential(case):
+    ot, ores = case["otree"], case["ores"]
+    far_o = np.empty_like(case["far"])
+    near_o = np.empty_like(case["near"])
+    far_o[ot.perm] = ores["ufar"]
+    near_o[ot.perm] = ores["ures"]
+    bar = case["bar"]["l2"]
+    assert rel_l2(case["far"], far_o) < bar
+    assert rel_l2(case["near"], near_o) < bar
+    assert rel_l2(case["pot"], ores["u"]) < bar
+
+
+def test_against_direct(case, oracle_mod):
+    pts, q = case["pts"], case["q"]
+    n = len(q)
+    idx = np.arange(n) if n <= 6000 else np.random.default_rng(0).choice(n, 3000, replace=False)
+    ud = oracle_mod.direct2(oracle_mod.LOG2, 0.0, pts, q, idx)
+    assert rel_l2(case["pot"][idx], ud) < case["bar"]["direct"]
+
+
+def test_graph_replay_matches_eager(case):
+    import paper_2308_00292_amd as dmk
+    dev = torch.device("cuda:0")
+    prec = dmk.DMK_FP64 if case["prec"] == "fp64" else dmk.DMK_MIXED
+    plan = dmk.Plan(torch.from_numpy(case["pts"]).to(dev), tol=1e-6, leaf_max=case["ns"], precision=prec,
+                    flags=dmk.DMK_FLAG_BATCHED)
+    tq = torch.from_numpy(case["q"]).to(dev)
+    for rep in range(3):
+        u = plan.eval(tq).cpu().numpy()
+        assert np.array_equal(u, case["pot"]), rep
+        junk = torch.randn(1000, device=dev).sum()
+        torch.cuda.synchronize()
+        del junk
+    plan.close()
+
+
+# ------------------------------------------------------------------ batches
+@pytest.fixture(scope="module", params=["fp64", "mixed"])
+def batch(request, oracle_mod):
+    import paper_2308_00292_amd as dmk
+    prec = request.param
+    off, pts, q = _batch_small()
+    ns = 40
+    _say(f"[2d batch {prec}] nprob={len(off) - 1} n={len(q)}")
+    dev = torch.device("cuda:0")
+    plan = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=ns, offsets=off, max_depth=20,
+                    precision=dmk.DMK_FP64 if prec == "fp64" else dmk.DMK_MIXED)
+    tq = torch.from_numpy(q).to(dev)
+    pot = plan.eval(tq).cpu().numpy()
+    far, near = plan.eval_parts(tq)
+    torch.cuda.synchronize()
+    pr = oracle_mod.params2_for(1e-6)
+    ps = oracle_mod.PSWF(pr.c)
+    probs = []
+    for b in range(len(off) - 1):
+        pb, qb = pts[off[b]:off[b + 1]], q[off[b]:off[b + 1]]
+        tr = oracle_mod.Tree(pb, ns, 20)
+        res = oracle_mod.dmk_eval(tr, pr, ps, qb, kern=oracle_mod.LOG2)
+        probs.append((pb, qb, tr, res))
+    yield dict(prec=prec, off=off, pts=pts, q=q, ns=ns, plan=plan, pot=pot, far=far.cpu().numpy(),
+               near=near.cpu().numpy(), probs=probs, bar=BARS[prec])
+    plan.close()
+
+
+def test_batch_trees(batch):
+    g = batch["plan"].export_tree()
+    off = batch["off"]
+    lev = g["level"].astype(np.int64)
+    pid = (g["bkey"] >> (2 * lev).astype(np.uint64)).astype(np.int64)
+    for b, (pb, qb, tr, res) in enumerate(batch["probs"]):
+        gidx = np.nonzero(pid == b)[0]
+        root_start = int(g["pstart"][b])
+        assert root_start == off[b]
+        assert np.array_equal(g["perm"][off[b]:off[b + 1]] - off[b], tr.perm)
+        _tree_equal(g, tr, gidx, pbase=off[b])
+        c, side = batch["plan"].problem_info(b)
+        assert side == tr.side and np.array_equal(c, tr.center), b
+
+
+def test_batch_potentials(batch, oracle_mod):
+    off, bar = batch["off"], batch["bar"]
+    for b, (pb, qb, tr, res) in enumerate(batch["probs"]):
+        u = batch["pot"][off[b]:off[b + 1]]
+        if len(qb) == 0:
+            continue
+        if len(qb) == 1:
+            # no other charge: what remains is the split's error at r = 0
+            assert abs(u[0]) < 1e-6 * abs(qb[0])
+            continue
+        assert rel_l2(u, res["u"]) < bar["l2"], b
+        ud = oracle_mod.direct2(oracle_mod.LOG2, 0.0, pb, qb)
+        assert rel_l2(u, ud) < bar["direct"], b
+
+
+def test_batch_equals_single_plans(batch):
+    """A batch is the same computation as one plan per problem."""
+    import paper_2308_00292_amd as dmk
+    dev = torch.device("cuda:0")
+    off = batch["off"]
+    prec = dmk.DMK_FP64 if batch["prec"] == "fp64" else dmk.DMK_MIXED
+    for b in range(len(off) - 1):
+        if off[b + 1] - off[b] < 2:
+            continue
+        p1 = dmk.Plan(torch.from_numpy(batch["pts"][off[b]:off[b + 1]]).to(dev), tol=1e-6, leaf_max=batch["ns"],
+                      max_depth=20, precision=prec)
+        u1 = p1.eval(torch.from_numpy(batch["q"][off[b]:off[b + 1]]).to(dev)).cpu().numpy()
+        p1.close()
+        u = batch["pot"][off[b]:off[b + 1]]
+        assert np.max(np.abs(u - u1)) <= 1e-12 * np.max(np.abs(u1)), b
+
+
+def test_batch_graph_replay(batch):
+    import paper_2308_00292_amd as dmk
+    dev = torch.device("cuda:0")
+    prec = dmk.DMK_FP64 if batch["prec"] == "fp64" else dmk.DMK_MIXED
+    plan = dmk.Plan(torch.from_numpy(batch["pts"]).to(dev), tol=1e-6, leaf_max=batch["ns"],
+                    offsets=batch["off"], max_depth=20, precision=prec, flags=dmk.DMK_FLAG_BATCHED)
+    tq = torch.from_numpy(batch["q"]).to(dev)
+    for rep in range(3):
+        u = plan.eval(tq).cpu().numpy()
+        assert np.array_equal(u, batch["pot"]), rep
+    plan.close()
+
+
+def test_2d_edge_cases(oracle_mod):
+    import paper_2308_00292_amd as dmk
+    dev = torch.device("cuda:0")
+    # empty and single point
+    p0 = dmk.Plan(torch.zeros((0, 2), dtype=torch.float64, device=dev), tol=1e-6)
+    assert p0.eval(torch.zeros(0, dtype=torch.float64, device=dev)).numel() == 0
+    p0.close()
+    p1 = dmk.Plan(torch.tensor([[0.2, 0.7]], dtype=torch.float64, device=dev), tol=1e-6)
+    u = p1.eval(torch.tensor([1.5], dtype=torch.float64, device=dev)).cpu().numpy()
+    assert abs(u[0]) < 1e-6 * 1.5  # the split's error at r = 0
+    p1.close()
+    # coincident points, identical points beyond the depth cap
+    pts = np.array([[0.1, 0.1], [0.1, 0.1], [0.6, 0.3]] + [[0.4, 0.4]] * 50)
+    q = np.random.default_rng(3).uniform(-1, 1, len(pts))
+    pl = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=10, max_depth=8)
+    u = pl.eval(torch.from_numpy(q).to(dev)).cpu().numpy()
+    pl.close()
+    ud = oracle_mod.direct2(oracle_mod.LOG2, 0.0, pts, q)
+    assert np.max(np.abs(u - ud)) < 1e-6 * np.abs(q).sum()

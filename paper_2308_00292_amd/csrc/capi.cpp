@@ -90,7 +90,7 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
 {
     if (dim != 2 && dim != 3) throw Error{DMK_ERR_ARG, "dim must be 2 or 3"};
     if (kernel != DMK_LAPLACE && kernel != DMK_YUKAWA) throw Error{DMK_ERR_ARG, "unknown kernel"};
-    if (kernel != DMK_LAPLACE) throw Error{DMK_ERR_UNSUPPORTED, "only the Laplace kernels are implemented"};
+    if (kernel == DMK_YUKAWA && dim != 2) throw Error{DMK_ERR_UNSUPPORTED, "the Yukawa kernel is built for dim = 2"};
     if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
     if (nprob < 1) throw Error{DMK_ERR_ARG, "nprob must be >= 1"};
     if (dim == 3 && nprob > 1) throw Error{DMK_ERR_UNSUPPORTED, "batches of 3-D problems are not built"};
@@ -118,6 +118,8 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
     const int kb = std::min(kbmax, (63 - pbits) / dim);
     const int dflt = (dim == 3) ? 20 : 30;
     if (o.leaf_max < 0 || o.max_depth < 0 || o.max_depth > kb) throw Error{DMK_ERR_ARG, "bad leaf_max/max_depth"};
+    if (kernel == DMK_YUKAWA && !(o.lambda > 0 && std::isfinite(o.lambda)))
+        throw Error{DMK_ERR_ARG, "the Yukawa kernel needs lambda > 0"};
     auto *P = new Plan();
     try {
         P->dim = dim;
@@ -142,6 +144,13 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         upload_tables(P, s);
         build_tree(P, pts, s);
         build_lists(P, s);
+        if (kernel == DMK_YUKAWA) {
+            if (P->nlevels > 32) throw Error{DMK_ERR_UNSUPPORTED, "Yukawa plans hold at most 32 levels"};
+            for (int b = 0; b < nprob; ++b)
+                if (o.lambda * P->pside[b] > 50.0)
+                    throw Error{DMK_ERR_UNSUPPORTED, "lambda times a problem's extent must stay <= 50"};
+            build_yukawa_tables(P, s);
+        }
         alloc_workspace(P);
         count_work(P, s);
         if (P->flags & DMK_FLAG_BATCHED) {

@@ -124,6 +124,7 @@ struct Plan {
     int32_t *oct_dst = nullptr;    // [noct][2^dim]
     int32_t *oct_src = nullptr;    // [noct][4^dim]
     int32_t *oct_level = nullptr;  // [noct] level of the children
+    int32_t *oct_prob = nullptr;   // [noct] problem of the group
     int64_t noct = 0;
 
     // near (residual) lists in gather form over l_leaf order
@@ -143,7 +144,16 @@ struct Plan {
     void *local = nullptr;   // [nanc][p^3]
     void *phi = nullptr;     // [max_fout_level][2][nh*nn*nn] planar
     void *psi = nullptr;     // [max_fin_level][2][nh*nn*nn] planar
-    void *w0vals = nullptr;  // [p^3] W_0 values on the root grid
+    void *w0vals = nullptr;  // [nprob][p^d] W_0 values on the root grids
+
+    // 2-D K_0(lambda r): tables per (problem, level), index b * nlevels + l,
+    // for mu = lambda S_b 2^-l (lambda S_b: the problem's scaled parameter)
+    double *y_wd64 = nullptr;  float *y_wd32 = nullptr;     // [ntab][nn*nh] D_l weights
+    double *y_ww = nullptr;                                  // [nprob][nwn*nwh] W_0 weights
+    double *y_cheb64 = nullptr; float *y_cheb32 = nullptr;  // [ntab][YDEG+1] smooth part M_l
+    double *y_self = nullptr;                                // [ntab] M_l(0)
+    double *y_lam = nullptr;                                 // [nprob] lambda S_b
+    int y_deg = 0, y_deg32 = 0;
 
     // per-stage event timing (dmk_stage_timing / dmk_stage_times)
     struct Rec { int stage; hipEvent_t a, b; };
@@ -184,6 +194,7 @@ void count_work(Plan *P, hipStream_t s);
 void run_eval2(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
                hipStream_t s);
 void alloc_workspace2(Plan *P);
+void build_yukawa_tables(Plan *P, hipStream_t s);
 void stage_work(const Plan *P, double *flops, double *bytes);
 
 // Records HIP events around one stage launch when timing is enabled.

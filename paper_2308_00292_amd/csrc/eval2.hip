@@ -41,6 +41,9 @@ constexpr int RLIST2 = 1024;  // longest residual list (checked at plan time)
 template <typename T>
 struct Dev2 {
     int p, nf, nn, nh, nw, nwn, nwh, gdeg, nprob;
+    int kern, nlev, ydeg;  // kern: 0 -log(r)/(2 pi), 1 K_0(lambda r)
+    const T *ywd, *ycheb;  // K_0: per (problem, level) D_l weights and residual series
+    const double *yww, *yself, *ylam;
     double m0;
     const double *X, *Y, *qs, *pside;
     const int32_t *pstart, *pcount, *child0, *parent, *col, *proxy_slot, *local_slot, *psi_slot, *blevel,
@@ -232,7 +235,7 @@ __global__ void __launch_bounds__(TPB) k_root2(Dev2<T> D, int npmax)
             sr += e[0] * ar - e[1] * ai;
             si += e[0] * ai + e[1] * ar;
         }
-        const double w = D.ww64[t];
+        const double w = D.kern ? D.yww[(int64_t)b * nwn * nwh + t] : D.ww64[t];
         fr[t] = sr * w;
         fi[t] = si * w;
     }
@@ -252,7 +255,7 @@ __global__ void __launch_bounds__(TPB) k_root2(Dev2<T> D, int npmax)
     }
     __syncthreads();
     // v[j1][j2] = sum_m2 c_m2 Re(conj(E_W[m2][j2]) g[j1][m2]) + C_b Q
-    const double Cb = -log(D.pside[b]) / (2.0 * M_PI);
+    const double Cb = D.kern ? 0.0 : -log(D.pside[b]) / (2.0 * M_PI);
     for (int t = threadIdx.x; t < P2; t += TPB) {
         const int j1 = t / P, j2 = t % P;
         double s = 0.0;
@@ -331,7 +334,8 @@ __device__ inline Cx2<T> root3b(int k)  // w^{-k}
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_pwshift2(Dev2<T> D, const int32_t *oct_dst, const int32_t *oct_src,
-                                                  int64_t noct, int nchunk)
+                                                  const int32_t *oct_level, const int32_t *oct_prob, int64_t noct,
+                                                  int nchunk)
 {
     __shared__ int32_t src[16];
     __shared__ int32_t dst[4];
@@ -386,7 +390,9 @@ __global__ void __launch_bounds__(TPB) k_pwshift2(Dev2<T> D, const int32_t *oct_
             acc[1][1].r += v1.r; acc[1][1].i += v1.i;
         }
     }
-    const T w = D.wd0[e];  // the log kernel's weights are the same at every level
+    // the log kernel's weights are the same at every level; K_0's depend on
+    // the problem and the level
+    const T w = D.kern ? D.ywd[((int64_t)oct_prob[o] * D.nlev + oct_level[o]) * nm + e] : D.wd0[e];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const int32_t d = dst[t];
@@ -527,6 +533,35 @@ __global__ void __launch_bounds__(TPB) k_leaf2(Dev2<T> D, const int32_t *anc, co
     }
 }
 
+// ------------------------------------------------------------ K_0(z), z > 0
+// z <= 2: the ascending series -(log(z/2) + gamma) I_0(z) + sum_k (z^2/4)^k H_k/(k!)^2
+// (Abramowitz & Stegun 9.6.13); z > 2: K_0(z) = int_0^inf exp(-z cosh t) dt by
+// the trapezoidal rule (geometric convergence for this analytic integrand).
+template <typename T>
+__device__ inline T bessel_k0(T z)
+{
+    if (z <= T(2)) {
+        const T y = T(0.25) * z * z;
+        T term = T(1), i0 = T(1), sum = T(0), H = T(0);
+        for (int k = 1; k <= 14; ++k) {
+            term *= y / T(k * k);
+            H += T(1) / T(k);
+            i0 += term;
+            sum += term * H;
+        }
+        return -(log(T(0.5) * z) + T(0.57721566490153286061)) * i0 + sum;
+    }
+    const T h = T(0.125);
+    const T cut = sizeof(T) == 8 ? T(700) : T(87);
+    T s = T(0.5) * exp(-z);
+    for (int j = 1; j < 200; ++j) {
+        const T ch = cosh(T(j) * h);
+        if (z * ch > cut) break;
+        s += exp(-z * ch);
+    }
+    return h * s;
+}
+
 // -------------------------------------------------------- residual sums
 // For a source in terminal box T at level l and r < s_l:
 //   R_l(r) = -log(r^2)/(4 pi) - l log(2)/(2 pi) - m(r/s_l)
@@ -537,22 +572,32 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
                                                    const int32_t *nl_src, const int32_t *nl_pre)
 {
     constexpr int RCAP = sizeof(T) == 8 ? 768 : 1024;
+    constexpr int YLEV = 32;  // levels of a K_0 problem's tables held in LDS
     __shared__ T sx[RCAP], sy[RCAP], sq[RCAP], sis2[RCAP], slc[RCAP];
     __shared__ int32_t loff[RLIST2 + 1];
     __shared__ T gc[48];
+    __shared__ T yc[YLEV * 48];
+    __shared__ T yself[YLEV];
     __shared__ double part[TPB];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.pstart[B];
     const int nt = D.pcount[B];
     const int32_t l0 = nl_off[blockIdx.x];
     const int L = nl_off[blockIdx.x + 1] - l0;
-    const int deg = D.gdeg;
-    for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
+    const int deg = D.kern ? D.ydeg : D.gdeg;
+    const int32_t prob = D.bprob[B];
+    if (D.kern) {
+        for (int t = threadIdx.x; t < D.nlev * 48; t += TPB) yc[t] = D.ycheb[(int64_t)prob * D.nlev * 48 + t];
+        for (int t = threadIdx.x; t < D.nlev; t += TPB) yself[t] = (T)D.yself[(int64_t)prob * D.nlev + t];
+    } else {
+        for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
+    }
     for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
     __syncthreads();
     const int nsrc = loff[L];
     const double cx = D.bcenter[2 * (int64_t)B], cy = D.bcenter[2 * (int64_t)B + 1];
-    const double Cb = -log(D.pside[D.bprob[B]]) / (2.0 * M_PI);
+    const double Cb = D.kern ? 0.0 : -log(D.pside[prob]) / (2.0 * M_PI);
+    const T lam = D.kern ? (T)D.ylam[prob] : T(0);
     const T zero_val = (T)(-(D.m0 + Cb));  // plus slc of the source level
     const T k4pi = (T)(-1.0 / (4.0 * M_PI));
     const int tch = (nt <= 32) ? 32 : 64;
@@ -580,10 +625,38 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
                 sy[idx] = (T)(D.Y[j] - cy);
                 sq[idx] = (T)D.qs[j];
                 sis2[idx] = (T)ldexp(1.0, 2 * lev);
-                slc[idx] = (T)(-lev * M_LN2 / (2.0 * M_PI));
+                slc[idx] = D.kern ? (T)lev : (T)(-lev * M_LN2 / (2.0 * M_PI));
             }
             __syncthreads();
             T pacc = T(0);
+            if (D.kern) {
+                // K_0(lambda r) - M_l(r) for 0 < r < s_l; -M_l(0) at r = 0
+                for (int j = split; j < cnt; j += nsplit) {
+                    const T dx = xt - sx[j], dy = yt - sy[j];
+                    const T r2 = dx * dx + dy * dy;
+                    const T tt = r2 * sis2[j];
+                    if (tt < T(1)) {
+                        const int lv = (int)slc[j];
+                        T val;
+                        if (r2 > T(0)) {
+                            const T *cf = yc + lv * 48;
+                            const T u = T(2) * tt - T(1);
+                            T b1 = T(0), b2 = T(0);
+                            for (int k = deg; k >= 1; --k) {
+                                T b0 = cf[k] + T(2) * u * b1 - b2;
+                                b2 = b1;
+                                b1 = b0;
+                            }
+                            val = bessel_k0<T>(lam * sqrt(r2)) - (cf[0] + u * b1 - b2);
+                        } else {
+                            val = -yself[lv];
+                        }
+                        pacc += sq[j] * val;
+                    }
+                }
+                acc += (double)pacc;
+                continue;
+            }
             for (int j = split; j < cnt; j += nsplit) {
                 const T dx = xt - sx[j], dy = yt - sy[j];
                 const T r2 = dx * dx + dy * dy;
@@ -647,6 +720,14 @@ Dev2<T> make_dev2(Plan *P)
     D.gdeg = sizeof(T) == 8 ? t.gdeg : t.gdeg32;
     D.nprob = P->nprob;
     D.m0 = t.m0;
+    D.kern = (P->kernel == DMK_YUKAWA) ? 1 : 0;
+    D.nlev = P->nlevels;
+    D.ydeg = sizeof(T) == 8 ? P->y_deg : P->y_deg32;
+    D.ywd = (const T *)(sizeof(T) == 8 ? (void *)P->y_wd64 : (void *)P->y_wd32);
+    D.ycheb = (const T *)(sizeof(T) == 8 ? (void *)P->y_cheb64 : (void *)P->y_cheb32);
+    D.yww = P->y_ww;
+    D.yself = P->y_self;
+    D.ylam = P->y_lam;
     D.X = P->X; D.Y = P->Y; D.qs = P->qs; D.pside = P->d_pside;
     D.pstart = P->pstart; D.pcount = P->pcount; D.child0 = P->child0; D.parent = P->parent; D.col = P->colleague;
     D.proxy_slot = P->proxy_slot; D.local_slot = P->local_slot; D.psi_slot = P->psi_slot; D.blevel = P->blevel;
@@ -726,7 +807,7 @@ static void enqueue_core2(Plan *Pl, hipStream_t s, hipStream_t side)
         const int nchunk = (int)((nm + TPB - 1) / TPB);
         const int64_t nb = (Pl->noct * nchunk + 7) / 8 * 8;
         hipLaunchKernelGGL((k_pwshift2<T>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
-                           Pl->noct, nchunk);
+                           Pl->oct_level, Pl->oct_prob, Pl->noct, nchunk);
     }
     for (int l = 0; l < L; ++l) {
         int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];

@@ -731,8 +731,9 @@ __global__ void k_oct_flag(const int32_t *fin, int64_t m, const int32_t *parent,
 // offset (g+1)/2 - 1 per axis
 template <int D>
 __global__ void k_oct_fill(const int32_t *octs, int64_t m, const int32_t *child0, const int32_t *col,
-                           const uint8_t *bflags, const int32_t *blevel, const int32_t *proxy_slot,
-                           const int32_t *psi_slot, int32_t *dst, int32_t *src, int32_t *lev)
+                           const uint8_t *bflags, const int32_t *blevel, const int32_t *bprob,
+                           const int32_t *proxy_slot, const int32_t *psi_slot, int32_t *dst, int32_t *src,
+                           int32_t *lev, int32_t *prob)
 {
     constexpr int NC = Geo<D>::NC, NCOL = Geo<D>::NCOL, NR = Geo<D>::NRING;
     int64_t i = blockIdx.x;
@@ -740,7 +741,10 @@ __global__ void k_oct_fill(const int32_t *octs, int64_t m, const int32_t *child0
     const int32_t P = octs[i];
     const int t = threadIdx.x;
     if (t < NC) dst[i * NC + t] = psi_slot[child0[P] + t];
-    if (t == 0) lev[i] = blevel[P] + 1;
+    if (t == 0) {
+        lev[i] = blevel[P] + 1;
+        prob[i] = bprob[P];
+    }
     if (t < NR) {
         int k = 0, c = 0, r = t;
         int g[3];
@@ -929,29 +933,32 @@ static void build_lists_t(Plan *P, hipStream_t s)
         DMK_HIP(hipMemcpyAsync(rpsi.data(), P->psi_slot, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DMK_HIP(hipMemcpyAsync(rphi.data(), P->proxy_slot, np * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DMK_HIP(hipStreamSynchronize(s));
-        std::vector<int32_t> hd, hs, hl;
+        std::vector<int32_t> hd, hs, hl, hp;
         int root_cell = (D == 3) ? 21 : 5;  // cell (1,..,1)
         for (int b = 0; b < np; ++b) {
             if (rpsi[b] < 0) continue;
             for (int k = 0; k < NC; ++k) hd.push_back(k == 0 ? rpsi[b] : -1);
             for (int k = 0; k < NR; ++k) hs.push_back(k == root_cell ? rphi[b] : -1);
             hl.push_back(0);
+            hp.push_back(b);
         }
         const int64_t r = (int64_t)hl.size();
         P->noct = m + r;
         P->oct_dst = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * NC);
         P->oct_src = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1) * NR);
         P->oct_level = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1));
+        P->oct_prob = talloc<int32_t>(P, std::max<int64_t>(P->noct, 1));
         if (r) {
             DMK_HIP(hipMemcpyAsync(P->oct_dst, hd.data(), hd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
             DMK_HIP(hipMemcpyAsync(P->oct_src, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
             DMK_HIP(hipMemcpyAsync(P->oct_level, hl.data(), hl.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipMemcpyAsync(P->oct_prob, hp.data(), hp.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
             DMK_HIP(hipStreamSynchronize(s));
         }
         if (m)
             hipLaunchKernelGGL(k_oct_fill<D>, dim3((unsigned)m), dim3(64), 0, s, octs, m, P->child0, P->colleague,
-                               P->bflags, P->blevel, P->proxy_slot, P->psi_slot, P->oct_dst + NC * r,
-                               P->oct_src + NR * r, P->oct_level + r);
+                               P->bflags, P->blevel, P->bprob, P->proxy_slot, P->psi_slot, P->oct_dst + NC * r,
+                               P->oct_src + NR * r, P->oct_level + r, P->oct_prob + r);
     }
 
     // targets grouped by the anchor of their leaf (leaf evaluation)

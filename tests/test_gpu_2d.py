@@ -1,6 +1,6 @@
-"""GPU parity of the 2-D path (kernel -log(r)/(2 pi)) through the C ABI
-against the 2-D FP64 oracle, for single problems and for batches of
-independent problems (dmk_plan_batched).
+"""GPU parity of the 2-D path (kernels -log(r)/(2 pi) and K_0(10 r)) through
+the C ABI against the 2-D FP64 oracle, for single problems and for batches
+of independent problems (dmk_plan_batched).
 
 FP64: quadtrees, flags, colleagues and coarse neighbours bit-exact (per
 problem for batches); residual lists equal to the source-centric definition;
@@ -62,42 +62,46 @@ SINGLE = {
     "gauss_5k": lambda: (*dmk_inputs.gaussian_2d(5000, 202), 30),
     "mixture_20k": lambda: (*_mixture(20000, 203), 60),
 }
+# kernels: (name, oracle kernel id, lambda in input units)
+KERNELS = {"log": (0, 0.0), "k0": (1, 10.0)}
 
 BARS = {"fp64": dict(box=1e-11, l2=1e-10, direct=2e-6), "mixed": dict(box=2e-5, l2=1e-5, direct=1e-5)}
 
 _ORACLE = {}
 
 
-def _oracle(oracle_mod, key, pts, q, ns):
+def _oracle(oracle_mod, key, pts, q, ns, kern, lam):
     if key not in _ORACLE:
         pr = oracle_mod.params2_for(1e-6)
         ps = oracle_mod.PSWF(pr.c)
         tr = oracle_mod.Tree(pts, ns)
-        res = oracle_mod.dmk_eval(tr, pr, ps, q, keep=True, kern=oracle_mod.LOG2)
+        res = oracle_mod.dmk_eval(tr, pr, ps, q, keep=True, kern=kern, lam=lam)
         _ORACLE.clear()
         _ORACLE[key] = (tr, res)
     return _ORACLE[key]
 
 
-PARAMS = [(name, prec) for name in SINGLE for prec in ("fp64", "mixed")]
+PARAMS = [(kn, name, prec) for kn in KERNELS for name in SINGLE for prec in ("fp64", "mixed")
+          if not (kn == "k0" and name == "gauss_5k")]
 
 
-@pytest.fixture(scope="module", params=PARAMS, ids=[f"{a}-{b}" for a, b in PARAMS])
+@pytest.fixture(scope="module", params=PARAMS, ids=[f"{a}-{b}-{c}" for a, b, c in PARAMS])
 def case(request, oracle_mod):
     import paper_2308_00292_amd as dmk
-    name, prec = request.param
+    kn, name, prec = request.param
+    kern, lam = KERNELS[kn]
     pts, q, ns = SINGLE[name]()
-    tr, res = _oracle(oracle_mod, name, pts, q, ns)
-    _say(f"[2d case {name} {prec}] n={len(q)} ns={ns}")
+    tr, res = _oracle(oracle_mod, (kn, name), pts, q, ns, kern, lam)
+    _say(f"[2d case {kn} {name} {prec}] n={len(q)} ns={ns}")
     dev = torch.device("cuda:0")
-    plan = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=ns,
+    plan = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=ns, kernel=kern, lam=lam,
                     precision=dmk.DMK_FP64 if prec == "fp64" else dmk.DMK_MIXED)
     tq = torch.from_numpy(q).to(dev)
     pot = plan.eval(tq)
     far, near = plan.eval_parts(tq)
     torch.cuda.synchronize()
-    out = dict(name=name, prec=prec, bar=BARS[prec], pts=pts, q=q, ns=ns, otree=tr, ores=res, plan=plan,
-               pot=pot.cpu().numpy(), far=far.cpu().numpy(), near=near.cpu().numpy())
+    out = dict(name=name, prec=prec, kern=kern, lam=lam, bar=BARS[prec], pts=pts, q=q, ns=ns, otree=tr,
+               ores=res, plan=plan, pot=pot.cpu().numpy(), far=far.cpu().numpy(), near=near.cpu().numpy())
     yield out
     plan.close()
 
@@ -198,7 +202,7 @@ def test_against_direct(case, oracle_mod):
     pts, q = case["pts"], case["q"]
     n = len(q)
     idx = np.arange(n) if n <= 6000 else np.random.default_rng(0).choice(n, 3000, replace=False)
-    ud = oracle_mod.direct2(oracle_mod.LOG2, 0.0, pts, q, idx)
+    ud = oracle_mod.direct2(case["kern"], case["lam"], pts, q, idx)
     assert rel_l2(case["pot"][idx], ud) < case["bar"]["direct"]
 
 
@@ -207,7 +211,7 @@ def test_graph_replay_matches_eager(case):
     dev = torch.device("cuda:0")
     prec = dmk.DMK_FP64 if case["prec"] == "fp64" else dmk.DMK_MIXED
     plan = dmk.Plan(torch.from_numpy(case["pts"]).to(dev), tol=1e-6, leaf_max=case["ns"], precision=prec,
-                    flags=dmk.DMK_FLAG_BATCHED)
+                    kernel=case["kern"], lam=case["lam"], flags=dmk.DMK_FLAG_BATCHED)
     tq = torch.from_numpy(case["q"]).to(dev)
     for rep in range(3):
         u = plan.eval(tq).cpu().numpy()
@@ -219,16 +223,20 @@ def test_graph_replay_matches_eager(case):
 
 
 # ------------------------------------------------------------------ batches
-@pytest.fixture(scope="module", params=["fp64", "mixed"])
+BPARAMS = [(kn, prec) for kn in KERNELS for prec in ("fp64", "mixed")]
+
+
+@pytest.fixture(scope="module", params=BPARAMS, ids=[f"{a}-{b}" for a, b in BPARAMS])
 def batch(request, oracle_mod):
     import paper_2308_00292_amd as dmk
-    prec = request.param
+    kn, prec = request.param
+    kern, lam = KERNELS[kn]
     off, pts, q = _batch_small()
     ns = 40
-    _say(f"[2d batch {prec}] nprob={len(off) - 1} n={len(q)}")
+    _say(f"[2d batch {kn} {prec}] nprob={len(off) - 1} n={len(q)}")
     dev = torch.device("cuda:0")
     plan = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=ns, offsets=off, max_depth=20,
-                    precision=dmk.DMK_FP64 if prec == "fp64" else dmk.DMK_MIXED)
+                    kernel=kern, lam=lam, precision=dmk.DMK_FP64 if prec == "fp64" else dmk.DMK_MIXED)
     tq = torch.from_numpy(q).to(dev)
     pot = plan.eval(tq).cpu().numpy()
     far, near = plan.eval_parts(tq)
@@ -239,10 +247,10 @@ def batch(request, oracle_mod):
     for b in range(len(off) - 1):
         pb, qb = pts[off[b]:off[b + 1]], q[off[b]:off[b + 1]]
         tr = oracle_mod.Tree(pb, ns, 20)
-        res = oracle_mod.dmk_eval(tr, pr, ps, qb, kern=oracle_mod.LOG2)
+        res = oracle_mod.dmk_eval(tr, pr, ps, qb, kern=kern, lam=lam)
         probs.append((pb, qb, tr, res))
-    yield dict(prec=prec, off=off, pts=pts, q=q, ns=ns, plan=plan, pot=pot, far=far.cpu().numpy(),
-               near=near.cpu().numpy(), probs=probs, bar=BARS[prec])
+    yield dict(prec=prec, kern=kern, lam=lam, off=off, pts=pts, q=q, ns=ns, plan=plan, pot=pot,
+               far=far.cpu().numpy(), near=near.cpu().numpy(), probs=probs, bar=BARS[prec])
     plan.close()
 
 
@@ -272,7 +280,7 @@ def test_batch_potentials(batch, oracle_mod):
             assert abs(u[0]) < 1e-6 * abs(qb[0])
             continue
         assert rel_l2(u, res["u"]) < bar["l2"], b
-        ud = oracle_mod.direct2(oracle_mod.LOG2, 0.0, pb, qb)
+        ud = oracle_mod.direct2(batch["kern"], batch["lam"], pb, qb)
         assert rel_l2(u, ud) < bar["direct"], b
 
 
@@ -286,11 +294,14 @@ def test_batch_equals_single_plans(batch):
         if off[b + 1] - off[b] < 2:
             continue
         p1 = dmk.Plan(torch.from_numpy(batch["pts"][off[b]:off[b + 1]]).to(dev), tol=1e-6, leaf_max=batch["ns"],
-                      max_depth=20, precision=prec)
+                      max_depth=20, precision=prec, kernel=batch["kern"], lam=batch["lam"])
         u1 = p1.eval(torch.from_numpy(batch["q"][off[b]:off[b + 1]]).to(dev)).cpu().numpy()
         p1.close()
         u = batch["pot"][off[b]:off[b + 1]]
-        assert np.max(np.abs(u - u1)) <= 1e-12 * np.max(np.abs(u1)), b
+        # K_0 tables are truncated at the largest degree any table of the plan
+        # needs, so in FP32 a batch and a single plan may keep different terms
+        bar = 1e-12 if (batch["prec"] == "fp64" or batch["kern"] == 0) else 1e-6
+        assert np.max(np.abs(u - u1)) <= bar * np.max(np.abs(u1)), b
 
 
 def test_batch_graph_replay(batch):
@@ -298,7 +309,8 @@ def test_batch_graph_replay(batch):
     dev = torch.device("cuda:0")
     prec = dmk.DMK_FP64 if batch["prec"] == "fp64" else dmk.DMK_MIXED
     plan = dmk.Plan(torch.from_numpy(batch["pts"]).to(dev), tol=1e-6, leaf_max=batch["ns"],
-                    offsets=batch["off"], max_depth=20, precision=prec, flags=dmk.DMK_FLAG_BATCHED)
+                    offsets=batch["off"], max_depth=20, precision=prec, flags=dmk.DMK_FLAG_BATCHED,
+                    kernel=batch["kern"], lam=batch["lam"])
     tq = torch.from_numpy(batch["q"]).to(dev)
     for rep in range(3):
         u = plan.eval(tq).cpu().numpy()
@@ -324,4 +336,16 @@ def test_2d_edge_cases(oracle_mod):
     u = pl.eval(torch.from_numpy(q).to(dev)).cpu().numpy()
     pl.close()
     ud = oracle_mod.direct2(oracle_mod.LOG2, 0.0, pts, q)
+    assert np.max(np.abs(u - ud)) < 1e-6 * np.abs(q).sum()
+    # K_0: one point, and coincident points
+    p1 = dmk.Plan(torch.tensor([[0.2, 0.7]], dtype=torch.float64, device=dev), tol=1e-6,
+                  kernel=dmk.DMK_YUKAWA, lam=3.0)
+    u = p1.eval(torch.tensor([1.5], dtype=torch.float64, device=dev)).cpu().numpy()
+    assert abs(u[0]) < 1e-6 * 1.5
+    p1.close()
+    pl = dmk.Plan(torch.from_numpy(pts).to(dev), tol=1e-6, leaf_max=10, max_depth=8, kernel=dmk.DMK_YUKAWA,
+                  lam=3.0)
+    u = pl.eval(torch.from_numpy(q).to(dev)).cpu().numpy()
+    pl.close()
+    ud = oracle_mod.direct2(oracle_mod.YUK2, 3.0, pts, q)
     assert np.max(np.abs(u - ud)) < 1e-6 * np.abs(q).sum()

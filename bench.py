@@ -36,16 +36,48 @@ STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward", "root": "k_root_st
                 "proxy2pw": "k_proxy2pw", "local": "k_local_pw", "pwshift": "k_pwshift",
                 "pw2grid": "k_local_pw", "leaf": "k_leaf", "residual": "k_residual",
                 "finalize": "k_finalize"}
+STAGE_KERNEL2 = {"gather": "k_gather_q2", "upward": "k_upward2", "root": "k_root2", "proxy2pw": "k_proxy2pw2",
+                 "local": "k_local_pw2", "pwshift": "k_pwshift2", "pw2grid": "k_local_pw2", "leaf": "k_leaf2",
+                 "residual": "k_residual2", "finalize": "k_finalize2"}
 WORKLOADS = {
     "cfg3_clustered_10m": "3-D Laplace, N=1e7 clustered (70% on the unit sphere, 30% in 3 Gaussian "
                           "blobs sigma=1e-3), charges U[-1,1], leaf<=64, tol 1e-6",
     "cfg2_uniform_1m": "3-D Laplace, N=1e6 uniform in the unit cube, charges U[-1,1], leaf<=64, tol 1e-6",
     "cfg1_uniform_2k": "3-D Laplace, N=2000 uniform in the unit cube, leaf<=50, tol 1e-6",
+    "cfg4_batch2d_512": "2-D batch of 512 independent problems, N_b = exp(U[ln 1e3, ln 2e5]) "
+                        "(1.79e7 points), U[0,1]^2 or 0.5+0.01 N(0,I) per problem, charges U[-1,1], leaf<=64, "
+                        "tol 1e-6; kernel -log(r)/(2 pi) or K_0(10 r) (--kernel)",
 }
+METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline_2d(off, pts, q, ns, tol, kern, lam, seed=7):
+    """The oracle on whole problems of the batch, drawn at random until about
+    15 s of eval work is done; points/s over the problems it ran."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    pr = oracle.params2_for(tol)
+    ps = oracle.PSWF(pr.c)
+    done, te = 0, 0.0
+    order = rng.permutation(len(off) - 1)
+    nprob = 0
+    for b in order:
+        pb, qb = pts[off[b]:off[b + 1]], q[off[b]:off[b + 1]]
+        tr = oracle.Tree(pb, ns)
+        t0 = time.perf_counter()
+        oracle.dmk_eval(tr, pr, ps, qb, kern=kern, lam=lam)
+        te += time.perf_counter() - t0
+        done += len(qb)
+        nprob += 1
+        if te > 15.0:
+            break
+    return {"value": done / te, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{nprob} whole problems of the batch drawn at random ({done} points), eval phase "
+                      f"{te:.2f} s, trees excluded, FP64, tol {tol:g}"}
 
 
 def cpu_baseline(pts, q, ns, tol, seed=7):
@@ -73,6 +105,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg3_clustered_10m", choices=list(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--kernel", default="log", choices=["log", "k0"],
+                    help="2-D workloads: -log(r)/(2 pi) or K_0(10 r)")
     ap.add_argument("--no-batched", action="store_true",
                     help="launch every stage eagerly instead of replaying the captured graph")
     ap.add_argument("--no-compare", action="store_true",
@@ -96,7 +130,15 @@ def main():
     prec = dmk.DMK_FP64 if args.precision == "fp64" else dmk.DMK_MIXED
     batched = not args.no_batched
     log(f"[bench] generating {args.workload}")
-    pts, q, ns = dmk_inputs.make(args.workload)
+    offsets = None
+    kern, lam = dmk.DMK_LAPLACE, 0.0
+    if args.workload == "cfg4_batch2d_512":
+        offsets, pts, q = dmk_inputs.batch_2d(512, 4)
+        ns = 64
+        if args.kernel == "k0":
+            kern, lam = dmk.DMK_YUKAWA, 10.0
+    else:
+        pts, q, ns = dmk_inputs.make(args.workload)
     n = len(q)
     dev = torch.device("cuda:0")
     tp_ = torch.from_numpy(pts).to(dev)
@@ -130,7 +172,7 @@ def main():
 
     log(f"[bench] plan ({args.precision}{', batched' if batched else ''})")
     t0 = time.perf_counter()
-    plan = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=prec,
+    plan = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=prec, offsets=offsets, kernel=kern, lam=lam,
                     flags=dmk.DMK_FLAG_BATCHED if batched else 0)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
@@ -159,8 +201,9 @@ def main():
     else:
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
+    kname = STAGE_KERNEL[dom] if offsets is None else STAGE_KERNEL2[dom]
     roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "kernel": STAGE_KERNEL[dom], "stage": dom,
+            "frac": achieved / peak, "traffic": None, "kernel": kname, "stage": dom,
             "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / nst}
     stages = {}
     for k in stage_ms:
@@ -178,7 +221,7 @@ def main():
     plain = None
     if not args.no_compare:
         log("[bench] plain FP64 comparison (eager launches)")
-        p64 = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=dmk.DMK_FP64)
+        p64 = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=dmk.DMK_FP64, offsets=offsets, kernel=kern, lam=lam)
         ms64, out64 = timed(p64, args.steps, args.warmup)
         u64 = out64.cpu().numpy()
         p64.close()
@@ -189,8 +232,18 @@ def main():
     # sampled parity against direct summation by the oracle
     import oracle
     rng = np.random.default_rng(11)
-    sidx = rng.choice(n, min(n, args.sample_targets), replace=False)
-    ud = oracle.direct(pts, q, sidx)
+    if offsets is None:
+        sidx = rng.choice(n, min(n, args.sample_targets), replace=False)
+        ud = oracle.direct(pts, q, sidx)
+    else:
+        # targets of 8 random problems, direct sums over their own problem
+        sidx, ud = [], []
+        for b in rng.choice(len(offsets) - 1, 8, replace=False):
+            o0, o1 = offsets[b], offsets[b + 1]
+            ti = rng.choice(o1 - o0, min(o1 - o0, args.sample_targets // 8), replace=False)
+            ud.append(oracle.direct2(kern, lam, pts[o0:o1], q[o0:o1], ti))
+            sidx.append(o0 + ti)
+        sidx, ud = np.concatenate(sidx), np.concatenate(ud)
     err = float(np.linalg.norm(u_main[sidx] - ud) / np.linalg.norm(ud))
     log(f"[bench] sampled rel l2 vs direct sum ({len(sidx)} targets): {err:.3e}")
     if plain is not None:
@@ -200,16 +253,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cpu = cpu_baseline(pts, q, ns, tol)
+        cpu = (cpu_baseline(pts, q, ns, tol) if offsets is None
+               else cpu_baseline_2d(offsets, pts, q, ns, tol, kern, lam))
         log(f"[bench] cpu baseline {cpu['value']:.4g} points/s on {cpu['cores']} threads")
 
     res = {
-        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC if offsets is None else METRIC_2D, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64" if prec == dmk.DMK_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n_points": n,
                    "tol": tol, "leaf_max": ns, "precision": args.precision, "batched": batched,
+                   "kernel": ("1/(4 pi r)" if offsets is None else
+                              ("-log(r)/(2 pi)" if kern == dmk.DMK_LAPLACE else "K_0(10 r)")),
                    "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"],
                    "p": info["p"], "nf": info["nf"], "t_plan_s": round(t_plan, 3),
                    "end_to_end_points_per_s": n / (t_plan + ms_step * 1e-3),

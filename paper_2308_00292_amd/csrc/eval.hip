@@ -626,6 +626,295 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
     store_tiles<T, P>(acc, D.local + (int64_t)D.local_slot[B] * P3);
 }
 
+// ------------------------------------------ local values on matrix cores
+// FP32 path of the local stage on MFMA (v_mfma_f32_16x16x4f32).  Every step
+// is a mode product Y(x, a) = sum_k X(x, k) B(k, a) with x running over the
+// two untouched indices (up to 325 rows) and a over the new one: waves take
+// 16-row slabs of x, 16-column tiles of a, and 4-deep steps of k; lane l
+// supplies X(x0 + l%16, k0 + l/16) and B(k0 + l/16, a0 + l%16) and receives
+// Y(x0 + 4(l/16) + i, a0 + l%16), i < 4.  B (the small interpolation and
+// plane-wave matrices) is loaded once into registers per tile.
+//   interpolation from the anchor (Lemma 2.2): contract x, then y, then z;
+//   plane waves -> grid (eq. incomingexpansion2): contract m1 (complex),
+//   then m2 (complex), then m3 with the real part and the half-spectrum
+//   weights; the last step lands in the same (x = (j1 j2), a = j3)
+//   fragments as the interpolation's last step, so both stay in registers.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int NWAVE = TPB / 64;
+
+template <int P, int NF>
+struct LocalMfma {
+    static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1, NM = NH * NN;
+    static constexpr int NSL = (P2 + 15) / 16;              // slabs of the p^2 x p outputs
+    static constexpr int NSW = (NSL + NWAVE - 1) / NWAVE;   // slabs per wave
+    static constexpr int NAT = (P + 15) / 16;               // column tiles of the new index
+    static constexpr int G = 16 / (P % 16 == 0 ? 16 : (P % 8 == 0 ? 8 : (P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1))));
+    static constexpr int KP = 2 * NH;                        // m3 real parts, then imaginary parts
+    static constexpr int TAB = 2 * NN * P + KP * P + 3 * P2 + 2 * P;
+    static constexpr int WORK_P2C = 2 * P3;
+    static constexpr int WORK_PW = 2 * P * NM + G * P * KP;
+    static constexpr int WORK = WORK_P2C > WORK_PW ? WORK_P2C : WORK_PW;
+    static size_t lds() { return sizeof(float) * (TAB + WORK); }
+};
+
+// real mode product into registers: acc[i][t] += sum_k X(x, k) B(k, a) for the
+// wave's slabs i (slab w + NWAVE i) and tiles t; Bt[k * P + a]
+template <int P, int NX, int NK, int NSW, int NAT, typename XF>
+__device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][NAT])
+{
+    constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    float breg[NAT][NKS];
+#pragma unroll
+    for (int t = 0; t < NAT; ++t)
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq, a = 16 * t + r16;
+            breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
+        }
+#pragma unroll
+    for (int i = 0; i < NSW; ++i) {
+        const int sl = w + NWAVE * i;
+        if (sl >= NSL) break;
+        const int xa = 16 * sl + r16;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq;
+            const float av = (xa < NX && k < NK) ? X(xa, k) : 0.f;
+#pragma unroll
+            for (int t = 0; t < NAT; ++t)
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[i][t], 0, 0, 0);
+        }
+    }
+}
+
+// real mode product with the result stored: Y(x, a) -> store(x, a, v)
+template <int P, int NX, int NK, int NAT, typename XF, typename SF>
+__device__ inline void mma_real_store(XF X, const float *Bt, SF store)
+{
+    constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    float breg[NAT][NKS];
+#pragma unroll
+    for (int t = 0; t < NAT; ++t)
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq, a = 16 * t + r16;
+            breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
+        }
+    for (int sl = w; sl < NSL; sl += NWAVE) {
+        const int xa = 16 * sl + r16;
+        f32x4 acc[NAT];
+#pragma unroll
+        for (int t = 0; t < NAT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq;
+            const float av = (xa < NX && k < NK) ? X(xa, k) : 0.f;
+#pragma unroll
+            for (int t = 0; t < NAT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NAT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
+                if (x < NX && a < P) store(x, a, acc[t][i]);
+            }
+    }
+}
+
+// complex mode product Y = X B, X planar (Xr, Xi functors), B planar tables
+template <int P, int NX, int NK, int NAT, typename XR, typename XI, typename SF>
+__device__ inline void mma_cplx_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
+{
+    constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    float br[NAT][NKS], bi[NAT][NKS];
+#pragma unroll
+    for (int t = 0; t < NAT; ++t)
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq, a = 16 * t + r16;
+            const bool ok = k < NK && a < P;
+            br[t][s] = ok ? Br[k * P + a] : 0.f;
+            bi[t][s] = ok ? Bi[k * P + a] : 0.f;
+        }
+    for (int sl = w; sl < NSL; sl += NWAVE) {
+        const int xa = 16 * sl + r16;
+        f32x4 cr[NAT], ci[NAT];
+#pragma unroll
+        for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq;
+            const bool ok = xa < NX && k < NK;
+            const float ar = ok ? Xr(xa, k) : 0.f, ai = ok ? Xi(xa, k) : 0.f, nai = -ai;
+#pragma unroll
+            for (int t = 0; t < NAT; ++t) {
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[t][s], cr[t], 0, 0, 0);
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bi[t][s], cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[t][s], ci[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[t][s], ci[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NAT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
+                if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
+            }
+    }
+}
+
+template <int P, int NF>
+__global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32_t *list, int level)
+{
+    using L = LocalMfma<P, NF>;
+    constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, NSW = L::NSW, NAT = L::NAT;
+    constexpr int G = L::G, KP = L::KP, NSL = L::NSL;
+    extern __shared__ unsigned char smraw[];
+    float *sm = reinterpret_cast<float *>(smraw);
+    float *Br1 = sm, *Bi1 = Br1 + NN * P;  // conj(E): B(k = m, a = j) = Er[m][j] - i Ei[m][j]
+    float *B3 = Bi1 + NN * P;              // [KP][P]: c_m3 Er[m3][j3], then c_m3 Ei[m3][j3]
+    float *Bx = B3 + KP * P, *By = Bx + P2, *Bz = By + P2;  // B(k = a, col = i) = M_d[i][a]
+    float *xc = Bz + P2, *bw = xc + P;
+    float *work = bw + P;
+    const int32_t B = list[blockIdx.x];
+    for (int t = threadIdx.x; t < NN * P; t += TPB) {
+        Br1[t] = D.epw[2 * t];
+        Bi1[t] = -D.epw[2 * t + 1];
+    }
+    for (int t = threadIdx.x; t < KP * P; t += TPB) {
+        const int k = t / P, j = t % P, m3 = (k < NH) ? k : k - NH;
+        const float cm = (m3 == 0) ? 1.f : 2.f;
+        const float *e = D.epw + 2 * ((m3 + NF) * P + j);
+        B3[t] = cm * ((k < NH) ? e[0] : e[1]);
+    }
+    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
+    f32x4 acc[NSW][NAT];
+#pragma unroll
+    for (int i = 0; i < NSW; ++i)
+#pragma unroll
+        for (int t = 0; t < NAT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    __syncthreads();
+    if (level == 0) {
+        // root: the windowed W_0 values, in the fragment layout of the last step
+#pragma unroll
+        for (int i = 0; i < NSW; ++i) {
+            const int sl = w + NWAVE * i;
+            if (sl >= NSL) break;
+#pragma unroll
+            for (int t = 0; t < NAT; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
+                    if (x < P2 && a < P) acc[i][t][q] = D.w0vals[x * P + a];
+                }
+        }
+    } else {
+        // interpolation from the anchor A of the parent: node i of B sits at
+        // A-coordinate ((c_B + s_B x_i / 2) - c_A) * 2 / s_A
+        const int32_t A = D.anchor[D.parent[B]];
+        const double sB = box_side(level), sA = box_side(D.blevel[A]);
+        for (int t = threadIdx.x; t < 3 * P; t += TPB) {
+            const int d = t / P, i = t % P;
+            const double xi = (D.bcenter[3 * (int64_t)B + d] + 0.5 * sB * D.xcheb64[i] - D.bcenter[3 * (int64_t)A + d]) *
+                              (2.0 / sA);
+            float row[P];
+            lagrange_row<float>(P, xc, bw, (float)xi, row);
+            float *Bd = (d == 0) ? Bx : (d == 1) ? By : Bz;
+#pragma unroll
+            for (int a = 0; a < P; ++a) Bd[a * P + i] = row[a];
+        }
+        float *vA = work, *t1 = work + P3;
+        const float *src = D.local + (int64_t)D.local_slot[A] * P3;
+        for (int t = threadIdx.x; t < P3; t += TPB) vA[t] = src[t];
+        __syncthreads();
+        // x: t1[i0][(a1 a2)] = sum_a0 vA[a0][(a1 a2)] Mx[i0][a0]
+        mma_real_store<P, P2, P, NAT>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
+                                      [&](int x, int a, float v) { t1[a * P2 + x] = v; });
+        __syncthreads();
+        // y: t2[i0][i1][a2] = sum_a1 t1[i0][a1][a2] My[i1][a1]; rows x = (i0, a2)
+        float *t2 = vA;
+        mma_real_store<P, P2, P, NAT>([&](int x, int k) { return t1[(x / P) * P2 + k * P + (x % P)]; }, By,
+                                      [&](int x, int a, float v) { t2[(x / P) * P2 + a * P + (x % P)] = v; });
+        __syncthreads();
+        // z: acc[(i0 i1)][i2] = sum_a2 t2[(i0 i1)][a2] Mz[i2][a2]
+        mma_real_acc<P, P2, P, NSW, NAT>([&](int x, int k) { return t2[x * P + k]; }, Bz, acc);
+    }
+    if (D.psi_slot[B] >= 0) {
+        const int64_t nm = D.pwstride;
+        const float *psr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *psi = psr + nm;
+        float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
+        __syncthreads();
+        // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
+        mma_cplx_store<P, NM, NN, NAT>([&](int x, int k) { return psr[k * NM + x]; },
+                                       [&](int x, int k) { return psi[k * NM + x]; }, Br1, Bi1,
+                                       [&](int x, int a, float vr, float vi) {
+                                           A1r[a * NM + x] = vr;
+                                           A1i[a * NM + x] = vi;
+                                       });
+        // m2 then m3, G values of j1 at a time (G p rows: whole slabs)
+        for (int g0 = 0; g0 < P; g0 += G) {
+            const int g = min(G, P - g0);
+            __syncthreads();
+            // m2: B2[(j1 j2)][m3 | NH + m3] = sum_m2 conj(E[m2][j2]) A1[j1][m3][m2]; rows x = (j1 - g0, m3)
+            mma_cplx_store<P, G * NH, NN, NAT>(
+                [&](int x, int k) { return (x < g * NH) ? A1r[(g0 * NH + x) * NN + k] : 0.f; },
+                [&](int x, int k) { return (x < g * NH) ? A1i[(g0 * NH + x) * NN + k] : 0.f; }, Br1, Bi1,
+                [&](int x, int a, float vr, float vi) {
+                    if (x < g * NH) {
+                        const int j1 = x / NH, m3 = x % NH;
+                        B2[(j1 * P + a) * KP + m3] = vr;
+                        B2[(j1 * P + a) * KP + NH + m3] = vi;
+                    }
+                });
+            __syncthreads();
+            // m3: acc[(j1 j2)][j3] += sum_k' B2[(j1 j2)][k'] B3[k'][j3] for the slabs of this group
+            constexpr int NKS = (KP + 3) / 4;
+            float breg[NAT][NKS];
+#pragma unroll
+            for (int t = 0; t < NAT; ++t)
+#pragma unroll
+                for (int s = 0; s < NKS; ++s) {
+                    const int k = 4 * s + kq, a = 16 * t + r16;
+                    breg[t][s] = (k < KP && a < P) ? B3[k * P + a] : 0.f;
+                }
+            const int r0 = g0 * P, r1 = (g0 + g) * P;  // rows of this group, multiples of 16 at r0
+#pragma unroll
+            for (int i = 0; i < NSW; ++i) {
+                const int sl = w + NWAVE * i;
+                if (sl >= NSL || 16 * sl < r0 || 16 * sl >= r1) continue;
+                const int xa = 16 * sl + r16;
+#pragma unroll
+                for (int s = 0; s < NKS; ++s) {
+                    const int k = 4 * s + kq;
+                    const float av = (xa < r1 && k < KP) ? B2[(xa - r0) * KP + k] : 0.f;
+#pragma unroll
+                    for (int t = 0; t < NAT; ++t)
+                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[i][t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *dst = D.local + (int64_t)D.local_slot[B] * P3;
+#pragma unroll
+    for (int i = 0; i < NSW; ++i) {
+        const int sl = w + NWAVE * i;
+        if (sl >= NSL) break;
+#pragma unroll
+        for (int t = 0; t < NAT; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
+                if (x < P2 && a < P) dst[x * P + a] = acc[i][t][q];
+            }
+    }
+}
+
 // ------------------------------------------------------------ leaf targets
 // Lagrange basis of the nodes at xi with one division (prefix products of
 // the differences, Montgomery's batch inversion), barycentric weights bw.
@@ -1076,8 +1365,13 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
         int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];
         if (!nan) continue;
         StageScope t(Pl, s, DMK_STAGE_PW2GRID);
-        hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,
-                           Pl->l_anc + ll.anc_off[l], l);
+        const size_t lds_mfma = LocalMfma<P, NF>::lds();
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_local_mfma<P, NF>), dim3((unsigned)nan), dim3(TPB), lds_mfma, s, D,
+                               Pl->l_anc + ll.anc_off[l], l);
+        else
+            hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,
+                               Pl->l_anc + ll.anc_off[l], l);
     }
     if (Pl->nleaf) {
         {
@@ -1106,6 +1400,8 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
         allow_lds(k_upward<T, P>, C::lds_up());
         allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
         allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
+        const size_t lds_mfma = LocalMfma<P, NF>::lds();
+        if constexpr (sizeof(T) == 4) allow_lds(k_local_mfma<P, NF>, lds_mfma);
         allow_lds(k_leaf<T, P>, C::lds_leaf());
         attrs = true;
     }

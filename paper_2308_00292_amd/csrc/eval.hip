@@ -1486,13 +1486,15 @@ void upload_tables(Plan *P, hipStream_t s)
     P->d_ew = up(t.ew);
     P->d_wd0 = up(t.wd0);
     P->d_ww = up(t.ww);
-    P->d_gcheb = up(t.gcheb);
+    std::vector<double> gpad(t.gcheb);
+    gpad.resize(std::max<size_t>(gpad.size(), 48), 0.0);  // room for a fixed number of terms
+    P->d_gcheb = up(gpad);
     P->d_xcheb = up(t.xcheb);
     P->d_bary = up(t.bary);
     P->f_c2p = upf(t.c2p);
     P->f_epw = upf(t.epw);
     P->f_wd0 = upf(t.wd0);
-    P->f_gcheb = upf(t.gcheb);
+    P->f_gcheb = upf(gpad);
     P->f_xcheb = upf(t.xcheb);
     P->f_bary = upf(t.bary);
     DMK_HIP(hipStreamSynchronize(s));

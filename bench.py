@@ -51,6 +51,24 @@ WORKLOADS = {
 METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
 
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 PMC runs of
+# this script (--pmc FETCH_SIZE, then --pmc WRITE_SIZE, with --copy-calibration):
+# FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0, the factors that make the
+# elementwise copy of 1 GiB read and write exactly 1 GiB.  Keyed by workload,
+# precision and kernel, and valid only for the kernel source it was measured
+# on (digest of csrc/eval.hip); otherwise traffic is reported as null.
+TRAFFIC = {
+    ("cfg3_clustered_10m", "mixed", "k_local_mfma"): (1.0878e9, "aad4ea755583dc58"),
+}
+
+
+def eval_src_digest():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2308_00292_amd", "csrc", "eval.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -202,8 +220,12 @@ def main():
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
     kname = STAGE_KERNEL[dom] if offsets is None else STAGE_KERNEL2[dom]
+    if offsets is None and dom == "pw2grid" and prec == dmk.DMK_MIXED:
+        kname = "k_local_mfma"  # the FP32 path's local stage runs on the matrix cores
+    tr = TRAFFIC.get((args.workload, args.precision, kname))
+    traffic = tr[0] if (tr is not None and tr[1] == eval_src_digest()) else None
     roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "kernel": kname, "stage": dom,
+            "frac": achieved / peak, "traffic": traffic, "kernel": kname, "stage": dom,
             "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / nst}
     stages = {}
     for k in stage_ms:

@@ -155,6 +155,30 @@ dmk_status dmk_plan_batched(int dim, dmk_kernel kernel, double tol, int32_t npro
                             const double *pts, const dmk_opts *opts, void *stream, dmk_plan_t *out);
 
 /*
+ * dmk_tune_leaf -- the leaf-capacity tuner: picks n_s among candidates by
+ * timing dmk_eval on the caller's points and charges.
+ *
+ * Paper: n_s balances the cost of the local (residual) interactions against
+ * all other steps and is chosen by experiment (remark at the end of Sec.
+ * 3.6; Sec. 6.1 quotes the values used).  Every candidate gives a result
+ * within tol; only the time differs.
+ *
+ *  dim, kernel, tol, opts  as dmk_plan / dmk_plan_batched (opts->leaf_max is
+ *                          ignored; opts->flags and precision apply).
+ *  nprob, offsets          HOST offsets [nprob+1]; a single point set is
+ *                          nprob = 1, offsets = {0, n}.
+ *  pts, charges            device, as for dmk_plan_batched and dmk_eval.
+ *  cand                    HOST [ncand] leaf capacities (>= 1).
+ *  reps                    timed evaluations per candidate (after one warm-up).
+ *  best                    HOST, receives the fastest candidate.
+ *  ms                      HOST [ncand] or NULL: mean eval time of each (ms).
+ * Builds and destroys one plan per candidate; synchronous on `stream`.
+ */
+dmk_status dmk_tune_leaf(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *offsets,
+                         const double *pts, const double *charges, const dmk_opts *opts, const int32_t *cand,
+                         int32_t ncand, int32_t reps, void *stream, int32_t *best, double *ms);
+
+/*
  * dmk_problem_info -- root box of problem `prob` of a plan (input units):
  * centre [dim] and side, both HOST pointers (either may be NULL).
  */

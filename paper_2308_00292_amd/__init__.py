@@ -19,7 +19,7 @@ DMK_LAPLACE, DMK_YUKAWA = 0, 1
 DMK_FLAG_BATCHED = 2
 
 # exported symbols, in the order of include/dmk.h
-SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_problem_info", "dmk_eval", "dmk_eval_parts",
+SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_problem_info", "dmk_eval", "dmk_eval_parts",
            "dmk_plan_info", "dmk_export_tree", "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
            "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
            "dmk_plan_destroy", "dmk_last_error"]
@@ -63,6 +63,8 @@ def lib():
         L.dmk_plan_batched.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, C.POINTER(Opts), vp,
                                        C.POINTER(vp)]
         L.dmk_problem_info.argtypes = [vp, C.c_int32, f64p, f64p]
+        L.dmk_tune_leaf.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, vp, C.POINTER(Opts), vp,
+                                    C.c_int32, C.c_int32, vp, vp, vp]
         L.dmk_eval.argtypes = [vp, vp, vp, vp]
         L.dmk_eval_parts.argtypes = [vp, vp, vp, vp, vp]
         L.dmk_plan_info.argtypes = [vp, C.POINTER(Stats)]
@@ -99,6 +101,23 @@ def _ptr(t):
 
 def _np_ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def tune_leaf(pts, charges, candidates, tol=1e-6, precision=DMK_FP64, flags=0, reps=3, kernel=DMK_LAPLACE,
+              lam=0.0, offsets=None, stream=None):
+    """dmk_tune_leaf: (best leaf capacity, {candidate: mean eval ms})."""
+    pts = pts.contiguous()
+    q = charges.contiguous()
+    n, dim = int(pts.shape[0]), int(pts.shape[1])
+    off = np.ascontiguousarray([0, n] if offsets is None else offsets, dtype=np.int64)
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    ms = np.zeros(len(cand))
+    best = np.zeros(1, dtype=np.int32)
+    o = Opts(0, 0, precision, 0, flags, float(lam))
+    _check(lib().dmk_tune_leaf(dim, int(kernel), float(tol), len(off) - 1, _np_ptr(off), _ptr(pts), _ptr(q),
+                               C.byref(o), _np_ptr(cand), len(cand), int(reps), _stream_handle(stream),
+                               _np_ptr(best), _np_ptr(ms)))
+    return int(best[0]), dict(zip(cand.tolist(), ms.tolist()))
 
 
 def precompute_probe(tol, what, x=None, n=None):

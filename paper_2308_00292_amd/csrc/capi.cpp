@@ -193,6 +193,66 @@ dmk_status dmk_plan_batched(int dim, dmk_kernel kernel, double tol, int32_t npro
     });
 }
 
+dmk_status dmk_tune_leaf(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *offsets,
+                         const double *pts, const double *charges, const dmk_opts *opts, const int32_t *cand,
+                         int32_t ncand, int32_t reps, void *stream, int32_t *best, double *ms)
+{
+    return guarded([&] {
+        if (!cand || ncand < 1 || !best) throw Error{DMK_ERR_ARG, "candidates and best are required"};
+        if (reps < 1) throw Error{DMK_ERR_ARG, "reps must be >= 1"};
+        if (!offsets) throw Error{DMK_ERR_ARG, "offsets is NULL"};
+        for (int32_t i = 0; i < ncand; ++i)
+            if (cand[i] < 1) throw Error{DMK_ERR_ARG, "leaf capacities must be >= 1"};
+        const int64_t n = offsets[nprob > 0 ? nprob : 0];
+        if (n > 0 && !charges) throw Error{DMK_ERR_ARG, "charges is NULL"};
+        dmk_opts o;
+        std::memset(&o, 0, sizeof(o));
+        if (opts) o = *opts;
+        hipStream_t s = (hipStream_t)stream;
+        double *pot = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        DMK_HIP(hipMalloc(&pot, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
+        double bestms = 0.0;
+        int32_t bi = -1;
+        try {
+            DMK_HIP(hipEventCreate(&e0));
+            DMK_HIP(hipEventCreate(&e1));
+            for (int32_t i = 0; i < ncand; ++i) {
+                o.leaf_max = cand[i];
+                dmk_plan_t h = make_plan(dim, kernel, tol, nprob, offsets, pts, &o, stream);
+                Plan *P = reinterpret_cast<Plan *>(h);
+                float t = 0.0f;
+                try {
+                    run_eval(P, charges, pot, nullptr, nullptr, s);  // warm-up (and graph capture)
+                    DMK_HIP(hipEventRecord(e0, s));
+                    for (int32_t r = 0; r < reps; ++r) run_eval(P, charges, pot, nullptr, nullptr, s);
+                    DMK_HIP(hipEventRecord(e1, s));
+                    DMK_HIP(hipEventSynchronize(e1));
+                    DMK_HIP(hipEventElapsedTime(&t, e0, e1));
+                } catch (...) {
+                    (void)hipStreamSynchronize(s);
+                    plan_release(P);
+                    throw;
+                }
+                DMK_HIP(hipStreamSynchronize(s));
+                plan_release(P);
+                const double m = (double)t / reps;
+                if (ms) ms[i] = m;
+                if (bi < 0 || m < bestms) { bi = i; bestms = m; }
+            }
+        } catch (...) {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            (void)hipFree(pot);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipFree(pot);
+        *best = cand[bi];
+    });
+}
+
 dmk_status dmk_problem_info(dmk_plan_t plan, int32_t prob, double *center, double *side)
 {
     return guarded([&] {

@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 15
+    assert len(names) == 16
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:
@@ -55,6 +55,10 @@ def test_argument_errors_without_device():
     assert L.dmk_plan_batched(2, 0, 1e-6, 0, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
                               C.byref(h)) == -1  # nprob
     assert h.value is None
+    best = C.c_int32(0)
+    off2 = np.array([0, 10], dtype=np.int64)
+    assert L.dmk_tune_leaf(3, 0, 1e-6, 1, off2.ctypes.data_as(C.c_void_p), None, None, None, None, 0, 1, None,
+                           C.byref(best), None) == -1  # no candidates
     with pytest.raises(dmk.DmkError):
         dmk.precompute_probe(1e-7, 0, np.zeros(1))
     with pytest.raises(dmk.DmkError):

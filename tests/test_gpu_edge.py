@@ -83,3 +83,31 @@ def test_errors_become_status_codes():
     with pytest.raises(dmk.DmkError) as e:
         dmk.Plan(_dev(pts), tol=1e-6).box_data(0, 10 ** 9)
     assert e.value.status == -1
+
+
+def test_tune_leaf_picks_a_candidate():
+    """dmk_tune_leaf times every candidate n_s and returns the fastest; each
+    candidate's result is a valid DMK result (checked on the winner)."""
+    import numpy as np
+    import torch
+    import dmk_inputs
+    import paper_2308_00292_amd as dmk
+    import oracle
+    pts, q = dmk_inputs.uniform_cube(30000, 321)
+    dev = torch.device("cuda:0")
+    tp, tq = torch.from_numpy(pts).to(dev), torch.from_numpy(q).to(dev)
+    cand = [16, 32, 64, 128]
+    best, ms = dmk.tune_leaf(tp, tq, cand, precision=dmk.DMK_MIXED, flags=dmk.DMK_FLAG_BATCHED, reps=2)
+    assert best in cand and set(ms) == set(cand)
+    assert all(v > 0 for v in ms.values()) and ms[best] == min(ms.values())
+    plan = dmk.Plan(tp, tol=1e-6, leaf_max=best, precision=dmk.DMK_MIXED)
+    u = plan.eval(tq).cpu().numpy()
+    plan.close()
+    idx = np.random.default_rng(1).choice(len(q), 500, replace=False)
+    ud = oracle.direct(pts, q, idx)
+    assert np.linalg.norm(u[idx] - ud) / np.linalg.norm(ud) < 1e-5
+    # 2-D batch
+    off, p2, q2 = dmk_inputs.batch_2d(5, 9, nmin=500, nmax=3000)
+    best2, ms2 = dmk.tune_leaf(torch.from_numpy(p2).to(dev), torch.from_numpy(q2).to(dev), [32, 64],
+                               offsets=off, reps=1)
+    assert best2 in (32, 64)

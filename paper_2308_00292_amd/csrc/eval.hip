@@ -768,6 +768,66 @@ __device__ inline void mma_cplx_store(XR Xr, XI Xi, const float *Br, const float
     }
 }
 
+// complex mode product with X planar in global memory (row stride xs,
+// column k at k * ks): the next slab's operands are loaded while the current
+// slab's MFMAs run, to hide the HBM latency
+template <int P, int NX, int NK, int NAT, typename SF>
+__device__ inline void mma_cplx_store_global(const float *Xr, const float *Xi, int64_t ks, const float *Br,
+                                             const float *Bi, SF store)
+{
+    constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    float br[NAT][NKS], bi[NAT][NKS];
+#pragma unroll
+    for (int t = 0; t < NAT; ++t)
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq, a = 16 * t + r16;
+            const bool ok = k < NK && a < P;
+            br[t][s] = ok ? Br[k * P + a] : 0.f;
+            bi[t][s] = ok ? Bi[k * P + a] : 0.f;
+        }
+    float ar[NKS], ai[NKS];
+    auto fetch = [&](int sl, float (&fr)[NKS], float (&fi)[NKS]) {
+        const int xa = 16 * sl + r16;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq;
+            const bool ok = sl < NSL && xa < NX && k < NK;
+            fr[s] = ok ? Xr[k * ks + xa] : 0.f;
+            fi[s] = ok ? Xi[k * ks + xa] : 0.f;
+        }
+    };
+    fetch(w, ar, ai);
+    for (int sl = w; sl < NSL; sl += NWAVE) {
+        float nr[NKS], ni[NKS];
+        fetch(sl + NWAVE, nr, ni);
+        f32x4 cr[NAT], ci[NAT];
+#pragma unroll
+        for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const float nai = -ai[s];
+#pragma unroll
+            for (int t = 0; t < NAT; ++t) {
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], br[t][s], cr[t], 0, 0, 0);
+                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bi[t][s], cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bi[t][s], ci[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], br[t][s], ci[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NAT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
+                if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
+            }
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) { ar[s] = nr[s]; ai[s] = ni[s]; }
+    }
+}
+
 template <int P, int NF>
 __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32_t *list, int level)
 {
@@ -851,12 +911,10 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
         float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
         __syncthreads();
         // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
-        mma_cplx_store<P, NM, NN, NAT>([&](int x, int k) { return psr[k * NM + x]; },
-                                       [&](int x, int k) { return psi[k * NM + x]; }, Br1, Bi1,
-                                       [&](int x, int a, float vr, float vi) {
-                                           A1r[a * NM + x] = vr;
-                                           A1i[a * NM + x] = vi;
-                                       });
+        mma_cplx_store_global<P, NM, NN, NAT>(psr, psi, NM, Br1, Bi1, [&](int x, int a, float vr, float vi) {
+            A1r[a * NM + x] = vr;
+            A1i[a * NM + x] = vi;
+        });
         // m2 then m3, G values of j1 at a time (G p rows: whole slabs)
         for (int g0 = 0; g0 < P; g0 += G) {
             const int g = min(G, P - g0);

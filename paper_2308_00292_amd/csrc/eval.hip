@@ -1308,6 +1308,74 @@ __global__ void k_finalize(const double *ufar, const double *ures, const int32_t
 
 inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + TPB - 1) / TPB); }
 
+// Leaf targets of the FP32 path on matrix cores: per anchor, 16 targets per
+// wave at a time.  W((j1 j2), t) = sum_j3 v[(j1 j2)][j3] Lz_t[j3] is an MFMA
+// mode product (rows (j1 j2), columns the targets); each lane then folds its
+// four rows of W with Lx_t[j1] Ly_t[j2] and the four lanes of a target add up.
+template <int P>
+__global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *anc, const int32_t *tbeg,
+                                                   const int32_t *tgt)
+{
+    constexpr int P2 = P * P, P3 = P2 * P, NSL = (P2 + 15) / 16, NKS = (P + 3) / 4;
+    __shared__ float v[P3], xc[P], bw[P];
+    __shared__ float Lr[NWAVE][3][16][P];  // Lagrange rows x, y, z of the wave's 16 targets
+    const int a = blockIdx.x;
+    const int b0 = tbeg[a], b1 = tbeg[a + 1];
+    if (b0 == b1) return;  // whole block
+    const int32_t A = anc[a];
+    const float *src = D.local + (int64_t)a * P3;
+    for (int t = threadIdx.x; t < P3; t += TPB) v[t] = src[t];
+    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
+    const double cA[3] = {D.bcenter[3 * (int64_t)A], D.bcenter[3 * (int64_t)A + 1], D.bcenter[3 * (int64_t)A + 2]};
+    const double sc = 2.0 / box_side(D.blevel[A]);
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    __syncthreads();
+    for (int base = b0; base < b1; base += 16 * NWAVE) {
+        const int t = base + 16 * w + r16;
+        const bool tv = t < b1;
+        if (kq < 3) {
+            float row[P];
+            if (tv) {
+                const int64_t i = tgt[t];
+                const double x = (kq == 0) ? D.X[i] : (kq == 1) ? D.Y[i] : D.Z[i];
+                lagrange_row_fast<float, P>(xc, bw, (float)((x - cA[kq]) * sc), row);
+            } else {
+#pragma unroll
+                for (int j = 0; j < P; ++j) row[j] = 0.f;
+            }
+#pragma unroll
+            for (int j = 0; j < P; ++j) Lr[w][kq][r16][j] = row[j];
+        }
+        __syncthreads();
+        float bz[NKS];
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq;
+            bz[s] = (k < P) ? Lr[w][2][r16][k] : 0.f;
+        }
+        float part = 0.f;
+        for (int sl = 0; sl < NSL; ++sl) {
+            const int xa = 16 * sl + r16;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                const int k = 4 * s + kq;
+                const float av = (xa < P2 && k < P) ? v[xa * P + k] : 0.f;
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bz[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x = 16 * sl + 4 * kq + q;
+                if (x < P2) part += Lr[w][0][r16][x / P] * Lr[w][1][r16][x % P] * acc[q];
+            }
+        }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (kq == 0 && tv) D.ufar[tgt[t]] = (double)part;
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ host side
 template <typename T, int P, int NF>
 struct Cfg {
@@ -1434,8 +1502,12 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
     if (Pl->nleaf) {
         {
             StageScope t(Pl, s, DMK_STAGE_LEAF);
-            hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D, Pl->l_anc,
-                               Pl->anc_tbeg, Pl->anc_tgt);
+            if constexpr (sizeof(T) == 4)
+                hipLaunchKernelGGL((k_leaf_mfma<P>), dim3((unsigned)Pl->nanc), dim3(TPB), 0, s, D, Pl->l_anc,
+                                   Pl->anc_tbeg, Pl->anc_tgt);
+            else
+                hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D,
+                                   Pl->l_anc, Pl->anc_tbeg, Pl->anc_tgt);
         }
         if (side) {
             DMK_HIP(hipStreamWaitEvent(s, Pl->ev_join, 0));

@@ -1082,7 +1082,9 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     __syncthreads();
     const int nsrc = loff[L];
     const double cx = D.bcenter[3 * (int64_t)B], cy = D.bcenter[3 * (int64_t)B + 1], cz = D.bcenter[3 * (int64_t)B + 2];
-    const int tch = (nt <= 32) ? 32 : 64;
+    // one thread per target and source share; a leaf of nt <= 64 targets uses
+    // TPB/nt shares so that few threads idle
+    const int tch = nt < 64 ? max(nt, 1) : 64;
     const int nsplit = TPB / tch;
     const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
     for (int tbase = 0; tbase < nt; tbase += tch) {
@@ -1112,7 +1114,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
             }
             __syncthreads();
             T pacc = T(0);
-            for (int j = split; j < cnt; j += nsplit) {
+            for (int j = split; j < cnt && split < nsplit; j += nsplit) {
                 const T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T tt = r2 * sis2[j];

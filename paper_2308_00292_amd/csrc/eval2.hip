@@ -600,7 +600,9 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
     const T lam = D.kern ? (T)D.ylam[prob] : T(0);
     const T zero_val = (T)(-(D.m0 + Cb));  // plus slc of the source level
     const T k4pi = (T)(-1.0 / (4.0 * M_PI));
-    const int tch = (nt <= 32) ? 32 : 64;
+    // one thread per target and source share; a leaf of nt <= 64 targets uses
+    // TPB/nt shares so that few threads idle
+    const int tch = nt < 64 ? max(nt, 1) : 64;
     const int nsplit = TPB / tch;
     const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
     for (int tbase = 0; tbase < nt; tbase += tch) {
@@ -631,7 +633,7 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
             T pacc = T(0);
             if (D.kern) {
                 // K_0(lambda r) - M_l(r) for 0 < r < s_l; -M_l(0) at r = 0
-                for (int j = split; j < cnt; j += nsplit) {
+                for (int j = split; j < cnt && split < nsplit; j += nsplit) {
                     const T dx = xt - sx[j], dy = yt - sy[j];
                     const T r2 = dx * dx + dy * dy;
                     const T tt = r2 * sis2[j];
@@ -657,7 +659,7 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
                 acc += (double)pacc;
                 continue;
             }
-            for (int j = split; j < cnt; j += nsplit) {
+            for (int j = split; j < cnt && split < nsplit; j += nsplit) {
                 const T dx = xt - sx[j], dy = yt - sy[j];
                 const T r2 = dx * dx + dy * dy;
                 const T tt = r2 * sis2[j];

@@ -67,6 +67,22 @@ class _Split2(C.Structure):
                 ("coef", _f64p), ("self", _f64p)]
 
 
+class VParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("q", C.c_int), ("sigma0", C.c_double), ("p", C.c_int), ("nf", C.c_int),
+                ("nw", C.c_int), ("hw", C.c_double), ("nleg", C.c_int), ("tau_a", C.c_double),
+                ("tpan_gl", C.c_int), ("tpan_w", C.c_double)]
+
+
+class _VTree(C.Structure):
+    _fields_ = [("q", C.c_int), ("nleaf", C.c_int64), ("level", _i32p), ("ijk", _i32p)]
+
+
+class _VResult(C.Structure):
+    _fields_ = [("n", C.c_int64), ("u", _f64p), ("ufar", _f64p), ("unear", _f64p), ("utail", _f64p)]
+
+
+DENSITY_FN = C.CFUNCTYPE(None, C.c_int64, _f64p, _f64p, C.c_void_p)
+
 LOG2, YUK2 = 0, 1  # 2-D kernels: -log(r)/(2 pi) and K_0(lambda r)
 
 _lib = None
@@ -131,6 +147,25 @@ def lib():
         L.orc_dmk2_eval.argtypes = [_P(_Tree), _P(Params), _P(Pswf), C.c_int, C.c_double, _f64p, C.c_int,
                                     _P(_Result)]
         L.orc_direct2.argtypes = [C.c_int, C.c_double, C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
+        # volume
+        L.orc_vparams_for.argtypes = [C.c_double, C.c_int, _P(VParams)]
+        for f in ("orc_gsplit_m", "orc_gsplit_d", "orc_gsplit_r", "orc_gdhat"):
+            getattr(L, f).argtypes = [_P(VParams), C.c_int, C.c_double]
+            getattr(L, f).restype = C.c_double
+        L.orc_gw0hat.argtypes = [_P(VParams), C.c_double]
+        L.orc_gw0hat.restype = C.c_double
+        L.orc_gsplit_d_pw.argtypes = [_P(VParams), C.c_int, _f64p]
+        L.orc_gsplit_d_pw.restype = C.c_double
+        L.orc_gsplit_w0_pw.argtypes = [_P(VParams), _f64p]
+        L.orc_gsplit_w0_pw.restype = C.c_double
+        L.orc_vsog.argtypes = [_P(VParams), C.c_double, C.c_double, _f64p, _f64p]
+        L.orc_vsog_count.argtypes = [_P(VParams), C.c_double, C.c_double]
+        L.orc_vtree_build.argtypes = [_P(VParams), C.c_double, C.c_int, C.c_int, DENSITY_FN, C.c_void_p,
+                                      _P(_VTree)]
+        L.orc_vtree_free.argtypes = [_P(_VTree)]
+        L.orc_vol_nodes.argtypes = [_P(_VTree), _f64p]
+        L.orc_vol_eval.argtypes = [_P(_VTree), _P(VParams), _f64p, _P(_VResult)]
+        L.orc_vol_result_free.argtypes = [_P(_VResult)]
         _lib = L
     return _lib
 
@@ -403,3 +438,99 @@ def direct2(kern, lam, pts, charges, tidx=None):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------- volume
+def vparams_for(tol: float = 1e-3, q: int = 8) -> VParams:
+    vp = VParams()
+    if lib().orc_vparams_for(tol, q, C.byref(vp)) != 0:
+        raise ValueError(f"unsupported volume parameters tol={tol} q={q}")
+    return vp
+
+
+class GSplit:
+    """Gaussian multilevel split of 1/r (unscaled, root box side 1)."""
+
+    def __init__(self, vp: VParams):
+        self.vp = vp
+
+    def m(self, l, r):
+        return lib().orc_gsplit_m(C.byref(self.vp), int(l), float(r))
+
+    def d(self, l, r):
+        return lib().orc_gsplit_d(C.byref(self.vp), int(l), float(r))
+
+    def r(self, l, r):
+        return lib().orc_gsplit_r(C.byref(self.vp), int(l), float(r))
+
+    def dhat(self, l, k):
+        return lib().orc_gdhat(C.byref(self.vp), int(l), float(k))
+
+    def w0hat(self, k):
+        return lib().orc_gw0hat(C.byref(self.vp), float(k))
+
+    def d_pw(self, l, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_gsplit_d_pw(C.byref(self.vp), int(l), _dp(x))
+
+    def w0_pw(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_gsplit_w0_pw(C.byref(self.vp), _dp(x))
+
+    def sog(self, t_lo, t_hi):
+        n = lib().orc_vsog_count(C.byref(self.vp), float(t_lo), float(t_hi))
+        t = np.zeros(max(n, 1))
+        w = np.zeros(max(n, 1))
+        lib().orc_vsog(C.byref(self.vp), float(t_lo), float(t_hi), _dp(t), _dp(w))
+        return t[:n], w[:n]
+
+
+def density_callback(f):
+    """Wrap f(xyz[n,3]) -> rho[n] as the C density callback."""
+    def cb(n, xyz, out, ctx):
+        x = np.ctypeslib.as_array(xyz, shape=(n * 3,)).reshape(n, 3)
+        o = np.ctypeslib.as_array(out, shape=(n,))
+        o[:] = f(x)
+    return DENSITY_FN(cb)
+
+
+class VTree:
+    """Leaves (level, cell) of the volume tree, in Morton order."""
+
+    def __init__(self, vp: VParams, density, rho_scale: float, min_level: int = 0, max_level: int = 12):
+        self.vp = vp
+        self._t = _VTree()
+        self._cb = density_callback(density)
+        rc = lib().orc_vtree_build(C.byref(vp), float(rho_scale), int(min_level), int(max_level), self._cb, None,
+                                   C.byref(self._t))
+        if rc != 0:
+            raise RuntimeError("orc_vtree_build failed")
+        n = self._t.nleaf
+        self.q, self.nleaf = vp.q, n
+        self.level = np.ctypeslib.as_array(self._t.level, shape=(n,)).copy()
+        self.ijk = np.ctypeslib.as_array(self._t.ijk, shape=(n * 3,)).reshape(n, 3).copy()
+
+    def nodes(self):
+        q3 = self.q ** 3
+        xyz = np.zeros((self.nleaf * q3, 3))
+        lib().orc_vol_nodes(C.byref(self._t), _dp(xyz))
+        return xyz
+
+    def eval(self, rho):
+        """Potential at the leaf nodes; returns dict u, ufar, unear, utail."""
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        if rho.shape != (self.nleaf * self.q ** 3,):
+            raise ValueError("rho must hold nleaf*q^3 node values")
+        res = _VResult()
+        if lib().orc_vol_eval(C.byref(self._t), C.byref(self.vp), _dp(rho), C.byref(res)) != 0:
+            raise RuntimeError("orc_vol_eval failed")
+        n = res.n
+        out = {k: np.ctypeslib.as_array(getattr(res, k), shape=(n,)).copy() for k in ("u", "ufar", "unear", "utail")}
+        lib().orc_vol_result_free(C.byref(res))
+        return out
+
+    def __del__(self):
+        try:
+            lib().orc_vtree_free(C.byref(self._t))
+        except Exception:
+            pass

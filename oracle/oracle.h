@@ -191,6 +191,55 @@ int  orc_dmk2_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
 void orc_direct2(int kern, double lam, int64_t n, const double *pts, const double *q,
                  int64_t nt, const int64_t *tidx, double *out);
 
+/* --------------------------------------------------------------- volume
+ * Volume potential u(x) = int_{B_0} rho(y)/(4 pi |x-y|) dy on the unit cube
+ * B_0 = [-1/2,1/2]^3 with the Gaussian multilevel split (Sec. 3.2) and the
+ * continuous-source modifications of Sec. 3.6 and Sec. 4.4; see vol.c. */
+typedef struct {
+    double tol;
+    int    q;        /* leaf grid: q Chebyshev nodes per axis               */
+    double sigma0;   /* Gaussian width at level 0, 1/sqrt(log(1/tol))        */
+    int    p, nf;    /* proxy order; plane-wave half width of D_l            */
+    int    nw;       /* plane-wave half width of the windowed W_0            */
+    double hw;       /* its spacing                                          */
+    int    nleg;     /* Gauss-Legendre nodes per axis for proxy charges      */
+    double tau_a;    /* t_a = tau_a / (target leaf side)                     */
+    int    tpan_gl;  /* Gauss-Legendre nodes per panel in log t              */
+    double tpan_w;   /* panel width in log t                                 */
+} orc_vparams;
+int orc_vparams_for(double tol, int q, orc_vparams *vp);  /* tol 1e-3 */
+
+double orc_gsplit_m(const orc_vparams *vp, int l, double r);   /* erf(r/s_l)/r */
+double orc_gsplit_d(const orc_vparams *vp, int l, double r);   /* D_l          */
+double orc_gsplit_r(const orc_vparams *vp, int l, double r);   /* R_l          */
+double orc_gdhat(const orc_vparams *vp, int l, double k);
+double orc_gw0hat(const orc_vparams *vp, double k);
+double orc_gsplit_d_pw(const orc_vparams *vp, int l, const double x[3]);
+double orc_gsplit_w0_pw(const orc_vparams *vp, const double x[3]);
+int    orc_vsog(const orc_vparams *vp, double t_lo, double t_hi, double *t, double *w);
+int    orc_vsog_count(const orc_vparams *vp, double t_lo, double t_hi);
+
+/* density callback: out[i] = rho(xyz[3i..3i+2]) for i < n */
+typedef void (*orc_density_fn)(int64_t n, const double *xyz, double *out, void *ctx);
+typedef struct {
+    int      q;
+    int64_t  nleaf;
+    int32_t *level;  /* [nleaf], leaves in Morton order                      */
+    int32_t *ijk;    /* [nleaf][3] integer cell of the leaf at its level      */
+} orc_vtree;
+int  orc_vtree_build(const orc_vparams *vp, double rho_scale, int minlevel, int maxlevel,
+                     orc_density_fn fn, void *ctx, orc_vtree *t);  /* maxlevel <= 19 */
+void orc_vtree_free(orc_vtree *t);
+/* leaf node coordinates [nleaf*q^3][3], leaf-major, node (i,j,k) with k fastest,
+ * coordinate c + (s/2) cos(pi (i + 1/2)/q) per axis */
+void orc_vol_nodes(const orc_vtree *t, double *xyz);
+typedef struct {
+    int64_t n;
+    double *u, *ufar, *unear, *utail;  /* [n] at the leaf nodes, times 1/(4 pi) */
+} orc_vol_result;
+int  orc_vol_eval(const orc_vtree *t, const orc_vparams *vp, const double *rho, orc_vol_result *res);
+void orc_vol_result_free(orc_vol_result *r);
+
 #ifdef __cplusplus
 }
 #endif

@@ -106,3 +106,29 @@ def make(name: str, n: int | None = None):
     gen, n0, seed, ns = CONFIGS[name]
     pts, q = gen(n0 if n is None else n, seed)
     return pts, q, ns
+
+
+# ------------------------------------------------------------ volume densities
+def vol_gaussians(seed, n=8, smin=1e-3, smax=1e-1, box=0.3, amp=1.0):
+    """n Gaussians exp(-|x - c|^2 / s^2) with s = exp(U[ln smin, ln smax]) and
+    centres c ~ U[-box, box]^3, peak value amp each.  Returns (s[n], c[n,3],
+    a[n])."""
+    rng = np.random.default_rng(seed)
+    sig = np.exp(rng.uniform(np.log(smin), np.log(smax), n))
+    cen = rng.uniform(-box, box, (n, 3))
+    return sig, cen, np.full(n, float(amp))
+
+
+def gaussian_mixture(x, sig, cen, amp):
+    """sum_i a_i exp(-|x - c_i|^2 / s_i^2) at points x[m, 3]."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros(len(x))
+    for s, c, a in zip(sig, cen, amp):
+        out += a * np.exp(-np.sum((x - c) ** 2, axis=1) / (s * s))
+    return out
+
+
+def gaussian_features(sig, cen, factor=4.0):
+    """Feature points (x, y, z, h) asking for boxes of side <= factor * s at
+    each centre."""
+    return np.hstack([np.asarray(cen, dtype=np.float64), factor * np.asarray(sig, dtype=np.float64)[:, None]])

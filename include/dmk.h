@@ -11,14 +11,23 @@
  *     K(r) = 1 / (4 pi r)        (3-D Laplace, eq. laplacesum), or
  *     K(r) = -log(r) / (2 pi)    (2-D Laplace),
  *
- * to a requested relative precision tol, with the O(N) scheme of Sec. 3.5-3.6
- * ("The linear scaling full DMK algorithm", "The full DMK algorithm for
- * discrete sources"), the PSWF kernel split of Sec. 3.7 in 3-D and its
- * Fourier-space form (Sec. 4.4, with the windowed root kernel of Sec. 4.5)
- * in 2-D.  Pairs at distance exactly zero (the self pair and coincident
- * points) contribute nothing.  A plan may hold many independent 2-D point
- * sets (dmk_plan_batched); each is solved in its own root box and every
- * stage runs over the boxes of all of them at once.
+ * to a requested relative precision tol, with the O(N) scheme of Sec. 3.3
+ * and Sec. 3.5 ("The linear scaling full DMK algorithm", "The full DMK
+ * algorithm for discrete sources"), the PSWF kernel split of Sec. 3.7 in
+ * 3-D and its Fourier-space form (Sec. 4.6, with the windowed root kernel of
+ * Sec. 4.7) in 2-D, where K(r) = K_0(lambda r) is also available.  Pairs at
+ * distance exactly zero (the self pair and coincident points) contribute
+ * nothing.  A plan may hold many independent 2-D point sets
+ * (dmk_plan_batched); each is solved in its own root box and every stage
+ * runs over the boxes of all of them at once.
+ *
+ * The volume entry points (dmk_vol_*) compute the continuous convolution
+ *
+ *     u(x) = int_{B_0} rho(y) / (4 pi |x - y|) dy,   B_0 = [-1/2, 1/2]^3,
+ *
+ * at the Chebyshev nodes of an adaptive tree that resolves rho (Sec. 3.6,
+ * "Modification of DMK for continuous sources"), with the Gaussian split of
+ * Sec. 3.2 and a sum-of-Gaussians near field (Sec. 3.6, Sec. 4.4).
  *
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers (memory of the current HIP
@@ -27,8 +36,7 @@
  *    stream.  Work is enqueued on it asynchronously unless stated otherwise.
  *  - Status codes only; no C++ exception crosses the ABI.  After a non-zero
  *    status, dmk_last_error() returns a message for the calling thread.
- *  - Implemented: DMK_LAPLACE in 2-D and 3-D.  DMK_YUKAWA returns
- *    DMK_ERR_UNSUPPORTED.
+ *  - Implemented: DMK_LAPLACE in 2-D and 3-D; DMK_YUKAWA in 2-D.
  */
 #ifndef DMK_H
 #define DMK_H
@@ -50,7 +58,7 @@ typedef enum {
 } dmk_status;
 
 /* DMK_LAPLACE: 1/(4 pi r) in 3-D, -log(r)/(2 pi) in 2-D.
- * DMK_YUKAWA: K_0(lambda r) in 2-D (not built: DMK_ERR_UNSUPPORTED). */
+ * DMK_YUKAWA: K_0(lambda r) in 2-D (lambda in dmk_opts). */
 typedef enum { DMK_LAPLACE = 0, DMK_YUKAWA = 1 } dmk_kernel;
 
 /* Arithmetic of the eval pipeline.  Input and output are always FP64. */
@@ -335,6 +343,87 @@ dmk_status dmk_stage_times(dmk_plan_t plan, double *ms, int64_t *launches, int n
  * The per-unit figures are documented beside the kernels.
  */
 dmk_status dmk_stage_work(dmk_plan_t plan, double *flops, double *bytes, int nstages);
+
+/* ------------------------------------------------------------ volume code
+ * Continuous sources (Sec. 3.6, "Modification of DMK for continuous
+ * sources").  Domain: the unit cube B_0 = [-1/2,1/2]^3 (fixed; no scaling).
+ *
+ * Tree.  Level-restricted adaptive octree whose leaves carry q x q x q
+ * first-kind Chebyshev nodes; leaf B with centre c and side s has node
+ * (i, j, k) at c + (s/2) (cos(pi (i+1/2)/q), cos(pi (j+1/2)/q),
+ * cos(pi (k+1/2)/q)).  A box is split while its level is below min_level or
+ * while the sum of |c_ijk| over the coefficients of the Chebyshev
+ * interpolant of rho on its nodes with max(i,j,k) >= q-2 exceeds
+ * tol * rho_scale, or while it contains a caller-given feature point whose
+ * requested side is below its own (node samples cannot see features much
+ * narrower than the node spacing), up to max_level; then the minimal
+ * refinement that makes adjacent leaves (face, edge or corner) differ by at
+ * most one level.
+ * Leaves are ordered by Morton key (x most significant).  Point layout of
+ * every node array: leaf-major in that order, node (i, j, k) with k fastest,
+ * [npoints] for values, [npoints][3] for coordinates.
+ *
+ * Split.  1/r = W_0 + sum_{l<L} D_l + R_L with Gaussians (Sec. 3.2, eqs.
+ * mlks, kerneldef, deltavalue): sigma_l = 2^-l / sqrt(log(1/tol)).  Proxy
+ * charges of a leaf: Gauss-Legendre weights times rho at the Legendre nodes,
+ * anterpolated to the parent's Chebyshev grid.  Far field on the anchors'
+ * grids, evaluated at the leaf nodes.  Near field: R_L of each source leaf as
+ * a sum of Gaussians (Gauss-Legendre in log t from 1/sigma_L to
+ * t_a = 2 tol^(-1/6) / s_target), each separable into three q x q matrices
+ * per (source, target) pair; Gaussians beyond t_a over R^3 by the expansion
+ * rho + Lap rho/(4t^2) + Lap^2 rho/(32 t^4) of the target leaf's polynomial
+ * (Sec. 4.4).  That expansion extends rho's polynomial beyond B_0 for nodes
+ * within about 3/t_a of the boundary, so densities that do not vanish on the
+ * boundary of B_0 carry an error there of the order of that part.
+ */
+
+/* density callback: out[i] = rho(xyz[3i], xyz[3i+1], xyz[3i+2]), i < n
+ * (HOST arrays, called from the planning thread, in batches of up to all
+ * boxes of one level) */
+typedef void (*dmk_density_fn)(int64_t n, const double *xyz, double *out, void *ctx);
+
+/*
+ * dmk_vol_plan -- build the tree (host, by calls of `density`), then the box
+ * structures, lists and tables on the device.
+ *  tol        1e-3 (p = 18 proxies, 25 plane waves per axis; else
+ *             DMK_ERR_UNSUPPORTED).
+ *  q          8 (leaf grid order; else DMK_ERR_UNSUPPORTED).
+ *  rho_scale  > 0, the density magnitude the refinement tolerance is
+ *             relative to.
+ *  min_level  >= 1 (the root is always split), <= max_level.
+ *  max_level  <= 19.
+ *  nfeat, feat  HOST array feat[nfeat][4] = (x, y, z, h): every box that
+ *             contains (x, y, z) (lo <= x < hi per axis) is split while its
+ *             side exceeds h > 0; nfeat may be 0 (feat NULL).
+ *  opts       precision DMK_FP64 only (DMK_MIXED: DMK_ERR_UNSUPPORTED);
+ *             leaf_max, max_depth, lambda ignored; NULL for defaults.
+ *  stream     for the device work; returns after it completes.
+ * The plan holds at most 2^31 - 1 nodes (nleaf q^3).  Free with
+ * dmk_plan_destroy.  A volume plan is evaluated with dmk_vol_eval only.
+ */
+dmk_status dmk_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_level, int32_t max_level,
+                        int32_t nfeat, const double *feat, dmk_density_fn density, void *ctx,
+                        const dmk_opts *opts, void *stream, dmk_plan_t *out);
+
+/* dmk_vol_info -- number of leaves and of nodes (nleaf q^3) of a volume plan */
+dmk_status dmk_vol_info(dmk_plan_t plan, int64_t *nleaf, int64_t *npoints);
+
+/* dmk_vol_leaves -- the leaves (HOST arrays): level[nleaf] and the integer
+ * cell ijk[nleaf][3] of each leaf at its level (0 <= ijk < 2^level). */
+dmk_status dmk_vol_leaves(dmk_plan_t plan, int32_t *level, int32_t *ijk);
+
+/* dmk_vol_nodes -- node coordinates, DEVICE array xyz[npoints][3] */
+dmk_status dmk_vol_nodes(dmk_plan_t plan, double *xyz, void *stream);
+
+/*
+ * dmk_vol_eval -- u at every node from rho at every node (DEVICE arrays
+ * [npoints], layout above).  far_part / near_part (DEVICE, [npoints], may be
+ * NULL) receive the far-field part and the near-field part (sum of Gaussians
+ * plus the asymptotic part); u = far_part + near_part.  u may be NULL when a
+ * part is requested.  Asynchronous on `stream`.
+ */
+dmk_status dmk_vol_eval(dmk_plan_t plan, const double *rho, double *u, double *far_part, double *near_part,
+                        void *stream);
 
 /* dmk_plan_destroy -- free a plan (NULL is ignored).  Synchronises the
  * plan's last stream first. */

@@ -160,8 +160,8 @@ def lib():
         L.orc_gsplit_w0_pw.restype = C.c_double
         L.orc_vsog.argtypes = [_P(VParams), C.c_double, C.c_double, _f64p, _f64p]
         L.orc_vsog_count.argtypes = [_P(VParams), C.c_double, C.c_double]
-        L.orc_vtree_build.argtypes = [_P(VParams), C.c_double, C.c_int, C.c_int, DENSITY_FN, C.c_void_p,
-                                      _P(_VTree)]
+        L.orc_vtree_build.argtypes = [_P(VParams), C.c_double, C.c_int, C.c_int, C.c_int, _f64p, DENSITY_FN,
+                                      C.c_void_p, _P(_VTree)]
         L.orc_vtree_free.argtypes = [_P(_VTree)]
         L.orc_vol_nodes.argtypes = [_P(_VTree), _f64p]
         L.orc_vol_eval.argtypes = [_P(_VTree), _P(VParams), _f64p, _P(_VResult)]
@@ -497,12 +497,15 @@ def density_callback(f):
 class VTree:
     """Leaves (level, cell) of the volume tree, in Morton order."""
 
-    def __init__(self, vp: VParams, density, rho_scale: float, min_level: int = 0, max_level: int = 12):
+    def __init__(self, vp: VParams, density, rho_scale: float, min_level: int = 0, max_level: int = 12,
+                 features=None):
         self.vp = vp
         self._t = _VTree()
         self._cb = density_callback(density)
-        rc = lib().orc_vtree_build(C.byref(vp), float(rho_scale), int(min_level), int(max_level), self._cb, None,
-                                   C.byref(self._t))
+        feat = np.ascontiguousarray(np.zeros((0, 4)) if features is None else features, dtype=np.float64)
+        self._feat = feat
+        rc = lib().orc_vtree_build(C.byref(vp), float(rho_scale), int(min_level), int(max_level), len(feat),
+                                   _dp(feat), self._cb, None, C.byref(self._t))
         if rc != 0:
             raise RuntimeError("orc_vtree_build failed")
         n = self._t.nleaf

@@ -227,8 +227,11 @@ typedef struct {
     int32_t *level;  /* [nleaf], leaves in Morton order                      */
     int32_t *ijk;    /* [nleaf][3] integer cell of the leaf at its level      */
 } orc_vtree;
+/* feat: [nfeat][4] points (x, y, z, h): boxes containing one are split while
+ * their side exceeds h */
 int  orc_vtree_build(const orc_vparams *vp, double rho_scale, int minlevel, int maxlevel,
-                     orc_density_fn fn, void *ctx, orc_vtree *t);  /* maxlevel <= 19 */
+                     int nfeat, const double *feat, orc_density_fn fn, void *ctx,
+                     orc_vtree *t);  /* maxlevel <= 19 */
 void orc_vtree_free(orc_vtree *t);
 /* leaf node coordinates [nleaf*q^3][3], leaf-major, node (i,j,k) with k fastest,
  * coordinate c + (s/2) cos(pi (i + 1/2)/q) per axis */

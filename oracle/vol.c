@@ -35,9 +35,11 @@
  * the GPU path, made independently there):
  *   - leaf nodes: first-kind Chebyshev points cos(pi (i + 1/2)/q) per axis;
  *   - refinement: a box is split when the sum of |c_ijk| over its Chebyshev
- *     coefficients with max(i,j,k) >= q-2 exceeds tol * rho_scale, or while
- *     its level is below min_level; then the minimal 2:1 balanced refinement
- *     (face, edge and corner adjacency);
+ *     coefficients with max(i,j,k) >= q-2 exceeds tol * rho_scale, while its
+ *     level is below min_level, or while it contains a caller-given feature
+ *     point (x, y, z, h) with h below its side (lo <= x < hi per axis): node
+ *     samples cannot see features much narrower than the node spacing; then
+ *     the minimal 2:1 balanced refinement (face, edge and corner adjacency);
  *   - proxy charges use p Gauss-Legendre nodes per axis (exact for the
  *     degree (p-1) + (q-1) products);
  *   - residual pairs: the source-centric lists of the point code (targets in
@@ -294,8 +296,25 @@ static int vbox_cmp_key(const void *a, const void *b)
     return x->l < y->l ? -1 : x->l > y->l;
 }
 
+/* does box (l, c) contain a feature point asking for a side below its own? */
+static int feature_split(int l, const int32_t c[3], int nfeat, const double *feat)
+{
+    const double s = ldexp(1.0, -l);
+    for (int f = 0; f < nfeat; ++f) {
+        const double *F = feat + 4 * f;
+        if (!(F[3] < s)) continue;
+        int in = 1;
+        for (int d = 0; d < 3; ++d) {
+            double lo = -0.5 + c[d] * s, hi = lo + s;
+            in &= (F[d] >= lo) && (F[d] < hi);
+        }
+        if (in) return 1;
+    }
+    return 0;
+}
+
 int orc_vtree_build(const orc_vparams *vp, double rho_scale, int minlevel, int maxlevel,
-                    orc_density_fn fn, void *ctx, orc_vtree *t)
+                    int nfeat, const double *feat, orc_density_fn fn, void *ctx, orc_vtree *t)
 {
     memset(t, 0, sizeof(*t));
     const int q = vp->q, q3 = q * q * q;
@@ -319,7 +338,8 @@ int orc_vtree_build(const orc_vparams *vp, double rho_scale, int minlevel, int m
                             node_coord(q, l, cur[b].c, i, j, k, &xyz[3 * (b * q3 + (i * q + j) * q + k)]);
             if (l >= minlevel) fn(ncur * q3, xyz, f, ctx);
             for (int64_t b = 0; b < ncur; ++b)
-                split[b] = (l < minlevel) || tail_coef(q, f + b * q3) > vp->tol * rho_scale;
+                split[b] = (l < minlevel) || feature_split(l, cur[b].c, nfeat, feat) ||
+                           tail_coef(q, f + b * q3) > vp->tol * rho_scale;
             free(xyz);
             free(f);
         }

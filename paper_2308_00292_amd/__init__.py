@@ -22,7 +22,11 @@ DMK_FLAG_BATCHED = 2
 SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_problem_info", "dmk_eval", "dmk_eval_parts",
            "dmk_plan_info", "dmk_export_tree", "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
            "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
+           "dmk_vol_plan", "dmk_vol_info", "dmk_vol_leaves", "dmk_vol_nodes", "dmk_vol_eval",
            "dmk_plan_destroy", "dmk_last_error"]
+
+# density callback of dmk_vol_plan: (n, xyz[3n], out[n], ctx), host arrays
+DENSITY_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
 
 STAGES = ["gather", "upward", "root", "proxy2pw", "local", "pwshift", "pw2grid", "leaf",
           "residual", "finalize"]
@@ -75,6 +79,12 @@ def lib():
         L.dmk_stage_timing.argtypes = [vp, C.c_int]
         L.dmk_stage_times.argtypes = [vp, vp, vp, C.c_int]
         L.dmk_stage_work.argtypes = [vp, vp, vp, C.c_int]
+        L.dmk_vol_plan.argtypes = [C.c_double, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int32, vp,
+                                   DENSITY_FN, vp, C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.dmk_vol_info.argtypes = [vp, vp, vp]
+        L.dmk_vol_leaves.argtypes = [vp, vp, vp]
+        L.dmk_vol_nodes.argtypes = [vp, vp, vp]
+        L.dmk_vol_eval.argtypes = [vp, vp, vp, vp, vp, vp]
         L.dmk_plan_destroy.argtypes = [vp]
         L.dmk_plan_destroy.restype = None
         L.dmk_last_error.restype = C.c_char_p
@@ -247,3 +257,74 @@ class Plan:
         _check(lib().dmk_copy_box_data(self._h, int(what), int(box),
                                        out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
+
+
+class VolPlan:
+    """dmk_vol_plan: volume potential of a density on the unit cube.
+    ``density`` maps host coordinates [n, 3] (numpy) to values [n]; it is
+    called while the tree is built.  eval(rho) maps node values (CUDA float64
+    [npoints]) to potentials at the same nodes."""
+
+    def __init__(self, density, tol=1e-3, q=8, rho_scale=1.0, min_level=1, max_level=12, features=None,
+                 stream=None):
+        def cb(n, xyz, out, ctx):
+            x = np.ctypeslib.as_array(xyz, shape=(n * 3,)).reshape(n, 3)
+            o = np.ctypeslib.as_array(out, shape=(n,))
+            o[:] = density(x)
+        self._cb = DENSITY_FN(cb)
+        o = Opts(0, 0, DMK_FP64, 0, 0, 0.0)
+        h = C.c_void_p()
+        feat = np.ascontiguousarray(np.zeros((0, 4)) if features is None else features, dtype=np.float64)
+        _check(lib().dmk_vol_plan(float(tol), int(q), float(rho_scale), int(min_level), int(max_level), len(feat),
+                                  _np_ptr(feat) if len(feat) else None, self._cb, None, C.byref(o),
+                                  _stream_handle(stream), C.byref(h)))
+        self._h = h
+        nl = np.zeros(1, np.int64)
+        npt = np.zeros(1, np.int64)
+        _check(lib().dmk_vol_info(self._h, _np_ptr(nl), _np_ptr(npt)))
+        self.nleaf, self.n, self.q = int(nl[0]), int(npt[0]), int(q)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmk_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def leaves(self):
+        lev = np.zeros(self.nleaf, np.int32)
+        ijk = np.zeros((self.nleaf, 3), np.int32)
+        _check(lib().dmk_vol_leaves(self._h, _np_ptr(lev), _np_ptr(ijk)))
+        return lev, ijk
+
+    def nodes(self, stream=None):
+        import torch
+        xyz = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        _check(lib().dmk_vol_nodes(self._h, _ptr(xyz), _stream_handle(stream)))
+        return xyz
+
+    def eval(self, rho, out=None, parts=False, stream=None):
+        """u at the nodes; with parts=True returns (u, far, near)."""
+        import torch
+        r = rho.contiguous()
+        if r.dtype != torch.float64 or not r.is_cuda or r.numel() != self.n:
+            raise TypeError("rho must be a float64 CUDA tensor with one value per node")
+        if out is None:
+            out = torch.empty_like(r)
+        far = torch.empty_like(r) if parts else None
+        near = torch.empty_like(r) if parts else None
+        _check(lib().dmk_vol_eval(self._h, _ptr(r), _ptr(out), _ptr(far), _ptr(near), _stream_handle(stream)))
+        return (out, far, near) if parts else out
+
+    def stage_timing(self, enable=True):
+        _check(lib().dmk_stage_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), np.int64)
+        _check(lib().dmk_stage_times(self._h, _np_ptr(ms), _np_ptr(cnt), len(STAGES)))
+        return dict(zip(STAGES, ms)), dict(zip(STAGES, cnt))

@@ -270,6 +270,7 @@ dmk_status dmk_eval_parts(dmk_plan_t plan, const double *charges, double *far_pa
     return guarded([&] {
         if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
         Plan *P = reinterpret_cast<Plan *>(plan);
+        if (P->is_vol) throw Error{DMK_ERR_ARG, "a volume plan is evaluated with dmk_vol_eval"};
         if (P->n > 0 && !charges) throw Error{DMK_ERR_ARG, "charges is NULL"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
@@ -283,10 +284,70 @@ dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *s
     return guarded([&] {
         if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
         Plan *P = reinterpret_cast<Plan *>(plan);
+        if (P->is_vol) throw Error{DMK_ERR_ARG, "a volume plan is evaluated with dmk_vol_eval"};
         if (P->n > 0 && (!charges || !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
         run_eval(P, charges, pot, nullptr, nullptr, s);
+        P->last_stream = s;
+    });
+}
+
+dmk_status dmk_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_level, int32_t max_level,
+                        int32_t nfeat, const double *feat, dmk_density_fn density, void *ctx, const dmk_opts *opts,
+                        void *stream, dmk_plan_t *out)
+{
+    return guarded([&] {
+        if (!out) throw Error{DMK_ERR_ARG, "out is NULL"};
+        *out = nullptr;
+        *out = make_vol_plan(tol, q, rho_scale, min_level, max_level, nfeat, feat, density, ctx, opts, stream);
+    });
+}
+
+dmk_status dmk_vol_info(dmk_plan_t plan, int64_t *nleaf, int64_t *npoints)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (!P->is_vol) throw Error{DMK_ERR_ARG, "not a volume plan"};
+        if (nleaf) *nleaf = P->vol.nleaf;
+        if (npoints) *npoints = P->n;
+    });
+}
+
+dmk_status dmk_vol_leaves(dmk_plan_t plan, int32_t *level, int32_t *ijk)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (!P->is_vol) throw Error{DMK_ERR_ARG, "not a volume plan"};
+        if (level) std::memcpy(level, P->vol.level.data(), P->vol.level.size() * sizeof(int32_t));
+        if (ijk) std::memcpy(ijk, P->vol.ijk.data(), P->vol.ijk.size() * sizeof(int32_t));
+    });
+}
+
+dmk_status dmk_vol_nodes(dmk_plan_t plan, double *xyz, void *stream)
+{
+    return guarded([&] {
+        if (!plan || !xyz) throw Error{DMK_ERR_ARG, "NULL argument"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (!P->is_vol) throw Error{DMK_ERR_ARG, "not a volume plan"};
+        vol_nodes(P, xyz, (hipStream_t)stream);
+    });
+}
+
+dmk_status dmk_vol_eval(dmk_plan_t plan, const double *rho, double *u, double *far_part, double *near_part,
+                        void *stream)
+{
+    return guarded([&] {
+        if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
+        Plan *P = reinterpret_cast<Plan *>(plan);
+        if (!P->is_vol) throw Error{DMK_ERR_ARG, "not a volume plan (use dmk_eval)"};
+        if (!rho) throw Error{DMK_ERR_ARG, "rho is NULL"};
+        if (!u && !far_part && !near_part) throw Error{DMK_ERR_ARG, "no output requested"};
+        BusyGuard g(P);
+        hipStream_t s = (hipStream_t)stream;
+        run_vol_eval(P, rho, u, far_part, near_part, s);
         P->last_stream = s;
     });
 }

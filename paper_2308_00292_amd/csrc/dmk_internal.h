@@ -72,8 +72,32 @@ struct LevelLists {
     std::vector<int64_t> fout_off, fin_off, anc_off, leaf_off;
 };
 
+// Volume potential (continuous sources on a density-adaptive tree of q^3
+// Chebyshev leaf grids; vol.hip).  The point machinery holds the box tree:
+// its points are the leaf nodes, leaf capacity q^3, root fixed to the unit
+// cube, so its leaves are exactly the volume leaves.
+struct VolData {
+    int q = 0;
+    int64_t nleaf = 0;
+    std::vector<int32_t> level, ijk;     // host leaf list, Morton order
+    double tau_a = 0, sqL = 0, tpan_w = 1.0;
+    int tpan_gl = 8;
+    int32_t *d_level = nullptr, *d_ijk = nullptr;
+    int32_t *box2v = nullptr;            // [nbox] volume leaf of a leaf box, -1 otherwise
+    double *d_v1 = nullptr;              // [2][p][q] density -> parent proxy matrices
+    float *f_v1 = nullptr;
+    double *d_xq = nullptr, *d_bq = nullptr;     // leaf nodes and barycentric weights
+    double *d_d2 = nullptr;              // [q][q] second derivative on the leaf nodes
+    double *d_tgl = nullptr, *d_tglw = nullptr;  // Gauss-Legendre rule per log-t panel
+    double *d_egl = nullptr, *d_eglw = nullptr;  // Gauss-Legendre rule of the 1-D Gaussian integrals
+    double *ufar = nullptr, *unear = nullptr;    // [nleaf q^3], leaf-major
+};
+
 struct Plan {
     // configuration
+    bool is_vol = false;
+    bool fixed_root = false;  // root = the unit cube centred at the origin
+    VolData vol;
     int dim = 3, p = 0, nf = 0, nw = 0, precision = 0, leaf_max = 64, max_depth = 20;
     int kernel = DMK_LAPLACE;
     double lambda = 0.0;       // Yukawa parameter, input units
@@ -188,6 +212,17 @@ void build_tree(Plan *P, const double *pts, hipStream_t s);
 void build_lists(Plan *P, hipStream_t s);
 void upload_tables(Plan *P, hipStream_t s);
 void alloc_workspace(Plan *P);
+// far-field stages shared with the volume code (root window, plane waves,
+// local values of the anchors); p = 18 only
+void far_stages(Plan *P, hipStream_t s);
+// volume potential: plan (host tree from the density callback, then the box
+// tree, lists and tables) and evaluation
+dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_level, int32_t max_level,
+                         int32_t nfeat, const double *feat, dmk_density_fn density, void *ctx, const dmk_opts *opts,
+                         void *stream);
+void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, double *near_part, hipStream_t s);
+void vol_nodes(Plan *P, double *xyz, hipStream_t s);
+
 void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
               hipStream_t s);
 void count_work(Plan *P, hipStream_t s);

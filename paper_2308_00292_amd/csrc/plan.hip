@@ -482,7 +482,7 @@ static void build_tree_t(Plan *P, const double *pts, hipStream_t s)
     Scratch S;
     // ---- root box of each problem from its bounding box
     std::vector<double> bbx(7 * (size_t)nprob, 0.0);
-    if (n > 0) {
+    if (n > 0 && !P->fixed_root) {
         if (nprob == 1) {
             int nb = (int)std::min<int64_t>(1024, (n + TPB - 1) / TPB);
             double *part = S.get<double>(7 * nb);
@@ -519,6 +519,10 @@ static void build_tree_t(Plan *P, const double *pts, hipStream_t s)
             if (hi - lo > ext) ext = hi - lo;
         }
         P->pside[b] = (ext > 0.0) ? ext * (1.0 + std::ldexp(1.0, -40)) : 1.0;
+    }
+    if (P->fixed_root) {  // the unit cube centred at the origin (volume plans: nprob = 1)
+        for (int d = 0; d < D; ++d) P->pcenter[d] = 0.0;
+        P->pside[0] = 1.0;
     }
     for (int d = 0; d < D; ++d) P->center[d] = P->pcenter[d];
     P->side = P->pside[0];

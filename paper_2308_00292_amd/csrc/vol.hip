@@ -1,0 +1,918 @@
+// Volume potential on gfx950: u(x) = int_{B_0} rho(y) / (4 pi |x - y|) dy on
+// the unit cube, at the Chebyshev nodes of a density-adaptive tree (Sec. 3.6,
+// "Modification of DMK for continuous sources").
+//
+// Split: the Gaussian multilevel form of Sec. 3.2 (eqs. mlks, kerneldef,
+// deltavalue), sigma_l = 2^-l / sqrt(log(1/eps)); its plane-wave weights obey
+// w_l = 2^l w_0 like the PSWF ones, so the far-field stages of the point code
+// (root window, outgoing and incoming plane waves, local values of the
+// anchors) run unchanged on Gaussian tables.  What the volume code adds:
+//
+//   host       the tree that resolves rho (calls of the density callback,
+//              Chebyshev tail test, 2:1 balance), handed to the point-code
+//              tree builder as its node set with leaf capacity q^3 and the
+//              unit cube as root, so that builder's leaves are these leaves.
+//   k_vol_upward  proxy charges of every non-leaf box: leaf children from
+//              their density (Gauss-Legendre weights times rho at the Legendre
+//              nodes, anterpolated to the parent grid: one p x q matrix per
+//              axis and child side), non-leaf children by the child->parent
+//              matrices.
+//   k_vol_leaf the anchor's local polynomial at the leaf's q^3 nodes (three
+//              q x p mode products).
+//   k_vol_near residual R_L of every source leaf in the target leaf's gather
+//              list as a sum of Gaussians (Gauss-Legendre in log t), each a
+//              product of three q x q matrices; the Gaussians narrower than
+//              1/t_a over R^3 through rho + Lap rho/(4t^2) + Lap^2 rho/(32t^4)
+//              of the target's polynomial (Sec. 4.4).
+//   k_vol_finalize  u = (far + near) / (4 pi).
+//
+// HBM layout: rho and u leaf-major in Morton order, q^3 per leaf with the
+// z index fastest; per-box p^3 grids and plane waves as in the point code.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_set>
+
+#include "dmk_internal.h"
+#include "tiles.h"
+
+namespace dmk {
+
+namespace {
+
+constexpr int VQ = 8;  // leaf grid order built
+
+// ---------------------------------------------------------------- host tree
+struct Cell {
+    int32_t l, c[3];
+};
+
+uint64_t spread_bits(uint64_t v)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+    return r;
+}
+
+// Morton key at 21 bits per axis (x most significant within a bit triple)
+uint64_t cell_key(const Cell &a)
+{
+    const int sh = 21 - a.l;
+    return (spread_bits((uint64_t)a.c[0] << sh) << 2) | (spread_bits((uint64_t)a.c[1] << sh) << 1) |
+           spread_bits((uint64_t)a.c[2] << sh);
+}
+
+// unique per (level, cell): the level above the level's own key bits
+uint64_t cell_id(int l, int64_t x, int64_t y, int64_t z)
+{
+    Cell a{l, {(int32_t)x, (int32_t)y, (int32_t)z}};
+    return ((uint64_t)l << 58) | (cell_key(a) >> (3 * (21 - l)));
+}
+
+// Chebyshev coefficients c_k = (2 - [k = 0]) / q sum_a f(x_a) T_k(x_a), x_a =
+// cos(pi (a + 1/2) / q), along one axis of a q^3 block (stride st)
+void dct_axis(int q, double *f, int st0, int st1, int st2)
+{
+    std::vector<double> C((size_t)q * q), tmp(q);
+    for (int k = 0; k < q; ++k)
+        for (int a = 0; a < q; ++a) C[k * q + a] = (k ? 2.0 : 1.0) / q * std::cos(k * M_PI * (a + 0.5) / q);
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j) {
+            double *b = f + i * st1 + j * st2;
+            for (int k = 0; k < q; ++k) {
+                double s = 0.0;
+                for (int a = 0; a < q; ++a) s += C[k * q + a] * b[a * st0];
+                tmp[k] = s;
+            }
+            for (int k = 0; k < q; ++k) b[k * st0] = tmp[k];
+        }
+}
+
+// refinement test: sum of |c_ijk| with max(i,j,k) >= q-2
+double cheb_tail(int q, std::vector<double> f)
+{
+    dct_axis(q, f.data(), q * q, q, 1);
+    dct_axis(q, f.data(), q, q * q, 1);
+    dct_axis(q, f.data(), 1, q * q, q);
+    double s = 0.0;
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j)
+            for (int k = 0; k < q; ++k)
+                if (i >= q - 2 || j >= q - 2 || k >= q - 2) s += std::fabs(f[(i * q + j) * q + k]);
+    return s;
+}
+
+void cell_nodes(int q, const Cell &b, double *xyz)
+{
+    const double s = std::ldexp(1.0, -b.l);
+    double cen[3];
+    for (int d = 0; d < 3; ++d) cen[d] = -0.5 + (b.c[d] + 0.5) * s;
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < q; ++j)
+            for (int k = 0; k < q; ++k) {
+                const int ix[3] = {i, j, k};
+                double *o = xyz + 3 * ((i * q + j) * q + k);
+                for (int d = 0; d < 3; ++d) o[d] = cen[d] + 0.5 * s * std::cos(M_PI * (ix[d] + 0.5) / q);
+            }
+}
+
+// a feature point inside the box asks for a side below the box's
+bool feature_split(const Cell &b, int32_t nfeat, const double *feat)
+{
+    const double s = std::ldexp(1.0, -b.l);
+    for (int32_t f = 0; f < nfeat; ++f) {
+        const double *F = feat + 4 * (size_t)f;
+        if (!(F[3] < s)) continue;
+        bool in = true;
+        for (int d = 0; d < 3; ++d) {
+            const double lo = -0.5 + b.c[d] * s;
+            in = in && F[d] >= lo && F[d] < lo + s;
+        }
+        if (in) return true;
+    }
+    return false;
+}
+
+std::vector<Cell> build_vol_tree(int q, double tol, double rho_scale, int min_level, int max_level, int32_t nfeat,
+                                 const double *feat, dmk_density_fn fn, void *ctx)
+{
+    const int q3 = q * q * q;
+    std::vector<Cell> leaves, cur{Cell{0, {0, 0, 0}}};
+    for (int l = 0; !cur.empty(); ++l) {
+        std::vector<char> split(cur.size(), 0);
+        if (l < max_level) {
+            if (l < min_level) {
+                std::fill(split.begin(), split.end(), 1);
+            } else {
+                std::vector<double> xyz(cur.size() * q3 * 3), f(cur.size() * q3);
+                for (size_t b = 0; b < cur.size(); ++b) cell_nodes(q, cur[b], xyz.data() + b * q3 * 3);
+                fn((int64_t)(cur.size() * q3), xyz.data(), f.data(), ctx);
+                for (size_t b = 0; b < cur.size(); ++b) {
+                    std::vector<double> fb(f.begin() + b * q3, f.begin() + (b + 1) * q3);
+                    for (double v : fb)
+                        if (!std::isfinite(v)) throw Error{DMK_ERR_ARG, "density returned a non-finite value"};
+                    split[b] = feature_split(cur[b], nfeat, feat) || cheb_tail(q, fb) > tol * rho_scale;
+                }
+            }
+        }
+        std::vector<Cell> nxt;
+        for (size_t b = 0; b < cur.size(); ++b) {
+            if (!split[b]) {
+                leaves.push_back(cur[b]);
+                continue;
+            }
+            for (int o = 0; o < 8; ++o)
+                nxt.push_back(Cell{l + 1, {2 * cur[b].c[0] + ((o >> 2) & 1), 2 * cur[b].c[1] + ((o >> 1) & 1),
+                                           2 * cur[b].c[2] + (o & 1)}});
+        }
+        cur.swap(nxt);
+    }
+    // minimal 2:1 balance: a leaf touching a leaf two or more levels finer is split
+    for (;;) {
+        std::unordered_set<uint64_t> have;
+        have.reserve(leaves.size() * 2);
+        for (const Cell &a : leaves) have.insert(cell_id(a.l, a.c[0], a.c[1], a.c[2]));
+        std::unordered_set<uint64_t> mark;
+        for (const Cell &a : leaves) {
+            if (a.l < 2) continue;
+            const int64_t lim = int64_t(1) << a.l;
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        if (!dx && !dy && !dz) continue;
+                        const int64_t n[3] = {a.c[0] + dx, a.c[1] + dy, a.c[2] + dz};
+                        if (n[0] < 0 || n[1] < 0 || n[2] < 0 || n[0] >= lim || n[1] >= lim || n[2] >= lim) continue;
+                        for (int up = 0; up <= a.l; ++up) {
+                            const uint64_t id = cell_id(a.l - up, n[0] >> up, n[1] >> up, n[2] >> up);
+                            if (have.count(id)) {
+                                if (up >= 2) mark.insert(id);
+                                break;
+                            }
+                        }
+                    }
+        }
+        if (mark.empty()) break;
+        std::vector<Cell> nl;
+        nl.reserve(leaves.size() + 7 * mark.size());
+        for (const Cell &a : leaves) {
+            if (!mark.count(cell_id(a.l, a.c[0], a.c[1], a.c[2]))) {
+                nl.push_back(a);
+                continue;
+            }
+            for (int o = 0; o < 8; ++o)
+                nl.push_back(Cell{a.l + 1, {2 * a.c[0] + ((o >> 2) & 1), 2 * a.c[1] + ((o >> 1) & 1),
+                                            2 * a.c[2] + (o & 1)}});
+        }
+        leaves.swap(nl);
+    }
+    std::sort(leaves.begin(), leaves.end(), [](const Cell &a, const Cell &b) { return cell_key(a) < cell_key(b); });
+    return leaves;
+}
+
+// ------------------------------------------------------------- host tables
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), d = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            d = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / d;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = pk;
+        }
+        d = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * d * d);
+    }
+}
+
+// Lagrange basis of the n first-kind Chebyshev nodes at x (barycentric)
+void cheb_lagrange(int n, double x, double *out)
+{
+    double den = 0.0;
+    for (int a = 0; a < n; ++a) {
+        const double xa = std::cos(M_PI * (a + 0.5) / n);
+        const double wa = ((a & 1) ? -1.0 : 1.0) * std::sin((2 * a + 1) * M_PI / (2.0 * n));
+        if (x == xa) {
+            for (int b = 0; b < n; ++b) out[b] = (b == a) ? 1.0 : 0.0;
+            return;
+        }
+        out[a] = wa / (x - xa);
+        den += out[a];
+    }
+    for (int a = 0; a < n; ++a) out[a] /= den;
+}
+
+// Gaussian split tables over a copy of the PSWF ones (same p, n_f, grids):
+// D_0 weights (h_0/2pi)^3 Dhat_0(h_0|m|), root window weights with the
+// Gaussian factor, spacing h_W = 2 pi / (2 sqrt 3 + 2), n_W = 14.
+void gauss_tables(Tables *t, double tol)
+{
+    const double s0 = 1.0 / std::sqrt(std::log(1.0 / tol)), s1 = 0.5 * s0;
+    const int nf = t->nf, p = t->p;
+    {
+        const double h = 2.0 * M_PI / 3.0, fac = std::pow(h / (2.0 * M_PI), 3);
+        const int maxk2 = 3 * nf * nf;
+        std::vector<double> memo(maxk2 + 1);
+        memo[0] = fac * M_PI * (s0 * s0 - s1 * s1);
+        for (int k2 = 1; k2 <= maxk2; ++k2) {
+            const double k = h * std::sqrt((double)k2);
+            // 4 pi (e^{-k^2 s1^2/4} - e^{-k^2 s0^2/4}) / k^2
+            memo[k2] = fac * 4.0 * M_PI * std::exp(-0.25 * k * k * s1 * s1) *
+                       (-std::expm1(-0.25 * k * k * (s0 * s0 - s1 * s1))) / (k * k);
+        }
+        for (int m1 = -nf; m1 <= nf; ++m1)
+            for (int m3 = 0; m3 <= nf; ++m3)
+                for (int m2 = -nf; m2 <= nf; ++m2)
+                    t->wd0[((size_t)(m1 + nf) * t->nh + m3) * t->nn + (m2 + nf)] = memo[m1 * m1 + m2 * m2 + m3 * m3];
+    }
+    const int nw = 14;
+    const double hw = 2.0 * M_PI / (2.0 * std::sqrt(3.0) + 2.0);
+    t->nw = nw;
+    t->nwn = 2 * nw + 1;
+    t->nwh = nw + 1;
+    t->prm.nw = nw;
+    t->prm.hw = hw;
+    t->ew.assign((size_t)t->nwn * p * 2, 0.0);
+    for (int m = -nw; m <= nw; ++m)
+        for (int j = 0; j < p; ++j) {
+            const double ph = -hw * m * 0.5 * t->xcheb[j];
+            t->ew[((size_t)(m + nw) * p + j) * 2 + 0] = std::cos(ph);
+            t->ew[((size_t)(m + nw) * p + j) * 2 + 1] = std::sin(ph);
+        }
+    const double A = 1.0 + std::sqrt(3.0), fac = std::pow(hw / (2.0 * M_PI), 3);
+    const int maxk2 = 3 * nw * nw;
+    std::vector<double> memo(maxk2 + 1);
+    memo[0] = fac * 2.0 * M_PI * A * A;
+    for (int k2 = 1; k2 <= maxk2; ++k2) {
+        const double k = hw * std::sqrt((double)k2), sn = std::sin(0.5 * k * A);
+        memo[k2] = fac * 8.0 * M_PI * sn * sn / (k * k) * std::exp(-0.25 * k * k * s0 * s0);
+    }
+    t->ww.assign((size_t)t->nwh * t->nwn * t->nwn, 0.0);
+    for (int m3 = 0; m3 <= nw; ++m3)
+        for (int m2 = -nw; m2 <= nw; ++m2)
+            for (int m1 = -nw; m1 <= nw; ++m1)
+                t->ww[((size_t)m3 * t->nwn + (m2 + nw)) * t->nwn + (m1 + nw)] = memo[m1 * m1 + m2 * m2 + m3 * m3];
+}
+
+// ------------------------------------------------------------ device view
+template <typename T>
+struct VDev {
+    const int32_t *child0, *blevel, *proxy_slot, *local_slot, *anchor, *box2v, *vlevel, *vijk;
+    const uint8_t *bflags;
+    const double *bcenter;
+    const T *c2p, *xcheb, *bary, *v1;
+    const double *xq, *bq, *d2, *tgl, *tglw, *egl, *eglw;
+    int ngl;
+    double tpan_w, tau_a, sqL;
+    const double *rho;
+    T *proxy;
+    const T *local;
+    double *ufar, *unear;
+};
+
+template <typename T>
+VDev<T> make_vdev(Plan *P)
+{
+    VDev<T> D;
+    const bool f64 = sizeof(T) == 8;
+    D.child0 = P->child0;
+    D.blevel = P->blevel;
+    D.proxy_slot = P->proxy_slot;
+    D.local_slot = P->local_slot;
+    D.anchor = P->anchor;
+    D.box2v = P->vol.box2v;
+    D.vlevel = P->vol.d_level;
+    D.vijk = P->vol.d_ijk;
+    D.bflags = P->bflags;
+    D.bcenter = P->bcenter;
+    D.c2p = (const T *)(f64 ? (void *)P->d_c2p : (void *)P->f_c2p);
+    D.xcheb = (const T *)(f64 ? (void *)P->d_xcheb : (void *)P->f_xcheb);
+    D.bary = (const T *)(f64 ? (void *)P->d_bary : (void *)P->f_bary);
+    D.v1 = (const T *)(f64 ? (void *)P->vol.d_v1 : (void *)P->vol.f_v1);
+    D.xq = P->vol.d_xq;
+    D.bq = P->vol.d_bq;
+    D.d2 = P->vol.d_d2;
+    D.tgl = P->vol.d_tgl;
+    D.tglw = P->vol.d_tglw;
+    D.egl = P->vol.d_egl;
+    D.eglw = P->vol.d_eglw;
+    D.ngl = P->vol.tpan_gl;
+    D.tpan_w = P->vol.tpan_w;
+    D.tau_a = P->vol.tau_a;
+    D.sqL = P->vol.sqL;
+    D.rho = nullptr;
+    D.proxy = (T *)P->proxy;
+    D.local = (const T *)P->local;
+    D.ufar = P->vol.ufar;
+    D.unear = P->vol.unear;
+    return D;
+}
+
+// ------------------------------------------------------------------ kernels
+// node coordinates of every leaf, [n][3]
+__global__ void __launch_bounds__(TPB) k_vol_nodes(const int32_t *lev, const int32_t *ijk, const double *xq, int q,
+                                                   int64_t n, double *xyz)
+{
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n) return;
+    const int q3 = q * q * q;
+    const int64_t b = i / q3;
+    const int r = (int)(i % q3);
+    const int ix[3] = {r / (q * q), (r / q) % q, r % q};
+    const double s = ldexp(1.0, -lev[b]);
+    for (int d = 0; d < 3; ++d) xyz[3 * i + d] = -0.5 + (ijk[3 * b + d] + 0.5) * s + 0.5 * s * xq[ix[d]];
+}
+
+// leaf box -> volume leaf, from the point-code tree over the nodes: every
+// leaf box must hold exactly the q^3 nodes of one volume leaf
+__global__ void __launch_bounds__(TPB) k_vol_map(const int32_t *leaves, int64_t nleaf, const int32_t *pstart,
+                                                 const int32_t *pcount, const int32_t *perm, int q3, int32_t *box2v,
+                                                 unsigned long long *bad)
+{
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= nleaf) return;
+    const int32_t B = leaves[i];
+    const int32_t c = pcount[B], s0 = pstart[B];
+    bool ok = (c == q3);
+    const int32_t v = ok ? perm[s0] / q3 : -1;
+    for (int k = 0; ok && k < q3; ++k) ok = (perm[s0 + k] / q3 == v);
+    box2v[B] = ok ? v : -1;
+    if (!ok) atomicAdd(bad, 1ull);
+}
+
+template <int P, int Q>
+struct VolLds {
+    static constexpr int P2 = P * P, P3 = P2 * P, Q3 = Q * Q * Q;
+    static constexpr int up_work = (2 * P3 > Q3 + Q * Q * P + Q * P2) ? 2 * P3 : Q3 + Q * Q * P + Q * P2;
+    static size_t up(size_t el) { return el * (2 * P2 + 2 * P * Q + up_work); }
+    static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
+    static constexpr int JB = 8;  // Gaussians per pass of the near-field kernel
+    static size_t near() { return sizeof(double) * (Q3 + JB * 3 * Q * Q + 2 * JB * Q3); }
+};
+
+// proxy charges of the non-leaf boxes of one level
+template <typename T, int P, int Q>
+__global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *list)
+{
+    constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
+    constexpr int RM = Tiles<P>::RM, RN = Tiles<P>::RN, ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN;
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *Am = sm;              // [2][p][p] child -> parent
+    T *Vm = Am + 2 * P2;     // [2][p][q] leaf density -> parent
+    T *w0 = Vm + 2 * P * Q;  // work
+    const int32_t Pb = list[blockIdx.x];
+    for (int t = threadIdx.x; t < 2 * P2; t += TPB) Am[t] = D.c2p[t];
+    for (int t = threadIdx.x; t < 2 * P * Q; t += TPB) Vm[t] = D.v1[t];
+    T acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
+    const double sc = ldexp(1.0, -3 * (D.blevel[Pb] + 2));  // (s_child / 2)^3
+    __syncthreads();
+    for (int k = 0; k < 8; ++k) {
+        const int32_t C = D.child0[Pb] + k;
+        const int bx = (k >> 2) & 1, by = (k >> 1) & 1, bz = k & 1;
+        if (D.bflags[C] & 2) {
+            const T *src = D.proxy + (int64_t)D.proxy_slot[C] * P3;
+            T *t1 = w0, *t2 = w0 + P3;
+            __syncthreads();
+            for (int t = threadIdx.x; t < P3; t += TPB) t2[t] = src[t];
+            __syncthreads();
+            gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Am + bz * P2, 0, 1, P, t1, 0, P, 1);
+            __syncthreads();
+            gemm<T, ZM, ZN, false>(P, P, P, P, Am + by * P2, 0, P, 1, t1, P2, P, 1, t2, P2, P, 1);
+            __syncthreads();
+            gemm_regs<T, RM, RN>(P, P2, P, Am + bx * P2, P, 1, t2, P2, 1, acc);
+        } else {
+            // leaf child: rho on its q^3 nodes -> parent grid
+            const double *rho = D.rho + (int64_t)D.box2v[C] * Q3;
+            T *r = w0, *t1 = r + Q3, *t2 = t1 + Q2 * P;
+            __syncthreads();
+            for (int t = threadIdx.x; t < Q3; t += TPB) r[t] = (T)(rho[t] * sc);
+            __syncthreads();
+            // z: t1[(i0 i1)][a2] = sum_i2 r[(i0 i1)][i2] V_z[a2][i2]
+            gemm<T, ZM, ZN, false>(1, Q2, P, Q, r, 0, Q, 1, Vm + bz * P * Q, 0, 1, Q, t1, 0, P, 1);
+            __syncthreads();
+            // y: t2[i0][a1][a2] = sum_i1 V_y[a1][i1] t1[i0][i1][a2]
+            gemm<T, ZM, ZN, false>(Q, P, P, Q, Vm + by * P * Q, 0, Q, 1, t1, Q * P, P, 1, t2, P2, P, 1);
+            __syncthreads();
+            // x: acc[a0][(a1 a2)] += sum_i0 V_x[a0][i0] t2[i0][(a1 a2)]
+            gemm_regs<T, RM, RN>(P, P2, Q, Vm + bx * P * Q, Q, 1, t2, P2, 1, acc);
+        }
+    }
+    store_tiles<T, P>(acc, D.proxy + (int64_t)D.proxy_slot[Pb] * P3);
+}
+
+// far field at the nodes of each leaf from its anchor's local values
+template <typename T, int P, int Q>
+__global__ void __launch_bounds__(TPB) k_vol_leaf(VDev<T> D, const int32_t *leaves)
+{
+    constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *v = sm;               // p^3 local values of the anchor
+    T *t1 = v + P3;          // [p][p][q]
+    T *t2 = t1 + P2 * Q;     // [p][q][q]
+    T *U = t2 + P * Q2;      // [3][q][p] Lagrange rows of the anchor grid at the nodes
+    T *xc = U + 3 * Q * P, *bw = xc + P;
+    const int32_t B = leaves[blockIdx.x];
+    const int32_t A = D.anchor[B];
+    const int32_t vB = D.box2v[B];
+    const T *src = D.local + (int64_t)D.local_slot[A] * P3;
+    for (int t = threadIdx.x; t < P3; t += TPB) v[t] = src[t];
+    for (int t = threadIdx.x; t < P; t += TPB) {
+        xc[t] = D.xcheb[t];
+        bw[t] = D.bary[t];
+    }
+    __syncthreads();
+    const double sB = ldexp(1.0, -D.blevel[B]), sA = ldexp(1.0, -D.blevel[A]);
+    for (int r = threadIdx.x; r < 3 * Q; r += TPB) {
+        const int d = r / Q, i = r % Q;
+        const double x = D.bcenter[3 * (int64_t)B + d] + 0.5 * sB * D.xq[i];
+        const T xi = (T)(2.0 * (x - D.bcenter[3 * (int64_t)A + d]) / sA);
+        T row[P];
+        lagrange_row<T>(P, xc, bw, xi, row);
+#pragma unroll
+        for (int a = 0; a < P; ++a) U[(d * Q + i) * P + a] = row[a];
+    }
+    __syncthreads();
+    // z: t1[(a0 a1)][i2] = sum_a2 v[(a0 a1)][a2] U_z[i2][a2]
+    gemm<T, 3, 2, false>(1, P2, Q, P, v, 0, P, 1, U + 2 * Q * P, 0, 1, P, t1, 0, Q, 1);
+    __syncthreads();
+    // y: t2[a0][i1][i2] = sum_a1 U_y[i1][a1] t1[a0][a1][i2]
+    gemm<T, 2, 2, false>(P, Q, Q, P, U + Q * P, 0, P, 1, t1, P * Q, Q, 1, t2, Q2, Q, 1);
+    __syncthreads();
+    // x: u[i0][(i1 i2)] = sum_a0 U_x[i0][a0] t2[a0][(i1 i2)]
+    const int o = threadIdx.x;
+    for (int k = o; k < Q * Q2; k += TPB) {
+        const int i0 = k / Q2, r = k % Q2;
+        double s = 0.0;
+        for (int a = 0; a < P; ++a) s += (double)U[i0 * P + a] * (double)t2[a * Q2 + r];
+        D.ufar[(int64_t)vB * Q * Q2 + k] = s;
+    }
+}
+
+// Near field of each target leaf: sum of Gaussians of R_L over the source
+// leaves of its gather list, then the asymptotic part.  FP64.
+template <int Q>
+__global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t *leaves, const int32_t *nl_off,
+                                                  const int32_t *nl_src)
+{
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NE = 32, NO = Q3 / TPB;
+    static_assert(Q3 % TPB == 0, "leaf grid must fill whole passes of the block");
+    extern __shared__ double vsm[];
+    double *rT = vsm;              // source density
+    double *G = rT + Q3;           // [JB][3][q][q]
+    double *t1 = G + JB * 3 * Q2;  // [JB][q^3]
+    double *t2 = t1 + JB * Q3;     // [JB][q^3]
+    __shared__ double xq[Q], Tx[Q][Q], egl[NE], eglw[NE], tgl[16], tglw[16];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < Q; t += TPB) xq[t] = D.xq[t];
+    for (int t = tid; t < Q2; t += TPB) {
+        // T_k(x_b) for the Chebyshev form of the Lagrange basis
+        const int k = t / Q, b = t % Q;
+        Tx[k][b] = cos(k * M_PI * (b + 0.5) / Q);
+    }
+    for (int t = tid; t < NE; t += TPB) {
+        egl[t] = D.egl[t];
+        eglw[t] = D.eglw[t];
+    }
+    for (int t = tid; t < D.ngl; t += TPB) {
+        tgl[t] = D.tgl[t];
+        tglw[t] = D.tglw[t];
+    }
+    const int64_t li = blockIdx.x;
+    const int32_t B = leaves[li];
+    const int32_t vB = D.box2v[B];
+    const double sB = ldexp(1.0, -D.blevel[B]);
+    double cB[3];
+    for (int d = 0; d < 3; ++d) cB[d] = D.bcenter[3 * (int64_t)B + d];
+    double acc[NO];
+#pragma unroll
+    for (int k = 0; k < NO; ++k) acc[k] = 0.0;
+    const double wnorm = 2.0 / sqrt(M_PI);
+    for (int e = nl_off[li]; e < nl_off[li + 1]; ++e) {
+        const int32_t T = nl_src[e];
+        const double sT = ldexp(1.0, -D.blevel[T]);
+        double cT[3], gap2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            cT[d] = D.bcenter[3 * (int64_t)T + d];
+            const double g = fabs(cB[d] - cT[d]) - 0.5 * (sB + sT);
+            if (g > 0.0) gap2 += g * g;
+        }
+        if (gap2 >= sT * sT) continue;  // every Gaussian of R_L is below eps there
+        const double u0 = log(D.sqL / sT), u1 = log(D.tau_a / sB);
+        int npan = (int)ceil((u1 - u0) / D.tpan_w - 1e-12);
+        if (npan < 1) npan = 1;
+        const double hp = (u1 - u0) / npan;
+        const int ng = npan * D.ngl;
+        __syncthreads();
+        const double *src = D.rho + (int64_t)D.box2v[T] * Q3;
+        for (int t = tid; t < Q3; t += TPB) rT[t] = src[t];
+        for (int j0 = 0; j0 < ng; j0 += JB) {
+            const int jb = min(JB, ng - j0);
+            __syncthreads();
+            // 1-D factors G_d[a][b] = (s_T/2) int_{-1}^{1} exp(-(xi_a - eta)^2 tau^2) L_b(eta) d eta
+            for (int r = tid; r < jb * 3 * Q; r += TPB) {
+                const int jj = r / (3 * Q), d = (r / Q) % 3, a = r % Q;
+                const int j = j0 + jj, pan = j / D.ngl, g = j % D.ngl;
+                const double tau = exp(u0 + hp * (pan + 0.5 * (tgl[g] + 1.0))) * 0.5 * sT;
+                const double xi = 2.0 * (cB[d] + 0.5 * sB * xq[a] - cT[d]) / sT;
+                const double lo = fmax(-1.0, xi - 7.0 / tau), hi = fmin(1.0, xi + 7.0 / tau);
+                double cf[Q];
+#pragma unroll
+                for (int k = 0; k < Q; ++k) cf[k] = 0.0;
+                if (hi > lo) {
+                    const double hc = 0.5 * (lo + hi), hr = 0.5 * (hi - lo);
+                    for (int n = 0; n < NE; ++n) {
+                        const double eta = hc + hr * egl[n];
+                        const double dd = (xi - eta) * tau;
+                        const double wgt = exp(-dd * dd) * hr * eglw[n];
+                        double tk0 = 1.0, tk1 = eta;
+                        cf[0] += wgt;
+                        cf[1] += wgt * eta;
+#pragma unroll
+                        for (int k = 2; k < Q; ++k) {
+                            const double tk2 = 2.0 * eta * tk1 - tk0;
+                            cf[k] += wgt * tk2;
+                            tk0 = tk1;
+                            tk1 = tk2;
+                        }
+                    }
+                }
+                // L_b = (1/q) [1 + 2 sum_{k>=1} T_k(x_b) T_k(eta)]
+                double *gr = G + ((jj * 3 + d) * Q + a) * Q;
+                for (int b = 0; b < Q; ++b) {
+                    double s = cf[0];
+#pragma unroll
+                    for (int k = 1; k < Q; ++k) s += 2.0 * Tx[k][b] * cf[k];
+                    gr[b] = 0.5 * sT * s / Q;
+                }
+            }
+            __syncthreads();
+            // z: t1[jj][i0][i1][c] = sum_i2 G_z[jj][c][i2] rT[i0][i1][i2]
+            for (int o = tid; o < jb * Q3; o += TPB) {
+                const int jj = o / Q3, r = o % Q3, c = r % Q, i01 = r / Q;
+                const double *g = G + ((jj * 3 + 2) * Q + c) * Q;
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) s += g[k] * rT[i01 * Q + k];
+                t1[o] = s;
+            }
+            __syncthreads();
+            // y: t2[jj][i0][b][c] = sum_i1 G_y[jj][b][i1] t1[jj][i0][i1][c]
+            for (int o = tid; o < jb * Q3; o += TPB) {
+                const int jj = o / Q3, r = o % Q3, c = r % Q, b = (r / Q) % Q, i0 = r / Q2;
+                const double *g = G + ((jj * 3 + 1) * Q + b) * Q;
+                const double *tt = t1 + jj * Q3 + i0 * Q2 + c;
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) s += g[k] * tt[k * Q];
+                t2[o] = s;
+            }
+            __syncthreads();
+            // x: u[a][b][c] += w_j sum_i0 G_x[jj][a][i0] t2[jj][i0][b][c]
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                const int o = tid + k * TPB, a = o / Q2, bc = o % Q2;
+                for (int jj = 0; jj < jb; ++jj) {
+                    const int j = j0 + jj, pan = j / D.ngl, g = j % D.ngl;
+                    const double tj = exp(u0 + hp * (pan + 0.5 * (tgl[g] + 1.0)));
+                    const double wj = wnorm * tj * 0.5 * hp * tglw[g];
+                    const double *gx = G + ((jj * 3 + 0) * Q + a) * Q;
+                    double s = 0.0;
+#pragma unroll
+                    for (int i0 = 0; i0 < Q; ++i0) s += gx[i0] * t2[jj * Q3 + i0 * Q2 + bc];
+                    acc[k] += wj * s;
+                }
+            }
+        }
+    }
+    // asymptotic part: Gaussians with t >= t_a over R^3 from rho_B's polynomial
+    __syncthreads();
+    const double *rb = D.rho + (int64_t)vB * Q3;
+    for (int t = tid; t < Q3; t += TPB) rT[t] = rb[t];
+    for (int t = tid; t < Q2; t += TPB) G[t] = D.d2[t];
+    __syncthreads();
+    const double lsc = 4.0 / (sB * sB);
+    for (int o = tid; o < Q3; o += TPB) {
+        const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
+        double s = 0.0;
+        for (int j = 0; j < Q; ++j)
+            s += G[a * Q + j] * rT[(j * Q + b) * Q + c] + G[b * Q + j] * rT[(a * Q + j) * Q + c] +
+                 G[c * Q + j] * rT[(a * Q + b) * Q + j];
+        t1[o] = s * lsc;
+    }
+    __syncthreads();
+    for (int o = tid; o < Q3; o += TPB) {
+        const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
+        double s = 0.0;
+        for (int j = 0; j < Q; ++j)
+            s += G[a * Q + j] * t1[(j * Q + b) * Q + c] + G[b * Q + j] * t1[(a * Q + j) * Q + c] +
+                 G[c * Q + j] * t1[(a * Q + b) * Q + j];
+        t2[o] = s * lsc;
+    }
+    __syncthreads();
+    const double ta = D.tau_a / sB, ta2 = ta * ta;
+#pragma unroll
+    for (int k = 0; k < NO; ++k) {
+        const int o = tid + k * TPB;
+        const double tail = 2.0 * M_PI * (rT[o] / (2.0 * ta2) + t1[o] / (16.0 * ta2 * ta2) +
+                                          t2[o] / (192.0 * ta2 * ta2 * ta2));
+        D.unear[(int64_t)vB * Q3 + o] = acc[k] + tail;
+    }
+}
+
+__global__ void __launch_bounds__(TPB) k_vol_finalize(const double *ufar, const double *unear, int64_t n, double *u,
+                                                      double *fp, double *np)
+{
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n) return;
+    const double kap = 0.25 / M_PI;
+    const double a = ufar[i] * kap, b = unear[i] * kap;
+    if (u) u[i] = a + b;
+    if (fp) fp[i] = a;
+    if (np) np[i] = b;
+}
+
+inline unsigned vblk(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+template <typename K>
+void vol_allow_lds(K kernel, size_t bytes)
+{
+    int dev = 0, lim = 0;
+    DMK_HIP(hipGetDevice(&dev));
+    DMK_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if ((size_t)lim < bytes) throw Error{DMK_ERR_UNSUPPORTED, "device LDS per workgroup too small for a volume stage"};
+    DMK_HIP(hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+template <typename T, int P, int Q>
+void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, hipStream_t s)
+{
+    using LD = VolLds<P, Q>;
+    static bool attrs = false;
+    if (!attrs) {
+        vol_allow_lds(k_vol_upward<T, P, Q>, LD::up(sizeof(T)));
+        vol_allow_lds(k_vol_leaf<T, P, Q>, LD::leaf(sizeof(T)));
+        vol_allow_lds(k_vol_near<Q>, LD::near());
+        attrs = true;
+    }
+    VDev<T> D = make_vdev<T>(Pl);
+    D.rho = rho;
+    const auto &ll = Pl->ll;
+    for (int l = Pl->nlevels - 1; l >= 0; --l) {
+        const int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
+        if (!m) continue;
+        StageScope t(Pl, s, DMK_STAGE_UPWARD);
+        hipLaunchKernelGGL((k_vol_upward<T, P, Q>), dim3((unsigned)m), dim3(TPB), LD::up(sizeof(T)), s, D,
+                           Pl->l_fout + ll.fout_off[l]);
+    }
+    far_stages(Pl, s);
+    {
+        StageScope t(Pl, s, DMK_STAGE_LEAF);
+        hipLaunchKernelGGL((k_vol_leaf<T, P, Q>), dim3((unsigned)Pl->nleaf), dim3(TPB), LD::leaf(sizeof(T)), s, D,
+                           Pl->l_leaf);
+    }
+    {
+        StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
+        VDev<double> D64 = make_vdev<double>(Pl);
+        D64.rho = rho;
+        hipLaunchKernelGGL((k_vol_near<Q>), dim3((unsigned)Pl->nleaf), dim3(TPB), LD::near(), s, D64, Pl->l_leaf,
+                           Pl->nl_off, Pl->nl_src);
+    }
+    {
+        StageScope t(Pl, s, DMK_STAGE_FINALIZE);
+        const int64_t n = Pl->vol.nleaf * Q * Q * Q;
+        hipLaunchKernelGGL(k_vol_finalize, dim3(vblk(n)), dim3(TPB), 0, s, Pl->vol.ufar, Pl->vol.unear, n, u, fp, np);
+    }
+    DMK_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plan
+dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_level, int32_t max_level,
+                         int32_t nfeat, const double *feat, dmk_density_fn density, void *ctx, const dmk_opts *opts,
+                         void *stream)
+{
+    if (!(tol == 1e-3)) throw Error{DMK_ERR_UNSUPPORTED, "volume plans are built for tol = 1e-3"};
+    if (q != VQ) throw Error{DMK_ERR_UNSUPPORTED, "volume plans are built for q = 8"};
+    if (!(rho_scale > 0) || !std::isfinite(rho_scale)) throw Error{DMK_ERR_ARG, "rho_scale must be positive"};
+    if (min_level < 1 || max_level > 19 || min_level > max_level)
+        throw Error{DMK_ERR_ARG, "need 1 <= min_level <= max_level <= 19"};
+    if (!density) throw Error{DMK_ERR_ARG, "density is NULL"};
+    if (nfeat < 0 || (nfeat > 0 && !feat)) throw Error{DMK_ERR_ARG, "bad feature list"};
+    for (int32_t f = 0; f < nfeat; ++f)
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(feat[4 * (size_t)f + k]) || (k == 3 && !(feat[4 * (size_t)f + 3] > 0)))
+                throw Error{DMK_ERR_ARG, "feature points need finite coordinates and h > 0"};
+    dmk_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (o.precision != DMK_FP64) throw Error{DMK_ERR_UNSUPPORTED, "volume plans run in FP64"};
+    std::vector<Cell> tree = build_vol_tree(q, tol, rho_scale, min_level, max_level, nfeat, feat, density, ctx);
+    const int q3 = q * q * q;
+    const int64_t nleaf = (int64_t)tree.size();
+    const int64_t n = nleaf * q3;
+    if (n >= (int64_t(1) << 31)) throw Error{DMK_ERR_ARG, "more than 2^31 - 1 nodes"};
+    Params prm;
+    if (!params_for(1e-6, &prm, 3) || prm.p != 18 || prm.nf != 12)
+        throw Error{DMK_ERR_STATE, "grid parameters p = 18, n_f = 12 unavailable"};
+    auto *P = new Plan();
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        P->is_vol = true;
+        P->fixed_root = true;
+        P->dim = 3;
+        P->kernel = DMK_LAPLACE;
+        P->nprob = 1;
+        P->poff = {0, n};
+        P->pbits = 0;
+        P->kb = 21;
+        P->precision = DMK_FP64;
+        P->leaf_max = q3;
+        P->max_depth = 20;
+        P->flags = 0;
+        P->n = n;
+        build_tables(prm, &P->tab, 3);
+        gauss_tables(&P->tab, tol);
+        P->p = P->tab.p;
+        P->nf = P->tab.nf;
+        P->nw = P->tab.nw;
+        VolData &V = P->vol;
+        V.q = q;
+        V.nleaf = nleaf;
+        V.tau_a = 2.0 * std::pow(tol, -1.0 / 6.0);
+        V.sqL = std::sqrt(std::log(1.0 / tol));
+        V.tpan_gl = 8;
+        V.tpan_w = 1.0;
+        V.level.resize(nleaf);
+        V.ijk.resize(3 * nleaf);
+        for (int64_t i = 0; i < nleaf; ++i) {
+            V.level[i] = tree[i].l;
+            for (int d = 0; d < 3; ++d) V.ijk[3 * i + d] = tree[i].c[d];
+        }
+        auto up64 = [&](const std::vector<double> &h) {
+            double *d = (double *)dalloc(P, std::max<size_t>(h.size(), 1) * sizeof(double));
+            DMK_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, s));
+            return d;
+        };
+        auto up32i = [&](const std::vector<int32_t> &h) {
+            int32_t *d = (int32_t *)dalloc(P, std::max<size_t>(h.size(), 1) * sizeof(int32_t));
+            DMK_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            return d;
+        };
+        P->d_poff = (int64_t *)dalloc(P, 2 * sizeof(int64_t));
+        DMK_HIP(hipMemcpyAsync(P->d_poff, P->poff.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        upload_tables(P, s);
+        V.d_level = up32i(V.level);
+        V.d_ijk = up32i(V.ijk);
+        std::vector<double> xq(q), bq(q);
+        for (int a = 0; a < q; ++a) {
+            xq[a] = std::cos(M_PI * (a + 0.5) / q);
+            bq[a] = ((a & 1) ? -1.0 : 1.0) * std::sin((2 * a + 1) * M_PI / (2.0 * q));
+        }
+        V.d_xq = up64(xq);
+        V.d_bq = up64(bq);
+        // nodes -> point-code tree (root = unit cube, capacity q^3)
+        double *pts = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * 3 * sizeof(double));
+        hipLaunchKernelGGL(k_vol_nodes, dim3(vblk(n)), dim3(TPB), 0, s, V.d_level, V.d_ijk, V.d_xq, q, n, pts);
+        build_tree(P, pts, s);
+        build_lists(P, s);
+        if (P->nleaf != nleaf) throw Error{DMK_ERR_STATE, "box tree does not reproduce the volume tree"};
+        V.box2v = (int32_t *)dalloc(P, (size_t)P->nbox * sizeof(int32_t));
+        DMK_HIP(hipMemsetAsync(V.box2v, 0xff, (size_t)P->nbox * sizeof(int32_t), s));
+        unsigned long long *bad = (unsigned long long *)dalloc(P, sizeof(unsigned long long));
+        DMK_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(k_vol_map, dim3(vblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, P->pstart, P->pcount,
+                           P->perm, q3, V.box2v, bad);
+        unsigned long long hbad = 0;
+        DMK_HIP(hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
+        DMK_HIP(hipStreamSynchronize(s));
+        if (hbad) throw Error{DMK_ERR_STATE, "box tree does not reproduce the volume tree"};
+        // density -> parent proxy matrices V_s[a][j] = int ell_a((eta + s)/2) L_j(eta) d eta
+        std::vector<double> gx, gw;
+        gauss_legendre(18, gx, gw);
+        const int p = P->p;
+        std::vector<double> v1((size_t)2 * p * q, 0.0), la(p), lj(q);
+        for (int sgn = 0; sgn < 2; ++sgn)
+            for (size_t k = 0; k < gx.size(); ++k) {
+                cheb_lagrange(p, 0.5 * (gx[k] + (sgn ? 1.0 : -1.0)), la.data());
+                cheb_lagrange(q, gx[k], lj.data());
+                for (int a = 0; a < p; ++a)
+                    for (int j = 0; j < q; ++j) v1[((size_t)sgn * p + a) * q + j] += gw[k] * la[a] * lj[j];
+            }
+        V.d_v1 = up64(v1);
+        {
+            std::vector<float> f(v1.begin(), v1.end());
+            V.f_v1 = (float *)dalloc(P, f.size() * sizeof(float));
+            DMK_HIP(hipMemcpyAsync(V.f_v1, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
+            DMK_HIP(hipStreamSynchronize(s));
+        }
+        // second-derivative matrix of the leaf interpolant: D2 = D1 D1,
+        // D1[i][j] = (w_j / w_i) / (x_i - x_j), D1[i][i] = -sum_{j != i} D1[i][j]
+        std::vector<double> d1((size_t)q * q, 0.0), d2((size_t)q * q, 0.0);
+        for (int i = 0; i < q; ++i) {
+            double sd = 0.0;
+            for (int j = 0; j < q; ++j) {
+                if (j == i) continue;
+                d1[i * q + j] = (bq[j] / bq[i]) / (xq[i] - xq[j]);
+                sd += d1[i * q + j];
+            }
+            d1[i * q + i] = -sd;
+        }
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j)
+                for (int k = 0; k < q; ++k) d2[i * q + j] += d1[i * q + k] * d1[k * q + j];
+        V.d_d2 = up64(d2);
+        gauss_legendre(V.tpan_gl, gx, gw);
+        V.d_tgl = up64(gx);
+        V.d_tglw = up64(gw);
+        gauss_legendre(32, gx, gw);
+        V.d_egl = up64(gx);
+        V.d_eglw = up64(gw);
+        alloc_workspace(P);
+        V.ufar = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+        V.unear = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+        DMK_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        plan_release(P);
+        throw;
+    }
+    return reinterpret_cast<dmk_plan_t>(P);
+}
+
+void vol_nodes(Plan *P, double *xyz, hipStream_t s)
+{
+    const int64_t n = P->n;
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_vol_nodes, dim3(vblk(n)), dim3(TPB), 0, s, P->vol.d_level, P->vol.d_ijk, P->vol.d_xq,
+                       P->vol.q, n, xyz);
+    DMK_HIP(hipGetLastError());
+}
+
+void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, double *near_part, hipStream_t s)
+{
+    if (P->vol.q != VQ || P->p != 18) throw Error{DMK_ERR_STATE, "volume plan with unexpected grid sizes"};
+    run_vol_t<double, 18, VQ>(P, rho, u, far_part, near_part, s);
+}
+
+}  // namespace dmk

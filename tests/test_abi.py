@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 16
+    assert len(names) == 21
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:
@@ -59,6 +59,28 @@ def test_argument_errors_without_device():
     off2 = np.array([0, 10], dtype=np.int64)
     assert L.dmk_tune_leaf(3, 0, 1e-6, 1, off2.ctypes.data_as(C.c_void_p), None, None, None, None, 0, 1, None,
                            C.byref(best), None) == -1  # no candidates
+    # volume plans: every check below fails before the tree build or any device call
+    calls = []
+    cb = dmk.DENSITY_FN(lambda n, x, out, ctx: calls.append(n))
+    ok = np.array([[0.0, 0.0, 0.0, 0.1]])
+    bad = np.array([[0.0, 0.0, 0.0, 0.0]])
+    assert L.dmk_vol_plan(1e-6, 8, 1.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -2  # tol
+    assert L.dmk_vol_plan(1e-3, 6, 1.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -2  # q
+    assert L.dmk_vol_plan(1e-3, 8, 0.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -1  # rho_scale
+    assert L.dmk_vol_plan(1e-3, 8, 1.0, 0, 4, 0, None, cb, None, None, None, C.byref(h)) == -1  # min_level
+    assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 20, 0, None, cb, None, None, None, C.byref(h)) == -1  # max_level
+    assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 0, None, dmk.DENSITY_FN(), None, None, None, C.byref(h)) == -1
+    assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 1, None, cb, None, None, None, C.byref(h)) == -1  # NULL features
+    assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 1, bad.ctypes.data_as(C.c_void_p), cb, None, None, None,
+                          C.byref(h)) == -1  # h <= 0
+    om = dmk.Opts(0, 0, dmk.DMK_MIXED, 0, 0, 0.0)
+    assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 1, ok.ctypes.data_as(C.c_void_p), cb, None, C.byref(om), None,
+                          C.byref(h)) == -2  # precision
+    assert calls == [] and h.value is None
+    assert L.dmk_vol_info(None, None, None) == -1
+    assert L.dmk_vol_leaves(None, None, None) == -1
+    assert L.dmk_vol_nodes(None, None, None) == -1
+    assert L.dmk_vol_eval(None, None, None, None, None, None) == -1
     with pytest.raises(dmk.DmkError):
         dmk.precompute_probe(1e-7, 0, np.zeros(1))
     with pytest.raises(dmk.DmkError):

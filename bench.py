@@ -47,8 +47,18 @@ WORKLOADS = {
     "cfg4_batch2d_512": "2-D batch of 512 independent problems, N_b = exp(U[ln 1e3, ln 2e5]) "
                         "(1.79e7 points), U[0,1]^2 or 0.5+0.01 N(0,I) per problem, charges U[-1,1], leaf<=64, "
                         "tol 1e-6; kernel -log(r)/(2 pi) or K_0(10 r) (--kernel)",
+    "cfg5_volume_8gauss": "3-D volume potential on [-1/2,1/2]^3 of rho = sum of 8 Gaussians exp(-|x-c|^2/s^2), "
+                          "s = exp(U[ln 1e-3, ln 1e-1]), c ~ U[-0.3,0.3]^3; adaptive tree of 8^3 Chebyshev leaves "
+                          "(density resolved to 3e-8 of its peak, leaves <= 4 s at each centre), 4.0e7 nodes; "
+                          "Gaussian split, tol 1e-3, FP64",
 }
 METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
+METRIC_VOL = "points/s, 3-D volume potential DMK (box code) at tol 1e-3, 1 GPU"
+STAGE_KERNEL_VOL = {"upward": "k_vol_upward", "root": "k_root_stage", "proxy2pw": "k_proxy2pw",
+                    "pwshift": "k_pwshift", "pw2grid": "k_local_pw", "leaf": "k_vol_leaf", "residual": "k_vol_near",
+                    "finalize": "k_vol_finalize"}
+# volume workload: density, refinement and tree limits
+VOL_SEED, VOL_RHO_SCALE, VOL_MAX_LEVEL = 5, 3e-5, 16
 
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 PMC runs of
@@ -116,6 +126,116 @@ def cpu_baseline(pts, q, ns, tol, seed=7):
                       f"{te:.2f} s, plan {tp:.2f} s excluded, FP64, tol {tol:g}"}
 
 
+def cpu_baseline_vol(sig, cen, amp, feat):
+    """The volume oracle (plain FP64 C, OpenMP) on the same density with the
+    tree cut at level 3 (same refinement rule otherwise): points/s of its
+    eval phase."""
+    import oracle
+    import dmk_inputs
+    vp = oracle.vparams_for(1e-3, 8)
+    f = lambda x: dmk_inputs.gaussian_mixture(x, sig, cen, amp)
+    T = oracle.VTree(vp, f, VOL_RHO_SCALE, 1, 3, features=feat)
+    rho = f(T.nodes())
+    t0 = time.perf_counter()
+    T.eval(rho)
+    te = time.perf_counter() - t0
+    n = T.nleaf * 512
+    return {"value": n / te, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"same density, tree cut at level 3 ({T.nleaf} leaves, {n} nodes), eval phase {te:.2f} s, "
+                      f"tree excluded, FP64, tol 1e-3"}
+
+
+def run_volume(args):
+    import torch
+
+    import dmk_inputs
+    import paper_2308_00292_amd as dmk
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from vol_exact import gauss_mixture_potential  # closed-form reference of the sampled check
+
+    sig, cen, amp = dmk_inputs.vol_gaussians(VOL_SEED)
+    f = lambda x: dmk_inputs.gaussian_mixture(x, sig, cen, amp)
+    feat = dmk_inputs.gaussian_features(sig, cen)
+    log("[bench] volume plan")
+    t0 = time.perf_counter()
+    plan = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
+                       features=feat)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    n = plan.n
+    lev, _ = plan.leaves()
+    log(f"[bench] plan {t_plan:.2f} s: {plan.nleaf} leaves, {n} nodes")
+    xyz = plan.nodes()
+    rho = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for s_, c_, a_ in zip(sig, cen, amp):
+        cc = torch.tensor(c_, dtype=torch.float64, device="cuda")
+        rho += a_ * torch.exp(-((xyz - cc) ** 2).sum(dim=1) / (s_ * s_))
+    out = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        plan.eval(rho, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.eval(rho, out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    value = n / (ms_step * 1e-3)
+    log(f"[bench] {ms_step:.3f} ms/step -> {value:.4g} points/s")
+    plan.stage_timing(True)
+    nst = max(2, min(args.steps, 5))
+    for _ in range(nst):
+        plan.eval(rho, out)
+    torch.cuda.synchronize()
+    stage_ms, launches = plan.stage_times()
+    plan.stage_timing(False)
+    flops, byts = plan.stage_work()
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    avg_ms = stage_ms[dom] / max(1, launches[dom])
+    hbm = STAGE_BOUND[dom] == "hbm"
+    per_launch = (byts[dom] if hbm else flops[dom]) * nst / max(1, launches[dom])
+    achieved = per_launch / (avg_ms * 1e-3) / (1e9 if hbm else 1e12)
+    peak, unit = PEAK["hbm"] if hbm else PEAK["alu64"]
+    roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": None, "kernel": STAGE_KERNEL_VOL.get(dom, dom), "stage": dom, "avg_launch_ms": avg_ms,
+            "launches_per_step": launches[dom] / nst}
+    stages = {}
+    for k in stage_ms:
+        ms = stage_ms[k] / nst
+        if ms <= 0:
+            continue
+        ent = {"ms": round(ms, 4)}
+        if flops[k] > 0:
+            ent["tflops"] = round(flops[k] / (ms * 1e-3) / 1e12, 3)
+        if byts[k] > 0:
+            ent["gbps"] = round(byts[k] / (ms * 1e-3) / 1e9, 1)
+        stages[k] = ent
+    u = out.cpu().numpy()
+    idx = np.random.default_rng(3).choice(n, args.sample_targets // 2, replace=False)
+    ex = gauss_mixture_potential(xyz.cpu().numpy()[idx], sig, cen, amp)
+    err = float(np.linalg.norm(u[idx] - ex) / np.linalg.norm(ex))
+    log(f"[bench] sampled rel l2 vs closed form ({len(idx)} nodes): {err:.3e}")
+    plan.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (volume oracle)")
+        cpu = cpu_baseline_vol(sig, cen, amp, feat)
+        log(f"[bench] cpu baseline {cpu['value']:.4g} points/s on {cpu['cores']} threads")
+    res = {
+        "metric": METRIC_VOL, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["cfg5_volume_8gauss"], "name": "cfg5_volume_8gauss", "n_points": n,
+                   "leaves": plan.nleaf, "levels": np.bincount(lev).tolist(), "q": 8, "p": 18, "nf": 12, "tol": 1e-3,
+                   "t_plan_s": round(t_plan, 3), "sampled_rel_l2_vs_closed_form": err, "stage_ms_per_step": stages},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +258,10 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "cfg5_volume_8gauss":
+        run_volume(args)
+        return
 
     import torch
 

@@ -328,3 +328,9 @@ class VolPlan:
         cnt = np.zeros(len(STAGES), np.int64)
         _check(lib().dmk_stage_times(self._h, _np_ptr(ms), _np_ptr(cnt), len(STAGES)))
         return dict(zip(STAGES, ms)), dict(zip(STAGES, cnt))
+
+    def stage_work(self):
+        fl = np.zeros(len(STAGES))
+        by = np.zeros(len(STAGES))
+        _check(lib().dmk_stage_work(self._h, _np_ptr(fl), _np_ptr(by), len(STAGES)))
+        return dict(zip(STAGES, fl)), dict(zip(STAGES, by))

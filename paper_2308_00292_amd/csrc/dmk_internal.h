@@ -91,6 +91,10 @@ struct VolData {
     double *d_tgl = nullptr, *d_tglw = nullptr;  // Gauss-Legendre rule per log-t panel
     double *d_egl = nullptr, *d_eglw = nullptr;  // Gauss-Legendre rule of the 1-D Gaussian integrals
     double *ufar = nullptr, *unear = nullptr;    // [nleaf q^3], leaf-major
+    // work counts gathered at plan time
+    int64_t n_merge = 0;        // non-leaf children merged by the child->parent matrices
+    int64_t n_pairs = 0;        // (source leaf, target leaf) pairs of the near field
+    int64_t n_gauss = 0;        // Gaussians summed over those pairs
 };
 
 struct Plan {
@@ -222,6 +226,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
                          void *stream);
 void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, double *near_part, hipStream_t s);
 void vol_nodes(Plan *P, double *xyz, hipStream_t s);
+void vol_stage_work(const Plan *P, double *F, double *Bt);
 
 void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
               hipStream_t s);

@@ -1610,6 +1610,10 @@ void stage_work(const Plan *P, double *F, double *Bt)
         Bt[DMK_STAGE_RESIDUAL] = 32 * N;
         return;
     }
+    if (P->is_vol) {
+        vol_stage_work(P, F, Bt);
+        return;
+    }
     const double p3 = p * p * p, p4 = p3 * p;
     const double pwflops = 4 * nh * p3 + 8 * nh * n * p * p + 8 * nh * n * n * p;  // one box, either direction
     const double pwbytes = 2 * el * nh * n * n;                                      // one half spectrum

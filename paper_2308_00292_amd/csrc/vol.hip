@@ -746,6 +746,57 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
     DMK_HIP(hipGetLastError());
 }
 
+// plan-time counts for the work model: merged children, shift pairs, and the
+// near-field pairs and Gaussians (same pruning and panel rule as k_vol_near)
+void vol_count_work(Plan *P)
+{
+    const int64_t nb = P->nbox, nl = P->nleaf;
+    std::vector<uint8_t> fl(nb);
+    std::vector<int32_t> c0(nb), col((size_t)nb * 27), lev(nb), leaf(nl), off(nl + 1);
+    std::vector<double> cen((size_t)nb * 3);
+    DMK_HIP(hipMemcpy(fl.data(), P->bflags, nb, hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(c0.data(), P->child0, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(col.data(), P->colleague, (size_t)nb * 27 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(lev.data(), P->blevel, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(cen.data(), P->bcenter, (size_t)nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(leaf.data(), P->l_leaf, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(off.data(), P->nl_off, (nl + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> src(std::max<int32_t>(off[nl], 1));
+    DMK_HIP(hipMemcpy(src.data(), P->nl_src, (size_t)off[nl] * sizeof(int32_t), hipMemcpyDeviceToHost));
+    VolData &V = P->vol;
+    V.n_merge = 0;
+    P->n_shift_pairs = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        if (fl[b] & 2)
+            for (int k = 0; k < 8; ++k)
+                if (fl[c0[b] + k] & 2) V.n_merge++;
+        if (fl[b] & 4)
+            for (int k = 0; k < 27; ++k) {
+                const int32_t j = col[(size_t)b * 27 + k];
+                if (j >= 0 && (fl[j] & 2)) P->n_shift_pairs++;
+            }
+    }
+    V.n_pairs = V.n_gauss = 0;
+    for (int64_t i = 0; i < nl; ++i) {
+        const int32_t B = leaf[i];
+        const double sB = std::ldexp(1.0, -lev[B]);
+        for (int32_t e = off[i]; e < off[i + 1]; ++e) {
+            const int32_t T = src[e];
+            const double sT = std::ldexp(1.0, -lev[T]);
+            double gap2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double g = std::fabs(cen[3 * (size_t)B + d] - cen[3 * (size_t)T + d]) - 0.5 * (sB + sT);
+                if (g > 0.0) gap2 += g * g;
+            }
+            if (gap2 >= sT * sT) continue;
+            const double u0 = std::log(V.sqL / sT), u1 = std::log(V.tau_a / sB);
+            int npan = (int)std::ceil((u1 - u0) / V.tpan_w - 1e-12);
+            V.n_pairs++;
+            V.n_gauss += (int64_t)std::max(npan, 1) * V.tpan_gl;
+        }
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- plan
@@ -889,6 +940,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         gauss_legendre(32, gx, gw);
         V.d_egl = up64(gx);
         V.d_eglw = up64(gw);
+        vol_count_work(P);
         alloc_workspace(P);
         V.ufar = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
         V.unear = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
@@ -913,6 +965,41 @@ void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, doubl
 {
     if (P->vol.q != VQ || P->p != 18) throw Error{DMK_ERR_STATE, "volume plan with unexpected grid sizes"};
     run_vol_t<double, 18, VQ>(P, rho, u, far_part, near_part, s);
+}
+
+// Algorithmic work of one volume eval (FP64): flops of the separable
+// contractions, bytes that must cross HBM once.
+//   upward    2 (q^3 p + q^2 p^2 + q p^3) per leaf (density -> parent grid),
+//             6 p^4 per merged child; density read once, proxies written once
+//   far       as the point code (proxy->PW, translation, PW->grid, root)
+//   leaf      2 (p^3 q + p^2 q^2 + p q^3) per leaf; anchor grid read, q^3 written
+//   residual  6 q^4 per (pair, Gaussian) (three q x q mode products) and
+//             12 q^4 per leaf (two Laplacians); density read, near part written
+void vol_stage_work(const Plan *P, double *F, double *Bt)
+{
+    const Tables &t = P->tab;
+    const double el = 8.0, p = t.p, n = t.nn, nh = t.nh, q = P->vol.q;
+    const double p3 = p * p * p, p4 = p3 * p, q3 = q * q * q, q4 = q3 * q;
+    const double NL = (double)P->vol.nleaf, N = (double)P->n;
+    for (int i = 0; i < DMK_NSTAGES; ++i) F[i] = Bt[i] = 0.0;
+    const double pwflops = 4 * nh * p3 + 8 * nh * n * p * p + 8 * nh * n * n * p;
+    const double pwbytes = 2 * el * nh * n * n;
+    F[DMK_STAGE_UPWARD] = 2 * (q3 * p + q * q * p * p + q * p3) * NL + 6 * p4 * P->vol.n_merge;
+    Bt[DMK_STAGE_UPWARD] = 8 * q3 * NL + el * p3 * (P->vol.n_merge + P->nfout);
+    const double nw = t.nwn, nwh = t.nwh;
+    F[DMK_STAGE_ROOT] = 2 * (4 * nwh * p3 + 8 * nwh * nw * p * p + 8 * nwh * nw * nw * p);
+    Bt[DMK_STAGE_ROOT] = 16 * p3;
+    F[DMK_STAGE_PROXY2PW] = pwflops * P->nfout;
+    Bt[DMK_STAGE_PROXY2PW] = (el * p3 + pwbytes) * P->nfout;
+    F[DMK_STAGE_PWSHIFT] = 8 * nh * n * n * P->n_shift_pairs;
+    Bt[DMK_STAGE_PWSHIFT] = pwbytes * (P->nfout + P->nfin);
+    F[DMK_STAGE_PW2GRID] = pwflops * P->nfin + 6 * p4 * std::max<int64_t>(P->nanc - 1, 0);
+    Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p3 * P->nanc;
+    F[DMK_STAGE_LEAF] = 2 * (p3 * q + p * p * q * q + p * q3) * NL;
+    Bt[DMK_STAGE_LEAF] = el * p3 * P->nanc + 8 * N;
+    F[DMK_STAGE_RESIDUAL] = 6 * q4 * (double)P->vol.n_gauss + 12 * q4 * NL;
+    Bt[DMK_STAGE_RESIDUAL] = 16 * N;
+    Bt[DMK_STAGE_FINALIZE] = 24 * N;
 }
 
 }  // namespace dmk

@@ -47,9 +47,11 @@
  *     boxes whose distance is at least the source box side (there every
  *     Gaussian of R_L is below eps);
  *   - the t-integral of R_L runs from 1/sigma_{L(source)} to
- *     t_a = 2 eps^(-1/6) 2^{L(target)} on panels of width 1 in log t, 8
- *     Gauss-Legendre nodes each; beyond t_a the expansion above (to the
- *     Delta^2 term) with the derivatives of the target leaf's polynomial.
+ *     t_a = 2 eps^(-1/6) 2^{L(target)} on panels of width 1 in log t, 5
+ *     Gauss-Legendre nodes each (the sum reproduces erfc(r/sigma)/r -
+ *     erfc(t_a r)/r to 3e-6 of 1/r, far below eps = 1e-3); beyond t_a the
+ *     expansion above (to the Delta^2 term) with the derivatives of the
+ *     target leaf's polynomial.
  */
 #include <complex.h>
 #include <math.h>
@@ -83,7 +85,7 @@ int orc_vparams_for(double tol, int q, orc_vparams *vp)
     vp->hw = 2.0 * M_PI / (2.0 * sqrt(3.0) + 2.0);
     vp->nleg = 18;
     vp->tau_a = 2.0 * pow(tol, -1.0 / 6.0);
-    vp->tpan_gl = 8;
+    vp->tpan_gl = 5;
     vp->tpan_w = 1.0;
     return 0;
 }

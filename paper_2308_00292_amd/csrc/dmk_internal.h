@@ -81,7 +81,7 @@ struct VolData {
     int64_t nleaf = 0;
     std::vector<int32_t> level, ijk;     // host leaf list, Morton order
     double tau_a = 0, sqL = 0, tpan_w = 1.0;
-    int tpan_gl = 8;
+    int tpan_gl = 5;
     int32_t *d_level = nullptr, *d_ijk = nullptr;
     int32_t *box2v = nullptr;            // [nbox] volume leaf of a leaf box, -1 otherwise
     double *d_v1 = nullptr;              // [2][p][q] density -> parent proxy matrices
@@ -91,6 +91,15 @@ struct VolData {
     double *d_tgl = nullptr, *d_tglw = nullptr;  // Gauss-Legendre rule per log-t panel
     double *d_egl = nullptr, *d_eglw = nullptr;  // Gauss-Legendre rule of the 1-D Gaussian integrals
     double *ufar = nullptr, *unear = nullptr;    // [nleaf q^3], leaf-major
+    // near-field tables: one q x q matrix per (per-axis offset class, Gaussian)
+    // for a unit source box; pkey[e][3] gives the class of each axis of
+    // gather-list entry e (-1: pair pruned)
+    int32_t *d_pkey = nullptr;
+    int32_t *d_kng = nullptr;            // [nkey] Gaussians of the class
+    int64_t *d_kbase = nullptr;          // [nkey] first Gaussian of the class
+    double *d_gtab = nullptr;            // [ngauss][q][q]
+    double *d_gw = nullptr;              // [ngauss] quadrature weight of the Gaussian
+    int64_t nkey = 0, ngauss_tab = 0;
     // work counts gathered at plan time
     int64_t n_merge = 0;        // non-leaf children merged by the child->parent matrices
     int64_t n_pairs = 0;        // (source leaf, target leaf) pairs of the near field

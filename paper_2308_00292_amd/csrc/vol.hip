@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <unordered_set>
 
 #include "dmk_internal.h"
@@ -401,8 +402,8 @@ struct VolLds {
     static constexpr int up_work = (2 * P3 > Q3 + Q * Q * P + Q * P2) ? 2 * P3 : Q3 + Q * Q * P + Q * P2;
     static size_t up(size_t el) { return el * (2 * P2 + 2 * P * Q + up_work); }
     static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
-    static constexpr int JB = 8;  // Gaussians per pass of the near-field kernel
-    static size_t near() { return sizeof(double) * (Q3 + JB * 3 * Q * Q + 2 * JB * Q3); }
+    static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel)
+    static size_t near() { return sizeof(double) * (Q * Q * (Q + 1) + JB * 3 * Q * Q + JB * Q * Q * (Q + 1) + JB * Q3); }
 };
 
 // proxy charges of the non-leaf boxes of one level
@@ -509,174 +510,205 @@ __global__ void __launch_bounds__(TPB) k_vol_leaf(VDev<T> D, const int32_t *leav
     }
 }
 
-// Near field of each target leaf: sum of Gaussians of R_L over the source
-// leaves of its gather list, then the asymptotic part.  FP64.
+// 1-D factors of the near field for a unit source box, one row (class c,
+// Gaussian j, target node a) per thread:
+//   G[a][b] = (1/2) int_{-1}^{1} exp(-(xi_a - eta)^2 tau_j^2) L_b(eta) d eta,
+//   xi_a = 2 delta + 2^-k x_a, tau_j = t_j / 2,
+// t_j the Gauss-Legendre nodes in log t of the class's panels; 32-point
+// Gauss-Legendre on the part of [-1,1] within 7/tau of xi (the rest is below
+// e^-49), with L_b = (1/q) [1 + 2 sum_k T_k(x_b) T_k(eta)] accumulated as
+// Chebyshev moments.  Row a = 0 also writes the weight
+// (2/sqrt pi) t_j (h/2) w_j of the Gaussian.
+__global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double *tgl, const double *tglw,
+                                                  const double *egl, const double *eglw, int ngl, double tpan_w,
+                                                  double tau_a, double sqL, int q, int64_t nk, const int32_t *kk,
+                                                  const double *kd, const int32_t *kng, const int64_t *kbase,
+                                                  int64_t rows, double *gtab, double *gw)
+{
+    const int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (r >= rows) return;
+    const int64_t g = r / q;
+    const int a = (int)(r % q);
+    int64_t lo = 0, hi = nk - 1;
+    while (lo < hi) {
+        const int64_t m = (lo + hi + 1) / 2;
+        if (kbase[m] <= g) lo = m;
+        else hi = m - 1;
+    }
+    const int64_t c = lo;
+    const int j = (int)(g - kbase[c]), k = kk[c];
+    const double u0 = log(sqL), u1 = log(tau_a) + k * log(2.0);
+    const int npan = kng[c] / ngl;
+    const double hp = (u1 - u0) / npan;
+    const int pan = j / ngl, gi = j % ngl;
+    const double tj = exp(u0 + hp * (pan + 0.5 * (tgl[gi] + 1.0)));
+    const double tau = 0.5 * tj;
+    const double xi = 2.0 * kd[c] + ldexp(1.0, -k) * xq[a];
+    const double lo_ = fmax(-1.0, xi - 7.0 / tau), hi_ = fmin(1.0, xi + 7.0 / tau);
+    double cf[16];
+    for (int m = 0; m < q; ++m) cf[m] = 0.0;
+    if (hi_ > lo_) {
+        const double hc = 0.5 * (lo_ + hi_), hr = 0.5 * (hi_ - lo_);
+        for (int n = 0; n < 32; ++n) {
+            const double eta = hc + hr * egl[n];
+            const double dd = (xi - eta) * tau;
+            const double wgt = exp(-dd * dd) * hr * eglw[n];
+            double t0 = 1.0, t1 = eta;
+            cf[0] += wgt;
+            if (q > 1) cf[1] += wgt * eta;
+            for (int m = 2; m < q; ++m) {
+                const double t2 = 2.0 * eta * t1 - t0;
+                cf[m] += wgt * t2;
+                t0 = t1;
+                t1 = t2;
+            }
+        }
+    }
+    double *out = gtab + (g * q + a) * q;
+    for (int b = 0; b < q; ++b) {
+        double s = cf[0];
+        for (int m = 1; m < q; ++m) s += 2.0 * cos(m * M_PI * (b + 0.5) / q) * cf[m];
+        out[b] = 0.5 * s / q;
+    }
+    if (a == 0) gw[g] = 2.0 / sqrt(M_PI) * tj * 0.5 * hp * tglw[gi];
+}
+
+// Near field of each target leaf: for every source leaf of its gather list
+// that survives the pruning, sum over the class's Gaussians of
+// s_T^2 w_j (G_x (x) G_y (x) G_z) rho_T (three q x q mode products per
+// Gaussian, register-blocked: a thread owns a row of rho or of the
+// intermediate and applies the broadcast 8 x 8 factor); then the asymptotic
+// part from the target's own polynomial.  FP64.
 template <int Q>
 __global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t *leaves, const int32_t *nl_off,
-                                                  const int32_t *nl_src)
+                                                  const int32_t *nl_src, const int32_t *pkey, const int32_t *kng,
+                                                  const int64_t *kbase, const double *gtab, const double *gw)
 {
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NE = 32, NO = Q3 / TPB;
-    static_assert(Q3 % TPB == 0, "leaf grid must fill whole passes of the block");
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, RS = Q + 1, NG = TPB / Q2;
+    static_assert(Q3 % TPB == 0 && TPB % Q2 == 0, "leaf grid must fill whole passes of the block");
     extern __shared__ double vsm[];
-    double *rT = vsm;              // source density
-    double *G = rT + Q3;           // [JB][3][q][q]
-    double *t1 = G + JB * 3 * Q2;  // [JB][q^3]
-    double *t2 = t1 + JB * Q3;     // [JB][q^3]
-    __shared__ double xq[Q], Tx[Q][Q], egl[NE], eglw[NE], tgl[16], tglw[16];
+    double *rT = vsm;                   // [q^2][RS] source density, rows (i0 i1)
+    double *G = rT + Q2 * RS;           // [3][JB][q][q] factors x, y, z
+    double *t1 = G + 3 * JB * Q2;       // [JB][q^2][RS]
+    double *t2 = t1 + JB * Q2 * RS;     // [JB][q^3]
+    __shared__ double wj[JB];
     const int tid = threadIdx.x;
-    for (int t = tid; t < Q; t += TPB) xq[t] = D.xq[t];
-    for (int t = tid; t < Q2; t += TPB) {
-        // T_k(x_b) for the Chebyshev form of the Lagrange basis
-        const int k = t / Q, b = t % Q;
-        Tx[k][b] = cos(k * M_PI * (b + 0.5) / Q);
-    }
-    for (int t = tid; t < NE; t += TPB) {
-        egl[t] = D.egl[t];
-        eglw[t] = D.eglw[t];
-    }
-    for (int t = tid; t < D.ngl; t += TPB) {
-        tgl[t] = D.tgl[t];
-        tglw[t] = D.tglw[t];
-    }
     const int64_t li = blockIdx.x;
     const int32_t B = leaves[li];
     const int32_t vB = D.box2v[B];
     const double sB = ldexp(1.0, -D.blevel[B]);
-    double cB[3];
-    for (int d = 0; d < 3; ++d) cB[d] = D.bcenter[3 * (int64_t)B + d];
-    double acc[NO];
+    const int bc = tid % Q2, grp = tid / Q2;
+    double acc[Q];
 #pragma unroll
-    for (int k = 0; k < NO; ++k) acc[k] = 0.0;
-    const double wnorm = 2.0 / sqrt(M_PI);
+    for (int a = 0; a < Q; ++a) acc[a] = 0.0;
     for (int e = nl_off[li]; e < nl_off[li + 1]; ++e) {
+        const int32_t kx = pkey[3 * (int64_t)e];
+        if (kx < 0) continue;  // pruned: every Gaussian is below eps there
+        const int32_t ky = pkey[3 * (int64_t)e + 1], kz = pkey[3 * (int64_t)e + 2];
         const int32_t T = nl_src[e];
         const double sT = ldexp(1.0, -D.blevel[T]);
-        double cT[3], gap2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            cT[d] = D.bcenter[3 * (int64_t)T + d];
-            const double g = fabs(cB[d] - cT[d]) - 0.5 * (sB + sT);
-            if (g > 0.0) gap2 += g * g;
-        }
-        if (gap2 >= sT * sT) continue;  // every Gaussian of R_L is below eps there
-        const double u0 = log(D.sqL / sT), u1 = log(D.tau_a / sB);
-        int npan = (int)ceil((u1 - u0) / D.tpan_w - 1e-12);
-        if (npan < 1) npan = 1;
-        const double hp = (u1 - u0) / npan;
-        const int ng = npan * D.ngl;
+        const int ng = kng[kx];
+        const int64_t base[3] = {kbase[kx], kbase[ky], kbase[kz]};
         __syncthreads();
         const double *src = D.rho + (int64_t)D.box2v[T] * Q3;
-        for (int t = tid; t < Q3; t += TPB) rT[t] = src[t];
+        for (int t = tid; t < Q3; t += TPB) rT[(t / Q) * RS + t % Q] = src[t];
         for (int j0 = 0; j0 < ng; j0 += JB) {
             const int jb = min(JB, ng - j0);
             __syncthreads();
-            // 1-D factors G_d[a][b] = (s_T/2) int_{-1}^{1} exp(-(xi_a - eta)^2 tau^2) L_b(eta) d eta
-            for (int r = tid; r < jb * 3 * Q; r += TPB) {
-                const int jj = r / (3 * Q), d = (r / Q) % 3, a = r % Q;
-                const int j = j0 + jj, pan = j / D.ngl, g = j % D.ngl;
-                const double tau = exp(u0 + hp * (pan + 0.5 * (tgl[g] + 1.0))) * 0.5 * sT;
-                const double xi = 2.0 * (cB[d] + 0.5 * sB * xq[a] - cT[d]) / sT;
-                const double lo = fmax(-1.0, xi - 7.0 / tau), hi = fmin(1.0, xi + 7.0 / tau);
-                double cf[Q];
-#pragma unroll
-                for (int k = 0; k < Q; ++k) cf[k] = 0.0;
-                if (hi > lo) {
-                    const double hc = 0.5 * (lo + hi), hr = 0.5 * (hi - lo);
-                    for (int n = 0; n < NE; ++n) {
-                        const double eta = hc + hr * egl[n];
-                        const double dd = (xi - eta) * tau;
-                        const double wgt = exp(-dd * dd) * hr * eglw[n];
-                        double tk0 = 1.0, tk1 = eta;
-                        cf[0] += wgt;
-                        cf[1] += wgt * eta;
-#pragma unroll
-                        for (int k = 2; k < Q; ++k) {
-                            const double tk2 = 2.0 * eta * tk1 - tk0;
-                            cf[k] += wgt * tk2;
-                            tk0 = tk1;
-                            tk1 = tk2;
-                        }
-                    }
-                }
-                // L_b = (1/q) [1 + 2 sum_{k>=1} T_k(x_b) T_k(eta)]
-                double *gr = G + ((jj * 3 + d) * Q + a) * Q;
-                for (int b = 0; b < Q; ++b) {
-                    double s = cf[0];
-#pragma unroll
-                    for (int k = 1; k < Q; ++k) s += 2.0 * Tx[k][b] * cf[k];
-                    gr[b] = 0.5 * sT * s / Q;
-                }
+            for (int t = tid; t < 3 * JB * Q2; t += TPB) {
+                const int d = t / (JB * Q2), jj = (t / Q2) % JB, m = t % Q2;
+                if (jj < jb) G[t] = gtab[(base[d] + j0 + jj) * Q2 + m];
             }
+            if (tid < jb) wj[tid] = gw[base[0] + j0 + tid] * sT * sT;
             __syncthreads();
-            // z: t1[jj][i0][i1][c] = sum_i2 G_z[jj][c][i2] rT[i0][i1][i2]
-            for (int o = tid; o < jb * Q3; o += TPB) {
-                const int jj = o / Q3, r = o % Q3, c = r % Q, i01 = r / Q;
-                const double *g = G + ((jj * 3 + 2) * Q + c) * Q;
-                double s = 0.0;
+            // z: t1[jj][(i0 i1)][c] = sum_i2 G_z[jj][c][i2] rT[(i0 i1)][i2]
+            for (int it = tid; it < jb * Q2; it += TPB) {
+                const int jj = it / Q2, r = it % Q2;
+                double x[Q];
 #pragma unroll
-                for (int k = 0; k < Q; ++k) s += g[k] * rT[i01 * Q + k];
-                t1[o] = s;
-            }
-            __syncthreads();
-            // y: t2[jj][i0][b][c] = sum_i1 G_y[jj][b][i1] t1[jj][i0][i1][c]
-            for (int o = tid; o < jb * Q3; o += TPB) {
-                const int jj = o / Q3, r = o % Q3, c = r % Q, b = (r / Q) % Q, i0 = r / Q2;
-                const double *g = G + ((jj * 3 + 1) * Q + b) * Q;
-                const double *tt = t1 + jj * Q3 + i0 * Q2 + c;
-                double s = 0.0;
+                for (int k = 0; k < Q; ++k) x[k] = rT[r * RS + k];
+                const double *g = G + (2 * JB + jj) * Q2;
+                double *o = t1 + (jj * Q2 + r) * RS;
 #pragma unroll
-                for (int k = 0; k < Q; ++k) s += g[k] * tt[k * Q];
-                t2[o] = s;
-            }
-            __syncthreads();
-            // x: u[a][b][c] += w_j sum_i0 G_x[jj][a][i0] t2[jj][i0][b][c]
-#pragma unroll
-            for (int k = 0; k < NO; ++k) {
-                const int o = tid + k * TPB, a = o / Q2, bc = o % Q2;
-                for (int jj = 0; jj < jb; ++jj) {
-                    const int j = j0 + jj, pan = j / D.ngl, g = j % D.ngl;
-                    const double tj = exp(u0 + hp * (pan + 0.5 * (tgl[g] + 1.0)));
-                    const double wj = wnorm * tj * 0.5 * hp * tglw[g];
-                    const double *gx = G + ((jj * 3 + 0) * Q + a) * Q;
+                for (int c = 0; c < Q; ++c) {
                     double s = 0.0;
 #pragma unroll
-                    for (int i0 = 0; i0 < Q; ++i0) s += gx[i0] * t2[jj * Q3 + i0 * Q2 + bc];
-                    acc[k] += wj * s;
+                    for (int k = 0; k < Q; ++k) s += g[c * Q + k] * x[k];
+                    o[c] = s;
+                }
+            }
+            __syncthreads();
+            // y: t2[jj][i0][b][c] = sum_i1 G_y[jj][b][i1] t1[jj][(i0 i1)][c]
+            for (int it = tid; it < jb * Q2; it += TPB) {
+                const int jj = it / Q2, i0 = (it / Q) % Q, c = it % Q;
+                double y[Q];
+#pragma unroll
+                for (int i1 = 0; i1 < Q; ++i1) y[i1] = t1[(jj * Q2 + i0 * Q + i1) * RS + c];
+                const double *g = G + (JB + jj) * Q2;
+                double *o = t2 + jj * Q3 + i0 * Q2 + c;
+#pragma unroll
+                for (int b = 0; b < Q; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i1 = 0; i1 < Q; ++i1) s += g[b * Q + i1] * y[i1];
+                    o[b * Q] = s;
+                }
+            }
+            __syncthreads();
+            // x: acc[a] += w_j sum_i0 G_x[jj][a][i0] t2[jj][i0][(b c)]
+            for (int jj = grp; jj < jb; jj += NG) {
+                double z[Q];
+#pragma unroll
+                for (int i0 = 0; i0 < Q; ++i0) z[i0] = t2[jj * Q3 + i0 * Q2 + bc];
+                const double *g = G + jj * Q2;
+                const double w = wj[jj];
+#pragma unroll
+                for (int a = 0; a < Q; ++a) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i0 = 0; i0 < Q; ++i0) s += g[a * Q + i0] * z[i0];
+                    acc[a] += w * s;
                 }
             }
         }
     }
-    // asymptotic part: Gaussians with t >= t_a over R^3 from rho_B's polynomial
+    // partial sums of the Gaussian groups, then the asymptotic part:
+    // Gaussians with t >= t_a over R^3 from rho_B's polynomial
     __syncthreads();
+#pragma unroll
+    for (int a = 0; a < Q; ++a) t2[(grp * Q + a) * Q2 + bc] = acc[a];
+    double *rB = G, *d2 = G + Q3, *l1 = t1, *l2 = t1 + Q3;
     const double *rb = D.rho + (int64_t)vB * Q3;
-    for (int t = tid; t < Q3; t += TPB) rT[t] = rb[t];
-    for (int t = tid; t < Q2; t += TPB) G[t] = D.d2[t];
+    for (int t = tid; t < Q3; t += TPB) rB[t] = rb[t];
+    for (int t = tid; t < Q2; t += TPB) d2[t] = D.d2[t];
     __syncthreads();
     const double lsc = 4.0 / (sB * sB);
     for (int o = tid; o < Q3; o += TPB) {
         const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
         double s = 0.0;
         for (int j = 0; j < Q; ++j)
-            s += G[a * Q + j] * rT[(j * Q + b) * Q + c] + G[b * Q + j] * rT[(a * Q + j) * Q + c] +
-                 G[c * Q + j] * rT[(a * Q + b) * Q + j];
-        t1[o] = s * lsc;
+            s += d2[a * Q + j] * rB[(j * Q + b) * Q + c] + d2[b * Q + j] * rB[(a * Q + j) * Q + c] +
+                 d2[c * Q + j] * rB[(a * Q + b) * Q + j];
+        l1[o] = s * lsc;
     }
     __syncthreads();
     for (int o = tid; o < Q3; o += TPB) {
         const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
         double s = 0.0;
         for (int j = 0; j < Q; ++j)
-            s += G[a * Q + j] * t1[(j * Q + b) * Q + c] + G[b * Q + j] * t1[(a * Q + j) * Q + c] +
-                 G[c * Q + j] * t1[(a * Q + b) * Q + j];
-        t2[o] = s * lsc;
+            s += d2[a * Q + j] * l1[(j * Q + b) * Q + c] + d2[b * Q + j] * l1[(a * Q + j) * Q + c] +
+                 d2[c * Q + j] * l1[(a * Q + b) * Q + j];
+        l2[o] = s * lsc;
     }
     __syncthreads();
     const double ta = D.tau_a / sB, ta2 = ta * ta;
+    for (int o = tid; o < Q3; o += TPB) {
+        double near = 0.0;
 #pragma unroll
-    for (int k = 0; k < NO; ++k) {
-        const int o = tid + k * TPB;
-        const double tail = 2.0 * M_PI * (rT[o] / (2.0 * ta2) + t1[o] / (16.0 * ta2 * ta2) +
-                                          t2[o] / (192.0 * ta2 * ta2 * ta2));
-        D.unear[(int64_t)vB * Q3 + o] = acc[k] + tail;
+        for (int g = 0; g < NG; ++g) near += t2[g * Q3 + o];
+        const double tail =
+            2.0 * M_PI * (rB[o] / (2.0 * ta2) + l1[o] / (16.0 * ta2 * ta2) + l2[o] / (192.0 * ta2 * ta2 * ta2));
+        D.unear[(int64_t)vB * Q3 + o] = near + tail;
     }
 }
 
@@ -735,8 +767,9 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
         VDev<double> D64 = make_vdev<double>(Pl);
         D64.rho = rho;
+        const VolData &V = Pl->vol;
         hipLaunchKernelGGL((k_vol_near<Q>), dim3((unsigned)Pl->nleaf), dim3(TPB), LD::near(), s, D64, Pl->l_leaf,
-                           Pl->nl_off, Pl->nl_src);
+                           Pl->nl_off, Pl->nl_src, V.d_pkey, V.d_kng, V.d_kbase, V.d_gtab, V.d_gw);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -746,9 +779,22 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
     DMK_HIP(hipGetLastError());
 }
 
-// plan-time counts for the work model: merged children, shift pairs, and the
-// near-field pairs and Gaussians (same pruning and panel rule as k_vol_near)
-void vol_count_work(Plan *P)
+// Gaussians of the near field of a pair whose target is 2^-k times the
+// source side: Gauss-Legendre panels of width <= tpan_w in log t from
+// sqrt(log(1/eps)) / s_T to tau_a / s_B
+int vol_npan(const VolData &V, int k)
+{
+    const double u0 = std::log(V.sqL), u1 = std::log(V.tau_a) + k * std::log(2.0);
+    return std::max(1, (int)std::ceil((u1 - u0) / V.tpan_w - 1e-12));
+}
+
+// Plan-time pass over the gather lists: work counts for the model (merged
+// children, shift pairs, near-field pairs and Gaussians) and the offset
+// classes of the near field.  For a pair (source T, target B) that survives
+// the pruning (box distance below s_T) each axis d has the class
+// (k = L_B - L_T, delta = (c_B,d - c_T,d) / s_T): its 1-D factors for a unit
+// source box depend on nothing else.
+void vol_count_work(Plan *P, hipStream_t s)
 {
     const int64_t nb = P->nbox, nl = P->nleaf;
     std::vector<uint8_t> fl(nb);
@@ -761,8 +807,9 @@ void vol_count_work(Plan *P)
     DMK_HIP(hipMemcpy(cen.data(), P->bcenter, (size_t)nb * 3 * sizeof(double), hipMemcpyDeviceToHost));
     DMK_HIP(hipMemcpy(leaf.data(), P->l_leaf, nl * sizeof(int32_t), hipMemcpyDeviceToHost));
     DMK_HIP(hipMemcpy(off.data(), P->nl_off, (nl + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
-    std::vector<int32_t> src(std::max<int32_t>(off[nl], 1));
-    DMK_HIP(hipMemcpy(src.data(), P->nl_src, (size_t)off[nl] * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const int64_t ne = off[nl];
+    std::vector<int32_t> src(std::max<int64_t>(ne, 1));
+    DMK_HIP(hipMemcpy(src.data(), P->nl_src, (size_t)ne * sizeof(int32_t), hipMemcpyDeviceToHost));
     VolData &V = P->vol;
     V.n_merge = 0;
     P->n_shift_pairs = 0;
@@ -776,6 +823,10 @@ void vol_count_work(Plan *P)
                 if (j >= 0 && (fl[j] & 2)) P->n_shift_pairs++;
             }
     }
+    std::map<std::pair<int, uint64_t>, int32_t> cls;
+    std::vector<int> ck;
+    std::vector<double> cd;
+    std::vector<int32_t> pkey((size_t)std::max<int64_t>(ne, 1) * 3, -1);
     V.n_pairs = V.n_gauss = 0;
     for (int64_t i = 0; i < nl; ++i) {
         const int32_t B = leaf[i];
@@ -789,12 +840,64 @@ void vol_count_work(Plan *P)
                 if (g > 0.0) gap2 += g * g;
             }
             if (gap2 >= sT * sT) continue;
-            const double u0 = std::log(V.sqL / sT), u1 = std::log(V.tau_a / sB);
-            int npan = (int)std::ceil((u1 - u0) / V.tpan_w - 1e-12);
+            const int k = lev[B] - lev[T];
+            for (int d = 0; d < 3; ++d) {
+                const double delta = (cen[3 * (size_t)B + d] - cen[3 * (size_t)T + d]) / sT;  // exact (dyadic)
+                uint64_t bits;
+                std::memcpy(&bits, &delta, sizeof(bits));
+                auto it = cls.find({k, bits});
+                int32_t id;
+                if (it == cls.end()) {
+                    id = (int32_t)ck.size();
+                    cls.emplace(std::make_pair(k, bits), id);
+                    ck.push_back(k);
+                    cd.push_back(delta);
+                } else {
+                    id = it->second;
+                }
+                pkey[3 * (size_t)e + d] = id;
+            }
             V.n_pairs++;
-            V.n_gauss += (int64_t)std::max(npan, 1) * V.tpan_gl;
+            V.n_gauss += (int64_t)vol_npan(V, k) * V.tpan_gl;
         }
     }
+    // classes -> tables on the device
+    const int64_t nk = (int64_t)ck.size();
+    std::vector<int32_t> kng(std::max<int64_t>(nk, 1), 0), kk(std::max<int64_t>(nk, 1), 0);
+    std::vector<int64_t> kbase(std::max<int64_t>(nk, 1), 0);
+    int64_t ng = 0;
+    for (int64_t c = 0; c < nk; ++c) {
+        kng[c] = vol_npan(V, ck[c]) * V.tpan_gl;
+        kk[c] = ck[c];
+        kbase[c] = ng;
+        ng += kng[c];
+    }
+    V.nkey = nk;
+    V.ngauss_tab = ng;
+    const int q = V.q;
+    auto upi = [&](const std::vector<int32_t> &h) {
+        int32_t *d = (int32_t *)dalloc(P, h.size() * sizeof(int32_t));
+        DMK_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        return d;
+    };
+    V.d_pkey = upi(pkey);
+    V.d_kng = upi(kng);
+    int32_t *d_kk = upi(kk);
+    V.d_kbase = (int64_t *)dalloc(P, kbase.size() * sizeof(int64_t));
+    DMK_HIP(hipMemcpyAsync(V.d_kbase, kbase.data(), kbase.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    std::vector<double> cdp(cd);
+    cdp.resize(std::max<int64_t>(nk, 1), 0.0);
+    double *d_cd = (double *)dalloc(P, cdp.size() * sizeof(double));
+    DMK_HIP(hipMemcpyAsync(d_cd, cdp.data(), cdp.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    V.d_gtab = (double *)dalloc(P, (size_t)std::max<int64_t>(ng, 1) * q * q * sizeof(double));
+    V.d_gw = (double *)dalloc(P, (size_t)std::max<int64_t>(ng, 1) * sizeof(double));
+    const int64_t rows = ng * q;
+    if (rows > 0)
+        hipLaunchKernelGGL(k_vol_gtab, dim3(vblk(rows)), dim3(TPB), 0, s, V.d_xq, V.d_tgl, V.d_tglw, V.d_egl,
+                           V.d_eglw, V.tpan_gl, V.tpan_w, V.tau_a, V.sqL, q, nk, d_kk, d_cd, V.d_kng, V.d_kbase,
+                           rows, V.d_gtab, V.d_gw);
+    DMK_HIP(hipGetLastError());
+    DMK_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -853,7 +956,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         V.nleaf = nleaf;
         V.tau_a = 2.0 * std::pow(tol, -1.0 / 6.0);
         V.sqL = std::sqrt(std::log(1.0 / tol));
-        V.tpan_gl = 8;
+        V.tpan_gl = 5;
         V.tpan_w = 1.0;
         V.level.resize(nleaf);
         V.ijk.resize(3 * nleaf);
@@ -934,13 +1037,14 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
             for (int j = 0; j < q; ++j)
                 for (int k = 0; k < q; ++k) d2[i * q + j] += d1[i * q + k] * d1[k * q + j];
         V.d_d2 = up64(d2);
-        gauss_legendre(V.tpan_gl, gx, gw);
-        V.d_tgl = up64(gx);
-        V.d_tglw = up64(gw);
-        gauss_legendre(32, gx, gw);
-        V.d_egl = up64(gx);
-        V.d_eglw = up64(gw);
-        vol_count_work(P);
+        std::vector<double> tx, tw, ex, ew;  // distinct buffers: the copies are asynchronous
+        gauss_legendre(V.tpan_gl, tx, tw);
+        V.d_tgl = up64(tx);
+        V.d_tglw = up64(tw);
+        gauss_legendre(32, ex, ew);
+        V.d_egl = up64(ex);
+        V.d_eglw = up64(ew);
+        vol_count_work(P, s);
         alloc_workspace(P);
         V.ufar = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
         V.unear = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));

@@ -115,7 +115,8 @@ def test_sum_of_gaussians_reproduces_erfc(gs, vp):
         r = np.geomspace(1e-4, 3.0, 300)
         approx = (np.exp(-np.outer(r ** 2, t ** 2)) @ w) + erfc(hi * r) / r
         exact = erfc(lo * r) / r
-        assert np.max(np.abs(approx - exact) * r) < 1e-8
+        # 5 nodes per unit panel in log t: 3e-6 of 1/r, far below tol = 1e-3
+        assert np.max(np.abs(approx - exact) * r) < 1e-5
 
 
 # ---------------------------------------------------------------------- tree

@@ -118,7 +118,7 @@ typedef struct {
  *
  * Paper: Step 0 (initialisation: level-restricted adaptive tree, flags
  * F_leaf/F_out/F_in) and Step 1 (precomputation of the 1-D transforms and
- * plane-wave weights) of Sec. 3.6; tree conventions of Sec. 3.3; parameters
+ * plane-wave weights) of Sec. 3.5; tree conventions of Sec. 3.2; parameters
  * c, N_1 = 2 n_f + 1, p of Table 1 (Sec. 3.7).
  *
  *  dim     2 or 3.
@@ -142,7 +142,7 @@ dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const dou
  * dmk_plan_batched -- one plan for nprob independent point sets.
  *
  * Paper: the same steps as dmk_plan, applied to every problem; each problem
- * gets its own root box from its own bounding box (Sec. 3.3).  The trees
+ * gets its own root box from its own bounding box (Sec. 3.1).  The trees
  * form a forest: level 0 holds the nprob roots, boxes of all problems are
  * interleaved level by level, and every stage of dmk_eval is one launch over
  * the boxes of all problems.
@@ -168,7 +168,7 @@ dmk_status dmk_plan_batched(int dim, dmk_kernel kernel, double tol, int32_t npro
  *
  * Paper: n_s balances the cost of the local (residual) interactions against
  * all other steps and is chosen by experiment (remark at the end of Sec.
- * 3.6; Sec. 6.1 quotes the values used).  Every candidate gives a result
+ * 3.5; Sec. 5.1 quotes the values used).  Every candidate gives a result
  * within tol; only the time differs.
  *
  *  dim, kernel, tol, opts  as dmk_plan / dmk_plan_batched (opts->leaf_max is
@@ -195,7 +195,7 @@ dmk_status dmk_problem_info(dmk_plan_t plan, int32_t prob, double *center, doubl
 /*
  * dmk_eval -- potentials of one charge vector on a planned point set.
  *
- * Paper: Steps 2-5 of Sec. 3.6 (upward pass, downward pass, direct
+ * Paper: Steps 2-5 of Sec. 3.5 (upward pass, downward pass, direct
  * interactions with the residual kernel, self-interaction correction).
  *
  *  charges device, [n] FP64, input order.
@@ -280,7 +280,7 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
 
 /*
  * dmk_precompute_probe -- HOST-only view of the tables that Step 1 of
- * Sec. 3.6 builds for a tolerance; no device is touched, so it also runs on
+ * Sec. 3.5 builds for a tolerance; no device is touched, so it also runs on
  * machines without a GPU.  x and out are host arrays of n entries.
  *   what = 0: psi_0^c(x_i) / psi_0^c(0) for any real x_i (the PSWF of the
  *             tolerance's c, continued off [-1,1] by the eigen-relation of
@@ -293,10 +293,10 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
  *   what = 3: plane-wave weight of the windowed W_0 at |m|^2 = x_i;
  *   what = 4: out[0..3] = psi(0), c_0, c_2, lambda_0 (n >= 4, x unused);
  *   what = 5: out[0..5] = c, n_f, p, n_w, h_w, degree of g (n >= 6);
- * 2-D tables (kernel -log(r)/(2 pi), Fourier-space split of Sec. 4.4):
+ * 2-D tables (kernel -log(r)/(2 pi), Fourier-space split of Sec. 4.6):
  *   what = 6: plane-wave weight of D_l at |m|^2 = x_i (the same at every
  *             level), NaN if no mode of the table has that |m|^2;
- *   what = 7: plane-wave weight of the windowed W_0 (Sec. 4.5) at |m|^2 = x_i;
+ *   what = 7: plane-wave weight of the windowed W_0 (Sec. 4.7) at |m|^2 = x_i;
  *   what = 8: m(x_i), the smooth part of the residual
  *             R_l(r) = -log(x)/(2 pi) - m(x), x = r/s_l in [0,1];
  *   what = 9: out[0..3] = m(0), n_w, h_w, degree of m (n >= 4).

@@ -1,5 +1,5 @@
 /*
- * dmk.c -- Steps 1-5 of the discrete DMK algorithm (Sec. 3.6, "The full DMK
+ * dmk.c -- Steps 1-5 of the discrete DMK algorithm (Sec. 3.5, "The full DMK
  * algorithm for discrete sources") for the 3-D Laplace kernel with the PSWF
  * split of Sec. 3.7, plus direct summation.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain FP64 loops; the

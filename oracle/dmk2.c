@@ -1,7 +1,7 @@
 /*
- * dmk2.c -- the discrete DMK algorithm (Sec. 3.6, Steps 1-5) in two
+ * dmk2.c -- the discrete DMK algorithm (Sec. 3.5, Steps 1-5) in two
  * dimensions, for K(r) = -log(r)/(2 pi) and K(r) = K_0(lambda r) with the
- * Fourier-space PSWF split of Sec. 4.4 (see split2.c), plus direct summation.
+ * Fourier-space PSWF split of Sec. 4.6 (see split2.c), plus direct summation.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain FP64 loops.
  *
  * The conventions of the 3-D driver carry over with d = 2: box side

@@ -16,7 +16,7 @@
  *     and the plane-wave weights (eqs. differencekernelft3, windowedkernelft2,
  *     wlmdef, with the trapezoidal factor h^d).
  *   - The level-restricted adaptive tree, colleagues, coarse neighbours,
- *     flags F_leaf/F_out/F_in (Sec. 3.3 and Sec. 3.6 "The full DMK algorithm
+ *     flags F_leaf/F_out/F_in (Sec. 3.2 and Sec. 3.5 "The full DMK algorithm
  *     for discrete sources", Step 0).
  *   - Steps 1-5 of that algorithm: proxies, upward pass, plane-wave outgoing
  *     and incoming expansions, local expansions, direct residual sums,
@@ -149,8 +149,8 @@ int orc_num_threads(void);
 
 /* ------------------------------------------------------------------- 2-D
  * Kernels (input units): ORC_LOG2 K(r) = -log(r)/(2 pi); ORC_YUK2 K(r) =
- * K_0(lambda r).  Split in Fourier space (Sec. 4.4, eq. yukawaPSWFkernels),
- * windowed root kernel (Sec. 4.5); see split2.c. */
+ * K_0(lambda r).  Split in Fourier space (Sec. 4.6, eq. yukawaPSWFkernels),
+ * windowed root kernel (Sec. 4.7); see split2.c. */
 enum { ORC_LOG2 = 0, ORC_YUK2 = 1 };
 #define ORC2_DEG 47   /* Chebyshev degree (in x^2) of the residual tables */
 

@@ -17,7 +17,7 @@
  *   R_L(r) = (1 - Phi(r/s_L))/r.
  * Fourier transforms: eq. differencekernelft3 for D_l; the windowed W_0 is the
  * mollifier transform psi(k s_0/c)/psi(0) times the transform of 1/r
- * truncated at A = (1 + sqrt 3) s_0 (Sec. 4.4, "Handling singularities in
+ * truncated at A = (1 + sqrt 3) s_0 (Sec. 4.7, "Handling singularities in
  * Fourier space", and the Vico truncation remark of Sec. 3.1), which is
  * 8 pi sin^2(kA/2)/k^2.
  */

@@ -10,7 +10,7 @@
  * psi(kappa s_l/c)/psi(0), s_l = 2^{-l} being the box side at level l:
  *   Dhat_l(k) = a [psi(kappa s_{l+1}/c) - psi(kappa s_l/c)] / (psi(0) kappa^2),
  *   a = 1 (log) or 2 pi (K_0).
- * The root carries the windowed kernel of Sec. 4.5 ("Handling singularities
+ * The root carries the windowed kernel of Sec. 4.7 ("Handling singularities
  * in Fourier space"): What_0 = psi(kappa s_0/c)/psi(0) * That(k), That being
  * the transform of K truncated at radius A = (1 + sqrt 2) s_0 (the Vico
  * truncation); for the log kernel

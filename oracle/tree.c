@@ -3,7 +3,7 @@
  * with colleagues, coarse neighbours and the flags of Step 0.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Definitions (Sec. 3.3, "An O(N log N) DMK method"; Sec. 3.6, Step 0):
+ * Definitions (Sec. 3.2, "An O(N log N) DMK method"; Sec. 3.5, Step 0):
  *  - points are rescaled and centred into the unit box [-1/2,1/2]^d;
  *  - a box is refined (into all 2^d children) while it holds more than n_s
  *    points and its level is below the depth cap;

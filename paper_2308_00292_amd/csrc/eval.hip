@@ -1,4 +1,4 @@
-// Steps 2-5 of the discrete DMK algorithm (Sec. 3.6) on gfx950.
+// Steps 2-5 of the discrete DMK algorithm (Sec. 3.5) on gfx950.
 //
 // Every stage is one kernel per tree level (one workgroup per box), written
 // once as a template over the arithmetic type T (double for the FP64 path,

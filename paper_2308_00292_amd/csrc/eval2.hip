@@ -1,6 +1,6 @@
-// Steps 2-5 of the discrete DMK algorithm (Sec. 3.6) in two dimensions on
+// Steps 2-5 of the discrete DMK algorithm (Sec. 3.5) in two dimensions on
 // gfx950, for the kernel -log(r)/(2 pi) with the Fourier-space PSWF split of
-// Sec. 4.4 and the windowed root kernel of Sec. 4.5.  The plan may hold many
+// Sec. 4.6 and the windowed root kernel of Sec. 4.7.  The plan may hold many
 // independent problems (a forest, one root per problem); every launch covers
 // the boxes of all problems.
 //

@@ -1,4 +1,4 @@
-// Step 0 of the discrete DMK algorithm (Sec. 3.6) on the GPU: root box,
+// Step 0 of the discrete DMK algorithm (Sec. 3.5) on the GPU: root box,
 // Morton keys, stable radix sort, the level-restricted adaptive tree (Sec.
 // 3.3; octree in 3-D, quadtree in 2-D), colleagues, coarse neighbours, the
 // flags F_leaf/F_out/F_in, per-level work lists and the residual interaction

@@ -1,4 +1,4 @@
-// Step 1 of the discrete DMK algorithm (Sec. 3.6): host-side precomputation
+// Step 1 of the discrete DMK algorithm (Sec. 3.5): host-side precomputation
 // in FP64 of everything the device stages read.
 //
 //  * psi_0^c, the first prolate spheroidal wave function of order zero
@@ -341,14 +341,14 @@ void build_tables(const Params &prm, Tables *t, int dim)
 }
 
 // ---------------------------------------------------------------- 2-D
-// Kernel -log(r)/(2 pi), split in Fourier space (Sec. 4.4): its transform
+// Kernel -log(r)/(2 pi), split in Fourier space (Sec. 4.6): its transform
 // 1/k^2 times the mollifier psi(k s_l/c)/psi(0).
 //  * D_l weights (h_l/2pi)^2 Dhat_l(h_l |m|), h_l s_l = 2 pi/3:
 //      w(m) = [psi(pi|m|/(3c)) - psi(2pi|m|/(3c))] / (4 pi^2 psi(0) |m|^2),
 //      w(0) = c_2/(24 c_0) (the k -> 0 limit), the same at every level
 //      (scale invariance of the log kernel up to a constant).
 //  * W_0 weights (hw/2pi)^2 psi(k/c)/psi(0) That(k), That the transform of the
-//    kernel cut at A = 1 + sqrt 2 (Sec. 4.5):
+//    kernel cut at A = 1 + sqrt 2 (Sec. 4.7):
 //      That(k) = (1 - J_0(kA))/k^2 - A log(A) J_1(kA)/k, That(0) = A^2/4 - A^2 log(A)/2.
 //  * The residual R_l(r) = -log(x)/(2 pi) - m(x), x = r/s_l < 1, with
 //      m(x) = (1/2 pi) int_0^{2c} psi(t/c)/psi(0) (J_0(tx) - J_0(t)) dt/t

@@ -1,4 +1,4 @@
-// Tables of the 2-D kernel K_0(lambda r) (Sec. 4.4, eq. yukawaPSWFkernels,
+// Tables of the 2-D kernel K_0(lambda r) (Sec. 4.6, eq. yukawaPSWFkernels,
 // taken with the transform 2 pi/(k^2 + lambda^2) of K_0(lambda r)).
 //
 // The split is not scale invariant: everything depends on mu = lambda S_b s_l
@@ -17,7 +17,7 @@
 //    J_0(z) = (1/pi) int_0^pi cos(z sin th) dth (exponentially convergent for
 //    this periodic analytic integrand), psi(x)/psi(0) on [0,2] from a
 //    piecewise Chebyshev interpolant built on the host;
-//  * the root's windowed kernel per problem (Sec. 4.5): psi(kappa/c)/psi(0)
+//  * the root's windowed kernel per problem (Sec. 4.7): psi(kappa/c)/psi(0)
 //    times the transform of K_0 truncated at A = 1 + sqrt 2,
 //      That(k) = 2 pi {1 + A [k J_1(kA) K_0(lA) - l J_0(kA) K_1(lA)]}/(k^2 + l^2)  (host).
 #include <algorithm>

@@ -1,6 +1,6 @@
 """C-ABI checks that need no GPU: the library loads, exports every entry point
 that include/dmk.h declares, validates arguments before touching a device,
-and its host-side tables (Step 1 of Sec. 3.6) agree with the oracle's
+and its host-side tables (Step 1 of Sec. 3.5) agree with the oracle's
 independently computed PSWF, window and plane-wave weights."""
 import ctypes as C
 import os

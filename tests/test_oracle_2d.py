@@ -1,6 +1,6 @@
 """Pins of the 2-D oracle (CPU only): kernels -log(r)/(2 pi) and K_0(lambda r)
-with the Fourier-space PSWF split (Sec. 4.4) and the windowed root kernel
-(Sec. 4.5).
+with the Fourier-space PSWF split (Sec. 4.6) and the windowed root kernel
+(Sec. 4.7).
 
   * Bessel K_0, K_1 against scipy.special (library routines);
   * the residual tables against the quadrature that defines them, and the

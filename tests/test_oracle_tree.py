@@ -1,6 +1,6 @@
 """Pins of the oracle's adaptive tree (CPU only), by brute force over boxes.
 
-Definitions (Sec. 3.3 and Step 0 of Sec. 3.6): refinement while a box holds
+Definitions (Sec. 3.2 and Step 0 of Sec. 3.5): refinement while a box holds
 more than n_s points; level restriction between leaves that share a boundary
 point; colleagues; coarse neighbours; flags F_leaf / F_out / F_in.  The
 oracle builds the tree by fixing violations one at a time; here every property

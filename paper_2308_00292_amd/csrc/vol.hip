@@ -580,12 +580,16 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
 // intermediate and applies the broadcast 8 x 8 factor); then the asymptotic
 // part from the target's own polynomial.  FP64.
 template <int Q>
-__global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t *leaves, const int32_t *nl_off,
+constexpr int vol_near_threads = Q * Q * 5;  // q^2 rows times the Gaussians of one panel
+
+template <int Q>
+__global__ void __launch_bounds__(vol_near_threads<Q>) k_vol_near(VDev<double> D, const int32_t *leaves, const int32_t *nl_off,
                                                   const int32_t *nl_src, const int32_t *pkey, const int32_t *kng,
                                                   const int64_t *kbase, const double *gtab, const double *gw)
 {
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, RS = Q + 1, NG = TPB / Q2;
-    static_assert(Q3 % TPB == 0 && TPB % Q2 == 0, "leaf grid must fill whole passes of the block");
+    // one thread per (Gaussian of the pass, row): JB q^2 threads
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, RS = Q + 1, NT = JB * Q2, NG = JB;
+    static_assert(NT == vol_near_threads<Q>, "block size");
     extern __shared__ double vsm[];
     double *rT = vsm;                   // [q^2][RS] source density, rows (i0 i1)
     double *G = rT + Q2 * RS;           // [3][JB][q][q] factors x, y, z
@@ -611,18 +615,18 @@ __global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t 
         const int64_t base[3] = {kbase[kx], kbase[ky], kbase[kz]};
         __syncthreads();
         const double *src = D.rho + (int64_t)D.box2v[T] * Q3;
-        for (int t = tid; t < Q3; t += TPB) rT[(t / Q) * RS + t % Q] = src[t];
+        for (int t = tid; t < Q3; t += NT) rT[(t / Q) * RS + t % Q] = src[t];
         for (int j0 = 0; j0 < ng; j0 += JB) {
             const int jb = min(JB, ng - j0);
             __syncthreads();
-            for (int t = tid; t < 3 * JB * Q2; t += TPB) {
+            for (int t = tid; t < 3 * JB * Q2; t += NT) {
                 const int d = t / (JB * Q2), jj = (t / Q2) % JB, m = t % Q2;
                 if (jj < jb) G[t] = gtab[(base[d] + j0 + jj) * Q2 + m];
             }
             if (tid < jb) wj[tid] = gw[base[0] + j0 + tid] * sT * sT;
             __syncthreads();
             // z: t1[jj][(i0 i1)][c] = sum_i2 G_z[jj][c][i2] rT[(i0 i1)][i2]
-            for (int it = tid; it < jb * Q2; it += TPB) {
+            for (int it = tid; it < jb * Q2; it += NT) {
                 const int jj = it / Q2, r = it % Q2;
                 double x[Q];
 #pragma unroll
@@ -639,7 +643,7 @@ __global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t 
             }
             __syncthreads();
             // y: t2[jj][i0][b][c] = sum_i1 G_y[jj][b][i1] t1[jj][(i0 i1)][c]
-            for (int it = tid; it < jb * Q2; it += TPB) {
+            for (int it = tid; it < jb * Q2; it += NT) {
                 const int jj = it / Q2, i0 = (it / Q) % Q, c = it % Q;
                 double y[Q];
 #pragma unroll
@@ -679,11 +683,11 @@ __global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t 
     for (int a = 0; a < Q; ++a) t2[(grp * Q + a) * Q2 + bc] = acc[a];
     double *rB = G, *d2 = G + Q3, *l1 = t1, *l2 = t1 + Q3;
     const double *rb = D.rho + (int64_t)vB * Q3;
-    for (int t = tid; t < Q3; t += TPB) rB[t] = rb[t];
-    for (int t = tid; t < Q2; t += TPB) d2[t] = D.d2[t];
+    for (int t = tid; t < Q3; t += NT) rB[t] = rb[t];
+    for (int t = tid; t < Q2; t += NT) d2[t] = D.d2[t];
     __syncthreads();
     const double lsc = 4.0 / (sB * sB);
-    for (int o = tid; o < Q3; o += TPB) {
+    for (int o = tid; o < Q3; o += NT) {
         const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
         double s = 0.0;
         for (int j = 0; j < Q; ++j)
@@ -692,7 +696,7 @@ __global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t 
         l1[o] = s * lsc;
     }
     __syncthreads();
-    for (int o = tid; o < Q3; o += TPB) {
+    for (int o = tid; o < Q3; o += NT) {
         const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
         double s = 0.0;
         for (int j = 0; j < Q; ++j)
@@ -702,7 +706,7 @@ __global__ void __launch_bounds__(TPB) k_vol_near(VDev<double> D, const int32_t 
     }
     __syncthreads();
     const double ta = D.tau_a / sB, ta2 = ta * ta;
-    for (int o = tid; o < Q3; o += TPB) {
+    for (int o = tid; o < Q3; o += NT) {
         double near = 0.0;
 #pragma unroll
         for (int g = 0; g < NG; ++g) near += t2[g * Q3 + o];
@@ -768,7 +772,7 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         VDev<double> D64 = make_vdev<double>(Pl);
         D64.rho = rho;
         const VolData &V = Pl->vol;
-        hipLaunchKernelGGL((k_vol_near<Q>), dim3((unsigned)Pl->nleaf), dim3(TPB), LD::near(), s, D64, Pl->l_leaf,
+        hipLaunchKernelGGL((k_vol_near<Q>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB), LD::near(), s, D64, Pl->l_leaf,
                            Pl->nl_off, Pl->nl_src, V.d_pkey, V.d_kng, V.d_kbase, V.d_gtab, V.d_gw);
     }
     {

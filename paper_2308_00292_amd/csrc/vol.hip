@@ -403,7 +403,10 @@ struct VolLds {
     static size_t up(size_t el) { return el * (2 * P2 + 2 * P * Q + up_work); }
     static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
     static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel)
-    static size_t near() { return sizeof(double) * (Q * Q * (Q + 1) + JB * 3 * Q * Q + JB * Q * Q * (Q + 1) + JB * Q3); }
+    // source rows, then per wave a [q^2][q+1] and a [q^3] buffer; the
+    // epilogue reuses the wave buffers for the partial sums and the
+    // Laplacians (JB q^3 + 3 q^3 + q^2 fits in them)
+    static size_t near() { return sizeof(double) * (Q * Q * (Q + 1) + JB * (Q * Q * (Q + 1) + Q3)); }
 };
 
 // proxy charges of the non-leaf boxes of one level
@@ -575,33 +578,38 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
 
 // Near field of each target leaf: for every source leaf of its gather list
 // that survives the pruning, sum over the class's Gaussians of
-// s_T^2 w_j (G_x (x) G_y (x) G_z) rho_T (three q x q mode products per
-// Gaussian, register-blocked: a thread owns a row of rho or of the
-// intermediate and applies the broadcast 8 x 8 factor); then the asymptotic
-// part from the target's own polynomial.  FP64.
+// s_T^2 w_j (G_x (x) G_y (x) G_z) rho_T, then the asymptotic part from the
+// target's own polynomial.  FP64.
+//
+// One wavefront per Gaussian of a log-t panel (5 waves, the panel's 5 nodes;
+// every class has whole panels).  The wave's three 8 x 8 factors are
+// wave-uniform and read-only, so they come through the scalar cache and feed
+// the FMAs as scalar operands; lane L holds one row of the 8^3 block in each
+// of the three mode products (rows (i0 i1), then (i0 c), then (b c)), with a
+// wave-private LDS buffer for the two regroupings in between.  Block-wide
+// barriers only around the shared source density.
 template <int Q>
 constexpr int vol_near_threads = Q * Q * 5;  // q^2 rows times the Gaussians of one panel
 
 template <int Q>
-__global__ void __launch_bounds__(vol_near_threads<Q>) k_vol_near(VDev<double> D, const int32_t *leaves, const int32_t *nl_off,
-                                                  const int32_t *nl_src, const int32_t *pkey, const int32_t *kng,
-                                                  const int64_t *kbase, const double *gtab, const double *gw)
+__global__ void __launch_bounds__(vol_near_threads<Q>)
+    k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
+               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pkey, const int32_t *__restrict__ kng,
+               const int64_t *__restrict__ kbase, const double *__restrict__ gtab, const double *__restrict__ gw)
 {
-    // one thread per (Gaussian of the pass, row): JB q^2 threads
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, RS = Q + 1, NT = JB * Q2, NG = JB;
-    static_assert(NT == vol_near_threads<Q>, "block size");
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, RS = Q + 1, NT = JB * Q2;
+    static_assert(NT == vol_near_threads<Q> && Q2 == 64, "one wavefront per Gaussian, one lane per row");
     extern __shared__ double vsm[];
     double *rT = vsm;                   // [q^2][RS] source density, rows (i0 i1)
-    double *G = rT + Q2 * RS;           // [3][JB][q][q] factors x, y, z
-    double *t1 = G + 3 * JB * Q2;       // [JB][q^2][RS]
-    double *t2 = t1 + JB * Q2 * RS;     // [JB][q^3]
-    __shared__ double wj[JB];
+    double *wb = rT + Q2 * RS;          // per wave: [q^2][RS] then [q^3]
     const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid / Q2);  // wave = Gaussian of the panel
+    const int L = tid % Q2;
+    double *b1 = wb + w * (Q2 * RS + Q3), *b2 = b1 + Q2 * RS;
     const int64_t li = blockIdx.x;
     const int32_t B = leaves[li];
     const int32_t vB = D.box2v[B];
     const double sB = ldexp(1.0, -D.blevel[B]);
-    const int bc = tid % Q2, grp = tid / Q2;
     double acc[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) acc[a] = 0.0;
@@ -612,76 +620,70 @@ __global__ void __launch_bounds__(vol_near_threads<Q>) k_vol_near(VDev<double> D
         const int32_t T = nl_src[e];
         const double sT = ldexp(1.0, -D.blevel[T]);
         const int ng = kng[kx];
-        const int64_t base[3] = {kbase[kx], kbase[ky], kbase[kz]};
         __syncthreads();
         const double *src = D.rho + (int64_t)D.box2v[T] * Q3;
         for (int t = tid; t < Q3; t += NT) rT[(t / Q) * RS + t % Q] = src[t];
+        __syncthreads();
         for (int j0 = 0; j0 < ng; j0 += JB) {
-            const int jb = min(JB, ng - j0);
-            __syncthreads();
-            for (int t = tid; t < 3 * JB * Q2; t += NT) {
-                const int d = t / (JB * Q2), jj = (t / Q2) % JB, m = t % Q2;
-                if (jj < jb) G[t] = gtab[(base[d] + j0 + jj) * Q2 + m];
+            const int64_t j = j0 + w;
+            const double *gx = gtab + (kbase[kx] + j) * Q2;
+            const double *gy = gtab + (kbase[ky] + j) * Q2;
+            const double *gz = gtab + (kbase[kz] + j) * Q2;
+            const double wj = gw[kbase[kx] + j] * sT * sT;
+            // z: lane (i0 i1): t[c] = sum_i2 G_z[c][i2] rho[(i0 i1)][i2]
+            double x[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) x[k] = rT[L * RS + k];
+#pragma unroll
+            for (int c = 0; c < Q; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k) s += gz[c * Q + k] * x[k];
+                b1[L * RS + c] = s;
             }
-            if (tid < jb) wj[tid] = gw[base[0] + j0 + tid] * sT * sT;
-            __syncthreads();
-            // z: t1[jj][(i0 i1)][c] = sum_i2 G_z[jj][c][i2] rT[(i0 i1)][i2]
-            for (int it = tid; it < jb * Q2; it += NT) {
-                const int jj = it / Q2, r = it % Q2;
-                double x[Q];
-#pragma unroll
-                for (int k = 0; k < Q; ++k) x[k] = rT[r * RS + k];
-                const double *g = G + (2 * JB + jj) * Q2;
-                double *o = t1 + (jj * Q2 + r) * RS;
-#pragma unroll
-                for (int c = 0; c < Q; ++c) {
-                    double s = 0.0;
-#pragma unroll
-                    for (int k = 0; k < Q; ++k) s += g[c * Q + k] * x[k];
-                    o[c] = s;
-                }
-            }
-            __syncthreads();
-            // y: t2[jj][i0][b][c] = sum_i1 G_y[jj][b][i1] t1[jj][(i0 i1)][c]
-            for (int it = tid; it < jb * Q2; it += NT) {
-                const int jj = it / Q2, i0 = (it / Q) % Q, c = it % Q;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // y: lane (i0 c): t2[i0][b][c] = sum_i1 G_y[b][i1] t[(i0 i1)][c]
+            {
+                const int i0 = L / Q, c = L % Q;
                 double y[Q];
 #pragma unroll
-                for (int i1 = 0; i1 < Q; ++i1) y[i1] = t1[(jj * Q2 + i0 * Q + i1) * RS + c];
-                const double *g = G + (JB + jj) * Q2;
-                double *o = t2 + jj * Q3 + i0 * Q2 + c;
+                for (int i1 = 0; i1 < Q; ++i1) y[i1] = b1[(i0 * Q + i1) * RS + c];
 #pragma unroll
-                for (int b = 0; b < Q; ++b) {
+                for (int bb = 0; bb < Q; ++bb) {
                     double s = 0.0;
 #pragma unroll
-                    for (int i1 = 0; i1 < Q; ++i1) s += g[b * Q + i1] * y[i1];
-                    o[b * Q] = s;
+                    for (int i1 = 0; i1 < Q; ++i1) s += gy[bb * Q + i1] * y[i1];
+                    b2[i0 * Q2 + bb * Q + c] = s;
                 }
             }
-            __syncthreads();
-            // x: acc[a] += w_j sum_i0 G_x[jj][a][i0] t2[jj][i0][(b c)]
-            for (int jj = grp; jj < jb; jj += NG) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // x: lane (b c): acc[a] += w_j sum_i0 G_x[a][i0] t2[i0][(b c)]
+            {
                 double z[Q];
 #pragma unroll
-                for (int i0 = 0; i0 < Q; ++i0) z[i0] = t2[jj * Q3 + i0 * Q2 + bc];
-                const double *g = G + jj * Q2;
-                const double w = wj[jj];
+                for (int i0 = 0; i0 < Q; ++i0) z[i0] = b2[i0 * Q2 + L];
 #pragma unroll
                 for (int a = 0; a < Q; ++a) {
                     double s = 0.0;
 #pragma unroll
-                    for (int i0 = 0; i0 < Q; ++i0) s += g[a * Q + i0] * z[i0];
-                    acc[a] += w * s;
+                    for (int i0 = 0; i0 < Q; ++i0) s += gx[a * Q + i0] * z[i0];
+                    acc[a] += wj * s;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    // partial sums of the Gaussian groups, then the asymptotic part:
-    // Gaussians with t >= t_a over R^3 from rho_B's polynomial
+    // sum of the waves' partial sums, then the asymptotic part: Gaussians
+    // with t >= t_a over R^3 from rho_B's polynomial
     __syncthreads();
+    double *part = wb;  // [JB][q^3]
 #pragma unroll
-    for (int a = 0; a < Q; ++a) t2[(grp * Q + a) * Q2 + bc] = acc[a];
-    double *rB = G, *d2 = G + Q3, *l1 = t1, *l2 = t1 + Q3;
+    for (int a = 0; a < Q; ++a) part[w * Q3 + a * Q2 + L] = acc[a];
+    double *rB = part + JB * Q3;  // after the partial sums: [q^3]
+    double *d2 = rB + Q3, *l1 = d2 + Q2, *l2 = l1 + Q3;
     const double *rb = D.rho + (int64_t)vB * Q3;
     for (int t = tid; t < Q3; t += NT) rB[t] = rb[t];
     for (int t = tid; t < Q2; t += NT) d2[t] = D.d2[t];
@@ -690,18 +692,18 @@ __global__ void __launch_bounds__(vol_near_threads<Q>) k_vol_near(VDev<double> D
     for (int o = tid; o < Q3; o += NT) {
         const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
         double s = 0.0;
-        for (int j = 0; j < Q; ++j)
-            s += d2[a * Q + j] * rB[(j * Q + b) * Q + c] + d2[b * Q + j] * rB[(a * Q + j) * Q + c] +
-                 d2[c * Q + j] * rB[(a * Q + b) * Q + j];
+        for (int jx = 0; jx < Q; ++jx)
+            s += d2[a * Q + jx] * rB[(jx * Q + b) * Q + c] + d2[b * Q + jx] * rB[(a * Q + jx) * Q + c] +
+                 d2[c * Q + jx] * rB[(a * Q + b) * Q + jx];
         l1[o] = s * lsc;
     }
     __syncthreads();
     for (int o = tid; o < Q3; o += NT) {
         const int a = o / Q2, b = (o / Q) % Q, c = o % Q;
         double s = 0.0;
-        for (int j = 0; j < Q; ++j)
-            s += d2[a * Q + j] * l1[(j * Q + b) * Q + c] + d2[b * Q + j] * l1[(a * Q + j) * Q + c] +
-                 d2[c * Q + j] * l1[(a * Q + b) * Q + j];
+        for (int jx = 0; jx < Q; ++jx)
+            s += d2[a * Q + jx] * l1[(jx * Q + b) * Q + c] + d2[b * Q + jx] * l1[(a * Q + jx) * Q + c] +
+                 d2[c * Q + jx] * l1[(a * Q + b) * Q + jx];
         l2[o] = s * lsc;
     }
     __syncthreads();
@@ -709,7 +711,7 @@ __global__ void __launch_bounds__(vol_near_threads<Q>) k_vol_near(VDev<double> D
     for (int o = tid; o < Q3; o += NT) {
         double near = 0.0;
 #pragma unroll
-        for (int g = 0; g < NG; ++g) near += t2[g * Q3 + o];
+        for (int g = 0; g < JB; ++g) near += part[g * Q3 + o];
         const double tail =
             2.0 * M_PI * (rB[o] / (2.0 * ta2) + l1[o] / (16.0 * ta2 * ta2) + l2[o] / (192.0 * ta2 * ta2 * ta2));
         D.unear[(int64_t)vB * Q3 + o] = near + tail;

@@ -50,7 +50,8 @@ WORKLOADS = {
     "cfg5_volume_8gauss": "3-D volume potential on [-1/2,1/2]^3 of rho = sum of 8 Gaussians exp(-|x-c|^2/s^2), "
                           "s = exp(U[ln 1e-3, ln 1e-1]), c ~ U[-0.3,0.3]^3; adaptive tree of 8^3 Chebyshev leaves "
                           "(density resolved to 3e-8 of its peak, leaves <= 4 s at each centre), 4.0e7 nodes; "
-                          "Gaussian split, tol 1e-3, FP64",
+                          "Gaussian split, tol 1e-3 (--precision: mixed = FP32 far-field transforms, FP64 "
+                          "near field and sums)",
 }
 METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
 METRIC_VOL = "points/s, 3-D volume potential DMK (box code) at tol 1e-3, 1 GPU"
@@ -156,10 +157,11 @@ def run_volume(args):
     sig, cen, amp = dmk_inputs.vol_gaussians(VOL_SEED)
     f = lambda x: dmk_inputs.gaussian_mixture(x, sig, cen, amp)
     feat = dmk_inputs.gaussian_features(sig, cen)
-    log("[bench] volume plan")
+    prec = dmk.DMK_FP64 if args.precision == "fp64" else dmk.DMK_MIXED
+    log(f"[bench] volume plan ({args.precision})")
     t0 = time.perf_counter()
     plan = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
-                       features=feat)
+                       features=feat, precision=prec)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     n = plan.n
@@ -197,7 +199,8 @@ def run_volume(args):
     hbm = STAGE_BOUND[dom] == "hbm"
     per_launch = (byts[dom] if hbm else flops[dom]) * nst / max(1, launches[dom])
     achieved = per_launch / (avg_ms * 1e-3) / (1e9 if hbm else 1e12)
-    peak, unit = PEAK["hbm"] if hbm else PEAK["alu64"]
+    peak, unit = PEAK["hbm"] if hbm else (PEAK["alu64"] if (dom == "residual" or prec == dmk.DMK_FP64)
+                                          else PEAK["alu32"])
     roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": None, "kernel": STAGE_KERNEL_VOL.get(dom, dom), "stage": dom, "avg_launch_ms": avg_ms,
             "launches_per_step": launches[dom] / nst}
@@ -218,6 +221,26 @@ def run_volume(args):
     err = float(np.linalg.norm(u[idx] - ex) / np.linalg.norm(ex))
     log(f"[bench] sampled rel l2 vs closed form ({len(idx)} nodes): {err:.3e}")
     plan.close()
+    fp64 = None
+    if not args.no_compare and prec != dmk.DMK_FP64:
+        p64 = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
+                          features=feat, precision=dmk.DMK_FP64)
+        out64 = torch.empty_like(rho)
+        for _ in range(args.warmup):
+            p64.eval(rho, out64)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            p64.eval(rho, out64)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = ev0.elapsed_time(ev1) / args.steps
+        u64 = out64.cpu().numpy()
+        p64.close()
+        fp64 = {"points_per_s": n / (ms64 * 1e-3), "ms_per_step": ms64,
+                "sampled_rel_l2_vs_closed_form": float(np.linalg.norm(u64[idx] - ex) / np.linalg.norm(ex)),
+                "rel_l2_vs_main": float(np.linalg.norm(u - u64) / np.linalg.norm(u64))}
+        log(f"[bench] FP64 volume {ms64:.3f} ms/step -> {fp64['points_per_s']:.4g} points/s")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (volume oracle)")
@@ -226,8 +249,9 @@ def run_volume(args):
     res = {
         "metric": METRIC_VOL, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "strong",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if prec == dmk.DMK_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": WORKLOADS["cfg5_volume_8gauss"], "name": "cfg5_volume_8gauss", "n_points": n,
+                   "precision": args.precision, "fp64": fp64,
                    "leaves": plan.nleaf, "levels": np.bincount(lev).tolist(), "q": 8, "p": 18, "nf": 12, "tol": 1e-3,
                    "t_plan_s": round(t_plan, 3), "sampled_rel_l2_vs_closed_form": err, "stage_ms_per_step": stages},
         "roofline": roof,

@@ -266,13 +266,13 @@ class VolPlan:
     [npoints]) to potentials at the same nodes."""
 
     def __init__(self, density, tol=1e-3, q=8, rho_scale=1.0, min_level=1, max_level=12, features=None,
-                 stream=None):
+                 precision=DMK_FP64, stream=None):
         def cb(n, xyz, out, ctx):
             x = np.ctypeslib.as_array(xyz, shape=(n * 3,)).reshape(n, 3)
             o = np.ctypeslib.as_array(out, shape=(n,))
             o[:] = density(x)
         self._cb = DENSITY_FN(cb)
-        o = Opts(0, 0, DMK_FP64, 0, 0, 0.0)
+        o = Opts(0, 0, precision, 0, 0, 0.0)
         h = C.c_void_p()
         feat = np.ascontiguousarray(np.zeros((0, 4)) if features is None else features, dtype=np.float64)
         _check(lib().dmk_vol_plan(float(tol), int(q), float(rho_scale), int(min_level), int(max_level), len(feat),

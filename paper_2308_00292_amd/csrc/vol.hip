@@ -927,7 +927,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
     dmk_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    if (o.precision != DMK_FP64) throw Error{DMK_ERR_UNSUPPORTED, "volume plans run in FP64"};
+    if (o.precision != DMK_FP64 && o.precision != DMK_MIXED) throw Error{DMK_ERR_ARG, "unknown precision"};
     std::vector<Cell> tree = build_vol_tree(q, tol, rho_scale, min_level, max_level, nfeat, feat, density, ctx);
     const int q3 = q * q * q;
     const int64_t nleaf = (int64_t)tree.size();
@@ -947,7 +947,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         P->poff = {0, n};
         P->pbits = 0;
         P->kb = 21;
-        P->precision = DMK_FP64;
+        P->precision = o.precision;
         P->leaf_max = q3;
         P->max_depth = 20;
         P->flags = 0;
@@ -1074,7 +1074,10 @@ void vol_nodes(Plan *P, double *xyz, hipStream_t s)
 void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, double *near_part, hipStream_t s)
 {
     if (P->vol.q != VQ || P->p != 18) throw Error{DMK_ERR_STATE, "volume plan with unexpected grid sizes"};
-    run_vol_t<double, 18, VQ>(P, rho, u, far_part, near_part, s);
+    if (P->precision == DMK_FP64)
+        run_vol_t<double, 18, VQ>(P, rho, u, far_part, near_part, s);
+    else
+        run_vol_t<float, 18, VQ>(P, rho, u, far_part, near_part, s);
 }
 
 // Algorithmic work of one volume eval (FP64): flops of the separable
@@ -1088,7 +1091,7 @@ void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, doubl
 void vol_stage_work(const Plan *P, double *F, double *Bt)
 {
     const Tables &t = P->tab;
-    const double el = 8.0, p = t.p, n = t.nn, nh = t.nh, q = P->vol.q;
+    const double el = (P->precision == DMK_FP64) ? 8.0 : 4.0, p = t.p, n = t.nn, nh = t.nh, q = P->vol.q;
     const double p3 = p * p * p, p4 = p3 * p, q3 = q * q * q, q4 = q3 * q;
     const double NL = (double)P->vol.nleaf, N = (double)P->n;
     for (int i = 0; i < DMK_NSTAGES; ++i) F[i] = Bt[i] = 0.0;

@@ -73,9 +73,9 @@ def test_argument_errors_without_device():
     assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 1, None, cb, None, None, None, C.byref(h)) == -1  # NULL features
     assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 1, bad.ctypes.data_as(C.c_void_p), cb, None, None, None,
                           C.byref(h)) == -1  # h <= 0
-    om = dmk.Opts(0, 0, dmk.DMK_MIXED, 0, 0, 0.0)
+    om = dmk.Opts(0, 0, 7, 0, 0, 0.0)
     assert L.dmk_vol_plan(1e-3, 8, 1.0, 1, 4, 1, ok.ctypes.data_as(C.c_void_p), cb, None, C.byref(om), None,
-                          C.byref(h)) == -2  # precision
+                          C.byref(h)) == -1  # unknown precision
     assert calls == [] and h.value is None
     assert L.dmk_vol_info(None, None, None) == -1
     assert L.dmk_vol_leaves(None, None, None) == -1

@@ -35,8 +35,14 @@ CASES = {
 
 @pytest.fixture(scope="module", params=list(CASES))
 def case(request, oracle_mod):
+    yield from _case(request.param, oracle_mod, fp64=True)
+
+
+_ORACLE = {}  # oracle results per case, shared by the FP64 and mixed fixtures
+
+
+def _case(name, oracle_mod, fp64):
     import paper_2308_00292_amd as dmk
-    name = request.param
     kw, rs, lo, hi, feat = CASES[name]
     sig, cen, amp = np.array(kw["sig"]), np.array(kw["cen"]), np.array(kw["amp"])
     f = lambda x: dmk_inputs.gaussian_mixture(x, sig, cen, amp)
@@ -44,12 +50,15 @@ def case(request, oracle_mod):
     vp = oracle_mod.vparams_for(1e-3, 8)
     T = oracle_mod.VTree(vp, f, rs, lo, hi, features=features)
     _say(f"[vol {name}] oracle tree {T.nleaf} leaves; plan")
-    plan = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=rs, min_level=lo, max_level=hi, features=features)
+    plan = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=rs, min_level=lo, max_level=hi, features=features,
+                       precision=dmk.DMK_FP64 if fp64 else dmk.DMK_MIXED)
     torch.cuda.synchronize()
     xyz_o = T.nodes()
     rho = f(xyz_o)
-    _say(f"[vol {name}] oracle eval")
-    ref = T.eval(rho)
+    if name not in _ORACLE:
+        _say(f"[vol {name}] oracle eval")
+        _ORACLE[name] = T.eval(rho)
+    ref = _ORACLE[name]
     yield name, T, plan, xyz_o, rho, ref
     plan.close()
 
@@ -86,6 +95,26 @@ def test_potential_and_parts(case):
     u3 = plan.eval(r).cpu().numpy()
     assert np.array_equal(u2, u3)
     assert np.allclose(u2, u, rtol=0, atol=1e-15 * np.max(np.abs(u)))
+
+
+@pytest.fixture(scope="module", params=["adaptive", "two_gauss_feat"])
+def case_mixed(request, oracle_mod):
+    yield from _case(request.param, oracle_mod, fp64=False)
+
+
+def test_mixed_precision(case_mixed):
+    """Far-field transforms in FP32 (near field and sums FP64): 1e-5 of the
+    FP64 oracle, the point code's mixed bar."""
+    name, T, plan, xyz_o, rho, ref = case_mixed
+    lev, ijk = plan.leaves()
+    assert np.array_equal(lev, T.level) and np.array_equal(ijk, T.ijk)
+    u, far, near = plan.eval(torch.from_numpy(rho).cuda(), parts=True)
+    u, far, near = u.cpu().numpy(), far.cpu().numpy(), near.cpu().numpy()
+    nu = np.linalg.norm(ref["u"])
+    _say(f"[vol mixed {name}] rel l2 u {np.linalg.norm(u - ref['u']) / nu:.3e} far "
+         f"{np.linalg.norm(far - ref['ufar']) / nu:.3e}")
+    assert np.linalg.norm(u - ref["u"]) < 1e-5 * nu
+    assert np.linalg.norm(near - ref["unear"] - ref["utail"]) < 1e-10 * nu
 
 
 def test_api_misuse(oracle_mod):

@@ -403,10 +403,14 @@ struct VolLds {
     static size_t up(size_t el) { return el * (2 * P2 + 2 * P * Q + up_work); }
     static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
     static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel)
-    // source rows, then per wave a [q^2][q+1] and a [q^3] buffer; the
-    // epilogue reuses the wave buffers for the partial sums and the
-    // Laplacians (JB q^3 + 3 q^3 + q^2 fits in them)
-    static size_t near() { return sizeof(double) * (Q * Q * (Q + 1) + JB * (Q * Q * (Q + 1) + Q3)); }
+    static constexpr int NB = 6;  // source densities staged per batch
+    // NB source blocks, then a [q^2][q+1] regrouping buffer per wave; the
+    // epilogue reuses them for the partial sums and the Laplacians
+    static size_t near()
+    {
+        const size_t main = NB * Q3 + JB * Q * Q * (Q + 1), epi = JB * Q3 + 3 * Q3 + Q * Q;
+        return sizeof(double) * (main > epi ? main : epi);
+    }
 };
 
 // proxy charges of the non-leaf boxes of one level
@@ -576,114 +580,145 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
     if (a == 0) gw[g] = 2.0 / sqrt(M_PI) * tj * 0.5 * hp * tglw[gi];
 }
 
-// Near field of each target leaf: for every source leaf of its gather list
+// Near field of each target leaf: for every source leaf T of its gather list
 // that survives the pruning, sum over the class's Gaussians of
 // s_T^2 w_j (G_x (x) G_y (x) G_z) rho_T, then the asymptotic part from the
 // target's own polynomial.  FP64.
 //
 // One wavefront per Gaussian of a log-t panel (5 waves, the panel's 5 nodes;
-// every class has whole panels).  The wave's three 8 x 8 factors are
-// wave-uniform and read-only, so they come through the scalar cache and feed
-// the FMAs as scalar operands; lane L holds one row of the 8^3 block in each
-// of the three mode products (rows (i0 i1), then (i0 c), then (b c)), with a
-// wave-private LDS buffer for the two regroupings in between.  Block-wide
-// barriers only around the shared source density.
+// every class has whole panels).  The 8 x 8 factors are wave-uniform and
+// read-only, so they come through the scalar cache and feed the FMAs as
+// scalar operands.  The entries of a gather list arrive sorted by (z class,
+// y class, x class): x passes are summed over the sources of a (y, z) group,
+// y passes over the groups of a z class, and one z pass closes each z
+// class (27 + 9 + 3 passes per Gaussian for the 27 colleagues of a uniform
+// region instead of 81).  Lane L holds one row of the 8^3 block in each pass
+// (rows (i1 i2), then (a i2), then (a b)); a wave-private LDS buffer
+// regroups between passes.  The sources' densities are staged in LDS in
+// batches of NB.
 template <int Q>
 constexpr int vol_near_threads = Q * Q * 5;  // q^2 rows times the Gaussians of one panel
 
 template <int Q>
 __global__ void __launch_bounds__(vol_near_threads<Q>)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
-               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pkey, const int32_t *__restrict__ kng,
+               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pk, const int32_t *__restrict__ kng,
                const int64_t *__restrict__ kbase, const double *__restrict__ gtab, const double *__restrict__ gw)
 {
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, RS = Q + 1, NT = JB * Q2;
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NB = VolLds<18, Q>::NB, RS = Q + 1,
+                  NT = JB * Q2;
     static_assert(NT == vol_near_threads<Q> && Q2 == 64, "one wavefront per Gaussian, one lane per row");
     extern __shared__ double vsm[];
-    double *rT = vsm;                   // [q^2][RS] source density, rows (i0 i1)
-    double *wb = rT + Q2 * RS;          // per wave: [q^2][RS] then [q^3]
+    double *slot = vsm;                 // [NB][q^3] source densities
+    double *wb = slot + NB * Q3;        // per wave: [q^2][RS] regrouping buffer
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / Q2);  // wave = Gaussian of the panel
     const int L = tid % Q2;
-    double *b1 = wb + w * (Q2 * RS + Q3), *b2 = b1 + Q2 * RS;
+    double *buf = wb + w * Q2 * RS;
     const int64_t li = blockIdx.x;
     const int32_t B = leaves[li];
     const int32_t vB = D.box2v[B];
     const double sB = ldexp(1.0, -D.blevel[B]);
-    double acc[Q];
+    double acc[Q];  // lane (a b): acc[c]
 #pragma unroll
-    for (int a = 0; a < Q; ++a) acc[a] = 0.0;
-    for (int e = nl_off[li]; e < nl_off[li + 1]; ++e) {
-        const int32_t kx = pkey[3 * (int64_t)e];
-        if (kx < 0) continue;  // pruned: every Gaussian is below eps there
-        const int32_t ky = pkey[3 * (int64_t)e + 1], kz = pkey[3 * (int64_t)e + 2];
-        const int32_t T = nl_src[e];
-        const double sT = ldexp(1.0, -D.blevel[T]);
-        const int ng = kng[kx];
-        __syncthreads();
-        const double *src = D.rho + (int64_t)D.box2v[T] * Q3;
-        for (int t = tid; t < Q3; t += NT) rT[(t / Q) * RS + t % Q] = src[t];
-        __syncthreads();
+    for (int c = 0; c < Q; ++c) acc[c] = 0.0;
+    const int eend = nl_off[li + 1];
+    for (int e = nl_off[li]; e < eend;) {
+        if (pk[4 * (int64_t)e] < 0) break;  // pruned entries come last
+        int ez = e;
+        for (;;) {  // end of this z class
+            const int fl = pk[4 * (int64_t)ez + 3];
+            ++ez;
+            if (fl & 2) break;
+        }
+        const int32_t kx0 = pk[4 * (int64_t)e], kzc = pk[4 * (int64_t)e + 2];
+        const double sT = ldexp(1.0, -D.blevel[nl_src[e]]);
+        const int ng = kng[kx0];
         for (int j0 = 0; j0 < ng; j0 += JB) {
             const int64_t j = j0 + w;
-            const double *gx = gtab + (kbase[kx] + j) * Q2;
-            const double *gy = gtab + (kbase[ky] + j) * Q2;
-            const double *gz = gtab + (kbase[kz] + j) * Q2;
-            const double wj = gw[kbase[kx] + j] * sT * sT;
-            // z: lane (i0 i1): t[c] = sum_i2 G_z[c][i2] rho[(i0 i1)][i2]
-            double x[Q];
+            const double wj = gw[kbase[kx0] + j] * sT * sT;
+            double xa[Q], ya[Q];  // lane (i1 i2): xa[a]; lane (a i2): ya[b]
 #pragma unroll
-            for (int k = 0; k < Q; ++k) x[k] = rT[L * RS + k];
+            for (int k = 0; k < Q; ++k) xa[k] = ya[k] = 0.0;
+            for (int b0 = e; b0 < ez; b0 += NB) {
+                const int nb = min(NB, ez - b0);
+                __syncthreads();
+                for (int t = tid; t < nb * Q3; t += NT) {
+                    const int sidx = t / Q3;
+                    slot[t] = D.rho[(int64_t)D.box2v[nl_src[b0 + sidx]] * Q3 + t % Q3];
+                }
+                __syncthreads();
+                for (int sidx = 0; sidx < nb; ++sidx) {
+                    const int64_t es = b0 + sidx;
+                    // x: xa[a] += sum_i0 G_x[a][i0] rho[i0][(i1 i2)]
+                    const double *gx = gtab + (kbase[pk[4 * es]] + j) * Q2;
+                    const double *rs = slot + sidx * Q3;
+                    double r[Q];
 #pragma unroll
-            for (int c = 0; c < Q; ++c) {
-                double s = 0.0;
+                    for (int i0 = 0; i0 < Q; ++i0) r[i0] = rs[i0 * Q2 + L];
 #pragma unroll
-                for (int k = 0; k < Q; ++k) s += gz[c * Q + k] * x[k];
-                b1[L * RS + c] = s;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            // y: lane (i0 c): t2[i0][b][c] = sum_i1 G_y[b][i1] t[(i0 i1)][c]
-            {
-                const int i0 = L / Q, c = L % Q;
-                double y[Q];
+                    for (int a = 0; a < Q; ++a) {
+                        double s = 0.0;
 #pragma unroll
-                for (int i1 = 0; i1 < Q; ++i1) y[i1] = b1[(i0 * Q + i1) * RS + c];
+                        for (int i0 = 0; i0 < Q; ++i0) s += gx[a * Q + i0] * r[i0];
+                        xa[a] += s;
+                    }
+                    if (pk[4 * es + 3] & 1) {
+                        // end of a (y, z) group: ya[b] += sum_i1 G_y[b][i1] X[a][i1][i2]
+                        const double *gy = gtab + (kbase[pk[4 * es + 1]] + j) * Q2;
 #pragma unroll
-                for (int bb = 0; bb < Q; ++bb) {
-                    double s = 0.0;
+                        for (int a = 0; a < Q; ++a) buf[L * RS + a] = xa[a];
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        const int a = L / Q, i2 = L % Q;
+                        double y[Q];
 #pragma unroll
-                    for (int i1 = 0; i1 < Q; ++i1) s += gy[bb * Q + i1] * y[i1];
-                    b2[i0 * Q2 + bb * Q + c] = s;
+                        for (int i1 = 0; i1 < Q; ++i1) y[i1] = buf[(i1 * Q + i2) * RS + a];
+#pragma unroll
+                        for (int bb = 0; bb < Q; ++bb) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int i1 = 0; i1 < Q; ++i1) s += gy[bb * Q + i1] * y[i1];
+                            ya[bb] += s;
+                        }
+#pragma unroll
+                        for (int k = 0; k < Q; ++k) xa[k] = 0.0;
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                    }
                 }
             }
+            // end of the z class: acc[c] += w_j sum_i2 G_z[c][i2] Y[a][b][i2]
+            const double *gz = gtab + (kbase[kzc] + j) * Q2;
+#pragma unroll
+            for (int bb = 0; bb < Q; ++bb) buf[L * RS + bb] = ya[bb];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // x: lane (b c): acc[a] += w_j sum_i0 G_x[a][i0] t2[i0][(b c)]
             {
-                double z[Q];
+                const int a = L / Q, bb = L % Q;
+                double y[Q];
 #pragma unroll
-                for (int i0 = 0; i0 < Q; ++i0) z[i0] = b2[i0 * Q2 + L];
+                for (int i2 = 0; i2 < Q; ++i2) y[i2] = buf[(a * Q + i2) * RS + bb];
 #pragma unroll
-                for (int a = 0; a < Q; ++a) {
+                for (int c = 0; c < Q; ++c) {
                     double s = 0.0;
 #pragma unroll
-                    for (int i0 = 0; i0 < Q; ++i0) s += gx[a * Q + i0] * z[i0];
-                    acc[a] += wj * s;
+                    for (int i2 = 0; i2 < Q; ++i2) s += gz[c * Q + i2] * y[i2];
+                    acc[c] += wj * s;
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
+        e = ez;
     }
     // sum of the waves' partial sums, then the asymptotic part: Gaussians
     // with t >= t_a over R^3 from rho_B's polynomial
     __syncthreads();
-    double *part = wb;  // [JB][q^3]
+    double *part = vsm;  // [JB][q^3]
 #pragma unroll
-    for (int a = 0; a < Q; ++a) part[w * Q3 + a * Q2 + L] = acc[a];
-    double *rB = part + JB * Q3;  // after the partial sums: [q^3]
-    double *d2 = rB + Q3, *l1 = d2 + Q2, *l2 = l1 + Q3;
+    for (int c = 0; c < Q; ++c) part[w * Q3 + L * Q + c] = acc[c];
+    double *rB = part + JB * Q3, *d2 = rB + Q3, *l1 = d2 + Q2, *l2 = l1 + Q3;
     const double *rb = D.rho + (int64_t)vB * Q3;
     for (int t = tid; t < Q3; t += NT) rB[t] = rb[t];
     for (int t = tid; t < Q2; t += NT) d2[t] = D.d2[t];
@@ -867,6 +902,47 @@ void vol_count_work(Plan *P, hipStream_t s)
             V.n_gauss += (int64_t)vol_npan(V, k) * V.tpan_gl;
         }
     }
+    // order every target's entries by (z class, y class, x class), pruned
+    // entries last, and mark the last entry of each (y, z) group and of each
+    // z group: the near-field kernel sums x passes over a (y, z) group and
+    // y passes over a z group before applying the next factor
+    std::vector<int32_t> pk4((size_t)std::max<int64_t>(ne, 1) * 4, -1);
+    {
+        std::vector<int32_t> ord;
+        for (int64_t i = 0; i < nl; ++i) {
+            ord.clear();
+            for (int32_t e = off[i]; e < off[i + 1]; ++e) ord.push_back(e);
+            std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+                const int32_t *A = &pkey[3 * (size_t)a], *B = &pkey[3 * (size_t)b];
+                const bool pa = A[0] < 0, pb = B[0] < 0;
+                if (pa != pb) return pb;  // kept entries first
+                if (pa) return false;
+                if (A[2] != B[2]) return A[2] < B[2];
+                if (A[1] != B[1]) return A[1] < B[1];
+                return A[0] < B[0];
+            });
+            std::vector<int32_t> s2(ord.size());
+            for (size_t r = 0; r < ord.size(); ++r) {
+                const int32_t e = ord[r], d = off[i] + (int32_t)r;
+                s2[r] = src[e];
+                for (int k = 0; k < 3; ++k) pk4[4 * (size_t)d + k] = pkey[3 * (size_t)e + k];
+            }
+            for (size_t r = 0; r < ord.size(); ++r) {
+                const int32_t d = off[i] + (int32_t)r;
+                int32_t *K = &pk4[4 * (size_t)d];
+                if (K[0] < 0) { K[3] = 0; continue; }
+                const bool last = (r + 1 == ord.size()) || pk4[4 * (size_t)(d + 1)] < 0;
+                const int32_t *N = last ? nullptr : &pk4[4 * (size_t)(d + 1)];
+                const bool lz = last || N[2] != K[2];
+                const bool ly = lz || N[1] != K[1];
+                K[3] = (ly ? 1 : 0) | (lz ? 2 : 0);
+            }
+            for (size_t r = 0; r < ord.size(); ++r) src[off[i] + r] = s2[r];
+        }
+        if (ne > 0)
+            DMK_HIP(hipMemcpy(P->nl_src, src.data(), (size_t)ne * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    pkey.swap(pk4);
     // classes -> tables on the device
     const int64_t nk = (int64_t)ck.size();
     std::vector<int32_t> kng(std::max<int64_t>(nk, 1), 0), kk(std::max<int64_t>(nk, 1), 0);

@@ -786,6 +786,86 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
     }
 }
 
+// ------------------------------------ outgoing plane waves on matrix cores
+// FP32 path of proxy -> plane waves (eq. outgoingexpansion2) on MFMA, the
+// mode products of k_proxy2pw in the fragment scheme of the local stage:
+//   j3 -> m3  A[(j1 j2)][m3 | NH + m3] = sum_j3 rho[(j1 j2)][j3] (Re | Im) E[m3][j3]
+//   j2 -> m2  B2[(j1 mm)][m2] = sum_j2 A[(j1 j2)][m3] E[m2][j2]   (complex)
+//   j1 -> m1  Phi[m1][(mm m2)] = sum_j1 E[m1][j1] B2[(j1 mm)][m2] (complex)
+// the last two for G values of m3 at a time; each group's Phi rows are
+// staged in LDS and written to HBM as contiguous runs of G * nn values.
+template <int P, int NF>
+struct P2pwMfma {
+    static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1, NM = NH * NN, W1 = 2 * NH;
+    static constexpr int G = 4;
+    static constexpr int R0 = (P3 > 2 * P * G * NN + 2 * NN * G * NN) ? P3 : 2 * P * G * NN + 2 * NN * G * NN;
+    static constexpr int TAB = P * W1 + 2 * P * NN;
+    static size_t lds() { return sizeof(float) * (TAB + R0 + P2 * W1); }
+};
+
+template <int P, int NF>
+__global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const int32_t *list)
+{
+    using L = P2pwMfma<P, NF>;
+    constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, W1 = L::W1, G = L::G;
+    extern __shared__ unsigned char smraw[];
+    float *sm = reinterpret_cast<float *>(smraw);
+    float *B1 = sm;                    // [j3][W1]: Re E[m3][j3] | Im E[m3][j3]
+    float *BrT = B1 + P * W1;          // [j][m]: Re E[m][j]
+    float *BiT = BrT + P * NN;         //         Im E[m][j]
+    float *r0 = BiT + P * NN;          // rho, then B2 and the staged Phi rows
+    float *A = r0 + L::R0;             // [(j1 j2)][W1]
+    float *B2r = r0, *B2i = B2r + P * G * NN;       // [(j1 mm)][m2]
+    float *Fr = B2i + P * G * NN, *Fi = Fr + NN * G * NN;  // [m1][(mm m2)]
+    const int32_t B = list[blockIdx.x];
+    for (int t = threadIdx.x; t < P * W1; t += TPB) {
+        const int j = t / W1, a = t % W1, m3 = (a < NH) ? a : a - NH;
+        B1[t] = D.epw[2 * ((m3 + NF) * P + j) + (a < NH ? 0 : 1)];
+    }
+    for (int t = threadIdx.x; t < P * NN; t += TPB) {
+        const int j = t / NN, m = t % NN;
+        BrT[t] = D.epw[2 * (m * P + j)];
+        BiT[t] = D.epw[2 * (m * P + j) + 1];
+    }
+    const float *src = D.proxy + (int64_t)D.proxy_slot[B] * P3;
+    for (int t = threadIdx.x; t < P3; t += TPB) r0[t] = src[t];
+    __syncthreads();
+    // j3 -> m3 (real rho times the real and imaginary rows)
+    mma_real_store<W1, P2, P, (W1 + 15) / 16>([&](int x, int k) { return r0[x * P + k]; }, B1,
+                                              [&](int x, int a, float v) { A[x * W1 + a] = v; });
+    const int64_t nm = D.pwstride;
+    float *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
+    float *outi = outr + nm;
+    for (int g0 = 0; g0 < NH; g0 += G) {
+        const int g = min(G, NH - g0);
+        __syncthreads();
+        // j2 -> m2: rows x = (j1, mm)
+        mma_cplx_store<NN, P * G, P, (NN + 15) / 16>(
+            [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
+            [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
+            BrT, BiT, [&](int x, int a, float vr, float vi) {
+                B2r[x * NN + a] = vr;
+                B2i[x * NN + a] = vi;
+            });
+        __syncthreads();
+        // j1 -> m1: rows x = (mm, m2)
+        mma_cplx_store<NN, G * NN, P, (NN + 15) / 16>(
+            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(k * G + mm) * NN + m2] : 0.f; },
+            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(k * G + mm) * NN + m2] : 0.f; },
+            BrT, BiT, [&](int x, int a, float vr, float vi) {
+                Fr[a * G * NN + x] = vr;
+                Fi[a * G * NN + x] = vi;
+            });
+        __syncthreads();
+        // the group's rows of Phi[m1][m3][m2]: runs of g * nn values per m1
+        for (int t = threadIdx.x; t < NN * g * NN; t += TPB) {
+            const int m1 = t / (g * NN), r = t % (g * NN);
+            outr[(int64_t)m1 * NM + g0 * NN + r] = Fr[m1 * G * NN + r];
+            outi[(int64_t)m1 * NM + g0 * NN + r] = Fi[m1 * G * NN + r];
+        }
+    }
+}
+
 // ------------------------------------------------------------ leaf targets
 // Lagrange basis of the nodes at xi with one division (prefix products of
 // the differences, Montgomery's batch inversion), barycentric weights bw.
@@ -1261,7 +1341,10 @@ static void set_lds_attrs()
     allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
     allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
     const size_t lds_mfma = LocalMfma<P, NF>::lds();
-    if constexpr (sizeof(T) == 4) allow_lds(k_local_mfma<P, NF>, lds_mfma);
+    if constexpr (sizeof(T) == 4) {
+        allow_lds(k_local_mfma<P, NF>, lds_mfma);
+        allow_lds(k_proxy2pw_mfma<P, NF>, P2pwMfma<P, NF>::lds());
+    }
     allow_lds(k_leaf<T, P>, C::lds_leaf());
     attrs = true;
 }
@@ -1291,8 +1374,13 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     // waves of every non-empty F_in box, all levels in one launch each
     if (Pl->nfout) {
         StageScope t(Pl, s, DMK_STAGE_PROXY2PW);
-        hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
-                           Pl->l_fout);
+        const size_t lds_p2pw_mfma = P2pwMfma<P, NF>::lds();
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_proxy2pw_mfma<P, NF>), dim3((unsigned)Pl->nfout), dim3(TPB), lds_p2pw_mfma, s, D,
+                               Pl->l_fout);
+        else
+            hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
+                               Pl->l_fout);
     }
     if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);

@@ -954,22 +954,25 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
 // the per-pass partial sums are added into an FP64 accumulator.
 constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
 
-template <typename T>
+// DEG: compile-time degree bucket of the Clenshaw sum (coefficients above
+// the plan's degree are zero, which leaves the recurrence's result unchanged);
+// the coefficients live in registers.
+template <typename T, int DEG>
 __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
                                                   const int32_t *nl_src, const int32_t *nl_pre)
 {
     constexpr int RCAP = sizeof(T) == 8 ? 512 : 1024;  // sources staged per pass
     __shared__ T sx[RCAP], sy[RCAP], sz[RCAP], sq[RCAP], sis[RCAP], sis2[RCAP];
     __shared__ int32_t loff[RLIST + 1];
-    __shared__ T gc[48];
     __shared__ double part[TPB];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.pstart[B];
     const int nt = D.pcount[B];
     const int32_t l0 = nl_off[blockIdx.x];
     const int L = nl_off[blockIdx.x + 1] - l0;
-    const int deg = D.gdeg;
-    for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
+    T gc[DEG + 1];
+#pragma unroll
+    for (int k = 0; k <= DEG; ++k) gc[k] = (k <= D.gdeg) ? D.gcheb[k] : T(0);
     // running source counts over the list (computed at plan time)
     for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
     __syncthreads();
@@ -1014,9 +1017,11 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                 if (tt < T(1)) {
                     // Clenshaw for g(t) = Phi(sqrt t)/sqrt t
                     const T u = T(2) * tt - T(1);
+                    const T u2 = T(2) * u;
                     T b1 = T(0), b2 = T(0);
-                    for (int k = deg; k >= 1; --k) {
-                        T b0 = gc[k] + T(2) * u * b1 - b2;
+#pragma unroll
+                    for (int k = DEG; k >= 1; --k) {
+                        T b0 = gc[k] + u2 * b1 - b2;
                         b2 = b1;
                         b1 = b0;
                     }
@@ -1330,6 +1335,21 @@ void allow_lds(K kernel, size_t bytes)
 
 }  // namespace
 
+// residual sums with the Clenshaw degree rounded up to a compiled bucket
+template <typename T>
+static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
+{
+    const dim3 g((unsigned)Pl->nleaf), b(TPB);
+    if (D.gdeg <= 11)
+        hipLaunchKernelGGL((k_residual<T, 11>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 15)
+        hipLaunchKernelGGL((k_residual<T, 15>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 23)
+        hipLaunchKernelGGL((k_residual<T, 23>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else
+        hipLaunchKernelGGL((k_residual<T, 47>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+}
+
 // dynamic LDS limits of the stage kernels, once per process
 template <typename T, int P, int NF>
 static void set_lds_attrs()
@@ -1420,8 +1440,7 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
     if (side && Pl->nleaf) {
         DMK_HIP(hipEventRecord(Pl->ev_fork, s));
         DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
-        hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, side, D, Pl->l_leaf, Pl->nl_off,
-                           Pl->nl_src, Pl->nl_pre);
+        launch_residual<T>(D, Pl, side);
         DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
     // Step 2: upward pass, finest level first
@@ -1446,8 +1465,7 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
             DMK_HIP(hipStreamWaitEvent(s, Pl->ev_join, 0));
         } else {
             StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
-            hipLaunchKernelGGL((k_residual<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf, Pl->nl_off,
-                               Pl->nl_src, Pl->nl_pre);
+            launch_residual<T>(D, Pl, s);
         }
     }
 }

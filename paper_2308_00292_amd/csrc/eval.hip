@@ -954,6 +954,11 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
 // the per-pass partial sums are added into an FP64 accumulator.
 constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
 
+// 1/sqrt in the working precision (the float overload is the hardware
+// reciprocal square root, about 1 ulp)
+__device__ inline float rsq(float x) { return rsqrtf(x); }
+__device__ inline double rsq(double x) { return rsqrt(x); }
+
 // DEG: compile-time degree bucket of the Clenshaw sum (coefficients above
 // the plan's degree are zero, which leaves the recurrence's result unchanged);
 // the coefficients live in registers.
@@ -980,7 +985,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     const double cx = D.bcenter[3 * (int64_t)B], cy = D.bcenter[3 * (int64_t)B + 1], cz = D.bcenter[3 * (int64_t)B + 2];
     // one thread per target and source share; a leaf of nt <= 64 targets uses
     // TPB/nt shares so that few threads idle
-    const int tch = nt < 64 ? max(nt, 1) : 64;
+    const int tch = min(max(nt, 1), 64);
     const int nsplit = TPB / tch;
     const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
     for (int tbase = 0; tbase < nt; tbase += tch) {
@@ -1026,7 +1031,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                         b1 = b0;
                     }
                     const T g = gc[0] + u * b1 - b2;
-                    const T rinv = (r2 > T(0)) ? rsqrt(r2) : T(0);
+                    const T rinv = (r2 > T(0)) ? rsq(r2) : T(0);
                     pacc += sq[j] * (rinv - g * sis[j]);
                 }
             }

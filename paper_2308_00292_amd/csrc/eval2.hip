@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
     const T k4pi = (T)(-1.0 / (4.0 * M_PI));
     // one thread per target and source share; a leaf of nt <= 64 targets uses
     // TPB/nt shares so that few threads idle
-    const int tch = nt < 64 ? max(nt, 1) : 64;
+    const int tch = min(max(nt, 1), 64);
     const int nsplit = TPB / tch;
     const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
     for (int tbase = 0; tbase < nt; tbase += tch) {

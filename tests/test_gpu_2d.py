@@ -61,6 +61,8 @@ SINGLE = {
     "square_4k": lambda: (*dmk_inputs.uniform_square(4000, 201), 40),
     "gauss_5k": lambda: (*dmk_inputs.gaussian_2d(5000, 202), 30),
     "mixture_20k": lambda: (*_mixture(20000, 203), 60),
+    # leaves of 65..120 points: the kernels' loops over target chunks of 64
+    "square_20k_ns120": lambda: (*dmk_inputs.uniform_square(20000, 204), 120),
 }
 # kernels: (name, oracle kernel id, lambda in input units)
 KERNELS = {"log": (0, 0.0), "k0": (1, 10.0)}

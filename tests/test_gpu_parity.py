@@ -40,6 +40,8 @@ CASES = {
     "two_clusters_6k": lambda: (*dmk_inputs.two_clusters_and_background(6000, 101), 20),
     "sphere_blobs_20k": lambda: (*dmk_inputs.sphere_and_blobs(20000, 102), 40),
     "uniform_30k": lambda: (*dmk_inputs.uniform_cube(30000, 103), 64),
+    # leaves of 65..128 points: the kernels' loops over target chunks of 64
+    "uniform_50k_ns128": lambda: (*dmk_inputs.uniform_cube(50000, 104), 128),
 }
 
 

@@ -455,11 +455,14 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int NWAVE = TPB / 64;
 
+constexpr int LOCAL_NT = 512;  // threads per block of the local stage (more waves hide MFMA latency)
+
 template <int P, int NF>
 struct LocalMfma {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1, NM = NH * NN;
     static constexpr int NSL = (P2 + 15) / 16;              // slabs of the p^2 x p outputs
-    static constexpr int NSW = (NSL + NWAVE - 1) / NWAVE;   // slabs per wave
+    static constexpr int NWV = LOCAL_NT / 64, NT = LOCAL_NT;  // waves and threads per block
+    static constexpr int NSW = (NSL + NWV - 1) / NWV;       // slabs per wave
     static constexpr int NAT = (P + 15) / 16;               // column tiles of the new index
     static constexpr int G = 16 / (P % 16 == 0 ? 16 : (P % 8 == 0 ? 8 : (P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1))));
     static constexpr int KP = 2 * NH;                        // m3 real parts, then imaginary parts
@@ -472,7 +475,7 @@ struct LocalMfma {
 
 // real mode product into registers: acc[i][t] += sum_k X(x, k) B(k, a) for the
 // wave's slabs i (slab w + NWAVE i) and tiles t; Bt[k * P + a]
-template <int P, int NX, int NK, int NSW, int NAT, typename XF>
+template <int NWV, int P, int NX, int NK, int NSW, int NAT, typename XF>
 __device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][NAT])
 {
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
@@ -487,7 +490,7 @@ __device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][NAT
         }
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
-        const int sl = w + NWAVE * i;
+        const int sl = w + NWV * i;
         if (sl >= NSL) break;
         const int xa = 16 * sl + r16;
 #pragma unroll
@@ -502,7 +505,7 @@ __device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][NAT
 }
 
 // real mode product with the result stored: Y(x, a) -> store(x, a, v)
-template <int P, int NX, int NK, int NAT, typename XF, typename SF>
+template <int NWV, int P, int NX, int NK, int NAT, typename XF, typename SF>
 __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
 {
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
@@ -515,7 +518,7 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
             const int k = 4 * s + kq, a = 16 * t + r16;
             breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
         }
-    for (int sl = w; sl < NSL; sl += NWAVE) {
+    for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
         f32x4 acc[NAT];
 #pragma unroll
@@ -538,7 +541,7 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
 }
 
 // complex mode product Y = X B, X planar (Xr, Xi functors), B planar tables
-template <int P, int NX, int NK, int NAT, typename XR, typename XI, typename SF>
+template <int NWV, int P, int NX, int NK, int NAT, typename XR, typename XI, typename SF>
 __device__ inline void mma_cplx_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
 {
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
@@ -553,7 +556,7 @@ __device__ inline void mma_cplx_store(XR Xr, XI Xi, const float *Br, const float
             br[t][s] = ok ? Br[k * P + a] : 0.f;
             bi[t][s] = ok ? Bi[k * P + a] : 0.f;
         }
-    for (int sl = w; sl < NSL; sl += NWAVE) {
+    for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
         f32x4 cr[NAT], ci[NAT];
 #pragma unroll
@@ -584,7 +587,7 @@ __device__ inline void mma_cplx_store(XR Xr, XI Xi, const float *Br, const float
 // complex mode product with X planar in global memory (row stride xs,
 // column k at k * ks): the next slab's operands are loaded while the current
 // slab's MFMAs run, to hide the HBM latency
-template <int P, int NX, int NK, int NAT, typename SF>
+template <int NWV, int P, int NX, int NK, int NAT, typename SF>
 __device__ inline void mma_cplx_store_global(const float *Xr, const float *Xi, int64_t ks, const float *Br,
                                              const float *Bi, SF store)
 {
@@ -612,9 +615,9 @@ __device__ inline void mma_cplx_store_global(const float *Xr, const float *Xi, i
         }
     };
     fetch(w, ar, ai);
-    for (int sl = w; sl < NSL; sl += NWAVE) {
+    for (int sl = w; sl < NSL; sl += NWV) {
         float nr[NKS], ni[NKS];
-        fetch(sl + NWAVE, nr, ni);
+        fetch(sl + NWV, nr, ni);
         f32x4 cr[NAT], ci[NAT];
 #pragma unroll
         for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -642,11 +645,11 @@ __device__ inline void mma_cplx_store_global(const float *Xr, const float *Xi, i
 }
 
 template <int P, int NF>
-__global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32_t *list, int level)
+__global__ void __launch_bounds__(LOCAL_NT) k_local_mfma(Dev<float> D, const int32_t *list, int level)
 {
     using L = LocalMfma<P, NF>;
     constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, NSW = L::NSW, NAT = L::NAT;
-    constexpr int G = L::G, KP = L::KP, NSL = L::NSL;
+    constexpr int G = L::G, KP = L::KP, NSL = L::NSL, NWV = L::NWV, NT = L::NT;
     extern __shared__ unsigned char smraw[];
     float *sm = reinterpret_cast<float *>(smraw);
     float *Br1 = sm, *Bi1 = Br1 + NN * P;  // conj(E): B(k = m, a = j) = Er[m][j] - i Ei[m][j]
@@ -655,17 +658,17 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
     float *xc = Bz + P2, *bw = xc + P;
     float *work = bw + P;
     const int32_t B = list[blockIdx.x];
-    for (int t = threadIdx.x; t < NN * P; t += TPB) {
+    for (int t = threadIdx.x; t < NN * P; t += NT) {
         Br1[t] = D.epw[2 * t];
         Bi1[t] = -D.epw[2 * t + 1];
     }
-    for (int t = threadIdx.x; t < KP * P; t += TPB) {
+    for (int t = threadIdx.x; t < KP * P; t += NT) {
         const int k = t / P, j = t % P, m3 = (k < NH) ? k : k - NH;
         const float cm = (m3 == 0) ? 1.f : 2.f;
         const float *e = D.epw + 2 * ((m3 + NF) * P + j);
         B3[t] = cm * ((k < NH) ? e[0] : e[1]);
     }
-    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
+    for (int t = threadIdx.x; t < P; t += NT) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
     f32x4 acc[NSW][NAT];
 #pragma unroll
     for (int i = 0; i < NSW; ++i)
@@ -677,7 +680,7 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
         // root: the windowed W_0 values, in the fragment layout of the last step
 #pragma unroll
         for (int i = 0; i < NSW; ++i) {
-            const int sl = w + NWAVE * i;
+            const int sl = w + NWV * i;
             if (sl >= NSL) break;
 #pragma unroll
             for (int t = 0; t < NAT; ++t)
@@ -692,7 +695,7 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
         // A-coordinate ((c_B + s_B x_i / 2) - c_A) * 2 / s_A
         const int32_t A = D.anchor[D.parent[B]];
         const double sB = box_side(level), sA = box_side(D.blevel[A]);
-        for (int t = threadIdx.x; t < 3 * P; t += TPB) {
+        for (int t = threadIdx.x; t < 3 * P; t += NT) {
             const int d = t / P, i = t % P;
             const double xi = (D.bcenter[3 * (int64_t)B + d] + 0.5 * sB * D.xcheb64[i] - D.bcenter[3 * (int64_t)A + d]) *
                               (2.0 / sA);
@@ -704,19 +707,19 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
         }
         float *vA = work, *t1 = work + P3;
         const float *src = D.local + (int64_t)D.local_slot[A] * P3;
-        for (int t = threadIdx.x; t < P3; t += TPB) vA[t] = src[t];
+        for (int t = threadIdx.x; t < P3; t += NT) vA[t] = src[t];
         __syncthreads();
         // x: t1[i0][(a1 a2)] = sum_a0 vA[a0][(a1 a2)] Mx[i0][a0]
-        mma_real_store<P, P2, P, NAT>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
+        mma_real_store<NWV, P, P2, P, NAT>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
                                       [&](int x, int a, float v) { t1[a * P2 + x] = v; });
         __syncthreads();
         // y: t2[i0][i1][a2] = sum_a1 t1[i0][a1][a2] My[i1][a1]; rows x = (i0, a2)
         float *t2 = vA;
-        mma_real_store<P, P2, P, NAT>([&](int x, int k) { return t1[(x / P) * P2 + k * P + (x % P)]; }, By,
+        mma_real_store<NWV, P, P2, P, NAT>([&](int x, int k) { return t1[(x / P) * P2 + k * P + (x % P)]; }, By,
                                       [&](int x, int a, float v) { t2[(x / P) * P2 + a * P + (x % P)] = v; });
         __syncthreads();
         // z: acc[(i0 i1)][i2] = sum_a2 t2[(i0 i1)][a2] Mz[i2][a2]
-        mma_real_acc<P, P2, P, NSW, NAT>([&](int x, int k) { return t2[x * P + k]; }, Bz, acc);
+        mma_real_acc<NWV, P, P2, P, NSW, NAT>([&](int x, int k) { return t2[x * P + k]; }, Bz, acc);
     }
     if (D.psi_slot[B] >= 0) {
         const int64_t nm = D.pwstride;
@@ -724,7 +727,7 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
         float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
         __syncthreads();
         // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
-        mma_cplx_store_global<P, NM, NN, NAT>(psr, psi, NM, Br1, Bi1, [&](int x, int a, float vr, float vi) {
+        mma_cplx_store_global<NWV, P, NM, NN, NAT>(psr, psi, NM, Br1, Bi1, [&](int x, int a, float vr, float vi) {
             A1r[a * NM + x] = vr;
             A1i[a * NM + x] = vi;
         });
@@ -733,7 +736,7 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
             const int g = min(G, P - g0);
             __syncthreads();
             // m2: B2[(j1 j2)][m3 | NH + m3] = sum_m2 conj(E[m2][j2]) A1[j1][m3][m2]; rows x = (j1 - g0, m3)
-            mma_cplx_store<P, G * NH, NN, NAT>(
+            mma_cplx_store<NWV, P, G * NH, NN, NAT>(
                 [&](int x, int k) { return (x < g * NH) ? A1r[(g0 * NH + x) * NN + k] : 0.f; },
                 [&](int x, int k) { return (x < g * NH) ? A1i[(g0 * NH + x) * NN + k] : 0.f; }, Br1, Bi1,
                 [&](int x, int a, float vr, float vi) {
@@ -757,7 +760,7 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
             const int r0 = g0 * P, r1 = (g0 + g) * P;  // rows of this group, multiples of 16 at r0
 #pragma unroll
             for (int i = 0; i < NSW; ++i) {
-                const int sl = w + NWAVE * i;
+                const int sl = w + NWV * i;
                 if (sl >= NSL || 16 * sl < r0 || 16 * sl >= r1) continue;
                 const int xa = 16 * sl + r16;
 #pragma unroll
@@ -774,7 +777,7 @@ __global__ void __launch_bounds__(TPB, 2) k_local_mfma(Dev<float> D, const int32
     float *dst = D.local + (int64_t)D.local_slot[B] * P3;
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
-        const int sl = w + NWAVE * i;
+        const int sl = w + NWV * i;
         if (sl >= NSL) break;
 #pragma unroll
         for (int t = 0; t < NAT; ++t)
@@ -831,7 +834,7 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
     for (int t = threadIdx.x; t < P3; t += TPB) r0[t] = src[t];
     __syncthreads();
     // j3 -> m3 (real rho times the real and imaginary rows)
-    mma_real_store<W1, P2, P, (W1 + 15) / 16>([&](int x, int k) { return r0[x * P + k]; }, B1,
+    mma_real_store<NWAVE, W1, P2, P, (W1 + 15) / 16>([&](int x, int k) { return r0[x * P + k]; }, B1,
                                               [&](int x, int a, float v) { A[x * W1 + a] = v; });
     const int64_t nm = D.pwstride;
     float *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
@@ -840,7 +843,7 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
         const int g = min(G, NH - g0);
         __syncthreads();
         // j2 -> m2: rows x = (j1, mm)
-        mma_cplx_store<NN, P * G, P, (NN + 15) / 16>(
+        mma_cplx_store<NWAVE, NN, P * G, P, (NN + 15) / 16>(
             [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
             [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
             BrT, BiT, [&](int x, int a, float vr, float vi) {
@@ -849,7 +852,7 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
             });
         __syncthreads();
         // j1 -> m1: rows x = (mm, m2)
-        mma_cplx_store<NN, G * NN, P, (NN + 15) / 16>(
+        mma_cplx_store<NWAVE, NN, G * NN, P, (NN + 15) / 16>(
             [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(k * G + mm) * NN + m2] : 0.f; },
             [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(k * G + mm) * NN + m2] : 0.f; },
             BrT, BiT, [&](int x, int a, float vr, float vi) {
@@ -1421,8 +1424,9 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
         if (!nan) continue;
         StageScope t(Pl, s, DMK_STAGE_PW2GRID);
         const size_t lds_mfma = LocalMfma<P, NF>::lds();
+        const unsigned nt_mfma = LocalMfma<P, NF>::NT;
         if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_local_mfma<P, NF>), dim3((unsigned)nan), dim3(TPB), lds_mfma, s, D,
+            hipLaunchKernelGGL((k_local_mfma<P, NF>), dim3((unsigned)nan), dim3(nt_mfma), lds_mfma, s, D,
                                Pl->l_anc + ll.anc_off[l], l);
         else
             hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,

@@ -797,6 +797,8 @@ __global__ void __launch_bounds__(LOCAL_NT) k_local_mfma(Dev<float> D, const int
 //   j1 -> m1  Phi[m1][(mm m2)] = sum_j1 E[m1][j1] B2[(j1 mm)][m2] (complex)
 // the last two for G values of m3 at a time; each group's Phi rows are
 // staged in LDS and written to HBM as contiguous runs of G * nn values.
+constexpr int P2PW_NT = 512;  // threads per block of proxy -> plane waves on matrix cores
+
 template <int P, int NF>
 struct P2pwMfma {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1, NM = NH * NN, W1 = 2 * NH;
@@ -807,7 +809,7 @@ struct P2pwMfma {
 };
 
 template <int P, int NF>
-__global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const int32_t *list)
+__global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const int32_t *list)
 {
     using L = P2pwMfma<P, NF>;
     constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, W1 = L::W1, G = L::G;
@@ -821,20 +823,20 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
     float *B2r = r0, *B2i = B2r + P * G * NN;       // [(j1 mm)][m2]
     float *Fr = B2i + P * G * NN, *Fi = Fr + NN * G * NN;  // [m1][(mm m2)]
     const int32_t B = list[blockIdx.x];
-    for (int t = threadIdx.x; t < P * W1; t += TPB) {
+    for (int t = threadIdx.x; t < P * W1; t += P2PW_NT) {
         const int j = t / W1, a = t % W1, m3 = (a < NH) ? a : a - NH;
         B1[t] = D.epw[2 * ((m3 + NF) * P + j) + (a < NH ? 0 : 1)];
     }
-    for (int t = threadIdx.x; t < P * NN; t += TPB) {
+    for (int t = threadIdx.x; t < P * NN; t += P2PW_NT) {
         const int j = t / NN, m = t % NN;
         BrT[t] = D.epw[2 * (m * P + j)];
         BiT[t] = D.epw[2 * (m * P + j) + 1];
     }
     const float *src = D.proxy + (int64_t)D.proxy_slot[B] * P3;
-    for (int t = threadIdx.x; t < P3; t += TPB) r0[t] = src[t];
+    for (int t = threadIdx.x; t < P3; t += P2PW_NT) r0[t] = src[t];
     __syncthreads();
     // j3 -> m3 (real rho times the real and imaginary rows)
-    mma_real_store<NWAVE, W1, P2, P, (W1 + 15) / 16>([&](int x, int k) { return r0[x * P + k]; }, B1,
+    mma_real_store<P2PW_NT / 64, W1, P2, P, (W1 + 15) / 16>([&](int x, int k) { return r0[x * P + k]; }, B1,
                                               [&](int x, int a, float v) { A[x * W1 + a] = v; });
     const int64_t nm = D.pwstride;
     float *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
@@ -843,7 +845,7 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
         const int g = min(G, NH - g0);
         __syncthreads();
         // j2 -> m2: rows x = (j1, mm)
-        mma_cplx_store<NWAVE, NN, P * G, P, (NN + 15) / 16>(
+        mma_cplx_store<P2PW_NT / 64, NN, P * G, P, (NN + 15) / 16>(
             [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
             [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
             BrT, BiT, [&](int x, int a, float vr, float vi) {
@@ -852,7 +854,7 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
             });
         __syncthreads();
         // j1 -> m1: rows x = (mm, m2)
-        mma_cplx_store<NWAVE, NN, G * NN, P, (NN + 15) / 16>(
+        mma_cplx_store<P2PW_NT / 64, NN, G * NN, P, (NN + 15) / 16>(
             [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(k * G + mm) * NN + m2] : 0.f; },
             [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(k * G + mm) * NN + m2] : 0.f; },
             BrT, BiT, [&](int x, int a, float vr, float vi) {
@@ -861,7 +863,7 @@ __global__ void __launch_bounds__(TPB, 2) k_proxy2pw_mfma(Dev<float> D, const in
             });
         __syncthreads();
         // the group's rows of Phi[m1][m3][m2]: runs of g * nn values per m1
-        for (int t = threadIdx.x; t < NN * g * NN; t += TPB) {
+        for (int t = threadIdx.x; t < NN * g * NN; t += P2PW_NT) {
             const int m1 = t / (g * NN), r = t % (g * NN);
             outr[(int64_t)m1 * NM + g0 * NN + r] = Fr[m1 * G * NN + r];
             outi[(int64_t)m1 * NM + g0 * NN + r] = Fi[m1 * G * NN + r];
@@ -1404,7 +1406,7 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
         StageScope t(Pl, s, DMK_STAGE_PROXY2PW);
         const size_t lds_p2pw_mfma = P2pwMfma<P, NF>::lds();
         if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_proxy2pw_mfma<P, NF>), dim3((unsigned)Pl->nfout), dim3(TPB), lds_p2pw_mfma, s, D,
+            hipLaunchKernelGGL((k_proxy2pw_mfma<P, NF>), dim3((unsigned)Pl->nfout), dim3(P2PW_NT), lds_p2pw_mfma, s, D,
                                Pl->l_fout);
         else
             hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,

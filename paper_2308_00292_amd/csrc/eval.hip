@@ -41,6 +41,11 @@ namespace dmk {
 namespace {
 
 // ------------------------------------------------------------ device view
+// elements per plane-wave set (real or imaginary part of one box): the
+// nh * nn * nn modes of the half spectrum, padded to a multiple of 64 so that
+// every set starts 256-byte aligned
+static inline int64_t pw_stride(const Tables &t) { return ((int64_t)t.nh * t.nn * t.nn + 63) / 64 * 64; }
+
 template <typename T>
 struct Dev {
     int p, nf, nn, nh, nw, nwn, nwh, gdeg;
@@ -53,7 +58,7 @@ struct Dev {
     const double *ew64, *ww64, *xcheb64, *bary64;     // FP64 tables
     T *proxy, *local, *phi, *psi, *w0vals;
     double *ufar, *ures, *rootscratch;
-    int64_t pwstride;  // elements per plane-wave set (nh * nn * nn)
+    int64_t pwstride;  // elements per plane-wave set: nh * nn * nn modes, padded to a multiple of 64
 };
 
 // ------------------------------------------------------------------ upward
@@ -192,8 +197,10 @@ __global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list)
 // as three passes of 3-term sums (z, then y, then x) shared by the siblings:
 // 64 loads per mode for 8 boxes instead of up to 27 per box.  One thread per
 // mode; a block covers TPB consecutive modes of one group.  Blocks are dealt
-// out so that each XCD gets a contiguous range of groups (neighbouring groups
-// share most of their sources, which then stay in that XCD's L2).
+// out so that each XCD gets a contiguous range of groups, and within it the
+// blocks run chunk by chunk over that range: neighbouring groups share most
+// of their sources, and a source's chunk is then read again by the next few
+// groups while it is still in that XCD's L2.
 template <typename T>
 struct Cx { T r, i; };
 
@@ -211,18 +218,24 @@ __device__ inline Cx<T> root3(int k)  // w^{-k}, any integer k
     return {T(-0.5), s3};
 }
 
-template <typename T>
+// MPT consecutive modes per thread, loaded and stored as one vector (the
+// plane-wave sets are padded to a multiple of 64 elements, so the vectors
+// are aligned); modes past the last one compute on padding and store nothing
+// that is read.
+template <typename T, int MPT>
 __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_dst, const int32_t *oct_src,
                                                  const int32_t *oct_level, int64_t noct, int nchunk)
 {
+    typedef T vec __attribute__((ext_vector_type(MPT)));
     __shared__ int32_t src[64];
     __shared__ int32_t dst[8];
     __shared__ int colany[16];
-    const int64_t G = gridDim.x;  // a multiple of 8
-    const int64_t Lb = (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8;
-    const int64_t o = Lb / nchunk;
-    const int chunk = (int)(Lb % nchunk);
-    if (o >= noct) return;  // whole block: before any barrier
+    // grid = 8 * per * nchunk; blocks go to the XCDs round-robin
+    const int64_t per = (noct + 7) / 8;  // groups per XCD
+    const int64_t Lb = blockIdx.x / 8;
+    const int chunk = (int)(Lb / per);
+    const int64_t o = (int64_t)(blockIdx.x % 8) * per + Lb % per;
+    if (o >= noct || chunk >= nchunk) return;  // whole block: before any barrier
     if (threadIdx.x < 64) src[threadIdx.x] = oct_src[o * 64 + threadIdx.x];
     if (threadIdx.x < 8) dst[threadIdx.x] = oct_dst[o * 8 + threadIdx.x];
     __syncthreads();
@@ -231,102 +244,130 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
         colany[c] = (src[4 * c] >= 0) | (src[4 * c + 1] >= 0) | (src[4 * c + 2] >= 0) | (src[4 * c + 3] >= 0);
     }
     __syncthreads();
-    const int64_t nm = D.pwstride;
-    const int64_t e = (int64_t)chunk * TPB + threadIdx.x;
-    if (e >= nm) return;
     const int nn = D.nn, nh = D.nh, nf = D.nf;
+    const int64_t nmode = (int64_t)nh * nn * nn, nm = D.pwstride;
+    const int64_t e0 = ((int64_t)chunk * TPB + threadIdx.x) * MPT;
+    if (e0 >= nmode) return;
+    // per-axis factors for delta = -1 and +1 (delta = 0 is 1);
     // e = (m1 * nh + m3) * nn + m2
-    const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
-    // per-axis factors for delta = -1 and +1 (delta = 0 is 1)
-    const Cx<T> xm = root3<T>(-m1), xp = root3<T>(m1);
-    const Cx<T> ym = root3<T>(-m2), yp = root3<T>(m2);
-    const Cx<T> zm = root3<T>(-m3), zp = root3<T>(m3);
-    Cx<T> acc[2][2][2];
+    Cx<T> xm[MPT], xp[MPT], ym[MPT], yp[MPT], zm[MPT], zp[MPT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int u = 0; u < MPT; ++u) {
+        const int64_t e = min(e0 + u, nmode - 1);
+        const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
+        xm[u] = root3<T>(-m1); xp[u] = root3<T>(m1);
+        ym[u] = root3<T>(-m2); yp[u] = root3<T>(m2);
+        zm[u] = root3<T>(-m3); zp[u] = root3<T>(m3);
+    }
+    Cx<T> acc[MPT][2][2][2];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+    for (int u = 0; u < MPT; ++u)
 #pragma unroll
-            for (int c = 0; c < 2; ++c) acc[a][b][c] = {T(0), T(0)};
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) acc[u][a][b][c] = {T(0), T(0)};
     const T *phi = D.phi;
 #pragma unroll
     for (int gx = 0; gx < 4; ++gx) {
         // z then y pass for this x slab: Y[ty][tz]
-        Cx<T> Y[2][2];
+        Cx<T> Y[MPT][2][2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int u = 0; u < MPT; ++u)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) Y[a][b] = {T(0), T(0)};
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) Y[u][a][b] = {T(0), T(0)};
         bool any = false;
 #pragma unroll
         for (int gy = 0; gy < 4; ++gy) {
             if (!colany[gx * 4 + gy]) continue;
             any = true;
-            Cx<T> f[4];
+            Cx<T> f[4][MPT];
 #pragma unroll
             for (int gz = 0; gz < 4; ++gz) {
                 const int32_t sl = src[(gx * 4 + gy) * 4 + gz];
+                vec vr = (vec)T(0), vi = (vec)T(0);
                 if (sl >= 0) {
-                    const T *q = phi + 2 * (int64_t)sl * nm + e;
-                    f[gz] = {q[0], q[nm]};
-                } else {
-                    f[gz] = {T(0), T(0)};
+                    const T *q = phi + 2 * (int64_t)sl * nm + e0;
+                    vr = *reinterpret_cast<const vec *>(q);
+                    vi = *reinterpret_cast<const vec *>(q + nm);
                 }
+#pragma unroll
+                for (int u = 0; u < MPT; ++u) f[gz][u] = {vr[u], vi[u]};
             }
-            // Z[tz] = sum over gz = tz .. tz+2 of w^{-m3 (gz - tz - 1)} f[gz]
-            Cx<T> z0 = cmul(f[0], zm), z1 = cmul(f[3], zp);
-            z0.r += f[1].r + cmul(f[2], zp).r;
-            z0.i += f[1].i + cmul(f[2], zp).i;
-            z1.r += f[2].r + cmul(f[1], zm).r;
-            z1.i += f[2].i + cmul(f[1], zm).i;
-            // ty = gy - 1 - delta: gy contributes to ty = 0 (delta = gy - 1) and ty = 1 (delta = gy - 2)
-            if (gy <= 2) {
-                const Cx<T> fy = (gy == 0) ? ym : (gy == 1) ? Cx<T>{T(1), T(0)} : yp;
-                const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
-                Y[0][0].r += a0.r; Y[0][0].i += a0.i;
-                Y[0][1].r += a1.r; Y[0][1].i += a1.i;
-            }
-            if (gy >= 1) {
-                const Cx<T> fy = (gy == 1) ? ym : (gy == 2) ? Cx<T>{T(1), T(0)} : yp;
-                const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
-                Y[1][0].r += a0.r; Y[1][0].i += a0.i;
-                Y[1][1].r += a1.r; Y[1][1].i += a1.i;
+#pragma unroll
+            for (int u = 0; u < MPT; ++u) {
+                // Z[tz] = sum over gz = tz .. tz+2 of w^{-m3 (gz - tz - 1)} f[gz]
+                Cx<T> z0 = cmul(f[0][u], zm[u]), z1 = cmul(f[3][u], zp[u]);
+                z0.r += f[1][u].r + cmul(f[2][u], zp[u]).r;
+                z0.i += f[1][u].i + cmul(f[2][u], zp[u]).i;
+                z1.r += f[2][u].r + cmul(f[1][u], zm[u]).r;
+                z1.i += f[2][u].i + cmul(f[1][u], zm[u]).i;
+                // ty = gy - 1 - delta: gy contributes to ty = 0 (delta = gy - 1) and ty = 1 (delta = gy - 2)
+                if (gy <= 2) {
+                    const Cx<T> fy = (gy == 0) ? ym[u] : (gy == 1) ? Cx<T>{T(1), T(0)} : yp[u];
+                    const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
+                    Y[u][0][0].r += a0.r; Y[u][0][0].i += a0.i;
+                    Y[u][0][1].r += a1.r; Y[u][0][1].i += a1.i;
+                }
+                if (gy >= 1) {
+                    const Cx<T> fy = (gy == 1) ? ym[u] : (gy == 2) ? Cx<T>{T(1), T(0)} : yp[u];
+                    const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
+                    Y[u][1][0].r += a0.r; Y[u][1][0].i += a0.i;
+                    Y[u][1][1].r += a1.r; Y[u][1][1].i += a1.i;
+                }
             }
         }
         if (!any) continue;
         // x pass
-        if (gx <= 2) {
-            const Cx<T> fx = (gx == 0) ? xm : (gx == 1) ? Cx<T>{T(1), T(0)} : xp;
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+        for (int u = 0; u < MPT; ++u) {
+            if (gx <= 2) {
+                const Cx<T> fx = (gx == 0) ? xm[u] : (gx == 1) ? Cx<T>{T(1), T(0)} : xp[u];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const Cx<T> v = cmul(Y[b][c], fx);
-                    acc[0][b][c].r += v.r;
-                    acc[0][b][c].i += v.i;
-                }
-        }
-        if (gx >= 1) {
-            const Cx<T> fx = (gx == 1) ? xm : (gx == 2) ? Cx<T>{T(1), T(0)} : xp;
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+                    for (int c = 0; c < 2; ++c) {
+                        const Cx<T> v = cmul(Y[u][b][c], fx);
+                        acc[u][0][b][c].r += v.r;
+                        acc[u][0][b][c].i += v.i;
+                    }
+            }
+            if (gx >= 1) {
+                const Cx<T> fx = (gx == 1) ? xm[u] : (gx == 2) ? Cx<T>{T(1), T(0)} : xp[u];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const Cx<T> v = cmul(Y[b][c], fx);
-                    acc[1][b][c].r += v.r;
-                    acc[1][b][c].i += v.i;
-                }
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const Cx<T> v = cmul(Y[u][b][c], fx);
+                        acc[u][1][b][c].r += v.r;
+                        acc[u][1][b][c].i += v.i;
+                    }
+            }
         }
     }
-    const T w = D.wd0[e] * (T)ldexp(1.0, oct_level[o]);  // w_l = 2^l w_0 (scale invariance of 1/r)
+    T w[MPT];
+    const T scale = (T)ldexp(1.0, oct_level[o]);  // w_l = 2^l w_0 (scale invariance of 1/r)
+#pragma unroll
+    for (int u = 0; u < MPT; ++u) w[u] = (e0 + u < nmode) ? D.wd0[e0 + u] * scale : T(0);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int32_t d = dst[t];
         if (d < 0) continue;
-        const Cx<T> v = acc[t >> 2][(t >> 1) & 1][t & 1];
-        T *out = D.psi + 2 * (int64_t)d * nm + e;
-        out[0] = v.r * w;
-        out[nm] = v.i * w;
+        vec vr, vi;
+#pragma unroll
+        for (int u = 0; u < MPT; ++u) {
+            const Cx<T> v = acc[u][t >> 2][(t >> 1) & 1][t & 1];
+            vr[u] = v.r * w[u];
+            vi[u] = v.i * w[u];
+        }
+        T *out = D.psi + 2 * (int64_t)d * nm + e0;
+        // streaming stores: Psi is read again only by the local stage, long
+        // after, so it should not displace the sources held in L2
+        __builtin_nontemporal_store(vr, reinterpret_cast<vec *>(out));
+        __builtin_nontemporal_store(vi, reinterpret_cast<vec *>(out + nm));
     }
 }
 
@@ -1327,7 +1368,7 @@ Dev<T> make_dev(Plan *P)
     D.proxy = (T *)P->proxy; D.local = (T *)P->local; D.phi = (T *)P->phi; D.psi = (T *)P->psi;
     D.w0vals = (T *)P->w0vals;
     D.ufar = P->ufar; D.ures = P->ures; D.rootscratch = P->rootscratch;
-    D.pwstride = (int64_t)t.nh * t.nn * t.nn;
+    D.pwstride = pw_stride(t);
     return D;
 }
 
@@ -1414,10 +1455,11 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     }
     if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
-        const int64_t nm = (int64_t)Pl->tab.nh * Pl->tab.nn * Pl->tab.nn;
-        const int nchunk = (int)((nm + TPB - 1) / TPB);
-        const int64_t nb = (Pl->noct * nchunk + 7) / 8 * 8;
-        hipLaunchKernelGGL((k_pwshift<T>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
+        constexpr int MPT = sizeof(T) == 4 ? 2 : 1;  // modes per thread
+        const int64_t nmode = (int64_t)Pl->tab.nh * Pl->tab.nn * Pl->tab.nn;
+        const int nchunk = (int)((nmode + TPB * MPT - 1) / (TPB * MPT));
+        const int64_t nb = 8 * ((Pl->noct + 7) / 8) * nchunk;
+        hipLaunchKernelGGL((k_pwshift<T, MPT>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
                            Pl->oct_level, Pl->noct, nchunk);
     }
     // local values of the anchors, coarse to fine
@@ -1604,7 +1646,7 @@ void alloc_workspace(Plan *P)
     const Tables &t = P->tab;
     const size_t el = (P->precision == DMK_FP64) ? sizeof(double) : sizeof(float);
     const int64_t p3 = (int64_t)t.p * t.p * t.p;
-    const int64_t nm = (int64_t)t.nh * t.nn * t.nn;
+    const int64_t nm = pw_stride(t);
     auto al = [&](int64_t cnt, size_t sz) { return dalloc(P, (size_t)std::max<int64_t>(cnt, 1) * sz); };
     P->qs = (double *)al(P->n, 8);
     P->ufar = (double *)al(P->n, 8);

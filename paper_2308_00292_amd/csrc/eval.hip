@@ -1305,19 +1305,37 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
             bz[s] = (k < P) ? Lr[w][2][r16][k] : 0.f;
         }
         float part = 0.f;
-        for (int sl = 0; sl < NSL; ++sl) {
-            const int xa = 16 * sl + r16;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        // LU slabs at a time (independent MFMA chains); the lane's first row
+        // x0 = 16 sl + 4 kq is tracked as (x0 / P, x0 % P)
+        constexpr int LU = 3;
+        int i0 = (4 * kq) / P, i1 = (4 * kq) % P;
+#pragma unroll 1
+        for (int sl = 0; sl < NSL; sl += LU) {
+            f32x4 acc[LU];
+#pragma unroll
+            for (int u = 0; u < LU; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < NKS; ++s) {
                 const int k = 4 * s + kq;
-                const float av = (xa < P2 && k < P) ? v[xa * P + k] : 0.f;
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bz[s], acc, 0, 0, 0);
+#pragma unroll
+                for (int u = 0; u < LU; ++u) {
+                    const int xa = 16 * (sl + u) + r16;
+                    const float av = (xa < P2 && k < P) ? v[xa * P + k] : 0.f;
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bz[s], acc[u], 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int x = 16 * sl + 4 * kq + q;
-                if (x < P2) part += Lr[w][0][r16][x / P] * Lr[w][1][r16][x % P] * acc[q];
+            for (int u = 0; u < LU; ++u) {
+                const int x0 = 16 * (sl + u) + 4 * kq;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    int j0 = i0, j1 = i1 + q;
+                    if (j1 >= P) { j1 -= P; ++j0; }
+                    if (x0 + q < P2) part += Lr[w][0][r16][j0] * Lr[w][1][r16][j1] * acc[u][q];
+                }
+                // next slab: x0 += 16
+                i1 += 16;
+                while (i1 >= P) { i1 -= P; ++i0; }
             }
         }
         part += __shfl_xor(part, 16);

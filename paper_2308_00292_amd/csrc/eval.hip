@@ -964,6 +964,57 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
 //   j1 -> m1  Phi[m1][(mm m2)] = sum_j1 E[m1][j1] B2[(j1 mm)][m2] (complex)
 // the last two for G values of m3 at a time; each group's Phi rows are
 // staged in LDS and written to HBM as contiguous runs of G * nn values.
+// Forward plane-wave contraction to a full output index m = -NF..NF:
+// Y[m] = sum_k E[m][k] X[k] with E[-m] = conj(E[m]) needs only the real
+// matrices Er, Ei at m >= 0:  U = Er.X, V = Ei.X (X complex),
+//   Y[m] = U + i V,  Y[-m] = U - i V,
+// which halves the matrix-core work of the plain complex product.  Br, Bi
+// point at column m = 0 of E (element (k, m) at k * NBS + m); store receives
+// (x, m, Y[m], Y[-m]) for m = 0..NF (Y[-0] is Y[0]).
+template <int NWV, int NF, int NX, int NK, int NBS, typename XR, typename XI, typename SF>
+__device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
+{
+    constexpr int NH = NF + 1, NKS = (NK + 3) / 4, NSL = (NX + 15) / 16, NAT = (NH + 15) / 16;
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
+    float br[NAT][NKS], bi[NAT][NKS];
+#pragma unroll
+    for (int t = 0; t < NAT; ++t)
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq, a = 16 * t + r16;
+            const bool ok = k < NK && a < NH;
+            br[t][s] = ok ? Br[k * NBS + a] : 0.f;
+            bi[t][s] = ok ? Bi[k * NBS + a] : 0.f;
+        }
+    for (int sl = w; sl < NSL; sl += NWV) {
+        const int xa = 16 * sl + r16;
+        f32x4 ur[NAT], ui[NAT], vr[NAT], vi[NAT];
+#pragma unroll
+        for (int t = 0; t < NAT; ++t) ur[t] = ui[t] = vr[t] = vi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const int k = 4 * s + kq;
+            const bool ok = xa < NX && k < NK;
+            const float ar = ok ? Xr(xa, k) : 0.f, ai = ok ? Xi(xa, k) : 0.f;
+#pragma unroll
+            for (int t = 0; t < NAT; ++t) {
+                ur[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[t][s], ur[t], 0, 0, 0);
+                ui[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[t][s], ui[t], 0, 0, 0);
+                vr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[t][s], vr[t], 0, 0, 0);
+                vi[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi[t][s], vi[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NAT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = 16 * sl + 4 * kq + i, m = 16 * t + r16;
+                if (x < NX && m < NH)
+                    store(x, m, ur[t][i] - vi[t][i], ui[t][i] + vr[t][i], ur[t][i] + vi[t][i], ui[t][i] - vr[t][i]);
+            }
+    }
+}
+
 constexpr int P2PW_NT = 512;  // threads per block of proxy -> plane waves on matrix cores
 
 template <int P, int NF>
@@ -1012,21 +1063,29 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
         const int g = min(G, NH - g0);
         __syncthreads();
         // j2 -> m2: rows x = (j1, mm)
-        mma_cplx_store<P2PW_NT / 64, NN, P * G, P, (NN + 15) / 16>(
+        mma_herm_out_store<P2PW_NT / 64, NF, P * G, P, NN>(
             [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
             [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
-            BrT, BiT, [&](int x, int a, float vr, float vi) {
-                B2r[x * NN + a] = vr;
-                B2i[x * NN + a] = vi;
+            BrT + NF, BiT + NF, [&](int x, int m, float pr, float pi, float nr, float ni) {
+                B2r[x * NN + NF + m] = pr;
+                B2i[x * NN + NF + m] = pi;
+                if (m > 0) {
+                    B2r[x * NN + NF - m] = nr;
+                    B2i[x * NN + NF - m] = ni;
+                }
             });
         __syncthreads();
         // j1 -> m1: rows x = (mm, m2)
-        mma_cplx_store<P2PW_NT / 64, NN, G * NN, P, (NN + 15) / 16>(
+        mma_herm_out_store<P2PW_NT / 64, NF, G * NN, P, NN>(
             [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(k * G + mm) * NN + m2] : 0.f; },
             [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(k * G + mm) * NN + m2] : 0.f; },
-            BrT, BiT, [&](int x, int a, float vr, float vi) {
-                Fr[a * G * NN + x] = vr;
-                Fi[a * G * NN + x] = vi;
+            BrT + NF, BiT + NF, [&](int x, int m, float pr, float pi, float nr, float ni) {
+                Fr[(NF + m) * G * NN + x] = pr;
+                Fi[(NF + m) * G * NN + x] = pi;
+                if (m > 0) {
+                    Fr[(NF - m) * G * NN + x] = nr;
+                    Fi[(NF - m) * G * NN + x] = ni;
+                }
             });
         __syncthreads();
         // the group's rows of Phi[m1][m3][m2]: runs of g * nn values per m1

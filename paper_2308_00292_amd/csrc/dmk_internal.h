@@ -171,9 +171,9 @@ struct Plan {
 
     // device tables, FP64 and FP32 copies
     double *d_c2p = nullptr, *d_epw = nullptr, *d_ew = nullptr, *d_wd0 = nullptr,
-           *d_ww = nullptr, *d_gcheb = nullptr, *d_xcheb = nullptr, *d_bary = nullptr;
-    float *f_c2p = nullptr, *f_epw = nullptr, *f_wd0 = nullptr, *f_gcheb = nullptr, *f_xcheb = nullptr,
-          *f_bary = nullptr;
+           *d_ww = nullptr, *d_gcheb = nullptr, *d_gmono = nullptr, *d_xcheb = nullptr, *d_bary = nullptr;
+    float *f_c2p = nullptr, *f_epw = nullptr, *f_wd0 = nullptr, *f_gcheb = nullptr, *f_gmono = nullptr,
+          *f_xcheb = nullptr, *f_bary = nullptr;
 
     // eval workspace (element type: double for DMK_FP64, float for DMK_MIXED)
     double *qs = nullptr, *ufar = nullptr, *ures = nullptr, *rootscratch = nullptr;

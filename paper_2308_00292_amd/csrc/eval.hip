@@ -54,7 +54,7 @@ struct Dev {
         *anchor;
     const uint8_t *bflags;
     const double *bcenter;
-    const T *c2p, *epw, *wd0, *gcheb, *xcheb, *bary;  // tables in T
+    const T *c2p, *epw, *wd0, *gcheb, *gmono, *xcheb, *bary;  // tables in T
     const double *ew64, *ww64, *xcheb64, *bary64;     // FP64 tables
     T *proxy, *local, *phi, *psi, *w0vals;
     double *ufar, *ures, *rootscratch;
@@ -823,6 +823,19 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
     float *xc = Bz + P2, *bw = xc + P;
     float *work = bw + P;
     const int32_t B = list[blockIdx.x];
+    // the parent anchor's values, loaded first so that their latency overlaps
+    // the table set-up and the Lagrange rows
+    constexpr int NVP = (P3 + NT - 1) / NT;
+    float vpre[NVP];
+    const int32_t A = level > 0 ? D.anchor[D.parent[B]] : -1;
+    if (level > 0) {
+        const float *src = D.local + (int64_t)D.local_slot[A] * P3;
+#pragma unroll
+        for (int i = 0; i < NVP; ++i) {
+            const int t = threadIdx.x + i * NT;
+            vpre[i] = t < P3 ? src[t] : 0.f;
+        }
+    }
     for (int t = threadIdx.x; t < NN * P; t += NT) {
         Br1[t] = D.epw[2 * t];
         Bi1[t] = -D.epw[2 * t + 1];
@@ -858,7 +871,6 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
     } else {
         // interpolation from the anchor A of the parent: node i of B sits at
         // A-coordinate ((c_B + s_B x_i / 2) - c_A) * 2 / s_A
-        const int32_t A = D.anchor[D.parent[B]];
         const double sB = box_side(level), sA = box_side(D.blevel[A]);
         for (int t = threadIdx.x; t < 3 * P; t += NT) {
             const int d = t / P, i = t % P;
@@ -871,8 +883,11 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
             for (int a = 0; a < P; ++a) Bd[a * P + i] = row[a];
         }
         float *vA = work, *t1 = work + P3;
-        const float *src = D.local + (int64_t)D.local_slot[A] * P3;
-        for (int t = threadIdx.x; t < P3; t += NT) vA[t] = src[t];
+#pragma unroll
+        for (int i = 0; i < NVP; ++i) {
+            const int t = threadIdx.x + i * NT;
+            if (t < P3) vA[t] = vpre[i];
+        }
         __syncthreads();
         // x: t1[i0][(a1 a2)] = sum_a0 vA[a0][(a1 a2)] Mx[i0][a0]
         mma_real_store<NWV, P, P2, P, NAT>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
@@ -1190,9 +1205,13 @@ constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
 __device__ inline float rsq(float x) { return rsqrtf(x); }
 __device__ inline double rsq(double x) { return rsqrt(x); }
 
-// DEG: compile-time degree bucket of the Clenshaw sum (coefficients above
-// the plan's degree are zero, which leaves the recurrence's result unchanged);
-// the coefficients live in registers.
+// g(t) = Phi(sqrt t)/sqrt t is evaluated by Horner's rule in u = 2t - 1 from
+// its power-series coefficients in u (converted on the host from the
+// Chebyshev series).  The function is well conditioned in that basis: the
+// sum of |a_k| stays within 0.2 % of max |g| for tolerances 1e-3 .. 1e-12,
+// so Horner is as accurate as Clenshaw's recurrence at half its operations.
+// DEG: compile-time degree bucket (coefficients above the plan's degree are
+// zero, which leaves the result unchanged); the coefficients live in registers.
 template <typename T, int DEG>
 __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
                                                   const int32_t *nl_src, const int32_t *nl_pre)
@@ -1208,7 +1227,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     const int L = nl_off[blockIdx.x + 1] - l0;
     T gc[DEG + 1];
 #pragma unroll
-    for (int k = 0; k <= DEG; ++k) gc[k] = (k <= D.gdeg) ? D.gcheb[k] : T(0);
+    for (int k = 0; k <= DEG; ++k) gc[k] = (k <= D.gdeg) ? D.gmono[k] : T(0);
     // running source counts over the list (computed at plan time)
     for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
     __syncthreads();
@@ -1251,17 +1270,11 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T tt = r2 * sis2[j];
                 if (tt < T(1)) {
-                    // Clenshaw for g(t) = Phi(sqrt t)/sqrt t
+                    // Horner for g(t) = Phi(sqrt t)/sqrt t in u = 2t - 1
                     const T u = T(2) * tt - T(1);
-                    const T u2 = T(2) * u;
-                    T b1 = T(0), b2 = T(0);
+                    T g = gc[DEG];
 #pragma unroll
-                    for (int k = DEG; k >= 1; --k) {
-                        T b0 = gc[k] + u2 * b1 - b2;
-                        b2 = b1;
-                        b1 = b0;
-                    }
-                    const T g = gc[0] + u * b1 - b2;
+                    for (int k = DEG - 1; k >= 0; --k) g = g * u + gc[k];
                     const T rinv = (r2 > T(0)) ? rsq(r2) : T(0);
                     pacc += sq[j] * (rinv - g * sis[j]);
                 }
@@ -1565,6 +1578,7 @@ Dev<T> make_dev(Plan *P)
     D.epw = (const T *)(f64 ? (void *)P->d_epw : (void *)P->f_epw);
     D.wd0 = (const T *)(f64 ? (void *)P->d_wd0 : (void *)P->f_wd0);
     D.gcheb = (const T *)(f64 ? (void *)P->d_gcheb : (void *)P->f_gcheb);
+    D.gmono = (const T *)(f64 ? (void *)P->d_gmono : (void *)P->f_gmono);
     D.xcheb = (const T *)(f64 ? (void *)P->d_xcheb : (void *)P->f_xcheb);
     D.bary = (const T *)(f64 ? (void *)P->d_bary : (void *)P->f_bary);
     D.ew64 = P->d_ew; D.ww64 = P->d_ww; D.xcheb64 = P->d_xcheb; D.bary64 = P->d_bary;
@@ -1589,17 +1603,23 @@ void allow_lds(K kernel, size_t bytes)
 
 }  // namespace
 
-// residual sums with the Clenshaw degree rounded up to a compiled bucket
+// residual sums with the polynomial degree rounded up to a compiled bucket
 template <typename T>
 static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
 {
     const dim3 g((unsigned)Pl->nleaf), b(TPB);
-    if (D.gdeg <= 11)
+    if (D.gdeg <= 7)
+        hipLaunchKernelGGL((k_residual<T, 7>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 9)
+        hipLaunchKernelGGL((k_residual<T, 9>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 11)
         hipLaunchKernelGGL((k_residual<T, 11>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 13)
+        hipLaunchKernelGGL((k_residual<T, 13>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 15)
         hipLaunchKernelGGL((k_residual<T, 15>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
-    else if (D.gdeg <= 23)
-        hipLaunchKernelGGL((k_residual<T, 23>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 20)
+        hipLaunchKernelGGL((k_residual<T, 20>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else
         hipLaunchKernelGGL((k_residual<T, 47>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
 }
@@ -1805,6 +1825,29 @@ void run_eval(Plan *P, const double *charges, double *pot, double *far_part, dou
     }
 }
 
+
+// coefficients a_k of sum_k c_k T_k(u) = sum_k a_k u^k for k <= deg
+static std::vector<double> cheb_to_power(const std::vector<double> &c, int deg)
+{
+    if (c.empty()) return std::vector<double>(1, 0.0);  // no residual series (volume plans)
+    deg = std::max(0, std::min(deg, (int)c.size() - 1));
+    std::vector<double> a(deg + 1, 0.0), tm(deg + 1, 0.0), tk(deg + 1, 0.0), tp(deg + 1, 0.0);
+    tm[0] = 1.0;  // T_0
+    a[0] = c[0];
+    if (deg >= 1) {
+        tk[1] = 1.0;  // T_1 = u
+        a[1] += c[1];
+    }
+    for (int k = 1; k < deg; ++k) {
+        // T_{k+1} = 2u T_k - T_{k-1}
+        for (int i = 0; i <= deg; ++i) tp[i] = (i > 0 ? 2.0 * tk[i - 1] : 0.0) - tm[i];
+        for (int i = 0; i <= deg; ++i) a[i] += c[k + 1] * tp[i];
+        tm.swap(tk);
+        tk.swap(tp);
+    }
+    return a;
+}
+
 void upload_tables(Plan *P, hipStream_t s)
 {
     const Tables &t = P->tab;
@@ -1829,6 +1872,13 @@ void upload_tables(Plan *P, hipStream_t s)
     std::vector<double> gpad(t.gcheb);
     gpad.resize(std::max<size_t>(gpad.size(), 48), 0.0);  // room for a fixed number of terms
     P->d_gcheb = up(gpad);
+    // power-series coefficients in u of the series truncated at the FP64 and
+    // the FP32 degree (the residual kernels evaluate them by Horner's rule)
+    std::vector<double> gm64 = cheb_to_power(t.gcheb, t.gdeg), gm32 = cheb_to_power(t.gcheb, t.gdeg32);
+    gm64.resize(48, 0.0);
+    gm32.resize(48, 0.0);
+    P->d_gmono = up(gm64);
+    P->f_gmono = upf(gm32);
     P->d_xcheb = up(t.xcheb);
     P->d_bary = up(t.bary);
     P->f_c2p = upf(t.c2p);

@@ -1201,8 +1201,9 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
 constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
 
 // 1/sqrt in the working precision (the float overload is the hardware
-// reciprocal square root, about 1 ulp)
-__device__ inline float rsq(float x) { return rsqrtf(x); }
+// reciprocal square root, about 1 ulp, without the rescaling for denormal
+// arguments: r^2 > 0 here is a squared distance between distinct points)
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsq(double x) { return rsqrt(x); }
 
 // g(t) = Phi(sqrt t)/sqrt t is evaluated by Horner's rule in u = 2t - 1 from
@@ -1265,18 +1266,34 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
             }
             __syncthreads();
             T pacc = T(0);
-            for (int j = split; j < cnt && split < nsplit; j += nsplit) {
-                const T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const T tt = r2 * sis2[j];
-                if (tt < T(1)) {
-                    // Horner for g(t) = Phi(sqrt t)/sqrt t in u = 2t - 1
-                    const T u = T(2) * tt - T(1);
-                    T g = gc[DEG];
+            // RB candidates per round: their operands are read and tested
+            // together (independent LDS reads in flight), then the pairs in
+            // range are summed one by one
+            constexpr int RB = 4;
+            for (int j0 = split; j0 < cnt && split < nsplit; j0 += RB * nsplit) {
+                T r2v[RB], ttv[RB];
+                int jv[RB];
 #pragma unroll
-                    for (int k = DEG - 1; k >= 0; --k) g = g * u + gc[k];
-                    const T rinv = (r2 > T(0)) ? rsq(r2) : T(0);
-                    pacc += sq[j] * (rinv - g * sis[j]);
+                for (int u = 0; u < RB; ++u) {
+                    const int j = j0 + u * nsplit;
+                    jv[u] = j < cnt ? j : -1;
+                    const int jj = j < cnt ? j : j0;  // a valid slot for the spare lanes
+                    const T dx = xt - sx[jj], dy = yt - sy[jj], dz = zt - sz[jj];
+                    r2v[u] = dx * dx + dy * dy + dz * dz;
+                    ttv[u] = r2v[u] * sis2[jj];
+                }
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    if (jv[u] >= 0 && ttv[u] < T(1)) {
+                        const int j = jv[u];
+                        // Horner for g(t) = Phi(sqrt t)/sqrt t in u = 2t - 1
+                        const T uu = T(2) * ttv[u] - T(1);
+                        T g = gc[DEG];
+#pragma unroll
+                        for (int k = DEG - 1; k >= 0; --k) g = g * uu + gc[k];
+                        const T rinv = (r2v[u] > T(0)) ? rsq(r2v[u]) : T(0);
+                        pacc += sq[j] * (rinv - g * sis[j]);
+                    }
                 }
             }
             acc += (double)pacc;

@@ -581,118 +581,6 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
     }
 }
 
-// complex mode product Y = X B, X planar (Xr, Xi functors), B planar tables
-template <int NWV, int P, int NX, int NK, int NAT, typename XR, typename XI, typename SF>
-__device__ inline void mma_cplx_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
-{
-    constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float br[NAT][NKS], bi[NAT][NKS];
-#pragma unroll
-    for (int t = 0; t < NAT; ++t)
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq, a = 16 * t + r16;
-            const bool ok = k < NK && a < P;
-            br[t][s] = ok ? Br[k * P + a] : 0.f;
-            bi[t][s] = ok ? Bi[k * P + a] : 0.f;
-        }
-    for (int sl = w; sl < NSL; sl += NWV) {
-        const int xa = 16 * sl + r16;
-        f32x4 cr[NAT], ci[NAT];
-#pragma unroll
-        for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq;
-            const bool ok = xa < NX && k < NK;
-            const float ar = ok ? Xr(xa, k) : 0.f, ai = ok ? Xi(xa, k) : 0.f, nai = -ai;
-#pragma unroll
-            for (int t = 0; t < NAT; ++t) {
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[t][s], cr[t], 0, 0, 0);
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bi[t][s], cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[t][s], ci[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[t][s], ci[t], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < NAT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
-                if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
-            }
-    }
-}
-
-// complex mode product with X planar in global memory (row stride xs,
-// column k at k * ks): the next slab's operands are loaded while the current
-// slab's MFMAs run, to hide the HBM latency
-template <int NWV, int P, int NX, int NK, int NAT, typename SF>
-__device__ inline void mma_cplx_store_global(const float *Xr, const float *Xi, int64_t ks, const float *Br,
-                                             const float *Bi, SF store)
-{
-    constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float br[NAT][NKS], bi[NAT][NKS];
-#pragma unroll
-    for (int t = 0; t < NAT; ++t)
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq, a = 16 * t + r16;
-            const bool ok = k < NK && a < P;
-            br[t][s] = ok ? Br[k * P + a] : 0.f;
-            bi[t][s] = ok ? Bi[k * P + a] : 0.f;
-        }
-    float ar[NKS], ai[NKS];
-    auto fetch = [&](int sl, float (&fr)[NKS], float (&fi)[NKS]) {
-        const int xa = 16 * sl + r16;
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq;
-            const bool ok = sl < NSL && xa < NX && k < NK;
-            fr[s] = ok ? Xr[k * ks + xa] : 0.f;
-            fi[s] = ok ? Xi[k * ks + xa] : 0.f;
-        }
-    };
-    fetch(w, ar, ai);
-    for (int sl = w; sl < NSL; sl += NWV) {
-        float nr[NKS], ni[NKS];
-        fetch(sl + NWV, nr, ni);
-        f32x4 cr[NAT], ci[NAT];
-#pragma unroll
-        for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const float nai = -ai[s];
-#pragma unroll
-            for (int t = 0; t < NAT; ++t) {
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], br[t][s], cr[t], 0, 0, 0);
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai, bi[t][s], cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[s], bi[t][s], ci[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[s], br[t][s], ci[t], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < NAT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
-                if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
-            }
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) { ar[s] = nr[s]; ai[s] = ni[s]; }
-    }
-}
-
-// Plane-wave contraction over a full index m = -NF..NF with the conjugated
-// exponentials B[m][a] = conj(E[m][a]), E[-m] = conj(E[m]):
-//   sum_m B[m] X[m] = sum_{m >= 0} Br[m] s[m] + i Bi[m] d[m],
-//   s[m] = X[m] + X[-m], d[m] = X[m] - X[-m] (s[0] = X[0], d[0] = 0),
-// so that the complex product runs over NF + 1 values of m with the real
-// matrices Br, Bi:  Re Y = Br.Re s - Bi.Im d,  Im Y = Br.Im s + Bi.Re d.
-// Br, Bi point at the rows m = 0..NF (row stride P); X(x, k) takes the stored
-// index k = m + NF.  Half the matrix-core work of the plain complex product.
 template <int NWV, int P, int NX, int NF, int NAT, typename XR, typename XI, typename SF>
 __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
 {
@@ -742,70 +630,6 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
                 const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
                 if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
             }
-    }
-}
-
-// the same with X planar in global memory (element (x, k) at k * ks + x);
-// the next slab's operands are loaded while the current slab's MFMAs run
-template <int NWV, int P, int NX, int NF, int NAT, typename SF>
-__device__ inline void mma_herm_store_global(const float *Xr, const float *Xi, int64_t ks, const float *Br,
-                                             const float *Bi, SF store)
-{
-    constexpr int NH = NF + 1, NKS = (NH + 3) / 4, NSL = (NX + 15) / 16;
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float br[NAT][NKS], bi[NAT][NKS];
-#pragma unroll
-    for (int t = 0; t < NAT; ++t)
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq, a = 16 * t + r16;
-            const bool ok = k < NH && a < P;
-            br[t][s] = ok ? Br[k * P + a] : 0.f;
-            bi[t][s] = ok ? Bi[k * P + a] : 0.f;
-        }
-    // raw operands of a slab: X[+m] and X[-m], real and imaginary parts
-    float pr[NKS], pi[NKS], qr[NKS], qi[NKS];
-    auto fetch = [&](int sl, float (&fpr)[NKS], float (&fpi)[NKS], float (&fqr)[NKS], float (&fqi)[NKS]) {
-        const int xa = 16 * sl + r16;
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int m = 4 * s + kq;
-            const bool ok = sl < NSL && xa < NX && m < NH;
-            const bool okq = ok && m > 0;
-            fpr[s] = ok ? Xr[(NF + m) * ks + xa] : 0.f;
-            fpi[s] = ok ? Xi[(NF + m) * ks + xa] : 0.f;
-            fqr[s] = okq ? Xr[(NF - m) * ks + xa] : 0.f;
-            fqi[s] = okq ? Xi[(NF - m) * ks + xa] : 0.f;
-        }
-    };
-    fetch(w, pr, pi, qr, qi);
-    for (int sl = w; sl < NSL; sl += NWV) {
-        float npr[NKS], npi[NKS], nqr[NKS], nqi[NKS];
-        fetch(sl + NWV, npr, npi, nqr, nqi);
-        f32x4 cr[NAT], ci[NAT];
-#pragma unroll
-        for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            // at m = 0 the q operands are zero: s = X[0], d = X[0] (its Bi row is zero)
-            const float sr = pr[s] + qr[s], si = pi[s] + qi[s], dr = pr[s] - qr[s], ndi = qi[s] - pi[s];
-#pragma unroll
-            for (int t = 0; t < NAT; ++t) {
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[t][s], cr[t], 0, 0, 0);
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ndi, bi[t][s], cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[t][s], ci[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, bi[t][s], ci[t], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < NAT; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
-                if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
-            }
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) { pr[s] = npr[s]; pi[s] = npi[s]; qr[s] = nqr[s]; qi[s] = nqi[s]; }
     }
 }
 
@@ -907,7 +731,8 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
         float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
         __syncthreads();
         // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
-        mma_herm_store_global<NWV, P, NM, NF, NAT>(psr, psi, NM, Br1 + NF * P, Bi1 + NF * P,
+        mma_herm_store<NWV, P, NM, NF, NAT>([&](int x, int k) { return psr[k * NM + x]; },
+                                            [&](int x, int k) { return psi[k * NM + x]; }, Br1 + NF * P, Bi1 + NF * P,
                                                    [&](int x, int a, float vr, float vi) {
             A1r[a * NM + x] = vr;
             A1i[a * NM + x] = vi;

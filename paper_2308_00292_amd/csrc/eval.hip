@@ -504,7 +504,6 @@ struct LocalMfma {
     static constexpr int NSL = (P2 + 15) / 16;              // slabs of the p^2 x p outputs
     static constexpr int NWV = LOCAL_NT / 64, NT = LOCAL_NT;  // waves and threads per block
     static constexpr int NSW = (NSL + NWV - 1) / NWV;       // slabs per wave
-    static constexpr int NAT = (P + 15) / 16;               // column tiles of the new index
     static constexpr int G = 16 / (P % 16 == 0 ? 16 : (P % 8 == 0 ? 8 : (P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1))));
     static constexpr int KP = 2 * NH;                        // m3 real parts, then imaginary parts
     static constexpr int TAB = 2 * NN * P + KP * P + 3 * P2 + 2 * P;
@@ -514,122 +513,201 @@ struct LocalMfma {
     static size_t lds() { return sizeof(float) * (TAB + WORK); }
 };
 
-// real mode product into registers: acc[i][t] += sum_k X(x, k) B(k, a) for the
-// wave's slabs i (slab w + NWAVE i) and tiles t; Bt[k * P + a]
-template <int NWV, int P, int NX, int NK, int NSW, int NAT, typename XF>
-__device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][NAT])
+// Column split of a p-wide new index: 16-column MFMA tiles, and a remainder
+// of at most 4 columns (p = 18: columns 16, 17) done on the vector ALUs.  A
+// padded tile would spend a whole MFMA chain on those 2 columns (44 % of the
+// matrix-core work at p = 18); on the VALU they cost 2 FMAs per k step.
+template <int P>
+struct ColSplit {
+    static constexpr int REM = P % 16;
+    static constexpr int NATM = P / 16 + (REM > 4 ? 1 : 0);  // MFMA column tiles
+    static constexpr int NREM = REM > 4 ? 0 : REM;           // remainder columns on the VALU
+    static constexpr int NRA = NREM > 0 ? NREM : 1;          // array extent for them
+};
+
+// sum over the four k quarters of a fragment (lanes r16, r16+16, r16+32, r16+48)
+__device__ inline float kq_sum(float v)
 {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+// real mode product into registers: acc[i][t] += sum_k X(x, k) B(k, a) for the
+// wave's slabs i (slab w + NWV i) and tiles t; Bt[k * P + a].  The remainder
+// columns a = 16 NATM + j go to accr[i][j] for row 16 sl + r16 (the same value
+// in the four lanes of a row).
+template <int NWV, int P, int NX, int NK, int NSW, typename XF>
+__device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][ColSplit<P>::NATM],
+                                    float (&accr)[NSW][ColSplit<P>::NRA])
+{
+    constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float breg[NAT][NKS];
+    float breg[NATM][NKS], brem[NRA][NKS];
 #pragma unroll
-    for (int t = 0; t < NAT; ++t)
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kq;
 #pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq, a = 16 * t + r16;
+        for (int t = 0; t < NATM; ++t) {
+            const int a = 16 * t + r16;
             breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
         }
 #pragma unroll
+        for (int j = 0; j < NREM; ++j) brem[j][s] = (k < NK) ? Bt[k * P + 16 * NATM + j] : 0.f;
+    }
+#pragma unroll
     for (int i = 0; i < NSW; ++i) {
         const int sl = w + NWV * i;
-        if (sl >= NSL) break;
+        if (sl >= NSL) break;  // uniform in the wave
         const int xa = 16 * sl + r16;
+        float pr[NRA];
+#pragma unroll
+        for (int j = 0; j < NRA; ++j) pr[j] = 0.f;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
             const float av = (xa < NX && k < NK) ? X(xa, k) : 0.f;
 #pragma unroll
-            for (int t = 0; t < NAT; ++t)
+            for (int t = 0; t < NATM; ++t)
                 acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[i][t], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NREM; ++j) pr[j] += av * brem[j][s];
         }
+#pragma unroll
+        for (int j = 0; j < NREM; ++j) accr[i][j] += kq_sum(pr[j]);
     }
 }
 
 // real mode product with the result stored: Y(x, a) -> store(x, a, v)
-template <int NWV, int P, int NX, int NK, int NAT, typename XF, typename SF>
+template <int NWV, int P, int NX, int NK, typename XF, typename SF>
 __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
 {
+    constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float breg[NAT][NKS];
+    float breg[NATM][NKS], brem[NRA][NKS];
 #pragma unroll
-    for (int t = 0; t < NAT; ++t)
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kq;
 #pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq, a = 16 * t + r16;
+        for (int t = 0; t < NATM; ++t) {
+            const int a = 16 * t + r16;
             breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
         }
+#pragma unroll
+        for (int j = 0; j < NREM; ++j) brem[j][s] = (k < NK) ? Bt[k * P + 16 * NATM + j] : 0.f;
+    }
     for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
-        f32x4 acc[NAT];
+        f32x4 acc[NATM];
+        float pr[NRA];
 #pragma unroll
-        for (int t = 0; t < NAT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NATM; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < NRA; ++j) pr[j] = 0.f;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
             const float av = (xa < NX && k < NK) ? X(xa, k) : 0.f;
 #pragma unroll
-            for (int t = 0; t < NAT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[t], 0, 0, 0);
+            for (int t = 0; t < NATM; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[t], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < NREM; ++j) pr[j] += av * brem[j][s];
         }
 #pragma unroll
-        for (int t = 0; t < NAT; ++t)
+        for (int t = 0; t < NATM; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
                 if (x < NX && a < P) store(x, a, acc[t][i]);
             }
+#pragma unroll
+        for (int j = 0; j < NREM; ++j) {
+            const float v = kq_sum(pr[j]);
+            if (kq == 0 && xa < NX) store(xa, 16 * NATM + j, v);
+        }
     }
 }
 
-template <int NWV, int P, int NX, int NF, int NAT, typename XR, typename XI, typename SF>
+// Plane-wave contraction over a full index m = -NF..NF with the conjugated
+// exponentials B[m][a] = conj(E[m][a]), E[-m] = conj(E[m]):
+//   sum_m B[m] X[m] = sum_{m >= 0} Br[m] s[m] + i Bi[m] d[m],
+//   s[m] = X[m] + X[-m], d[m] = X[m] - X[-m] (s[0] = X[0], d[0] = 0),
+// so that the complex product runs over NF + 1 values of m with the real
+// matrices Br, Bi:  Re Y = Br.Re s - Bi.Im d,  Im Y = Br.Im s + Bi.Re d.
+// Br, Bi point at the rows m = 0..NF (row stride P); X(x, k) takes the stored
+// index k = m + NF.  Half the matrix-core work of the plain complex product.
+template <int NWV, int P, int NX, int NF, typename XR, typename XI, typename SF>
 __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
 {
+    constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int NH = NF + 1, NKS = (NH + 3) / 4, NSL = (NX + 15) / 16;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float br[NAT][NKS], bi[NAT][NKS];
+    float br[NATM][NKS], bi[NATM][NKS], rr[NRA][NKS], ri[NRA][NKS];
 #pragma unroll
-    for (int t = 0; t < NAT; ++t)
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kq;
 #pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            const int k = 4 * s + kq, a = 16 * t + r16;
+        for (int t = 0; t < NATM; ++t) {
+            const int a = 16 * t + r16;
             const bool ok = k < NH && a < P;
             br[t][s] = ok ? Br[k * P + a] : 0.f;
             bi[t][s] = ok ? Bi[k * P + a] : 0.f;
         }
+#pragma unroll
+        for (int j = 0; j < NREM; ++j) {
+            rr[j][s] = (k < NH) ? Br[k * P + 16 * NATM + j] : 0.f;
+            ri[j][s] = (k < NH) ? Bi[k * P + 16 * NATM + j] : 0.f;
+        }
+    }
     for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
-        f32x4 cr[NAT], ci[NAT];
+        f32x4 cr[NATM], ci[NATM];
+        float pr[NRA], pi[NRA];
 #pragma unroll
-        for (int t = 0; t < NAT; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NATM; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < NRA; ++j) pr[j] = pi[j] = 0.f;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int m = 4 * s + kq;
             float sr = 0.f, si = 0.f, dr = 0.f, di = 0.f;
             if (xa < NX && m < NH) {
-                const float pr = Xr(xa, NF + m), pi = Xi(xa, NF + m);
+                const float ar = Xr(xa, NF + m), ai = Xi(xa, NF + m);
                 if (m > 0) {
                     const float qr = Xr(xa, NF - m), qi = Xi(xa, NF - m);
-                    sr = pr + qr; si = pi + qi; dr = pr - qr; di = pi - qi;
+                    sr = ar + qr; si = ai + qi; dr = ar - qr; di = ai - qi;
                 } else {
-                    sr = pr; si = pi;
+                    sr = ar; si = ai;
                 }
             }
             const float ndi = -di;
 #pragma unroll
-            for (int t = 0; t < NAT; ++t) {
+            for (int t = 0; t < NATM; ++t) {
                 cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[t][s], cr[t], 0, 0, 0);
                 cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ndi, bi[t][s], cr[t], 0, 0, 0);
                 ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[t][s], ci[t], 0, 0, 0);
                 ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, bi[t][s], ci[t], 0, 0, 0);
             }
+#pragma unroll
+            for (int j = 0; j < NREM; ++j) {
+                pr[j] += sr * rr[j][s] + ndi * ri[j][s];
+                pi[j] += si * rr[j][s] + dr * ri[j][s];
+            }
         }
 #pragma unroll
-        for (int t = 0; t < NAT; ++t)
+        for (int t = 0; t < NATM; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
                 if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
             }
+#pragma unroll
+        for (int j = 0; j < NREM; ++j) {
+            const float vr = kq_sum(pr[j]), vi = kq_sum(pi[j]);
+            if (kq == 0 && xa < NX) store(xa, 16 * NATM + j, vr, vi);
+        }
     }
 }
 
@@ -637,7 +715,8 @@ template <int P, int NF>
 __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const int32_t *list, int level)
 {
     using L = LocalMfma<P, NF>;
-    constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, NSW = L::NSW, NAT = L::NAT;
+    constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, NSW = L::NSW;
+    constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int G = L::G, KP = L::KP, NSL = L::NSL, NWV = L::NWV, NT = L::NT;
     extern __shared__ unsigned char smraw[];
     float *sm = reinterpret_cast<float *>(smraw);
@@ -671,11 +750,17 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
         B3[t] = cm * ((k < NH) ? e[0] : e[1]);
     }
     for (int t = threadIdx.x; t < P; t += NT) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
-    f32x4 acc[NSW][NAT];
+    // the box's values: columns j3 < 16 NATM in MFMA fragments, the last
+    // NREM columns in accr (row 16 sl + r16, the same in the row's four lanes)
+    f32x4 acc[NSW][NATM];
+    float accr[NSW][NRA];
 #pragma unroll
-    for (int i = 0; i < NSW; ++i)
+    for (int i = 0; i < NSW; ++i) {
 #pragma unroll
-        for (int t = 0; t < NAT; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NATM; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < NRA; ++j) accr[i][j] = 0.f;
+    }
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
     __syncthreads();
     if (level == 0) {
@@ -685,12 +770,15 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
             const int sl = w + NWV * i;
             if (sl >= NSL) break;
 #pragma unroll
-            for (int t = 0; t < NAT; ++t)
+            for (int t = 0; t < NATM; ++t)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
                     if (x < P2 && a < P) acc[i][t][q] = D.w0vals[x * P + a];
                 }
+            const int xa = 16 * sl + r16;
+#pragma unroll
+            for (int j = 0; j < NREM; ++j) accr[i][j] = (xa < P2) ? D.w0vals[xa * P + 16 * NATM + j] : 0.f;
         }
     } else {
         // interpolation from the anchor A of the parent: node i of B sits at
@@ -714,16 +802,16 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
         }
         __syncthreads();
         // x: t1[i0][(a1 a2)] = sum_a0 vA[a0][(a1 a2)] Mx[i0][a0]
-        mma_real_store<NWV, P, P2, P, NAT>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
+        mma_real_store<NWV, P, P2, P>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
                                       [&](int x, int a, float v) { t1[a * P2 + x] = v; });
         __syncthreads();
         // y: t2[i0][i1][a2] = sum_a1 t1[i0][a1][a2] My[i1][a1]; rows x = (i0, a2)
         float *t2 = vA;
-        mma_real_store<NWV, P, P2, P, NAT>([&](int x, int k) { return t1[(x / P) * P2 + k * P + (x % P)]; }, By,
+        mma_real_store<NWV, P, P2, P>([&](int x, int k) { return t1[(x / P) * P2 + k * P + (x % P)]; }, By,
                                       [&](int x, int a, float v) { t2[(x / P) * P2 + a * P + (x % P)] = v; });
         __syncthreads();
         // z: acc[(i0 i1)][i2] = sum_a2 t2[(i0 i1)][a2] Mz[i2][a2]
-        mma_real_acc<NWV, P, P2, P, NSW, NAT>([&](int x, int k) { return t2[x * P + k]; }, Bz, acc);
+        mma_real_acc<NWV, P, P2, P, NSW>([&](int x, int k) { return t2[x * P + k]; }, Bz, acc, accr);
     }
     if (D.psi_slot[B] >= 0) {
         const int64_t nm = D.pwstride;
@@ -731,7 +819,7 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
         float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
         __syncthreads();
         // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
-        mma_herm_store<NWV, P, NM, NF, NAT>([&](int x, int k) { return psr[k * NM + x]; },
+        mma_herm_store<NWV, P, NM, NF>([&](int x, int k) { return psr[k * NM + x]; },
                                             [&](int x, int k) { return psi[k * NM + x]; }, Br1 + NF * P, Bi1 + NF * P,
                                                    [&](int x, int a, float vr, float vi) {
             A1r[a * NM + x] = vr;
@@ -742,7 +830,7 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
             const int g = min(G, P - g0);
             __syncthreads();
             // m2: B2[(j1 j2)][m3 | NH + m3] = sum_m2 conj(E[m2][j2]) A1[j1][m3][m2]; rows x = (j1 - g0, m3)
-            mma_herm_store<NWV, P, G * NH, NF, NAT>(
+            mma_herm_store<NWV, P, G * NH, NF>(
                 [&](int x, int k) { return (x < g * NH) ? A1r[(g0 * NH + x) * NN + k] : 0.f; },
                 [&](int x, int k) { return (x < g * NH) ? A1i[(g0 * NH + x) * NN + k] : 0.f; }, Br1 + NF * P,
                 Bi1 + NF * P,
@@ -756,28 +844,39 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
             __syncthreads();
             // m3: acc[(j1 j2)][j3] += sum_k' B2[(j1 j2)][k'] B3[k'][j3] for the slabs of this group
             constexpr int NKS = (KP + 3) / 4;
-            float breg[NAT][NKS];
+            float breg[NATM][NKS], brem[NRA][NKS];
 #pragma unroll
-            for (int t = 0; t < NAT; ++t)
+            for (int s = 0; s < NKS; ++s) {
+                const int k = 4 * s + kq;
 #pragma unroll
-                for (int s = 0; s < NKS; ++s) {
-                    const int k = 4 * s + kq, a = 16 * t + r16;
+                for (int t = 0; t < NATM; ++t) {
+                    const int a = 16 * t + r16;
                     breg[t][s] = (k < KP && a < P) ? B3[k * P + a] : 0.f;
                 }
+#pragma unroll
+                for (int j = 0; j < NREM; ++j) brem[j][s] = (k < KP) ? B3[k * P + 16 * NATM + j] : 0.f;
+            }
             const int r0 = g0 * P, r1 = (g0 + g) * P;  // rows of this group, multiples of 16 at r0
 #pragma unroll
             for (int i = 0; i < NSW; ++i) {
                 const int sl = w + NWV * i;
-                if (sl >= NSL || 16 * sl < r0 || 16 * sl >= r1) continue;
+                if (sl >= NSL || 16 * sl < r0 || 16 * sl >= r1) continue;  // uniform in the wave
                 const int xa = 16 * sl + r16;
+                float pr[NRA];
+#pragma unroll
+                for (int j = 0; j < NRA; ++j) pr[j] = 0.f;
 #pragma unroll
                 for (int s = 0; s < NKS; ++s) {
                     const int k = 4 * s + kq;
                     const float av = (xa < r1 && k < KP) ? B2[(xa - r0) * KP + k] : 0.f;
 #pragma unroll
-                    for (int t = 0; t < NAT; ++t)
+                    for (int t = 0; t < NATM; ++t)
                         acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[i][t], 0, 0, 0);
+#pragma unroll
+                    for (int j = 0; j < NREM; ++j) pr[j] += av * brem[j][s];
                 }
+#pragma unroll
+                for (int j = 0; j < NREM; ++j) accr[i][j] += kq_sum(pr[j]);
             }
         }
     }
@@ -787,12 +886,16 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
         const int sl = w + NWV * i;
         if (sl >= NSL) break;
 #pragma unroll
-        for (int t = 0; t < NAT; ++t)
+        for (int t = 0; t < NATM; ++t)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
                 if (x < P2 && a < P) dst[x * P + a] = acc[i][t][q];
             }
+        const int xa = 16 * sl + r16;
+#pragma unroll
+        for (int j = 0; j < NREM; ++j)
+            if (kq == 0 && xa < P2) dst[xa * P + 16 * NATM + j] = accr[i][j];
     }
 }
 
@@ -894,7 +997,7 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
     for (int t = threadIdx.x; t < P3; t += P2PW_NT) r0[t] = src[t];
     __syncthreads();
     // j3 -> m3 (real rho times the real and imaginary rows)
-    mma_real_store<P2PW_NT / 64, W1, P2, P, (W1 + 15) / 16>([&](int x, int k) { return r0[x * P + k]; }, B1,
+    mma_real_store<P2PW_NT / 64, W1, P2, P>([&](int x, int k) { return r0[x * P + k]; }, B1,
                                               [&](int x, int a, float v) { A[x * W1 + a] = v; });
     const int64_t nm = D.pwstride;
     float *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;

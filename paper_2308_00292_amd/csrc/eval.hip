@@ -62,9 +62,11 @@ struct Dev {
 };
 
 // ------------------------------------------------------------------ upward
+// points per anterpolation chunk: three Lagrange rows per point in the
+// kernel's work area of 2 p^3 values
 template <int P> constexpr int up_chunk()
 {
-    return (2 * P * P * P) / (4 * P + P * P + 1) < 64 ? (2 * P * P * P) / (4 * P + P * P + 1) : 64;
+    return (2 * P * P * P) / (3 * P) < 128 ? (2 * P * P * P) / (3 * P) : 128;
 }
 
 template <typename T, int P>
@@ -72,6 +74,7 @@ __global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
 {
     constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
     constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, CH = up_chunk<P>();
+    constexpr int MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;  // tile grid of the p x p^2 accumulator
     extern __shared__ unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *Am = sm;              // 2 p^2 child->parent matrices
@@ -88,6 +91,12 @@ __global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
         for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
     const double *cP = D.bcenter + 3 * (int64_t)Pb;
     const double sc = 2.0 / box_side(D.blevel[Pb]);
+    // the leaf children's point ranges, concatenated (their anterpolation does
+    // not depend on the child: every point goes onto the parent's grid)
+    __shared__ int64_t rlo[8];
+    __shared__ int roff[9];
+    int nr = 0, npts = 0;
+    if (threadIdx.x == 0) roff[0] = 0;
     __syncthreads();
     for (int k = 0; k < 8; ++k) {
         const int32_t C = D.child0[Pb] + k;
@@ -110,31 +119,76 @@ __global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
             // x: acc[a0][r] += sum_i0 Ax[a0][i0] t2[i0][r]
             gemm_regs<T, RM, RN>(P, P2, P, Ax, P, 1, t2, P2, 1, acc);
         } else {
-            // anterpolate the child's points onto the parent grid:
-            // rho[a0][(a1 a2)] += sum_pt Lx[pt][a0] (Ly[pt][a1] Lz[pt][a2] q[pt])
-            T *Lx = w0, *Ly = Lx + CH * P, *Lz = Ly + CH * P, *W = Lz + CH * P, *qq = W + CH * P2;
-            const int64_t i0 = D.pstart[C];
-            for (int base = 0; base < cnt; base += CH) {
-                const int m = min(CH, cnt - base);
-                __syncthreads();
-                for (int t = threadIdx.x; t < 3 * m; t += TPB) {
-                    int pt = t / 3, d = t % 3;
-                    int64_t i = i0 + base + pt;
-                    double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
-                    T row[P];
-                    lagrange_row<T>(P, xc, bw, (T)((x - cP[d]) * sc), row);
-                    T *dst = (d == 0 ? Lx : d == 1 ? Ly : Lz) + pt * P;
+            if (threadIdx.x == 0) {
+                rlo[nr] = D.pstart[C];
+                roff[nr + 1] = npts + cnt;
+            }
+            npts += cnt;
+            ++nr;
+        }
+    }
+    // anterpolate the leaf children's points onto the parent grid:
+    // rho[a0][(a1 a2)] += sum_pt Lx[pt][a0] Ly[pt][a1] (Lz[pt][a2] q[pt]),
+    // the product Ly Lz q formed per k step for the thread's columns
+    if (npts > 0) {
+        static_assert(NT % P == 0, "column tiles step whole rows of the p x p block");
+        T *Lx = w0, *Ly = Lx + CH * P, *Lzq = Ly + CH * P;
+        const int t = threadIdx.x;
+        const bool own = t < MT * NT;
+        const int mt = own ? t / NT : 0, nt = own ? t % NT : 0;
+        // column n = nt + j NT of the thread is (a1, a2) = (nt / P + j NT / P, nt % P)
+        const int c10 = nt / P, c2 = nt % P;
+        for (int base = 0; base < npts; base += CH) {
+            const int m = min(CH, npts - base);
+            __syncthreads();
+            for (int u = threadIdx.x; u < 3 * m; u += TPB) {
+                const int pt = u / 3, d = u % 3;
+                const int v = base + pt;
+                int r = 0;
+                while (v >= roff[r + 1]) ++r;
+                const int64_t i = rlo[r] + (v - roff[r]);
+                const double x = (d == 0) ? D.X[i] : (d == 1) ? D.Y[i] : D.Z[i];
+                T row[P];
+                lagrange_row<T>(P, xc, bw, (T)((x - cP[d]) * sc), row);
+                const T f = (d == 2) ? (T)D.qs[i] : T(1);
+                T *dst = (d == 0 ? Lx : d == 1 ? Ly : Lzq) + pt * P;
 #pragma unroll
-                    for (int a = 0; a < P; ++a) dst[a] = row[a];
+                for (int a = 0; a < P; ++a) dst[a] = row[a] * f;
+            }
+            __syncthreads();
+            if (own) {
+                // partial sums over runs of up to 32 points, then added to acc
+                // (shorter running sums: these charges cancel heavily)
+                for (int k0 = 0; k0 < m; k0 += 32) {
+                    T part[RM][RN];
+#pragma unroll
+                    for (int i = 0; i < RM; ++i)
+#pragma unroll
+                        for (int j = 0; j < RN; ++j) part[i][j] = T(0);
+                    const int k1 = min(m, k0 + 32);
+                    for (int k = k0; k < k1; ++k) {
+                        T a[RM], bb[RN];
+#pragma unroll
+                        for (int i = 0; i < RM; ++i) {
+                            const int mm = mt + i * MT;
+                            a[i] = (mm < P) ? Lx[k * P + mm] : T(0);
+                        }
+                        const T lz = Lzq[k * P + c2];
+#pragma unroll
+                        for (int j = 0; j < RN; ++j) {
+                            const int c1 = c10 + j * (NT / P);
+                            bb[j] = (c1 < P) ? Ly[k * P + c1] * lz : T(0);
+                        }
+#pragma unroll
+                        for (int i = 0; i < RM; ++i)
+#pragma unroll
+                            for (int j = 0; j < RN; ++j) part[i][j] += a[i] * bb[j];
+                    }
+#pragma unroll
+                    for (int i = 0; i < RM; ++i)
+#pragma unroll
+                        for (int j = 0; j < RN; ++j) acc[i][j] += part[i][j];
                 }
-                for (int t = threadIdx.x; t < m; t += TPB) qq[t] = (T)D.qs[i0 + base + t];
-                __syncthreads();
-                for (int t = threadIdx.x; t < m * P2; t += TPB) {
-                    int pt = t / P2, c = t % P2;
-                    W[t] = Ly[pt * P + c / P] * Lz[pt * P + c % P] * qq[pt];
-                }
-                __syncthreads();
-                gemm_regs<T, RM, RN>(P, P2, m, Lx, 1, P, W, P2, 1, acc);
             }
         }
     }

@@ -692,7 +692,9 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
 // matrices Br, Bi:  Re Y = Br.Re s - Bi.Im d,  Im Y = Br.Im s + Bi.Re d.
 // Br, Bi point at the rows m = 0..NF (row stride P); X(x, k) takes the stored
 // index k = m + NF.  Half the matrix-core work of the plain complex product.
-template <int NWV, int P, int NX, int NF, typename XR, typename XI, typename SF>
+// PF: the operands of the wave's next slab are loaded before the current
+// slab's products (for X in global memory: hides the load latency).
+template <int NWV, int P, int NX, int NF, bool PF, typename XR, typename XI, typename SF>
 __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
 {
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
@@ -715,28 +717,36 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
             ri[j][s] = (k < NH) ? Bi[k * P + 16 * NATM + j] : 0.f;
         }
     }
-    for (int sl = w; sl < NSL; sl += NWV) {
+    // raw operands X[+m], X[-m] of a slab (X[-0] = 0: then s = d = X[0], and
+    // the Bi row of m = 0 is zero, so d drops out there)
+    auto fetch = [&](int sl, float (&fpr)[NKS], float (&fpi)[NKS], float (&fqr)[NKS], float (&fqi)[NKS]) {
         const int xa = 16 * sl + r16;
-        f32x4 cr[NATM], ci[NATM];
-        float pr[NRA], pi[NRA];
-#pragma unroll
-        for (int t = 0; t < NATM; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < NRA; ++j) pr[j] = pi[j] = 0.f;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int m = 4 * s + kq;
-            float sr = 0.f, si = 0.f, dr = 0.f, di = 0.f;
-            if (xa < NX && m < NH) {
-                const float ar = Xr(xa, NF + m), ai = Xi(xa, NF + m);
-                if (m > 0) {
-                    const float qr = Xr(xa, NF - m), qi = Xi(xa, NF - m);
-                    sr = ar + qr; si = ai + qi; dr = ar - qr; di = ai - qi;
-                } else {
-                    sr = ar; si = ai;
-                }
-            }
-            const float ndi = -di;
+            const bool ok = sl < NSL && xa < NX && m < NH, okq = ok && m > 0;
+            fpr[s] = ok ? Xr(xa, NF + m) : 0.f;
+            fpi[s] = ok ? Xi(xa, NF + m) : 0.f;
+            fqr[s] = okq ? Xr(xa, NF - m) : 0.f;
+            fqi[s] = okq ? Xi(xa, NF - m) : 0.f;
+        }
+    };
+    float pr[NKS], pi[NKS], qr[NKS], qi[NKS];
+    if (PF) fetch(w, pr, pi, qr, qi);
+    for (int sl = w; sl < NSL; sl += NWV) {
+        const int xa = 16 * sl + r16;
+        float npr[NKS], npi[NKS], nqr[NKS], nqi[NKS];
+        if (PF) fetch(sl + NWV, npr, npi, nqr, nqi);
+        else fetch(sl, pr, pi, qr, qi);
+        f32x4 cr[NATM], ci[NATM];
+        float ar[NRA], ai[NRA];
+#pragma unroll
+        for (int t = 0; t < NATM; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < NRA; ++j) ar[j] = ai[j] = 0.f;
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            const float sr = pr[s] + qr[s], si = pi[s] + qi[s], dr = pr[s] - qr[s], ndi = qi[s] - pi[s];
 #pragma unroll
             for (int t = 0; t < NATM; ++t) {
                 cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[t][s], cr[t], 0, 0, 0);
@@ -746,8 +756,8 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
             }
 #pragma unroll
             for (int j = 0; j < NREM; ++j) {
-                pr[j] += sr * rr[j][s] + ndi * ri[j][s];
-                pi[j] += si * rr[j][s] + dr * ri[j][s];
+                ar[j] += sr * rr[j][s] + ndi * ri[j][s];
+                ai[j] += si * rr[j][s] + dr * ri[j][s];
             }
         }
 #pragma unroll
@@ -759,8 +769,12 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
             }
 #pragma unroll
         for (int j = 0; j < NREM; ++j) {
-            const float vr = kq_sum(pr[j]), vi = kq_sum(pi[j]);
+            const float vr = kq_sum(ar[j]), vi = kq_sum(ai[j]);
             if (kq == 0 && xa < NX) store(xa, 16 * NATM + j, vr, vi);
+        }
+        if (PF) {
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) { pr[s] = npr[s]; pi[s] = npi[s]; qr[s] = nqr[s]; qi[s] = nqi[s]; }
         }
     }
 }
@@ -873,7 +887,7 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
         float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
         __syncthreads();
         // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
-        mma_herm_store<NWV, P, NM, NF>([&](int x, int k) { return psr[k * NM + x]; },
+        mma_herm_store<NWV, P, NM, NF, true>([&](int x, int k) { return psr[k * NM + x]; },
                                             [&](int x, int k) { return psi[k * NM + x]; }, Br1 + NF * P, Bi1 + NF * P,
                                                    [&](int x, int a, float vr, float vi) {
             A1r[a * NM + x] = vr;
@@ -884,7 +898,7 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
             const int g = min(G, P - g0);
             __syncthreads();
             // m2: B2[(j1 j2)][m3 | NH + m3] = sum_m2 conj(E[m2][j2]) A1[j1][m3][m2]; rows x = (j1 - g0, m3)
-            mma_herm_store<NWV, P, G * NH, NF>(
+            mma_herm_store<NWV, P, G * NH, NF, false>(
                 [&](int x, int k) { return (x < g * NH) ? A1r[(g0 * NH + x) * NN + k] : 0.f; },
                 [&](int x, int k) { return (x < g * NH) ? A1i[(g0 * NH + x) * NN + k] : 0.f; }, Br1 + NF * P,
                 Bi1 + NF * P,

@@ -1492,8 +1492,11 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
     const double sc = 2.0 / box_side(D.blevel[A]);
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
     __syncthreads();
-    for (int base = b0; base < b1; base += 16 * NWAVE) {
-        const int t = base + 16 * w + r16;
+    // each wave takes its own groups of 16 targets (the Lagrange rows in LDS
+    // are per wave, so no block barrier is needed past the set-up), and a
+    // wave with no targets left stops instead of running empty products
+    for (int base = b0 + 16 * w; base < b1; base += 16 * NWAVE) {
+        const int t = base + r16;
         const bool tv = t < b1;
         if (kq < 3) {
             float row[P];
@@ -1508,7 +1511,11 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
 #pragma unroll
             for (int j = 0; j < P; ++j) Lr[w][kq][r16][j] = row[j];
         }
-        __syncthreads();
+        // the wave's LDS writes above precede its reads below (one wave's LDS
+        // operations complete in order; this keeps the compiler from moving them)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float bz[NKS];
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
@@ -1552,7 +1559,10 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
         if (kq == 0 && tv) D.ufar[tgt[t]] = (double)part;
-        __syncthreads();
+        // this round's reads of Lr[w] precede the next round's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 

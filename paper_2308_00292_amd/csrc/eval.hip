@@ -1191,9 +1191,11 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
 // -------------------------------------------------------------- residual
 // One workgroup per target leaf.  The sources of the leaf's whole gather list
 // are staged in LDS (offsets from the leaf centre formed in FP64 and rounded
-// to T once per point, with 1/s and 1/s^2 of the source box level); each
-// thread then sums one target against a stride of the staged sources, and
-// the per-pass partial sums are added into an FP64 accumulator.
+// to T once per point, with 1/s of the source box level, a power of two, so
+// t = r^2 (1/s)^2 is formed exactly in the loop); each thread then sums one
+// target against a stride of the staged sources, and the per-pass partial
+// sums are added into an FP64 accumulator.  Five staged arrays keep the LDS
+// of a block under 27 KB, so that six blocks fit on a CU.
 constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
 
 // 1/sqrt in the working precision (the float overload is the hardware
@@ -1214,7 +1216,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                                                   const int32_t *nl_src, const int32_t *nl_pre)
 {
     constexpr int RCAP = sizeof(T) == 8 ? 512 : 1024;  // sources staged per pass
-    __shared__ T sx[RCAP], sy[RCAP], sz[RCAP], sq[RCAP], sis[RCAP], sis2[RCAP];
+    __shared__ T sx[RCAP], sy[RCAP], sz[RCAP], sq[RCAP], sis[RCAP];  // 1/s of the source box
     __shared__ int32_t loff[RLIST + 1];
     __shared__ double part[TPB];
     const int32_t B = leaves[blockIdx.x];
@@ -1258,7 +1260,6 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                 sz[idx] = (T)(D.Z[j] - cz);
                 sq[idx] = (T)D.qs[j];
                 sis[idx] = (T)ldexp(1.0, lev);
-                sis2[idx] = (T)ldexp(1.0, 2 * lev);
             }
             __syncthreads();
             T pacc = T(0);
@@ -1276,7 +1277,8 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                     const int jj = j < cnt ? j : j0;  // a valid slot for the spare lanes
                     const T dx = xt - sx[jj], dy = yt - sy[jj], dz = zt - sz[jj];
                     r2v[u] = dx * dx + dy * dy + dz * dz;
-                    ttv[u] = r2v[u] * sis2[jj];
+                    const T is = sis[jj];
+                    ttv[u] = r2v[u] * is * is;
                 }
 #pragma unroll
                 for (int u = 0; u < RB; ++u) {

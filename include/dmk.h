@@ -396,8 +396,9 @@ typedef void (*dmk_density_fn)(int64_t n, const double *xyz, double *out, void *
  *             contains (x, y, z) (lo <= x < hi per axis) is split while its
  *             side exceeds h > 0; nfeat may be 0 (feat NULL).
  *  opts       precision: DMK_FP64, or DMK_MIXED (the far-field transforms
- *             in FP32 as in the point code, the near field and all sums in
- *             FP64); leaf_max, max_depth, lambda ignored; NULL for defaults.
+ *             and the near-field factor products in FP32, the asymptotic
+ *             part and the final sums in FP64); leaf_max, max_depth, lambda
+ *             ignored; NULL for defaults.
  *  stream     for the device work; returns after it completes.
  * The plan holds at most 2^31 - 1 nodes (nleaf q^3).  Free with
  * dmk_plan_destroy.  A volume plan is evaluated with dmk_vol_eval only.

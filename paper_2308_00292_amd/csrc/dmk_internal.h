@@ -98,6 +98,7 @@ struct VolData {
     int32_t *d_kng = nullptr;            // [nkey] Gaussians of the class
     int64_t *d_kbase = nullptr;          // [nkey] first Gaussian of the class
     double *d_gtab = nullptr;            // [ngauss][q][q]
+    float *f_gtab = nullptr;             // FP32 copy for mixed-precision plans
     double *d_gw = nullptr;              // [ngauss] quadrature weight of the Gaussian
     int64_t nkey = 0, ngauss_tab = 0;
     // work counts gathered at plan time

@@ -406,10 +406,10 @@ struct VolLds {
     static constexpr int NB = 6;  // source densities staged per batch
     // NB source blocks, then a [q^2][q+1] regrouping buffer per wave; the
     // epilogue reuses them for the partial sums and the Laplacians
-    static size_t near()
+    static size_t near(size_t el)
     {
-        const size_t main = NB * Q3 + JB * Q * Q * (Q + 1), epi = JB * Q3 + 3 * Q3 + Q * Q;
-        return sizeof(double) * (main > epi ? main : epi);
+        const size_t main = el * (NB * Q3 + JB * Q * Q * (Q + 1)), epi = sizeof(double) * (JB * Q3 + 3 * Q3 + Q * Q);
+        return main > epi ? main : epi;
     }
 };
 
@@ -580,6 +580,12 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
     if (a == 0) gw[g] = 2.0 / sqrt(M_PI) * tj * 0.5 * hp * tglw[gi];
 }
 
+__global__ void __launch_bounds__(TPB) k_vol_tof32(const double *src, float *dst, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
 // Near field of each target leaf: for every source leaf T of its gather list
 // that survives the pruning, sum over the class's Gaussians of
 // s_T^2 w_j (G_x (x) G_y (x) G_z) rho_T, then the asymptotic part from the
@@ -599,29 +605,31 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
 template <int Q>
 constexpr int vol_near_threads = Q * Q * 5;  // q^2 rows times the Gaussians of one panel
 
-template <int Q>
+// T: precision of the factor products and their sums (FP64, or FP32 for
+// mixed-precision plans); the asymptotic part and the output stay FP64.
+template <typename T, int Q>
 __global__ void __launch_bounds__(vol_near_threads<Q>)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
                const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pk, const int32_t *__restrict__ kng,
-               const int64_t *__restrict__ kbase, const double *__restrict__ gtab, const double *__restrict__ gw)
+               const int64_t *__restrict__ kbase, const T *__restrict__ gtab, const double *__restrict__ gw)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NB = VolLds<18, Q>::NB, RS = Q + 1,
                   NT = JB * Q2;
     static_assert(NT == vol_near_threads<Q> && Q2 == 64, "one wavefront per Gaussian, one lane per row");
     extern __shared__ double vsm[];
-    double *slot = vsm;                 // [NB][q^3] source densities
-    double *wb = slot + NB * Q3;        // per wave: [q^2][RS] regrouping buffer
+    T *slot = reinterpret_cast<T *>(vsm);  // [NB][q^3] source densities
+    T *wb = slot + NB * Q3;                // per wave: [q^2][RS] regrouping buffer
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid / Q2);  // wave = Gaussian of the panel
     const int L = tid % Q2;
-    double *buf = wb + w * Q2 * RS;
+    T *buf = wb + w * Q2 * RS;
     const int64_t li = blockIdx.x;
     const int32_t B = leaves[li];
     const int32_t vB = D.box2v[B];
     const double sB = ldexp(1.0, -D.blevel[B]);
-    double acc[Q];  // lane (a b): acc[c]
+    T acc[Q];  // lane (a b): acc[c]
 #pragma unroll
-    for (int c = 0; c < Q; ++c) acc[c] = 0.0;
+    for (int c = 0; c < Q; ++c) acc[c] = T(0);
     const int eend = nl_off[li + 1];
     for (int e = nl_off[li]; e < eend;) {
         if (pk[4 * (int64_t)e] < 0) break;  // pruned entries come last
@@ -636,72 +644,72 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
         const int ng = kng[kx0];
         for (int j0 = 0; j0 < ng; j0 += JB) {
             const int64_t j = j0 + w;
-            const double wj = gw[kbase[kx0] + j] * sT * sT;
-            double xa[Q], ya[Q];  // lane (i1 i2): xa[a]; lane (a i2): ya[b]
+            const T wj = (T)(gw[kbase[kx0] + j] * sT * sT);
+            T xa[Q], ya[Q];  // lane (i1 i2): xa[a]; lane (a i2): ya[b]
 #pragma unroll
-            for (int k = 0; k < Q; ++k) xa[k] = ya[k] = 0.0;
+            for (int k = 0; k < Q; ++k) xa[k] = ya[k] = T(0);
             for (int b0 = e; b0 < ez; b0 += NB) {
                 const int nb = min(NB, ez - b0);
                 __syncthreads();
                 for (int t = tid; t < nb * Q3; t += NT) {
                     const int sidx = t / Q3;
-                    slot[t] = D.rho[(int64_t)D.box2v[nl_src[b0 + sidx]] * Q3 + t % Q3];
+                    slot[t] = (T)D.rho[(int64_t)D.box2v[nl_src[b0 + sidx]] * Q3 + t % Q3];
                 }
                 __syncthreads();
                 for (int sidx = 0; sidx < nb; ++sidx) {
                     const int64_t es = b0 + sidx;
                     // x: xa[a] += sum_i0 G_x[a][i0] rho[i0][(i1 i2)]
-                    const double *gx = gtab + (kbase[pk[4 * es]] + j) * Q2;
-                    const double *rs = slot + sidx * Q3;
-                    double r[Q];
+                    const T *gx = gtab + (kbase[pk[4 * es]] + j) * Q2;
+                    const T *rs = slot + sidx * Q3;
+                    T r[Q];
 #pragma unroll
                     for (int i0 = 0; i0 < Q; ++i0) r[i0] = rs[i0 * Q2 + L];
 #pragma unroll
                     for (int a = 0; a < Q; ++a) {
-                        double s = 0.0;
+                        T s = T(0);
 #pragma unroll
                         for (int i0 = 0; i0 < Q; ++i0) s += gx[a * Q + i0] * r[i0];
                         xa[a] += s;
                     }
                     if (pk[4 * es + 3] & 1) {
                         // end of a (y, z) group: ya[b] += sum_i1 G_y[b][i1] X[a][i1][i2]
-                        const double *gy = gtab + (kbase[pk[4 * es + 1]] + j) * Q2;
+                        const T *gy = gtab + (kbase[pk[4 * es + 1]] + j) * Q2;
 #pragma unroll
                         for (int a = 0; a < Q; ++a) buf[L * RS + a] = xa[a];
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         __builtin_amdgcn_wave_barrier();
                         const int a = L / Q, i2 = L % Q;
-                        double y[Q];
+                        T y[Q];
 #pragma unroll
                         for (int i1 = 0; i1 < Q; ++i1) y[i1] = buf[(i1 * Q + i2) * RS + a];
 #pragma unroll
                         for (int bb = 0; bb < Q; ++bb) {
-                            double s = 0.0;
+                            T s = T(0);
 #pragma unroll
                             for (int i1 = 0; i1 < Q; ++i1) s += gy[bb * Q + i1] * y[i1];
                             ya[bb] += s;
                         }
 #pragma unroll
-                        for (int k = 0; k < Q; ++k) xa[k] = 0.0;
+                        for (int k = 0; k < Q; ++k) xa[k] = T(0);
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         __builtin_amdgcn_wave_barrier();
                     }
                 }
             }
             // end of the z class: acc[c] += w_j sum_i2 G_z[c][i2] Y[a][b][i2]
-            const double *gz = gtab + (kbase[kzc] + j) * Q2;
+            const T *gz = gtab + (kbase[kzc] + j) * Q2;
 #pragma unroll
             for (int bb = 0; bb < Q; ++bb) buf[L * RS + bb] = ya[bb];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             {
                 const int a = L / Q, bb = L % Q;
-                double y[Q];
+                T y[Q];
 #pragma unroll
                 for (int i2 = 0; i2 < Q; ++i2) y[i2] = buf[(a * Q + i2) * RS + bb];
 #pragma unroll
                 for (int c = 0; c < Q; ++c) {
-                    double s = 0.0;
+                    T s = T(0);
 #pragma unroll
                     for (int i2 = 0; i2 < Q; ++i2) s += gz[c * Q + i2] * y[i2];
                     acc[c] += wj * s;
@@ -717,7 +725,7 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
     __syncthreads();
     double *part = vsm;  // [JB][q^3]
 #pragma unroll
-    for (int c = 0; c < Q; ++c) part[w * Q3 + L * Q + c] = acc[c];
+    for (int c = 0; c < Q; ++c) part[w * Q3 + L * Q + c] = (double)acc[c];
     double *rB = part + JB * Q3, *d2 = rB + Q3, *l1 = d2 + Q2, *l2 = l1 + Q3;
     const double *rb = D.rho + (int64_t)vB * Q3;
     for (int t = tid; t < Q3; t += NT) rB[t] = rb[t];
@@ -785,7 +793,7 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
     if (!attrs) {
         vol_allow_lds(k_vol_upward<T, P, Q>, LD::up(sizeof(T)));
         vol_allow_lds(k_vol_leaf<T, P, Q>, LD::leaf(sizeof(T)));
-        vol_allow_lds(k_vol_near<Q>, LD::near());
+        vol_allow_lds(k_vol_near<T, Q>, LD::near(sizeof(T)));
         attrs = true;
     }
     VDev<T> D = make_vdev<T>(Pl);
@@ -809,8 +817,10 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         VDev<double> D64 = make_vdev<double>(Pl);
         D64.rho = rho;
         const VolData &V = Pl->vol;
-        hipLaunchKernelGGL((k_vol_near<Q>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB), LD::near(), s, D64, Pl->l_leaf,
-                           Pl->nl_off, Pl->nl_src, V.d_pkey, V.d_kng, V.d_kbase, V.d_gtab, V.d_gw);
+        const T *gtab = sizeof(T) == 8 ? (const T *)V.d_gtab : (const T *)V.f_gtab;
+        const size_t lds_near = LD::near(sizeof(T));
+        hipLaunchKernelGGL((k_vol_near<T, Q>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB), lds_near, s, D64,
+                           Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey, V.d_kng, V.d_kbase, gtab, V.d_gw);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -978,6 +988,12 @@ void vol_count_work(Plan *P, hipStream_t s)
         hipLaunchKernelGGL(k_vol_gtab, dim3(vblk(rows)), dim3(TPB), 0, s, V.d_xq, V.d_tgl, V.d_tglw, V.d_egl,
                            V.d_eglw, V.tpan_gl, V.tpan_w, V.tau_a, V.sqL, q, nk, d_kk, d_cd, V.d_kng, V.d_kbase,
                            rows, V.d_gtab, V.d_gw);
+    if (P->precision == DMK_MIXED) {
+        // the mixed path's near field multiplies in FP32
+        const int64_t nt = std::max<int64_t>(ng, 1) * q * q;
+        V.f_gtab = (float *)dalloc(P, (size_t)nt * sizeof(float));
+        if (rows > 0) hipLaunchKernelGGL(k_vol_tof32, dim3(vblk(nt)), dim3(TPB), 0, s, V.d_gtab, V.f_gtab, nt);
+    }
     DMK_HIP(hipGetLastError());
     DMK_HIP(hipStreamSynchronize(s));
 }

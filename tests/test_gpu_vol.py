@@ -103,8 +103,9 @@ def case_mixed(request, oracle_mod):
 
 
 def test_mixed_precision(case_mixed):
-    """Far-field transforms in FP32 (near field and sums FP64): 1e-5 of the
-    FP64 oracle, the point code's mixed bar."""
+    """Far-field transforms and near-field factor sums in FP32 (the asymptotic
+    part and the final sums FP64): 1e-5 of the FP64 oracle, the point code's
+    mixed bar, for the potential and for its near part alone."""
     name, T, plan, xyz_o, rho, ref = case_mixed
     lev, ijk = plan.leaves()
     assert np.array_equal(lev, T.level) and np.array_equal(ijk, T.ijk)
@@ -112,9 +113,10 @@ def test_mixed_precision(case_mixed):
     u, far, near = u.cpu().numpy(), far.cpu().numpy(), near.cpu().numpy()
     nu = np.linalg.norm(ref["u"])
     _say(f"[vol mixed {name}] rel l2 u {np.linalg.norm(u - ref['u']) / nu:.3e} far "
-         f"{np.linalg.norm(far - ref['ufar']) / nu:.3e}")
+         f"{np.linalg.norm(far - ref['ufar']) / nu:.3e} near "
+         f"{np.linalg.norm(near - ref['unear'] - ref['utail']) / nu:.3e}")
     assert np.linalg.norm(u - ref["u"]) < 1e-5 * nu
-    assert np.linalg.norm(near - ref["unear"] - ref["utail"]) < 1e-10 * nu
+    assert np.linalg.norm(near - ref["unear"] - ref["utail"]) < 1e-5 * nu
 
 
 def test_api_misuse(oracle_mod):

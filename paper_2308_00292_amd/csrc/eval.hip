@@ -695,10 +695,11 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
 // PF: the operands of the wave's next slab are loaded before the current
 // slab's products (for X in global memory: hides the load latency).
 template <int NWV, int P, int NX, int NF, bool PF, typename XR, typename XI, typename SF>
-__device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
+__device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store, int nx = NX)
 {
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
-    constexpr int NH = NF + 1, NKS = (NH + 3) / 4, NSL = (NX + 15) / 16;
+    constexpr int NH = NF + 1, NKS = (NH + 3) / 4;
+    const int NSL = (nx + 15) / 16;  // slabs holding the nx live rows
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
     float br[NATM][NKS], bi[NATM][NKS], rr[NRA][NKS], ri[NRA][NKS];
 #pragma unroll
@@ -724,7 +725,7 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int m = 4 * s + kq;
-            const bool ok = sl < NSL && xa < NX && m < NH, okq = ok && m > 0;
+            const bool ok = sl < NSL && xa < nx && m < NH, okq = ok && m > 0;
             fpr[s] = ok ? Xr(xa, NF + m) : 0.f;
             fpi[s] = ok ? Xi(xa, NF + m) : 0.f;
             fqr[s] = okq ? Xr(xa, NF - m) : 0.f;
@@ -765,12 +766,12 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
-                if (x < NX && a < P) store(x, a, cr[t][i], ci[t][i]);
+                if (x < nx && a < P) store(x, a, cr[t][i], ci[t][i]);
             }
 #pragma unroll
         for (int j = 0; j < NREM; ++j) {
             const float vr = kq_sum(ar[j]), vi = kq_sum(ai[j]);
-            if (kq == 0 && xa < NX) store(xa, 16 * NATM + j, vr, vi);
+            if (kq == 0 && xa < nx) store(xa, 16 * NATM + j, vr, vi);
         }
         if (PF) {
 #pragma unroll
@@ -908,7 +909,8 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
                         B2[(j1 * P + a) * KP + m3] = vr;
                         B2[(j1 * P + a) * KP + NH + m3] = vi;
                     }
-                });
+                },
+                g * NH);
             __syncthreads();
             // m3: acc[(j1 j2)][j3] += sum_k' B2[(j1 j2)][k'] B3[k'][j3] for the slabs of this group
             constexpr int NKS = (KP + 3) / 4;
@@ -971,8 +973,8 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
 // FP32 path of proxy -> plane waves (eq. outgoingexpansion2) on MFMA, the
 // mode products of k_proxy2pw in the fragment scheme of the local stage:
 //   j3 -> m3  A[(j1 j2)][m3 | NH + m3] = sum_j3 rho[(j1 j2)][j3] (Re | Im) E[m3][j3]
-//   j2 -> m2  B2[(j1 mm)][m2] = sum_j2 A[(j1 j2)][m3] E[m2][j2]   (complex)
-//   j1 -> m1  Phi[m1][(mm m2)] = sum_j1 E[m1][j1] B2[(j1 mm)][m2] (complex)
+//   j2 -> m2  B2[(mm j1)][m2] = sum_j2 A[(j1 j2)][m3] E[m2][j2]   (complex)
+//   j1 -> m1  Phi[m1][(mm m2)] = sum_j1 E[m1][j1] B2[(mm j1)][m2] (complex)
 // the last two for G values of m3 at a time; each group's Phi rows are
 // staged in LDS and written to HBM as contiguous runs of G * nn values.
 // Forward plane-wave contraction to a full output index m = -NF..NF:
@@ -983,9 +985,10 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
 // point at column m = 0 of E (element (k, m) at k * NBS + m); store receives
 // (x, m, Y[m], Y[-m]) for m = 0..NF (Y[-0] is Y[0]).
 template <int NWV, int NF, int NX, int NK, int NBS, typename XR, typename XI, typename SF>
-__device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store)
+__device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store, int nx = NX)
 {
-    constexpr int NH = NF + 1, NKS = (NK + 3) / 4, NSL = (NX + 15) / 16, NAT = (NH + 15) / 16;
+    constexpr int NH = NF + 1, NKS = (NK + 3) / 4, NAT = (NH + 15) / 16;
+    const int NSL = (nx + 15) / 16;  // slabs holding the nx live rows
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
     float br[NAT][NKS], bi[NAT][NKS];
 #pragma unroll
@@ -1005,7 +1008,7 @@ __device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const f
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
-            const bool ok = xa < NX && k < NK;
+            const bool ok = xa < nx && k < NK;
             const float ar = ok ? Xr(xa, k) : 0.f, ai = ok ? Xi(xa, k) : 0.f;
 #pragma unroll
             for (int t = 0; t < NAT; ++t) {
@@ -1020,7 +1023,7 @@ __device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const f
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int x = 16 * sl + 4 * kq + i, m = 16 * t + r16;
-                if (x < NX && m < NH)
+                if (x < nx && m < NH)
                     store(x, m, ur[t][i] - vi[t][i], ui[t][i] + vr[t][i], ur[t][i] + vi[t][i], ui[t][i] - vr[t][i]);
             }
     }
@@ -1049,7 +1052,7 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
     float *BiT = BrT + P * NN;         //         Im E[m][j]
     float *r0 = BiT + P * NN;          // rho, then B2 and the staged Phi rows
     float *A = r0 + L::R0;             // [(j1 j2)][W1]
-    float *B2r = r0, *B2i = B2r + P * G * NN;       // [(j1 mm)][m2]
+    float *B2r = r0, *B2i = B2r + P * G * NN;       // [(mm j1)][m2]
     float *Fr = B2i + P * G * NN, *Fi = Fr + NN * G * NN;  // [m1][(mm m2)]
     const int32_t B = list[blockIdx.x];
     for (int t = threadIdx.x; t < P * W1; t += P2PW_NT) {
@@ -1073,10 +1076,10 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
     for (int g0 = 0; g0 < NH; g0 += G) {
         const int g = min(G, NH - g0);
         __syncthreads();
-        // j2 -> m2: rows x = (j1, mm)
+        // j2 -> m2: rows x = (mm, j1), the g P live rows first
         mma_herm_out_store<P2PW_NT / 64, NF, P * G, P, NN>(
-            [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
-            [&](int x, int k) { const int j1 = x / G, mm = x % G; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
+            [&](int x, int k) { const int mm = x / P, j1 = x % P; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
+            [&](int x, int k) { const int mm = x / P, j1 = x % P; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
             BrT + NF, BiT + NF, [&](int x, int m, float pr, float pi, float nr, float ni) {
                 B2r[x * NN + NF + m] = pr;
                 B2i[x * NN + NF + m] = pi;
@@ -1084,12 +1087,13 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
                     B2r[x * NN + NF - m] = nr;
                     B2i[x * NN + NF - m] = ni;
                 }
-            });
+            },
+            P * g);
         __syncthreads();
         // j1 -> m1: rows x = (mm, m2)
         mma_herm_out_store<P2PW_NT / 64, NF, G * NN, P, NN>(
-            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(k * G + mm) * NN + m2] : 0.f; },
-            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(k * G + mm) * NN + m2] : 0.f; },
+            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(mm * P + k) * NN + m2] : 0.f; },
+            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(mm * P + k) * NN + m2] : 0.f; },
             BrT + NF, BiT + NF, [&](int x, int m, float pr, float pi, float nr, float ni) {
                 Fr[(NF + m) * G * NN + x] = pr;
                 Fi[(NF + m) * G * NN + x] = pi;
@@ -1097,7 +1101,8 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
                     Fr[(NF - m) * G * NN + x] = nr;
                     Fi[(NF - m) * G * NN + x] = ni;
                 }
-            });
+            },
+            g * NN);
         __syncthreads();
         // the group's rows of Phi[m1][m3][m2]: runs of g * nn values per m1
         for (int t = threadIdx.x; t < NN * g * NN; t += P2PW_NT) {

@@ -1675,9 +1675,13 @@ static void set_lds_attrs()
 
 // Root window W_0, outgoing and incoming plane waves and the local values of
 // the anchors: the stages between the proxy charges and the evaluation at
-// the targets, shared by the point code and the volume code.
+// the targets, shared by the point code and the volume code.  With a `side`
+// stream the residual sums are forked onto it just before the translation:
+// that stage waits on memory, so the residual's arithmetic fills the compute
+// units beside it (forked at the start, the residual would compete with the
+// upward pass, which is arithmetic-bound too, and the step gains nothing).
 template <typename T, int P, int NF>
-static void enqueue_far(Plan *Pl, hipStream_t s)
+static void enqueue_far(Plan *Pl, hipStream_t s, hipStream_t side = nullptr)
 {
     using C = Cfg<T, P, NF>;
     Dev<T> D = make_dev<T>(Pl);
@@ -1705,6 +1709,12 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
         else
             hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
                                Pl->l_fout);
+    }
+    if (side && Pl->nleaf) {
+        DMK_HIP(hipEventRecord(Pl->ev_fork, s));
+        DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
+        launch_residual<T>(D, Pl, side);
+        DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
     if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
@@ -1734,7 +1744,8 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
 // The stages between the charge gather and the final scatter.  They read and
 // write plan-owned buffers only, so the sequence can be captured into a HIP
 // graph once and replayed.  `side` (if not null) is a second stream on which
-// the residual sums run concurrently with the far-field chain.
+// the residual sums run concurrently with the far-field chain (from the
+// translation on).
 template <typename T, int P, int NF>
 static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
 {
@@ -1743,12 +1754,6 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
     const auto &ll = Pl->ll;
     const int L = Pl->nlevels;
     const int64_t n = Pl->n;
-    if (side && Pl->nleaf) {
-        DMK_HIP(hipEventRecord(Pl->ev_fork, s));
-        DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
-        launch_residual<T>(D, Pl, side);
-        DMK_HIP(hipEventRecord(Pl->ev_join, side));
-    }
     // Step 2: upward pass, finest level first
     for (int l = L - 1; l >= 0; --l) {
         int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
@@ -1756,7 +1761,7 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
         StageScope t(Pl, s, DMK_STAGE_UPWARD);
         hipLaunchKernelGGL((k_upward<T, P>), dim3((unsigned)m), dim3(TPB), C::lds_up(), s, D, Pl->l_fout + ll.fout_off[l]);
     }
-    enqueue_far<T, P, NF>(Pl, s);
+    enqueue_far<T, P, NF>(Pl, s, side);
     if (Pl->nleaf) {
         {
             StageScope t(Pl, s, DMK_STAGE_LEAF);

@@ -262,6 +262,9 @@ template <typename T>
 __device__ inline Cx<T> cmul(Cx<T> a, Cx<T> f) { return {a.r * f.r - a.i * f.i, a.r * f.i + a.i * f.r}; }
 
 template <typename T>
+__device__ inline Cx<T> cj(Cx<T> a) { return {a.r, -a.i}; }
+
+template <typename T>
 __device__ inline Cx<T> root3(int k)  // w^{-k}, any integer k
 {
     k %= 3;
@@ -304,14 +307,15 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
     if (e0 >= nmode) return;
     // per-axis factors for delta = -1 and +1 (delta = 0 is 1);
     // e = (m1 * nh + m3) * nn + m2
-    Cx<T> xm[MPT], xp[MPT], ym[MPT], yp[MPT], zm[MPT], zp[MPT];
+    // (the factor for delta = +1 is the conjugate of the one for -1)
+    Cx<T> xm[MPT], ym[MPT], zm[MPT];
 #pragma unroll
     for (int u = 0; u < MPT; ++u) {
         const int64_t e = min(e0 + u, nmode - 1);
         const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
-        xm[u] = root3<T>(-m1); xp[u] = root3<T>(m1);
-        ym[u] = root3<T>(-m2); yp[u] = root3<T>(m2);
-        zm[u] = root3<T>(-m3); zp[u] = root3<T>(m3);
+        xm[u] = root3<T>(-m1);
+        ym[u] = root3<T>(-m2);
+        zm[u] = root3<T>(-m3);
     }
     Cx<T> acc[MPT][2][2][2];
 #pragma unroll
@@ -354,20 +358,20 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
 #pragma unroll
             for (int u = 0; u < MPT; ++u) {
                 // Z[tz] = sum over gz = tz .. tz+2 of w^{-m3 (gz - tz - 1)} f[gz]
-                Cx<T> z0 = cmul(f[0][u], zm[u]), z1 = cmul(f[3][u], zp[u]);
-                z0.r += f[1][u].r + cmul(f[2][u], zp[u]).r;
-                z0.i += f[1][u].i + cmul(f[2][u], zp[u]).i;
+                Cx<T> z0 = cmul(f[0][u], zm[u]), z1 = cmul(f[3][u], cj(zm[u]));
+                z0.r += f[1][u].r + cmul(f[2][u], cj(zm[u])).r;
+                z0.i += f[1][u].i + cmul(f[2][u], cj(zm[u])).i;
                 z1.r += f[2][u].r + cmul(f[1][u], zm[u]).r;
                 z1.i += f[2][u].i + cmul(f[1][u], zm[u]).i;
                 // ty = gy - 1 - delta: gy contributes to ty = 0 (delta = gy - 1) and ty = 1 (delta = gy - 2)
                 if (gy <= 2) {
-                    const Cx<T> fy = (gy == 0) ? ym[u] : (gy == 1) ? Cx<T>{T(1), T(0)} : yp[u];
+                    const Cx<T> fy = (gy == 0) ? ym[u] : (gy == 1) ? Cx<T>{T(1), T(0)} : cj(ym[u]);
                     const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
                     Y[u][0][0].r += a0.r; Y[u][0][0].i += a0.i;
                     Y[u][0][1].r += a1.r; Y[u][0][1].i += a1.i;
                 }
                 if (gy >= 1) {
-                    const Cx<T> fy = (gy == 1) ? ym[u] : (gy == 2) ? Cx<T>{T(1), T(0)} : yp[u];
+                    const Cx<T> fy = (gy == 1) ? ym[u] : (gy == 2) ? Cx<T>{T(1), T(0)} : cj(ym[u]);
                     const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
                     Y[u][1][0].r += a0.r; Y[u][1][0].i += a0.i;
                     Y[u][1][1].r += a1.r; Y[u][1][1].i += a1.i;
@@ -379,7 +383,7 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
 #pragma unroll
         for (int u = 0; u < MPT; ++u) {
             if (gx <= 2) {
-                const Cx<T> fx = (gx == 0) ? xm[u] : (gx == 1) ? Cx<T>{T(1), T(0)} : xp[u];
+                const Cx<T> fx = (gx == 0) ? xm[u] : (gx == 1) ? Cx<T>{T(1), T(0)} : cj(xm[u]);
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -390,7 +394,7 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
                     }
             }
             if (gx >= 1) {
-                const Cx<T> fx = (gx == 1) ? xm[u] : (gx == 2) ? Cx<T>{T(1), T(0)} : xp[u];
+                const Cx<T> fx = (gx == 1) ? xm[u] : (gx == 2) ? Cx<T>{T(1), T(0)} : cj(xm[u]);
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
 #pragma unroll

@@ -1224,7 +1224,9 @@ template <typename T, int DEG>
 __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
                                                   const int32_t *nl_src, const int32_t *nl_pre)
 {
-    constexpr int RCAP = sizeof(T) == 8 ? 512 : 1024;  // sources staged per pass
+    // sources staged per pass (12 KB of LDS in FP32: more blocks share a
+    // compute unit, also beside the translation; 1024 was 6 % slower)
+    constexpr int RCAP = 512;
     __shared__ T sx[RCAP], sy[RCAP], sz[RCAP], sq[RCAP], sis[RCAP];  // 1/s of the source box
     __shared__ int32_t loff[RLIST + 1];
     __shared__ double part[TPB];

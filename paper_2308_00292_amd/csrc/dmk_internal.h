@@ -168,6 +168,7 @@ struct Plan {
     // near (residual) lists in gather form over l_leaf order
     int32_t *nl_off = nullptr, *nl_src = nullptr;
     int32_t *nl_pre = nullptr;     // [nl_total + nleaf] running source-point counts per list (+ total)
+    int32_t nl_max = 0;            // longest residual list (source boxes)
     int64_t nl_total = 0, npairs = 0;
 
     // device tables, FP64 and FP32 copies

@@ -1203,9 +1203,10 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
 // to T once per point, with 1/s of the source box level, a power of two, so
 // t = r^2 (1/s)^2 is formed exactly in the loop); each thread then sums one
 // target against a stride of the staged sources, and the per-pass partial
-// sums are added into an FP64 accumulator.  Five staged arrays keep the LDS
-// of a block under 27 KB, so that six blocks fit on a CU.
-constexpr int RLIST = 1024;  // longest gather list (checked at plan time)
+// sums are added into an FP64 accumulator.  Five staged arrays of 512 values
+// (the partial-sum buffer reuses them) and the list offsets keep the LDS of
+// an FP32 block near 10 KB, so that residual blocks also fit beside the
+// upward pass and the translation.
 
 // 1/sqrt in the working precision (the float overload is the hardware
 // reciprocal square root, about 1 ulp, without the rescaling for denormal
@@ -1224,12 +1225,20 @@ template <typename T, int DEG>
 __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
                                                   const int32_t *nl_src, const int32_t *nl_pre)
 {
-    // sources staged per pass (12 KB of LDS in FP32: more blocks share a
-    // compute unit, also beside the translation; 1024 was 6 % slower)
+    // sources staged per pass (10 KB of LDS in FP32: more blocks share a
+    // compute unit; 1024 was 6 % slower, 256 slower too)
     constexpr int RCAP = 512;
-    __shared__ T sx[RCAP], sy[RCAP], sz[RCAP], sq[RCAP], sis[RCAP];  // 1/s of the source box
-    __shared__ int32_t loff[RLIST + 1];
-    __shared__ double part[TPB];
+    // staged sources (sis: 1/s of the source box); the per-split partial
+    // sums reuse their space once a target chunk is done
+    __shared__ union {
+        struct { T x[RCAP], y[RCAP], z[RCAP], q[RCAP], is[RCAP]; } s;
+        double part[TPB];
+    } stg;
+    T *sx = stg.s.x, *sy = stg.s.y, *sz = stg.s.z, *sq = stg.s.q, *sis = stg.s.is;
+    double *part = stg.part;
+    // running source counts of the block's list: L + 1 entries in the
+    // dynamic LDS, sized at launch to the plan's longest list
+    extern __shared__ int32_t loff[];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.pstart[B];
     const int nt = D.pcount[B];
@@ -1644,20 +1653,21 @@ template <typename T>
 static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
 {
     const dim3 g((unsigned)Pl->nleaf), b(TPB);
+    const size_t lds = sizeof(int32_t) * ((size_t)Pl->nl_max + 1);  // loff
     if (D.gdeg <= 7)
-        hipLaunchKernelGGL((k_residual<T, 7>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 7>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 9)
-        hipLaunchKernelGGL((k_residual<T, 9>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 9>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 11)
-        hipLaunchKernelGGL((k_residual<T, 11>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 11>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 13)
-        hipLaunchKernelGGL((k_residual<T, 13>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 13>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 15)
-        hipLaunchKernelGGL((k_residual<T, 15>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 15>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 20)
-        hipLaunchKernelGGL((k_residual<T, 20>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 20>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else
-        hipLaunchKernelGGL((k_residual<T, 47>), g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL((k_residual<T, 47>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
 }
 
 // dynamic LDS limits of the stage kernels, once per process
@@ -1681,13 +1691,9 @@ static void set_lds_attrs()
 
 // Root window W_0, outgoing and incoming plane waves and the local values of
 // the anchors: the stages between the proxy charges and the evaluation at
-// the targets, shared by the point code and the volume code.  With a `side`
-// stream the residual sums are forked onto it just before the translation:
-// that stage waits on memory, so the residual's arithmetic fills the compute
-// units beside it (forked at the start, the residual would compete with the
-// upward pass, which is arithmetic-bound too, and the step gains nothing).
+// the targets, shared by the point code and the volume code.
 template <typename T, int P, int NF>
-static void enqueue_far(Plan *Pl, hipStream_t s, hipStream_t side = nullptr)
+static void enqueue_far(Plan *Pl, hipStream_t s)
 {
     using C = Cfg<T, P, NF>;
     Dev<T> D = make_dev<T>(Pl);
@@ -1715,12 +1721,6 @@ static void enqueue_far(Plan *Pl, hipStream_t s, hipStream_t side = nullptr)
         else
             hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
                                Pl->l_fout);
-    }
-    if (side && Pl->nleaf) {
-        DMK_HIP(hipEventRecord(Pl->ev_fork, s));
-        DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
-        launch_residual<T>(D, Pl, side);
-        DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
     if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
@@ -1750,8 +1750,9 @@ static void enqueue_far(Plan *Pl, hipStream_t s, hipStream_t side = nullptr)
 // The stages between the charge gather and the final scatter.  They read and
 // write plan-owned buffers only, so the sequence can be captured into a HIP
 // graph once and replayed.  `side` (if not null) is a second stream on which
-// the residual sums run concurrently with the far-field chain (from the
-// translation on).
+// the residual sums run concurrently with the far-field chain: their blocks
+// (about 10 KB of LDS in FP32) fit on a compute unit beside three blocks of
+// the upward pass, and later beside the translation.
 template <typename T, int P, int NF>
 static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
 {
@@ -1760,6 +1761,12 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
     const auto &ll = Pl->ll;
     const int L = Pl->nlevels;
     const int64_t n = Pl->n;
+    if (side && Pl->nleaf) {
+        DMK_HIP(hipEventRecord(Pl->ev_fork, s));
+        DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
+        launch_residual<T>(D, Pl, side);
+        DMK_HIP(hipEventRecord(Pl->ev_join, side));
+    }
     // Step 2: upward pass, finest level first
     for (int l = L - 1; l >= 0; --l) {
         int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
@@ -1767,7 +1774,7 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
         StageScope t(Pl, s, DMK_STAGE_UPWARD);
         hipLaunchKernelGGL((k_upward<T, P>), dim3((unsigned)m), dim3(TPB), C::lds_up(), s, D, Pl->l_fout + ll.fout_off[l]);
     }
-    enqueue_far<T, P, NF>(Pl, s, side);
+    enqueue_far<T, P, NF>(Pl, s);
     if (Pl->nleaf) {
         {
             StageScope t(Pl, s, DMK_STAGE_LEAF);

@@ -1034,6 +1034,7 @@ static void build_lists_t(Plan *P, hipStream_t s)
             DMK_HIP(hipStreamSynchronize(s));
             if (hmx > 1024)
                 throw Error{DMK_ERR_UNSUPPORTED, "a leaf's residual list exceeds 1024 source boxes"};
+            P->nl_max = hmx;
         }
         int64_t *psum = S.get<int64_t>(1);
         tb = 0;

@@ -1205,8 +1205,8 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
 // target against a stride of the staged sources, and the per-pass partial
 // sums are added into an FP64 accumulator.  Five staged arrays of 512 values
 // (the partial-sum buffer reuses them) and the list offsets keep the LDS of
-// an FP32 block near 10 KB, so that residual blocks also fit beside the
-// upward pass and the translation.
+// an FP32 block near 10 KB, so that many blocks share a compute unit, also
+// beside the far-field kernels.
 
 // 1/sqrt in the working precision (the float overload is the hardware
 // reciprocal square root, about 1 ulp, without the rescaling for denormal
@@ -1750,9 +1750,10 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
 // The stages between the charge gather and the final scatter.  They read and
 // write plan-owned buffers only, so the sequence can be captured into a HIP
 // graph once and replayed.  `side` (if not null) is a second stream on which
-// the residual sums run concurrently with the far-field chain: their blocks
-// (about 10 KB of LDS in FP32) fit on a compute unit beside three blocks of
-// the upward pass, and later beside the translation.
+// the residual sums run concurrently with the far-field chain.  In a replay
+// the residual kernel starts together with the translation, a stage that
+// waits on memory, and its blocks (about 10 KB of LDS in FP32, 46 VGPRs)
+// fill the compute-unit room that the translation leaves.
 template <typename T, int P, int NF>
 static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
 {

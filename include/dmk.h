@@ -122,7 +122,9 @@ typedef struct {
  * c, N_1 = 2 n_f + 1, p of Table 1 (Sec. 3.7).
  *
  *  dim     2 or 3.
- *  kernel  DMK_LAPLACE (DMK_YUKAWA: DMK_ERR_UNSUPPORTED).
+ *  kernel  DMK_LAPLACE (dim 3: 1/(4 pi r); dim 2: -log(r)/(2 pi)), or
+ *          DMK_YUKAWA with dim 2 (K_0(lambda r), lambda from opts->lambda);
+ *          DMK_YUKAWA with dim 3 gives DMK_ERR_UNSUPPORTED.
  *  tol     one of 1e-3, 1e-6, 1e-9, 1e-12 (Table 1) or 1e-5.  DMK_MIXED
  *          requires tol >= 1e-6 (else DMK_ERR_PRECISION).
  *  n       number of points, 0 <= n < 2^31.
@@ -203,8 +205,11 @@ dmk_status dmk_problem_info(dmk_plan_t plan, int32_t prob, double *center, doubl
  *  stream  asynchronous: pot is valid once the stream has been synchronised.
  *
  * A plan owns its workspace: a second dmk_eval on the same plan while one
- * is in flight on another host thread returns DMK_ERR_STATE.  Calls on the
- * same stream are ordered and may be issued back to back.
+ * is in flight on another host thread returns DMK_ERR_STATE.  Evals on one
+ * plan are ordered whatever streams they use: each one records a completion
+ * event on its stream and the next one makes its stream wait on it (not
+ * while the stream is being captured into a graph: the capture orders the
+ * work).  Calls may be issued back to back.
  */
 dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *stream);
 

@@ -73,7 +73,37 @@ struct BusyGuard {
     ~BusyGuard() { P->busy.store(0); }
 };
 
+// An eval reads and writes plan-owned workspace, so it must not overlap the
+// previous eval on the same plan, whichever stream that one used: the new
+// stream waits for the completion event of the last one, and the event is
+// recorded again at the end.  Under stream capture the caller's graph orders
+// the work itself, and events from outside the capture may not be waited on.
+bool capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    DMK_HIP(hipStreamIsCapturing(s, &st));
+    return st != hipStreamCaptureStatusNone;
+}
+
+void begin_eval(Plan *P, hipStream_t s)
+{
+    if (P->ev_done && P->done_recorded && !capturing(s)) DMK_HIP(hipStreamWaitEvent(s, P->ev_done, 0));
+}
+
+void end_eval(Plan *P, hipStream_t s)
+{
+    if (P->ev_done && !capturing(s)) {
+        DMK_HIP(hipEventRecord(P->ev_done, s));
+        P->done_recorded = true;
+    }
+    P->last_stream = s;
+}
+
 }  // namespace
+
+namespace dmk {
+void create_done_event(Plan *P) { DMK_HIP(hipEventCreateWithFlags(&P->ev_done, hipEventDisableTiming)); }
+}  // namespace dmk
 
 extern "C" {
 
@@ -153,6 +183,7 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         }
         alloc_workspace(P);
         count_work(P, s);
+        create_done_event(P);
         if (P->flags & DMK_FLAG_BATCHED) {
             // default-priority streams only
             DMK_HIP(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
@@ -274,8 +305,9 @@ dmk_status dmk_eval_parts(dmk_plan_t plan, const double *charges, double *far_pa
         if (P->n > 0 && !charges) throw Error{DMK_ERR_ARG, "charges is NULL"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
+        begin_eval(P, s);
         run_eval(P, charges, nullptr, far_part, near_part, s);
-        P->last_stream = s;
+        end_eval(P, s);
     });
 }
 
@@ -288,8 +320,9 @@ dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *s
         if (P->n > 0 && (!charges || !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
+        begin_eval(P, s);
         run_eval(P, charges, pot, nullptr, nullptr, s);
-        P->last_stream = s;
+        end_eval(P, s);
     });
 }
 
@@ -347,8 +380,9 @@ dmk_status dmk_vol_eval(dmk_plan_t plan, const double *rho, double *u, double *f
         if (!u && !far_part && !near_part) throw Error{DMK_ERR_ARG, "no output requested"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
+        begin_eval(P, s);
         run_vol_eval(P, rho, u, far_part, near_part, s);
-        P->last_stream = s;
+        end_eval(P, s);
     });
 }
 
@@ -618,6 +652,7 @@ void plan_release(Plan *P)
     if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
     if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
     if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+    if (P->ev_done) (void)hipEventDestroy(P->ev_done);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
     if (P->side_stream) (void)hipStreamDestroy(P->side_stream);
     plan_free_all(P);

@@ -207,6 +207,7 @@ struct Plan {
     int64_t n_merge = 0;       // F_out children merged by c2p
     int64_t n_shift_pairs = 0; // (F_in box, F_out colleague) pairs
     int64_t npairs_in = 0;     // residual pairs closer than the source box side
+    int64_t nanc_tgt = 0;      // anchors with at least one target (blocks of the leaf stage that read values)
 
     // batched execution: graph of the eval core, capture and side streams
     hipStream_t cap_stream = nullptr, side_stream = nullptr;
@@ -217,10 +218,15 @@ struct Plan {
     int64_t device_bytes = 0;
     std::atomic<int> busy{0};
     hipStream_t last_stream = nullptr;
+    // completion of the last eval (recorded on its stream): the next eval's
+    // stream waits on it, because the workspace is plan-owned
+    hipEvent_t ev_done = nullptr;
+    bool done_recorded = false;
 };
 
 void *dalloc(Plan *P, size_t bytes);  // tracked device allocation
 void plan_free_all(Plan *P);
+void create_done_event(Plan *P);  // the completion event that orders evals on different streams
 void plan_release(Plan *P);  // device memory, events, streams, graph, then the Plan itself
 
 void build_tree(Plan *P, const double *pts, hipStream_t s);

@@ -2023,6 +2023,12 @@ void count_work(Plan *P, hipStream_t s)
                 if (j >= 0 && (fl[j] & 2)) P->n_shift_pairs++;
             }
     }
+    P->nanc_tgt = 0;
+    if (P->nanc) {
+        std::vector<int32_t> tb(P->nanc + 1);
+        DMK_HIP(hipMemcpy(tb.data(), P->anc_tbeg, (P->nanc + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t a = 0; a < P->nanc; ++a) P->nanc_tgt += (tb[a + 1] > tb[a]);
+    }
     P->npairs_in = 0;
     if (P->nleaf) {
         unsigned long long *d = nullptr;
@@ -2066,7 +2072,7 @@ void stage_work(const Plan *P, double *F, double *Bt)
         F[DMK_STAGE_PW2GRID] = pwflops * P->nfin + 4 * p3 * std::max<int64_t>(P->nanc - P->nprob, 0);
         Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p2 * P->nanc;
         F[DMK_STAGE_LEAF] = 2 * p2 * N;
-        Bt[DMK_STAGE_LEAF] = 32 * N + el * p2 * P->nleaf;
+        Bt[DMK_STAGE_LEAF] = 32 * N + el * p2 * P->nanc_tgt;  // one block per anchor reads its values once
         F[DMK_STAGE_RESIDUAL] = 6.0 * P->npairs + (2.0 * gd + 12.0) * P->npairs_in;
         Bt[DMK_STAGE_RESIDUAL] = 32 * N;
         return;
@@ -2093,7 +2099,7 @@ void stage_work(const Plan *P, double *F, double *Bt)
     F[DMK_STAGE_PW2GRID] = pwflops * P->nfin + 6 * p4 * std::max<int64_t>(P->nanc - 1, 0);
     Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p3 * P->nanc;
     F[DMK_STAGE_LEAF] = 2 * p3 * N;
-    Bt[DMK_STAGE_LEAF] = 40 * N + el * p3 * P->nleaf;
+    Bt[DMK_STAGE_LEAF] = 40 * N + el * p3 * P->nanc_tgt;  // one block per anchor reads its values once
     F[DMK_STAGE_RESIDUAL] = 8.0 * P->npairs + (2.0 * gd + 8.0) * P->npairs_in;
     Bt[DMK_STAGE_RESIDUAL] = 40 * N;
 }

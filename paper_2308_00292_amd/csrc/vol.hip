@@ -1146,6 +1146,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         alloc_workspace(P);
         V.ufar = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
         V.unear = (double *)dalloc(P, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+        create_done_event(P);
         DMK_HIP(hipStreamSynchronize(s));
     } catch (...) {
         plan_release(P);

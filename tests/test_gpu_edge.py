@@ -111,3 +111,29 @@ def test_tune_leaf_picks_a_candidate():
     best2, ms2 = dmk.tune_leaf(torch.from_numpy(p2).to(dev), torch.from_numpy(q2).to(dev), [32, 64],
                                offsets=off, reps=1)
     assert best2 in (32, 64)
+
+
+@pytest.mark.parametrize("precision,flags", [(0, 0), (1, 2)], ids=["fp64_eager", "mixed_batched"])
+def test_evals_on_two_streams_are_ordered(precision, flags):
+    """Two evals of one plan issued back to back on two different streams:
+    the plan's workspace is shared, so the second must wait for the first.
+    Both results equal the ones of evals run one at a time, bit for bit."""
+    import paper_2308_00292_amd as dmk
+    _say(f"[edge] two streams, precision {precision} flags {flags}")
+    pts, q1 = dmk_inputs.uniform_cube(40000, 11)
+    q2 = np.random.default_rng(12).uniform(-1, 1, len(q1))
+    pl = dmk.Plan(_dev(pts), tol=1e-6, leaf_max=32, precision=precision, flags=flags)
+    d1, d2 = _dev(q1), _dev(q2)
+    ref1 = pl.eval(d1).cpu().numpy()
+    ref2 = pl.eval(d2).cpu().numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = [(torch.empty_like(d1), torch.empty_like(d2)) for _ in range(3)]
+    torch.cuda.synchronize()
+    for o1, o2 in outs:
+        pl.eval(d1, out=o1, stream=s1)
+        pl.eval(d2, out=o2, stream=s2)
+    torch.cuda.synchronize()
+    for o1, o2 in outs:
+        assert np.array_equal(o1.cpu().numpy(), ref1)
+        assert np.array_equal(o2.cpu().numpy(), ref2)
+    pl.close()

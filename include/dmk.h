@@ -88,6 +88,16 @@ typedef struct {
  * stream.  Results are identical either way. */
 #define DMK_FLAG_BATCHED 2ull
 
+/* The plan allocates no eval workspace (gathered charges, proxies, plane
+ * waves, local values, partial potentials): such a plan is evaluated only
+ * with dmk_eval_noalloc, which takes the workspace from the library's static
+ * scratch; dmk_eval, dmk_eval_parts and dmk_copy_box_data return
+ * DMK_ERR_STATE on it.  Ignored by dmk_vol_plan. */
+#define DMK_FLAG_NO_WORKSPACE 4ull
+
+/* Size of the static device scratch of dmk_eval_noalloc, per device. */
+#define DMK_NOALLOC_MAX_BYTES (128ll << 20)
+
 typedef struct dmk_plan_s *dmk_plan_t;
 
 /* Sizes of a plan (host struct filled by dmk_plan_info). */
@@ -212,6 +222,33 @@ dmk_status dmk_problem_info(dmk_plan_t plan, int32_t prob, double *center, doubl
  * work).  Calls may be issued back to back.
  */
 dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *stream);
+
+/*
+ * dmk_eval_noalloc -- dmk_eval for callers that cannot allocate device
+ * memory at call time (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).
+ *
+ * Same arguments and the same result as dmk_eval (bit for bit, as the eager
+ * form of dmk_eval).  The eval workspace comes from a static device array of
+ * DMK_NOALLOC_MAX_BYTES that the library holds on every device it runs on
+ * until the process ends, not from the plan, so plans built with
+ * DMK_FLAG_NO_WORKSPACE hold none of their own.  The call allocates nothing:
+ * no hipMalloc, no hipFree, no events.  Stages run as eager launches on
+ * `stream` (no graph replay, no second stream, no stage timing).
+ *
+ *  plan     a point plan (dmk_plan or dmk_plan_batched); volume plans give
+ *           DMK_ERR_ARG.
+ *  charges  device, [n] FP64, input order.
+ *  pot      device, [n] FP64, input order, overwritten.
+ *  stream   asynchronous, as dmk_eval.
+ * Errors: DMK_ERR_ARG if the plan's workspace (sum of its buffers, each
+ * rounded up to 256 bytes) exceeds DMK_NOALLOC_MAX_BYTES; otherwise as
+ * dmk_eval.  Every call on one device shares the one array, which keeps the
+ * last call's contents: calls that overlap in time on one device (other
+ * streams, other threads, other plans) race and give wrong results; calls
+ * on one stream, or ordered by the caller, are safe.
+ */
+dmk_status dmk_eval_noalloc(dmk_plan_t plan, const double *charges, double *pot, void *stream);
 
 /*
  * dmk_eval_parts -- like dmk_eval, but returns the far-field part (the

@@ -17,9 +17,11 @@ LIBPATH = os.path.join(_HERE, "libdmk.so")
 DMK_FP64, DMK_MIXED = 0, 1
 DMK_LAPLACE, DMK_YUKAWA = 0, 1
 DMK_FLAG_BATCHED = 2
+DMK_FLAG_NO_WORKSPACE = 4
+NOALLOC_MAX_BYTES = 128 << 20
 
 # exported symbols, in the order of include/dmk.h
-SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_problem_info", "dmk_eval", "dmk_eval_parts",
+SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_problem_info", "dmk_eval", "dmk_eval_noalloc", "dmk_eval_parts",
            "dmk_plan_info", "dmk_export_tree", "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
            "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
            "dmk_vol_plan", "dmk_vol_info", "dmk_vol_leaves", "dmk_vol_nodes", "dmk_vol_eval",
@@ -70,6 +72,7 @@ def lib():
         L.dmk_tune_leaf.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, vp, C.POINTER(Opts), vp,
                                     C.c_int32, C.c_int32, vp, vp, vp]
         L.dmk_eval.argtypes = [vp, vp, vp, vp]
+        L.dmk_eval_noalloc.argtypes = [vp, vp, vp, vp]
         L.dmk_eval_parts.argtypes = [vp, vp, vp, vp, vp]
         L.dmk_plan_info.argtypes = [vp, C.POINTER(Stats)]
         L.dmk_export_tree.argtypes = [vp] + [vp] * 11
@@ -187,6 +190,18 @@ class Plan:
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device=q.device)
         _check(lib().dmk_eval(self._h, _ptr(q), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def eval_noalloc(self, charges, out, stream=None):
+        """dmk_eval_noalloc: the workspace comes from the library's static
+        scratch; ``out`` (float64 CUDA [n]) is required, nothing is allocated."""
+        import torch
+        if charges.dtype != torch.float64 or not charges.is_cuda or charges.numel() != self.n \
+                or not charges.is_contiguous():
+            raise TypeError("charges must be a contiguous float64 CUDA tensor with n entries")
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() != self.n or not out.is_contiguous():
+            raise TypeError("out must be a contiguous float64 CUDA tensor with n entries")
+        _check(lib().dmk_eval_noalloc(self._h, _ptr(charges), _ptr(out), _stream_handle(stream)))
         return out
 
     def eval_parts(self, charges, stream=None):

@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["capi.cpp", "precompute.cpp", "plan.hip", "eval.hip", "eval2.hip", "yukawa2.hip", "vol.hip"]
+SRC = ["capi.cpp", "precompute.cpp", "plan.hip", "eval.hip", "eval2.hip", "yukawa2.hip", "vol.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "libdmk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -32,7 +32,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=7) as ex:
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
         objs = list(ex.map(_compile, SRC))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", tmp, *objs]

@@ -39,46 +39,14 @@ void plan_free_all(Plan *P)
 
 using namespace dmk;
 
-namespace {
-
-template <typename F>
-dmk_status guarded(F &&f)
-{
-    try {
-        f();
-        return DMK_OK;
-    } catch (const Error &e) {
-        set_error(e.msg);
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        set_error("host allocation failed");
-        return DMK_ERR_NOMEM;
-    } catch (const std::exception &e) {
-        set_error(e.what());
-        return DMK_ERR_STATE;
-    } catch (...) {
-        set_error("unknown failure");
-        return DMK_ERR_STATE;
-    }
-}
-
-struct BusyGuard {
-    Plan *P;
-    explicit BusyGuard(Plan *p) : P(p)
-    {
-        int expect = 0;
-        if (!P->busy.compare_exchange_strong(expect, 1))
-            throw Error{DMK_ERR_STATE, "plan is in use by another dmk_eval"};
-    }
-    ~BusyGuard() { P->busy.store(0); }
-};
+namespace dmk {
 
 // An eval reads and writes plan-owned workspace, so it must not overlap the
 // previous eval on the same plan, whichever stream that one used: the new
 // stream waits for the completion event of the last one, and the event is
 // recorded again at the end.  Under stream capture the caller's graph orders
 // the work itself, and events from outside the capture may not be waited on.
-bool capturing(hipStream_t s)
+static bool capturing(hipStream_t s)
 {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     DMK_HIP(hipStreamIsCapturing(s, &st));
@@ -99,9 +67,6 @@ void end_eval(Plan *P, hipStream_t s)
     P->last_stream = s;
 }
 
-}  // namespace
-
-namespace dmk {
 void create_done_event(Plan *P) { DMK_HIP(hipEventCreateWithFlags(&P->ev_done, hipEventDisableTiming)); }
 }  // namespace dmk
 
@@ -469,6 +434,7 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
         if (!plan || !out) throw Error{DMK_ERR_ARG, "NULL argument"};
         Plan *P = reinterpret_cast<Plan *>(plan);
         if (box < 0 || box >= P->nbox) throw Error{DMK_ERR_ARG, "box out of range"};
+        if (!P->has_workspace) throw Error{DMK_ERR_STATE, "the plan holds no eval workspace (DMK_FLAG_NO_WORKSPACE)"};
         const int64_t p3 = (P->dim == 3) ? (int64_t)P->p * P->p * P->p : (int64_t)P->p * P->p;
         int32_t slot = -1;
         const double *base = nullptr;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <exception>
+#include <new>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -184,6 +186,8 @@ struct Plan {
     void *phi = nullptr;     // [max_fout_level][2][nh*nn*nn] planar
     void *psi = nullptr;     // [max_fin_level][2][nh*nn*nn] planar
     void *w0vals = nullptr;  // [nprob][p^d] W_0 values on the root grids
+    int64_t ws_bytes = 0;         // the workspace's size, each buffer rounded up to 256 bytes
+    bool has_workspace = false;   // false for DMK_FLAG_NO_WORKSPACE plans
 
     // 2-D K_0(lambda r): tables per (problem, level), index b * nlevels + l,
     // for mu = lambda S_b 2^-l (lambda S_b: the problem's scaled parameter)
@@ -227,11 +231,57 @@ struct Plan {
 void *dalloc(Plan *P, size_t bytes);  // tracked device allocation
 void plan_free_all(Plan *P);
 void create_done_event(Plan *P);  // the completion event that orders evals on different streams
+// Orders an eval after the plan's previous one (begin) and records its
+// completion (end); both skip the event while the stream is being captured.
+void begin_eval(Plan *P, hipStream_t s);
+void end_eval(Plan *P, hipStream_t s);
+
+// One eval at a time per plan (host side): a second concurrent call fails.
+struct BusyGuard {
+    Plan *P;
+    explicit BusyGuard(Plan *p) : P(p)
+    {
+        int expect = 0;
+        if (!P->busy.compare_exchange_strong(expect, 1))
+            throw Error{DMK_ERR_STATE, "plan is in use by another dmk_eval"};
+    }
+    ~BusyGuard() { P->busy.store(0); }
+};
+
+// Runs f and turns every exception into a status code and a message.
+template <typename F>
+dmk_status guarded(F &&f)
+{
+    try {
+        f();
+        return DMK_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return DMK_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return DMK_ERR_STATE;
+    } catch (...) {
+        set_error("unknown failure");
+        return DMK_ERR_STATE;
+    }
+}
 void plan_release(Plan *P);  // device memory, events, streams, graph, then the Plan itself
 
 void build_tree(Plan *P, const double *pts, hipStream_t s);
 void build_lists(Plan *P, hipStream_t s);
 void upload_tables(Plan *P, hipStream_t s);
+// one buffer of the eval workspace: the plan field that points to it, and its size
+struct WsItem {
+    void **ptr;
+    size_t bytes;
+};
+void workspace_layout(Plan *P, std::vector<WsItem> &items);
+void workspace_layout2(Plan *P, std::vector<WsItem> &items);
+// dalloc's the workspace (not for DMK_FLAG_NO_WORKSPACE point plans); sets ws_bytes
 void alloc_workspace(Plan *P);
 // far-field stages shared with the volume code (root window, plane waves,
 // local values of the anchors); p = 18 only
@@ -250,7 +300,6 @@ void run_eval(Plan *P, const double *charges, double *pot, double *far_part, dou
 void count_work(Plan *P, hipStream_t s);
 void run_eval2(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
                hipStream_t s);
-void alloc_workspace2(Plan *P);
 void build_yukawa_tables(Plan *P, hipStream_t s);
 void stage_work(const Plan *P, double *flops, double *bytes);
 

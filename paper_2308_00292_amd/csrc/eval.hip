@@ -1851,6 +1851,8 @@ void far_stages(Plan *P, hipStream_t s)
 void run_eval(Plan *P, const double *charges, double *pot, double *far_part, double *near_part, hipStream_t s)
 {
     if (P->n == 0) return;
+    if (!P->qs)
+        throw Error{DMK_ERR_STATE, "the plan holds no eval workspace (DMK_FLAG_NO_WORKSPACE): use dmk_eval_noalloc"};
     if (P->dim == 2) {
         run_eval2(P, charges, pot, far_part, near_part, s);
         return;
@@ -1939,26 +1941,43 @@ void upload_tables(Plan *P, hipStream_t s)
     DMK_HIP(hipStreamSynchronize(s));
 }
 
-void alloc_workspace(Plan *P)
+// The eval workspace of a point plan: buffers every eval writes before it
+// reads them (gathered charges, proxies, plane waves, local values, partial
+// potentials, root scratch).  Listed once, for alloc_workspace and for the
+// static-scratch eval.
+void workspace_layout(Plan *P, std::vector<WsItem> &items)
 {
     if (P->dim == 2) {
-        alloc_workspace2(P);
+        workspace_layout2(P, items);
         return;
     }
     const Tables &t = P->tab;
     const size_t el = (P->precision == DMK_FP64) ? sizeof(double) : sizeof(float);
     const int64_t p3 = (int64_t)t.p * t.p * t.p;
     const int64_t nm = pw_stride(t);
-    auto al = [&](int64_t cnt, size_t sz) { return dalloc(P, (size_t)std::max<int64_t>(cnt, 1) * sz); };
-    P->qs = (double *)al(P->n, 8);
-    P->ufar = (double *)al(P->n, 8);
-    P->ures = (double *)al(P->n, 8);
-    P->rootscratch = (double *)al(root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
-    P->proxy = al(P->nfout * p3, el);
-    P->local = al(P->nanc * p3, el);
-    P->phi = al(2 * P->nfout * nm, el);
-    P->psi = al(2 * P->nfin * nm, el);
-    P->w0vals = al(p3, el);
+    auto add = [&](void *field, int64_t cnt, size_t sz) {
+        items.push_back({(void **)field, (size_t)std::max<int64_t>(cnt, 1) * sz});
+    };
+    add(&P->qs, P->n, 8);
+    add(&P->ufar, P->n, 8);
+    add(&P->ures, P->n, 8);
+    add(&P->rootscratch, root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
+    add(&P->proxy, P->nfout * p3, el);
+    add(&P->local, P->nanc * p3, el);
+    add(&P->phi, 2 * P->nfout * nm, el);
+    add(&P->psi, 2 * P->nfin * nm, el);
+    add(&P->w0vals, p3, el);
+}
+
+void alloc_workspace(Plan *P)
+{
+    std::vector<WsItem> items;
+    workspace_layout(P, items);
+    P->ws_bytes = 0;
+    for (const WsItem &it : items) P->ws_bytes += (int64_t)((it.bytes + 255) / 256 * 256);
+    if ((P->flags & DMK_FLAG_NO_WORKSPACE) && !P->is_vol) return;  // evaluated from the static scratch
+    for (const WsItem &it : items) *it.ptr = dalloc(P, it.bytes);
+    P->has_workspace = true;
 }
 
 // ---------------------------------------------------------- work counts

@@ -895,21 +895,23 @@ void run_eval2(Plan *P, const double *charges, double *pot, double *far_part, do
     }
 }
 
-void alloc_workspace2(Plan *P)
+void workspace_layout2(Plan *P, std::vector<WsItem> &items)
 {
     const Tables &t = P->tab;
     const size_t el = (P->precision == DMK_FP64) ? sizeof(double) : sizeof(float);
     const int64_t p2 = (int64_t)t.p * t.p;
     const int64_t nm = (int64_t)t.nh * t.nn;
-    auto al = [&](int64_t cnt, size_t sz) { return dalloc(P, (size_t)std::max<int64_t>(cnt, 1) * sz); };
-    P->qs = (double *)al(P->n, 8);
-    P->ufar = (double *)al(P->n, 8);
-    P->ures = (double *)al(P->n, 8);
-    P->proxy = al(P->nfout * p2, el);
-    P->local = al(P->nanc * p2, el);
-    P->phi = al(2 * P->nfout * nm, el);
-    P->psi = al(2 * P->nfin * nm, el);
-    P->w0vals = al(P->nprob * p2, el);
+    auto add = [&](void *field, int64_t cnt, size_t sz) {
+        items.push_back({(void **)field, (size_t)std::max<int64_t>(cnt, 1) * sz});
+    };
+    add(&P->qs, P->n, 8);
+    add(&P->ufar, P->n, 8);
+    add(&P->ures, P->n, 8);
+    add(&P->proxy, P->nfout * p2, el);
+    add(&P->local, P->nanc * p2, el);
+    add(&P->phi, 2 * P->nfout * nm, el);
+    add(&P->psi, 2 * P->nfin * nm, el);
+    add(&P->w0vals, P->nprob * p2, el);
 }
 
 }  // namespace dmk

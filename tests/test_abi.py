@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 21
+    assert len(names) == 22
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:
@@ -43,6 +43,7 @@ def test_argument_errors_without_device():
     assert L.dmk_plan(3, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # NULL pts
     assert b"NULL" in L.dmk_last_error()
     assert L.dmk_eval(None, None, None, None) == -1
+    assert L.dmk_eval_noalloc(None, None, None, None) == -1
     off = np.array([0, 5, 3], dtype=np.int64)
     assert L.dmk_plan_batched(2, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
                               C.byref(h)) == -1  # decreasing offsets

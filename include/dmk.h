@@ -78,6 +78,12 @@ typedef struct {
     int32_t  reserved0;
     uint64_t flags;       /* DMK_FLAG_* bits (DMK_FLAG_BATCHED)               */
     double   lambda;      /* Yukawa parameter in input units (DMK_YUKAWA)     */
+    int32_t  p;           /* proxy (Chebyshev) order per axis; 0: from tol    */
+    int32_t  n_f;         /* plane-wave half width of D_l (N_1 = 2 n_f + 1);
+                             0: from tol.  A nonzero p and/or n_f must name a
+                             compiled pair: (9, 6), (15, 10) or (18, 12); the
+                             missing member is taken from that pair          */
+    double   pswf_c;      /* PSWF parameter c in [2, 40]; 0: from tol         */
 } dmk_opts;
 
 /* Batched execution of dmk_eval: the middle of the pipeline (upward pass,
@@ -135,8 +141,20 @@ typedef struct {
  *  kernel  DMK_LAPLACE (dim 3: 1/(4 pi r); dim 2: -log(r)/(2 pi)), or
  *          DMK_YUKAWA with dim 2 (K_0(lambda r), lambda from opts->lambda);
  *          DMK_YUKAWA with dim 3 gives DMK_ERR_UNSUPPORTED.
- *  tol     one of 1e-3, 1e-6, 1e-9, 1e-12 (Table 1) or 1e-5.  DMK_MIXED
- *          requires tol >= 1e-6 (else DMK_ERR_PRECISION).
+ *  tol     in [1e-12, 1e-2] (else DMK_ERR_ARG).  Parameters (c, n_f, p):
+ *          for tol = 1e-3, 1e-6 (Table 1) or 1e-5 (c = log 1e5, n_f = 10,
+ *          p = 15) the table's row; for any other tol, or when opts sets
+ *          pswf_c, c = opts->pswf_c or log(1/tol) (eq. pswfcvalue) and the
+ *          smallest n_f and p whose plane-wave and proxy errors on the
+ *          level-0 difference kernel stay within tol (the rule that gives
+ *          Table 1's N_1 and p at its tolerances), rounded up to the
+ *          smallest compiled (p, n_f) pair: (9, 6), (15, 10), (18, 12).
+ *          Tolerances that need more (below about 1e-6, including Table 1's
+ *          1e-9 and 1e-12 rows: p = 28 and 38) give DMK_ERR_UNSUPPORTED:
+ *          those proxy grids (p^3 = 22k and 55k values per box) do not fit
+ *          the kernels' per-box LDS staging.  The chosen values are reported
+ *          by dmk_plan_info.  DMK_MIXED requires tol >= 1e-6 (else
+ *          DMK_ERR_PRECISION).
  *  n       number of points, 0 <= n < 2^31.
  *  pts     device, [n][dim] FP64, row-major, input order.  Read during the
  *          call only; the plan keeps its own sorted copy.  Non-finite

@@ -95,6 +95,7 @@ def lib():
             build()
         L = C.CDLL(_LIBPATH)
         L.orc_params_for.argtypes = [C.c_double, _P(Params)]
+        L.orc_params_set.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, _P(Params)]
         L.orc_pswf_init.argtypes = [C.c_double, _P(Pswf)]
         for f in ("orc_pswf_eval", "orc_pswf_eval_ext", "orc_pswf_phi"):
             getattr(L, f).argtypes = [_P(Pswf), C.c_double]
@@ -178,6 +179,14 @@ def params_for(tol: float) -> Params:
     pr = Params()
     if lib().orc_params_for(tol, C.byref(pr)) != 0:
         raise ValueError(f"unsupported tolerance {tol}")
+    return pr
+
+
+def params_set(tol: float, c: float, nf: int, p: int, dim: int = 3) -> Params:
+    """Params for any (c, nf, p), root window spacing by the oracle's reading."""
+    pr = Params()
+    if lib().orc_params_set(float(tol), float(c), int(nf), int(p), int(dim), C.byref(pr)) != 0:
+        raise ValueError("bad parameters")
     return pr
 
 

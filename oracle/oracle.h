@@ -48,6 +48,7 @@ typedef struct {
 /* Parameters of Table 1 (c, N_1, p); tol 1e-5 uses c = log(1e5), nf = 10,
  * p = 15.  Returns 0 on success, -1 for an unsupported tol. */
 int orc_params_for(double tol, orc_params *out);
+int orc_params_set(double tol, double c, int nf, int p, int dim, orc_params *out);
 
 /* ------------------------------------------------------------------ PSWF */
 #define ORC_PSWF_MAXTERM 96

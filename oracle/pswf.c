@@ -284,6 +284,22 @@ double orc_split_w0_pw(const orc_pswf *ps, const orc_params *pr, const double x[
     return s;
 }
 
+/* Any (c, nf, p), e.g. a caller's choice for a tolerance off the table; the
+ * root window's spacing follows from its support as for the table rows (in
+ * d dimensions W_0 vanishes beyond A + s_0 = 2 + sqrt d and offsets inside
+ * the unit box reach 1 per axis). */
+int orc_params_set(double tol, double c, int nf, int p, int dim, orc_params *out)
+{
+    if (!(c > 0) || nf < 1 || p < 2 || (dim != 2 && dim != 3)) return -1;
+    out->tol = tol;
+    out->c = c;
+    out->nf = nf;
+    out->p = p;
+    out->hw = 2.0 * M_PI / (3.0 + sqrt((double)dim));
+    out->nw = (int)ceil(c / out->hw);
+    return 0;
+}
+
 /* Table 1 of the paper (c, N_1 = 2 nf + 1, p) and one row of our own for the
  * mixed-precision tolerance 1e-5 (c = log(1/eps), the rule of eq.
  * pswfcvalue). */

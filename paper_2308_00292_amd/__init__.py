@@ -36,7 +36,8 @@ STAGES = ["gather", "upward", "root", "proxy2pw", "local", "pwshift", "pw2grid",
 
 class Opts(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("max_depth", C.c_int32), ("precision", C.c_int32),
-                ("reserved0", C.c_int32), ("flags", C.c_uint64), ("lambda_", C.c_double)]
+                ("reserved0", C.c_int32), ("flags", C.c_uint64), ("lambda_", C.c_double),
+                ("p", C.c_int32), ("n_f", C.c_int32), ("pswf_c", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -149,7 +150,7 @@ class Plan:
     eval() applies dmk_eval to charge vectors."""
 
     def __init__(self, pts, tol=1e-6, leaf_max=64, max_depth=0, precision=DMK_FP64, flags=0,
-                 stream=None, kernel=DMK_LAPLACE, lam=0.0, offsets=None):
+                 stream=None, kernel=DMK_LAPLACE, lam=0.0, offsets=None, p=0, n_f=0, pswf_c=0.0):
         import torch
         if not (isinstance(pts, torch.Tensor) and pts.is_cuda and pts.dtype == torch.float64
                 and pts.dim() == 2 and pts.shape[1] in (2, 3)):
@@ -157,7 +158,7 @@ class Plan:
         pts = pts.contiguous()
         self.n = int(pts.shape[0])
         self.dim = int(pts.shape[1])
-        o = Opts(leaf_max, max_depth, precision, 0, flags, float(lam))
+        o = Opts(leaf_max, max_depth, precision, 0, flags, float(lam), int(p), int(n_f), float(pswf_c))
         h = C.c_void_p()
         if offsets is None:
             _check(lib().dmk_plan(self.dim, int(kernel), float(tol), self.n, _ptr(pts), C.byref(o),

@@ -78,6 +78,69 @@ const char *dmk_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
+// (p, n_f) pairs with compiled kernels, in increasing order
+constexpr int kBuilt[][2] = {{9, 6}, {15, 10}, {18, 12}};
+
+// c, n_f, p for tol: the parameter table's row (Table 1 plus 1e-5) when tol
+// has one and nothing is overridden; otherwise c = opts->pswf_c or
+// log(1/tol) (eq. pswfcvalue) and the search of Sec. 3.7 for n_f and p,
+// rounded up to the smallest compiled pair.  A caller's p and/or n_f must
+// name a compiled pair (the other member is taken from it).
+Params choose_params(double tol, int dim, const dmk_opts &o)
+{
+    if (o.p < 0 || o.n_f < 0 || o.pswf_c < 0 || !std::isfinite(o.pswf_c))
+        throw Error{DMK_ERR_ARG, "p, n_f and pswf_c must be >= 0"};
+    if (o.pswf_c != 0 && (o.pswf_c < 2.0 || o.pswf_c > 40.0)) throw Error{DMK_ERR_ARG, "pswf_c must lie in [2, 40]"};
+    Params prm;
+    const bool row = params_for(tol, &prm, dim);
+    auto built = [](int p, int nf) {
+        for (const auto &b : kBuilt)
+            if (b[0] == p && b[1] == nf) return true;
+        return false;
+    };
+    if (row && !o.p && !o.n_f && !o.pswf_c) {
+        if (!built(prm.p, prm.nf))
+            throw Error{DMK_ERR_UNSUPPORTED, "tol " + std::to_string(tol) + " needs proxy order p = " +
+                                                 std::to_string(prm.p) + ", not built (largest: 18, tol >= 1e-6)"};
+        return prm;
+    }
+    const double c = o.pswf_c ? o.pswf_c : (row ? prm.c : std::log(1.0 / tol));
+    int p = o.p, nf = o.n_f;
+    if (!p || !nf) {
+        if (p || nf) {  // one given: the compiled pair that has it
+            for (const auto &b : kBuilt)
+                if (b[0] == p || b[1] == nf) {
+                    p = b[0];
+                    nf = b[1];
+                    break;
+                }
+        } else {
+            Params sp;
+            search_params(tol, c, &sp, nullptr, nullptr);
+            for (const auto &b : kBuilt)
+                if (b[0] >= sp.p && b[1] >= sp.nf) {
+                    p = b[0];
+                    nf = b[1];
+                    break;
+                }
+            if (!p)
+                throw Error{DMK_ERR_UNSUPPORTED, "tol " + std::to_string(tol) + " needs p = " + std::to_string(sp.p) +
+                                                     ", n_f = " + std::to_string(sp.nf) +
+                                                     "; kernels are built for p <= 18, n_f <= 12"};
+        }
+    }
+    if (!built(p, nf))
+        throw Error{DMK_ERR_UNSUPPORTED, "(p, n_f) = (" + std::to_string(p) + ", " + std::to_string(nf) +
+                                             ") is not built; built pairs: (9, 6), (15, 10), (18, 12)"};
+    prm.tol = tol;
+    prm.c = c;
+    prm.p = p;
+    prm.nf = nf;
+    prm.hw = 2.0 * M_PI / (3.0 + std::sqrt((double)dim));
+    prm.nw = (int)std::ceil(c / prm.hw);
+    return prm;
+}
+
 // Shared by dmk_plan and dmk_plan_batched: validates, builds tables, the
 // forest of trees, lists and workspace.  poff: host offsets [nprob+1].
 dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *poff, const double *pts,
@@ -99,10 +162,8 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
     dmk_opts o;
     std::memset(&o, 0, sizeof(o));
     if (opts) o = *opts;
-    Params prm;
-    if (!params_for(tol, &prm, dim))
-        throw Error{DMK_ERR_UNSUPPORTED, "tol must be one of 1e-3, 1e-5, 1e-6, 1e-9, 1e-12"};
-    if (prm.p > 18) throw Error{DMK_ERR_UNSUPPORTED, "tol below 1e-6 needs proxy order > 18, not built"};
+    if (tol > 1e-2 || tol < 1e-12) throw Error{DMK_ERR_ARG, "tol must lie in [1e-12, 1e-2]"};
+    const Params prm = choose_params(tol, dim, o);
     if (o.precision != DMK_FP64 && o.precision != DMK_MIXED) throw Error{DMK_ERR_ARG, "unknown precision"};
     if (o.precision == DMK_MIXED && tol < 1e-6 * (1 - 1e-9))
         throw Error{DMK_ERR_PRECISION, "mixed precision needs tol >= 1e-6"};
@@ -468,6 +529,16 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
 {
     return guarded([&] {
         if (n < 0 || (n > 0 && !out)) throw Error{DMK_ERR_ARG, "bad n or out"};
+        if (what == 10) {  // parameter search: x[0] = c (0: log(1/tol)); out = c, n_f, p, errors
+            if (n < 5) throw Error{DMK_ERR_ARG, "n >= 5 needed"};
+            if (!(tol > 0 && tol < 1)) throw Error{DMK_ERR_ARG, "tol must lie in (0, 1)"};
+            const double c = (x && x[0] > 0) ? x[0] : std::log(1.0 / tol);
+            Params prm;
+            double e_nf = 0.0, e_p = 0.0;
+            search_params(tol, c, &prm, &e_nf, &e_p);
+            out[0] = prm.c; out[1] = prm.nf; out[2] = prm.p; out[3] = e_nf; out[4] = e_p;
+            return;
+        }
         const int dim = (what >= 6) ? 2 : 3;
         Params prm;
         if (!params_for(tol, &prm, dim)) throw Error{DMK_ERR_UNSUPPORTED, "tolerance not in the table"};

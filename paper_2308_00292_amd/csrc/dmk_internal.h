@@ -40,6 +40,9 @@ struct Params {
     double hw;   // plane-wave spacing of W_0 (root side 1)
 };
 bool params_for(double tol, Params *out, int dim = 3);
+// Sec. 3.7 for tolerances off the table: the smallest n_f and p meeting tol
+// for PSWF parameter c (errors of the chosen values returned if non-NULL).
+void search_params(double tol, double c, Params *out, double *err_nf, double *err_p);
 
 // Host-side tables, all FP64 (Step 1 of the algorithm).  In 2-D the
 // plane-wave arrays are [m1][m2] with m2 >= 0, the weights are those of the

@@ -451,4 +451,187 @@ void build_tables2(Tables *t)
     }
 }
 
+
+// ------------------------------------------------------ parameter search
+// For a tolerance without a row in the parameter table (Sec. 3.7): c from
+// the rule c ~ log(1/eps) of eq. pswfcvalue (or the caller's c), then the
+// smallest plane-wave half width n_f and the smallest proxy order p that
+// each meet eps, both measured on the level-0 difference kernel
+// D_0(r) = (Phi(2r) - Phi(r))/r (box side 1) relative to D_0(0) = psi(0)/c_0:
+//  * n_f: the trapezoidal sum over the modes m in [-n_f, n_f]^3 at spacing
+//    h = 2 pi/3 against D_0(|x|) for offsets x in the colleague range
+//    [-2, 2]^3;
+//  * p: the tensor interpolant on p first-kind Chebyshev nodes per axis of
+//    y -> D_0(|x - y|) over the source box [-1/2, 1/2]^3 against D_0 itself,
+//    for targets x in [-3/2, 3/2]^3 (the box and its colleagues).
+// Sample points are a fixed Halton sequence, so the search is deterministic.
+// At the table's tolerances (with its c) it returns the table's N_1 and p.
+namespace {
+
+double halton(int i, int base)
+{
+    double f = 1.0, r = 0.0;
+    for (int k = i + 1; k > 0; k /= base) {
+        f /= base;
+        r += f * (k % base);
+    }
+    return r;
+}
+
+struct D0Eval {
+    const Tables &t;
+    double d00;
+    explicit D0Eval(const Tables &tt) : t(tt), d00(tt.psi0 / tt.c0) {}
+    // g(t) = Phi(sqrt t)/sqrt t on [0, 1] from its Chebyshev series in 2t - 1
+    double g(double tt) const
+    {
+        const double u = 2.0 * tt - 1.0;
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = t.gdeg; k >= 1; --k) {
+            const double b0 = t.gcheb[k] + 2.0 * u * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
+        return t.gcheb[0] + u * b1 - b2;
+    }
+    // D_0(r) = (Phi(2r) - Phi(r))/r, Phi(x) = x g(x^2) below 1 and 1 beyond
+    double operator()(double r) const
+    {
+        if (r >= 1.0) return 0.0;
+        const double inner = g(r * r);
+        if (2.0 * r < 1.0) return 2.0 * g(4.0 * r * r) - inner;
+        return 1.0 / r - inner;
+    }
+};
+
+double pw_error(const Tables &t, const D0Eval &D0, int nf)
+{
+    const double c = t.prm.c, h = 2.0 * M_PI / 3.0;
+    const int nn = 2 * nf + 1, maxk2 = 3 * nf * nf;
+    std::vector<double> w(maxk2 + 1);
+    // weights (h/2pi)^3 Dhat_0(h|m|) of the 1/r split,
+    // Dhat_0(k) = 4 pi [psi(k/(2c)) - psi(k/c)]/(psi(0) k^2), Dhat_0(0) = 2 pi (c_2/c_0)(1 - 1/4)
+    const double fac = std::pow(h / (2.0 * M_PI), 3);
+    w[0] = fac * 2.0 * M_PI * t.c2 / t.c0 * (1.0 - 0.25);
+    for (int k2 = 1; k2 <= maxk2; ++k2) {
+        double k = h * std::sqrt((double)k2);
+        w[k2] = fac * 4.0 * M_PI * (pswf_eval(t, 0.5 * k / c) - pswf_eval(t, k / c)) / (t.psi0 * k * k);
+    }
+    std::vector<double> er(3 * nn), ei(3 * nn);
+    double err = 0.0;
+    const int NS = 96;
+    for (int s = 0; s < NS + 24; ++s) {
+        double x[3];
+        if (s < NS) {
+            for (int d = 0; d < 3; ++d) x[d] = 4.0 * halton(s, d == 0 ? 2 : (d == 1 ? 3 : 5)) - 2.0;
+        } else {  // points on an axis and on the diagonal
+            double u = 2.0 * ((s - NS) % 12) / 11.0;
+            x[0] = u;
+            x[1] = x[2] = (s - NS < 12) ? 0.0 : u;
+        }
+        for (int d = 0; d < 3; ++d)
+            for (int m = -nf; m <= nf; ++m) {
+                er[d * nn + m + nf] = std::cos(h * m * x[d]);
+                ei[d * nn + m + nf] = std::sin(h * m * x[d]);
+            }
+        double sum = 0.0;
+        for (int m1 = -nf; m1 <= nf; ++m1)
+            for (int m2 = -nf; m2 <= nf; ++m2) {
+                const double ar = er[m1 + nf] * er[nn + m2 + nf] - ei[m1 + nf] * ei[nn + m2 + nf];
+                const double ai = er[m1 + nf] * ei[nn + m2 + nf] + ei[m1 + nf] * er[nn + m2 + nf];
+                const int b2 = m1 * m1 + m2 * m2;
+                for (int m3 = -nf; m3 <= nf; ++m3)
+                    sum += w[b2 + m3 * m3] * (ar * er[2 * nn + m3 + nf] - ai * ei[2 * nn + m3 + nf]);
+            }
+        const double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        err = std::max(err, std::fabs(sum - D0(r)));
+    }
+    return err / D0.d00;
+}
+
+double proxy_error(const Tables &t, const D0Eval &D0, int p)
+{
+    std::vector<double> nodes(p), bw(p);
+    for (int j = 0; j < p; ++j) {
+        nodes[j] = 0.5 * std::cos(M_PI * (j + 0.5) / p);
+        bw[j] = ((j & 1) ? -1.0 : 1.0) * std::sin((2 * j + 1) * M_PI / (2.0 * p));
+    }
+    auto basis = [&](double y, double *out) {
+        for (int a = 0; a < p; ++a)
+            if (y == nodes[a]) {
+                for (int b = 0; b < p; ++b) out[b] = (a == b) ? 1.0 : 0.0;
+                return;
+            }
+        double den = 0.0;
+        for (int a = 0; a < p; ++a) den += (out[a] = bw[a] / (y - nodes[a]));
+        for (int a = 0; a < p; ++a) out[a] /= den;
+    };
+    const int NX = 48, NY = 64;
+    std::vector<double> V((size_t)p * p * p), L((size_t)3 * NY * p), ys((size_t)3 * NY), t1((size_t)p * p), t2(p);
+    for (int j = 0; j < NY; ++j)
+        for (int d = 0; d < 3; ++d) {
+            ys[3 * j + d] = halton(j + 7, d == 0 ? 7 : (d == 1 ? 11 : 13)) - 0.5;
+            basis(ys[3 * j + d], &L[((size_t)d * NY + j) * p]);
+        }
+    double err = 0.0;
+    for (int s = 0; s < NX; ++s) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = 3.0 * halton(s + 3, d == 0 ? 2 : (d == 1 ? 3 : 5)) - 1.5;
+        for (int i = 0; i < p; ++i)
+            for (int j = 0; j < p; ++j)
+                for (int k = 0; k < p; ++k) {
+                    const double a = x[0] - nodes[i], b = x[1] - nodes[j], cc = x[2] - nodes[k];
+                    V[((size_t)i * p + j) * p + k] = D0(std::sqrt(a * a + b * b + cc * cc));
+                }
+        for (int yj = 0; yj < NY; ++yj) {
+            const double *l1 = &L[(size_t)yj * p], *l2 = &L[((size_t)NY + yj) * p], *l3 = &L[((size_t)2 * NY + yj) * p];
+            double v = 0.0;
+            for (int i = 0; i < p; ++i) {
+                double si = 0.0;
+                for (int j = 0; j < p; ++j) {
+                    const double *row = &V[((size_t)i * p + j) * p];
+                    double sj = 0.0;
+                    for (int k = 0; k < p; ++k) sj += l3[k] * row[k];
+                    si += l2[j] * sj;
+                }
+                v += l1[i] * si;
+            }
+            const double a = x[0] - ys[3 * yj], b = x[1] - ys[3 * yj + 1], cc = x[2] - ys[3 * yj + 2];
+            err = std::max(err, std::fabs(v - D0(std::sqrt(a * a + b * b + cc * cc))));
+        }
+    }
+    return err / D0.d00;
+}
+
+}  // namespace
+
+void search_params(double tol, double c, Params *out, double *err_nf, double *err_p)
+{
+    Params prm{};
+    prm.tol = tol;
+    prm.c = c;
+    prm.nf = 1;
+    prm.p = 2;
+    prm.nw = 1;
+    prm.hw = 1.0;
+    Tables t;
+    build_tables(prm, &t, 3);
+    const D0Eval D0(t);
+    // errors fall with n_f and p until the split's own floor; start below
+    // the table's ratios (n_f ~ 0.87 c / (pi 2/3) ... p ~ 1.3 c) and step up
+    int nf = std::max(1, (int)std::floor(0.5 * c)), p = std::max(2, (int)std::floor(0.9 * c));
+    double e = pw_error(t, D0, nf);
+    while (nf > 1 && e <= tol) e = pw_error(t, D0, --nf);  // make sure the start is below the answer
+    while (e > tol && nf < 64) e = pw_error(t, D0, ++nf);
+    if (err_nf) *err_nf = e;
+    double ep = proxy_error(t, D0, p);
+    while (p > 2 && ep <= tol) ep = proxy_error(t, D0, --p);
+    while (ep > tol && p < 64) ep = proxy_error(t, D0, ++p);
+    if (err_p) *err_p = ep;
+    out->tol = tol;
+    out->c = c;
+    out->nf = nf;
+    out->p = p;
+}
+
 }  // namespace dmk

@@ -144,3 +144,39 @@ def test_host_tables_2d_match_oracle(oracle_mod):
     got = dmk.precompute_probe(1e-6, 8, xs)
     ref = np.array([ps.smooth_quad(0, 0.0, x) for x in xs])
     assert np.max(np.abs(got - ref)) < 1e-13
+
+
+def test_parameter_search_reproduces_table1():
+    """The library's parameter search (smallest n_f and p meeting eps on the
+    level-0 difference kernel, Sec. 3.7) run at Table 1's tolerances with
+    Table 1's c gives Table 1's N_1 = 2 n_f + 1 and p (tests/golden), and at
+    1e-5 with c = log(1/eps) (eq. pswfcvalue) the library's own 1e-5 row
+    (n_f = 10, p = 15).  The errors of the chosen values meet eps."""
+    from conftest import golden
+    for eps, c, n1, p in golden("table1_pswf_params.txt"):
+        eps, c, n1, p = float(eps), float(c), int(n1), int(p)
+        got = dmk.precompute_probe(eps, 10, np.array([c, 0.0, 0.0, 0.0, 0.0]))
+        assert (2 * int(got[1]) + 1, int(got[2])) == (n1, p), (eps, got)
+        assert got[3] <= eps and got[4] <= eps
+    got = dmk.precompute_probe(1e-5, 10, np.zeros(5))
+    assert got[0] == pytest.approx(np.log(1e5), rel=1e-15)
+    assert (int(got[1]), int(got[2])) == (10, 15)
+
+
+def test_parameter_choice_errors_without_device():
+    """Plans whose parameters cannot be built fail before any device work."""
+    L = dmk.lib()
+    h = C.c_void_p()
+    one = C.c_void_p(1)
+    assert L.dmk_plan(3, 0, 0.5, 10, one, None, None, C.byref(h)) == -1  # tol above 1e-2
+    assert L.dmk_plan(3, 0, 1e-13, 10, one, None, None, C.byref(h)) == -1  # tol below 1e-12
+    assert L.dmk_plan(3, 0, 1e-9, 10, one, None, None, C.byref(h)) == -2  # Table 1 row, p = 28 not built
+    assert b"p = 28" in L.dmk_last_error()
+    assert L.dmk_plan(3, 0, 1e-7, 10, one, None, None, C.byref(h)) == -2  # off the table, search needs p > 18
+    for kw, code in ((dict(p=12), -2), (dict(p=18, n_f=10), -2), (dict(n_f=7), -2), (dict(pswf_c=1.0), -1),
+                     (dict(p=-1), -1)):
+        o = dmk.Opts(0, 0, 0, 0, 0, 0.0, kw.get("p", 0), kw.get("n_f", 0), kw.get("pswf_c", 0.0))
+        assert L.dmk_plan(3, 0, 1e-6, 10, one, C.byref(o), None, C.byref(h)) == code, kw
+    o = dmk.Opts(0, 0, 1, 0, 0, 0.0)
+    assert L.dmk_plan(3, 0, 3e-7, 10, one, C.byref(o), None, C.byref(h)) in (-2, -5)
+    assert h.value is None

@@ -21,12 +21,12 @@
 // l is (problem << d l) | Morton prefix, level 0 holds one root per problem,
 // and neighbour searches never leave a problem.  Each problem has its own
 // root box from its own bounding box.
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
 
 #include "dmk_internal.h"
+#include "prim.h"
 
 namespace dmk {
 
@@ -448,16 +448,10 @@ int64_t sort_unique(Scratch &S, uint64_t *in, int64_t n, uint64_t **out, hipStre
 {
     if (n == 0) { *out = S.get<uint64_t>(1); return 0; }
     uint64_t *sorted = S.get<uint64_t>(n);
-    size_t tb = 0;
-    DMK_HIP(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, in, sorted, (int)n, 0, 64, s));
-    void *tmp = S.get<char>((int64_t)tb);
-    DMK_HIP(hipcub::DeviceRadixSort::SortKeys(tmp, tb, in, sorted, (int)n, 0, 64, s));
+    prim::sort_pairs(S, (const uint64_t *)in, sorted, (const int32_t *)nullptr, (int32_t *)nullptr, n, 64, s);
     uint64_t *uniq = S.get<uint64_t>(n);
     int64_t *cnt = S.get<int64_t>(1);
-    tb = 0;
-    DMK_HIP(hipcub::DeviceSelect::Unique(nullptr, tb, sorted, uniq, cnt, (int)n, s));
-    tmp = S.get<char>((int64_t)tb);
-    DMK_HIP(hipcub::DeviceSelect::Unique(tmp, tb, sorted, uniq, cnt, (int)n, s));
+    prim::unique_sorted(S, (const uint64_t *)sorted, uniq, cnt, n, s);
     int64_t m = 0;
     DMK_HIP(hipMemcpyAsync(&m, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DMK_HIP(hipStreamSynchronize(s));
@@ -545,10 +539,7 @@ static void build_tree_t(Plan *P, const double *pts, hipStream_t s)
         hipLaunchKernelGGL(k_keys<D>, dim3(nblk(n)), dim3(TPB), 0, s, pts, n, P->d_poff, nprob, P->d_pcenter,
                            P->d_pside, kb, xn, k0, i0);
         const int endbit = D * kb + P->pbits;
-        size_t tb = 0;
-        DMK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, P->keys, i0, P->perm, (int)n, 0, endbit, s));
-        void *tmp = S.get<char>((int64_t)tb);
-        DMK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, k0, P->keys, i0, P->perm, (int)n, 0, endbit, s));
+        prim::sort_pairs(S, (const uint64_t *)k0, P->keys, (const int32_t *)i0, P->perm, n, endbit, s);
         hipLaunchKernelGGL(k_gather_points<D>, dim3(nblk(n)), dim3(TPB), 0, s, xn, P->perm, n, P->X, P->Y, P->Z);
     }
 
@@ -575,10 +566,7 @@ static void build_tree_t(Plan *P, const double *pts, hipStream_t s)
                            P->leaf_max, flag);
         uint64_t *sel = S.get<uint64_t>(nex);
         int64_t *cnt = S.get<int64_t>(1);
-        size_t tb = 0;
-        DMK_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb, ex, flag, sel, cnt, (int)nex, s));
-        void *tmp = S.get<char>((int64_t)tb);
-        DMK_HIP(hipcub::DeviceSelect::Flagged(tmp, tb, ex, flag, sel, cnt, (int)nex, s));
+        prim::select_flagged(S, (const uint64_t *)ex, (uint64_t)0, (const uint8_t *)flag, sel, cnt, nex, s);
         int64_t m = 0;
         DMK_HIP(hipMemcpyAsync(&m, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         DMK_HIP(hipStreamSynchronize(s));
@@ -843,12 +831,8 @@ int64_t select_indices(Scratch &S, const uint8_t *flag, int64_t first, int64_t c
                        hipStream_t s)
 {
     if (count == 0) return 0;
-    hipcub::CountingInputIterator<int32_t> it((int32_t)first);
     int64_t *cnt = S.get<int64_t>(1);
-    size_t tb = 0;
-    DMK_HIP(hipcub::DeviceSelect::Flagged(nullptr, tb, it, flag + first, out, cnt, (int)count, s));
-    void *tmp = S.get<char>((int64_t)tb);
-    DMK_HIP(hipcub::DeviceSelect::Flagged(tmp, tb, it, flag + first, out, cnt, (int)count, s));
+    prim::select_flagged(S, (const int32_t *)nullptr, (int32_t)first, flag + first, out, cnt, count, s);
     int64_t m = 0;
     DMK_HIP(hipMemcpyAsync(&m, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DMK_HIP(hipStreamSynchronize(s));
@@ -977,24 +961,18 @@ static void build_lists_t(Plan *P, hipStream_t s)
             int32_t *skey = S.get<int32_t>(nleaf), *sleaf = S.get<int32_t>(nleaf);
             hipLaunchKernelGGL(k_leaf_keys, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, P->anchor,
                                P->local_slot, P->pcount, key, ident, cnt);
-            size_t tb = 0;
-            DMK_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, key, skey, ident, sleaf, (int)nleaf, 0, 32, s));
-            void *tmp = S.get<char>((int64_t)tb);
-            DMK_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, key, skey, ident, sleaf, (int)nleaf, 0, 32, s));
+            int kbits = 1;  // keys are anchor slots in [0, nanc)
+            while ((int64_t(1) << kbits) < nanc) ++kbits;
+            prim::sort_pairs(S, (const uint32_t *)key, (uint32_t *)skey, (const int32_t *)ident, sleaf, nleaf, kbits,
+                             s);
             int32_t *lc = S.get<int32_t>(nleaf + 1), *pos = S.get<int32_t>(nleaf + 1);
             hipLaunchKernelGGL(k_leaf_counts, dim3(nblk(nleaf)), dim3(TPB), 0, s, sleaf, nleaf, P->pcount, lc);
             DMK_HIP(hipMemsetAsync(lc + nleaf, 0, sizeof(int32_t), s));
-            tb = 0;
-            DMK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, lc, pos, (int)nleaf + 1, s));
-            tmp = S.get<char>((int64_t)tb);
-            DMK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, lc, pos, (int)nleaf + 1, s));
+            prim::exclusive_scan(S, lc, pos, nleaf + 1, s);
             hipLaunchKernelGGL(k_fill_targets, dim3((unsigned)nleaf), dim3(TPB), 0, s, sleaf, nleaf, P->pstart,
                                P->pcount, pos, P->anc_tgt);
         }
-        size_t tb = 0;
-        DMK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, P->anc_tbeg, (int)nanc + 1, s));
-        void *tmp = S.get<char>((int64_t)tb);
-        DMK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, P->anc_tbeg, (int)nanc + 1, s));
+        prim::exclusive_scan(S, cnt, P->anc_tbeg, nanc + 1, s);
     }
 
     // near lists over the leaf order
@@ -1013,22 +991,16 @@ static void build_lists_t(Plan *P, hipStream_t s)
         hipLaunchKernelGGL((k_near_lists<D, false>), dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
                            P->blevel, P->parent, P->colleague, P->bflags, P->pcount, cnt, (const int32_t *)nullptr,
                            (int32_t *)nullptr, (int32_t *)nullptr, pairs);
-        size_t tb = 0;
-        DMK_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, P->nl_off, (int)nleaf + 1, s));
         // exclusive sum over nleaf+1 entries needs a trailing zero in the input
         int32_t *cnt1 = S.get<int32_t>(nleaf + 1);
         DMK_HIP(hipMemcpyAsync(cnt1, cnt, nleaf * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         DMK_HIP(hipMemsetAsync(cnt1 + nleaf, 0, sizeof(int32_t), s));
-        void *tmp = S.get<char>((int64_t)tb);
-        DMK_HIP(hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt1, P->nl_off, (int)nleaf + 1, s));
+        prim::exclusive_scan(S, cnt1, P->nl_off, nleaf + 1, s);
         int32_t total = 0;
         DMK_HIP(hipMemcpyAsync(&total, P->nl_off + nleaf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         {
             int32_t *mx = S.get<int32_t>(1);
-            size_t tbm = 0;
-            DMK_HIP(hipcub::DeviceReduce::Max(nullptr, tbm, cnt, mx, (int)nleaf, s));
-            void *tmpm = S.get<char>((int64_t)tbm);
-            DMK_HIP(hipcub::DeviceReduce::Max(tmpm, tbm, cnt, mx, (int)nleaf, s));
+            prim::reduce_max(cnt, nleaf, mx, s);
             int32_t hmx = 0;
             DMK_HIP(hipMemcpyAsync(&hmx, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             DMK_HIP(hipStreamSynchronize(s));
@@ -1037,10 +1009,7 @@ static void build_lists_t(Plan *P, hipStream_t s)
             P->nl_max = hmx;
         }
         int64_t *psum = S.get<int64_t>(1);
-        tb = 0;
-        DMK_HIP(hipcub::DeviceReduce::Sum(nullptr, tb, pairs, psum, (int)nleaf, s));
-        tmp = S.get<char>((int64_t)tb);
-        DMK_HIP(hipcub::DeviceReduce::Sum(tmp, tb, pairs, psum, (int)nleaf, s));
+        prim::reduce_sum(pairs, nleaf, psum, s);
         DMK_HIP(hipMemcpyAsync(&P->npairs, psum, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         DMK_HIP(hipStreamSynchronize(s));
         P->nl_total = total;

@@ -67,6 +67,11 @@ class _Split2(C.Structure):
                 ("coef", _f64p), ("self", _f64p)]
 
 
+class _Split3(C.Structure):
+    _fields_ = [("lam", C.c_double), ("nlev", C.c_int), ("deg", C.c_int), ("coef", _P(C.c_double)),
+                ("self", _P(C.c_double))]
+
+
 class VParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("q", C.c_int), ("sigma0", C.c_double), ("p", C.c_int), ("nf", C.c_int),
                 ("nw", C.c_int), ("hw", C.c_double), ("nleg", C.c_int), ("tau_a", C.c_double),
@@ -84,6 +89,7 @@ class _VResult(C.Structure):
 DENSITY_FN = C.CFUNCTYPE(None, C.c_int64, _f64p, _f64p, C.c_void_p)
 
 LOG2, YUK2 = 0, 1  # 2-D kernels: -log(r)/(2 pi) and K_0(lambda r)
+LAP3, YUK3 = 0, 1  # 3-D kernels: 1/(4 pi r) and exp(-lambda r)/(4 pi r)
 
 _lib = None
 
@@ -148,6 +154,23 @@ def lib():
         L.orc_dmk2_eval.argtypes = [_P(_Tree), _P(Params), _P(Pswf), C.c_int, C.c_double, _f64p, C.c_int,
                                     _P(_Result)]
         L.orc_direct2.argtypes = [C.c_int, C.c_double, C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
+        # 3-D Yukawa
+        L.orc_dmk_eval_k.argtypes = [_P(_Tree), _P(Params), _P(Pswf), C.c_int, C.c_double, _f64p, C.c_int,
+                                     _P(_Result)]
+        L.orc_y3_dhat.argtypes = [_P(Pswf), C.c_double, C.c_int, C.c_double]
+        L.orc_y3_that.argtypes = [C.c_double, C.c_double]
+        L.orc_y3_w0hat.argtypes = [_P(Pswf), C.c_double, C.c_double]
+        L.orc_y3_smooth_quad.argtypes = [_P(Pswf), C.c_double, C.c_double]
+        for f in ("orc_y3_dhat", "orc_y3_that", "orc_y3_w0hat", "orc_y3_smooth_quad", "orc_y3_smooth",
+                  "orc_y3_residual", "orc_y3_d_pw", "orc_y3_w0_pw"):
+            getattr(L, f).restype = C.c_double
+        L.orc_y3_split_init.argtypes = [_P(Pswf), C.c_double, C.c_int, _P(_Split3)]
+        L.orc_y3_split_free.argtypes = [_P(_Split3)]
+        L.orc_y3_smooth.argtypes = [_P(_Split3), C.c_int, C.c_double]
+        L.orc_y3_residual.argtypes = [_P(_Split3), C.c_int, C.c_double]
+        L.orc_y3_d_pw.argtypes = [_P(Pswf), _P(Params), C.c_double, C.c_int, _f64p]
+        L.orc_y3_w0_pw.argtypes = [_P(Pswf), _P(Params), C.c_double, _f64p]
+        L.orc_direct_yuk3.argtypes = [C.c_double, C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
         # volume
         L.orc_vparams_for.argtypes = [C.c_double, C.c_int, _P(VParams)]
         for f in ("orc_gsplit_m", "orc_gsplit_d", "orc_gsplit_r", "orc_gdhat"):
@@ -257,6 +280,65 @@ class PSWF:
         return lib().orc2_w0_pw(C.byref(self.s), C.byref(params), int(kern), float(lam), _dp(x))
 
 
+class Yuk3:
+    """The 3-D Yukawa split e^{-lam r}/r (root-box units): transforms,
+    mollified kernel by quadrature, per-level tables, plane-wave sums."""
+
+    def __init__(self, pswf: "PSWF", lam: float, nlev: int = 0):
+        self.ps, self.lam = pswf, float(lam)
+        self._s = None
+        if nlev:
+            self._s = _Split3()
+            lib().orc_y3_split_init(C.byref(pswf.s), self.lam, int(nlev), C.byref(self._s))
+            self.self_ = np.ctypeslib.as_array(self._s.self, shape=(nlev,)).copy()
+
+    def dhat(self, l, k):
+        return lib().orc_y3_dhat(C.byref(self.ps.s), self.lam, int(l), float(k))
+
+    def that(self, k):
+        return lib().orc_y3_that(self.lam, float(k))
+
+    def w0hat(self, k):
+        return lib().orc_y3_w0hat(C.byref(self.ps.s), self.lam, float(k))
+
+    def smooth_quad(self, mu, x):
+        return lib().orc_y3_smooth_quad(C.byref(self.ps.s), float(mu), float(x))
+
+    def smooth(self, l, x):
+        return lib().orc_y3_smooth(C.byref(self._s), int(l), float(x))
+
+    def residual(self, l, r):
+        return lib().orc_y3_residual(C.byref(self._s), int(l), float(r))
+
+    def d_pw(self, params: "Params", l, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_y3_d_pw(C.byref(self.ps.s), C.byref(params), self.lam, int(l), _dp(x))
+
+    def w0_pw(self, params: "Params", x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_y3_w0_pw(C.byref(self.ps.s), C.byref(params), self.lam, _dp(x))
+
+    def __del__(self):
+        try:
+            if self._s is not None:
+                lib().orc_y3_split_free(C.byref(self._s))
+        except Exception:
+            pass
+
+
+def direct_yuk3(lam, pts, charges, tidx=None):
+    """u_i = sum_{j != i, r > 0} q_j exp(-lam r_ij)/(4 pi r_ij) (lam in input units)."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    n = pts.shape[0]
+    if tidx is None:
+        tidx = np.arange(n, dtype=np.int64)
+    tidx = np.ascontiguousarray(tidx, dtype=np.int64)
+    out = np.zeros(len(tidx))
+    lib().orc_direct_yuk3(float(lam), n, _dp(pts), _dp(q), len(tidx), tidx.ctypes.data_as(_i64p), _dp(out))
+    return out
+
+
 class Split2:
     """Per-level residual tables of the 2-D split (smooth part and M_l(0))."""
 
@@ -363,15 +445,15 @@ def dmk_eval(tree: Tree, params: Params, pswf: PSWF, charges: np.ndarray, keep: 
     """Run Steps 2-5 on a built tree.  Returns a dict with the potential in
     input order (u) and, in sorted order and normalised units, the far and
     residual parts; with keep=True also the per-box proxies and local values.
-    2-D trees use kern (LOG2 / YUK2) and lam (input units)."""
+    kern and lam (input units): 2-D trees LOG2 / YUK2; 3-D trees LAP3 / YUK3."""
     q = np.ascontiguousarray(charges, dtype=np.float64)
     res = _Result()
     if tree.dim == 2:
         rc = lib().orc_dmk2_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), int(kern), float(lam),
                                  _dp(q), 1 if keep else 0, C.byref(res))
-    else:
-        rc = lib().orc_dmk_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), _dp(q),
-                                1 if keep else 0, C.byref(res))
+    else:  # kern 0: 1/(4 pi r); kern 1: exp(-lam r)/(4 pi r)
+        rc = lib().orc_dmk_eval_k(C.byref(tree._t), C.byref(params), C.byref(pswf.s), int(kern), float(lam),
+                                  _dp(q), 1 if keep else 0, C.byref(res))
     if rc != 0:
         raise RuntimeError("orc_dmk_eval failed")
     n = tree.n

@@ -234,8 +234,16 @@ static void child_bits(const orc_tree *t, int64_t b, int o[3])
 int orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
                  const double *charges, int keep, orc_dmk_result *res)
 {
+    return orc_dmk_eval_k(t, pr, ps, ORC_LAP3, 0.0, charges, keep, res);
+}
+
+int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, int kern, double lam_in,
+                   const double *charges, int keep, orc_dmk_result *res)
+{
     memset(res, 0, sizeof(*res));
     if (t->dim != 3) return -1;
+    const double lam = lam_in * t->side; /* Yukawa parameter in root-box units */
+    if (kern == ORC_YUK3 && !(lam >= 1e-3)) return -1;
     const int64_t n = t->n;
     const int p = pr->p, p3 = p * p * p;
     const int nf = pr->nf, nn = 2 * nf + 1, n3 = nn * nn * nn;
@@ -313,7 +321,10 @@ int orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
         double fac = pow(hw / (2.0 * M_PI), 3);
         int maxk2 = 3 * nw * nw;
         double *memo = (double *)malloc((size_t)(maxk2 + 1) * sizeof(double));
-        for (int k2 = 0; k2 <= maxk2; ++k2) memo[k2] = fac * orc_w0hat(ps, hw * sqrt((double)k2));
+        for (int k2 = 0; k2 <= maxk2; ++k2) {
+            const double k = hw * sqrt((double)k2);
+            memo[k2] = fac * (kern == ORC_YUK3 ? orc_y3_w0hat(ps, lam, k) : orc_w0hat(ps, k));
+        }
         for (int a = 0; a < nwn; ++a)
             for (int bb = 0; bb < nwn; ++bb)
                 for (int cc = 0; cc < nwn; ++cc) {
@@ -343,7 +354,10 @@ int orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
         const double s = ldexp(1.0, -l);
         const double h = 2.0 * M_PI / (3.0 * s);
         double fac = pow(h / (2.0 * M_PI), 3);
-        for (int k2 = 0; k2 <= maxk2; ++k2) dmemo[k2] = fac * orc_dhat(ps, l, h * sqrt((double)k2));
+        for (int k2 = 0; k2 <= maxk2; ++k2) {
+            const double k = h * sqrt((double)k2);
+            dmemo[k2] = fac * (kern == ORC_YUK3 ? orc_y3_dhat(ps, lam, l, k) : orc_dhat(ps, l, k));
+        }
 
         /* outgoing expansions Phi_l(B) for F_out boxes */
 #pragma omp parallel for schedule(dynamic, 1)
@@ -447,12 +461,15 @@ int orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
     free(dmemo);
 
     /* ---- Steps 4-5: residual sums and self-interaction correction */
+    orc_split3 sp3;
+    memset(&sp3, 0, sizeof(sp3));
+    if (kern == ORC_YUK3) orc_y3_split_init(ps, lam, t->nlevels, &sp3);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t T = 0; T < nbox; ++T) {
         if (!t->terminal[T] || t->pcount[T] == 0) continue;
         const int l = t->level[T];
         const double s = ldexp(1.0, -l);
-        const double m0 = orc_split_m0(ps, l);
+        const double m0 = (kern == ORC_YUK3) ? sp3.self[l] : orc_split_m0(ps, l);
         int64_t lists[27 + 7][2];
         int nl = 0;
         for (int k = 0; k < 27; ++k) {
@@ -479,7 +496,8 @@ int orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
                     double r = sqrt(dx * dx + dy * dy + dz * dz);
                     double contrib;
                     if (r == 0.0) contrib = -m0 * q[j];
-                    else if (r < s) contrib = orc_split_r(ps, l, r) * q[j];
+                    else if (r < s)
+                        contrib = (kern == ORC_YUK3 ? orc_y3_residual(&sp3, l, r) : orc_split_r(ps, l, r)) * q[j];
                     else continue;
 #pragma omp atomic
                     res->ures[i] += contrib;
@@ -487,6 +505,7 @@ int orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
         }
     }
 
+    if (kern == ORC_YUK3) orc_y3_split_free(&sp3);
     const double scale = 1.0 / (4.0 * M_PI * t->side);
     for (int64_t i = 0; i < n; ++i) res->u[t->perm[i]] = (res->ufar[i] + res->ures[i]) * scale;
 

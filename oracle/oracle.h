@@ -23,8 +23,9 @@
  *     self-interaction correction.
  *   - Direct O(N M) summation with compensated accumulation (eq. laplacesum).
  *
- * Kernel: 3-D Laplace, K(r) = 1/(4 pi r).  Sources equal targets; the pair
- * i = j and pairs at distance exactly 0 are excluded from the sum.
+ * Kernels: 3-D Laplace, K(r) = 1/(4 pi r), and 3-D Yukawa e^{-lambda r}/(4 pi r)
+ * (yuk3.c); 2-D log and K_0 (split2.c, dmk2.c).  Sources equal targets; the
+ * pair i = j and pairs at distance exactly 0 are excluded from the sum.
  */
 #ifndef DMK_ORACLE_H
 #define DMK_ORACLE_H
@@ -134,6 +135,33 @@ typedef struct {
 
 int  orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
                   const double *charges, int keep, orc_dmk_result *res);
+/* The same with a choice of 3-D kernel: ORC_LAP3 1/(4 pi r) (physical-space
+ * PSWF split, Sec. 3.7) or ORC_YUK3 e^{-lambda r}/(4 pi r) (Fourier-space
+ * PSWF split, Sec. 4.6; lam in input units, > 0; see yuk3.c). */
+enum { ORC_LAP3 = 0, ORC_YUK3 = 1 };
+int  orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, int kern, double lam,
+                    const double *charges, int keep, orc_dmk_result *res);
+
+/* ---- 3-D Yukawa split (yuk3.c); lam in root-box units (lambda S) */
+#define ORC3_DEG 47   /* Chebyshev degree (in x^2) of the mollified-kernel tables */
+typedef struct {
+    double  lam;
+    int     nlev, deg;
+    double *coef;     /* [nlev][deg+1] m_mu(x), x = r/s_l, series in 2x^2 - 1 */
+    double *self;     /* [nlev] M_l(0)                                        */
+} orc_split3;
+double orc_y3_dhat(const orc_pswf *ps, double lam, int l, double k);
+double orc_y3_that(double lam, double k);   /* transform of K cut at (1+sqrt 3) */
+double orc_y3_w0hat(const orc_pswf *ps, double lam, double k);
+double orc_y3_smooth_quad(const orc_pswf *ps, double mu, double x);  /* m_mu(x) */
+int    orc_y3_split_init(const orc_pswf *ps, double lam, int nlev, orc_split3 *sp);
+void   orc_y3_split_free(orc_split3 *sp);
+double orc_y3_smooth(const orc_split3 *sp, int l, double x);
+double orc_y3_residual(const orc_split3 *sp, int l, double r);  /* r > 0, root units */
+double orc_y3_d_pw(const orc_pswf *ps, const orc_params *pr, double lam, int l, const double x[3]);
+double orc_y3_w0_pw(const orc_pswf *ps, const orc_params *pr, double lam, const double x[3]);
+void   orc_direct_yuk3(double lam, int64_t n, const double *pts, const double *q, int64_t nt,
+                       const int64_t *tidx, double *out);  /* lam in input units */
 void orc_dmk_result_free(const orc_tree *t, orc_dmk_result *res);
 
 /* Direct sum u_i = sum_{j != i, r_ij > 0} q_j / (4 pi r_ij) for the targets

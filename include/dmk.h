@@ -36,7 +36,7 @@
  *    stream.  Work is enqueued on it asynchronously unless stated otherwise.
  *  - Status codes only; no C++ exception crosses the ABI.  After a non-zero
  *    status, dmk_last_error() returns a message for the calling thread.
- *  - Implemented: DMK_LAPLACE in 2-D and 3-D; DMK_YUKAWA in 2-D.
+ *  - Implemented: DMK_LAPLACE and DMK_YUKAWA in 2-D and 3-D.
  */
 #ifndef DMK_H
 #define DMK_H
@@ -58,7 +58,8 @@ typedef enum {
 } dmk_status;
 
 /* DMK_LAPLACE: 1/(4 pi r) in 3-D, -log(r)/(2 pi) in 2-D.
- * DMK_YUKAWA: K_0(lambda r) in 2-D (lambda in dmk_opts). */
+ * DMK_YUKAWA: e^{-lambda r}/(4 pi r) in 3-D, K_0(lambda r) in 2-D (lambda in
+ * dmk_opts); both split in Fourier space with the PSWF (Sec. 4.6). */
 typedef enum { DMK_LAPLACE = 0, DMK_YUKAWA = 1 } dmk_kernel;
 
 /* Arithmetic of the eval pipeline.  Input and output are always FP64. */
@@ -139,8 +140,10 @@ typedef struct {
  *
  *  dim     2 or 3.
  *  kernel  DMK_LAPLACE (dim 3: 1/(4 pi r); dim 2: -log(r)/(2 pi)), or
- *          DMK_YUKAWA with dim 2 (K_0(lambda r), lambda from opts->lambda);
- *          DMK_YUKAWA with dim 3 gives DMK_ERR_UNSUPPORTED.
+ *          DMK_YUKAWA (dim 3: e^{-lambda r}/(4 pi r); dim 2: K_0(lambda r)),
+ *          lambda = opts->lambda > 0 in input units.  Limits (else
+ *          DMK_ERR_UNSUPPORTED): dim 3, lambda S in [1e-3, 1000]; dim 2,
+ *          lambda S <= 50 per problem (S the root box side).
  *  tol     in [1e-12, 1e-2] (else DMK_ERR_ARG).  Parameters (c, n_f, p):
  *          for tol = 1e-3, 1e-6 (Table 1) or 1e-5 (c = log 1e5, n_f = 10,
  *          p = 15) the table's row; for any other tol, or when opts sets

@@ -148,7 +148,6 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
 {
     if (dim != 2 && dim != 3) throw Error{DMK_ERR_ARG, "dim must be 2 or 3"};
     if (kernel != DMK_LAPLACE && kernel != DMK_YUKAWA) throw Error{DMK_ERR_ARG, "unknown kernel"};
-    if (kernel == DMK_YUKAWA && dim != 2) throw Error{DMK_ERR_UNSUPPORTED, "the Yukawa kernel is built for dim = 2"};
     if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
     if (nprob < 1) throw Error{DMK_ERR_ARG, "nprob must be >= 1"};
     if (dim == 3 && nprob > 1) throw Error{DMK_ERR_UNSUPPORTED, "batches of 3-D problems are not built"};
@@ -200,12 +199,21 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         upload_tables(P, s);
         build_tree(P, pts, s);
         build_lists(P, s);
-        if (kernel == DMK_YUKAWA) {
+        if (kernel == DMK_YUKAWA && dim == 2) {
             if (P->nlevels > 32) throw Error{DMK_ERR_UNSUPPORTED, "Yukawa plans hold at most 32 levels"};
             for (int b = 0; b < nprob; ++b)
                 if (o.lambda * P->pside[b] > 50.0)
                     throw Error{DMK_ERR_UNSUPPORTED, "lambda times a problem's extent must stay <= 50"};
             build_yukawa_tables(P, s);
+        } else if (kernel == DMK_YUKAWA) {
+            // lambda S: below 1e-3 the k -> 0 differences of the mollifier lose
+            // digits (and the kernel is 1/r to that precision); above 1000 every
+            // level's mollified kernel is zero and the direct sums carry all
+            const double ls = o.lambda * P->pside[0];
+            if (!(ls >= 1e-3 && ls <= 1000.0))
+                throw Error{DMK_ERR_UNSUPPORTED, "lambda times the point set's extent must lie in [1e-3, 1000]"};
+            if (P->nlevels > 32) throw Error{DMK_ERR_UNSUPPORTED, "Yukawa plans hold at most 32 levels"};
+            build_yukawa3_tables(P, s);
         }
         alloc_workspace(P);
         count_work(P, s);

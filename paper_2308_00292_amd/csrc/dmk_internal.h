@@ -303,7 +303,8 @@ void run_eval(Plan *P, const double *charges, double *pot, double *far_part, dou
 void count_work(Plan *P, hipStream_t s);
 void run_eval2(Plan *P, const double *charges, double *pot, double *far_part, double *near_part,
                hipStream_t s);
-void build_yukawa_tables(Plan *P, hipStream_t s);
+void build_yukawa_tables(Plan *P, hipStream_t s);   // 2-D K_0(lambda r)
+void build_yukawa3_tables(Plan *P, hipStream_t s);  // 3-D e^{-lambda r}/(4 pi r)
 void stage_work(const Plan *P, double *flops, double *bytes);
 
 // Records HIP events around one stage launch when timing is enabled.

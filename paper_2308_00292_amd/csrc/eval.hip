@@ -59,6 +59,13 @@ struct Dev {
     T *proxy, *local, *phi, *psi, *w0vals;
     double *ufar, *ures, *rootscratch;
     int64_t pwstride;  // elements per plane-wave set: nh * nn * nn modes, padded to a multiple of 64
+    // Yukawa e^{-lambda r}/r (null ywd for 1/r): per-level D_l weights, the
+    // mollified kernels' series per level, M_l(0), lambda in root units
+    const T *ywd, *ycheb;
+    const double *yself;
+    int64_t ywd_stride;
+    double ylam;
+    int ydeg, ynlev;
 };
 
 // ------------------------------------------------------------------ upward
@@ -407,9 +414,11 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
         }
     }
     T w[MPT];
-    const T scale = (T)ldexp(1.0, oct_level[o]);  // w_l = 2^l w_0 (scale invariance of 1/r)
+    // 1/r: w_l = 2^l w_0 (scale invariance); Yukawa: the level's own table
+    const T scale = D.ywd ? T(1) : (T)ldexp(1.0, oct_level[o]);
+    const T *wt = D.ywd ? D.ywd + (int64_t)oct_level[o] * D.ywd_stride : D.wd0;
 #pragma unroll
-    for (int u = 0; u < MPT; ++u) w[u] = (e0 + u < nmode) ? D.wd0[e0 + u] * scale : T(0);
+    for (int u = 0; u < MPT; ++u) w[u] = (e0 + u < nmode) ? wt[e0 + u] * scale : T(0);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int32_t d = dst[t];
@@ -1327,6 +1336,105 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     }
 }
 
+// Residual sums of the Yukawa kernel: e^{-lambda r}/r - M_l(r) for
+// 0 < r < s_l and -M_l(0) at r = 0, M_l(x s_l) = m_l(x)/s_l from the level's
+// Chebyshev series in u = 2x^2 - 1 (all levels' series in LDS).  Gather lists,
+// staging and thread layout as in k_residual.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_residual_y3(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
+                                                     const int32_t *nl_src, const int32_t *nl_pre)
+{
+    constexpr int RCAP = 512, YLEV = 32, YC = 48;
+    __shared__ union {
+        struct { T x[RCAP], y[RCAP], z[RCAP], q[RCAP], is[RCAP]; } s;
+        double part[TPB];
+    } stg;
+    __shared__ T yc[YLEV * YC];
+    __shared__ T yself[YLEV];
+    __shared__ int8_t slev[RCAP];
+    T *sx = stg.s.x, *sy = stg.s.y, *sz = stg.s.z, *sq = stg.s.q, *sis = stg.s.is;
+    double *part = stg.part;
+    extern __shared__ int32_t loff[];
+    const int32_t B = leaves[blockIdx.x];
+    const int64_t t0 = D.pstart[B];
+    const int nt = D.pcount[B];
+    const int32_t l0 = nl_off[blockIdx.x];
+    const int L = nl_off[blockIdx.x + 1] - l0;
+    const int deg = D.ydeg;
+    for (int k = threadIdx.x; k < D.ynlev * YC; k += TPB) yc[k] = D.ycheb[k];
+    for (int k = threadIdx.x; k < D.ynlev; k += TPB) yself[k] = (T)D.yself[k];
+    for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
+    __syncthreads();
+    const int nsrc = loff[L];
+    const T lam = (T)D.ylam;
+    const double cx = D.bcenter[3 * (int64_t)B], cy = D.bcenter[3 * (int64_t)B + 1], cz = D.bcenter[3 * (int64_t)B + 2];
+    const int tch = min(max(nt, 1), 64);
+    const int nsplit = TPB / tch;
+    const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
+    for (int tbase = 0; tbase < nt; tbase += tch) {
+        const bool active = (tbase + tl) < nt;
+        const int64_t it = t0 + tbase + (active ? tl : 0);
+        const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy), zt = (T)(D.Z[it] - cz);
+        double acc = 0.0;
+        for (int pb = 0; pb < nsrc; pb += RCAP) {
+            const int cnt = min(RCAP, nsrc - pb);
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < cnt; idx += TPB) {
+                const int g = pb + idx;
+                int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (loff[mid] <= g) lo = mid; else hi = mid - 1;
+                }
+                const int32_t Tb = nl_src[l0 + lo];
+                const int64_t j = D.pstart[Tb] + (g - loff[lo]);
+                const int lev = D.blevel[Tb];
+                sx[idx] = (T)(D.X[j] - cx);
+                sy[idx] = (T)(D.Y[j] - cy);
+                sz[idx] = (T)(D.Z[j] - cz);
+                sq[idx] = (T)D.qs[j];
+                sis[idx] = (T)ldexp(1.0, lev);
+                slev[idx] = (int8_t)lev;
+            }
+            __syncthreads();
+            T pacc = T(0);
+            for (int j = split; j < cnt && split < nsplit; j += nsplit) {
+                const T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T is = sis[j];
+                const T tt = r2 * is * is;
+                if (tt < T(1)) {
+                    const T *cf = yc + (int)slev[j] * YC;
+                    T val;
+                    if (r2 > T(0)) {
+                        const T u = T(2) * tt - T(1);
+                        T b1 = T(0), b2 = T(0);
+                        for (int k = deg; k >= 1; --k) {
+                            const T b0 = cf[k] + T(2) * u * b1 - b2;
+                            b2 = b1;
+                            b1 = b0;
+                        }
+                        const T r = sqrt(r2);
+                        val = exp(-lam * r) / r - (cf[0] + u * b1 - b2) * is;
+                    } else {
+                        val = -yself[slev[j]];
+                    }
+                    pacc += sq[j] * val;
+                }
+            }
+            acc += (double)pacc;
+        }
+        __syncthreads();
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        if (split == 0 && active) {
+            double sum = 0.0;
+            for (int k = 0; k < nsplit; ++k) sum += part[k * tch + tl];
+            D.ures[t0 + tbase + tl] = sum;
+        }
+    }
+}
+
 // ----------------------------------------------------------- root window
 // Root proxies -> W_0 plane waves (spacing hw, half width nw) times the
 // window weights -> values on the root grid, in FP64 (O(1) work per eval).
@@ -1631,6 +1739,22 @@ Dev<T> make_dev(Plan *P)
     D.w0vals = (T *)P->w0vals;
     D.ufar = P->ufar; D.ures = P->ures; D.rootscratch = P->rootscratch;
     D.pwstride = pw_stride(t);
+    D.ywd = nullptr;
+    D.ycheb = nullptr;
+    D.yself = nullptr;
+    D.ywd_stride = 0;
+    D.ylam = 0.0;
+    D.ydeg = 0;
+    D.ynlev = 0;
+    if (P->kernel == DMK_YUKAWA && P->dim == 3) {
+        D.ywd = (const T *)(f64 ? (void *)P->y_wd64 : (void *)P->y_wd32);
+        D.ycheb = (const T *)(f64 ? (void *)P->y_cheb64 : (void *)P->y_cheb32);
+        D.yself = P->y_self;
+        D.ywd_stride = (int64_t)t.nh * t.nn * t.nn;
+        D.ylam = P->lambda * P->pside[0];
+        D.ydeg = f64 ? P->y_deg : P->y_deg32;
+        D.ynlev = P->nlevels;
+    }
     return D;
 }
 
@@ -1654,6 +1778,10 @@ static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
 {
     const dim3 g((unsigned)Pl->nleaf), b(TPB);
     const size_t lds = sizeof(int32_t) * ((size_t)Pl->nl_max + 1);  // loff
+    if (D.ywd) {
+        hipLaunchKernelGGL((k_residual_y3<T>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        return;
+    }
     if (D.gdeg <= 7)
         hipLaunchKernelGGL((k_residual<T, 7>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     else if (D.gdeg <= 9)
@@ -2120,6 +2248,10 @@ void stage_work(const Plan *P, double *F, double *Bt)
     F[DMK_STAGE_LEAF] = 2 * p3 * N;
     Bt[DMK_STAGE_LEAF] = 40 * N + el * p3 * P->nanc_tgt;  // one block per anchor reads its values once
     F[DMK_STAGE_RESIDUAL] = 8.0 * P->npairs + (2.0 * gd + 8.0) * P->npairs_in;
+    if (P->kernel == DMK_YUKAWA) {  // Clenshaw (4 flop per term), exp and a division per pair in range
+        const double yd = (double)((P->precision == DMK_FP64) ? P->y_deg : P->y_deg32);
+        F[DMK_STAGE_RESIDUAL] = 8.0 * P->npairs + (4.0 * yd + 16.0) * P->npairs_in;
+    }
     Bt[DMK_STAGE_RESIDUAL] = 40 * N;
 }
 

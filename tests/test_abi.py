@@ -34,7 +34,7 @@ def test_argument_errors_without_device():
     h = C.c_void_p()
     assert L.dmk_plan(4, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # dim
     assert L.dmk_plan(2, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # 2-D, NULL pts
-    assert L.dmk_plan(3, 1, 1e-6, 10, None, None, None, C.byref(h)) == -2  # kernel
+    assert L.dmk_plan(3, 1, 1e-6, 10, None, None, None, C.byref(h)) == -1  # Yukawa without lambda
     assert L.dmk_plan(3, 7, 1e-6, 10, None, None, None, C.byref(h)) == -1  # unknown kernel
     o = dmk.Opts(0, 0, 0, 0, 0, 0.0)
     assert L.dmk_plan(2, 1, 1e-6, 10, C.c_void_p(1), C.byref(o), None, C.byref(h)) == -1  # Yukawa, lambda 0

@@ -72,6 +72,10 @@ class _Split3(C.Structure):
                 ("self", _P(C.c_double))]
 
 
+class _Pow2(C.Structure):
+    _fields_ = [("ps", C.c_void_p), ("c1", C.c_double), ("coef", C.c_double * 48)]
+
+
 class VParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("q", C.c_int), ("sigma0", C.c_double), ("p", C.c_int), ("nf", C.c_int),
                 ("nw", C.c_int), ("hw", C.c_double), ("nleg", C.c_int), ("tau_a", C.c_double),
@@ -89,7 +93,7 @@ class _VResult(C.Structure):
 DENSITY_FN = C.CFUNCTYPE(None, C.c_int64, _f64p, _f64p, C.c_void_p)
 
 LOG2, YUK2 = 0, 1  # 2-D kernels: -log(r)/(2 pi) and K_0(lambda r)
-LAP3, YUK3 = 0, 1  # 3-D kernels: 1/(4 pi r) and exp(-lambda r)/(4 pi r)
+LAP3, YUK3, POW3 = 0, 1, 2  # 3-D kernels: 1/(4 pi r), exp(-lambda r)/(4 pi r), 1/r^2
 
 _lib = None
 
@@ -171,6 +175,21 @@ def lib():
         L.orc_y3_d_pw.argtypes = [_P(Pswf), _P(Params), C.c_double, C.c_int, _f64p]
         L.orc_y3_w0_pw.argtypes = [_P(Pswf), _P(Params), C.c_double, _f64p]
         L.orc_direct_yuk3.argtypes = [C.c_double, C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
+        # 3-D 1/r^2
+        L.orc_p2_c1.argtypes = [_P(Pswf)]
+        L.orc_p2_phi_quad.argtypes = [_P(Pswf), C.c_double]
+        L.orc_p2_init.argtypes = [_P(Pswf), _P(_Pow2)]
+        for f in ("orc_p2_phi", "orc_p2_w0", "orc_p2_w0hat"):
+            getattr(L, f).argtypes = [_P(_Pow2), C.c_double]
+        L.orc_p2_m0.argtypes = [_P(_Pow2), C.c_int]
+        for f in ("orc_p2_d", "orc_p2_r", "orc_p2_dhat"):
+            getattr(L, f).argtypes = [_P(_Pow2), C.c_int, C.c_double]
+        L.orc_p2_d_pw.argtypes = [_P(_Pow2), _P(Params), C.c_int, _f64p]
+        L.orc_p2_w0_pw.argtypes = [_P(_Pow2), _P(Params), _f64p]
+        for f in ("orc_p2_c1", "orc_p2_phi_quad", "orc_p2_phi", "orc_p2_w0", "orc_p2_w0hat", "orc_p2_m0",
+                  "orc_p2_d", "orc_p2_r", "orc_p2_dhat", "orc_p2_d_pw", "orc_p2_w0_pw"):
+            getattr(L, f).restype = C.c_double
+        L.orc_direct_pow2.argtypes = [C.c_int64, _f64p, _f64p, C.c_int64, _i64p, _f64p]
         # volume
         L.orc_vparams_for.argtypes = [C.c_double, C.c_int, _P(VParams)]
         for f in ("orc_gsplit_m", "orc_gsplit_d", "orc_gsplit_r", "orc_gdhat"):
@@ -339,6 +358,61 @@ def direct_yuk3(lam, pts, charges, tidx=None):
     return out
 
 
+class Pow2:
+    """The 3-D 1/r^2 split (PSWF power function, root-box units)."""
+
+    def __init__(self, pswf: "PSWF"):
+        self.ps = pswf
+        self._t = _Pow2()
+        lib().orc_p2_init(C.byref(pswf.s), C.byref(self._t))
+        self.c1 = self._t.c1
+
+    def phi_quad(self, x):
+        return lib().orc_p2_phi_quad(C.byref(self.ps.s), float(x))
+
+    def phi(self, x):
+        return lib().orc_p2_phi(C.byref(self._t), float(x))
+
+    def m0(self, L):
+        return lib().orc_p2_m0(C.byref(self._t), int(L))
+
+    def d(self, l, r):
+        return lib().orc_p2_d(C.byref(self._t), int(l), float(r))
+
+    def r(self, L, r):
+        return lib().orc_p2_r(C.byref(self._t), int(L), float(r))
+
+    def w0(self, r):
+        return lib().orc_p2_w0(C.byref(self._t), float(r))
+
+    def dhat(self, l, k):
+        return lib().orc_p2_dhat(C.byref(self._t), int(l), float(k))
+
+    def w0hat(self, k):
+        return lib().orc_p2_w0hat(C.byref(self._t), float(k))
+
+    def d_pw(self, params: "Params", l, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_p2_d_pw(C.byref(self._t), C.byref(params), int(l), _dp(x))
+
+    def w0_pw(self, params: "Params", x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_p2_w0_pw(C.byref(self._t), C.byref(params), _dp(x))
+
+
+def direct_pow2(pts, charges, tidx=None):
+    """u_i = sum_{j != i, r > 0} q_j / r_ij^2."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    q = np.ascontiguousarray(charges, dtype=np.float64)
+    n = pts.shape[0]
+    if tidx is None:
+        tidx = np.arange(n, dtype=np.int64)
+    tidx = np.ascontiguousarray(tidx, dtype=np.int64)
+    out = np.zeros(len(tidx))
+    lib().orc_direct_pow2(n, _dp(pts), _dp(q), len(tidx), tidx.ctypes.data_as(_i64p), _dp(out))
+    return out
+
+
 class Split2:
     """Per-level residual tables of the 2-D split (smooth part and M_l(0))."""
 
@@ -451,7 +525,7 @@ def dmk_eval(tree: Tree, params: Params, pswf: PSWF, charges: np.ndarray, keep: 
     if tree.dim == 2:
         rc = lib().orc_dmk2_eval(C.byref(tree._t), C.byref(params), C.byref(pswf.s), int(kern), float(lam),
                                  _dp(q), 1 if keep else 0, C.byref(res))
-    else:  # kern 0: 1/(4 pi r); kern 1: exp(-lam r)/(4 pi r)
+    else:  # kern 0: 1/(4 pi r); kern 1: exp(-lam r)/(4 pi r); kern 2: 1/r^2
         rc = lib().orc_dmk_eval_k(C.byref(tree._t), C.byref(params), C.byref(pswf.s), int(kern), float(lam),
                                   _dp(q), 1 if keep else 0, C.byref(res))
     if rc != 0:

@@ -244,6 +244,9 @@ int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
     if (t->dim != 3) return -1;
     const double lam = lam_in * t->side; /* Yukawa parameter in root-box units */
     if (kern == ORC_YUK3 && !(lam >= 1e-3)) return -1;
+    if (kern != ORC_LAP3 && kern != ORC_YUK3 && kern != ORC_POW3) return -1;
+    orc_pow2 p2;
+    if (kern == ORC_POW3) orc_p2_init(ps, &p2);
     const int64_t n = t->n;
     const int p = pr->p, p3 = p * p * p;
     const int nf = pr->nf, nn = 2 * nf + 1, n3 = nn * nn * nn;
@@ -323,7 +326,9 @@ int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
         double *memo = (double *)malloc((size_t)(maxk2 + 1) * sizeof(double));
         for (int k2 = 0; k2 <= maxk2; ++k2) {
             const double k = hw * sqrt((double)k2);
-            memo[k2] = fac * (kern == ORC_YUK3 ? orc_y3_w0hat(ps, lam, k) : orc_w0hat(ps, k));
+            memo[k2] = fac * (kern == ORC_YUK3   ? orc_y3_w0hat(ps, lam, k)
+                              : kern == ORC_POW3 ? orc_p2_w0hat(&p2, k)
+                                                 : orc_w0hat(ps, k));
         }
         for (int a = 0; a < nwn; ++a)
             for (int bb = 0; bb < nwn; ++bb)
@@ -356,7 +361,9 @@ int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
         double fac = pow(h / (2.0 * M_PI), 3);
         for (int k2 = 0; k2 <= maxk2; ++k2) {
             const double k = h * sqrt((double)k2);
-            dmemo[k2] = fac * (kern == ORC_YUK3 ? orc_y3_dhat(ps, lam, l, k) : orc_dhat(ps, l, k));
+            dmemo[k2] = fac * (kern == ORC_YUK3   ? orc_y3_dhat(ps, lam, l, k)
+                               : kern == ORC_POW3 ? orc_p2_dhat(&p2, l, k)
+                                                  : orc_dhat(ps, l, k));
         }
 
         /* outgoing expansions Phi_l(B) for F_out boxes */
@@ -469,7 +476,7 @@ int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
         if (!t->terminal[T] || t->pcount[T] == 0) continue;
         const int l = t->level[T];
         const double s = ldexp(1.0, -l);
-        const double m0 = (kern == ORC_YUK3) ? sp3.self[l] : orc_split_m0(ps, l);
+        const double m0 = (kern == ORC_YUK3) ? sp3.self[l] : (kern == ORC_POW3) ? orc_p2_m0(&p2, l) : orc_split_m0(ps, l);
         int64_t lists[27 + 7][2];
         int nl = 0;
         for (int k = 0; k < 27; ++k) {
@@ -497,7 +504,10 @@ int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
                     double contrib;
                     if (r == 0.0) contrib = -m0 * q[j];
                     else if (r < s)
-                        contrib = (kern == ORC_YUK3 ? orc_y3_residual(&sp3, l, r) : orc_split_r(ps, l, r)) * q[j];
+                        contrib = (kern == ORC_YUK3   ? orc_y3_residual(&sp3, l, r)
+                                   : kern == ORC_POW3 ? orc_p2_r(&p2, l, r)
+                                                      : orc_split_r(ps, l, r)) *
+                                  q[j];
                     else continue;
 #pragma omp atomic
                     res->ures[i] += contrib;
@@ -506,7 +516,8 @@ int orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, 
     }
 
     if (kern == ORC_YUK3) orc_y3_split_free(&sp3);
-    const double scale = 1.0 / (4.0 * M_PI * t->side);
+    /* unit change: 1/(4 pi S) for the 1/r kernels, 1/S^2 for 1/r^2 */
+    const double scale = (kern == ORC_POW3) ? 1.0 / (t->side * t->side) : 1.0 / (4.0 * M_PI * t->side);
     for (int64_t i = 0; i < n; ++i) res->u[t->perm[i]] = (res->ufar[i] + res->ures[i]) * scale;
 
     if (keep) {

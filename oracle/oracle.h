@@ -136,9 +136,10 @@ typedef struct {
 int  orc_dmk_eval(const orc_tree *t, const orc_params *pr, const orc_pswf *ps,
                   const double *charges, int keep, orc_dmk_result *res);
 /* The same with a choice of 3-D kernel: ORC_LAP3 1/(4 pi r) (physical-space
- * PSWF split, Sec. 3.7) or ORC_YUK3 e^{-lambda r}/(4 pi r) (Fourier-space
- * PSWF split, Sec. 4.6; lam in input units, > 0; see yuk3.c). */
-enum { ORC_LAP3 = 0, ORC_YUK3 = 1 };
+ * PSWF split, Sec. 3.7), ORC_YUK3 e^{-lambda r}/(4 pi r) (Fourier-space
+ * PSWF split, Sec. 4.6; lam in input units, lam S >= 1e-3; see yuk3.c) or
+ * ORC_POW3 1/r^2 (PSWF power-function split, Sec. 4.5; see pow2.c). */
+enum { ORC_LAP3 = 0, ORC_YUK3 = 1, ORC_POW3 = 2 };
 int  orc_dmk_eval_k(const orc_tree *t, const orc_params *pr, const orc_pswf *ps, int kern, double lam,
                     const double *charges, int keep, orc_dmk_result *res);
 
@@ -162,6 +163,28 @@ double orc_y3_d_pw(const orc_pswf *ps, const orc_params *pr, double lam, int l, 
 double orc_y3_w0_pw(const orc_pswf *ps, const orc_params *pr, double lam, const double x[3]);
 void   orc_direct_yuk3(double lam, int64_t n, const double *pts, const double *q, int64_t nt,
                        const int64_t *tidx, double *out);  /* lam in input units */
+
+/* ---- 3-D 1/r^2 split (pow2.c), root-box units */
+#define ORC_P2_NC 48
+typedef struct {
+    const orc_pswf *ps;
+    double c1;                  /* int_0^1 t psi(t) dt                  */
+    double coef[ORC_P2_NC];     /* Phi(x)/x^2, series in 2x^2 - 1       */
+} orc_pow2;
+double orc_p2_c1(const orc_pswf *ps);
+double orc_p2_phi_quad(const orc_pswf *ps, double x);   /* Phi by its integral */
+int    orc_p2_init(const orc_pswf *ps, orc_pow2 *tb);
+double orc_p2_phi(const orc_pow2 *tb, double x);
+double orc_p2_m0(const orc_pow2 *tb, int L);
+double orc_p2_d(const orc_pow2 *tb, int l, double r);
+double orc_p2_r(const orc_pow2 *tb, int L, double r);
+double orc_p2_w0(const orc_pow2 *tb, double r);          /* windowed M_0     */
+double orc_p2_dhat(const orc_pow2 *tb, int l, double k);
+double orc_p2_w0hat(const orc_pow2 *tb, double k);
+double orc_p2_d_pw(const orc_pow2 *tb, const orc_params *pr, int l, const double x[3]);
+double orc_p2_w0_pw(const orc_pow2 *tb, const orc_params *pr, const double x[3]);
+void   orc_direct_pow2(int64_t n, const double *pts, const double *q, int64_t nt, const int64_t *tidx,
+                       double *out);
 void orc_dmk_result_free(const orc_tree *t, orc_dmk_result *res);
 
 /* Direct sum u_i = sum_{j != i, r_ij > 0} q_j / (4 pi r_ij) for the targets

@@ -36,7 +36,7 @@
  *    stream.  Work is enqueued on it asynchronously unless stated otherwise.
  *  - Status codes only; no C++ exception crosses the ABI.  After a non-zero
  *    status, dmk_last_error() returns a message for the calling thread.
- *  - Implemented: DMK_LAPLACE and DMK_YUKAWA in 2-D and 3-D.
+ *  - Implemented: DMK_LAPLACE and DMK_YUKAWA in 2-D and 3-D; DMK_POWER2 in 3-D.
  */
 #ifndef DMK_H
 #define DMK_H
@@ -59,8 +59,10 @@ typedef enum {
 
 /* DMK_LAPLACE: 1/(4 pi r) in 3-D, -log(r)/(2 pi) in 2-D.
  * DMK_YUKAWA: e^{-lambda r}/(4 pi r) in 3-D, K_0(lambda r) in 2-D (lambda in
- * dmk_opts); both split in Fourier space with the PSWF (Sec. 4.6). */
-typedef enum { DMK_LAPLACE = 0, DMK_YUKAWA = 1 } dmk_kernel;
+ * dmk_opts); both split in Fourier space with the PSWF (Sec. 4.6).
+ * DMK_POWER2: 1/r^2 in 3-D (no constant factor), split in physical space
+ * with the PSWF power-function window (Sec. 4.5, alpha = 2). */
+typedef enum { DMK_LAPLACE = 0, DMK_YUKAWA = 1, DMK_POWER2 = 2 } dmk_kernel;
 
 /* Arithmetic of the eval pipeline.  Input and output are always FP64. */
 typedef enum {
@@ -141,6 +143,7 @@ typedef struct {
  *  dim     2 or 3.
  *  kernel  DMK_LAPLACE (dim 3: 1/(4 pi r); dim 2: -log(r)/(2 pi)), or
  *          DMK_YUKAWA (dim 3: e^{-lambda r}/(4 pi r); dim 2: K_0(lambda r)),
+ *          or DMK_POWER2 (dim 3 only: 1/r^2),
  *          lambda = opts->lambda > 0 in input units.  Limits (else
  *          DMK_ERR_UNSUPPORTED): dim 3, lambda S in [1e-3, 1000]; dim 2,
  *          lambda S <= 50 per problem (S the root box side).
@@ -363,6 +366,14 @@ dmk_status dmk_copy_box_data(dmk_plan_t plan, int what, int64_t box, double *out
  *   what = 8: m(x_i), the smooth part of the residual
  *             R_l(r) = -log(x)/(2 pi) - m(x), x = r/s_l in [0,1];
  *   what = 9: out[0..3] = m(0), n_w, h_w, degree of m (n >= 4).
+ * Parameter search (Sec. 3.7 rule for c; smallest n_f and p meeting tol):
+ *   what = 10: x[0] = c (0: log(1/tol)); out[0..4] = c, n_f, p and the
+ *             plane-wave and proxy errors of those values (n >= 5).
+ * 3-D 1/r^2 tables (PSWF power-function split, Sec. 4.5, alpha = 2):
+ *   what = 12: g2(t_i) = Phi2(sqrt t_i)/t_i for t_i in [0,1]
+ *             (R_l(r) = 1/r^2 - g2(r^2/s_l^2)/s_l^2);
+ *   what = 13: plane-wave weight of D_0 at |m|^2 = x_i (level l: 4^l times);
+ *   what = 14: plane-wave weight of the windowed root kernel at |m|^2 = x_i.
  * DMK_ERR_UNSUPPORTED for a tolerance outside the table, DMK_ERR_ARG for a
  * bad `what` or n.
  */

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libdmk.so")
 
 DMK_FP64, DMK_MIXED = 0, 1
-DMK_LAPLACE, DMK_YUKAWA = 0, 1
+DMK_LAPLACE, DMK_YUKAWA, DMK_POWER2 = 0, 1, 2
 DMK_FLAG_BATCHED = 2
 DMK_FLAG_NO_WORKSPACE = 4
 NOALLOC_MAX_BYTES = 128 << 20

@@ -147,7 +147,8 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
                      const dmk_opts *opts, void *stream)
 {
     if (dim != 2 && dim != 3) throw Error{DMK_ERR_ARG, "dim must be 2 or 3"};
-    if (kernel != DMK_LAPLACE && kernel != DMK_YUKAWA) throw Error{DMK_ERR_ARG, "unknown kernel"};
+    if (kernel != DMK_LAPLACE && kernel != DMK_YUKAWA && kernel != DMK_POWER2) throw Error{DMK_ERR_ARG, "unknown kernel"};
+    if (kernel == DMK_POWER2 && dim != 3) throw Error{DMK_ERR_UNSUPPORTED, "the 1/r^2 kernel is built for dim = 3"};
     if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
     if (nprob < 1) throw Error{DMK_ERR_ARG, "nprob must be >= 1"};
     if (dim == 3 && nprob > 1) throw Error{DMK_ERR_UNSUPPORTED, "batches of 3-D problems are not built"};
@@ -189,7 +190,7 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         P->max_depth = o.max_depth ? o.max_depth : std::min(dflt, kb);
         P->flags = o.flags;
         P->n = n;
-        build_tables(prm, &P->tab, dim);
+        build_tables(prm, &P->tab, dim, kernel == DMK_POWER2 ? 2 : 0);
         P->p = prm.p;
         P->nf = prm.nf;
         P->nw = prm.nw;
@@ -547,11 +548,14 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
             out[0] = prm.c; out[1] = prm.nf; out[2] = prm.p; out[3] = e_nf; out[4] = e_p;
             return;
         }
+        // what 12, 13, 14: the 1/r^2 tables, as what 1, 2, 3 for 1/r
+        const int kind = (what >= 12 && what <= 14) ? 2 : 0;
+        if (kind == 2) what -= 11;
         const int dim = (what >= 6) ? 2 : 3;
         Params prm;
         if (!params_for(tol, &prm, dim)) throw Error{DMK_ERR_UNSUPPORTED, "tolerance not in the table"};
         Tables t;
-        build_tables(prm, &t, dim);
+        build_tables(prm, &t, dim, kind);
         if (what == 9) {
             if (n < 4) throw Error{DMK_ERR_ARG, "n >= 4 needed"};
             out[0] = t.m0; out[1] = prm.nw; out[2] = prm.hw; out[3] = t.gdeg;
@@ -611,7 +615,7 @@ dmk_status dmk_precompute_probe(double tol, int what, int64_t n, const double *x
                 }
                 v = t.gcheb[0] + u * b1 - b2;
             } else {
-                throw Error{DMK_ERR_ARG, "what must be 0..9"};
+                throw Error{DMK_ERR_ARG, "what must be 0..10 or 12..14"};
             }
             out[i] = v;
         }

@@ -65,8 +65,10 @@ struct Tables {
     std::vector<double> gcheb;             // Chebyshev coefficients of Phi(sqrt t)/sqrt t on [0,1]
     int gdeg;                              // degree kept for FP64 evaluation
     int gdeg32;                            // degree kept for FP32 evaluation
+    int kind = 0;                          // 0: 1/r split (or 2-D); 2: 1/r^2 (gcheb: Phi2(sqrt t)/t; weights scale 4^l)
 };
-void build_tables(const Params &prm, Tables *t, int dim = 3);
+// kind: 0 for the 1/r-type splits (and every 2-D table), 2 for 1/r^2 in 3-D
+void build_tables(const Params &prm, Tables *t, int dim = 3, int kind = 0);
 
 // PSWF helpers exposed for the host-side self checks in the tests.
 double pswf_eval(const Tables &t, double x);  // any real x

@@ -66,6 +66,7 @@ struct Dev {
     int64_t ywd_stride;
     double ylam;
     int ydeg, ynlev;
+    int wshift;  // level-l weights are 2^(wshift l) times level 0's: 1 for 1/r, 2 for 1/r^2
 };
 
 // ------------------------------------------------------------------ upward
@@ -414,8 +415,8 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
         }
     }
     T w[MPT];
-    // 1/r: w_l = 2^l w_0 (scale invariance); Yukawa: the level's own table
-    const T scale = D.ywd ? T(1) : (T)ldexp(1.0, oct_level[o]);
+    // 1/r: w_l = 2^l w_0, 1/r^2: 4^l w_0 (scale invariance); Yukawa: the level's own table
+    const T scale = D.ywd ? T(1) : (T)ldexp(1.0, D.wshift * oct_level[o]);
     const T *wt = D.ywd ? D.ywd + (int64_t)oct_level[o] * D.ywd_stride : D.wd0;
 #pragma unroll
     for (int u = 0; u < MPT; ++u) w[u] = (e0 + u < nmode) ? wt[e0 + u] * scale : T(0);
@@ -1230,7 +1231,7 @@ __device__ inline double rsq(double x) { return rsqrt(x); }
 // so Horner is as accurate as Clenshaw's recurrence at half its operations.
 // DEG: compile-time degree bucket (coefficients above the plan's degree are
 // zero, which leaves the result unchanged); the coefficients live in registers.
-template <typename T, int DEG>
+template <typename T, int DEG, int POW>
 __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leaves, const int32_t *nl_off,
                                                   const int32_t *nl_src, const int32_t *nl_pre)
 {
@@ -1318,8 +1319,13 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
                         T g = gc[DEG];
 #pragma unroll
                         for (int k = DEG - 1; k >= 0; --k) g = g * uu + gc[k];
-                        const T rinv = (r2v[u] > T(0)) ? rsq(r2v[u]) : T(0);
-                        pacc += sq[j] * (rinv - g * sis[j]);
+                        if constexpr (POW == 1) {  // 1/r - g(t)/s
+                            const T rinv = (r2v[u] > T(0)) ? rsq(r2v[u]) : T(0);
+                            pacc += sq[j] * (rinv - g * sis[j]);
+                        } else {  // 1/r^2 - g2(t)/s^2
+                            const T r2inv = (r2v[u] > T(0)) ? T(1) / r2v[u] : T(0);
+                            pacc += sq[j] * (r2inv - g * sis[j] * sis[j]);
+                        }
                     }
                 }
             }
@@ -1746,6 +1752,7 @@ Dev<T> make_dev(Plan *P)
     D.ylam = 0.0;
     D.ydeg = 0;
     D.ynlev = 0;
+    D.wshift = (t.kind == 2) ? 2 : 1;
     if (P->kernel == DMK_YUKAWA && P->dim == 3) {
         D.ywd = (const T *)(f64 ? (void *)P->y_wd64 : (void *)P->y_wd32);
         D.ycheb = (const T *)(f64 ? (void *)P->y_cheb64 : (void *)P->y_cheb32);
@@ -1773,6 +1780,26 @@ void allow_lds(K kernel, size_t bytes)
 }  // namespace
 
 // residual sums with the polynomial degree rounded up to a compiled bucket
+// the residual kernel for the series degree (a compile-time bucket)
+template <typename T, int POW>
+static void launch_residual_deg(const Dev<T> &D, Plan *Pl, dim3 g, dim3 b, size_t lds, hipStream_t s)
+{
+    if (D.gdeg <= 7)
+        hipLaunchKernelGGL((k_residual<T, 7, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 9)
+        hipLaunchKernelGGL((k_residual<T, 9, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 11)
+        hipLaunchKernelGGL((k_residual<T, 11, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 13)
+        hipLaunchKernelGGL((k_residual<T, 13, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 15)
+        hipLaunchKernelGGL((k_residual<T, 15, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else if (D.gdeg <= 20)
+        hipLaunchKernelGGL((k_residual<T, 20, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    else
+        hipLaunchKernelGGL((k_residual<T, 47, POW>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+}
+
 template <typename T>
 static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
 {
@@ -1782,20 +1809,10 @@ static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
         hipLaunchKernelGGL((k_residual_y3<T>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
         return;
     }
-    if (D.gdeg <= 7)
-        hipLaunchKernelGGL((k_residual<T, 7>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
-    else if (D.gdeg <= 9)
-        hipLaunchKernelGGL((k_residual<T, 9>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
-    else if (D.gdeg <= 11)
-        hipLaunchKernelGGL((k_residual<T, 11>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
-    else if (D.gdeg <= 13)
-        hipLaunchKernelGGL((k_residual<T, 13>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
-    else if (D.gdeg <= 15)
-        hipLaunchKernelGGL((k_residual<T, 15>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
-    else if (D.gdeg <= 20)
-        hipLaunchKernelGGL((k_residual<T, 20>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    if (D.wshift == 2)
+        launch_residual_deg<T, 2>(D, Pl, g, b, lds, s);
     else
-        hipLaunchKernelGGL((k_residual<T, 47>), g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        launch_residual_deg<T, 1>(D, Pl, g, b, lds, s);
 }
 
 // dynamic LDS limits of the stage kernels, once per process
@@ -1957,7 +1974,8 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
-        const double scale = 1.0 / (4.0 * M_PI * Pl->side);
+        // unit change: 1/(4 pi S) for the 1/r kernels, 1/S^2 for 1/r^2
+        const double scale = (Pl->tab.kind == 2) ? 1.0 / (Pl->side * Pl->side) : 1.0 / (4.0 * M_PI * Pl->side);
         hipLaunchKernelGGL(k_finalize, dim3(nblk(n)), dim3(TPB), 0, s, Pl->ufar, Pl->ures, Pl->perm, n, scale, pot,
                            far_part, near_part);
     }

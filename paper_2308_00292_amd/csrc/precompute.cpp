@@ -191,9 +191,11 @@ double pswf_eval(const Tables &t, double x)
 }
 
 void build_tables2(Tables *t);
+void build_tables_pow2(Tables *t);
 
-void build_tables(const Params &prm, Tables *t, int dim)
+void build_tables(const Params &prm, Tables *t, int dim, int kind)
 {
+    t->kind = kind;
     t->prm = prm;
     t->dim = dim;
     const double c = prm.c;
@@ -272,6 +274,10 @@ void build_tables(const Params &prm, Tables *t, int dim)
 
     if (dim == 2) {
         build_tables2(t);
+        return;
+    }
+    if (kind == 2) {
+        build_tables_pow2(t);
         return;
     }
     // ---- plane-wave weights of D_0 (level l multiplies by 2^l), half spectrum
@@ -451,6 +457,167 @@ void build_tables2(Tables *t)
     }
 }
 
+
+// ---------------------------------------------------------------- 1/r^2
+// Kernel 1/r^2 in 3-D with the PSWF power-function split (Sec. 4.5, alpha = 2):
+//   Phi2(x) = (1/C_1) int_0^x t psi(t) dt (x <= 1; 1 beyond), C_1 = int_0^1 t psi,
+//   D_l(r) = (Phi2(r/s_{l+1}) - Phi2(r/s_l))/r^2 = 4^l D_0(2^l r),
+//   R_L(r) = (1 - Phi2(r/s_L))/r^2 = 1/r^2 - g2(r^2/s_L^2)/s_L^2 for r < s_L,
+// with g2(t) = Phi2(sqrt t)/t smooth on [0, 1] (g2(0) = psi(0)/(2 C_1), the
+// self term).  Phi2 from Legendre integrals of the PSWF's series:
+// t P_n = ((n+1) P_{n+1} + n P_{n-1})/(2n+1), int_0^x P_m = (P_{m+1} - P_{m-1})/(2m+1) |_0^x.
+//  * level-0 weights (h_0/2pi)^3 Dhat_0(h_0 |m|), Dhat_0(k) = (4 pi/k) int_0^1 D_0(r) r sin(kr) dr
+//    (Gauss-Legendre panels on [0, 1/2] and [1/2, 1]); level l multiplies by 4^l;
+//  * root: W_0 = M_0 chi with M_0 = Phi2(r)/r^2 and chi a smooth step from 1
+//    at sqrt 3 to 0 at sqrt 3 + 2, chi = (1 - sign(y) Phi(|y|))/2, y = r - sqrt 3 - 1,
+//    Phi the 1/r split's window; its transform by radial quadrature;
+//  * residual series: g2 as a Chebyshev series in 2t - 1.
+namespace {
+
+double phi2_raw(const Tables &t, double x)  // int_0^x t psi(t) dt
+{
+    const int K = (int)t.coef.size(), kmax = 2 * K + 2;
+    std::vector<double> Px, P0;
+    legendre(kmax, x, Px);
+    legendre(kmax, 0.0, P0);
+    auto I = [&](int m) {  // int_0^x P_m
+        if (m == 0) return x;
+        return (Px[m + 1] - Px[m - 1] - P0[m + 1] + P0[m - 1]) / (2.0 * m + 1.0);
+    };
+    double s = 0.0;
+    for (int i = 0; i < K; ++i) {
+        const int n = 2 * i;
+        const double tPn = ((n + 1) * I(n + 1) + (n > 0 ? n * I(n - 1) : 0.0)) / (2.0 * n + 1.0);
+        s += t.coef[i] * std::sqrt(n + 0.5) * tPn;
+    }
+    return s;
+}
+
+void gl_nodes(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = pk;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+void build_tables_pow2(Tables *t)
+{
+    const Params &prm = t->prm;
+    const double c1 = phi2_raw(*t, 1.0);
+    auto phi2 = [&](double x) { return x >= 1.0 ? 1.0 : phi2_raw(*t, x) / c1; };
+    // ---- g2(tt) = Phi2(sqrt tt)/tt, Chebyshev series in 2 tt - 1
+    const int M = 48;
+    std::vector<double> cf(M);
+    {
+        std::vector<double> f(M);
+        for (int k = 0; k < M; ++k) {
+            const double tt = 0.5 * (std::cos(M_PI * (k + 0.5) / M) + 1.0);
+            f[k] = phi2(std::sqrt(tt)) / tt;
+        }
+        for (int j = 0; j < M; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < M; ++k) acc += f[k] * std::cos(M_PI * j * (k + 0.5) / M);
+            cf[j] = (j == 0 ? 1.0 : 2.0) * acc / M;
+        }
+    }
+    auto g2 = [&](double tt) {
+        const double u = 2.0 * tt - 1.0;
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = M - 1; k >= 1; --k) {
+            const double b0 = cf[k] + 2.0 * u * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
+        return cf[0] + u * b1 - b2;
+    };
+    {
+        int deg = M - 1;
+        while (deg > 0 && std::fabs(cf[deg]) < 1e-14 * std::fabs(cf[0])) deg--;
+        t->gdeg = deg;
+        t->gcheb.assign(cf.begin(), cf.begin() + deg + 1);
+        int deg32 = deg;
+        while (deg32 > 0 && std::fabs(cf[deg32]) < 1e-7 * std::fabs(cf[0])) deg32--;
+        t->gdeg32 = deg32;
+    }
+    std::vector<double> gx, gw;
+    gl_nodes(20, gx, gw);
+    // radial transform (4 pi/k) int_a^b f(r) r sin(kr) dr on npan panels
+    auto radial = [&](auto f, double a, double b, int npan, double k) {
+        double acc = 0.0;
+        for (int q = 0; q < npan; ++q) {
+            const double lo = a + (b - a) * q / npan, hi = a + (b - a) * (q + 1) / npan;
+            for (size_t i = 0; i < gx.size(); ++i) {
+                const double r = 0.5 * (lo + hi) + 0.5 * (hi - lo) * gx[i];
+                acc += 0.5 * (hi - lo) * gw[i] * f(r) * r * (k == 0.0 ? r : std::sin(k * r) / k);
+            }
+        }
+        return 4.0 * M_PI * acc;
+    };
+    // ---- level-0 difference-kernel weights, layout [m1][m3][m2]
+    {
+        auto d0 = [&](double r) { return (r < 0.5) ? 4.0 * g2(4.0 * r * r) - g2(r * r) : 1.0 / (r * r) - g2(r * r); };
+        const double h = 2.0 * M_PI / 3.0, fac = std::pow(h / (2.0 * M_PI), 3);
+        const int nf = prm.nf, maxk2 = 3 * nf * nf;
+        std::vector<double> memo(maxk2 + 1);
+        for (int k2 = 0; k2 <= maxk2; ++k2) {
+            const double k = h * std::sqrt((double)k2);
+            memo[k2] = fac * (radial(d0, 0.0, 0.5, 16, k) + radial(d0, 0.5, 1.0, 16, k));
+        }
+        t->wd0.assign((size_t)t->nh * t->nn * t->nn, 0.0);
+        for (int m1 = -nf; m1 <= nf; ++m1)
+            for (int m3 = 0; m3 <= nf; ++m3)
+                for (int m2 = -nf; m2 <= nf; ++m2)
+                    t->wd0[((size_t)(m1 + nf) * t->nh + m3) * t->nn + (m2 + nf)] = memo[m1 * m1 + m2 * m2 + m3 * m3];
+    }
+    // ---- root window weights (hw/2pi)^3 What_0(hw |m|), layout [m3][m2][m1]
+    {
+        const double a = std::sqrt(3.0);
+        auto w0 = [&](double r) {
+            const double m0 = (r < 1.0) ? g2(r * r) : 1.0 / (r * r);
+            if (r <= a) return m0;
+            if (r >= a + 2.0) return 0.0;
+            const double y = r - a - 1.0;
+            return m0 * 0.5 * (1.0 - (y >= 0.0 ? 1.0 : -1.0) * phi_window(*t, std::fabs(y)));
+        };
+        const double h = prm.hw, fac = std::pow(h / (2.0 * M_PI), 3);
+        const int nw = prm.nw, maxk2 = 3 * nw * nw;
+        std::vector<double> memo(maxk2 + 1);
+        for (int k2 = 0; k2 <= maxk2; ++k2) {
+            const double k = h * std::sqrt((double)k2);
+            memo[k2] = fac * (radial(w0, 0.0, 1.0, 20, k) + radial(w0, 1.0, a, 10, k) + radial(w0, a, a + 2.0, 20, k));
+        }
+        t->ww.assign((size_t)t->nwh * t->nwn * t->nwn, 0.0);
+        for (int m3 = 0; m3 <= nw; ++m3)
+            for (int m2 = -nw; m2 <= nw; ++m2)
+                for (int m1 = -nw; m1 <= nw; ++m1)
+                    t->ww[((size_t)m3 * t->nwn + (m2 + nw)) * t->nwn + (m1 + nw)] = memo[m1 * m1 + m2 * m2 + m3 * m3];
+    }
+}
 
 // ------------------------------------------------------ parameter search
 // For a tolerance without a row in the parameter table (Sec. 3.7): c from

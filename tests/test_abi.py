@@ -180,3 +180,30 @@ def test_parameter_choice_errors_without_device():
     o = dmk.Opts(0, 0, 1, 0, 0, 0.0)
     assert L.dmk_plan(3, 0, 3e-7, 10, one, C.byref(o), None, C.byref(h)) in (-2, -5)
     assert h.value is None
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6])
+def test_host_tables_pow2_match_oracle(oracle_mod, tol):
+    """1/r^2 tables (Sec. 4.5, alpha = 2): the library builds Phi2 from
+    Legendre integrals of the PSWF series and its transforms with its own
+    Gauss-Legendre panels; the oracle integrates t psi(t) numerically and uses
+    other panels.  Residual series g2, level-0 weights and root window
+    weights agree to rounding."""
+    pr = oracle_mod.params_for(tol)
+    p2 = oracle_mod.Pow2(oracle_mod.PSWF(pr.c))
+    ts = np.linspace(0.0, 1.0, 41)
+    ts[0] = 1e-9
+    got = dmk.precompute_probe(tol, 12, ts)
+    ref = np.array([p2.phi(np.sqrt(t)) / t for t in ts])
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    h = 2 * np.pi / 3
+    k2 = np.arange(0, 3 * pr.nf ** 2 + 1, 7.0)
+    got = dmk.precompute_probe(tol, 13, k2)
+    ref = np.array([(h / (2 * np.pi)) ** 3 * p2.dhat(0, h * np.sqrt(k)) for k in k2])
+    ok = ~np.isnan(got)
+    assert ok.sum() >= 8 and np.max(np.abs(got[ok] - ref[ok])) < 1e-13 * np.max(np.abs(ref))
+    k2 = np.arange(0, 3 * pr.nw ** 2 + 1, 5.0)
+    got = dmk.precompute_probe(tol, 14, k2)
+    ref = np.array([(pr.hw / (2 * np.pi)) ** 3 * p2.w0hat(pr.hw * np.sqrt(k)) for k in k2])
+    ok = ~np.isnan(got)
+    assert ok.sum() > 5 and np.max(np.abs(got[ok] - ref[ok])) < 1e-13 * np.max(np.abs(ref))

@@ -94,6 +94,32 @@ def batch_2d(nprob: int, seed: int, nmin: float = 1e3, nmax: float = 2e5, scale:
     return off, np.ascontiguousarray(np.concatenate(parts)), np.concatenate(charges)
 
 
+def batch_3d(nprob: int, seed: int, nmin: float = 300, nmax: float = 6000):
+    """Many independent 3-D problems: problem b draws from default_rng(1000 seed + b)
+    a size N_b = floor(exp(U[ln nmin, ln nmax])) (at least 1), then one of
+    three distributions with equal odds (uniform in [0,1]^3; a Gaussian blob
+    0.5 + 0.05 N(0, I_3); the unit sphere, normalised Gaussian vectors), the
+    points, and charges uniform in [-1,1].  Returns (offsets, pts, q)."""
+    sizes, parts, charges = [], [], []
+    for b in range(nprob):
+        rng = np.random.default_rng(1000 * seed + b)
+        nb = max(1, int(np.floor(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))))
+        kind = rng.integers(3)
+        if kind == 0:
+            p = rng.random((nb, 3))
+        elif kind == 1:
+            p = 0.5 + 0.05 * rng.standard_normal((nb, 3))
+        else:
+            g = rng.standard_normal((nb, 3))
+            p = g / np.linalg.norm(g, axis=1)[:, None]
+        parts.append(p)
+        charges.append(rng.uniform(-1.0, 1.0, nb))
+        sizes.append(nb)
+    off = np.zeros(nprob + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off, np.ascontiguousarray(np.concatenate(parts)), np.concatenate(charges)
+
+
 # Named workloads: (generator, N, seed, leaf capacity n_s).
 CONFIGS = {
     "cfg1_uniform_2k": (uniform_cube, 2_000, 1, 50),

@@ -183,7 +183,8 @@ dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const dou
  * interleaved level by level, and every stage of dmk_eval is one launch over
  * the boxes of all problems.
  *
- *  dim      must be 2 (3-D batches: DMK_ERR_UNSUPPORTED).
+ *  dim      2 or 3 (3-D batches of the Yukawa kernel, whose tables depend
+ *           on each problem's lambda S_b: DMK_ERR_UNSUPPORTED).
  *  nprob    >= 1.
  *  offsets  HOST, [nprob+1] int64, offsets[0] = 0, non-decreasing; problem b
  *           is points offsets[b] .. offsets[b+1]-1 (empty problems allowed).

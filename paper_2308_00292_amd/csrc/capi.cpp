@@ -151,7 +151,8 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
     if (kernel == DMK_POWER2 && dim != 3) throw Error{DMK_ERR_UNSUPPORTED, "the 1/r^2 kernel is built for dim = 3"};
     if (!(tol > 0) || !std::isfinite(tol)) throw Error{DMK_ERR_ARG, "tol must be positive"};
     if (nprob < 1) throw Error{DMK_ERR_ARG, "nprob must be >= 1"};
-    if (dim == 3 && nprob > 1) throw Error{DMK_ERR_UNSUPPORTED, "batches of 3-D problems are not built"};
+    if (dim == 3 && nprob > 1 && kernel == DMK_YUKAWA)
+        throw Error{DMK_ERR_UNSUPPORTED, "batches of 3-D Yukawa problems are not built (tables per problem)"};
     if (!poff) throw Error{DMK_ERR_ARG, "offsets is NULL"};
     if (poff[0] != 0) throw Error{DMK_ERR_ARG, "offsets[0] must be 0"};
     for (int32_t b = 0; b < nprob; ++b)
@@ -200,6 +201,13 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         upload_tables(P, s);
         build_tree(P, pts, s);
         build_lists(P, s);
+        if (dim == 3) {  // unit change per problem: 1/(4 pi S_b) for the 1/r kernels, 1/S_b^2 for 1/r^2
+            std::vector<double> sc(nprob);
+            for (int b = 0; b < nprob; ++b)
+                sc[b] = (kernel == DMK_POWER2) ? 1.0 / (P->pside[b] * P->pside[b]) : 1.0 / (4.0 * M_PI * P->pside[b]);
+            P->d_pscale = (double *)dalloc(P, nprob * sizeof(double));
+            DMK_HIP(hipMemcpy(P->d_pscale, sc.data(), nprob * sizeof(double), hipMemcpyHostToDevice));
+        }
         if (kernel == DMK_YUKAWA && dim == 2) {
             if (P->nlevels > 32) throw Error{DMK_ERR_UNSUPPORTED, "Yukawa plans hold at most 32 levels"};
             for (int b = 0; b < nprob; ++b)

@@ -135,6 +135,7 @@ struct Plan {
     std::vector<double> pcenter, pside;   // host [nprob][dim], [nprob]
     int64_t *d_poff = nullptr;            // device copies
     double *d_pcenter = nullptr, *d_pside = nullptr;
+    double *d_pscale = nullptr;           // [nprob] 3-D unit change of each problem's potentials
     int32_t *bprob = nullptr;             // [nbox] problem of each box
 
     // sorted points

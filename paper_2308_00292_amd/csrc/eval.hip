@@ -67,6 +67,10 @@ struct Dev {
     double ylam;
     int ydeg, ynlev;
     int wshift;  // level-l weights are 2^(wshift l) times level 0's: 1 for 1/r, 2 for 1/r^2
+    // batches of independent problems: root scratch per problem, and the
+    // most points a root leaf holds (the scratch's Lagrange-row region)
+    int64_t root_stride;
+    int root_npmax;
 };
 
 // ------------------------------------------------------------------ upward
@@ -487,7 +491,7 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
 #pragma unroll
                 for (int j = 0; j < RN; ++j) {
                     int m = mt + i * MT, n = nt + j * NT;
-                    if (m < P && n < P2) acc[i][j] = D.w0vals[m * P2 + n];
+                    if (m < P && n < P2) acc[i][j] = D.w0vals[(int64_t)B * P3 + m * P2 + n];  // root B = problem B
                 }
         }
     } else {
@@ -848,6 +852,7 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
     __syncthreads();
     if (level == 0) {
         // root: the windowed W_0 values, in the fragment layout of the last step
+        const float *w0B = D.w0vals + (int64_t)B * P3;  // root B = problem B
 #pragma unroll
         for (int i = 0; i < NSW; ++i) {
             const int sl = w + NWV * i;
@@ -857,11 +862,11 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
-                    if (x < P2 && a < P) acc[i][t][q] = D.w0vals[x * P + a];
+                    if (x < P2 && a < P) acc[i][t][q] = w0B[x * P + a];
                 }
             const int xa = 16 * sl + r16;
 #pragma unroll
-            for (int j = 0; j < NREM; ++j) accr[i][j] = (xa < P2) ? D.w0vals[xa * P + 16 * NATM + j] : 0.f;
+            for (int j = 0; j < NREM; ++j) accr[i][j] = (xa < P2) ? w0B[xa * P + 16 * NATM + j] : 0.f;
         }
     } else {
         // interpolation from the anchor A of the parent: node i of B sits at
@@ -1468,30 +1473,37 @@ struct RootLayout {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_root_stage(Dev<T> D, int stage, int root_fout, int npts)
+__global__ void __launch_bounds__(TPB) k_root_stage(Dev<T> D, int stage)
 {
+    // problem b = blockIdx.y: its root is box b, its scratch its own slice
+    const int b = blockIdx.y;
     const int p = D.p, p2 = p * p, p3 = p2 * p, n = D.nwn, nh = D.nwh, nw = D.nw;
-    const RootLayout R(p, n, nh, npts);
-    double *S = D.rootscratch;
+    const int npm = D.root_npmax;
+    const RootLayout R(p, n, nh, npm);
+    double *S = D.rootscratch + (int64_t)b * D.root_stride;
     const double *E = D.ew64;  // [n][p][2], rows m + nw
     const int64_t e = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    const bool root_fout = (D.bflags[b] & 2) != 0;
+    const int npts = root_fout ? 0 : D.pcount[b];  // a root without F_out is a leaf of <= npm points
+    const int64_t p0 = D.pstart[b];
     switch (stage) {
     case 0:  // Lagrange rows of the root's points (root without F_out)
         if (e < 3 * npts) {
             const int pt = (int)(e / 3), d = (int)(e % 3);
-            const double x = (d == 0) ? D.X[pt] : (d == 1) ? D.Y[pt] : D.Z[pt];
-            lagrange_row<double>(p, D.xcheb64, D.bary64, 2.0 * x, S + R.rows + (d * (int64_t)npts + pt) * p);
+            const double x = (d == 0) ? D.X[p0 + pt] : (d == 1) ? D.Y[p0 + pt] : D.Z[p0 + pt];
+            lagrange_row<double>(p, D.xcheb64, D.bary64, 2.0 * x, S + R.rows + (d * (int64_t)npm + pt) * p);
         }
         break;
     case 1:  // root proxies
         if (e < p3) {
             double v = 0.0;
             if (root_fout) {
-                v = (double)D.proxy[(int64_t)D.proxy_slot[0] * p3 + e];
+                v = (double)D.proxy[(int64_t)D.proxy_slot[b] * p3 + e];
             } else {
                 const int a0 = (int)(e / p2), a1 = (int)((e / p) % p), a2 = (int)(e % p);
-                const double *Lx = S + R.rows, *Ly = Lx + (int64_t)npts * p, *Lz = Ly + (int64_t)npts * p;
-                for (int pt = 0; pt < npts; ++pt) v += Lx[pt * p + a0] * Ly[pt * p + a1] * Lz[pt * p + a2] * D.qs[pt];
+                const double *Lx = S + R.rows, *Ly = Lx + (int64_t)npm * p, *Lz = Ly + (int64_t)npm * p;
+                for (int pt = 0; pt < npts; ++pt)
+                    v += Lx[pt * p + a0] * Ly[pt * p + a1] * Lz[pt * p + a2] * D.qs[p0 + pt];
             }
             S[R.rho + e] = v;
         }
@@ -1574,7 +1586,7 @@ __global__ void __launch_bounds__(TPB) k_root_stage(Dev<T> D, int stage, int roo
                 const double er = E[2 * (m1 * p + j1)], ei = E[2 * (m1 * p + j1) + 1];
                 v += er * S[R.C2r + m1 * p2 + r] + ei * S[R.C2i + m1 * p2 + r];
             }
-            D.w0vals[e] = (T)v;
+            D.w0vals[(int64_t)b * p3 + e] = (T)v;
         }
         break;
     }
@@ -1592,13 +1604,19 @@ __global__ void k_gather_q(const double *charges, const int32_t *perm, int64_t n
     if (i < n) qs[i] = charges[perm[i]];
 }
 
-__global__ void k_finalize(const double *ufar, const double *ures, const int32_t *perm, int64_t n, double scale,
-                           double *pot, double *farp, double *nearp)
+// scale[b]: the unit change of problem b, whose points are [poff[b], poff[b+1]) in tree order
+__global__ void k_finalize(const double *ufar, const double *ures, const int32_t *perm, int64_t n, const double *scale,
+                           const int64_t *poff, int nprob, double *pot, double *farp, double *nearp)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (i >= n) return;
+    int lo = 0, hi = nprob - 1;  // the problem b with poff[b] <= i < poff[b+1]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (poff[mid] <= i) lo = mid; else hi = mid - 1;
+    }
     int64_t j = perm[i];
-    double f = ufar[i] * scale, r = ures[i] * scale;
+    double f = ufar[i] * scale[lo], r = ures[i] * scale[lo];
     if (pot) pot[j] = f + r;
     if (farp) farp[j] = f;
     if (nearp) nearp[j] = r;
@@ -1753,6 +1771,8 @@ Dev<T> make_dev(Plan *P)
     D.ydeg = 0;
     D.ynlev = 0;
     D.wshift = (t.kind == 2) ? 2 : 1;
+    D.root_npmax = (int)std::min<int64_t>(P->n, P->leaf_max);
+    D.root_stride = root_scratch_elems(t, D.root_npmax);
     if (P->kernel == DMK_YUKAWA && P->dim == 3) {
         D.ywd = (const T *)(f64 ? (void *)P->y_wd64 : (void *)P->y_wd32);
         D.ycheb = (const T *)(f64 ? (void *)P->y_cheb64 : (void *)P->y_cheb32);
@@ -1847,13 +1867,13 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     const int64_t n = Pl->n;
     {
         StageScope t(Pl, s, DMK_STAGE_ROOT);
-        const int root_fout = (ll.fout_off[1] > 0) ? 1 : 0;
-        const int npts = root_fout ? 0 : (int)n;
+        // every problem's root at once (grid y); stage 0 only if some root is a leaf
+        const bool any_leaf_root = ll.fout_off[1] < Pl->nprob;
         const int64_t p = P, nw = Pl->tab.nwn, nwh = Pl->tab.nwh;
-        const int64_t outs[8] = {3 * (int64_t)npts, p * p * p, p * p * nwh, p * nwh * nw, nw * nwh * nw,
+        const int64_t outs[8] = {3 * (int64_t)D.root_npmax, p * p * p, p * p * nwh, p * nwh * nw, nw * nwh * nw,
                                  nw * nw * p, nw * p * p, p * p * p};
-        for (int st = root_fout ? 1 : 0; st < 8; ++st)
-            hipLaunchKernelGGL((k_root_stage<T>), dim3(nblk(outs[st])), dim3(TPB), 0, s, D, st, root_fout, npts);
+        for (int st = any_leaf_root ? 0 : 1; st < 8; ++st)
+            hipLaunchKernelGGL((k_root_stage<T>), dim3(nblk(outs[st]), (unsigned)Pl->nprob), dim3(TPB), 0, s, D, st);
     }
     // Step 3: outgoing plane waves of every F_out box and incoming plane
     // waves of every non-empty F_in box, all levels in one launch each
@@ -1974,10 +1994,9 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
-        // unit change: 1/(4 pi S) for the 1/r kernels, 1/S^2 for 1/r^2
-        const double scale = (Pl->tab.kind == 2) ? 1.0 / (Pl->side * Pl->side) : 1.0 / (4.0 * M_PI * Pl->side);
-        hipLaunchKernelGGL(k_finalize, dim3(nblk(n)), dim3(TPB), 0, s, Pl->ufar, Pl->ures, Pl->perm, n, scale, pot,
-                           far_part, near_part);
+        hipLaunchKernelGGL(k_finalize, dim3(nblk(n)), dim3(TPB), 0, s, Pl->ufar, Pl->ures, Pl->perm, n,
+                           (const double *)Pl->d_pscale, (const int64_t *)Pl->d_poff, Pl->nprob, pot, far_part,
+                           near_part);
     }
     DMK_HIP(hipGetLastError());
 }
@@ -2107,12 +2126,12 @@ void workspace_layout(Plan *P, std::vector<WsItem> &items)
     add(&P->qs, P->n, 8);
     add(&P->ufar, P->n, 8);
     add(&P->ures, P->n, 8);
-    add(&P->rootscratch, root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
+    add(&P->rootscratch, P->nprob * root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
     add(&P->proxy, P->nfout * p3, el);
     add(&P->local, P->nanc * p3, el);
     add(&P->phi, 2 * P->nfout * nm, el);
     add(&P->psi, 2 * P->nfin * nm, el);
-    add(&P->w0vals, p3, el);
+    add(&P->w0vals, P->nprob * p3, el);
 }
 
 void alloc_workspace(Plan *P)

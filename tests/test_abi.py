@@ -51,8 +51,8 @@ def test_argument_errors_without_device():
     assert L.dmk_plan_batched(2, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
                               C.byref(h)) == -1  # offsets[0] != 0
     off = np.array([0, 5, 9], dtype=np.int64)
-    assert L.dmk_plan_batched(3, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
-                              C.byref(h)) == -2  # 3-D batches
+    assert L.dmk_plan_batched(3, 1, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
+                              C.byref(h)) == -2  # 3-D Yukawa batches
     assert L.dmk_plan_batched(2, 0, 1e-6, 0, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
                               C.byref(h)) == -1  # nprob
     assert h.value is None

@@ -224,6 +224,33 @@ dmk_status dmk_tune_leaf(int dim, dmk_kernel kernel, double tol, int32_t nprob, 
                          int32_t ncand, int32_t reps, void *stream, int32_t *best, double *ms);
 
 /*
+ * dmk_tune -- the autotuner: picks the proxy order and plane-wave width
+ * (p, n_f) and the leaf capacity n_s for the caller's points and charges.
+ *
+ * Paper: the parameters of Table 1 (Sec. 3.7) are chosen for the method's
+ * error bound, and n_s by experiment (remark at the end of Sec. 3.5).  The
+ * tuner measures instead of bounding: direct sums (the definition, FP64,
+ * compensated) at up to 256 evenly spaced targets give an accuracy gate; the
+ * coarsest compiled (p, n_f) pair whose sampled relative l2 error is within
+ * tol at n_s = cand[0] is kept (the pairs are tried from the coarsest; the
+ * caller's p/n_f if opts sets them), then every candidate n_s is timed and
+ * the fastest kept; if that configuration misses tol, the next pair is
+ * timed.  c stays that of the tolerance (opts->pswf_c if set).
+ *
+ *  dim, kernel, tol, nprob, offsets, pts, charges, opts  as dmk_tune_leaf.
+ *  cand, ncand, reps  HOST leaf capacities to time, evals per candidate.
+ *  best   HOST, receives opts with leaf_max, p, n_f and pswf_c filled in.
+ *  ms     HOST [ncand] or NULL: mean eval time of each candidate (ms), for
+ *         the pair kept.
+ *  err    HOST or NULL: sampled relative l2 error of the configuration kept.
+ * Builds and destroys one plan per trial; synchronous on `stream`; needs at
+ * least two points.
+ */
+dmk_status dmk_tune(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *offsets,
+                    const double *pts, const double *charges, const dmk_opts *opts, const int32_t *cand,
+                    int32_t ncand, int32_t reps, void *stream, dmk_opts *best, double *ms, double *err);
+
+/*
  * dmk_problem_info -- root box of problem `prob` of a plan (input units):
  * centre [dim] and side, both HOST pointers (either may be NULL).
  */

@@ -21,7 +21,7 @@ DMK_FLAG_NO_WORKSPACE = 4
 NOALLOC_MAX_BYTES = 128 << 20
 
 # exported symbols, in the order of include/dmk.h
-SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_problem_info", "dmk_eval", "dmk_eval_noalloc", "dmk_eval_parts",
+SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_tune", "dmk_problem_info", "dmk_eval", "dmk_eval_noalloc", "dmk_eval_parts",
            "dmk_plan_info", "dmk_export_tree", "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
            "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
            "dmk_vol_plan", "dmk_vol_info", "dmk_vol_leaves", "dmk_vol_nodes", "dmk_vol_eval",
@@ -72,6 +72,8 @@ def lib():
         L.dmk_problem_info.argtypes = [vp, C.c_int32, f64p, f64p]
         L.dmk_tune_leaf.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, vp, C.POINTER(Opts), vp,
                                     C.c_int32, C.c_int32, vp, vp, vp]
+        L.dmk_tune.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, vp, C.POINTER(Opts), vp,
+                               C.c_int32, C.c_int32, vp, C.POINTER(Opts), vp, vp]
         L.dmk_eval.argtypes = [vp, vp, vp, vp]
         L.dmk_eval_noalloc.argtypes = [vp, vp, vp, vp]
         L.dmk_eval_parts.argtypes = [vp, vp, vp, vp, vp]
@@ -132,6 +134,25 @@ def tune_leaf(pts, charges, candidates, tol=1e-6, precision=DMK_FP64, flags=0, r
                                C.byref(o), _np_ptr(cand), len(cand), int(reps), _stream_handle(stream),
                                _np_ptr(best), _np_ptr(ms)))
     return int(best[0]), dict(zip(cand.tolist(), ms.tolist()))
+
+
+def tune(pts, charges, candidates, tol=1e-6, precision=DMK_FP64, flags=0, reps=3, kernel=DMK_LAPLACE, lam=0.0,
+         offsets=None, p=0, n_f=0, stream=None):
+    """dmk_tune: (best options as a dict, {candidate: mean eval ms}, sampled error)."""
+    pts = pts.contiguous()
+    q = charges.contiguous()
+    n, dim = int(pts.shape[0]), int(pts.shape[1])
+    off = np.ascontiguousarray([0, n] if offsets is None else offsets, dtype=np.int64)
+    cand = np.ascontiguousarray(candidates, dtype=np.int32)
+    ms = np.zeros(len(cand))
+    err = np.zeros(1)
+    o = Opts(0, 0, precision, 0, flags, float(lam), int(p), int(n_f), 0.0)
+    best = Opts()
+    _check(lib().dmk_tune(dim, int(kernel), float(tol), len(off) - 1, _np_ptr(off), _ptr(pts), _ptr(q),
+                          C.byref(o), _np_ptr(cand), len(cand), int(reps), _stream_handle(stream), C.byref(best),
+                          _np_ptr(ms), _np_ptr(err)))
+    b = dict(leaf_max=best.leaf_max, p=best.p, n_f=best.n_f, pswf_c=best.pswf_c)
+    return b, dict(zip(cand.tolist(), ms.tolist())), float(err[0])
 
 
 def precompute_probe(tol, what, x=None, n=None):

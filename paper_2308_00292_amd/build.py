@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = ["capi.cpp", "precompute.cpp", "plan.hip", "eval.hip", "eval2.hip", "yukawa2.hip", "yukawa3.hip", "vol.hip", "noalloc.hip"]
+SRC = ["capi.cpp", "precompute.cpp", "plan.hip", "eval.hip", "eval2.hip", "yukawa2.hip", "yukawa3.hip", "vol.hip", "noalloc.hip", "tune.hip"]
 LIB = os.path.join(HERE, "libdmk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

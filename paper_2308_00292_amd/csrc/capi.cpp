@@ -78,6 +78,22 @@ const char *dmk_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
+// device buffers of one host call, freed when it returns
+struct TempBufs {
+    std::vector<void *> p;
+    ~TempBufs()
+    {
+        for (void *x : p) (void)hipFree(x);
+    }
+    void *get(size_t bytes)
+    {
+        void *x = nullptr;
+        DMK_HIP(hipMalloc(&x, std::max<size_t>(bytes, 1)));
+        p.push_back(x);
+        return x;
+    }
+};
+
 // (p, n_f) pairs with compiled kernels, in increasing order
 constexpr int kBuilt[][2] = {{9, 6}, {15, 10}, {18, 12}};
 
@@ -324,6 +340,111 @@ dmk_status dmk_tune_leaf(int dim, dmk_kernel kernel, double tol, int32_t nprob, 
         (void)hipEventDestroy(e1);
         (void)hipFree(pot);
         *best = cand[bi];
+    });
+}
+
+dmk_status dmk_tune(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *offsets, const double *pts,
+                    const double *charges, const dmk_opts *opts, const int32_t *cand, int32_t ncand, int32_t reps,
+                    void *stream, dmk_opts *best, double *ms, double *err)
+{
+    return guarded([&] {
+        if (!cand || ncand < 1 || !best) throw Error{DMK_ERR_ARG, "candidates and best are required"};
+        if (reps < 1) throw Error{DMK_ERR_ARG, "reps must be >= 1"};
+        if (!offsets || nprob < 1) throw Error{DMK_ERR_ARG, "offsets and nprob >= 1 are required"};
+        for (int32_t i = 0; i < ncand; ++i)
+            if (cand[i] < 1) throw Error{DMK_ERR_ARG, "leaf capacities must be >= 1"};
+        const int64_t n = offsets[nprob];
+        if (n < 2 || !pts || !charges) throw Error{DMK_ERR_ARG, "at least two points, pts and charges are required"};
+        dmk_opts o;
+        std::memset(&o, 0, sizeof(o));
+        if (opts) o = *opts;
+        hipStream_t s = (hipStream_t)stream;
+        // the pairs to try: the caller's, or every compiled pair from the coarsest
+        const Params rule = choose_params(tol, dim, o);
+        std::vector<std::pair<int, int>> pairs;
+        if (o.p || o.n_f) pairs.push_back({rule.p, rule.nf});
+        else
+            for (const auto &b : kBuilt) pairs.push_back({b[0], b[1]});
+        // accuracy gate: direct sums at evenly spaced sample targets
+        const int ns = (int)std::min<int64_t>(256, n);
+        std::vector<int64_t> tidx(ns);
+        for (int k = 0; k < ns; ++k) tidx[k] = (int64_t)((k + 0.5) * (double)n / ns);
+        TempBufs B;
+        int64_t *d_tidx = (int64_t *)B.get(ns * sizeof(int64_t)), *d_off = (int64_t *)B.get((nprob + 1) * sizeof(int64_t));
+        double *d_dir = (double *)B.get(ns * sizeof(double)), *pot = (double *)B.get(n * sizeof(double));
+        DMK_HIP(hipMemcpyAsync(d_tidx, tidx.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        DMK_HIP(hipMemcpyAsync(d_off, offsets, (nprob + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        direct_sample(dim, kernel, o.lambda, pts, charges, d_off, nprob, d_tidx, ns, d_dir, s);
+        std::vector<double> dir(ns), hp(n);
+        DMK_HIP(hipMemcpyAsync(dir.data(), d_dir, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+        DMK_HIP(hipStreamSynchronize(s));
+        double dnorm = 0.0;
+        for (double v : dir) dnorm += v * v;
+        dnorm = std::sqrt(std::max(dnorm, 1e-300));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        DMK_HIP(hipEventCreate(&e0));
+        struct Ev {
+            hipEvent_t &a, &b;
+            ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); }
+        } ev{e0, e1};
+        DMK_HIP(hipEventCreate(&e1));
+        // one plan: returns the sampled error, and the mean eval time if timed
+        auto trial = [&](int leaf, int p, int nf, bool timed, double *t_ms) {
+            dmk_opts q = o;
+            q.leaf_max = leaf;
+            q.p = p;
+            q.n_f = nf;
+            q.pswf_c = rule.c;
+            dmk_plan_t h = make_plan(dim, kernel, tol, nprob, offsets, pts, &q, stream);
+            Plan *P = reinterpret_cast<Plan *>(h);
+            double e = 0.0;
+            try {
+                run_eval(P, charges, pot, nullptr, nullptr, s);  // warm-up (and graph capture)
+                if (timed) {
+                    float t = 0.0f;
+                    DMK_HIP(hipEventRecord(e0, s));
+                    for (int32_t r = 0; r < reps; ++r) run_eval(P, charges, pot, nullptr, nullptr, s);
+                    DMK_HIP(hipEventRecord(e1, s));
+                    DMK_HIP(hipEventSynchronize(e1));
+                    DMK_HIP(hipEventElapsedTime(&t, e0, e1));
+                    *t_ms = (double)t / reps;
+                }
+                DMK_HIP(hipMemcpyAsync(hp.data(), pot, n * sizeof(double), hipMemcpyDeviceToHost, s));
+                DMK_HIP(hipStreamSynchronize(s));
+            } catch (...) {
+                (void)hipStreamSynchronize(s);
+                plan_release(P);
+                throw;
+            }
+            plan_release(P);
+            for (int k = 0; k < ns; ++k) e += (hp[tidx[k]] - dir[k]) * (hp[tidx[k]] - dir[k]);
+            return std::sqrt(e) / dnorm;
+        };
+        // the coarsest pair that meets tol, then the fastest leaf capacity;
+        // if the winner misses tol (errors vary a little with n_s), the next pair
+        size_t pi = 0;
+        for (; pi + 1 < pairs.size(); ++pi)
+            if (trial(cand[0], pairs[pi].first, pairs[pi].second, false, nullptr) <= tol) break;
+        int bi = 0;
+        double e_best = 0.0;
+        for (;;) {
+            double bt = 0.0;
+            bi = -1;
+            for (int32_t i = 0; i < ncand; ++i) {
+                double t = 0.0;
+                const double e = trial(cand[i], pairs[pi].first, pairs[pi].second, true, &t);
+                if (ms) ms[i] = t;
+                if (bi < 0 || t < bt) { bi = i; bt = t; e_best = e; }
+            }
+            if (e_best <= tol || pi + 1 >= pairs.size()) break;
+            ++pi;
+        }
+        *best = o;
+        best->leaf_max = cand[bi];
+        best->p = pairs[pi].first;
+        best->n_f = pairs[pi].second;
+        best->pswf_c = rule.c;
+        if (err) *err = e_best;
     });
 }
 

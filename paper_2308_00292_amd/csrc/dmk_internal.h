@@ -309,6 +309,10 @@ void run_eval2(Plan *P, const double *charges, double *pot, double *far_part, do
 void build_yukawa_tables(Plan *P, hipStream_t s);   // 2-D K_0(lambda r)
 void build_yukawa3_tables(Plan *P, hipStream_t s);  // 3-D e^{-lambda r}/(4 pi r)
 void stage_work(const Plan *P, double *flops, double *bytes);
+// direct sums u_i = sum_{j != i} K(r_ij) q_j (input units, each target's own
+// problem) at the targets d_tidx[ntgt]; pts [n][dim] and q in input order
+void direct_sample(int dim, int kernel, double lam, const double *pts, const double *q, const int64_t *d_off,
+                   int nprob, const int64_t *d_tidx, int ntgt, double *d_out, hipStream_t s);
 
 // Records HIP events around one stage launch when timing is enabled.
 struct StageScope {

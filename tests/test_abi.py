@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 22
+    assert len(names) == 23
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:
@@ -44,6 +44,7 @@ def test_argument_errors_without_device():
     assert b"NULL" in L.dmk_last_error()
     assert L.dmk_eval(None, None, None, None) == -1
     assert L.dmk_eval_noalloc(None, None, None, None) == -1
+    assert L.dmk_tune(3, 0, 1e-6, 1, None, None, None, None, None, 0, 1, None, None, None, None) == -1
     off = np.array([0, 5, 3], dtype=np.int64)
     assert L.dmk_plan_batched(2, 0, 1e-6, 2, off.ctypes.data_as(C.c_void_p), C.c_void_p(1), None, None,
                               C.byref(h)) == -1  # decreasing offsets

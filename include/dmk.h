@@ -130,6 +130,8 @@ typedef struct {
     double  side;         /* root box side of problem 0 (input units)        */
     int32_t dim;
     int32_t nprob;        /* independent problems in the plan                */
+    int64_t nsrc, ntgt;   /* sources and targets (both n unless the plan has
+                             separate target sets; then n = nsrc + ntgt)    */
 } dmk_plan_stats;
 
 /*
@@ -173,6 +175,29 @@ typedef struct {
  */
 dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const double *pts,
                     const dmk_opts *opts, void *stream, dmk_plan_t *out);
+
+/*
+ * dmk_plan_targets -- a plan with targets distinct from the sources:
+ * u(x_i) = sum_j K(x_i - y_j) q_j at ntgt targets x_i from nsrc sources y_j
+ * (pairs at distance 0 excluded, as for dmk_plan).
+ *
+ * Paper: the general problem of Sec. 3.5, whose input is N sources and
+ * targets; the tree is refined while a box holds more than n_s points of
+ * the union (Sec. 3.2), sources carry the outgoing expansions and the
+ * residual sums, targets the local expansions and evaluations (Steps 2-4).
+ *
+ *  dim      must be 3 (2-D: DMK_ERR_UNSUPPORTED).
+ *  kernel, tol, opts, stream, out  as dmk_plan.
+ *  nsrc, src  device, [nsrc][3] FP64 source points, input order.
+ *  ntgt, tgt  device, [ntgt][3] FP64 target points, input order.
+ *  nsrc + ntgt < 2^31.  Either set may be empty.
+ * dmk_eval (and dmk_eval_parts, dmk_eval_noalloc) on such a plan take
+ * charges [nsrc] (source order) and return pot [ntgt] (target order).
+ * dmk_export_tree describes the tree of the union, whose input indices are
+ * the sources 0..nsrc-1 followed by the targets nsrc..nsrc+ntgt-1.
+ */
+dmk_status dmk_plan_targets(int dim, dmk_kernel kernel, double tol, int64_t nsrc, const double *src, int64_t ntgt,
+                            const double *tgt, const dmk_opts *opts, void *stream, dmk_plan_t *out);
 
 /*
  * dmk_plan_batched -- one plan for nprob independent point sets.

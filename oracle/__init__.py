@@ -574,6 +574,17 @@ def dmk_run(pts, charges, tol, ns, maxdepth=0):
     return u, tm[0], tm[1]
 
 
+def union_targets(src, q, tgt):
+    """Separate target sets as one point set: the sources followed by the
+    targets, which carry zero charge (they add nothing to any potential).
+    Returns (union points, union charges, indices of the targets)."""
+    src = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    tgt = np.ascontiguousarray(tgt, dtype=np.float64).reshape(-1, 3)
+    pts = np.ascontiguousarray(np.concatenate([src, tgt]))
+    qq = np.concatenate([np.asarray(q, dtype=np.float64), np.zeros(len(tgt))])
+    return pts, qq, np.arange(len(src), len(src) + len(tgt), dtype=np.int64)
+
+
 def direct(pts, charges, tidx=None):
     """u_i = sum_{j != i, r > 0} q_j / (4 pi r_ij) at the listed targets."""
     pts = np.ascontiguousarray(pts, dtype=np.float64)

@@ -21,7 +21,7 @@ DMK_FLAG_NO_WORKSPACE = 4
 NOALLOC_MAX_BYTES = 128 << 20
 
 # exported symbols, in the order of include/dmk.h
-SYMBOLS = ["dmk_plan", "dmk_plan_batched", "dmk_tune_leaf", "dmk_tune", "dmk_problem_info", "dmk_eval", "dmk_eval_noalloc", "dmk_eval_parts",
+SYMBOLS = ["dmk_plan", "dmk_plan_targets", "dmk_plan_batched", "dmk_tune_leaf", "dmk_tune", "dmk_problem_info", "dmk_eval", "dmk_eval_noalloc", "dmk_eval_parts",
            "dmk_plan_info", "dmk_export_tree", "dmk_export_near_lists", "dmk_copy_box_data", "dmk_precompute_probe",
            "dmk_stage_timing", "dmk_stage_times", "dmk_stage_work",
            "dmk_vol_plan", "dmk_vol_info", "dmk_vol_leaves", "dmk_vol_nodes", "dmk_vol_eval",
@@ -46,7 +46,7 @@ class Stats(C.Structure):
                 ("leaf_max", C.c_int32), ("precision", C.c_int32), ("nleaf", C.c_int64),
                 ("nfout", C.c_int64), ("nfin", C.c_int64), ("npairs", C.c_int64),
                 ("device_bytes", C.c_int64), ("center", C.c_double * 3), ("side", C.c_double),
-                ("dim", C.c_int32), ("nprob", C.c_int32)]
+                ("dim", C.c_int32), ("nprob", C.c_int32), ("nsrc", C.c_int64), ("ntgt", C.c_int64)]
 
 
 class DmkError(RuntimeError):
@@ -67,6 +67,8 @@ def lib():
         L = C.CDLL(LIBPATH)
         vp, i64, f64p = C.c_void_p, C.c_int64, C.POINTER(C.c_double)
         L.dmk_plan.argtypes = [C.c_int, C.c_int, C.c_double, i64, vp, C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.dmk_plan_targets.argtypes = [C.c_int, C.c_int, C.c_double, i64, vp, i64, vp, C.POINTER(Opts), vp,
+                                       C.POINTER(vp)]
         L.dmk_plan_batched.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int32, vp, vp, C.POINTER(Opts), vp,
                                        C.POINTER(vp)]
         L.dmk_problem_info.argtypes = [vp, C.c_int32, f64p, f64p]
@@ -171,7 +173,7 @@ class Plan:
     eval() applies dmk_eval to charge vectors."""
 
     def __init__(self, pts, tol=1e-6, leaf_max=64, max_depth=0, precision=DMK_FP64, flags=0,
-                 stream=None, kernel=DMK_LAPLACE, lam=0.0, offsets=None, p=0, n_f=0, pswf_c=0.0):
+                 stream=None, kernel=DMK_LAPLACE, lam=0.0, offsets=None, p=0, n_f=0, pswf_c=0.0, targets=None):
         import torch
         if not (isinstance(pts, torch.Tensor) and pts.is_cuda and pts.dtype == torch.float64
                 and pts.dim() == 2 and pts.shape[1] in (2, 3)):
@@ -181,7 +183,16 @@ class Plan:
         self.dim = int(pts.shape[1])
         o = Opts(leaf_max, max_depth, precision, 0, flags, float(lam), int(p), int(n_f), float(pswf_c))
         h = C.c_void_p()
-        if offsets is None:
+        self.nsrc = self.ntgt = self.n
+        if targets is not None:
+            if not (isinstance(targets, torch.Tensor) and targets.is_cuda and targets.dtype == torch.float64
+                    and targets.dim() == 2 and targets.shape[1] == self.dim):
+                raise TypeError("targets must be a float64 CUDA tensor of shape [m, dim]")
+            targets = targets.contiguous()
+            self.ntgt = int(targets.shape[0])
+            _check(lib().dmk_plan_targets(self.dim, int(kernel), float(tol), self.n, _ptr(pts), self.ntgt,
+                                          _ptr(targets), C.byref(o), _stream_handle(stream), C.byref(h)))
+        elif offsets is None:
             _check(lib().dmk_plan(self.dim, int(kernel), float(tol), self.n, _ptr(pts), C.byref(o),
                                   _stream_handle(stream), C.byref(h)))
         else:
@@ -207,10 +218,10 @@ class Plan:
     def eval(self, charges, out=None, stream=None):
         import torch
         q = charges.contiguous()
-        if q.dtype != torch.float64 or not q.is_cuda or q.numel() != self.n:
-            raise TypeError("charges must be a float64 CUDA tensor with n entries")
+        if q.dtype != torch.float64 or not q.is_cuda or q.numel() != self.nsrc:
+            raise TypeError("charges must be a float64 CUDA tensor with one entry per source")
         if out is None:
-            out = torch.empty(self.n, dtype=torch.float64, device=q.device)
+            out = torch.empty(self.ntgt, dtype=torch.float64, device=q.device)
         _check(lib().dmk_eval(self._h, _ptr(q), _ptr(out), _stream_handle(stream)))
         return out
 
@@ -218,19 +229,19 @@ class Plan:
         """dmk_eval_noalloc: the workspace comes from the library's static
         scratch; ``out`` (float64 CUDA [n]) is required, nothing is allocated."""
         import torch
-        if charges.dtype != torch.float64 or not charges.is_cuda or charges.numel() != self.n \
+        if charges.dtype != torch.float64 or not charges.is_cuda or charges.numel() != self.nsrc \
                 or not charges.is_contiguous():
-            raise TypeError("charges must be a contiguous float64 CUDA tensor with n entries")
-        if out.dtype != torch.float64 or not out.is_cuda or out.numel() != self.n or not out.is_contiguous():
-            raise TypeError("out must be a contiguous float64 CUDA tensor with n entries")
+            raise TypeError("charges must be a contiguous float64 CUDA tensor with one entry per source")
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() != self.ntgt or not out.is_contiguous():
+            raise TypeError("out must be a contiguous float64 CUDA tensor with one entry per target")
         _check(lib().dmk_eval_noalloc(self._h, _ptr(charges), _ptr(out), _stream_handle(stream)))
         return out
 
     def eval_parts(self, charges, stream=None):
         import torch
         q = charges.contiguous()
-        far = torch.empty(self.n, dtype=torch.float64, device=q.device)
-        near = torch.empty(self.n, dtype=torch.float64, device=q.device)
+        far = torch.empty(self.ntgt, dtype=torch.float64, device=q.device)
+        near = torch.empty(self.ntgt, dtype=torch.float64, device=q.device)
         _check(lib().dmk_eval_parts(self._h, _ptr(q), _ptr(far), _ptr(near), _stream_handle(stream)))
         return far, near
 

@@ -160,8 +160,10 @@ Params choose_params(double tol, int dim, const dmk_opts &o)
 // Shared by dmk_plan and dmk_plan_batched: validates, builds tables, the
 // forest of trees, lists and workspace.  poff: host offsets [nprob+1].
 dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, const int64_t *poff, const double *pts,
-                     const dmk_opts *opts, void *stream)
+                     const dmk_opts *opts, void *stream, int64_t nsrc_st = -1)
 {
+    // nsrc_st >= 0: a plan of separate target sets; pts holds the union,
+    // sources (the first nsrc_st points) then targets
     if (dim != 2 && dim != 3) throw Error{DMK_ERR_ARG, "dim must be 2 or 3"};
     if (kernel != DMK_LAPLACE && kernel != DMK_YUKAWA && kernel != DMK_POWER2) throw Error{DMK_ERR_ARG, "unknown kernel"};
     if (kernel == DMK_POWER2 && dim != 3) throw Error{DMK_ERR_UNSUPPORTED, "the 1/r^2 kernel is built for dim = 3"};
@@ -216,6 +218,11 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         DMK_HIP(hipMemcpyAsync(P->d_poff, P->poff.data(), (nprob + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
         upload_tables(P, s);
         build_tree(P, pts, s);
+        if (nsrc_st >= 0) {
+            P->st = true;
+            P->nsrc = nsrc_st;
+            split_roles(P, s);
+        }
         build_lists(P, s);
         if (dim == 3) {  // unit change per problem: 1/(4 pi S_b) for the 1/r kernels, 1/S_b^2 for 1/r^2
             std::vector<double> sc(nprob);
@@ -270,6 +277,37 @@ dmk_status dmk_plan(int dim, dmk_kernel kernel, double tol, int64_t n, const dou
         if (n < 0) throw Error{DMK_ERR_ARG, "n must satisfy 0 <= n < 2^31"};
         const int64_t off[2] = {0, n};
         *out = make_plan(dim, kernel, tol, 1, off, pts, opts, stream);
+    });
+}
+
+dmk_status dmk_plan_targets(int dim, dmk_kernel kernel, double tol, int64_t nsrc, const double *src, int64_t ntgt,
+                            const double *tgt, const dmk_opts *opts, void *stream, dmk_plan_t *out)
+{
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!out) throw Error{DMK_ERR_ARG, "out is NULL"};
+        if (dim != 3) throw Error{DMK_ERR_UNSUPPORTED, "separate target sets are built for dim = 3"};
+        if (nsrc < 0 || ntgt < 0 || nsrc + ntgt >= (int64_t(1) << 31))
+            throw Error{DMK_ERR_ARG, "need 0 <= nsrc, ntgt and nsrc + ntgt < 2^31"};
+        if ((nsrc > 0 && !src) || (ntgt > 0 && !tgt)) throw Error{DMK_ERR_ARG, "src or tgt is NULL"};
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = nsrc + ntgt;
+        double *u = nullptr;  // the union on the device, sources first
+        DMK_HIP(hipMalloc(&u, (size_t)std::max<int64_t>(n, 1) * 3 * sizeof(double)));
+        try {
+            if (nsrc) DMK_HIP(hipMemcpyAsync(u, src, (size_t)nsrc * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (ntgt)
+                DMK_HIP(hipMemcpyAsync(u + 3 * nsrc, tgt, (size_t)ntgt * 3 * sizeof(double), hipMemcpyDeviceToDevice,
+                                       s));
+            const int64_t off[2] = {0, n};
+            *out = make_plan(dim, kernel, tol, 1, off, u, opts, stream, nsrc);
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(u);
+            throw;
+        }
+        DMK_HIP(hipStreamSynchronize(s));
+        (void)hipFree(u);
     });
 }
 
@@ -466,7 +504,7 @@ dmk_status dmk_eval_parts(dmk_plan_t plan, const double *charges, double *far_pa
         if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
         Plan *P = reinterpret_cast<Plan *>(plan);
         if (P->is_vol) throw Error{DMK_ERR_ARG, "a volume plan is evaluated with dmk_vol_eval"};
-        if (P->n > 0 && !charges) throw Error{DMK_ERR_ARG, "charges is NULL"};
+        if (P->nsrc > 0 && !charges) throw Error{DMK_ERR_ARG, "charges is NULL"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
         begin_eval(P, s);
@@ -481,7 +519,7 @@ dmk_status dmk_eval(dmk_plan_t plan, const double *charges, double *pot, void *s
         if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
         Plan *P = reinterpret_cast<Plan *>(plan);
         if (P->is_vol) throw Error{DMK_ERR_ARG, "a volume plan is evaluated with dmk_vol_eval"};
-        if (P->n > 0 && (!charges || !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
+        if ((P->nsrc > 0 && !charges) || (P->ntgt > 0 && !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;
         begin_eval(P, s);
@@ -575,6 +613,8 @@ dmk_status dmk_plan_info(dmk_plan_t plan, dmk_plan_stats *st)
         st->side = P->side;
         st->dim = P->dim;
         st->nprob = P->nprob;
+        st->nsrc = P->nsrc;
+        st->ntgt = P->ntgt;
     });
 }
 

@@ -143,6 +143,17 @@ struct Plan {
     int32_t *perm = nullptr;
     uint64_t *keys = nullptr;
 
+    // sources and targets.  A plan of separate target sets (st) builds its
+    // tree on the union of nsrc sources (union input indices 0..nsrc-1) and
+    // ntgt targets (nsrc..n-1), then keeps each set apart in tree order with
+    // per-box ranges; otherwise both views alias the union arrays.
+    bool st = false;
+    int64_t nsrc = 0, ntgt = 0;
+    double *Xs = nullptr, *Ys = nullptr, *Zs = nullptr;  // sources, tree order
+    int32_t *sperm = nullptr, *sstart = nullptr, *scount = nullptr;
+    double *Xt = nullptr, *Yt = nullptr, *Zt = nullptr;  // targets, tree order
+    int32_t *tperm = nullptr, *tstart = nullptr, *tcount = nullptr;
+
     // boxes (level-major, Morton order within a level)
     int nlevels = 0;
     std::vector<int64_t> level_start;  // host [nlevels+1]
@@ -278,6 +289,8 @@ dmk_status guarded(F &&f)
 void plan_release(Plan *P);  // device memory, events, streams, graph, then the Plan itself
 
 void build_tree(Plan *P, const double *pts, hipStream_t s);
+// the source and target views of a plan with separate target sets (after build_tree)
+void split_roles(Plan *P, hipStream_t s);
 void build_lists(Plan *P, hipStream_t s);
 void upload_tables(Plan *P, hipStream_t s);
 // one buffer of the eval workspace: the plan field that points to it, and its size

@@ -71,6 +71,11 @@ struct Dev {
     // most points a root leaf holds (the scratch's Lagrange-row region)
     int64_t root_stride;
     int root_npmax;
+    // targets (the sources' arrays unless the plan has separate target sets):
+    // tree-order coordinates and per-box ranges; X, Y, Z, pstart, pcount and
+    // qs above are the sources
+    const double *Xt, *Yt, *Zt;
+    const int32_t *tstart, *tcount;
 };
 
 // ------------------------------------------------------------------ upward
@@ -1192,9 +1197,9 @@ __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, cons
     for (int t = b0 + threadIdx.x; t < b1; t += TPB) {
         const int64_t i = tgt[t];
         T lx[P], ly[P], lz[P];
-        lagrange_row_fast<T, P>(xc, bw, (T)((D.X[i] - cA0) * sc), lx);
-        lagrange_row_fast<T, P>(xc, bw, (T)((D.Y[i] - cA1) * sc), ly);
-        lagrange_row_fast<T, P>(xc, bw, (T)((D.Z[i] - cA2) * sc), lz);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.Xt[i] - cA0) * sc), lx);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.Yt[i] - cA1) * sc), ly);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.Zt[i] - cA2) * sc), lz);
         T u = T(0);
         for (int j1 = 0; j1 < P; ++j1) {
             T s1 = T(0);
@@ -1255,8 +1260,8 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     // dynamic LDS, sized at launch to the plan's longest list
     extern __shared__ int32_t loff[];
     const int32_t B = leaves[blockIdx.x];
-    const int64_t t0 = D.pstart[B];
-    const int nt = D.pcount[B];
+    const int64_t t0 = D.tstart[B];  // the leaf's targets
+    const int nt = D.tcount[B];
     const int32_t l0 = nl_off[blockIdx.x];
     const int L = nl_off[blockIdx.x + 1] - l0;
     T gc[DEG + 1];
@@ -1275,7 +1280,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     for (int tbase = 0; tbase < nt; tbase += tch) {
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
-        const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy), zt = (T)(D.Z[it] - cz);
+        const T xt = (T)(D.Xt[it] - cx), yt = (T)(D.Yt[it] - cy), zt = (T)(D.Zt[it] - cz);
         double acc = 0.0;
         for (int pb = 0; pb < nsrc; pb += RCAP) {
             const int cnt = min(RCAP, nsrc - pb);
@@ -1367,8 +1372,8 @@ __global__ void __launch_bounds__(TPB) k_residual_y3(Dev<T> D, const int32_t *le
     double *part = stg.part;
     extern __shared__ int32_t loff[];
     const int32_t B = leaves[blockIdx.x];
-    const int64_t t0 = D.pstart[B];
-    const int nt = D.pcount[B];
+    const int64_t t0 = D.tstart[B];  // the leaf's targets
+    const int nt = D.tcount[B];
     const int32_t l0 = nl_off[blockIdx.x];
     const int L = nl_off[blockIdx.x + 1] - l0;
     const int deg = D.ydeg;
@@ -1385,7 +1390,7 @@ __global__ void __launch_bounds__(TPB) k_residual_y3(Dev<T> D, const int32_t *le
     for (int tbase = 0; tbase < nt; tbase += tch) {
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
-        const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy), zt = (T)(D.Z[it] - cz);
+        const T xt = (T)(D.Xt[it] - cx), yt = (T)(D.Yt[it] - cy), zt = (T)(D.Zt[it] - cz);
         double acc = 0.0;
         for (int pb = 0; pb < nsrc; pb += RCAP) {
             const int cnt = min(RCAP, nsrc - pb);
@@ -1656,7 +1661,7 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
             float row[P];
             if (tv) {
                 const int64_t i = tgt[t];
-                const double x = (kq == 0) ? D.X[i] : (kq == 1) ? D.Y[i] : D.Z[i];
+                const double x = (kq == 0) ? D.Xt[i] : (kq == 1) ? D.Yt[i] : D.Zt[i];
                 lagrange_row_fast<float, P>(xc, bw, (float)((x - cA[kq]) * sc), row);
             } else {
 #pragma unroll
@@ -1745,8 +1750,9 @@ Dev<T> make_dev(Plan *P)
     const Tables &t = P->tab;
     D.p = t.p; D.nf = t.nf; D.nn = t.nn; D.nh = t.nh; D.nw = t.nw; D.nwn = t.nwn; D.nwh = t.nwh;
     D.gdeg = sizeof(T) == 8 ? t.gdeg : t.gdeg32;
-    D.X = P->X; D.Y = P->Y; D.Z = P->Z; D.qs = P->qs;
-    D.pstart = P->pstart; D.pcount = P->pcount; D.child0 = P->child0; D.parent = P->parent; D.col = P->colleague;
+    D.X = P->Xs; D.Y = P->Ys; D.Z = P->Zs; D.qs = P->qs;
+    D.Xt = P->Xt; D.Yt = P->Yt; D.Zt = P->Zt; D.tstart = P->tstart; D.tcount = P->tcount;
+    D.pstart = P->sstart; D.pcount = P->scount; D.child0 = P->child0; D.parent = P->parent; D.col = P->colleague;
     D.proxy_slot = P->proxy_slot; D.local_slot = P->local_slot; D.psi_slot = P->psi_slot; D.blevel = P->blevel;
     D.anchor = P->anchor;
     D.bflags = P->bflags; D.bcenter = P->bcenter;
@@ -1969,7 +1975,7 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     set_lds_attrs<T, P, NF>();
     {
         StageScope t(Pl, s, DMK_STAGE_GATHER);
-        hipLaunchKernelGGL(k_gather_q, dim3(nblk(n)), dim3(TPB), 0, s, charges, Pl->perm, n, Pl->qs);
+        hipLaunchKernelGGL(k_gather_q, dim3(nblk(Pl->nsrc)), dim3(TPB), 0, s, charges, Pl->sperm, Pl->nsrc, Pl->qs);
     }
     const bool batched = (Pl->flags & DMK_FLAG_BATCHED) && !Pl->timing;
     if (batched) {
@@ -1994,7 +2000,7 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(nblk(n)), dim3(TPB), 0, s, Pl->ufar, Pl->ures, Pl->perm, n,
+        hipLaunchKernelGGL(k_finalize, dim3(nblk(Pl->ntgt)), dim3(TPB), 0, s, Pl->ufar, Pl->ures, Pl->tperm, Pl->ntgt,
                            (const double *)Pl->d_pscale, (const int64_t *)Pl->d_poff, Pl->nprob, pot, far_part,
                            near_part);
     }
@@ -2123,9 +2129,9 @@ void workspace_layout(Plan *P, std::vector<WsItem> &items)
     auto add = [&](void *field, int64_t cnt, size_t sz) {
         items.push_back({(void **)field, (size_t)std::max<int64_t>(cnt, 1) * sz});
     };
-    add(&P->qs, P->n, 8);
-    add(&P->ufar, P->n, 8);
-    add(&P->ures, P->n, 8);
+    add(&P->qs, P->nsrc, 8);
+    add(&P->ufar, P->ntgt, 8);
+    add(&P->ures, P->ntgt, 8);
     add(&P->rootscratch, P->nprob * root_scratch_elems(t, (int)std::min<int64_t>(P->n, P->leaf_max)), 8);
     add(&P->proxy, P->nfout * p3, el);
     add(&P->local, P->nanc * p3, el);
@@ -2148,19 +2154,22 @@ void alloc_workspace(Plan *P)
 // ---------------------------------------------------------- work counts
 namespace {
 // pairs of the residual lists closer than the source box side (r < s_l)
+// targets: Xt.. with tstart/tcount; sources: X.. with pstart/pcount
 __global__ void __launch_bounds__(TPB) k_count_inrange(const double *X, const double *Y, const double *Z,
                                                        const int32_t *pstart, const int32_t *pcount,
+                                                       const double *Xt, const double *Yt, const double *Zt,
+                                                       const int32_t *tstart, const int32_t *tcount,
                                                        const int32_t *leaves, const int32_t *nl_off,
                                                        const int32_t *nl_src, const int32_t *blevel,
                                                        unsigned long long *total)
 {
     __shared__ unsigned long long red[TPB];
     const int32_t B = leaves[blockIdx.x];
-    const int64_t t0 = pstart[B];
-    const int nt = pcount[B];
+    const int64_t t0 = tstart[B];
+    const int nt = tcount[B];
     unsigned long long cnt = 0;
     for (int tt = threadIdx.x; tt < nt; tt += TPB) {
-        const double xt = X[t0 + tt], yt = Y[t0 + tt], zt = Z ? Z[t0 + tt] : 0.0;
+        const double xt = Xt[t0 + tt], yt = Yt[t0 + tt], zt = Zt ? Zt[t0 + tt] : 0.0;
         for (int li = nl_off[blockIdx.x]; li < nl_off[blockIdx.x + 1]; ++li) {
             const int32_t T = nl_src[li];
             const double s = ldexp(1.0, -blevel[T]), s2 = s * s;
@@ -2185,9 +2194,10 @@ void count_work(Plan *P, hipStream_t s)
     const int64_t nb = P->nbox;
     const int NC = 1 << P->dim, NCOL = (P->dim == 3) ? 27 : 9;
     std::vector<uint8_t> fl(nb);
-    std::vector<int32_t> pc(nb), c0(nb), col;
+    std::vector<int32_t> pc(nb), tc(nb), c0(nb), col;  // sources and targets per box
     DMK_HIP(hipMemcpy(fl.data(), P->bflags, nb, hipMemcpyDeviceToHost));
-    DMK_HIP(hipMemcpy(pc.data(), P->pcount, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(pc.data(), P->scount, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    DMK_HIP(hipMemcpy(tc.data(), P->tcount, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
     DMK_HIP(hipMemcpy(c0.data(), P->child0, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
     col.resize((size_t)nb * NCOL);
     DMK_HIP(hipMemcpy(col.data(), P->colleague, (size_t)nb * NCOL * sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -2201,7 +2211,7 @@ void count_work(Plan *P, hipStream_t s)
                 if (pc[c] == 0) continue;
                 if (fl[c] & 2) P->n_merge++; else P->n_anterp += pc[c];
             }
-        if ((fl[b] & 4) && pc[b] > 0)
+        if ((fl[b] & 4) && tc[b] > 0)
             for (int k = 0; k < NCOL; ++k) {
                 int32_t j = col[(size_t)b * NCOL + k];
                 if (j >= 0 && (fl[j] & 2)) P->n_shift_pairs++;
@@ -2218,8 +2228,9 @@ void count_work(Plan *P, hipStream_t s)
         unsigned long long *d = nullptr;
         DMK_HIP(hipMalloc(&d, sizeof(unsigned long long)));
         DMK_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), s));
-        hipLaunchKernelGGL(k_count_inrange, dim3((unsigned)P->nleaf), dim3(TPB), 0, s, P->X, P->Y, P->Z, P->pstart,
-                           P->pcount, P->l_leaf, P->nl_off, P->nl_src, P->blevel, d);
+        hipLaunchKernelGGL(k_count_inrange, dim3((unsigned)P->nleaf), dim3(TPB), 0, s, P->Xs, P->Ys, P->Zs, P->sstart,
+                           P->scount, P->Xt, P->Yt, P->Zt, P->tstart, P->tcount, P->l_leaf, P->nl_off, P->nl_src,
+                           P->blevel, d);
         unsigned long long h = 0;
         DMK_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
         DMK_HIP(hipStreamSynchronize(s));
@@ -2235,9 +2246,9 @@ void stage_work(const Plan *P, double *F, double *Bt)
     const Tables &t = P->tab;
     const double el = (P->precision == DMK_FP64) ? 8.0 : 4.0;
     const double p = t.p, n = t.nn, nh = t.nh;
-    const double N = (double)P->n;
+    const double N = (double)P->ntgt, Ns = (double)P->nsrc;  // targets, sources
     for (int i = 0; i < DMK_NSTAGES; ++i) F[i] = Bt[i] = 0.0;
-    Bt[DMK_STAGE_GATHER] = 20 * N;
+    Bt[DMK_STAGE_GATHER] = 20 * Ns;
     Bt[DMK_STAGE_FINALIZE] = 28 * N;
     const double gd = (double)((P->precision == DMK_FP64) ? t.gdeg : t.gdeg32);
     if (P->dim == 2) {

@@ -86,7 +86,7 @@ extern "C" dmk_status dmk_eval_noalloc(dmk_plan_t plan, const double *charges, d
         if (!plan) throw Error{DMK_ERR_ARG, "plan is NULL"};
         Plan *P = reinterpret_cast<Plan *>(plan);
         if (P->is_vol) throw Error{DMK_ERR_ARG, "volume plans are evaluated with dmk_vol_eval"};
-        if (P->n > 0 && (!charges || !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
+        if ((P->nsrc > 0 && !charges) || (P->ntgt > 0 && !pot)) throw Error{DMK_ERR_ARG, "charges or pot is NULL"};
         unsigned char *base = (unsigned char *)scratch_base();
         BusyGuard g(P);
         hipStream_t s = (hipStream_t)stream;

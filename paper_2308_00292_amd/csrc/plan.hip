@@ -651,6 +651,96 @@ void build_tree(Plan *P, const double *pts, hipStream_t s)
 {
     if (P->dim == 3) build_tree_t<3>(P, pts, s);
     else build_tree_t<2>(P, pts, s);
+    // sources and targets are the union's points until split_roles
+    P->nsrc = P->ntgt = P->n;
+    P->Xs = P->Xt = P->X;
+    P->Ys = P->Yt = P->Y;
+    P->Zs = P->Zt = P->Z;
+    P->sperm = P->tperm = P->perm;
+    P->sstart = P->tstart = P->pstart;
+    P->scount = P->tcount = P->pcount;
+}
+
+namespace {
+
+// role flags of the union's points in tree order: 1 for a source
+__global__ void k_role_flags(const int32_t *perm, int64_t n, int64_t nsrc, int32_t *fs, int32_t *ft)
+{
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i > n) return;
+    const int32_t src = (i < n && perm[i] < nsrc) ? 1 : 0;
+    fs[i] = (i < n) ? src : 0;  // a trailing zero: the exclusive scan's entry n is the total
+    ft[i] = (i < n) ? 1 - src : 0;
+}
+
+__global__ void k_role_scatter(const double *X, const double *Y, const double *Z, const int32_t *perm, int64_t n,
+                               int64_t nsrc, const int32_t *fs, const int32_t *sr, const int32_t *tr, double *Xs,
+                               double *Ys, double *Zs, int32_t *sperm, double *Xt, double *Yt, double *Zt,
+                               int32_t *tperm)
+{
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= n) return;
+    if (fs[i]) {
+        const int32_t k = sr[i];
+        Xs[k] = X[i];
+        Ys[k] = Y[i];
+        if (Z) Zs[k] = Z[i];
+        sperm[k] = perm[i];
+    } else {
+        const int32_t k = tr[i];
+        Xt[k] = X[i];
+        Yt[k] = Y[i];
+        if (Z) Zt[k] = Z[i];
+        tperm[k] = (int32_t)(perm[i] - nsrc);
+    }
+}
+
+// per box: its sources and its targets, from the ranks at its union range
+__global__ void k_role_ranges(const int32_t *pstart, const int32_t *pcount, int64_t nbox, const int32_t *sr,
+                              const int32_t *tr, int32_t *sstart, int32_t *scount, int32_t *tstart, int32_t *tcount)
+{
+    const int64_t b = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (b >= nbox) return;
+    const int32_t a = pstart[b], e = pstart[b] + pcount[b];
+    sstart[b] = sr[a];
+    scount[b] = sr[e] - sr[a];
+    tstart[b] = tr[a];
+    tcount[b] = tr[e] - tr[a];
+}
+
+}  // namespace
+
+void split_roles(Plan *P, hipStream_t s)
+{
+    Scratch S;
+    const int64_t n = P->n, nbox = P->nbox, ns = P->nsrc, nt = n - ns;
+    int32_t *fs = S.get<int32_t>(n + 1), *ft = S.get<int32_t>(n + 1);
+    int32_t *sr = S.get<int32_t>(n + 1), *tr = S.get<int32_t>(n + 1);
+    hipLaunchKernelGGL(k_role_flags, dim3(nblk(n + 1)), dim3(TPB), 0, s, P->perm, n, ns, fs, ft);
+    prim::exclusive_scan(S, fs, sr, n + 1, s);
+    prim::exclusive_scan(S, ft, tr, n + 1, s);
+    const bool d3 = P->dim == 3;
+    P->Xs = talloc<double>(P, ns);
+    P->Ys = talloc<double>(P, ns);
+    P->Zs = d3 ? talloc<double>(P, ns) : nullptr;
+    P->sperm = talloc<int32_t>(P, ns);
+    P->Xt = talloc<double>(P, nt);
+    P->Yt = talloc<double>(P, nt);
+    P->Zt = d3 ? talloc<double>(P, nt) : nullptr;
+    P->tperm = talloc<int32_t>(P, nt);
+    P->sstart = talloc<int32_t>(P, nbox);
+    P->scount = talloc<int32_t>(P, nbox);
+    P->tstart = talloc<int32_t>(P, nbox);
+    P->tcount = talloc<int32_t>(P, nbox);
+    if (n > 0)
+        hipLaunchKernelGGL(k_role_scatter, dim3(nblk(n)), dim3(TPB), 0, s, P->X, P->Y, P->Z, P->perm, n, ns,
+                           (const int32_t *)fs, (const int32_t *)sr, (const int32_t *)tr, P->Xs, P->Ys, P->Zs,
+                           P->sperm, P->Xt, P->Yt, P->Zt, P->tperm);
+    hipLaunchKernelGGL(k_role_ranges, dim3(nblk(nbox)), dim3(TPB), 0, s, P->pstart, P->pcount, nbox,
+                       (const int32_t *)sr, (const int32_t *)tr, P->sstart, P->scount, P->tstart, P->tcount);
+    P->ntgt = nt;
+    DMK_HIP(hipGetLastError());
+    DMK_HIP(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------------ lists
@@ -772,7 +862,8 @@ template <int D, bool FILL>
 __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t *lstart_dev, int nlevels,
                              const uint64_t *bkey, const int32_t *blevel, const int32_t *parent,
                              const int32_t *col, const uint8_t *bflags, const int32_t *pcount,
-                             int32_t *count, const int32_t *off, int32_t *src, int32_t *pre, int64_t *pairs)
+                             const int32_t *tcount, int32_t *count, const int32_t *off, int32_t *src, int32_t *pre,
+                             int64_t *pairs)
 {
     constexpr int NCOL = Geo<D>::NCOL, NR = Geo<D>::NRING;
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -823,7 +914,7 @@ __global__ void k_near_lists(const int32_t *leaves, int64_t nleaf, const int32_t
     if (FILL) pre[base + i + cnt] = (int32_t)pr;  // total after the last entry (one extra slot per leaf)
     if (!FILL) {
         count[i] = cnt;
-        pairs[i] = pr * pcount[B];
+        pairs[i] = pr * tcount[B];
     }
 }
 
@@ -849,7 +940,8 @@ static void build_lists_t(Plan *P, hipStream_t s)
     const int64_t nbox = P->nbox;
     const int L = P->nlevels;
     uint8_t *f_fout = S.get<uint8_t>(nbox), *f_fin = S.get<uint8_t>(nbox), *f_leaf = S.get<uint8_t>(nbox);
-    hipLaunchKernelGGL(k_list_flags, dim3(nblk(nbox)), dim3(TPB), 0, s, nbox, P->bflags, P->pcount, f_fout, f_fin,
+    // boxes that need local values and leaves to evaluate: those holding targets
+    hipLaunchKernelGGL(k_list_flags, dim3(nblk(nbox)), dim3(TPB), 0, s, nbox, P->bflags, P->tcount, f_fout, f_fin,
                        f_leaf);
     P->l_fout = talloc<int32_t>(P, nbox);
     P->l_fin = talloc<int32_t>(P, nbox);
@@ -872,7 +964,7 @@ static void build_lists_t(Plan *P, hipStream_t s)
     // levels >= 1
     {
         uint8_t *f_root = S.get<uint8_t>(P->nprob);
-        hipLaunchKernelGGL(k_nonempty, dim3(nblk(P->nprob)), dim3(TPB), 0, s, P->pcount, (int64_t)P->nprob, f_root);
+        hipLaunchKernelGGL(k_nonempty, dim3(nblk(P->nprob)), dim3(TPB), 0, s, P->tcount, (int64_t)P->nprob, f_root);
         ll.anc_off[0] = 0;
         ll.anc_off[1] = select_indices(S, f_root, 0, P->nprob, P->l_anc, s);
         for (int l = 1; l < L; ++l) {
@@ -960,17 +1052,17 @@ static void build_lists_t(Plan *P, hipStream_t s)
             int32_t *key = S.get<int32_t>(nleaf), *ident = S.get<int32_t>(nleaf);
             int32_t *skey = S.get<int32_t>(nleaf), *sleaf = S.get<int32_t>(nleaf);
             hipLaunchKernelGGL(k_leaf_keys, dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, P->anchor,
-                               P->local_slot, P->pcount, key, ident, cnt);
+                               P->local_slot, P->tcount, key, ident, cnt);
             int kbits = 1;  // keys are anchor slots in [0, nanc)
             while ((int64_t(1) << kbits) < nanc) ++kbits;
             prim::sort_pairs(S, (const uint32_t *)key, (uint32_t *)skey, (const int32_t *)ident, sleaf, nleaf, kbits,
                              s);
             int32_t *lc = S.get<int32_t>(nleaf + 1), *pos = S.get<int32_t>(nleaf + 1);
-            hipLaunchKernelGGL(k_leaf_counts, dim3(nblk(nleaf)), dim3(TPB), 0, s, sleaf, nleaf, P->pcount, lc);
+            hipLaunchKernelGGL(k_leaf_counts, dim3(nblk(nleaf)), dim3(TPB), 0, s, sleaf, nleaf, P->tcount, lc);
             DMK_HIP(hipMemsetAsync(lc + nleaf, 0, sizeof(int32_t), s));
             prim::exclusive_scan(S, lc, pos, nleaf + 1, s);
-            hipLaunchKernelGGL(k_fill_targets, dim3((unsigned)nleaf), dim3(TPB), 0, s, sleaf, nleaf, P->pstart,
-                               P->pcount, pos, P->anc_tgt);
+            hipLaunchKernelGGL(k_fill_targets, dim3((unsigned)nleaf), dim3(TPB), 0, s, sleaf, nleaf, P->tstart,
+                               P->tcount, pos, P->anc_tgt);
         }
         prim::exclusive_scan(S, cnt, P->anc_tbeg, nanc + 1, s);
     }
@@ -989,7 +1081,8 @@ static void build_lists_t(Plan *P, hipStream_t s)
         int32_t *cnt = S.get<int32_t>(nleaf);
         int64_t *pairs = S.get<int64_t>(nleaf);
         hipLaunchKernelGGL((k_near_lists<D, false>), dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
-                           P->blevel, P->parent, P->colleague, P->bflags, P->pcount, cnt, (const int32_t *)nullptr,
+                           P->blevel, P->parent, P->colleague, P->bflags, P->scount, P->tcount, cnt,
+                           (const int32_t *)nullptr,
                            (int32_t *)nullptr, (int32_t *)nullptr, pairs);
         // exclusive sum over nleaf+1 entries needs a trailing zero in the input
         int32_t *cnt1 = S.get<int32_t>(nleaf + 1);
@@ -1016,7 +1109,7 @@ static void build_lists_t(Plan *P, hipStream_t s)
         P->nl_src = talloc<int32_t>(P, total);
         P->nl_pre = talloc<int32_t>(P, total + nleaf);
         hipLaunchKernelGGL((k_near_lists<D, true>), dim3(nblk(nleaf)), dim3(TPB), 0, s, P->l_leaf, nleaf, lsd, L, P->bkey,
-                           P->blevel, P->parent, P->colleague, P->bflags, P->pcount, (int32_t *)nullptr,
+                           P->blevel, P->parent, P->colleague, P->bflags, P->scount, P->tcount, (int32_t *)nullptr,
                            (const int32_t *)P->nl_off, P->nl_src, P->nl_pre, (int64_t *)nullptr);
     } else {
         P->nl_src = talloc<int32_t>(P, 1);

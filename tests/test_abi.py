@@ -22,7 +22,7 @@ def declared_symbols():
 
 def test_exports_every_declared_symbol():
     names = declared_symbols()
-    assert len(names) == 23
+    assert len(names) == 24
     assert sorted(names) == sorted(dmk.SYMBOLS)
     L = C.CDLL(dmk.LIBPATH)
     for n in names:
@@ -43,6 +43,9 @@ def test_argument_errors_without_device():
     assert L.dmk_plan(3, 0, 1e-6, 10, None, None, None, C.byref(h)) == -1  # NULL pts
     assert b"NULL" in L.dmk_last_error()
     assert L.dmk_eval(None, None, None, None) == -1
+    assert L.dmk_plan_targets(2, 0, 1e-6, 10, None, 10, None, None, None, C.byref(h)) == -2  # 2-D
+    assert L.dmk_plan_targets(3, 0, 1e-6, 10, None, 10, None, None, None, C.byref(h)) == -1  # NULL points
+    assert L.dmk_plan_targets(3, 0, 1e-6, -1, None, 10, None, None, None, C.byref(h)) == -1  # nsrc < 0
     assert L.dmk_eval_noalloc(None, None, None, None) == -1
     assert L.dmk_tune(3, 0, 1e-6, 1, None, None, None, None, None, 0, 1, None, None, None, None) == -1
     off = np.array([0, 5, 3], dtype=np.int64)

@@ -32,9 +32,9 @@ PEAK = {"hbm": (8000.0, "GB/s"), "alu64": (78.6, "TFLOP/s"), "alu32": (157.3, "T
 # bound of each stage: memory streams vs arithmetic on the vector ALUs
 STAGE_BOUND = {"gather": "hbm", "finalize": "hbm", "pwshift": "hbm", "upward": "alu", "root": "alu",
                "proxy2pw": "alu", "local": "alu", "pw2grid": "alu", "leaf": "alu", "residual": "alu"}
-STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward", "root": "k_root_stage",
-                "proxy2pw": "k_proxy2pw", "local": "k_local_pw", "pwshift": "k_pwshift",
-                "pw2grid": "k_local_pw", "leaf": "k_leaf", "residual": "k_residual",
+STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward_q", "root": "k_root_stage",
+                "proxy2pw": "k_proxy2pw", "local": "k_local_pw_q", "pwshift": "k_pwshift",
+                "pw2grid": "k_local_pw_q", "leaf": "k_leaf", "residual": "k_residual",
                 "finalize": "k_finalize"}
 STAGE_KERNEL2 = {"gather": "k_gather_q2", "upward": "k_upward2", "root": "k_root2", "proxy2pw": "k_proxy2pw2",
                  "local": "k_local_pw2", "pwshift": "k_pwshift2", "pw2grid": "k_local_pw2", "leaf": "k_leaf2",
@@ -56,7 +56,7 @@ WORKLOADS = {
 METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
 METRIC_VOL = "points/s, 3-D volume potential DMK (box code) at tol 1e-3, 1 GPU"
 STAGE_KERNEL_VOL = {"upward": "k_vol_upward", "root": "k_root_stage", "proxy2pw": "k_proxy2pw",
-                    "pwshift": "k_pwshift", "pw2grid": "k_local_pw", "leaf": "k_vol_leaf", "residual": "k_vol_near",
+                    "pwshift": "k_pwshift", "pw2grid": "k_local_pw_q", "leaf": "k_vol_leaf", "residual": "k_vol_near",
                     "finalize": "k_vol_finalize"}
 # volume workload: density, refinement and tree limits
 VOL_SEED, VOL_RHO_SCALE, VOL_MAX_LEVEL = 5, 3e-5, 16
@@ -72,6 +72,11 @@ TRAFFIC = {
     ("cfg3_clustered_10m", "mixed", "k_local_mfma"): (1.0730e+09, "cb8f9cdc80f5b5c5"),
     ("cfg3_clustered_10m", "mixed", "k_upward"): (3.2140e+08, "cb8f9cdc80f5b5c5"),
 }
+
+
+def per_level(kname, args):
+    """the kernel name under --level-launches (the per-level launches drop the _q suffix)"""
+    return kname[:-2] if (args.level_launches and kname.endswith("_q")) else kname
 
 
 def eval_src_digest():
@@ -161,8 +166,9 @@ def run_volume(args):
     prec = dmk.DMK_FP64 if args.precision == "fp64" else dmk.DMK_MIXED
     log(f"[bench] volume plan ({args.precision})")
     t0 = time.perf_counter()
+    lvl = dmk.DMK_FLAG_LEVEL_LAUNCHES if args.level_launches else 0
     plan = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
-                       features=feat, precision=prec)
+                       features=feat, precision=prec, flags=lvl)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     n = plan.n
@@ -203,7 +209,7 @@ def run_volume(args):
     # every stage, the near field included, computes in FP32 in a mixed plan
     peak, unit = PEAK["hbm"] if hbm else (PEAK["alu64"] if prec == dmk.DMK_FP64 else PEAK["alu32"])
     roof = {"bound": STAGE_BOUND[dom], "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
-            "traffic": None, "kernel": STAGE_KERNEL_VOL.get(dom, dom), "stage": dom, "avg_launch_ms": avg_ms,
+            "traffic": None, "kernel": per_level(STAGE_KERNEL_VOL.get(dom, dom), args), "stage": dom, "avg_launch_ms": avg_ms,
             "launches_per_step": launches[dom] / nst}
     stages = {}
     for k in stage_ms:
@@ -225,7 +231,7 @@ def run_volume(args):
     fp64 = None
     if not args.no_compare and prec != dmk.DMK_FP64:
         p64 = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
-                          features=feat, precision=dmk.DMK_FP64)
+                          features=feat, precision=dmk.DMK_FP64, flags=lvl)
         out64 = torch.empty_like(rho)
         for _ in range(args.warmup):
             p64.eval(rho, out64)
@@ -253,6 +259,7 @@ def run_volume(args):
         "vs_baseline": None, "dtype": "f64" if prec == dmk.DMK_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": WORKLOADS["cfg5_volume_8gauss"], "name": "cfg5_volume_8gauss", "n_points": n,
                    "precision": args.precision, "fp64": fp64,
+                   "schedule": "per-level launches" if args.level_launches else "queue-fed over all levels",
                    "leaves": plan.nleaf, "levels": np.bincount(lev).tolist(), "q": 8, "p": 18, "nf": 12, "tol": 1e-3,
                    "t_plan_s": round(t_plan, 3), "sampled_rel_l2_vs_closed_form": err, "stage_ms_per_step": stages},
         "roofline": roof,
@@ -276,6 +283,9 @@ def main():
                     help="skip the plain FP64 (eager) comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sample-targets", type=int, default=200)
+    ap.add_argument("--level-launches", action="store_true",
+                    help="launch the upward and local stages one tree level at a time instead of the "
+                         "queue-fed kernels over all levels (DMK_FLAG_LEVEL_LAUNCHES)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run an elementwise copy of 1 GiB first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -339,8 +349,9 @@ def main():
 
     log(f"[bench] plan ({args.precision}{', batched' if batched else ''})")
     t0 = time.perf_counter()
+    lvl = dmk.DMK_FLAG_LEVEL_LAUNCHES if args.level_launches else 0
     plan = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=prec, offsets=offsets, kernel=kern, lam=lam,
-                    flags=dmk.DMK_FLAG_BATCHED if batched else 0)
+                    flags=(dmk.DMK_FLAG_BATCHED if batched else 0) | lvl)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
@@ -370,9 +381,10 @@ def main():
         peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
     kname = STAGE_KERNEL[dom] if offsets is None else STAGE_KERNEL2[dom]
     if offsets is None and dom == "pw2grid" and prec == dmk.DMK_MIXED:
-        kname = "k_local_mfma"  # the FP32 path's local stage runs on the matrix cores
+        kname = "k_local_mfma_q"  # the FP32 path's local stage runs on the matrix cores
+    kname = per_level(kname, args)
     bound = STAGE_BOUND[dom]
-    if kname.endswith("_mfma"):
+    if "_mfma" in kname:
         bound = "mfma"  # FP32 matrix-core products; dense FP32 MFMA peak is the same 157.3 TFLOP/s
     tr = TRAFFIC.get((args.workload, args.precision, kname))
     traffic = tr[0] if (tr is not None and tr[1] == eval_src_digest()) else None
@@ -389,13 +401,15 @@ def main():
             ent["gbps"] = round(byts[k] / (ms * 1e-3) / 1e9, 1)
         stages[k] = ent
     u_main = out.cpu().numpy()
+    queue_timeouts = plan.info()["queue_timeouts"]
     plan.close()
     del plan
 
     plain = None
     if not args.no_compare:
         log("[bench] plain FP64 comparison (eager launches)")
-        p64 = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=dmk.DMK_FP64, offsets=offsets, kernel=kern, lam=lam)
+        p64 = dmk.Plan(tp_, tol=tol, leaf_max=ns, precision=dmk.DMK_FP64, offsets=offsets, kernel=kern, lam=lam,
+                       flags=lvl)
         ms64, out64 = timed(p64, args.steps, args.warmup)
         u64 = out64.cpu().numpy()
         p64.close()
@@ -438,13 +452,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n_points": n,
                    "tol": tol, "leaf_max": ns, "precision": args.precision, "batched": batched,
+                   "schedule": "per-level launches" if args.level_launches else "queue-fed over all levels",
                    "kernel": ("1/(4 pi r)" if offsets is None else
                               ("-log(r)/(2 pi)" if kern == dmk.DMK_LAPLACE else "K_0(10 r)")),
                    "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"],
                    "p": info["p"], "nf": info["nf"], "t_plan_s": round(t_plan, 3),
                    "end_to_end_points_per_s": n / (t_plan + ms_step * 1e-3),
                    "sampled_rel_l2_vs_direct": err, "stage_ms_per_step": stages,
-                   "plain_fp64": plain,
+                   "plain_fp64": plain, "queue_timeouts": queue_timeouts,
                    "speedup_vs_plain_fp64": (value / plain["points_per_s"]) if plain else None},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -104,6 +104,16 @@ typedef struct {
  * DMK_ERR_STATE on it.  Ignored by dmk_vol_plan. */
 #define DMK_FLAG_NO_WORKSPACE 4ull
 
+/* The upward pass and the local values are launched one tree level at a
+ * time, one workgroup per box, instead of as one queue-fed launch each over
+ * all levels (the default: a persistent grid takes the boxes from a device
+ * work queue in dependency order, finest level first for the upward pass and
+ * coarsest first for the local values, and a box waits on flags until the
+ * boxes it reads are done).  Each box is computed by the same code either
+ * way, so the results are bit-identical.  3-D point and volume plans; 2-D
+ * plans always launch per level. */
+#define DMK_FLAG_LEVEL_LAUNCHES 8ull
+
 /* Size of the static device scratch of dmk_eval_noalloc, per device. */
 #define DMK_NOALLOC_MAX_BYTES (128ll << 20)
 
@@ -132,6 +142,12 @@ typedef struct {
     int32_t nprob;        /* independent problems in the plan                */
     int64_t nsrc, ntgt;   /* sources and targets (both n unless the plan has
                              separate target sets; then n = nsrc + ntgt)    */
+    int32_t queue_timeouts; /* waits of the queue-fed kernels that ran out of
+                             their poll bound, over all evals of the plan so
+                             far (read from the device: synchronise the eval
+                             streams first).  0 in every correct run; any
+                             other value means results since then are wrong. */
+    int32_t reserved1;
 } dmk_plan_stats;
 
 /*
@@ -524,8 +540,9 @@ typedef void (*dmk_density_fn)(int64_t n, const double *xyz, double *out, void *
  *             side exceeds h > 0; nfeat may be 0 (feat NULL).
  *  opts       precision: DMK_FP64, or DMK_MIXED (the far-field transforms
  *             and the near-field factor products in FP32, the asymptotic
- *             part and the final sums in FP64); leaf_max, max_depth, lambda
- *             ignored; NULL for defaults.
+ *             part and the final sums in FP64); flags: DMK_FLAG_LEVEL_LAUNCHES
+ *             only (others ignored); leaf_max, max_depth, lambda, p, n_f,
+ *             pswf_c ignored; NULL for defaults.
  *  stream     for the device work; returns after it completes.
  * The plan holds at most 2^31 - 1 nodes (nleaf q^3).  Free with
  * dmk_plan_destroy.  A volume plan is evaluated with dmk_vol_eval only.

@@ -18,6 +18,7 @@ DMK_FP64, DMK_MIXED = 0, 1
 DMK_LAPLACE, DMK_YUKAWA, DMK_POWER2 = 0, 1, 2
 DMK_FLAG_BATCHED = 2
 DMK_FLAG_NO_WORKSPACE = 4
+DMK_FLAG_LEVEL_LAUNCHES = 8
 NOALLOC_MAX_BYTES = 128 << 20
 
 # exported symbols, in the order of include/dmk.h
@@ -46,7 +47,8 @@ class Stats(C.Structure):
                 ("leaf_max", C.c_int32), ("precision", C.c_int32), ("nleaf", C.c_int64),
                 ("nfout", C.c_int64), ("nfin", C.c_int64), ("npairs", C.c_int64),
                 ("device_bytes", C.c_int64), ("center", C.c_double * 3), ("side", C.c_double),
-                ("dim", C.c_int32), ("nprob", C.c_int32), ("nsrc", C.c_int64), ("ntgt", C.c_int64)]
+                ("dim", C.c_int32), ("nprob", C.c_int32), ("nsrc", C.c_int64), ("ntgt", C.c_int64),
+                ("queue_timeouts", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class DmkError(RuntimeError):
@@ -314,13 +316,13 @@ class VolPlan:
     [npoints]) to potentials at the same nodes."""
 
     def __init__(self, density, tol=1e-3, q=8, rho_scale=1.0, min_level=1, max_level=12, features=None,
-                 precision=DMK_FP64, stream=None):
+                 precision=DMK_FP64, flags=0, stream=None):
         def cb(n, xyz, out, ctx):
             x = np.ctypeslib.as_array(xyz, shape=(n * 3,)).reshape(n, 3)
             o = np.ctypeslib.as_array(out, shape=(n,))
             o[:] = density(x)
         self._cb = DENSITY_FN(cb)
-        o = Opts(0, 0, precision, 0, 0, 0.0)
+        o = Opts(0, 0, precision, 0, int(flags), 0.0)
         h = C.c_void_p()
         feat = np.ascontiguousarray(np.zeros((0, 4)) if features is None else features, dtype=np.float64)
         _check(lib().dmk_vol_plan(float(tol), int(q), float(rho_scale), int(min_level), int(max_level), len(feat),
@@ -342,6 +344,9 @@ class VolPlan:
             self.close()
         except Exception:
             pass
+
+    def info(self):
+        return Plan.info(self)
 
     def leaves(self):
         lev = np.zeros(self.nleaf, np.int32)

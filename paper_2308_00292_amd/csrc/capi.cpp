@@ -615,6 +615,7 @@ dmk_status dmk_plan_info(dmk_plan_t plan, dmk_plan_stats *st)
         st->nprob = P->nprob;
         st->nsrc = P->nsrc;
         st->ntgt = P->ntgt;
+        if (P->q_fail) DMK_HIP(hipMemcpy(&st->queue_timeouts, P->q_fail, sizeof(int32_t), hipMemcpyDeviceToHost));
     });
 }
 

@@ -173,6 +173,8 @@ struct Plan {
     int32_t *anc_tbeg = nullptr;   // [nanc+1] offsets into anc_tgt
     int32_t *anc_tgt = nullptr;    // [nleaf points] targets grouped by the anchor of their leaf
     int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
+    int32_t *l_fout_up = nullptr;  // l_fout with the levels in reverse (finest first): the upward queue
+    int32_t *q_fail = nullptr;     // waits of the queue-fed kernels that ran out of polls (sticky)
     int64_t nfout = 0, nfin = 0, nanc = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
     // sibling groups for the diagonal translation: per parent of F_in boxes,
     // the Psi slots of its 2^dim children and the Phi slots of the 4^dim
@@ -203,6 +205,7 @@ struct Plan {
     void *phi = nullptr;     // [max_fout_level][2][nh*nn*nn] planar
     void *psi = nullptr;     // [max_fin_level][2][nh*nn*nn] planar
     void *w0vals = nullptr;  // [nprob][p^d] W_0 values on the root grids
+    int32_t *qctl = nullptr; // queue heads [4], then per-slot flags: upward [nfout], local [nanc]
     int64_t ws_bytes = 0;         // the workspace's size, each buffer rounded up to 256 bytes
     bool has_workspace = false;   // false for DMK_FLAG_NO_WORKSPACE plans
 

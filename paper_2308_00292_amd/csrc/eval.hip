@@ -34,6 +34,7 @@
 #include <cmath>
 
 #include "dmk_internal.h"
+#include "queue.h"
 #include "tiles.h"
 
 namespace dmk {
@@ -86,19 +87,19 @@ template <int P> constexpr int up_chunk()
     return (2 * P * P * P) / (3 * P) < 128 ? (2 * P * P * P) / (3 * P) : 128;
 }
 
-template <typename T, int P>
-__global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
+// COH: the box's children were computed by the same launch (queue-fed)
+template <typename T, int P, bool COH>
+__device__ __forceinline__ void upward_box(const Dev<T> &D, const int32_t Pb)
 {
     constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
     constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, CH = up_chunk<P>();
     constexpr int MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;  // tile grid of the p x p^2 accumulator
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *Am = sm;              // 2 p^2 child->parent matrices
     T *xc = Am + 2 * P2;     // nodes
     T *bw = xc + P;          // barycentric weights
     T *w0 = bw + P;          // work area of 2 p^3
-    const int32_t Pb = list[blockIdx.x];
     for (int t = threadIdx.x; t < 2 * P2; t += TPB) Am[t] = D.c2p[t];
     for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
     T acc[RM][RN];
@@ -125,7 +126,7 @@ __global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
             T *t1 = w0, *t2 = w0 + P3;
             const T *Ax = Am + ((k >> 2) & 1) * P2, *Ay = Am + ((k >> 1) & 1) * P2, *Az = Am + (k & 1) * P2;
             __syncthreads();
-            for (int t = threadIdx.x; t < P3; t += TPB) t2[t] = src[t];
+            copy_to_lds<COH, TPB>(t2, src, P3);
             __syncthreads();
             // z: t1[(i0 i1)][a2] = sum_i2 t2[(i0 i1)][i2] Az[a2][i2]
             gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Az, 0, 1, P, t1, 0, P, 1);
@@ -209,7 +210,30 @@ __global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
             }
         }
     }
-    store_tiles<T, P>(acc, D.proxy + (int64_t)D.proxy_slot[Pb] * P3);
+    store_tiles<T, P, COH>(acc, D.proxy + (int64_t)D.proxy_slot[Pb] * P3);
+}
+
+// one level's F_out boxes, one workgroup per box
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_upward(Dev<T> D, const int32_t *list)
+{
+    upward_box<T, P, false>(D, list[blockIdx.x]);
+}
+
+// the F_out boxes of every level, finest first, from the work queue: a box
+// waits for its F_out children
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_upward_q(Dev<T> D, WorkQ q)
+{
+    queue_loop(
+        q,
+        [&](int32_t Pb) {
+            if (threadIdx.x < 8) {
+                const int32_t C = D.child0[Pb] + threadIdx.x;
+                if (D.pcount[C] > 0 && (D.bflags[C] & 2)) wait_done(q, C);
+            }
+        },
+        [&](int32_t Pb) { upward_box<T, P, true>(D, Pb); });
 }
 
 // -------------------------------------------- proxies -> plane waves
@@ -219,7 +243,7 @@ template <typename T, int P, int NF, int G>
 __global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list)
 {
     constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *rho = sm;                  // p^3
     T *Er = rho + P3;             // [nn][p]
@@ -450,12 +474,13 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
 
 // ------------------------------------------------ local values (anchors)
 // v_B = interp(anchor(parent(B)) -> B's grid) + Re sum_m exp(+i pi m.x/3) Psi_B[m]
-template <typename T, int P, int NF, int G1>
-__global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list, int level)
+// COH: the anchor above the box was computed by the same launch (queue-fed)
+template <typename T, int P, int NF, int G1, bool COH>
+__device__ __forceinline__ void local_box(const Dev<T> &D, const int32_t B, const int level)
 {
     constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
     constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, NN = 2 * NF + 1, NH = NF + 1;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *Er = sm;                // [nn][p]  Re E
     T *Ein = Er + NN * P;      // [nn][p] -Im E  (imaginary part of conj(E))
@@ -464,7 +489,6 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
     T *xc = Gc + 2 * NN * P;
     T *bw = xc + P;
     T *w0 = bw + P;            // work area
-    const int32_t B = list[blockIdx.x];
     for (int t = threadIdx.x; t < NN * P; t += TPB) {
         T er = D.epw[2 * t], ei = D.epw[2 * t + 1];
         Er[t] = er;
@@ -516,7 +540,7 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
             for (int a = 0; a < P; ++a) dst[a] = row[a];
         }
         const T *src = D.local + (int64_t)D.local_slot[A] * P3;
-        for (int t = threadIdx.x; t < P3; t += TPB) t2[t] = src[t];
+        copy_to_lds<COH, TPB>(t2, src, P3);
         __syncthreads();
         // z: t1[(a0 a1)][i2] = sum_a2 v[(a0 a1)][a2] Mz[i2][a2]
         gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Mz, 0, 1, P, t1, 0, P, 1);
@@ -554,7 +578,28 @@ __global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list,
             gemm_regs<T, RM, RN>(P, P2, g, Gc + NN * P + g0 * P, 1, P, Dc + g * P2, P2, 1, acc);
         }
     }
-    store_tiles<T, P>(acc, D.local + (int64_t)D.local_slot[B] * P3);
+    store_tiles<T, P, COH>(acc, D.local + (int64_t)D.local_slot[B] * P3);
+}
+
+// one level's anchors, one workgroup per box
+template <typename T, int P, int NF, int G1>
+__global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list, int level)
+{
+    local_box<T, P, NF, G1, false>(D, list[blockIdx.x], level);
+}
+
+// the anchors of every level, coarsest first, from the work queue: a box
+// below the root waits for the anchor of its parent
+// one box per workgroup (grid = anchors), taken from the queue
+template <typename T, int P, int NF, int G1>
+__global__ void __launch_bounds__(TPB) k_local_pw_q(Dev<T> D, WorkQ q)
+{
+    queue_item(
+        q,
+        [&](int32_t B) {
+            if (threadIdx.x == 0 && D.blevel[B] > 0) wait_done(q, D.anchor[D.parent[B]]);
+        },
+        [&](int32_t B) { local_box<T, P, NF, G1, true>(D, B, D.blevel[B]); });
 }
 
 // ------------------------------------------ local values on matrix cores
@@ -803,21 +848,21 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
     }
 }
 
-template <int P, int NF>
-__global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const int32_t *list, int level)
+// COH: the anchor above the box was computed by the same launch (queue-fed)
+template <int P, int NF, bool COH>
+__device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_t B, const int level)
 {
     using L = LocalMfma<P, NF>;
     constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, NSW = L::NSW;
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int G = L::G, KP = L::KP, NSL = L::NSL, NWV = L::NWV, NT = L::NT;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     float *sm = reinterpret_cast<float *>(smraw);
     float *Br1 = sm, *Bi1 = Br1 + NN * P;  // conj(E): B(k = m, a = j) = Er[m][j] - i Ei[m][j]
     float *B3 = Bi1 + NN * P;              // [KP][P]: c_m3 Er[m3][j3], then c_m3 Ei[m3][j3]
     float *Bx = B3 + KP * P, *By = Bx + P2, *Bz = By + P2;  // B(k = a, col = i) = M_d[i][a]
     float *xc = Bz + P2, *bw = xc + P;
     float *work = bw + P;
-    const int32_t B = list[blockIdx.x];
     // the parent anchor's values, loaded first so that their latency overlaps
     // the table set-up and the Lagrange rows
     constexpr int NVP = (P3 + NT - 1) / NT;
@@ -828,7 +873,7 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
 #pragma unroll
         for (int i = 0; i < NVP; ++i) {
             const int t = threadIdx.x + i * NT;
-            vpre[i] = t < P3 ? src[t] : 0.f;
+            vpre[i] = t < P3 ? ld_c<COH>(src + t) : 0.f;
         }
     }
     for (int t = threadIdx.x; t < NN * P; t += NT) {
@@ -974,7 +1019,16 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
             }
         }
     }
+    // the box's values, x-major p^3 block: straight from the fragments, or
+    // (COH: read by later boxes of the same launch) through LDS and out in
+    // whole lines with cache-bypassing stores; atomic stores straight from
+    // the fragments keep their order and cost this kernel registers
     float *dst = D.local + (int64_t)D.local_slot[B] * P3;
+    float *out = dst;
+    if constexpr (COH) {
+        out = work;
+        __syncthreads();  // the last group's B2 reads are done
+    }
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
         const int sl = w + NWV * i;
@@ -984,13 +1038,37 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
-                if (x < P2 && a < P) dst[x * P + a] = acc[i][t][q];
+                if (x < P2 && a < P) out[x * P + a] = acc[i][t][q];
             }
         const int xa = 16 * sl + r16;
 #pragma unroll
         for (int j = 0; j < NREM; ++j)
-            if (kq == 0 && xa < P2) dst[xa * P + 16 * NATM + j] = accr[i][j];
+            if (kq == 0 && xa < P2) out[xa * P + 16 * NATM + j] = accr[i][j];
     }
+    if constexpr (COH) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < P3; t += NT) st_c<true>(dst + t, work[t]);
+    }
+}
+
+template <int P, int NF>
+__global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const int32_t *list, int level)
+{
+    local_box_mfma<P, NF, false>(D, list[blockIdx.x], level);
+}
+
+// one box per workgroup (grid = anchors), taken from the queue: looping over
+// boxes in one workgroup held the body's loop-invariant index arithmetic in
+// registers across items and pushed this kernel into scratch
+template <int P, int NF>
+__global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma_q(Dev<float> D, WorkQ q)
+{
+    queue_item(
+        q,
+        [&](int32_t B) {
+            if (threadIdx.x == 0 && D.blevel[B] > 0) wait_done(q, D.anchor[D.parent[B]]);
+        },
+        [&](int32_t B) { local_box_mfma<P, NF, true>(D, B, D.blevel[B]); });
 }
 
 // ------------------------------------ outgoing plane waves on matrix cores
@@ -1069,7 +1147,7 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
 {
     using L = P2pwMfma<P, NF>;
     constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, W1 = L::W1, G = L::G;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     float *sm = reinterpret_cast<float *>(smraw);
     float *B1 = sm;                    // [j3][W1]: Re E[m3][j3] | Im E[m3][j3]
     float *BrT = B1 + P * W1;          // [j][m]: Re E[m][j]
@@ -1180,7 +1258,7 @@ template <typename T, int P>
 __global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, const int32_t *tbeg, const int32_t *tgt)
 {
     constexpr int P2 = P * P, P3 = P2 * P;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *v = sm, *xc = v + P3, *bw = xc + P;
     const int a = blockIdx.x;
@@ -1258,7 +1336,7 @@ __global__ void __launch_bounds__(TPB) k_residual(Dev<T> D, const int32_t *leave
     double *part = stg.part;
     // running source counts of the block's list: L + 1 entries in the
     // dynamic LDS, sized at launch to the plan's longest list
-    extern __shared__ int32_t loff[];
+    extern __shared__ __align__(16) int32_t loff[];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.tstart[B];  // the leaf's targets
     const int nt = D.tcount[B];
@@ -1370,7 +1448,7 @@ __global__ void __launch_bounds__(TPB) k_residual_y3(Dev<T> D, const int32_t *le
     __shared__ int8_t slev[RCAP];
     T *sx = stg.s.x, *sy = stg.s.y, *sz = stg.s.z, *sq = stg.s.q, *sis = stg.s.is;
     double *part = stg.part;
-    extern __shared__ int32_t loff[];
+    extern __shared__ __align__(16) int32_t loff[];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.tstart[B];  // the leaf's targets
     const int nt = D.tcount[B];
@@ -1841,6 +1919,39 @@ static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
         launch_residual_deg<T, 1>(D, Pl, g, b, lds, s);
 }
 
+// workgroups of a kernel that fit on the device at once (the persistent grid
+// of a queue-fed kernel; more would only wait for a slot)
+template <typename K>
+static unsigned resident_blocks(K kernel, int nthreads, size_t lds)
+{
+    int dev = 0, ncu = 0, per = 0;
+    DMK_HIP(hipGetDevice(&dev));
+    DMK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    DMK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nthreads, lds));
+    return (unsigned)std::max(1, per) * (unsigned)std::max(1, ncu);
+}
+
+// the longest wait of a queue-fed kernel, in ticks of the device's
+// constant-rate wall clock: 200 ms, far beyond any real wait (a whole stage
+// takes a few ms), so that a wait that runs out means a fault
+static int64_t queue_wait_ticks()
+{
+    static const int64_t ticks = [] {
+        int dev = 0, khz = 0;
+        DMK_HIP(hipGetDevice(&dev));
+        DMK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        return (int64_t)std::max(khz, 1000) * 200;
+    }();
+    return ticks;
+}
+
+// persistent grids of the queue-fed kernels (set with the LDS limits, before
+// any graph capture)
+template <typename T, int P, int NF>
+struct QGrid {
+    static inline unsigned upward = 0;
+};
+
 // dynamic LDS limits of the stage kernels, once per process
 template <typename T, int P, int NF>
 static void set_lds_attrs()
@@ -1849,15 +1960,38 @@ static void set_lds_attrs()
     static bool attrs = false;
     if (attrs) return;
     allow_lds(k_upward<T, P>, C::lds_up());
+    allow_lds(k_upward_q<T, P>, C::lds_up());
     allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
     allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
+    allow_lds(k_local_pw_q<T, P, NF, C::G1>, C::lds_local());
     const size_t lds_mfma = LocalMfma<P, NF>::lds();
     if constexpr (sizeof(T) == 4) {
         allow_lds(k_local_mfma<P, NF>, lds_mfma);
+        allow_lds(k_local_mfma_q<P, NF>, lds_mfma);
         allow_lds(k_proxy2pw_mfma<P, NF>, P2pwMfma<P, NF>::lds());
     }
     allow_lds(k_leaf<T, P>, C::lds_leaf());
+    (void)queue_wait_ticks();
+    QGrid<T, P, NF>::upward = resident_blocks(k_upward_q<T, P>, TPB, C::lds_up());
     attrs = true;
+}
+
+// the queues' control words: [0, 4 + nfout) the upward pass's head and flags,
+// [4 + nfout, 8 + nfout + nanc) the local values' (cleared by the stage's
+// reset kernel before each of its launches)
+static WorkQ upward_queue(Plan *Pl)
+{
+    return WorkQ{Pl->qctl, Pl->qctl + 4, Pl->l_fout_up, Pl->proxy_slot, Pl->q_fail, (int32_t)Pl->nfout,
+                 queue_wait_ticks()};
+}
+static WorkQ local_queue(Plan *Pl)
+{
+    int32_t *base = Pl->qctl + 4 + Pl->nfout;
+    return WorkQ{base, base + 4, Pl->l_anc, Pl->local_slot, Pl->q_fail, (int32_t)Pl->nanc, queue_wait_ticks()};
+}
+static void reset_queue(int32_t *p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)std::min<int64_t>(nblk(n), 1024)), dim3(256), 0, s, p, n);
 }
 
 // Root window W_0, outgoing and incoming plane waves and the local values of
@@ -1902,7 +2036,22 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
         hipLaunchKernelGGL((k_pwshift<T, MPT>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
                            Pl->oct_level, Pl->noct, nchunk);
     }
-    // local values of the anchors, coarse to fine
+    // local values of the anchors, coarse to fine: one queue-fed launch over
+    // all levels, or one launch per level
+    if (Pl->nanc && !(Pl->flags & DMK_FLAG_LEVEL_LAUNCHES)) {
+        StageScope t(Pl, s, DMK_STAGE_PW2GRID);
+        const WorkQ q = local_queue(Pl);
+        reset_queue(q.head, 4 + Pl->nanc, s);
+        if constexpr (sizeof(T) == 4) {
+            const size_t lds = LocalMfma<P, NF>::lds();
+            hipLaunchKernelGGL((k_local_mfma_q<P, NF>), dim3((unsigned)Pl->nanc),
+                               dim3(LOCAL_NT), lds, s, D, q);
+        } else {
+            hipLaunchKernelGGL((k_local_pw_q<T, P, NF, C::G1>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_local(), s,
+                               D, q);
+        }
+        return;
+    }
     for (int l = 0; l < L; ++l) {
         int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];
         if (!nan) continue;
@@ -1939,8 +2088,17 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
         launch_residual<T>(D, Pl, side);
         DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
-    // Step 2: upward pass, finest level first
-    for (int l = L - 1; l >= 0; --l) {
+    // Step 2: upward pass, finest level first: one queue-fed launch over all
+    // levels, or one launch per level
+    if (Pl->nfout && !(Pl->flags & DMK_FLAG_LEVEL_LAUNCHES)) {
+        StageScope t(Pl, s, DMK_STAGE_UPWARD);
+        const WorkQ q = upward_queue(Pl);
+        reset_queue(q.head, 4 + Pl->nfout, s);
+        hipLaunchKernelGGL((k_upward_q<T, P>), dim3((unsigned)std::min<int64_t>(Pl->nfout, QGrid<T, P, NF>::upward)),
+                           dim3(TPB),
+                           C::lds_up(), s, D, q);
+    }
+    for (int l = L - 1; l >= 0 && (Pl->flags & DMK_FLAG_LEVEL_LAUNCHES); --l) {
         int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
         if (!m) continue;
         StageScope t(Pl, s, DMK_STAGE_UPWARD);
@@ -2138,6 +2296,7 @@ void workspace_layout(Plan *P, std::vector<WsItem> &items)
     add(&P->phi, 2 * P->nfout * nm, el);
     add(&P->psi, 2 * P->nfin * nm, el);
     add(&P->w0vals, P->nprob * p3, el);
+    add(&P->qctl, 8 + P->nfout + P->nanc, 4);
 }
 
 void alloc_workspace(Plan *P)

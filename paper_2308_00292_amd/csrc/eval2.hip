@@ -168,7 +168,7 @@ template <typename T, int P>
 __global__ void __launch_bounds__(TPB) k_root2(Dev2<T> D, int npmax)
 {
     constexpr int P2 = P * P;
-    extern __shared__ double rsm[];
+    extern __shared__ __align__(16) double rsm[];
     const int nwn = D.nwn, nwh = D.nwh, nw = D.nw;
     double *rho = rsm;                    // p^2
     double *t1r = rho + P2, *t1i = t1r + P * nwh;         // [j1][m2]

@@ -985,6 +985,17 @@ static void build_lists_t(Plan *P, hipStream_t s)
         P->max_fin_level = std::max(P->max_fin_level, ll.fin_off[l + 1] - ll.fin_off[l]);
         P->max_fout_level = std::max(P->max_fout_level, ll.fout_off[l + 1] - ll.fout_off[l]);
     }
+    // the upward pass's queue: the F_out boxes finest level first
+    P->l_fout_up = talloc<int32_t>(P, std::max<int64_t>(P->nfout, 1));
+    for (int l = L - 1, pos = 0; l >= 0; --l) {
+        const int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
+        if (m)
+            DMK_HIP(hipMemcpyAsync(P->l_fout_up + pos, P->l_fout + ll.fout_off[l], m * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+        pos += (int)m;
+    }
+    P->q_fail = talloc<int32_t>(P, 1);
+    DMK_HIP(hipMemsetAsync(P->q_fail, 0, sizeof(int32_t), s));
     P->proxy_slot = talloc<int32_t>(P, nbox);
     P->local_slot = talloc<int32_t>(P, nbox);
     P->psi_slot = talloc<int32_t>(P, nbox);

@@ -158,8 +158,10 @@ template <> struct Tiles<18> { static constexpr int RM = 3, RN = 9, ZM = 3, ZN =
 template <> struct Tiles<15> { static constexpr int RM = 3, RN = 5, ZM = 3, ZN = 5; };
 template <> struct Tiles<9> { static constexpr int RM = 1, RN = 3, ZM = 3, ZN = 3; };
 
-// store a p x p^2 register accumulator (tile layout of gemm_regs)
-template <typename T, int P, int RM, int RN>
+// store a p x p^2 register accumulator (tile layout of gemm_regs); COH: with
+// relaxed agent-scope atomic stores (read by another workgroup of the same
+// launch)
+template <typename T, int P, bool COH = false, int RM, int RN>
 __device__ inline void store_tiles(const T (&acc)[RM][RN], T *dst)
 {
     constexpr int P2 = P * P, MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;
@@ -171,7 +173,12 @@ __device__ inline void store_tiles(const T (&acc)[RM][RN], T *dst)
 #pragma unroll
         for (int j = 0; j < RN; ++j) {
             int m = mt + i * MT, n = nt + j * NT;
-            if (m < P && n < P2) dst[m * P2 + n] = acc[i][j];
+            if (m < P && n < P2) {
+                if constexpr (COH)
+                    __hip_atomic_store(dst + m * P2 + n, acc[i][j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    dst[m * P2 + n] = acc[i][j];
+            }
         }
 }
 

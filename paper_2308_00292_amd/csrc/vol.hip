@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *li
 {
     constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int RM = Tiles<P>::RM, RN = Tiles<P>::RN, ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *Am = sm;              // [2][p][p] child -> parent
     T *Vm = Am + 2 * P2;     // [2][p][q] leaf density -> parent
@@ -473,7 +473,7 @@ template <typename T, int P, int Q>
 __global__ void __launch_bounds__(TPB) k_vol_leaf(VDev<T> D, const int32_t *leaves)
 {
     constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q;
-    extern __shared__ unsigned char smraw[];
+    extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *v = sm;               // p^3 local values of the anchor
     T *t1 = v + P3;          // [p][p][q]
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NB = VolLds<18, Q>::NB, RS = Q + 1,
                   NT = JB * Q2;
     static_assert(NT == vol_near_threads<Q> && Q2 == 64, "one wavefront per Gaussian, one lane per row");
-    extern __shared__ double vsm[];
+    extern __shared__ __align__(16) double vsm[];
     T *slot = reinterpret_cast<T *>(vsm);  // [NB][q^3] source densities
     T *wb = slot + NB * Q3;                // per wave: [q^2][RS] regrouping buffer
     const int tid = threadIdx.x;
@@ -1042,7 +1042,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         P->precision = o.precision;
         P->leaf_max = q3;
         P->max_depth = 20;
-        P->flags = 0;
+        P->flags = o.flags & DMK_FLAG_LEVEL_LAUNCHES;
         P->n = n;
         build_tables(prm, &P->tab, 3);
         gauss_tables(&P->tab, tol);

@@ -2067,27 +2067,18 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     }
 }
 
-// The stages between the charge gather and the final scatter.  They read and
-// write plan-owned buffers only, so the sequence can be captured into a HIP
-// graph once and replayed.  `side` (if not null) is a second stream on which
-// the residual sums run concurrently with the far-field chain.  In a replay
-// the residual kernel starts together with the translation, a stage that
-// waits on memory, and its blocks (about 10 KB of LDS in FP32, 46 VGPRs)
-// fill the compute-unit room that the translation leaves.
+// The far-field chain between the charge gather and the final scatter
+// (upward pass to leaf evaluation).  It reads and writes plan-owned buffers
+// only, so it can be captured into a HIP graph once and replayed.  The
+// residual sums are not part of it: they depend on the gathered charges only
+// and run beside the chain (run_eval_t).
 template <typename T, int P, int NF>
-static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
+static void enqueue_chain(Plan *Pl, hipStream_t s)
 {
     using C = Cfg<T, P, NF>;
     Dev<T> D = make_dev<T>(Pl);
     const auto &ll = Pl->ll;
     const int L = Pl->nlevels;
-    const int64_t n = Pl->n;
-    if (side && Pl->nleaf) {
-        DMK_HIP(hipEventRecord(Pl->ev_fork, s));
-        DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
-        launch_residual<T>(D, Pl, side);
-        DMK_HIP(hipEventRecord(Pl->ev_join, side));
-    }
     // Step 2: upward pass, finest level first: one queue-fed launch over all
     // levels, or one launch per level
     if (Pl->nfout && !(Pl->flags & DMK_FLAG_LEVEL_LAUNCHES)) {
@@ -2106,21 +2097,13 @@ static void enqueue_core(Plan *Pl, hipStream_t s, hipStream_t side)
     }
     enqueue_far<T, P, NF>(Pl, s);
     if (Pl->nleaf) {
-        {
-            StageScope t(Pl, s, DMK_STAGE_LEAF);
-            if constexpr (sizeof(T) == 4)
-                hipLaunchKernelGGL((k_leaf_mfma<P>), dim3((unsigned)Pl->nanc), dim3(TPB), 0, s, D, Pl->l_anc,
-                                   Pl->anc_tbeg, Pl->anc_tgt);
-            else
-                hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D,
-                                   Pl->l_anc, Pl->anc_tbeg, Pl->anc_tgt);
-        }
-        if (side) {
-            DMK_HIP(hipStreamWaitEvent(s, Pl->ev_join, 0));
-        } else {
-            StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
-            launch_residual<T>(D, Pl, s);
-        }
+        StageScope t(Pl, s, DMK_STAGE_LEAF);
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((k_leaf_mfma<P>), dim3((unsigned)Pl->nanc), dim3(TPB), 0, s, D, Pl->l_anc,
+                               Pl->anc_tbeg, Pl->anc_tgt);
+        else
+            hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D,
+                               Pl->l_anc, Pl->anc_tbeg, Pl->anc_tgt);
     }
 }
 
@@ -2137,12 +2120,22 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
     }
     const bool batched = (Pl->flags & DMK_FLAG_BATCHED) && !Pl->timing;
     if (batched) {
+        // the residual sums on the side stream, beside the replayed chain: a
+        // second hardware queue lets their workgroups fill the room the
+        // chain's memory-bound stages leave (measured: a graph holding both
+        // branches ran them with less overlap)
+        if (Pl->nleaf) {
+            DMK_HIP(hipEventRecord(Pl->ev_fork, s));
+            DMK_HIP(hipStreamWaitEvent(Pl->side_stream, Pl->ev_fork, 0));
+            launch_residual<T>(make_dev<T>(Pl), Pl, Pl->side_stream);
+            DMK_HIP(hipEventRecord(Pl->ev_join, Pl->side_stream));
+        }
         if (!Pl->graph_exec) {
-            // capture once: the core touches plan-owned buffers only
+            // capture once: the chain touches plan-owned buffers only
             hipGraph_t g = nullptr;
             DMK_HIP(hipStreamBeginCapture(Pl->cap_stream, hipStreamCaptureModeThreadLocal));
             try {
-                enqueue_core<T, P, NF>(Pl, Pl->cap_stream, Pl->side_stream);
+                enqueue_chain<T, P, NF>(Pl, Pl->cap_stream);
             } catch (...) {
                 (void)hipStreamEndCapture(Pl->cap_stream, &g);
                 if (g) (void)hipGraphDestroy(g);
@@ -2153,8 +2146,13 @@ static void run_eval_t(Plan *Pl, const double *charges, double *pot, double *far
             DMK_HIP(hipGraphDestroy(g));
         }
         DMK_HIP(hipGraphLaunch(Pl->graph_exec, s));
+        if (Pl->nleaf) DMK_HIP(hipStreamWaitEvent(s, Pl->ev_join, 0));
     } else {
-        enqueue_core<T, P, NF>(Pl, s, nullptr);
+        enqueue_chain<T, P, NF>(Pl, s);
+        if (Pl->nleaf) {
+            StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
+            launch_residual<T>(make_dev<T>(Pl), Pl, s);
+        }
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);

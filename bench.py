@@ -115,22 +115,57 @@ def cpu_baseline_2d(off, pts, q, ns, tol, kern, lam, seed=7):
                       f"{te:.2f} s, trees excluded, FP64, tol {tol:g}"}
 
 
+def morton_runs(pts, m, rng, nrun=8):
+    """indices of nrun runs of about m/nrun consecutive points in Morton order
+    (10 bits per axis), at random places: spatially compact pieces of the set
+    at its own local density, so the oracle's tree over them is as deep
+    there as the full tree (a uniform random subset would be sparser and its
+    tree shallower)"""
+    n = len(pts)
+    lo = pts.min(0)
+    ext = float((pts.max(0) - lo).max()) or 1.0
+    c = np.clip(((pts - lo) / ext * 1024).astype(np.int64), 0, 1023)
+
+    def spread(v):  # 10 bits -> every third bit of 30
+        v = (v | (v << 16)) & 0x030000FF
+        v = (v | (v << 8)) & 0x0300F00F
+        v = (v | (v << 4)) & 0x030C30C3
+        return (v | (v << 2)) & 0x09249249
+
+    order = np.argsort((spread(c[:, 0]) << 2) | (spread(c[:, 1]) << 1) | spread(c[:, 2]), kind="stable")
+    k = max(1, m // nrun)
+    starts = np.sort(rng.choice(max(1, n - k + 1), nrun, replace=False))
+    idx = np.unique(np.concatenate([order[s0:s0 + k] for s0 in starts]))
+    return idx
+
+
 def cpu_baseline(pts, q, ns, tol, seed=7):
-    """The oracle (plain FP64 C, OpenMP over all host threads) on a random
-    subset of the same point set, sized for roughly 10-20 s of CPU work."""
+    """The oracle (plain FP64 C, OpenMP over all host threads) on Morton runs
+    of the same point set (morton_runs), sized for roughly 15 s of eval work
+    on all threads, then on one thread for roughly 8 s."""
     import oracle
     rng = np.random.default_rng(seed)
     n = len(q)
-    m0 = min(n, 50_000)
-    idx = rng.choice(n, m0, replace=False)
+    idx = morton_runs(pts, min(n, 50_000), rng)
     _, _, te = oracle.dmk_run(pts[idx], q[idx], tol, ns)
-    rate = m0 / te
-    m = int(min(n, max(100_000, min(2_000_000, rate * 15.0))))
-    idx = rng.choice(n, m, replace=False)
+    rate = len(idx) / te
+    idx = morton_runs(pts, int(min(n, max(100_000, min(3_000_000, rate * 15.0)))), rng)
+    m = len(idx)
     _, tp, te = oracle.dmk_run(pts[idx], q[idx], tol, ns)
-    return {"value": m / te, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"random subset of {m} of the {n} points (same distribution), eval phase "
-                      f"{te:.2f} s, plan {tp:.2f} s excluded, FP64, tol {tol:g}"}
+    cores = oracle.num_threads()
+    res = {"value": m / te, "unit": "points/s", "cores": cores, "kind": "oracle",
+           "sample": f"8 runs of consecutive points in Morton order at random places ({m} of the {n} points, "
+                     f"the full set's local density), eval phase {te:.2f} s, plan {tp:.2f} s excluded, "
+                     f"FP64, tol {tol:g}"}
+    prev = oracle.set_threads(1)
+    try:
+        idx1 = morton_runs(pts, int(max(20_000, min(m, (m / te) / cores * 8.0))), rng)
+        _, _, te1 = oracle.dmk_run(pts[idx1], q[idx1], tol, ns)
+    finally:
+        oracle.set_threads(prev)
+    res["single_thread"] = {"value": len(idx1) / te1, "cores": 1,
+                            "sample": f"8 Morton runs, {len(idx1)} points, eval phase {te1:.2f} s"}
+    return res
 
 
 def cpu_baseline_vol(sig, cen, amp, feat):

@@ -132,6 +132,8 @@ def lib():
         L.orc_dmk_run.argtypes = [C.c_int64, _f64p, _f64p, C.c_double, C.c_int, C.c_int, _f64p,
                                   _f64p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = C.c_int
         # 2-D
         for f in ("orc_bessel_k0", "orc_bessel_k1"):
             getattr(L, f).argtypes = [C.c_double]
@@ -614,6 +616,11 @@ def direct2(kern, lam, pts, charges, tidx=None):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> int:
+    """threads of the oracle's parallel loops from now on; returns the previous count"""
+    return int(lib().orc_set_threads(int(n)))
 
 
 # ---------------------------------------------------------------- volume

@@ -43,6 +43,19 @@
 
 typedef double complex cplx;
 
+/* threads of the following parallel regions (n >= 1); returns the previous count */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    const int prev = omp_get_max_threads();
+    if (n >= 1) omp_set_num_threads(n);
+    return prev;
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -198,6 +198,7 @@ int orc_dmk_run(int64_t n, const double *pts, const double *q, double tol,
                 int ns, int maxdepth, double *u, double *times);
 
 int orc_num_threads(void);
+int orc_set_threads(int n);
 
 /* ------------------------------------------------------------------- 2-D
  * Kernels (input units): ORC_LOG2 K(r) = -log(r)/(2 pi); ORC_YUK2 K(r) =

@@ -33,8 +33,8 @@ PEAK = {"hbm": (8000.0, "GB/s"), "alu64": (78.6, "TFLOP/s"), "alu32": (157.3, "T
 STAGE_BOUND = {"gather": "hbm", "finalize": "hbm", "pwshift": "hbm", "upward": "alu", "root": "alu",
                "proxy2pw": "alu", "local": "alu", "pw2grid": "alu", "leaf": "alu", "residual": "alu"}
 STAGE_KERNEL = {"gather": "k_gather_q", "upward": "k_upward_q", "root": "k_root_stage",
-                "proxy2pw": "k_proxy2pw", "local": "k_local_pw_q", "pwshift": "k_pwshift",
-                "pw2grid": "k_local_pw_q", "leaf": "k_leaf", "residual": "k_residual",
+                "proxy2pw": "k_proxy2pw_mfma", "local": "k_local_mfma_q", "pwshift": "k_pwshift",
+                "pw2grid": "k_local_mfma_q", "leaf": "k_leaf_mfma", "residual": "k_residual",
                 "finalize": "k_finalize"}
 STAGE_KERNEL2 = {"gather": "k_gather_q2", "upward": "k_upward2", "root": "k_root2", "proxy2pw": "k_proxy2pw2",
                  "local": "k_local_pw2", "pwshift": "k_pwshift2", "pw2grid": "k_local_pw2", "leaf": "k_leaf2",
@@ -55,8 +55,8 @@ WORKLOADS = {
 }
 METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
 METRIC_VOL = "points/s, 3-D volume potential DMK (box code) at tol 1e-3, 1 GPU"
-STAGE_KERNEL_VOL = {"upward": "k_vol_upward", "root": "k_root_stage", "proxy2pw": "k_proxy2pw",
-                    "pwshift": "k_pwshift", "pw2grid": "k_local_pw_q", "leaf": "k_vol_leaf", "residual": "k_vol_near",
+STAGE_KERNEL_VOL = {"upward": "k_vol_upward", "root": "k_root_stage", "proxy2pw": "k_proxy2pw_mfma",
+                    "pwshift": "k_pwshift", "pw2grid": "k_local_mfma_q", "leaf": "k_vol_leaf", "residual": "k_vol_near",
                     "finalize": "k_vol_finalize"}
 # volume workload: density, refinement and tree limits
 VOL_SEED, VOL_RHO_SCALE, VOL_MAX_LEVEL = 5, 3e-5, 16
@@ -415,12 +415,10 @@ def main():
         achieved = per_launch / (avg_ms * 1e-3) / 1e12
         peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
     kname = STAGE_KERNEL[dom] if offsets is None else STAGE_KERNEL2[dom]
-    if offsets is None and dom == "pw2grid" and prec == dmk.DMK_MIXED:
-        kname = "k_local_mfma_q"  # the FP32 path's local stage runs on the matrix cores
     kname = per_level(kname, args)
     bound = STAGE_BOUND[dom]
     if "_mfma" in kname:
-        bound = "mfma"  # FP32 matrix-core products; dense FP32 MFMA peak is the same 157.3 TFLOP/s
+        bound = "mfma"  # matrix-core products: the dense MFMA peaks equal the vector ones (FP32 157.3, FP64 78.6)
     tr = TRAFFIC.get((args.workload, args.precision, kname))
     traffic = tr[0] if (tr is not None and tr[1] == eval_src_digest()) else None
     roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,

@@ -1,26 +1,31 @@
 // Steps 2-5 of the discrete DMK algorithm (Sec. 3.5) on gfx950.
 //
-// Every stage is one kernel per tree level (one workgroup per box), written
-// once as a template over the arithmetic type T (double for the FP64 path,
-// float for the mixed path), the Chebyshev order P and the plane-wave half
-// width NF.  The tensor-product transforms are sequences of small dense
-// contractions (Lemmas 2.1/2.2, eqs. outgoingexpansion2/incomingexpansion2);
-// they run as register-tiled GEMMs on operands staged in LDS.
+// Every stage is written once as a template over the arithmetic type T
+// (double for the FP64 path, float for the mixed path), the Chebyshev order
+// P and the plane-wave half width NF.  The tensor-product transforms are
+// sequences of small dense contractions (Lemmas 2.1/2.2, eqs.
+// outgoingexpansion2/incomingexpansion2); the plane-wave transforms, the
+// local values and the leaf evaluation run them on the matrix cores
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64), the upward pass as
+// register-tiled products on the vector ALUs.
 //
-//   k_upward     proxy charges of each F_out box: F_out children are merged
-//                with the child->parent anterpolation matrices (Lemma 2.1);
-//                the points of all other children are anterpolated straight
-//                onto the parent's grid (Def. 2.1, exact by Lemma 2.1).
+//   k_upward_q   proxy charges of each F_out box, all levels in one launch
+//                fed by a device work queue (k_upward: one level): F_out
+//                children are merged with the child->parent anterpolation
+//                matrices (Lemma 2.1); the points of all other children are
+//                anterpolated straight onto the parent's grid (Def. 2.1,
+//                exact by Lemma 2.1).
 //   k_root_stage windowed kernel W_0 on the root grid (FP64 always).
-//   k_proxy2pw   outgoing plane waves Phi_l(B) of F_out boxes.
+//   k_proxy2pw_mfma  outgoing plane waves Phi_l(B) of F_out boxes.
 //   k_pwshift    incoming plane waves Psi_l(B) from the F_out colleagues
 //                (diagonal translation; with h_l s_l = 2 pi/3 the phases
 //                are cube roots of unity).
-//   k_local_pw   local values of the anchor boxes (the root and the boxes
-//                with F_in): interpolation of the nearest anchor ancestor's
-//                polynomial to the box's grid (Lemma 2.2) plus the box's own
-//                incoming plane waves evaluated on that grid.
-//   k_leaf       far potential at the targets of each leaf, read from its
+//   k_local_mfma_q  local values of the anchor boxes (the root and the
+//                boxes with F_in), all levels from a work queue
+//                (k_local_mfma: one level): interpolation of the nearest
+//                anchor ancestor's polynomial to the box's grid (Lemma 2.2)
+//                plus the box's own incoming plane waves on that grid.
+//   k_leaf_mfma  far potential at the targets of each leaf, read from its
 //                anchor's polynomial (a box without F_in adds nothing of its
 //                own, so its polynomial is its anchor's, restricted).
 //   k_residual   residual-kernel sums in gather form with the r = 0 self
@@ -236,53 +241,6 @@ __global__ void __launch_bounds__(TPB) k_upward_q(Dev<T> D, WorkQ q)
         [&](int32_t Pb) { upward_box<T, P, true>(D, Pb); });
 }
 
-// -------------------------------------------- proxies -> plane waves
-// Phi[m1][m3][m2] = sum_j E[m1][j1] E[m2][j2] E[m3][j3] rho[j1][j2][j3],
-// E[m][j] = exp(-i pi m x_j / 3); m3 >= 0 only (rho is real).
-template <typename T, int P, int NF, int G>
-__global__ void __launch_bounds__(TPB) k_proxy2pw(Dev<T> D, const int32_t *list)
-{
-    constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
-    extern __shared__ __align__(16) unsigned char smraw[];
-    T *sm = reinterpret_cast<T *>(smraw);
-    T *rho = sm;                  // p^3
-    T *Er = rho + P3;             // [nn][p]
-    T *Ei = Er + NN * P;
-    T *Bc = Ei + NN * P;          // [p][2G]: E rows m3 of the group, re | im
-    T *Ag = Bc + P * 2 * G;       // [(j1 j2)][2G]
-    T *Bg = Ag + P2 * 2 * G;      // planar [j1][G][nn] re, then im
-    const int32_t B = list[blockIdx.x];
-    const T *src = D.proxy + (int64_t)D.proxy_slot[B] * P3;
-    for (int t = threadIdx.x; t < P3; t += TPB) rho[t] = src[t];
-    for (int t = threadIdx.x; t < NN * P; t += TPB) {
-        Er[t] = D.epw[2 * t];
-        Ei[t] = D.epw[2 * t + 1];
-    }
-    const int64_t nm = D.pwstride;
-    T *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
-    T *outi = outr + nm;
-    for (int g0 = 0; g0 < NH; g0 += G) {
-        const int g = min(G, NH - g0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < P * 2 * g; t += TPB) {
-            int k = t / (2 * g), c = t % (2 * g);
-            int m3 = g0 + (c < g ? c : c - g);
-            Bc[k * 2 * g + c] = (c < g) ? Er[(m3 + NF) * P + k] : Ei[(m3 + NF) * P + k];
-        }
-        __syncthreads();
-        // A[(j1 j2)][c] = sum_j3 rho[(j1 j2)][j3] Bc[j3][c]
-        gemm<T, 6, 2, false>(1, P2, 2 * g, P, rho, 0, P, 1, Bc, 0, 2 * g, 1, Ag, 0, 2 * g, 1);
-        __syncthreads();
-        // B[j1][m3][m2] = sum_j2 A[j1][j2][m3] E[m2][j2]
-        cgemm<T, 2, 5, false>(P, g, NN, P, Ag, Ag + g, P * 2 * g, 1, 2 * g, Er, Ei, 0, 1, P, Bg, Bg + P * g * NN,
-                              g * NN, NN, 1);
-        __syncthreads();
-        // Phi[m1][(m3 m2)] = sum_j1 E[m1][j1] B[j1][(m3 m2)]  (the group's rows are contiguous)
-        cgemm<T, 5, 4, false>(1, NN, g * NN, P, Er, Ei, 0, P, 1, Bg, Bg + P * g * NN, 0, g * NN, 1,
-                              outr + g0 * NN, outi + g0 * NN, 0, NH * NN, 1);
-    }
-}
-
 // ------------------------------------------------ diagonal translation
 // Incoming plane waves of the children of one parent (a sibling group).  The
 // colleagues of the 8 children lie in the 4x4x4 block of boxes around them;
@@ -472,136 +430,6 @@ __global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_ds
     }
 }
 
-// ------------------------------------------------ local values (anchors)
-// v_B = interp(anchor(parent(B)) -> B's grid) + Re sum_m exp(+i pi m.x/3) Psi_B[m]
-// COH: the anchor above the box was computed by the same launch (queue-fed)
-template <typename T, int P, int NF, int G1, bool COH>
-__device__ __forceinline__ void local_box(const Dev<T> &D, const int32_t B, const int level)
-{
-    constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
-    constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, NN = 2 * NF + 1, NH = NF + 1;
-    extern __shared__ __align__(16) unsigned char smraw[];
-    T *sm = reinterpret_cast<T *>(smraw);
-    T *Er = sm;                // [nn][p]  Re E
-    T *Ein = Er + NN * P;      // [nn][p] -Im E  (imaginary part of conj(E))
-    T *Gw = Ein + NN * P;      // [nh][p] re then [nh][p] im: c_m3 conj(E[m3][j3])
-    T *Gc = Gw + 2 * NH * P;   // [2 nn][p]: Re E rows, then Im E rows
-    T *xc = Gc + 2 * NN * P;
-    T *bw = xc + P;
-    T *w0 = bw + P;            // work area
-    for (int t = threadIdx.x; t < NN * P; t += TPB) {
-        T er = D.epw[2 * t], ei = D.epw[2 * t + 1];
-        Er[t] = er;
-        Ein[t] = -ei;
-        Gc[t] = er;
-        Gc[NN * P + t] = ei;
-    }
-    for (int t = threadIdx.x; t < NH * P; t += TPB) {
-        int m3 = t / P, j = t % P;
-        T c = (m3 == 0) ? T(1) : T(2);
-        Gw[t] = c * D.epw[2 * ((m3 + NF) * P + j)];
-        Gw[NH * P + t] = -c * D.epw[2 * ((m3 + NF) * P + j) + 1];
-    }
-    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
-    T acc[RM][RN];
-#pragma unroll
-    for (int i = 0; i < RM; ++i)
-#pragma unroll
-        for (int j = 0; j < RN; ++j) acc[i][j] = T(0);
-    __syncthreads();
-    if (level == 0) {
-        // root: the windowed W_0 values
-        constexpr int MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;
-        const int t = threadIdx.x;
-        if (t < MT * NT) {
-            const int mt = t / NT, nt = t % NT;
-#pragma unroll
-            for (int i = 0; i < RM; ++i)
-#pragma unroll
-                for (int j = 0; j < RN; ++j) {
-                    int m = mt + i * MT, n = nt + j * NT;
-                    if (m < P && n < P2) acc[i][j] = D.w0vals[(int64_t)B * P3 + m * P2 + n];  // root B = problem B
-                }
-        }
-    } else {
-        // interpolation from the anchor A of the parent: node i of B sits at
-        // A-coordinate ((c_B + s_B x_i / 2) - c_A) * 2 / s_A
-        const int32_t A = D.anchor[D.parent[B]];
-        T *Mx = w0, *My = Mx + P2, *Mz = My + P2, *t1 = Mz + P2, *t2 = t1 + P3;
-        const double sB = box_side(level), sA = box_side(D.blevel[A]);
-        for (int t = threadIdx.x; t < 3 * P; t += TPB) {
-            int d = t / P, i = t % P;
-            double xi = (D.bcenter[3 * (int64_t)B + d] + 0.5 * sB * D.xcheb64[i] - D.bcenter[3 * (int64_t)A + d]) *
-                        (2.0 / sA);
-            T row[P];
-            lagrange_row<T>(P, xc, bw, (T)xi, row);
-            T *dst = (d == 0 ? Mx : d == 1 ? My : Mz) + i * P;
-#pragma unroll
-            for (int a = 0; a < P; ++a) dst[a] = row[a];
-        }
-        const T *src = D.local + (int64_t)D.local_slot[A] * P3;
-        copy_to_lds<COH, TPB>(t2, src, P3);
-        __syncthreads();
-        // z: t1[(a0 a1)][i2] = sum_a2 v[(a0 a1)][a2] Mz[i2][a2]
-        gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Mz, 0, 1, P, t1, 0, P, 1);
-        __syncthreads();
-        // y: t2[a0][i1][i2] = sum_a1 My[i1][a1] t1[a0][a1][i2]
-        gemm<T, ZM, ZN, false>(P, P, P, P, My, 0, P, 1, t1, P2, P, 1, t2, P2, P, 1);
-        __syncthreads();
-        // x: acc[i0][r] = sum_a0 Mx[i0][a0] t2[a0][r]
-        gemm_regs<T, RM, RN>(P, P2, P, Mx, P, 1, t2, P2, 1, acc);
-    }
-    if (D.psi_slot[B] >= 0) {
-        const int64_t nm = D.pwstride;
-        const T *psr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *psim = psr + nm;
-        T *Sr = w0, *Si = Sr + G1 * NH * NN;                       // Psi rows of an m1 group [m1][m3][m2]
-        T *D1r = Si + G1 * NH * NN, *D1i = D1r + G1 * NN * P;      // [m1][m2][j3]
-        T *Dc = D1i + G1 * NN * P;                                  // [m1][(j2 j3)] re rows, then im rows
-        for (int g0 = 0; g0 < NN; g0 += G1) {
-            const int g = min(G1, NN - g0);
-            __syncthreads();
-            for (int t = threadIdx.x; t < g * NH * NN; t += TPB) {
-                Sr[t] = psr[(int64_t)g0 * NH * NN + t];
-                Si[t] = psim[(int64_t)g0 * NH * NN + t];
-            }
-            __syncthreads();
-            // D1[m1][m2][j3] = sum_m3 S[m1][m3][m2] Gw[m3][j3]
-            cgemm<T, 5, 3, false>(g, NN, P, NH, Sr, Si, NH * NN, 1, NN, Gw, Gw + NH * P, 0, P, 1, D1r, D1i,
-                                  NN * P, P, 1);
-            __syncthreads();
-            // D2[m1][j2][j3] = sum_m2 conj(E[m2][j2]) D1[m1][m2][j3]
-            cgemm<T, 3, 3, false>(g, P, P, NN, Er, Ein, 0, 1, P, D1r, D1i, NN * P, P, 1, Dc, Dc + g * P2, P2, P, 1);
-            __syncthreads();
-            // acc[j1][(j2 j3)] += sum_m1 Re(conj(E[m1][j1]) D2[m1][(j2 j3)])
-            //                  = sum_m1 ReE[m1][j1] D2r + ImE[m1][j1] D2i
-            gemm_regs<T, RM, RN>(P, P2, g, Gc + g0 * P, 1, P, Dc, P2, 1, acc);
-            gemm_regs<T, RM, RN>(P, P2, g, Gc + NN * P + g0 * P, 1, P, Dc + g * P2, P2, 1, acc);
-        }
-    }
-    store_tiles<T, P, COH>(acc, D.local + (int64_t)D.local_slot[B] * P3);
-}
-
-// one level's anchors, one workgroup per box
-template <typename T, int P, int NF, int G1>
-__global__ void __launch_bounds__(TPB) k_local_pw(Dev<T> D, const int32_t *list, int level)
-{
-    local_box<T, P, NF, G1, false>(D, list[blockIdx.x], level);
-}
-
-// the anchors of every level, coarsest first, from the work queue: a box
-// below the root waits for the anchor of its parent
-// one box per workgroup (grid = anchors), taken from the queue
-template <typename T, int P, int NF, int G1>
-__global__ void __launch_bounds__(TPB) k_local_pw_q(Dev<T> D, WorkQ q)
-{
-    queue_item(
-        q,
-        [&](int32_t B) {
-            if (threadIdx.x == 0 && D.blevel[B] > 0) wait_done(q, D.anchor[D.parent[B]]);
-        },
-        [&](int32_t B) { local_box<T, P, NF, G1, true>(D, B, D.blevel[B]); });
-}
-
 // ------------------------------------------ local values on matrix cores
 // FP32 path of the local stage on MFMA (v_mfma_f32_16x16x4f32).  Every step
 // is a mode product Y(x, a) = sum_k X(x, k) B(k, a) with x running over the
@@ -616,11 +444,39 @@ __global__ void __launch_bounds__(TPB) k_local_pw_q(Dev<T> D, WorkQ q)
 //   weights; the last step lands in the same (x = (j1 j2), a = j3)
 //   fragments as the interpolation's last step, so both stay in registers.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int NWAVE = TPB / 64;
+
+// one 16x16x4 matrix-core product in T: v_mfma_f32_16x16x4f32 or
+// v_mfma_f64_16x16x4f64.  Both take A(l%16, l/16) and B(l/16, l%16) from
+// lane l; they differ in where the 16x16 result lands: item q of lane l is
+// D(4(l/16) + q, l%16) in FP32 and D(l/16 + 4q, l%16) in FP64 (RB, RS)
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    using v4 = f32x4;
+    static constexpr int RB = 4, RS = 1;  // result item q of lane l: row RB (l / 16) + RS q
+    static __device__ __forceinline__ v4 mma(float a, float b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<double> {
+    using v4 = f64x4;
+    static constexpr int RB = 1, RS = 4;
+    static __device__ __forceinline__ v4 mma(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <typename T>
+using v4_t = typename Mfma<T>::v4;
 
 constexpr int LOCAL_NT = 512;  // threads per block of the local stage (more waves hide MFMA latency)
 
-template <int P, int NF>
+template <typename T, int P, int NF>
 struct LocalMfma {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1, NM = NH * NN;
     static constexpr int NSL = (P2 + 15) / 16;              // slabs of the p^2 x p outputs
@@ -632,7 +488,7 @@ struct LocalMfma {
     static constexpr int WORK_P2C = 2 * P3;
     static constexpr int WORK_PW = 2 * P * NM + G * P * KP;
     static constexpr int WORK = WORK_P2C > WORK_PW ? WORK_P2C : WORK_PW;
-    static size_t lds() { return sizeof(float) * (TAB + WORK); }
+    static size_t lds() { return sizeof(T) * (TAB + WORK); }
 };
 
 // Column split of a p-wide new index: 16-column MFMA tiles, and a remainder
@@ -648,7 +504,8 @@ struct ColSplit {
 };
 
 // sum over the four k quarters of a fragment (lanes r16, r16+16, r16+32, r16+48)
-__device__ inline float kq_sum(float v)
+template <typename T>
+__device__ inline T kq_sum(T v)
 {
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);
@@ -659,40 +516,40 @@ __device__ inline float kq_sum(float v)
 // wave's slabs i (slab w + NWV i) and tiles t; Bt[k * P + a].  The remainder
 // columns a = 16 NATM + j go to accr[i][j] for row 16 sl + r16 (the same value
 // in the four lanes of a row).
-template <int NWV, int P, int NX, int NK, int NSW, typename XF>
-__device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][ColSplit<P>::NATM],
-                                    float (&accr)[NSW][ColSplit<P>::NRA])
+template <int NWV, int P, int NX, int NK, int NSW, typename XF, typename T>
+__device__ inline void mma_real_acc(XF X, const T *Bt, v4_t<T> (&acc)[NSW][ColSplit<P>::NATM],
+                                    T (&accr)[NSW][ColSplit<P>::NRA])
 {
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float breg[NATM][NKS], brem[NRA][NKS];
+    T breg[NATM][NKS], brem[NRA][NKS];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
         const int k = 4 * s + kq;
 #pragma unroll
         for (int t = 0; t < NATM; ++t) {
             const int a = 16 * t + r16;
-            breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
+            breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : T(0);
         }
 #pragma unroll
-        for (int j = 0; j < NREM; ++j) brem[j][s] = (k < NK) ? Bt[k * P + 16 * NATM + j] : 0.f;
+        for (int j = 0; j < NREM; ++j) brem[j][s] = (k < NK) ? Bt[k * P + 16 * NATM + j] : T(0);
     }
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
         const int sl = w + NWV * i;
         if (sl >= NSL) break;  // uniform in the wave
         const int xa = 16 * sl + r16;
-        float pr[NRA];
+        T pr[NRA];
 #pragma unroll
-        for (int j = 0; j < NRA; ++j) pr[j] = 0.f;
+        for (int j = 0; j < NRA; ++j) pr[j] = T(0);
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
-            const float av = (xa < NX && k < NK) ? X(xa, k) : 0.f;
+            const T av = (xa < NX && k < NK) ? X(xa, k) : T(0);
 #pragma unroll
             for (int t = 0; t < NATM; ++t)
-                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[i][t], 0, 0, 0);
+                acc[i][t] = Mfma<T>::mma(av, breg[t][s], acc[i][t]);
 #pragma unroll
             for (int j = 0; j < NREM; ++j) pr[j] += av * brem[j][s];
         }
@@ -702,38 +559,38 @@ __device__ inline void mma_real_acc(XF X, const float *Bt, f32x4 (&acc)[NSW][Col
 }
 
 // real mode product with the result stored: Y(x, a) -> store(x, a, v)
-template <int NWV, int P, int NX, int NK, typename XF, typename SF>
-__device__ inline void mma_real_store(XF X, const float *Bt, SF store)
+template <int NWV, int P, int NX, int NK, typename XF, typename SF, typename T>
+__device__ inline void mma_real_store(XF X, const T *Bt, SF store)
 {
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int NKS = (NK + 3) / 4, NSL = (NX + 15) / 16;
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float breg[NATM][NKS], brem[NRA][NKS];
+    T breg[NATM][NKS], brem[NRA][NKS];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
         const int k = 4 * s + kq;
 #pragma unroll
         for (int t = 0; t < NATM; ++t) {
             const int a = 16 * t + r16;
-            breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : 0.f;
+            breg[t][s] = (k < NK && a < P) ? Bt[k * P + a] : T(0);
         }
 #pragma unroll
-        for (int j = 0; j < NREM; ++j) brem[j][s] = (k < NK) ? Bt[k * P + 16 * NATM + j] : 0.f;
+        for (int j = 0; j < NREM; ++j) brem[j][s] = (k < NK) ? Bt[k * P + 16 * NATM + j] : T(0);
     }
     for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
-        f32x4 acc[NATM];
-        float pr[NRA];
+        v4_t<T> acc[NATM];
+        T pr[NRA];
 #pragma unroll
-        for (int t = 0; t < NATM; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NATM; ++t) acc[t] = v4_t<T>{T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int j = 0; j < NRA; ++j) pr[j] = 0.f;
+        for (int j = 0; j < NRA; ++j) pr[j] = T(0);
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
-            const float av = (xa < NX && k < NK) ? X(xa, k) : 0.f;
+            const T av = (xa < NX && k < NK) ? X(xa, k) : T(0);
 #pragma unroll
-            for (int t = 0; t < NATM; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[t], 0, 0, 0);
+            for (int t = 0; t < NATM; ++t) acc[t] = Mfma<T>::mma(av, breg[t][s], acc[t]);
 #pragma unroll
             for (int j = 0; j < NREM; ++j) pr[j] += av * brem[j][s];
         }
@@ -741,12 +598,12 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
         for (int t = 0; t < NATM; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
+                const int x = 16 * sl + Mfma<T>::RB * kq + Mfma<T>::RS * i, a = 16 * t + r16;
                 if (x < NX && a < P) store(x, a, acc[t][i]);
             }
 #pragma unroll
         for (int j = 0; j < NREM; ++j) {
-            const float v = kq_sum(pr[j]);
+            const T v = kq_sum(pr[j]);
             if (kq == 0 && xa < NX) store(xa, 16 * NATM + j, v);
         }
     }
@@ -762,14 +619,14 @@ __device__ inline void mma_real_store(XF X, const float *Bt, SF store)
 // index k = m + NF.  Half the matrix-core work of the plain complex product.
 // PF: the operands of the wave's next slab are loaded before the current
 // slab's products (for X in global memory: hides the load latency).
-template <int NWV, int P, int NX, int NF, bool PF, typename XR, typename XI, typename SF>
-__device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store, int nx = NX)
+template <int NWV, int P, int NX, int NF, bool PF, typename XR, typename XI, typename SF, typename T>
+__device__ inline void mma_herm_store(XR Xr, XI Xi, const T *Br, const T *Bi, SF store, int nx = NX)
 {
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int NH = NF + 1, NKS = (NH + 3) / 4;
     const int NSL = (nx + 15) / 16;  // slabs holding the nx live rows
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float br[NATM][NKS], bi[NATM][NKS], rr[NRA][NKS], ri[NRA][NKS];
+    T br[NATM][NKS], bi[NATM][NKS], rr[NRA][NKS], ri[NRA][NKS];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
         const int k = 4 * s + kq;
@@ -777,51 +634,51 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
         for (int t = 0; t < NATM; ++t) {
             const int a = 16 * t + r16;
             const bool ok = k < NH && a < P;
-            br[t][s] = ok ? Br[k * P + a] : 0.f;
-            bi[t][s] = ok ? Bi[k * P + a] : 0.f;
+            br[t][s] = ok ? Br[k * P + a] : T(0);
+            bi[t][s] = ok ? Bi[k * P + a] : T(0);
         }
 #pragma unroll
         for (int j = 0; j < NREM; ++j) {
-            rr[j][s] = (k < NH) ? Br[k * P + 16 * NATM + j] : 0.f;
-            ri[j][s] = (k < NH) ? Bi[k * P + 16 * NATM + j] : 0.f;
+            rr[j][s] = (k < NH) ? Br[k * P + 16 * NATM + j] : T(0);
+            ri[j][s] = (k < NH) ? Bi[k * P + 16 * NATM + j] : T(0);
         }
     }
     // raw operands X[+m], X[-m] of a slab (X[-0] = 0: then s = d = X[0], and
     // the Bi row of m = 0 is zero, so d drops out there)
-    auto fetch = [&](int sl, float (&fpr)[NKS], float (&fpi)[NKS], float (&fqr)[NKS], float (&fqi)[NKS]) {
+    auto fetch = [&](int sl, T (&fpr)[NKS], T (&fpi)[NKS], T (&fqr)[NKS], T (&fqi)[NKS]) {
         const int xa = 16 * sl + r16;
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int m = 4 * s + kq;
             const bool ok = sl < NSL && xa < nx && m < NH, okq = ok && m > 0;
-            fpr[s] = ok ? Xr(xa, NF + m) : 0.f;
-            fpi[s] = ok ? Xi(xa, NF + m) : 0.f;
-            fqr[s] = okq ? Xr(xa, NF - m) : 0.f;
-            fqi[s] = okq ? Xi(xa, NF - m) : 0.f;
+            fpr[s] = ok ? Xr(xa, NF + m) : T(0);
+            fpi[s] = ok ? Xi(xa, NF + m) : T(0);
+            fqr[s] = okq ? Xr(xa, NF - m) : T(0);
+            fqi[s] = okq ? Xi(xa, NF - m) : T(0);
         }
     };
-    float pr[NKS], pi[NKS], qr[NKS], qi[NKS];
+    T pr[NKS], pi[NKS], qr[NKS], qi[NKS];
     if (PF) fetch(w, pr, pi, qr, qi);
     for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
-        float npr[NKS], npi[NKS], nqr[NKS], nqi[NKS];
+        T npr[NKS], npi[NKS], nqr[NKS], nqi[NKS];
         if (PF) fetch(sl + NWV, npr, npi, nqr, nqi);
         else fetch(sl, pr, pi, qr, qi);
-        f32x4 cr[NATM], ci[NATM];
-        float ar[NRA], ai[NRA];
+        v4_t<T> cr[NATM], ci[NATM];
+        T ar[NRA], ai[NRA];
 #pragma unroll
-        for (int t = 0; t < NATM; ++t) cr[t] = ci[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NATM; ++t) cr[t] = ci[t] = v4_t<T>{T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int j = 0; j < NRA; ++j) ar[j] = ai[j] = 0.f;
+        for (int j = 0; j < NRA; ++j) ar[j] = ai[j] = T(0);
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
-            const float sr = pr[s] + qr[s], si = pi[s] + qi[s], dr = pr[s] - qr[s], ndi = qi[s] - pi[s];
+            const T sr = pr[s] + qr[s], si = pi[s] + qi[s], dr = pr[s] - qr[s], ndi = qi[s] - pi[s];
 #pragma unroll
             for (int t = 0; t < NATM; ++t) {
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sr, br[t][s], cr[t], 0, 0, 0);
-                cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ndi, bi[t][s], cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(si, br[t][s], ci[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(dr, bi[t][s], ci[t], 0, 0, 0);
+                cr[t] = Mfma<T>::mma(sr, br[t][s], cr[t]);
+                cr[t] = Mfma<T>::mma(ndi, bi[t][s], cr[t]);
+                ci[t] = Mfma<T>::mma(si, br[t][s], ci[t]);
+                ci[t] = Mfma<T>::mma(dr, bi[t][s], ci[t]);
             }
 #pragma unroll
             for (int j = 0; j < NREM; ++j) {
@@ -833,12 +690,12 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
         for (int t = 0; t < NATM; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int x = 16 * sl + 4 * kq + i, a = 16 * t + r16;
+                const int x = 16 * sl + Mfma<T>::RB * kq + Mfma<T>::RS * i, a = 16 * t + r16;
                 if (x < nx && a < P) store(x, a, cr[t][i], ci[t][i]);
             }
 #pragma unroll
         for (int j = 0; j < NREM; ++j) {
-            const float vr = kq_sum(ar[j]), vi = kq_sum(ai[j]);
+            const T vr = kq_sum(ar[j]), vi = kq_sum(ai[j]);
             if (kq == 0 && xa < nx) store(xa, 16 * NATM + j, vr, vi);
         }
         if (PF) {
@@ -849,31 +706,31 @@ __device__ inline void mma_herm_store(XR Xr, XI Xi, const float *Br, const float
 }
 
 // COH: the anchor above the box was computed by the same launch (queue-fed)
-template <int P, int NF, bool COH>
-__device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_t B, const int level)
+template <typename T, int P, int NF, bool COH>
+__device__ __forceinline__ void local_box_mfma(const Dev<T> &D, const int32_t B, const int level)
 {
-    using L = LocalMfma<P, NF>;
+    using L = LocalMfma<T, P, NF>;
     constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, NSW = L::NSW;
     constexpr int NATM = ColSplit<P>::NATM, NREM = ColSplit<P>::NREM, NRA = ColSplit<P>::NRA;
     constexpr int G = L::G, KP = L::KP, NSL = L::NSL, NWV = L::NWV, NT = L::NT;
     extern __shared__ __align__(16) unsigned char smraw[];
-    float *sm = reinterpret_cast<float *>(smraw);
-    float *Br1 = sm, *Bi1 = Br1 + NN * P;  // conj(E): B(k = m, a = j) = Er[m][j] - i Ei[m][j]
-    float *B3 = Bi1 + NN * P;              // [KP][P]: c_m3 Er[m3][j3], then c_m3 Ei[m3][j3]
-    float *Bx = B3 + KP * P, *By = Bx + P2, *Bz = By + P2;  // B(k = a, col = i) = M_d[i][a]
-    float *xc = Bz + P2, *bw = xc + P;
-    float *work = bw + P;
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *Br1 = sm, *Bi1 = Br1 + NN * P;  // conj(E): B(k = m, a = j) = Er[m][j] - i Ei[m][j]
+    T *B3 = Bi1 + NN * P;              // [KP][P]: c_m3 Er[m3][j3], then c_m3 Ei[m3][j3]
+    T *Bx = B3 + KP * P, *By = Bx + P2, *Bz = By + P2;  // B(k = a, col = i) = M_d[i][a]
+    T *xc = Bz + P2, *bw = xc + P;
+    T *work = bw + P;
     // the parent anchor's values, loaded first so that their latency overlaps
     // the table set-up and the Lagrange rows
     constexpr int NVP = (P3 + NT - 1) / NT;
-    float vpre[NVP];
+    T vpre[NVP];
     const int32_t A = level > 0 ? D.anchor[D.parent[B]] : -1;
     if (level > 0) {
-        const float *src = D.local + (int64_t)D.local_slot[A] * P3;
+        const T *src = D.local + (int64_t)D.local_slot[A] * P3;
 #pragma unroll
         for (int i = 0; i < NVP; ++i) {
             const int t = threadIdx.x + i * NT;
-            vpre[i] = t < P3 ? ld_c<COH>(src + t) : 0.f;
+            vpre[i] = t < P3 ? ld_c<COH>(src + t) : T(0);
         }
     }
     for (int t = threadIdx.x; t < NN * P; t += NT) {
@@ -882,27 +739,27 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
     }
     for (int t = threadIdx.x; t < KP * P; t += NT) {
         const int k = t / P, j = t % P, m3 = (k < NH) ? k : k - NH;
-        const float cm = (m3 == 0) ? 1.f : 2.f;
-        const float *e = D.epw + 2 * ((m3 + NF) * P + j);
+        const T cm = (m3 == 0) ? T(1) : T(2);
+        const T *e = D.epw + 2 * ((m3 + NF) * P + j);
         B3[t] = cm * ((k < NH) ? e[0] : e[1]);
     }
     for (int t = threadIdx.x; t < P; t += NT) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
     // the box's values: columns j3 < 16 NATM in MFMA fragments, the last
     // NREM columns in accr (row 16 sl + r16, the same in the row's four lanes)
-    f32x4 acc[NSW][NATM];
-    float accr[NSW][NRA];
+    v4_t<T> acc[NSW][NATM];
+    T accr[NSW][NRA];
 #pragma unroll
     for (int i = 0; i < NSW; ++i) {
 #pragma unroll
-        for (int t = 0; t < NATM; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NATM; ++t) acc[i][t] = v4_t<T>{T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int j = 0; j < NRA; ++j) accr[i][j] = 0.f;
+        for (int j = 0; j < NRA; ++j) accr[i][j] = T(0);
     }
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
     __syncthreads();
     if (level == 0) {
         // root: the windowed W_0 values, in the fragment layout of the last step
-        const float *w0B = D.w0vals + (int64_t)B * P3;  // root B = problem B
+        const T *w0B = D.w0vals + (int64_t)B * P3;  // root B = problem B
 #pragma unroll
         for (int i = 0; i < NSW; ++i) {
             const int sl = w + NWV * i;
@@ -911,12 +768,12 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
             for (int t = 0; t < NATM; ++t)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
+                    const int x = 16 * sl + Mfma<T>::RB * kq + Mfma<T>::RS * q, a = 16 * t + r16;
                     if (x < P2 && a < P) acc[i][t][q] = w0B[x * P + a];
                 }
             const int xa = 16 * sl + r16;
 #pragma unroll
-            for (int j = 0; j < NREM; ++j) accr[i][j] = (xa < P2) ? w0B[xa * P + 16 * NATM + j] : 0.f;
+            for (int j = 0; j < NREM; ++j) accr[i][j] = (xa < P2) ? w0B[xa * P + 16 * NATM + j] : T(0);
         }
     } else {
         // interpolation from the anchor A of the parent: node i of B sits at
@@ -926,13 +783,13 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
             const int d = t / P, i = t % P;
             const double xi = (D.bcenter[3 * (int64_t)B + d] + 0.5 * sB * D.xcheb64[i] - D.bcenter[3 * (int64_t)A + d]) *
                               (2.0 / sA);
-            float row[P];
-            lagrange_row<float>(P, xc, bw, (float)xi, row);
-            float *Bd = (d == 0) ? Bx : (d == 1) ? By : Bz;
+            T row[P];
+            lagrange_row<T>(P, xc, bw, (T)xi, row);
+            T *Bd = (d == 0) ? Bx : (d == 1) ? By : Bz;
 #pragma unroll
             for (int a = 0; a < P; ++a) Bd[a * P + i] = row[a];
         }
-        float *vA = work, *t1 = work + P3;
+        T *vA = work, *t1 = work + P3;
 #pragma unroll
         for (int i = 0; i < NVP; ++i) {
             const int t = threadIdx.x + i * NT;
@@ -941,25 +798,25 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
         __syncthreads();
         // x: t1[i0][(a1 a2)] = sum_a0 vA[a0][(a1 a2)] Mx[i0][a0]
         mma_real_store<NWV, P, P2, P>([&](int x, int k) { return vA[k * P2 + x]; }, Bx,
-                                      [&](int x, int a, float v) { t1[a * P2 + x] = v; });
+                                      [&](int x, int a, T v) { t1[a * P2 + x] = v; });
         __syncthreads();
         // y: t2[i0][i1][a2] = sum_a1 t1[i0][a1][a2] My[i1][a1]; rows x = (i0, a2)
-        float *t2 = vA;
+        T *t2 = vA;
         mma_real_store<NWV, P, P2, P>([&](int x, int k) { return t1[(x / P) * P2 + k * P + (x % P)]; }, By,
-                                      [&](int x, int a, float v) { t2[(x / P) * P2 + a * P + (x % P)] = v; });
+                                      [&](int x, int a, T v) { t2[(x / P) * P2 + a * P + (x % P)] = v; });
         __syncthreads();
         // z: acc[(i0 i1)][i2] = sum_a2 t2[(i0 i1)][a2] Mz[i2][a2]
         mma_real_acc<NWV, P, P2, P, NSW>([&](int x, int k) { return t2[x * P + k]; }, Bz, acc, accr);
     }
     if (D.psi_slot[B] >= 0) {
         const int64_t nm = D.pwstride;
-        const float *psr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *psi = psr + nm;
-        float *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
+        const T *psr = D.psi + 2 * (int64_t)D.psi_slot[B] * nm, *psi = psr + nm;
+        T *A1r = work, *A1i = work + P * NM, *B2 = work + 2 * P * NM;
         __syncthreads();
         // m1: A1[j1][(m3 m2)] = sum_m1 conj(E[m1][j1]) Psi[m1][(m3 m2)], Psi read from HBM
         mma_herm_store<NWV, P, NM, NF, true>([&](int x, int k) { return psr[k * NM + x]; },
                                             [&](int x, int k) { return psi[k * NM + x]; }, Br1 + NF * P, Bi1 + NF * P,
-                                                   [&](int x, int a, float vr, float vi) {
+                                                   [&](int x, int a, T vr, T vi) {
             A1r[a * NM + x] = vr;
             A1i[a * NM + x] = vi;
         });
@@ -969,10 +826,10 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
             __syncthreads();
             // m2: B2[(j1 j2)][m3 | NH + m3] = sum_m2 conj(E[m2][j2]) A1[j1][m3][m2]; rows x = (j1 - g0, m3)
             mma_herm_store<NWV, P, G * NH, NF, false>(
-                [&](int x, int k) { return (x < g * NH) ? A1r[(g0 * NH + x) * NN + k] : 0.f; },
-                [&](int x, int k) { return (x < g * NH) ? A1i[(g0 * NH + x) * NN + k] : 0.f; }, Br1 + NF * P,
+                [&](int x, int k) { return (x < g * NH) ? A1r[(g0 * NH + x) * NN + k] : T(0); },
+                [&](int x, int k) { return (x < g * NH) ? A1i[(g0 * NH + x) * NN + k] : T(0); }, Br1 + NF * P,
                 Bi1 + NF * P,
-                [&](int x, int a, float vr, float vi) {
+                [&](int x, int a, T vr, T vi) {
                     if (x < g * NH) {
                         const int j1 = x / NH, m3 = x % NH;
                         B2[(j1 * P + a) * KP + m3] = vr;
@@ -983,17 +840,17 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
             __syncthreads();
             // m3: acc[(j1 j2)][j3] += sum_k' B2[(j1 j2)][k'] B3[k'][j3] for the slabs of this group
             constexpr int NKS = (KP + 3) / 4;
-            float breg[NATM][NKS], brem[NRA][NKS];
+            T breg[NATM][NKS], brem[NRA][NKS];
 #pragma unroll
             for (int s = 0; s < NKS; ++s) {
                 const int k = 4 * s + kq;
 #pragma unroll
                 for (int t = 0; t < NATM; ++t) {
                     const int a = 16 * t + r16;
-                    breg[t][s] = (k < KP && a < P) ? B3[k * P + a] : 0.f;
+                    breg[t][s] = (k < KP && a < P) ? B3[k * P + a] : T(0);
                 }
 #pragma unroll
-                for (int j = 0; j < NREM; ++j) brem[j][s] = (k < KP) ? B3[k * P + 16 * NATM + j] : 0.f;
+                for (int j = 0; j < NREM; ++j) brem[j][s] = (k < KP) ? B3[k * P + 16 * NATM + j] : T(0);
             }
             const int r0 = g0 * P, r1 = (g0 + g) * P;  // rows of this group, multiples of 16 at r0
 #pragma unroll
@@ -1001,16 +858,16 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
                 const int sl = w + NWV * i;
                 if (sl >= NSL || 16 * sl < r0 || 16 * sl >= r1) continue;  // uniform in the wave
                 const int xa = 16 * sl + r16;
-                float pr[NRA];
+                T pr[NRA];
 #pragma unroll
-                for (int j = 0; j < NRA; ++j) pr[j] = 0.f;
+                for (int j = 0; j < NRA; ++j) pr[j] = T(0);
 #pragma unroll
                 for (int s = 0; s < NKS; ++s) {
                     const int k = 4 * s + kq;
-                    const float av = (xa < r1 && k < KP) ? B2[(xa - r0) * KP + k] : 0.f;
+                    const T av = (xa < r1 && k < KP) ? B2[(xa - r0) * KP + k] : T(0);
 #pragma unroll
                     for (int t = 0; t < NATM; ++t)
-                        acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, breg[t][s], acc[i][t], 0, 0, 0);
+                        acc[i][t] = Mfma<T>::mma(av, breg[t][s], acc[i][t]);
 #pragma unroll
                     for (int j = 0; j < NREM; ++j) pr[j] += av * brem[j][s];
                 }
@@ -1023,8 +880,8 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
     // (COH: read by later boxes of the same launch) through LDS and out in
     // whole lines with cache-bypassing stores; atomic stores straight from
     // the fragments keep their order and cost this kernel registers
-    float *dst = D.local + (int64_t)D.local_slot[B] * P3;
-    float *out = dst;
+    T *dst = D.local + (int64_t)D.local_slot[B] * P3;
+    T *out = dst;
     if constexpr (COH) {
         out = work;
         __syncthreads();  // the last group's B2 reads are done
@@ -1037,7 +894,7 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
         for (int t = 0; t < NATM; ++t)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int x = 16 * sl + 4 * kq + q, a = 16 * t + r16;
+                const int x = 16 * sl + Mfma<T>::RB * kq + Mfma<T>::RS * q, a = 16 * t + r16;
                 if (x < P2 && a < P) out[x * P + a] = acc[i][t][q];
             }
         const int xa = 16 * sl + r16;
@@ -1051,29 +908,34 @@ __device__ __forceinline__ void local_box_mfma(const Dev<float> &D, const int32_
     }
 }
 
-template <int P, int NF>
-__global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma(Dev<float> D, const int32_t *list, int level)
+// FP32: 4 waves per SIMD (two blocks per CU); FP64: two (LDS and registers
+// take one block per CU)
+template <typename T>
+constexpr int local_waves() { return sizeof(T) == 4 ? 4 : 2; }
+
+template <typename T, int P, int NF>
+__global__ void __launch_bounds__(LOCAL_NT, local_waves<T>()) k_local_mfma(Dev<T> D, const int32_t *list, int level)
 {
-    local_box_mfma<P, NF, false>(D, list[blockIdx.x], level);
+    local_box_mfma<T, P, NF, false>(D, list[blockIdx.x], level);
 }
 
 // one box per workgroup (grid = anchors), taken from the queue: looping over
 // boxes in one workgroup held the body's loop-invariant index arithmetic in
 // registers across items and pushed this kernel into scratch
-template <int P, int NF>
-__global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma_q(Dev<float> D, WorkQ q)
+template <typename T, int P, int NF>
+__global__ void __launch_bounds__(LOCAL_NT, local_waves<T>()) k_local_mfma_q(Dev<T> D, WorkQ q)
 {
     queue_item(
         q,
         [&](int32_t B) {
             if (threadIdx.x == 0 && D.blevel[B] > 0) wait_done(q, D.anchor[D.parent[B]]);
         },
-        [&](int32_t B) { local_box_mfma<P, NF, true>(D, B, D.blevel[B]); });
+        [&](int32_t B) { local_box_mfma<T, P, NF, true>(D, B, D.blevel[B]); });
 }
 
 // ------------------------------------ outgoing plane waves on matrix cores
-// FP32 path of proxy -> plane waves (eq. outgoingexpansion2) on MFMA, the
-// mode products of k_proxy2pw in the fragment scheme of the local stage:
+// Proxy -> plane waves (eq. outgoingexpansion2) on MFMA, three mode
+// products in the fragment scheme of the local stage:
 //   j3 -> m3  A[(j1 j2)][m3 | NH + m3] = sum_j3 rho[(j1 j2)][j3] (Re | Im) E[m3][j3]
 //   j2 -> m2  B2[(mm j1)][m2] = sum_j2 A[(j1 j2)][m3] E[m2][j2]   (complex)
 //   j1 -> m1  Phi[m1][(mm m2)] = sum_j1 E[m1][j1] B2[(mm j1)][m2] (complex)
@@ -1086,45 +948,45 @@ __global__ void __launch_bounds__(LOCAL_NT, 4) k_local_mfma_q(Dev<float> D, Work
 // which halves the matrix-core work of the plain complex product.  Br, Bi
 // point at column m = 0 of E (element (k, m) at k * NBS + m); store receives
 // (x, m, Y[m], Y[-m]) for m = 0..NF (Y[-0] is Y[0]).
-template <int NWV, int NF, int NX, int NK, int NBS, typename XR, typename XI, typename SF>
-__device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const float *Bi, SF store, int nx = NX)
+template <int NWV, int NF, int NX, int NK, int NBS, typename XR, typename XI, typename SF, typename T>
+__device__ inline void mma_herm_out_store(XR Xr, XI Xi, const T *Br, const T *Bi, SF store, int nx = NX)
 {
     constexpr int NH = NF + 1, NKS = (NK + 3) / 4, NAT = (NH + 15) / 16;
     const int NSL = (nx + 15) / 16;  // slabs holding the nx live rows
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6, kq = l >> 4, r16 = l & 15;
-    float br[NAT][NKS], bi[NAT][NKS];
+    T br[NAT][NKS], bi[NAT][NKS];
 #pragma unroll
     for (int t = 0; t < NAT; ++t)
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq, a = 16 * t + r16;
             const bool ok = k < NK && a < NH;
-            br[t][s] = ok ? Br[k * NBS + a] : 0.f;
-            bi[t][s] = ok ? Bi[k * NBS + a] : 0.f;
+            br[t][s] = ok ? Br[k * NBS + a] : T(0);
+            bi[t][s] = ok ? Bi[k * NBS + a] : T(0);
         }
     for (int sl = w; sl < NSL; sl += NWV) {
         const int xa = 16 * sl + r16;
-        f32x4 ur[NAT], ui[NAT], vr[NAT], vi[NAT];
+        v4_t<T> ur[NAT], ui[NAT], vr[NAT], vi[NAT];
 #pragma unroll
-        for (int t = 0; t < NAT; ++t) ur[t] = ui[t] = vr[t] = vi[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NAT; ++t) ur[t] = ui[t] = vr[t] = vi[t] = v4_t<T>{T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
             const bool ok = xa < nx && k < NK;
-            const float ar = ok ? Xr(xa, k) : 0.f, ai = ok ? Xi(xa, k) : 0.f;
+            const T ar = ok ? Xr(xa, k) : T(0), ai = ok ? Xi(xa, k) : T(0);
 #pragma unroll
             for (int t = 0; t < NAT; ++t) {
-                ur[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br[t][s], ur[t], 0, 0, 0);
-                ui[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br[t][s], ui[t], 0, 0, 0);
-                vr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi[t][s], vr[t], 0, 0, 0);
-                vi[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi[t][s], vi[t], 0, 0, 0);
+                ur[t] = Mfma<T>::mma(ar, br[t][s], ur[t]);
+                ui[t] = Mfma<T>::mma(ai, br[t][s], ui[t]);
+                vr[t] = Mfma<T>::mma(ar, bi[t][s], vr[t]);
+                vi[t] = Mfma<T>::mma(ai, bi[t][s], vi[t]);
             }
         }
 #pragma unroll
         for (int t = 0; t < NAT; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int x = 16 * sl + 4 * kq + i, m = 16 * t + r16;
+                const int x = 16 * sl + Mfma<T>::RB * kq + Mfma<T>::RS * i, m = 16 * t + r16;
                 if (x < nx && m < NH)
                     store(x, m, ur[t][i] - vi[t][i], ui[t][i] + vr[t][i], ur[t][i] + vi[t][i], ui[t][i] - vr[t][i]);
             }
@@ -1133,29 +995,29 @@ __device__ inline void mma_herm_out_store(XR Xr, XI Xi, const float *Br, const f
 
 constexpr int P2PW_NT = 512;  // threads per block of proxy -> plane waves on matrix cores
 
-template <int P, int NF>
+template <typename T, int P, int NF>
 struct P2pwMfma {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1, NM = NH * NN, W1 = 2 * NH;
     static constexpr int G = 4;
     static constexpr int R0 = (P3 > 2 * P * G * NN + 2 * NN * G * NN) ? P3 : 2 * P * G * NN + 2 * NN * G * NN;
     static constexpr int TAB = P * W1 + 2 * P * NN;
-    static size_t lds() { return sizeof(float) * (TAB + R0 + P2 * W1); }
+    static size_t lds() { return sizeof(T) * (TAB + R0 + P2 * W1); }
 };
 
-template <int P, int NF>
-__global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const int32_t *list)
+template <typename T, int P, int NF>
+__global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<T> D, const int32_t *list)
 {
-    using L = P2pwMfma<P, NF>;
+    using L = P2pwMfma<T, P, NF>;
     constexpr int P2 = L::P2, P3 = L::P3, NN = L::NN, NH = L::NH, NM = L::NM, W1 = L::W1, G = L::G;
     extern __shared__ __align__(16) unsigned char smraw[];
-    float *sm = reinterpret_cast<float *>(smraw);
-    float *B1 = sm;                    // [j3][W1]: Re E[m3][j3] | Im E[m3][j3]
-    float *BrT = B1 + P * W1;          // [j][m]: Re E[m][j]
-    float *BiT = BrT + P * NN;         //         Im E[m][j]
-    float *r0 = BiT + P * NN;          // rho, then B2 and the staged Phi rows
-    float *A = r0 + L::R0;             // [(j1 j2)][W1]
-    float *B2r = r0, *B2i = B2r + P * G * NN;       // [(mm j1)][m2]
-    float *Fr = B2i + P * G * NN, *Fi = Fr + NN * G * NN;  // [m1][(mm m2)]
+    T *sm = reinterpret_cast<T *>(smraw);
+    T *B1 = sm;                    // [j3][W1]: Re E[m3][j3] | Im E[m3][j3]
+    T *BrT = B1 + P * W1;          // [j][m]: Re E[m][j]
+    T *BiT = BrT + P * NN;         //         Im E[m][j]
+    T *r0 = BiT + P * NN;          // rho, then B2 and the staged Phi rows
+    T *A = r0 + L::R0;             // [(j1 j2)][W1]
+    T *B2r = r0, *B2i = B2r + P * G * NN;       // [(mm j1)][m2]
+    T *Fr = B2i + P * G * NN, *Fi = Fr + NN * G * NN;  // [m1][(mm m2)]
     const int32_t B = list[blockIdx.x];
     for (int t = threadIdx.x; t < P * W1; t += P2PW_NT) {
         const int j = t / W1, a = t % W1, m3 = (a < NH) ? a : a - NH;
@@ -1166,23 +1028,23 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
         BrT[t] = D.epw[2 * (m * P + j)];
         BiT[t] = D.epw[2 * (m * P + j) + 1];
     }
-    const float *src = D.proxy + (int64_t)D.proxy_slot[B] * P3;
+    const T *src = D.proxy + (int64_t)D.proxy_slot[B] * P3;
     for (int t = threadIdx.x; t < P3; t += P2PW_NT) r0[t] = src[t];
     __syncthreads();
     // j3 -> m3 (real rho times the real and imaginary rows)
     mma_real_store<P2PW_NT / 64, W1, P2, P>([&](int x, int k) { return r0[x * P + k]; }, B1,
-                                              [&](int x, int a, float v) { A[x * W1 + a] = v; });
+                                              [&](int x, int a, T v) { A[x * W1 + a] = v; });
     const int64_t nm = D.pwstride;
-    float *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
-    float *outi = outr + nm;
+    T *outr = D.phi + 2 * (int64_t)D.proxy_slot[B] * nm;
+    T *outi = outr + nm;
     for (int g0 = 0; g0 < NH; g0 += G) {
         const int g = min(G, NH - g0);
         __syncthreads();
         // j2 -> m2: rows x = (mm, j1), the g P live rows first
         mma_herm_out_store<P2PW_NT / 64, NF, P * G, P, NN>(
-            [&](int x, int k) { const int mm = x / P, j1 = x % P; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : 0.f; },
-            [&](int x, int k) { const int mm = x / P, j1 = x % P; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : 0.f; },
-            BrT + NF, BiT + NF, [&](int x, int m, float pr, float pi, float nr, float ni) {
+            [&](int x, int k) { const int mm = x / P, j1 = x % P; return (mm < g) ? A[(j1 * P + k) * W1 + g0 + mm] : T(0); },
+            [&](int x, int k) { const int mm = x / P, j1 = x % P; return (mm < g) ? A[(j1 * P + k) * W1 + NH + g0 + mm] : T(0); },
+            BrT + NF, BiT + NF, [&](int x, int m, T pr, T pi, T nr, T ni) {
                 B2r[x * NN + NF + m] = pr;
                 B2i[x * NN + NF + m] = pi;
                 if (m > 0) {
@@ -1194,9 +1056,9 @@ __global__ void __launch_bounds__(P2PW_NT) k_proxy2pw_mfma(Dev<float> D, const i
         __syncthreads();
         // j1 -> m1: rows x = (mm, m2)
         mma_herm_out_store<P2PW_NT / 64, NF, G * NN, P, NN>(
-            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(mm * P + k) * NN + m2] : 0.f; },
-            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(mm * P + k) * NN + m2] : 0.f; },
-            BrT + NF, BiT + NF, [&](int x, int m, float pr, float pi, float nr, float ni) {
+            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2r[(mm * P + k) * NN + m2] : T(0); },
+            [&](int x, int k) { const int mm = x / NN, m2 = x % NN; return (mm < g) ? B2i[(mm * P + k) * NN + m2] : T(0); },
+            BrT + NF, BiT + NF, [&](int x, int m, T pr, T pi, T nr, T ni) {
                 Fr[(NF + m) * G * NN + x] = pr;
                 Fi[(NF + m) * G * NN + x] = pi;
                 if (m > 0) {
@@ -1251,49 +1113,6 @@ __device__ inline void lagrange_row_fast(const T *xc, const T *bw, T xi, T (&out
     for (int a = 0; a < P; ++a) out[a] *= r;
 }
 
-// One workgroup per anchor box; one thread per target among the points of
-// the leaves whose anchor it is (at most 8 n_s of them): the anchor's p^3
-// values sit in LDS and every lane reads the same entry at the same time.
-template <typename T, int P>
-__global__ void __launch_bounds__(TPB) k_leaf(Dev<T> D, const int32_t *anc, const int32_t *tbeg, const int32_t *tgt)
-{
-    constexpr int P2 = P * P, P3 = P2 * P;
-    extern __shared__ __align__(16) unsigned char smraw[];
-    T *sm = reinterpret_cast<T *>(smraw);
-    T *v = sm, *xc = v + P3, *bw = xc + P;
-    const int a = blockIdx.x;
-    const int b0 = tbeg[a], b1 = tbeg[a + 1];
-    if (b0 == b1) return;
-    const int32_t A = anc[a];
-    const T *src = D.local + (int64_t)a * P3;
-    for (int t = threadIdx.x; t < P3; t += TPB) v[t] = src[t];
-    for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
-    __syncthreads();
-    const double cA0 = D.bcenter[3 * (int64_t)A], cA1 = D.bcenter[3 * (int64_t)A + 1],
-                 cA2 = D.bcenter[3 * (int64_t)A + 2];
-    const double sc = 2.0 / box_side(D.blevel[A]);
-    for (int t = b0 + threadIdx.x; t < b1; t += TPB) {
-        const int64_t i = tgt[t];
-        T lx[P], ly[P], lz[P];
-        lagrange_row_fast<T, P>(xc, bw, (T)((D.Xt[i] - cA0) * sc), lx);
-        lagrange_row_fast<T, P>(xc, bw, (T)((D.Yt[i] - cA1) * sc), ly);
-        lagrange_row_fast<T, P>(xc, bw, (T)((D.Zt[i] - cA2) * sc), lz);
-        T u = T(0);
-        for (int j1 = 0; j1 < P; ++j1) {
-            T s1 = T(0);
-#pragma unroll
-            for (int j2 = 0; j2 < P; ++j2) {
-                const T *row = v + j1 * P2 + j2 * P;
-                T s2 = T(0);
-#pragma unroll
-                for (int j3 = 0; j3 < P; ++j3) s2 += row[j3] * lz[j3];
-                s1 += ly[j2] * s2;
-            }
-            u += lx[j1] * s1;
-        }
-        D.ufar[i] = (double)u;
-    }
-}
 
 // -------------------------------------------------------------- residual
 // One workgroup per target leaf.  The sources of the leaf's whole gather list
@@ -1711,18 +1530,18 @@ inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + TPB
 // wave at a time.  W((j1 j2), t) = sum_j3 v[(j1 j2)][j3] Lz_t[j3] is an MFMA
 // mode product (rows (j1 j2), columns the targets); each lane then folds its
 // four rows of W with Lx_t[j1] Ly_t[j2] and the four lanes of a target add up.
-template <int P>
-__global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *anc, const int32_t *tbeg,
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<T> D, const int32_t *anc, const int32_t *tbeg,
                                                    const int32_t *tgt)
 {
     constexpr int P2 = P * P, P3 = P2 * P, NSL = (P2 + 15) / 16, NKS = (P + 3) / 4;
-    __shared__ float v[P3], xc[P], bw[P];
-    __shared__ float Lr[NWAVE][3][16][P];  // Lagrange rows x, y, z of the wave's 16 targets
+    __shared__ T v[P3], xc[P], bw[P];
+    __shared__ T Lr[NWAVE][3][16][P];  // Lagrange rows x, y, z of the wave's 16 targets
     const int a = blockIdx.x;
     const int b0 = tbeg[a], b1 = tbeg[a + 1];
     if (b0 == b1) return;  // whole block
     const int32_t A = anc[a];
-    const float *src = D.local + (int64_t)a * P3;
+    const T *src = D.local + (int64_t)a * P3;
     for (int t = threadIdx.x; t < P3; t += TPB) v[t] = src[t];
     for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
     const double cA[3] = {D.bcenter[3 * (int64_t)A], D.bcenter[3 * (int64_t)A + 1], D.bcenter[3 * (int64_t)A + 2]};
@@ -1736,14 +1555,14 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
         const int t = base + r16;
         const bool tv = t < b1;
         if (kq < 3) {
-            float row[P];
+            T row[P];
             if (tv) {
                 const int64_t i = tgt[t];
                 const double x = (kq == 0) ? D.Xt[i] : (kq == 1) ? D.Yt[i] : D.Zt[i];
-                lagrange_row_fast<float, P>(xc, bw, (float)((x - cA[kq]) * sc), row);
+                lagrange_row_fast<T, P>(xc, bw, (T)((x - cA[kq]) * sc), row);
             } else {
 #pragma unroll
-                for (int j = 0; j < P; ++j) row[j] = 0.f;
+                for (int j = 0; j < P; ++j) row[j] = T(0);
             }
 #pragma unroll
             for (int j = 0; j < P; ++j) Lr[w][kq][r16][j] = row[j];
@@ -1753,40 +1572,45 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float bz[NKS];
+        T bz[NKS];
 #pragma unroll
         for (int s = 0; s < NKS; ++s) {
             const int k = 4 * s + kq;
-            bz[s] = (k < P) ? Lr[w][2][r16][k] : 0.f;
+            bz[s] = (k < P) ? Lr[w][2][r16][k] : T(0);
         }
-        float part = 0.f;
+        T part = T(0);
         // LU slabs at a time (independent MFMA chains); the lane's first row
-        // x0 = 16 sl + 4 kq is tracked as (x0 / P, x0 % P)
-        constexpr int LU = 3;
-        int i0 = (4 * kq) / P, i1 = (4 * kq) % P;
+        // x0 = 16 sl + RB kq is tracked as (x0 / P, x0 % P), its rows are
+        // x0 + RS q
+        constexpr int LU = 3, RB = Mfma<T>::RB, RS = Mfma<T>::RS;
+        int i0 = (RB * kq) / P, i1 = (RB * kq) % P;
 #pragma unroll 1
         for (int sl = 0; sl < NSL; sl += LU) {
-            f32x4 acc[LU];
+            v4_t<T> acc[LU];
 #pragma unroll
-            for (int u = 0; u < LU; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int u = 0; u < LU; ++u) acc[u] = v4_t<T>{T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int s = 0; s < NKS; ++s) {
                 const int k = 4 * s + kq;
 #pragma unroll
                 for (int u = 0; u < LU; ++u) {
                     const int xa = 16 * (sl + u) + r16;
-                    const float av = (xa < P2 && k < P) ? v[xa * P + k] : 0.f;
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bz[s], acc[u], 0, 0, 0);
+                    const T av = (xa < P2 && k < P) ? v[xa * P + k] : T(0);
+                    acc[u] = Mfma<T>::mma(av, bz[s], acc[u]);
                 }
             }
 #pragma unroll
             for (int u = 0; u < LU; ++u) {
-                const int x0 = 16 * (sl + u) + 4 * kq;
+                const int x0 = 16 * (sl + u) + RB * kq;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    int j0 = i0, j1 = i1 + q;
-                    if (j1 >= P) { j1 -= P; ++j0; }
-                    if (x0 + q < P2) part += Lr[w][0][r16][j0] * Lr[w][1][r16][j1] * acc[u][q];
+                    int j0 = i0, j1 = i1 + RS * q;
+                    if constexpr (RS == 1) {
+                        if (j1 >= P) { j1 -= P; ++j0; }
+                    } else {
+                        while (j1 >= P) { j1 -= P; ++j0; }
+                    }
+                    if (x0 + RS * q < P2) part += Lr[w][0][r16][j0] * Lr[w][1][r16][j1] * acc[u][q];
                 }
                 // next slab: x0 += 16
                 i1 += 16;
@@ -1807,18 +1631,7 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<float> D, const int32_t *
 template <typename T, int P, int NF>
 struct Cfg {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
-    static constexpr int G = sizeof(T) == 8 ? 4 : 7;    // m3 group of k_proxy2pw
-    static constexpr int G1 = 5;                        // m1 group of k_local_pw
     static size_t lds_up() { return sizeof(T) * (2 * P2 + 2 * P + 2 * P3); }
-    static size_t lds_p2pw() { return sizeof(T) * (P3 + 2 * NN * P + P * 2 * G + P2 * 2 * G + 2 * P * G * NN); }
-    static size_t lds_local()
-    {
-        size_t fixed = 2 * NN * P + 2 * NH * P + 2 * NN * P + 2 * P;
-        size_t p2c = 3 * P2 + 2 * P3;
-        size_t pw = 2 * G1 * NH * NN + 2 * G1 * NN * P + 2 * G1 * P2;
-        return sizeof(T) * (fixed + std::max(p2c, pw));
-    }
-    static size_t lds_leaf() { return sizeof(T) * (P3 + 2 * P); }
 };
 
 template <typename T>
@@ -1961,16 +1774,10 @@ static void set_lds_attrs()
     if (attrs) return;
     allow_lds(k_upward<T, P>, C::lds_up());
     allow_lds(k_upward_q<T, P>, C::lds_up());
-    allow_lds(k_proxy2pw<T, P, NF, C::G>, C::lds_p2pw());
-    allow_lds(k_local_pw<T, P, NF, C::G1>, C::lds_local());
-    allow_lds(k_local_pw_q<T, P, NF, C::G1>, C::lds_local());
-    const size_t lds_mfma = LocalMfma<P, NF>::lds();
-    if constexpr (sizeof(T) == 4) {
-        allow_lds(k_local_mfma<P, NF>, lds_mfma);
-        allow_lds(k_local_mfma_q<P, NF>, lds_mfma);
-        allow_lds(k_proxy2pw_mfma<P, NF>, P2pwMfma<P, NF>::lds());
-    }
-    allow_lds(k_leaf<T, P>, C::lds_leaf());
+    const size_t lds_mfma = LocalMfma<T, P, NF>::lds();
+    allow_lds(k_local_mfma<T, P, NF>, lds_mfma);
+    allow_lds(k_local_mfma_q<T, P, NF>, lds_mfma);
+    allow_lds(k_proxy2pw_mfma<T, P, NF>, P2pwMfma<T, P, NF>::lds());
     (void)queue_wait_ticks();
     QGrid<T, P, NF>::upward = resident_blocks(k_upward_q<T, P>, TPB, C::lds_up());
     attrs = true;
@@ -2019,13 +1826,8 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     // waves of every non-empty F_in box, all levels in one launch each
     if (Pl->nfout) {
         StageScope t(Pl, s, DMK_STAGE_PROXY2PW);
-        const size_t lds_p2pw_mfma = P2pwMfma<P, NF>::lds();
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_proxy2pw_mfma<P, NF>), dim3((unsigned)Pl->nfout), dim3(P2PW_NT), lds_p2pw_mfma, s, D,
-                               Pl->l_fout);
-        else
-            hipLaunchKernelGGL((k_proxy2pw<T, P, NF, C::G>), dim3((unsigned)Pl->nfout), dim3(TPB), C::lds_p2pw(), s, D,
-                               Pl->l_fout);
+        hipLaunchKernelGGL((k_proxy2pw_mfma<T, P, NF>), dim3((unsigned)Pl->nfout), dim3(P2PW_NT),
+                           (P2pwMfma<T, P, NF>::lds()), s, D, Pl->l_fout);
     }
     if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
@@ -2042,28 +1844,16 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
         StageScope t(Pl, s, DMK_STAGE_PW2GRID);
         const WorkQ q = local_queue(Pl);
         reset_queue(q.head, 4 + Pl->nanc, s);
-        if constexpr (sizeof(T) == 4) {
-            const size_t lds = LocalMfma<P, NF>::lds();
-            hipLaunchKernelGGL((k_local_mfma_q<P, NF>), dim3((unsigned)Pl->nanc),
-                               dim3(LOCAL_NT), lds, s, D, q);
-        } else {
-            hipLaunchKernelGGL((k_local_pw_q<T, P, NF, C::G1>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_local(), s,
-                               D, q);
-        }
+        hipLaunchKernelGGL((k_local_mfma_q<T, P, NF>), dim3((unsigned)Pl->nanc), dim3(LOCAL_NT),
+                           (LocalMfma<T, P, NF>::lds()), s, D, q);
         return;
     }
     for (int l = 0; l < L; ++l) {
         int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];
         if (!nan) continue;
         StageScope t(Pl, s, DMK_STAGE_PW2GRID);
-        const size_t lds_mfma = LocalMfma<P, NF>::lds();
-        const unsigned nt_mfma = LocalMfma<P, NF>::NT;
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_local_mfma<P, NF>), dim3((unsigned)nan), dim3(nt_mfma), lds_mfma, s, D,
-                               Pl->l_anc + ll.anc_off[l], l);
-        else
-            hipLaunchKernelGGL((k_local_pw<T, P, NF, C::G1>), dim3((unsigned)nan), dim3(TPB), C::lds_local(), s, D,
-                               Pl->l_anc + ll.anc_off[l], l);
+        hipLaunchKernelGGL((k_local_mfma<T, P, NF>), dim3((unsigned)nan), dim3(LOCAL_NT), (LocalMfma<T, P, NF>::lds()),
+                           s, D, Pl->l_anc + ll.anc_off[l], l);
     }
 }
 
@@ -2098,12 +1888,8 @@ static void enqueue_chain(Plan *Pl, hipStream_t s)
     enqueue_far<T, P, NF>(Pl, s);
     if (Pl->nleaf) {
         StageScope t(Pl, s, DMK_STAGE_LEAF);
-        if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL((k_leaf_mfma<P>), dim3((unsigned)Pl->nanc), dim3(TPB), 0, s, D, Pl->l_anc,
-                               Pl->anc_tbeg, Pl->anc_tgt);
-        else
-            hipLaunchKernelGGL((k_leaf<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), C::lds_leaf(), s, D,
-                               Pl->l_anc, Pl->anc_tbeg, Pl->anc_tgt);
+        hipLaunchKernelGGL((k_leaf_mfma<T, P>), dim3((unsigned)Pl->nanc), dim3(TPB), 0, s, D, Pl->l_anc, Pl->anc_tbeg,
+                           Pl->anc_tgt);
     }
 }
 

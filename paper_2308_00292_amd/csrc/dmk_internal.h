@@ -164,6 +164,7 @@ struct Plan {
     uint8_t *bflags = nullptr;  // bit0 leaf, bit1 fout, bit2 fin, bit3 terminal
     int32_t *colleague = nullptr;  // [nbox][3^dim]
     int32_t *anchor = nullptr;     // [nbox] nearest ancestor-or-self holding local values
+    uint8_t *anc_read = nullptr;   // [nanc] 1 where a finer anchor reads the anchor's local values
     int32_t *ncoarse = nullptr, *coarse = nullptr;  // [nbox], [nbox][2^dim - 1]
     double *bcenter = nullptr;     // [nbox][dim]
 

@@ -59,6 +59,7 @@ struct Dev {
     const int32_t *pstart, *pcount, *child0, *parent, *col, *proxy_slot, *local_slot, *psi_slot, *blevel,
         *anchor;
     const uint8_t *bflags;
+    const uint8_t *anc_read;  // per anchor slot: its values are read by a finer anchor
     const double *bcenter;
     const T *c2p, *epw, *wd0, *gcheb, *gmono, *xcheb, *bary;  // tables in T
     const double *ew64, *ww64, *xcheb64, *bary64;     // FP64 tables
@@ -877,12 +878,14 @@ __device__ __forceinline__ void local_box_mfma(const Dev<T> &D, const int32_t B,
         }
     }
     // the box's values, x-major p^3 block: straight from the fragments, or
-    // (COH: read by later boxes of the same launch) through LDS and out in
-    // whole lines with cache-bypassing stores; atomic stores straight from
-    // the fragments keep their order and cost this kernel registers
+    // (COH, and a finer anchor of the same launch reads them) through LDS
+    // and out in whole lines with cache-bypassing stores; atomic stores
+    // straight from the fragments keep their order and cost this kernel
+    // registers
     T *dst = D.local + (int64_t)D.local_slot[B] * P3;
+    const bool coh = COH && D.anc_read[D.local_slot[B]];
     T *out = dst;
-    if constexpr (COH) {
+    if (coh) {
         out = work;
         __syncthreads();  // the last group's B2 reads are done
     }
@@ -902,7 +905,7 @@ __device__ __forceinline__ void local_box_mfma(const Dev<T> &D, const int32_t B,
         for (int j = 0; j < NREM; ++j)
             if (kq == 0 && xa < P2) out[xa * P + 16 * NATM + j] = accr[i][j];
     }
-    if constexpr (COH) {
+    if (coh) {
         __syncthreads();
         for (int t = threadIdx.x; t < P3; t += NT) st_c<true>(dst + t, work[t]);
     }
@@ -1646,6 +1649,7 @@ Dev<T> make_dev(Plan *P)
     D.pstart = P->sstart; D.pcount = P->scount; D.child0 = P->child0; D.parent = P->parent; D.col = P->colleague;
     D.proxy_slot = P->proxy_slot; D.local_slot = P->local_slot; D.psi_slot = P->psi_slot; D.blevel = P->blevel;
     D.anchor = P->anchor;
+    D.anc_read = P->anc_read;
     D.bflags = P->bflags; D.bcenter = P->bcenter;
     const bool f64 = sizeof(T) == 8;
     D.c2p = (const T *)(f64 ? (void *)P->d_c2p : (void *)P->f_c2p);

@@ -787,6 +787,16 @@ __global__ void k_fill_targets(const int32_t *sorted_leaves, int64_t nleaf, cons
     for (int k = threadIdx.x; k < pcount[L]; k += TPB) tgt[pos[i] + k] = pstart[L] + k;
 }
 
+// anchors whose local values a finer anchor reads (its parent's anchor)
+__global__ void k_anchor_read(const int32_t *anc, int64_t m, const int32_t *blevel, const int32_t *parent,
+                              const int32_t *anchor, const int32_t *local_slot, uint8_t *read)
+{
+    int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (i >= m) return;
+    const int32_t B = anc[i];
+    if (blevel[B] > 0) read[local_slot[anchor[parent[B]]]] = 1;
+}
+
 __global__ void k_slots(const int32_t *list, int64_t m, int32_t *slot)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -1006,6 +1016,11 @@ static void build_lists_t(Plan *P, hipStream_t s)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfout)), dim3(TPB), 0, s, P->l_fout, P->nfout, P->proxy_slot);
     if (P->nanc)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nanc)), dim3(TPB), 0, s, P->l_anc, P->nanc, P->local_slot);
+    P->anc_read = talloc<uint8_t>(P, std::max<int64_t>(P->nanc, 1));
+    DMK_HIP(hipMemsetAsync(P->anc_read, 0, std::max<int64_t>(P->nanc, 1), s));
+    if (P->nanc)
+        hipLaunchKernelGGL(k_anchor_read, dim3(nblk(P->nanc)), dim3(TPB), 0, s, P->l_anc, P->nanc, P->blevel, P->parent,
+                           P->anchor, P->local_slot, P->anc_read);
     if (P->nfin)
         hipLaunchKernelGGL(k_slots, dim3(nblk(P->nfin)), dim3(TPB), 0, s, P->l_fin, P->nfin, P->psi_slot);
 

@@ -51,7 +51,7 @@ struct Dev2 {
         *anchor, *bprob;
     const uint8_t *bflags;
     const double *bcenter;
-    const T *c2p, *epw, *wd0, *gcheb, *xcheb, *bary;
+    const T *c2p, *epw, *wd0, *gcheb, *gmono, *xcheb, *bary;  // gmono: m(x) as a power series in u = 2x^2 - 1
     const double *ew64, *ww64, *xcheb64, *bary64;
     T *proxy, *local, *phi, *psi, *w0vals;
     double *ufar, *ures;
@@ -665,6 +665,131 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
     }
 }
 
+// log(x) for x > 0: the hardware base-2 logarithm in FP32 (operands below
+// 1e-30, never produced by distinct points of a normalised tree, go through
+// the library function), the library function in FP64
+__device__ inline float log_r2(float x) { return x > 1e-30f ? 0.69314718055994531f * __builtin_amdgcn_logf(x) : logf(x); }
+__device__ inline double log_r2(double x) { return log(x); }
+
+// Residual sums of -log(r)/(2 pi) in gather form, the same layout as
+// k_residual2 (which keeps the K_0 kernel): per pair with x = r/s_l < 1,
+//   -log(r^2)/(4 pi) - m(x) + level constant,
+// m as a power series of degree DEG in u = 2x^2 - 1 held in registers and
+// evaluated by Horner's rule; RB candidates per round are read and tested
+// together, then the ones in range are summed.
+template <typename T, int DEG>
+__global__ void __launch_bounds__(TPB) k_residual2_log(Dev2<T> D, const int32_t *leaves, const int32_t *nl_off,
+                                                       const int32_t *nl_src, const int32_t *nl_pre)
+{
+    constexpr int RCAP = 512;
+    __shared__ union {
+        struct { T x[RCAP], y[RCAP], q[RCAP], is2[RCAP], lc[RCAP]; } s;
+        double part[TPB];
+    } stg;
+    T *sx = stg.s.x, *sy = stg.s.y, *sq = stg.s.q, *sis2 = stg.s.is2, *slc = stg.s.lc;
+    double *part = stg.part;
+    __shared__ int32_t loff[RLIST2 + 1];
+    const int32_t B = leaves[blockIdx.x];
+    const int64_t t0 = D.pstart[B];
+    const int nt = D.pcount[B];
+    const int32_t l0 = nl_off[blockIdx.x];
+    const int L = nl_off[blockIdx.x + 1] - l0;
+    T gm[DEG + 1];
+#pragma unroll
+    for (int k = 0; k <= DEG; ++k) gm[k] = (k <= D.gdeg) ? D.gmono[k] : T(0);
+    for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
+    __syncthreads();
+    const int nsrc = loff[L];
+    const int32_t prob = D.bprob[B];
+    const double cx = D.bcenter[2 * (int64_t)B], cy = D.bcenter[2 * (int64_t)B + 1];
+    const double Cb = -log(D.pside[prob]) / (2.0 * M_PI);
+    const T zero_val = (T)(-(D.m0 + Cb));  // plus the source level's constant
+    const T k4pi = (T)(-1.0 / (4.0 * M_PI));
+    const int tch = min(max(nt, 1), 64);
+    const int nsplit = TPB / tch;
+    const int tl = threadIdx.x % tch, split = threadIdx.x / tch;
+    for (int tbase = 0; tbase < nt; tbase += tch) {
+        const bool active = (tbase + tl) < nt;
+        const int64_t it = t0 + tbase + (active ? tl : 0);
+        const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy);
+        double acc = 0.0;
+        for (int pb = 0; pb < nsrc; pb += RCAP) {
+            const int cnt = min(RCAP, nsrc - pb);
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < cnt; idx += TPB) {
+                const int g = pb + idx;
+                int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (loff[mid] <= g) lo = mid; else hi = mid - 1;
+                }
+                const int32_t Tb = nl_src[l0 + lo];
+                const int64_t j = D.pstart[Tb] + (g - loff[lo]);
+                const int lev = D.blevel[Tb];
+                sx[idx] = (T)(D.X[j] - cx);
+                sy[idx] = (T)(D.Y[j] - cy);
+                sq[idx] = (T)D.qs[j];
+                sis2[idx] = (T)ldexp(1.0, 2 * lev);
+                slc[idx] = (T)(-lev * M_LN2 / (2.0 * M_PI));
+            }
+            __syncthreads();
+            T pacc = T(0);
+            constexpr int RB = 4;
+            for (int j0 = split; j0 < cnt && split < nsplit; j0 += RB * nsplit) {
+                T r2v[RB], ttv[RB];
+                int jv[RB];
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    const int j = j0 + u * nsplit;
+                    jv[u] = j < cnt ? j : -1;
+                    const int jj = j < cnt ? j : j0;  // a valid slot for the spare lanes
+                    const T dx = xt - sx[jj], dy = yt - sy[jj];
+                    r2v[u] = dx * dx + dy * dy;
+                    ttv[u] = r2v[u] * sis2[jj];
+                }
+#pragma unroll
+                for (int u = 0; u < RB; ++u) {
+                    if (jv[u] >= 0 && ttv[u] < T(1)) {
+                        const int j = jv[u];
+                        const T uu = T(2) * ttv[u] - T(1);
+                        T m = gm[DEG];
+#pragma unroll
+                        for (int k = DEG - 1; k >= 0; --k) m = m * uu + gm[k];
+                        const T val = (r2v[u] > T(0)) ? k4pi * log_r2(r2v[u]) - m : zero_val;
+                        pacc += sq[j] * (val + slc[j]);
+                    }
+                }
+            }
+            acc += (double)pacc;
+        }
+        __syncthreads();
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        if (split == 0 && active) {
+            double sum = 0.0;
+            for (int k = 0; k < nsplit; ++k) sum += part[k * tch + tl];
+            D.ures[t0 + tbase + tl] = sum;
+        }
+    }
+}
+
+// the residual launch: K_0 problems in k_residual2, the log kernel in
+// k_residual2_log with the series' degree as a compile-time bucket
+template <typename T>
+static void launch_residual2(const Dev2<T> &D, Plan *Pl, hipStream_t s)
+{
+    const dim3 g((unsigned)Pl->nleaf), b(TPB);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+    };
+    if (D.kern) go(k_residual2<T>);
+    else if (D.gdeg <= 9) go(k_residual2_log<T, 9>);
+    else if (D.gdeg <= 13) go(k_residual2_log<T, 13>);
+    else if (D.gdeg <= 17) go(k_residual2_log<T, 17>);
+    else if (D.gdeg <= 23) go(k_residual2_log<T, 23>);
+    else go(k_residual2_log<T, 47>);
+}
+
 __global__ void k_gather_q2(const double *charges, const int32_t *perm, int64_t n, double *qs)
 {
     int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
@@ -712,6 +837,7 @@ Dev2<T> make_dev2(Plan *P)
     D.epw = (const T *)(f64 ? (void *)P->d_epw : (void *)P->f_epw);
     D.wd0 = (const T *)(f64 ? (void *)P->d_wd0 : (void *)P->f_wd0);
     D.gcheb = (const T *)(f64 ? (void *)P->d_gcheb : (void *)P->f_gcheb);
+    D.gmono = (const T *)(f64 ? (void *)P->d_gmono : (void *)P->f_gmono);
     D.xcheb = (const T *)(f64 ? (void *)P->d_xcheb : (void *)P->f_xcheb);
     D.bary = (const T *)(f64 ? (void *)P->d_bary : (void *)P->f_bary);
     D.ew64 = P->d_ew; D.ww64 = P->d_ww; D.xcheb64 = P->d_xcheb; D.bary64 = P->d_bary;
@@ -755,8 +881,7 @@ static void enqueue_core2(Plan *Pl, hipStream_t s, hipStream_t side)
     if (side && Pl->nleaf) {
         DMK_HIP(hipEventRecord(Pl->ev_fork, s));
         DMK_HIP(hipStreamWaitEvent(side, Pl->ev_fork, 0));
-        hipLaunchKernelGGL((k_residual2<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, side, D, Pl->l_leaf,
-                           Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        launch_residual2<T>(D, Pl, side);
         DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
     for (int l = L - 1; l >= 0; --l) {
@@ -800,8 +925,7 @@ static void enqueue_core2(Plan *Pl, hipStream_t s, hipStream_t side)
             DMK_HIP(hipStreamWaitEvent(s, Pl->ev_join, 0));
         } else {
             StageScope t(Pl, s, DMK_STAGE_RESIDUAL);
-            hipLaunchKernelGGL((k_residual2<T>), dim3((unsigned)Pl->nleaf), dim3(TPB), 0, s, D, Pl->l_leaf,
-                               Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+            launch_residual2<T>(D, Pl, s);
         }
     }
 }

@@ -446,8 +446,10 @@ void build_tables2(Tables *t)
         }
         double cmax = 0.0;
         for (double v : cf) cmax = std::max(cmax, std::fabs(v));
+        // keep the terms above the rounding floor of the samples (~2e-15 of
+        // the largest coefficient)
         int deg = M - 1;
-        while (deg > 0 && std::fabs(cf[deg]) < 1e-15 * cmax) deg--;
+        while (deg > 0 && std::fabs(cf[deg]) < 1e-14 * cmax) deg--;
         t->gdeg = deg;
         t->gcheb.assign(cf.begin(), cf.begin() + deg + 1);
         int deg32 = deg;

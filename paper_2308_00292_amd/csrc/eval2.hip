@@ -31,6 +31,7 @@
 
 #include "dmk_internal.h"
 #include "kfun.h"
+#include "lagrange.h"
 
 namespace dmk {
 
@@ -521,8 +522,8 @@ __global__ void __launch_bounds__(TPB) k_leaf2(Dev2<T> D, const int32_t *anc, co
     for (int t = b0 + threadIdx.x; t < b1; t += TPB) {
         const int64_t i = tgt[t];
         T lx[P], ly[P];
-        lagrange_row<T>(P, xc, bw, (T)((D.X[i] - cA0) * sc), lx);
-        lagrange_row<T>(P, xc, bw, (T)((D.Y[i] - cA1) * sc), ly);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.X[i] - cA0) * sc), lx);
+        lagrange_row_fast<T, P>(xc, bw, (T)((D.Y[i] - cA1) * sc), ly);
         T u = T(0);
         for (int j1 = 0; j1 < P; ++j1) {
             T s = T(0);

@@ -485,7 +485,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload, "n_points": n,
                    "tol": tol, "leaf_max": ns, "precision": args.precision, "batched": batched,
-                   "schedule": "per-level launches" if args.level_launches else "queue-fed over all levels",
+                   "schedule": ("per-level launches" if (args.level_launches or offsets is not None)
+                                else "queue-fed over all levels"),
                    "kernel": ("1/(4 pi r)" if offsets is None else
                               ("-log(r)/(2 pi)" if kern == dmk.DMK_LAPLACE else "K_0(10 r)")),
                    "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"],

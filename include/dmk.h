@@ -104,15 +104,18 @@ typedef struct {
  * DMK_ERR_STATE on it.  Ignored by dmk_vol_plan. */
 #define DMK_FLAG_NO_WORKSPACE 4ull
 
-/* The upward pass and the local values are launched one tree level at a
- * time, one workgroup per box, instead of as one queue-fed launch each over
- * all levels (the default: a persistent grid takes the boxes from a device
- * work queue in dependency order, finest level first for the upward pass and
- * coarsest first for the local values, and a box waits on flags until the
- * boxes it reads are done).  Each box is computed by the same code either
- * way, so the results are bit-identical.  3-D point and volume plans; 2-D
- * plans always launch per level. */
+/* Schedule of the upward pass and of the local values.  Queue-fed: one
+ * launch per stage over all levels, in which a grid takes the boxes from a
+ * device work queue in dependency order (finest level first for the upward
+ * pass, coarsest first for the local values) and a box waits on flags until
+ * the boxes it reads are done.  Per level: one launch per tree level, one
+ * workgroup per box.  Each box is computed by the same code either way, so
+ * the results are bit-identical.  Default: queue-fed in 3-D (point and
+ * volume plans), per level in 2-D (where a box is p^2 values and the queue's
+ * own cost outweighs what it saves).  The two flags force one schedule;
+ * both together are DMK_ERR_ARG. */
 #define DMK_FLAG_LEVEL_LAUNCHES 8ull
+#define DMK_FLAG_QUEUE_LAUNCHES 16ull
 
 /* Size of the static device scratch of dmk_eval_noalloc, per device. */
 #define DMK_NOALLOC_MAX_BYTES (128ll << 20)
@@ -541,7 +544,7 @@ typedef void (*dmk_density_fn)(int64_t n, const double *xyz, double *out, void *
  *  opts       precision: DMK_FP64, or DMK_MIXED (the far-field transforms
  *             and the near-field factor products in FP32, the asymptotic
  *             part and the final sums in FP64); flags: DMK_FLAG_LEVEL_LAUNCHES
- *             only (others ignored); leaf_max, max_depth, lambda, p, n_f,
+ *             or DMK_FLAG_QUEUE_LAUNCHES only (others ignored); leaf_max, max_depth, lambda, p, n_f,
  *             pswf_c ignored; NULL for defaults.
  *  stream     for the device work; returns after it completes.
  * The plan holds at most 2^31 - 1 nodes (nleaf q^3).  Free with

@@ -19,6 +19,7 @@ DMK_LAPLACE, DMK_YUKAWA, DMK_POWER2 = 0, 1, 2
 DMK_FLAG_BATCHED = 2
 DMK_FLAG_NO_WORKSPACE = 4
 DMK_FLAG_LEVEL_LAUNCHES = 8
+DMK_FLAG_QUEUE_LAUNCHES = 16
 NOALLOC_MAX_BYTES = 128 << 20
 
 # exported symbols, in the order of include/dmk.h

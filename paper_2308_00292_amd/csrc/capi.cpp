@@ -195,6 +195,8 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
     if (o.leaf_max < 0 || o.max_depth < 0 || o.max_depth > kb) throw Error{DMK_ERR_ARG, "bad leaf_max/max_depth"};
     if (kernel == DMK_YUKAWA && !(o.lambda > 0 && std::isfinite(o.lambda)))
         throw Error{DMK_ERR_ARG, "the Yukawa kernel needs lambda > 0"};
+    if ((o.flags & DMK_FLAG_LEVEL_LAUNCHES) && (o.flags & DMK_FLAG_QUEUE_LAUNCHES))
+        throw Error{DMK_ERR_ARG, "DMK_FLAG_LEVEL_LAUNCHES and DMK_FLAG_QUEUE_LAUNCHES exclude each other"};
     auto *P = new Plan();
     try {
         P->dim = dim;
@@ -208,6 +210,7 @@ dmk_plan_t make_plan(int dim, dmk_kernel kernel, double tol, int32_t nprob, cons
         P->leaf_max = o.leaf_max ? o.leaf_max : 64;
         P->max_depth = o.max_depth ? o.max_depth : std::min(dflt, kb);
         P->flags = o.flags;
+        P->queued = queue_schedule(dim, o.flags);
         P->n = n;
         build_tables(prm, &P->tab, dim, kernel == DMK_POWER2 ? 2 : 0);
         P->p = prm.p;

@@ -174,6 +174,7 @@ struct Plan {
     int32_t *anc_tbeg = nullptr;   // [nanc+1] offsets into anc_tgt
     int32_t *anc_tgt = nullptr;    // [nleaf points] targets grouped by the anchor of their leaf
     int32_t *proxy_slot = nullptr, *local_slot = nullptr, *psi_slot = nullptr;
+    bool queued = false;           // upward pass and local values queue-fed (else one launch per level)
     int32_t *l_fout_up = nullptr;  // l_fout with the levels in reverse (finest first): the upward queue
     int32_t *q_fail = nullptr;     // waits of the queue-fed kernels that ran out of polls (sticky)
     int64_t nfout = 0, nfin = 0, nanc = 0, nleaf = 0, max_fin_level = 0, max_fout_level = 0;
@@ -302,6 +303,15 @@ struct WsItem {
     void **ptr;
     size_t bytes;
 };
+// the schedule of the upward pass and the local values: queue-fed over all
+// levels by default in 3-D, one launch per level by default in 2-D; the
+// flags force either
+inline bool queue_schedule(int dim, uint64_t flags)
+{
+    if (flags & DMK_FLAG_QUEUE_LAUNCHES) return true;
+    if (flags & DMK_FLAG_LEVEL_LAUNCHES) return false;
+    return dim == 3;
+}
 void workspace_layout(Plan *P, std::vector<WsItem> &items);
 void workspace_layout2(Plan *P, std::vector<WsItem> &items);
 // dalloc's the workspace (not for DMK_FLAG_NO_WORKSPACE point plans); sets ws_bytes

@@ -1703,32 +1703,6 @@ static void launch_residual(const Dev<T> &D, Plan *Pl, hipStream_t s)
         launch_residual_deg<T, 1>(D, Pl, g, b, lds, s);
 }
 
-// workgroups of a kernel that fit on the device at once (the persistent grid
-// of a queue-fed kernel; more would only wait for a slot)
-template <typename K>
-static unsigned resident_blocks(K kernel, int nthreads, size_t lds)
-{
-    int dev = 0, ncu = 0, per = 0;
-    DMK_HIP(hipGetDevice(&dev));
-    DMK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    DMK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nthreads, lds));
-    return (unsigned)std::max(1, per) * (unsigned)std::max(1, ncu);
-}
-
-// the longest wait of a queue-fed kernel, in ticks of the device's
-// constant-rate wall clock: 200 ms, far beyond any real wait (a whole stage
-// takes a few ms), so that a wait that runs out means a fault
-static int64_t queue_wait_ticks()
-{
-    static const int64_t ticks = [] {
-        int dev = 0, khz = 0;
-        DMK_HIP(hipGetDevice(&dev));
-        DMK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-        return (int64_t)std::max(khz, 1000) * 200;
-    }();
-    return ticks;
-}
-
 // persistent grids of the queue-fed kernels (set with the LDS limits, before
 // any graph capture)
 template <typename T, int P, int NF>
@@ -1754,23 +1728,6 @@ static void set_lds_attrs()
     attrs = true;
 }
 
-// the queues' control words: [0, 4 + nfout) the upward pass's head and flags,
-// [4 + nfout, 8 + nfout + nanc) the local values' (cleared by the stage's
-// reset kernel before each of its launches)
-static WorkQ upward_queue(Plan *Pl)
-{
-    return WorkQ{Pl->qctl, Pl->qctl + 4, Pl->l_fout_up, Pl->proxy_slot, Pl->q_fail, (int32_t)Pl->nfout,
-                 queue_wait_ticks()};
-}
-static WorkQ local_queue(Plan *Pl)
-{
-    int32_t *base = Pl->qctl + 4 + Pl->nfout;
-    return WorkQ{base, base + 4, Pl->l_anc, Pl->local_slot, Pl->q_fail, (int32_t)Pl->nanc, queue_wait_ticks()};
-}
-static void reset_queue(int32_t *p, int64_t n, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)std::min<int64_t>(nblk(n), 1024)), dim3(256), 0, s, p, n);
-}
 
 // Root window W_0, outgoing and incoming plane waves and the local values of
 // the anchors: the stages between the proxy charges and the evaluation at
@@ -1811,7 +1768,7 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     }
     // local values of the anchors, coarse to fine: one queue-fed launch over
     // all levels, or one launch per level
-    if (Pl->nanc && !(Pl->flags & DMK_FLAG_LEVEL_LAUNCHES)) {
+    if (Pl->nanc && Pl->queued) {
         StageScope t(Pl, s, DMK_STAGE_PW2GRID);
         const WorkQ q = local_queue(Pl);
         reset_queue(q.head, 4 + Pl->nanc, s);
@@ -1842,7 +1799,7 @@ static void enqueue_chain(Plan *Pl, hipStream_t s)
     const int L = Pl->nlevels;
     // Step 2: upward pass, finest level first: one queue-fed launch over all
     // levels, or one launch per level
-    if (Pl->nfout && !(Pl->flags & DMK_FLAG_LEVEL_LAUNCHES)) {
+    if (Pl->nfout && Pl->queued) {
         StageScope t(Pl, s, DMK_STAGE_UPWARD);
         const WorkQ q = upward_queue(Pl);
         reset_queue(q.head, 4 + Pl->nfout, s);
@@ -1850,7 +1807,7 @@ static void enqueue_chain(Plan *Pl, hipStream_t s)
                            dim3(TPB),
                            C::lds_up(), s, D, q);
     }
-    for (int l = L - 1; l >= 0 && (Pl->flags & DMK_FLAG_LEVEL_LAUNCHES); --l) {
+    for (int l = L - 1; l >= 0 && !Pl->queued; --l) {
         int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
         if (!m) continue;
         StageScope t(Pl, s, DMK_STAGE_UPWARD);
@@ -2051,7 +2008,7 @@ void workspace_layout(Plan *P, std::vector<WsItem> &items)
     add(&P->phi, 2 * P->nfout * nm, el);
     add(&P->psi, 2 * P->nfin * nm, el);
     add(&P->w0vals, P->nprob * p3, el);
-    add(&P->qctl, 8 + P->nfout + P->nanc, 4);
+    add(&P->qctl, queue_ctl_words(P), 4);
 }
 
 void alloc_workspace(Plan *P)

@@ -32,6 +32,7 @@
 #include "dmk_internal.h"
 #include "kfun.h"
 #include "lagrange.h"
+#include "queue.h"
 
 namespace dmk {
 
@@ -51,6 +52,7 @@ struct Dev2 {
     const int32_t *pstart, *pcount, *child0, *parent, *col, *proxy_slot, *local_slot, *psi_slot, *blevel,
         *anchor, *bprob;
     const uint8_t *bflags;
+    const uint8_t *anc_read;  // per anchor slot: its values are read by a finer anchor
     const double *bcenter;
     const T *c2p, *epw, *wd0, *gcheb, *gmono, *xcheb, *bary;  // gmono: m(x) as a power series in u = 2x^2 - 1
     const double *ew64, *ww64, *xcheb64, *bary64;
@@ -86,12 +88,12 @@ __device__ inline double box_side(int level) { return ldexp(1.0, -level); }
 template <int P>
 constexpr int nown() { return (P * P + TPB - 1) / TPB; }
 
-template <typename T, int P>
-__global__ void __launch_bounds__(TPB) k_upward2(Dev2<T> D, const int32_t *list)
+// COH: the box's F_out children were computed by the same launch (queue-fed)
+template <typename T, int P, bool COH>
+__device__ __forceinline__ void upward2_box(const Dev2<T> &D, const int32_t B)
 {
     constexpr int P2 = P * P, NO = nown<P>(), CH = 64;
-    __shared__ T Am[2 * P2], xc[P], bw[P], tmp[P2], L0[CH * P], L1[CH * P], qq[CH];
-    const int32_t B = list[blockIdx.x];
+    __shared__ T Am[2 * P2], xc[P], bw[P], tmp[P2], cs[P2], L0[CH * P], L1[CH * P], qq[CH];
     for (int t = threadIdx.x; t < 2 * P2; t += TPB) Am[t] = D.c2p[t];
     for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
     T acc[NO];
@@ -105,14 +107,15 @@ __global__ void __launch_bounds__(TPB) k_upward2(Dev2<T> D, const int32_t *list)
         const int cnt = D.pcount[C];
         if (cnt == 0) continue;
         if (D.bflags[C] & 2) {
-            const T *src = D.proxy + (int64_t)D.proxy_slot[C] * P2;
             const T *Ax = Am + ((k >> 1) & 1) * P2, *Ay = Am + (k & 1) * P2;
             __syncthreads();
-            // tmp[i0][a1] = sum_i1 src[i0][i1] Ay[a1][i1]
+            copy_to_lds<COH, TPB>(cs, D.proxy + (int64_t)D.proxy_slot[C] * P2, P2);
+            __syncthreads();
+            // tmp[i0][a1] = sum_i1 cs[i0][i1] Ay[a1][i1]
             for (int t = threadIdx.x; t < P2; t += TPB) {
                 const int i0 = t / P, a1 = t % P;
                 T s = T(0);
-                for (int i1 = 0; i1 < P; ++i1) s += src[i0 * P + i1] * Ay[a1 * P + i1];
+                for (int i1 = 0; i1 < P; ++i1) s += cs[i0 * P + i1] * Ay[a1 * P + i1];
                 tmp[t] = s;
             }
             __syncthreads();
@@ -157,8 +160,31 @@ __global__ void __launch_bounds__(TPB) k_upward2(Dev2<T> D, const int32_t *list)
 #pragma unroll
     for (int o = 0; o < NO; ++o) {
         const int t = threadIdx.x + o * TPB;
-        if (t < P2) dst[t] = acc[o];
+        if (t < P2) st_c<COH>(dst + t, acc[o]);
     }
+}
+
+// one level's F_out boxes, one workgroup per box
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_upward2(Dev2<T> D, const int32_t *list)
+{
+    upward2_box<T, P, false>(D, list[blockIdx.x]);
+}
+
+// the F_out boxes of every level, finest first, from the work queue (a box
+// waits for its F_out children)
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) k_upward2_q(Dev2<T> D, WorkQ q)
+{
+    queue_loop(
+        q,
+        [&](int32_t B) {
+            if (threadIdx.x < 4) {
+                const int32_t C = D.child0[B] + threadIdx.x;
+                if (D.pcount[C] > 0 && (D.bflags[C] & 2)) wait_done(q, C);
+            }
+        },
+        [&](int32_t B) { upward2_box<T, P, true>(D, B); });
 }
 
 // --------------------------------------------------------------- root W_0
@@ -407,13 +433,13 @@ __global__ void __launch_bounds__(TPB) k_pwshift2(Dev2<T> D, const int32_t *oct_
 }
 
 // ------------------------------------------------ local values (anchors)
-template <typename T, int P, int NF>
-__global__ void __launch_bounds__(TPB) k_local_pw2(Dev2<T> D, const int32_t *list, int level)
+// COH: the anchor above the box was computed by the same launch (queue-fed)
+template <typename T, int P, int NF, bool COH>
+__device__ __forceinline__ void local2_box(const Dev2<T> &D, const int32_t B, const int level)
 {
     constexpr int P2 = P * P, NN = 2 * NF + 1, NH = NF + 1, NO = nown<P>();
     __shared__ T Er[NN * P], Ei[NN * P], xc[P], bw[P], v[P2], tmp[P2], Mx[P2], My[P2];
     __shared__ T gr[P * NH], gi[P * NH];
-    const int32_t B = list[blockIdx.x];
     for (int t = threadIdx.x; t < NN * P; t += TPB) {
         Er[t] = D.epw[2 * t];
         Ei[t] = D.epw[2 * t + 1];
@@ -440,8 +466,7 @@ __global__ void __launch_bounds__(TPB) k_local_pw2(Dev2<T> D, const int32_t *lis
                 (D.bcenter[2 * (int64_t)B + d] + 0.5 * sB * D.xcheb64[i] - D.bcenter[2 * (int64_t)A + d]) * (2.0 / sA);
             lagrange_row<T>(P, xc, bw, (T)xi, (d == 0 ? Mx : My) + i * P);
         }
-        const T *src = D.local + (int64_t)D.local_slot[A] * P2;
-        for (int t = threadIdx.x; t < P2; t += TPB) v[t] = src[t];
+        copy_to_lds<COH, TPB>(v, D.local + (int64_t)D.local_slot[A] * P2, P2);
         __syncthreads();
         // tmp[a0][i1] = sum_a1 v[a0][a1] My[i1][a1]
         for (int t = threadIdx.x; t < P2; t += TPB) {
@@ -495,12 +520,42 @@ __global__ void __launch_bounds__(TPB) k_local_pw2(Dev2<T> D, const int32_t *lis
             }
         }
     }
+    // a finer anchor of the same launch reads these values: past the caches
     T *dst = D.local + (int64_t)D.local_slot[B] * P2;
+    if (COH && D.anc_read[D.local_slot[B]]) {
 #pragma unroll
-    for (int o = 0; o < NO; ++o) {
-        const int t = threadIdx.x + o * TPB;
-        if (t < P2) dst[t] = acc[o];
+        for (int o = 0; o < NO; ++o) {
+            const int t = threadIdx.x + o * TPB;
+            if (t < P2) st_c<true>(dst + t, acc[o]);
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+            const int t = threadIdx.x + o * TPB;
+            if (t < P2) dst[t] = acc[o];
+        }
     }
+}
+
+// one level's anchors, one workgroup per box
+template <typename T, int P, int NF>
+__global__ void __launch_bounds__(TPB) k_local_pw2(Dev2<T> D, const int32_t *list, int level)
+{
+    local2_box<T, P, NF, false>(D, list[blockIdx.x], level);
+}
+
+// the anchors of every level, coarsest first, from the work queue (a box
+// below a root waits for the anchor of its parent); one box per workgroup
+// (a box loop held more registers and halved the occupancy)
+template <typename T, int P, int NF>
+__global__ void __launch_bounds__(TPB) k_local_pw2_q(Dev2<T> D, WorkQ q)
+{
+    queue_item(
+        q,
+        [&](int32_t B) {
+            if (threadIdx.x == 0 && D.blevel[B] > 0) wait_done(q, D.anchor[D.parent[B]]);
+        },
+        [&](int32_t B) { local2_box<T, P, NF, true>(D, B, D.blevel[B]); });
 }
 
 // ------------------------------------------------------------ leaf targets
@@ -832,7 +887,7 @@ Dev2<T> make_dev2(Plan *P)
     D.pstart = P->pstart; D.pcount = P->pcount; D.child0 = P->child0; D.parent = P->parent; D.col = P->colleague;
     D.proxy_slot = P->proxy_slot; D.local_slot = P->local_slot; D.psi_slot = P->psi_slot; D.blevel = P->blevel;
     D.anchor = P->anchor; D.bprob = P->bprob;
-    D.bflags = P->bflags; D.bcenter = P->bcenter;
+    D.bflags = P->bflags; D.bcenter = P->bcenter; D.anc_read = P->anc_read;
     const bool f64 = sizeof(T) == 8;
     D.c2p = (const T *)(f64 ? (void *)P->d_c2p : (void *)P->f_c2p);
     D.epw = (const T *)(f64 ? (void *)P->d_epw : (void *)P->f_epw);
@@ -873,6 +928,17 @@ void allow_lds2(K kernel, size_t bytes)
 // Points a root leaf may hold (it is anterpolated inside the root kernel).
 static int root_leaf_points(const Plan *Pl) { return (int)std::min<int64_t>(Pl->n, Pl->leaf_max); }
 
+// persistent grid of the queue-fed upward kernel (set before any capture)
+template <typename T, int P>
+struct QGrid2 {
+    static inline unsigned upward = 0;
+    static void set()
+    {
+        if (!upward) upward = resident_blocks(k_upward2_q<T, P>, TPB, 0);
+        (void)queue_wait_ticks();
+    }
+};
+
 template <typename T, int P, int NF>
 static void enqueue_core2(Plan *Pl, hipStream_t s, hipStream_t side)
 {
@@ -885,7 +951,15 @@ static void enqueue_core2(Plan *Pl, hipStream_t s, hipStream_t side)
         launch_residual2<T>(D, Pl, side);
         DMK_HIP(hipEventRecord(Pl->ev_join, side));
     }
-    for (int l = L - 1; l >= 0; --l) {
+    const bool levels = !Pl->queued;
+    if (Pl->nfout && !levels) {  // one queue-fed launch over all levels
+        StageScope t(Pl, s, DMK_STAGE_UPWARD);
+        const WorkQ q = upward_queue(Pl);
+        reset_queue(q.head, 4 + Pl->nfout, s);
+        hipLaunchKernelGGL((k_upward2_q<T, P>), dim3((unsigned)std::min<int64_t>(Pl->nfout, QGrid2<T, P>::upward)),
+                           dim3(TPB), 0, s, D, q);
+    }
+    for (int l = L - 1; l >= 0 && levels; --l) {
         int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
         if (!m) continue;
         StageScope t(Pl, s, DMK_STAGE_UPWARD);
@@ -909,7 +983,13 @@ static void enqueue_core2(Plan *Pl, hipStream_t s, hipStream_t side)
         hipLaunchKernelGGL((k_pwshift2<T>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
                            Pl->oct_level, Pl->oct_prob, Pl->noct, nchunk);
     }
-    for (int l = 0; l < L; ++l) {
+    if (Pl->nanc && !levels) {  // one queue-fed launch over all levels
+        StageScope t(Pl, s, DMK_STAGE_PW2GRID);
+        const WorkQ q = local_queue(Pl);
+        reset_queue(q.head, 4 + Pl->nanc, s);
+        hipLaunchKernelGGL((k_local_pw2_q<T, P, NF>), dim3((unsigned)Pl->nanc), dim3(TPB), 0, s, D, q);
+    }
+    for (int l = 0; l < L && levels; ++l) {
         int64_t nan = ll.anc_off[l + 1] - ll.anc_off[l];
         if (!nan) continue;
         StageScope t(Pl, s, DMK_STAGE_PW2GRID);
@@ -938,6 +1018,7 @@ static void run_eval2_t(Plan *Pl, const double *charges, double *pot, double *fa
     const int64_t n = Pl->n;
     // the root kernel stages a root leaf's points: at most leaf_max of them
     allow_lds2(k_root2<T, P>, lds_root2(Pl->tab, root_leaf_points(Pl)));
+    QGrid2<T, P>::set();
     {
         StageScope t(Pl, s, DMK_STAGE_GATHER);
         hipLaunchKernelGGL(k_gather_q2, dim3(nblk(n)), dim3(TPB), 0, s, charges, Pl->perm, n, Pl->qs);
@@ -1009,6 +1090,7 @@ void workspace_layout2(Plan *P, std::vector<WsItem> &items)
     add(&P->phi, 2 * P->nfout * nm, el);
     add(&P->psi, 2 * P->nfin * nm, el);
     add(&P->w0vals, P->nprob * p2, el);
+    add(&P->qctl, queue_ctl_words(P), 4);
 }
 
 }  // namespace dmk

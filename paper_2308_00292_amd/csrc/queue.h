@@ -34,7 +34,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+
+#include "dmk_internal.h"
 
 namespace dmk {
 
@@ -162,6 +165,33 @@ __device__ __forceinline__ void queue_item(const WorkQ &q, Wait wait, Body body)
     if (threadIdx.x == 0) __hip_atomic_store(q.done + q.slot[b], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ---------------------------------------------------------------- host
+// workgroups of a kernel that fit on the device at once (the persistent grid
+// of a queue-fed kernel; more would only wait for a slot)
+template <typename K>
+inline unsigned resident_blocks(K kernel, int nthreads, size_t lds)
+{
+    int dev = 0, ncu = 0, per = 0;
+    DMK_HIP(hipGetDevice(&dev));
+    DMK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    DMK_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nthreads, lds));
+    return (unsigned)std::max(1, per) * (unsigned)std::max(1, ncu);
+}
+
+// the longest wait of a queue-fed kernel, in ticks of the device's
+// constant-rate wall clock: 200 ms, far beyond any real wait (a whole stage
+// takes a few ms), so that a wait that runs out means a fault
+inline int64_t queue_wait_ticks()
+{
+    static const int64_t ticks = [] {
+        int dev = 0, khz = 0;
+        DMK_HIP(hipGetDevice(&dev));
+        DMK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        return (int64_t)std::max(khz, 1000) * 200;
+    }();
+    return ticks;
+}
+
 namespace {
 // clears the heads and flags of the queues (a kernel, so that it can sit in a
 // captured graph)
@@ -170,5 +200,28 @@ __global__ void __launch_bounds__(256) k_queue_reset(int32_t *p, int64_t n)
     for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) p[i] = 0;
 }
 }  // namespace
+
+// clears n control words (head and flags) of a queue
+static inline void reset_queue(int32_t *p, int64_t n, hipStream_t s)
+{
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_queue_reset, dim3((unsigned)std::max<int64_t>(nb, 1)), dim3(256), 0, s, p, n);
+}
+
+// the queues' control words (workspace, 8 + nfout + nanc ints): [0, 4 + nfout)
+// the upward pass's head and flags, [4 + nfout, 8 + nfout + nanc) the local
+// values' (cleared by the stage's reset kernel before each of its launches)
+inline WorkQ upward_queue(Plan *Pl)
+{
+    return WorkQ{Pl->qctl, Pl->qctl + 4, Pl->l_fout_up, Pl->proxy_slot, Pl->q_fail, (int32_t)Pl->nfout,
+                 queue_wait_ticks()};
+}
+inline WorkQ local_queue(Plan *Pl)
+{
+    int32_t *base = Pl->qctl + 4 + Pl->nfout;
+    return WorkQ{base, base + 4, Pl->l_anc, Pl->local_slot, Pl->q_fail, (int32_t)Pl->nanc, queue_wait_ticks()};
+}
+inline int64_t queue_ctl_words(const Plan *Pl) { return 8 + Pl->nfout + Pl->nanc; }
+
 
 }  // namespace dmk

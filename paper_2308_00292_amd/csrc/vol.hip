@@ -1042,7 +1042,10 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         P->precision = o.precision;
         P->leaf_max = q3;
         P->max_depth = 20;
-        P->flags = o.flags & DMK_FLAG_LEVEL_LAUNCHES;
+        if ((o.flags & DMK_FLAG_LEVEL_LAUNCHES) && (o.flags & DMK_FLAG_QUEUE_LAUNCHES))
+            throw Error{DMK_ERR_ARG, "DMK_FLAG_LEVEL_LAUNCHES and DMK_FLAG_QUEUE_LAUNCHES exclude each other"};
+        P->flags = o.flags & (DMK_FLAG_LEVEL_LAUNCHES | DMK_FLAG_QUEUE_LAUNCHES);
+        P->queued = queue_schedule(3, P->flags);
         P->n = n;
         build_tables(prm, &P->tab, 3);
         gauss_tables(&P->tab, tol);

@@ -1,7 +1,8 @@
-"""The queue-fed upward and local stages (one persistent launch per stage
-over every level, boxes taken from a device work queue in dependency order)
-against the same stages launched one level at a time
-(DMK_FLAG_LEVEL_LAUNCHES).  Each box is computed by the same code in both
+"""The queue-fed upward and local stages (one launch per stage over every
+level, boxes taken from a device work queue in dependency order) against
+the same stages launched one level at a time (DMK_FLAG_LEVEL_LAUNCHES; in
+2-D, where per-level launches are the default, DMK_FLAG_QUEUE_LAUNCHES
+forces the queue).  Each box is computed by the same code in both
 schedules, so potentials must agree bit for bit; no queue wait may run out
 of its poll bound.  The default (queue) schedule is the one every other GPU
 test compares against the oracle.
@@ -93,3 +94,44 @@ def test_queue_volume():
             assert vp.info()["queue_timeouts"] == 0
             vp.close()
         assert np.array_equal(outs[1], outs[0])
+
+
+P2_CASES = [("gauss2d_60k", "log"), ("gauss2d_60k", "k0"), ("batch2d", "log")]
+
+
+@pytest.mark.parametrize("name,kn", P2_CASES, ids=[f"{a}-{b}" for a, b in P2_CASES])
+def test_queue_2d(name, kn):
+    import paper_2308_00292_amd as dmk
+    if name == "batch2d":
+        off, pts, q = dmk_inputs.batch_2d(48, 907, nmin=300, nmax=20000)
+        extra = dict(offsets=off, max_depth=20)
+    else:
+        pts, q = dmk_inputs.gaussian_2d(60000, 906)
+        extra = {}
+    kern = dmk.DMK_LAPLACE if kn == "log" else dmk.DMK_YUKAWA
+    dev = torch.device("cuda:0")
+    tp, tq = torch.from_numpy(pts).to(dev), torch.from_numpy(q).to(dev)
+    for precision in (dmk.DMK_FP64, dmk.DMK_MIXED):
+        outs = []
+        # 2-D plans launch per level by default: the queue is forced here
+        for fl in (0, dmk.DMK_FLAG_QUEUE_LAUNCHES, dmk.DMK_FLAG_QUEUE_LAUNCHES | dmk.DMK_FLAG_BATCHED):
+            _say(f"[queue 2-D {name} {kn} prec={precision} flags={fl}]")
+            plan = dmk.Plan(tp, tol=1e-6, leaf_max=32, precision=precision, flags=fl, kernel=kern, lam=10.0, **extra)
+            res = [plan.eval(tq).cpu().numpy() for _ in range(2)]
+            torch.cuda.synchronize()
+            assert plan.info()["queue_timeouts"] == 0
+            if name != "batch2d":
+                assert plan.info()["nlevels"] >= 8
+            plan.close()
+            assert np.array_equal(res[1], res[0])
+            outs.append(res[0])
+        assert np.array_equal(outs[1], outs[0]) and np.array_equal(outs[2], outs[0])
+
+
+def test_schedule_flags_exclusive():
+    import paper_2308_00292_amd as dmk
+    pts, q = dmk_inputs.uniform_cube(2000, 908)
+    with pytest.raises(dmk.DmkError) as e:
+        dmk.Plan(torch.from_numpy(pts).to("cuda:0"), tol=1e-6,
+                 flags=dmk.DMK_FLAG_LEVEL_LAUNCHES | dmk.DMK_FLAG_QUEUE_LAUNCHES)
+    assert e.value.status == -1

@@ -35,6 +35,7 @@
 #include <unordered_set>
 
 #include "dmk_internal.h"
+#include "queue.h"
 #include "tiles.h"
 
 namespace dmk {
@@ -414,8 +415,9 @@ struct VolLds {
 };
 
 // proxy charges of the non-leaf boxes of one level
-template <typename T, int P, int Q>
-__global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *list)
+// COH: the box's F_out children were computed by the same launch (queue-fed)
+template <typename T, int P, int Q, bool COH>
+__device__ __forceinline__ void vol_upward_box(const VDev<T> &D, const int32_t Pb)
 {
     constexpr int P2 = P * P, P3 = P2 * P, Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int RM = Tiles<P>::RM, RN = Tiles<P>::RN, ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN;
@@ -424,7 +426,6 @@ __global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *li
     T *Am = sm;              // [2][p][p] child -> parent
     T *Vm = Am + 2 * P2;     // [2][p][q] leaf density -> parent
     T *w0 = Vm + 2 * P * Q;  // work
-    const int32_t Pb = list[blockIdx.x];
     for (int t = threadIdx.x; t < 2 * P2; t += TPB) Am[t] = D.c2p[t];
     for (int t = threadIdx.x; t < 2 * P * Q; t += TPB) Vm[t] = D.v1[t];
     T acc[RM][RN];
@@ -441,7 +442,7 @@ __global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *li
             const T *src = D.proxy + (int64_t)D.proxy_slot[C] * P3;
             T *t1 = w0, *t2 = w0 + P3;
             __syncthreads();
-            for (int t = threadIdx.x; t < P3; t += TPB) t2[t] = src[t];
+            copy_to_lds<COH, TPB>(t2, src, P3);
             __syncthreads();
             gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Am + bz * P2, 0, 1, P, t1, 0, P, 1);
             __syncthreads();
@@ -465,7 +466,30 @@ __global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *li
             gemm_regs<T, RM, RN>(P, P2, Q, Vm + bx * P * Q, Q, 1, t2, P2, 1, acc);
         }
     }
-    store_tiles<T, P>(acc, D.proxy + (int64_t)D.proxy_slot[Pb] * P3);
+    store_tiles<T, P, COH>(acc, D.proxy + (int64_t)D.proxy_slot[Pb] * P3);
+}
+
+// one level's non-leaf boxes, one workgroup per box
+template <typename T, int P, int Q>
+__global__ void __launch_bounds__(TPB) k_vol_upward(VDev<T> D, const int32_t *list)
+{
+    vol_upward_box<T, P, Q, false>(D, list[blockIdx.x]);
+}
+
+// the non-leaf boxes of every level, finest first, from the work queue (a
+// box waits for its non-leaf children)
+template <typename T, int P, int Q>
+__global__ void __launch_bounds__(TPB) k_vol_upward_q(VDev<T> D, WorkQ q)
+{
+    queue_loop(
+        q,
+        [&](int32_t Pb) {
+            if (threadIdx.x < 8) {
+                const int32_t C = D.child0[Pb] + threadIdx.x;
+                if (D.bflags[C] & 2) wait_done(q, C);
+            }
+        },
+        [&](int32_t Pb) { vol_upward_box<T, P, Q, true>(D, Pb); });
 }
 
 // far field at the nodes of each leaf from its anchor's local values
@@ -792,6 +816,7 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
     static bool attrs = false;
     if (!attrs) {
         vol_allow_lds(k_vol_upward<T, P, Q>, LD::up(sizeof(T)));
+        vol_allow_lds(k_vol_upward_q<T, P, Q>, LD::up(sizeof(T)));
         vol_allow_lds(k_vol_leaf<T, P, Q>, LD::leaf(sizeof(T)));
         vol_allow_lds(k_vol_near<T, Q>, LD::near(sizeof(T)));
         attrs = true;
@@ -799,7 +824,15 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
     VDev<T> D = make_vdev<T>(Pl);
     D.rho = rho;
     const auto &ll = Pl->ll;
-    for (int l = Pl->nlevels - 1; l >= 0; --l) {
+    if (Pl->nfout && Pl->queued) {  // one queue-fed launch over all levels
+        StageScope t(Pl, s, DMK_STAGE_UPWARD);
+        const WorkQ q = upward_queue(Pl);
+        reset_queue(q.head, 4 + Pl->nfout, s);
+        static const unsigned nres = resident_blocks(k_vol_upward_q<T, P, Q>, TPB, LD::up(sizeof(T)));
+        hipLaunchKernelGGL((k_vol_upward_q<T, P, Q>), dim3((unsigned)std::min<int64_t>(Pl->nfout, nres)), dim3(TPB),
+                           LD::up(sizeof(T)), s, D, q);
+    }
+    for (int l = Pl->nlevels - 1; l >= 0 && !Pl->queued; --l) {
         const int64_t m = ll.fout_off[l + 1] - ll.fout_off[l];
         if (!m) continue;
         StageScope t(Pl, s, DMK_STAGE_UPWARD);

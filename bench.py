@@ -69,8 +69,9 @@ VOL_SEED, VOL_RHO_SCALE, VOL_MAX_LEVEL = 5, 3e-5, 16
 # precision and kernel, and valid only for the kernel source it was measured
 # on (digest of csrc/eval.hip); otherwise traffic is reported as null.
 TRAFFIC = {
-    ("cfg3_clustered_10m", "mixed", "k_local_mfma"): (1.0730e+09, "cb8f9cdc80f5b5c5"),
-    ("cfg3_clustered_10m", "mixed", "k_upward"): (3.2140e+08, "cb8f9cdc80f5b5c5"),
+    ("cfg3_clustered_10m", "mixed", "k_local_mfma_q"): (1.4598e+10, "203818613417994d"),
+    ("cfg3_clustered_10m", "mixed", "k_upward_q"): (5.1550e+09, "203818613417994d"),
+    ("cfg3_clustered_10m", "mixed", "k_pwshift"): (1.7185e+10, "203818613417994d"),
 }
 
 

@@ -250,185 +250,178 @@ __global__ void __launch_bounds__(TPB) k_upward_q(Dev<T> D, WorkQ q)
 // translation factor exp(i h m.(c_B - c_S)) = w^{-(m.delta)}, w = e^{2 pi i/3}
 // (h_l s_l = 2 pi/3), factors per axis, so the 27-term sum of each child runs
 // as three passes of 3-term sums (z, then y, then x) shared by the siblings:
-// 64 loads per mode for 8 boxes instead of up to 27 per box.  One thread per
-// mode; a block covers TPB consecutive modes of one group.  Blocks are dealt
-// out so that each XCD gets a contiguous range of groups, and within it the
+// 64 loads per mode for 8 boxes instead of up to 27 per box.  Each 3-term sum
+// is a x + y + conj(a) z with a = w^{-m_k} for the axis, which takes 8
+// operations in the form below (a complex multiply alone takes 6).
+//
+// Each source is read by every group that has it in its 4x4x4 block (6.6
+// groups on average for clustered points), mostly from L2.  The stage waits
+// on loads: a wave's loads complete in order, so a batch waits for its
+// slowest, often an HBM miss, and what keeps the memory system busy is the
+// number of resident waves rather than the size of each wave's batches.  So
+// the kernel keeps its registers few (8 waves per SIMD in FP32, 5 in FP64)
+// and its batches small (one or two rows of 4 sources), does no arithmetic
+// beyond those sums (one thread per mode), keeps the box lists and the tests
+// on them in scalar registers (they are the same for the whole workgroup,
+// read through the scalar cache), addresses its loads from a scalar base,
+// and loads nothing for absent sources or empty rows and slabs.
+//
+// A block covers TPB consecutive modes of one group.  Blocks are dealt out
+// so that each XCD gets a contiguous range of groups, and within it the
 // blocks run chunk by chunk over that range: neighbouring groups share most
 // of their sources, and a source's chunk is then read again by the next few
 // groups while it is still in that XCD's L2.
 template <typename T>
 struct Cx { T r, i; };
 
+// a x + y + conj(a) z, a = (c, s)
 template <typename T>
-__device__ inline Cx<T> cmul(Cx<T> a, Cx<T> f) { return {a.r * f.r - a.i * f.i, a.r * f.i + a.i * f.r}; }
+__device__ __forceinline__ Cx<T> sum3(T c, T s, Cx<T> x, Cx<T> y, Cx<T> z)
+{
+    const T u = x.r + z.r, v = x.i - z.i, p = x.i + z.i, q = x.r - z.r;
+    return {fma(c, u, fma(-s, v, y.r)), fma(c, p, fma(s, q, y.i))};
+}
 
+// w^{-k} = (cos, sin) for any integer k
 template <typename T>
-__device__ inline Cx<T> cj(Cx<T> a) { return {a.r, -a.i}; }
-
-template <typename T>
-__device__ inline Cx<T> root3(int k)  // w^{-k}, any integer k
+__device__ __forceinline__ void root3(int k, T &c, T &s)
 {
     k %= 3;
     if (k < 0) k += 3;
     const T s3 = T(0.86602540378443864676);
-    if (k == 0) return {T(1), T(0)};
-    if (k == 1) return {T(-0.5), -s3};
-    return {T(-0.5), s3};
+    c = k == 0 ? T(1) : T(-0.5);
+    s = k == 0 ? T(0) : (k == 1 ? -s3 : s3);
 }
 
-// MPT consecutive modes per thread, loaded and stored as one vector (the
-// plane-wave sets are padded to a multiple of 64 elements, so the vectors
-// are aligned); modes past the last one compute on padding and store nothing
-// that is read.
-template <typename T, int MPT>
-__global__ void __launch_bounds__(TPB) k_pwshift(Dev<T> D, const int32_t *oct_dst, const int32_t *oct_src,
-                                                 const int32_t *oct_level, int64_t noct, int nchunk)
+// the value at byte offset `off` (per thread) of the `bytes` bytes at a
+// workgroup-uniform base, through a buffer descriptor built in scalar
+// registers (no per-thread address arithmetic; 0x20000: 32-bit data format)
+template <typename T>
+__device__ __forceinline__ T ld_buf(const T *base, uint32_t bytes, uint32_t off)
 {
-    typedef T vec __attribute__((ext_vector_type(MPT)));
-    __shared__ int32_t src[64];
-    __shared__ int32_t dst[8];
-    __shared__ int colany[16];
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(base), (short)0, (int)bytes, 0x00020000);
+    T v;
+    if constexpr (sizeof(T) == 4) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &u, sizeof(T));
+    } else {
+        static_assert(sizeof(T) == 8, "float or double");
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        __builtin_memcpy(&v, &u, sizeof(T));
+    }
+    return v;
+}
+
+// RB source rows (4 RB boxes) are loaded at a time, all issued before the
+// first is used.
+template <typename T, int RB>
+__global__ void __launch_bounds__(TPB, sizeof(T) == 4 ? 8 : 5)
+    k_pwshift(Dev<T> D, const int32_t *oct_dst, const int32_t *oct_src, const int32_t *oct_level, int64_t noct,
+              int nchunk)
+{
+    static_assert(4 % RB == 0, "rows per batch");
     // grid = 8 * per * nchunk; blocks go to the XCDs round-robin
     const int64_t per = (noct + 7) / 8;  // groups per XCD
     const int64_t Lb = blockIdx.x / 8;
     const int chunk = (int)(Lb / per);
     const int64_t o = (int64_t)(blockIdx.x % 8) * per + Lb % per;
-    if (o >= noct || chunk >= nchunk) return;  // whole block: before any barrier
-    if (threadIdx.x < 64) src[threadIdx.x] = oct_src[o * 64 + threadIdx.x];
-    if (threadIdx.x < 8) dst[threadIdx.x] = oct_dst[o * 8 + threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x < 16) {
-        const int c = threadIdx.x;
-        colany[c] = (src[4 * c] >= 0) | (src[4 * c + 1] >= 0) | (src[4 * c + 2] >= 0) | (src[4 * c + 3] >= 0);
-    }
-    __syncthreads();
     const int nn = D.nn, nh = D.nh, nf = D.nf;
-    const int64_t nmode = (int64_t)nh * nn * nn, nm = D.pwstride;
-    const int64_t e0 = ((int64_t)chunk * TPB + threadIdx.x) * MPT;
-    if (e0 >= nmode) return;
-    // per-axis factors for delta = -1 and +1 (delta = 0 is 1);
-    // e = (m1 * nh + m3) * nn + m2
-    // (the factor for delta = +1 is the conjugate of the one for -1)
-    Cx<T> xm[MPT], ym[MPT], zm[MPT];
+    const int nmode = nh * nn * nn;
+    const int e = chunk * TPB + (int)threadIdx.x;
+    if (o >= noct || e >= nmode) return;
+    const int32_t *src = oct_src + o * 64, *dst = oct_dst + o * 8;
+    const int64_t nm = D.pwstride;
+    const uint32_t eb = (uint32_t)e * sizeof(T);         // byte offset of this thread's mode in a set
+    const uint32_t hbytes = (uint32_t)(nm * sizeof(T));  // the real part, then the imaginary part
+    // per-axis factors a = w^{-m}; e = (m1 * nh + m3) * nn + m2
+    T xc, xs, yc, ys, zc, zs;
+    root3<T>(-(e / (nn * nh) - nf), xc, xs);
+    root3<T>(-(e % nn - nf), yc, ys);
+    root3<T>(-((e / nn) % nh), zc, zs);
+    const Cx<T> zero = {T(0), T(0)};
+    // acc[tx][ty][tz]: the x pass, accumulated slab by slab (slab gx enters
+    // tx = gx with factor a, tx = gx - 1 with 1 and tx = gx - 2 with conj(a))
+    Cx<T> acc[2][2][2];
 #pragma unroll
-    for (int u = 0; u < MPT; ++u) {
-        const int64_t e = min(e0 + u, nmode - 1);
-        const int m2 = (int)(e % nn) - nf, m3 = (int)((e / nn) % nh), m1 = (int)(e / (nn * nh)) - nf;
-        xm[u] = root3<T>(-m1);
-        ym[u] = root3<T>(-m2);
-        zm[u] = root3<T>(-m3);
-    }
-    Cx<T> acc[MPT][2][2][2];
+    for (int tx = 0; tx < 2; ++tx)
 #pragma unroll
-    for (int u = 0; u < MPT; ++u)
+        for (int ty = 0; ty < 2; ++ty)
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) acc[u][a][b][c] = {T(0), T(0)};
-    const T *phi = D.phi;
+            for (int tz = 0; tz < 2; ++tz) acc[tx][ty][tz] = zero;
 #pragma unroll
     for (int gx = 0; gx < 4; ++gx) {
-        // z then y pass for this x slab: Y[ty][tz]
-        Cx<T> Y[MPT][2][2];
+        // the slab is empty when all 16 of its entries are negative
+        int32_t all = -1;
 #pragma unroll
-        for (int u = 0; u < MPT; ++u)
+        for (int k = 0; k < 16; ++k) all &= src[gx * 16 + k];
+        if (all < 0) continue;
+        Cx<T> Z[4][2];  // z pass of each row: Z[gy][tz]
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+        for (int gy0 = 0; gy0 < 4; gy0 += RB) {
+            Cx<T> f[RB][4];
+            bool rempty[RB];  // rows with no source are not loaded
 #pragma unroll
-                for (int b = 0; b < 2; ++b) Y[u][a][b] = {T(0), T(0)};
-        bool any = false;
+            for (int a = 0; a < RB; ++a) {
+                const int32_t *rw = src + (gx * 4 + gy0 + a) * 4;
+                rempty[a] = (rw[0] & rw[1] & rw[2] & rw[3]) < 0;
+                if (rempty[a]) continue;
 #pragma unroll
-        for (int gy = 0; gy < 4; ++gy) {
-            if (!colany[gx * 4 + gy]) continue;
-            any = true;
-            Cx<T> f[4][MPT];
-#pragma unroll
-            for (int gz = 0; gz < 4; ++gz) {
-                const int32_t sl = src[(gx * 4 + gy) * 4 + gz];
-                vec vr = (vec)T(0), vi = (vec)T(0);
-                if (sl >= 0) {
-                    const T *q = phi + 2 * (int64_t)sl * nm + e0;
-                    vr = *reinterpret_cast<const vec *>(q);
-                    vi = *reinterpret_cast<const vec *>(q + nm);
+                for (int gz = 0; gz < 4; ++gz) {
+                    const int32_t sl = rw[gz];
+                    f[a][gz] = zero;
+                    if (sl < 0) continue;
+                    const T *q = D.phi + 2 * (int64_t)sl * nm;
+                    f[a][gz] = {ld_buf(q, 2 * hbytes, eb), ld_buf(q, 2 * hbytes, eb + hbytes)};
                 }
-#pragma unroll
-                for (int u = 0; u < MPT; ++u) f[gz][u] = {vr[u], vi[u]};
             }
 #pragma unroll
-            for (int u = 0; u < MPT; ++u) {
-                // Z[tz] = sum over gz = tz .. tz+2 of w^{-m3 (gz - tz - 1)} f[gz]
-                Cx<T> z0 = cmul(f[0][u], zm[u]), z1 = cmul(f[3][u], cj(zm[u]));
-                z0.r += f[1][u].r + cmul(f[2][u], cj(zm[u])).r;
-                z0.i += f[1][u].i + cmul(f[2][u], cj(zm[u])).i;
-                z1.r += f[2][u].r + cmul(f[1][u], zm[u]).r;
-                z1.i += f[2][u].i + cmul(f[1][u], zm[u]).i;
-                // ty = gy - 1 - delta: gy contributes to ty = 0 (delta = gy - 1) and ty = 1 (delta = gy - 2)
-                if (gy <= 2) {
-                    const Cx<T> fy = (gy == 0) ? ym[u] : (gy == 1) ? Cx<T>{T(1), T(0)} : cj(ym[u]);
-                    const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
-                    Y[u][0][0].r += a0.r; Y[u][0][0].i += a0.i;
-                    Y[u][0][1].r += a1.r; Y[u][0][1].i += a1.i;
+            for (int a = 0; a < RB; ++a) {
+                if (rempty[a]) {
+                    Z[gy0 + a][0] = zero;
+                    Z[gy0 + a][1] = zero;
+                    continue;
                 }
-                if (gy >= 1) {
-                    const Cx<T> fy = (gy == 1) ? ym[u] : (gy == 2) ? Cx<T>{T(1), T(0)} : cj(ym[u]);
-                    const Cx<T> a0 = cmul(z0, fy), a1 = cmul(z1, fy);
-                    Y[u][1][0].r += a0.r; Y[u][1][0].i += a0.i;
-                    Y[u][1][1].r += a1.r; Y[u][1][1].i += a1.i;
-                }
+                Z[gy0 + a][0] = sum3(zc, zs, f[a][0], f[a][1], f[a][2]);
+                Z[gy0 + a][1] = sum3(zc, zs, f[a][1], f[a][2], f[a][3]);
             }
         }
-        if (!any) continue;
-        // x pass
 #pragma unroll
-        for (int u = 0; u < MPT; ++u) {
-            if (gx <= 2) {
-                const Cx<T> fx = (gx == 0) ? xm[u] : (gx == 1) ? Cx<T>{T(1), T(0)} : cj(xm[u]);
+        for (int ty = 0; ty < 2; ++ty)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const Cx<T> v = cmul(Y[u][b][c], fx);
-                        acc[u][0][b][c].r += v.r;
-                        acc[u][0][b][c].i += v.i;
-                    }
+            for (int tz = 0; tz < 2; ++tz) {
+                const Cx<T> Y = sum3(yc, ys, Z[ty][tz], Z[ty + 1][tz], Z[ty + 2][tz]);
+                const Cx<T> aY = {xc * Y.r - xs * Y.i, xc * Y.i + xs * Y.r};  // a Y
+                const Cx<T> cY = {xc * Y.r + xs * Y.i, xc * Y.i - xs * Y.r};  // conj(a) Y
+                if (gx <= 1) {
+                    acc[gx][ty][tz].r += aY.r;
+                    acc[gx][ty][tz].i += aY.i;
+                }
+                if (gx >= 1 && gx <= 2) {
+                    acc[gx - 1][ty][tz].r += Y.r;
+                    acc[gx - 1][ty][tz].i += Y.i;
+                }
+                if (gx >= 2) {
+                    acc[gx - 2][ty][tz].r += cY.r;
+                    acc[gx - 2][ty][tz].i += cY.i;
+                }
             }
-            if (gx >= 1) {
-                const Cx<T> fx = (gx == 1) ? xm[u] : (gx == 2) ? Cx<T>{T(1), T(0)} : cj(xm[u]);
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const Cx<T> v = cmul(Y[u][b][c], fx);
-                        acc[u][1][b][c].r += v.r;
-                        acc[u][1][b][c].i += v.i;
-                    }
-            }
-        }
     }
-    T w[MPT];
+    // the level's weight, and the stores
     // 1/r: w_l = 2^l w_0, 1/r^2: 4^l w_0 (scale invariance); Yukawa: the level's own table
     const T scale = D.ywd ? T(1) : (T)ldexp(1.0, D.wshift * oct_level[o]);
     const T *wt = D.ywd ? D.ywd + (int64_t)oct_level[o] * D.ywd_stride : D.wd0;
-#pragma unroll
-    for (int u = 0; u < MPT; ++u) w[u] = (e0 + u < nmode) ? wt[e0 + u] * scale : T(0);
+    const T w = wt[e] * scale;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int32_t d = dst[t];
         if (d < 0) continue;
-        vec vr, vi;
-#pragma unroll
-        for (int u = 0; u < MPT; ++u) {
-            const Cx<T> v = acc[u][t >> 2][(t >> 1) & 1][t & 1];
-            vr[u] = v.r * w[u];
-            vi[u] = v.i * w[u];
-        }
-        T *out = D.psi + 2 * (int64_t)d * nm + e0;
+        const Cx<T> v = acc[t >> 2][(t >> 1) & 1][t & 1];
+        char *out = reinterpret_cast<char *>(D.psi + 2 * (int64_t)d * nm) + eb;
         // streaming stores: Psi is read again only by the local stage, long
         // after, so it should not displace the sources held in L2
-        __builtin_nontemporal_store(vr, reinterpret_cast<vec *>(out));
-        __builtin_nontemporal_store(vi, reinterpret_cast<vec *>(out + nm));
+        __builtin_nontemporal_store(v.r * w, reinterpret_cast<T *>(out));
+        __builtin_nontemporal_store(v.i * w, reinterpret_cast<T *>(out + hbytes));
     }
 }
 
@@ -1759,11 +1752,11 @@ static void enqueue_far(Plan *Pl, hipStream_t s)
     }
     if (Pl->noct) {
         StageScope t(Pl, s, DMK_STAGE_PWSHIFT);
-        constexpr int MPT = sizeof(T) == 4 ? 2 : 1;  // modes per thread
         const int64_t nmode = (int64_t)Pl->tab.nh * Pl->tab.nn * Pl->tab.nn;
-        const int nchunk = (int)((nmode + TPB * MPT - 1) / (TPB * MPT));
+        const int nchunk = (int)((nmode + TPB - 1) / TPB);
+        constexpr int RB = sizeof(T) == 4 ? 2 : 1;  // source rows per batch of loads
         const int64_t nb = 8 * ((Pl->noct + 7) / 8) * nchunk;
-        hipLaunchKernelGGL((k_pwshift<T, MPT>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
+        hipLaunchKernelGGL((k_pwshift<T, RB>), dim3((unsigned)nb), dim3(TPB), 0, s, D, Pl->oct_dst, Pl->oct_src,
                            Pl->oct_level, Pl->noct, nchunk);
     }
     // local values of the anchors, coarse to fine: one queue-fed launch over

@@ -397,43 +397,48 @@ def main():
     value = n / (ms_step * 1e-3)
     log(f"[bench] {ms_step:.3f} ms/step -> {value:.4g} points/s")
 
-    # per-stage breakdown: HIP events around every launch (eager launches)
-    plan.stage_timing(True)
-    nst = max(2, min(args.steps, 5))
-    for _ in range(nst):
-        plan.eval(tq, out)
-    torch.cuda.synchronize()
-    stage_ms, launches = plan.stage_times()
-    plan.stage_timing(False)
-    flops, byts = plan.stage_work()
-    dom = max(stage_ms, key=lambda k: stage_ms[k])
-    avg_ms = stage_ms[dom] / max(1, launches[dom])
-    per_launch = (byts[dom] if STAGE_BOUND[dom] == "hbm" else flops[dom]) * nst / max(1, launches[dom])
-    if STAGE_BOUND[dom] == "hbm":
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        peak, unit = PEAK["hbm"]
-    else:
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
-    kname = STAGE_KERNEL[dom] if offsets is None else STAGE_KERNEL2[dom]
-    kname = per_level(kname, args)
-    bound = STAGE_BOUND[dom]
-    if "_mfma" in kname:
-        bound = "mfma"  # matrix-core products: the dense MFMA peaks equal the vector ones (FP32 157.3, FP64 78.6)
-    tr = TRAFFIC.get((args.workload, args.precision, kname))
-    traffic = tr[0] if (tr is not None and tr[1] == eval_src_digest()) else None
-    roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic, "kernel": kname, "stage": dom,
-            "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / nst}
-    stages = {}
-    for k in stage_ms:
-        ms = stage_ms[k] / nst
-        ent = {"ms": round(ms, 4)}
-        if ms > 0 and flops[k] > 0:
-            ent["tflops"] = round(flops[k] / (ms * 1e-3) / 1e12, 3)
-        if ms > 0 and byts[k] > 0:
-            ent["gbps"] = round(byts[k] / (ms * 1e-3) / 1e9, 1)
-        stages[k] = ent
+    def breakdown(plan, out, prec, pname):
+        """per-stage times (HIP events around every launch, eager) and the
+        roofline of the dominant stage's kernel"""
+        plan.stage_timing(True)
+        nst = max(2, min(args.steps, 5))
+        for _ in range(nst):
+            plan.eval(tq, out)
+        torch.cuda.synchronize()
+        stage_ms, launches = plan.stage_times()
+        plan.stage_timing(False)
+        flops, byts = plan.stage_work()
+        dom = max(stage_ms, key=lambda k: stage_ms[k])
+        avg_ms = stage_ms[dom] / max(1, launches[dom])
+        per_launch = (byts[dom] if STAGE_BOUND[dom] == "hbm" else flops[dom]) * nst / max(1, launches[dom])
+        if STAGE_BOUND[dom] == "hbm":
+            achieved = per_launch / (avg_ms * 1e-3) / 1e9
+            peak, unit = PEAK["hbm"]
+        else:
+            achieved = per_launch / (avg_ms * 1e-3) / 1e12
+            peak, unit = PEAK["alu64" if prec == dmk.DMK_FP64 else "alu32"]
+        kname = STAGE_KERNEL[dom] if offsets is None else STAGE_KERNEL2[dom]
+        kname = per_level(kname, args)
+        bound = STAGE_BOUND[dom]
+        if "_mfma" in kname:
+            bound = "mfma"  # matrix-core products: the dense MFMA peaks equal the vector ones (FP32 157.3, FP64 78.6)
+        tr = TRAFFIC.get((args.workload, pname, kname))
+        traffic = tr[0] if (tr is not None and tr[1] == eval_src_digest()) else None
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": traffic, "kernel": kname, "stage": dom,
+                "avg_launch_ms": avg_ms, "launches_per_step": launches[dom] / nst}
+        stages = {}
+        for k in stage_ms:
+            ms = stage_ms[k] / nst
+            ent = {"ms": round(ms, 4)}
+            if ms > 0 and flops[k] > 0:
+                ent["tflops"] = round(flops[k] / (ms * 1e-3) / 1e12, 3)
+            if ms > 0 and byts[k] > 0:
+                ent["gbps"] = round(byts[k] / (ms * 1e-3) / 1e9, 1)
+            stages[k] = ent
+        return roof, stages
+
+    roof, stages = breakdown(plan, out, prec, args.precision)
     u_main = out.cpu().numpy()
     queue_timeouts = plan.info()["queue_timeouts"]
     plan.close()
@@ -446,9 +451,11 @@ def main():
                        flags=lvl)
         ms64, out64 = timed(p64, args.steps, args.warmup)
         u64 = out64.cpu().numpy()
+        roof64, stages64 = breakdown(p64, out64, dmk.DMK_FP64, "fp64")
         p64.close()
         del p64
-        plain = {"points_per_s": n / (ms64 * 1e-3), "ms_per_step": ms64}
+        plain = {"points_per_s": n / (ms64 * 1e-3), "ms_per_step": ms64, "roofline": roof64,
+                 "stage_ms_per_step": stages64}
         log(f"[bench] plain FP64 {ms64:.3f} ms/step -> {plain['points_per_s']:.4g} points/s")
 
     # sampled parity against direct summation by the oracle

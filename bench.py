@@ -497,7 +497,7 @@ def main():
                                 else "queue-fed over all levels"),
                    "kernel": ("1/(4 pi r)" if offsets is None else
                               ("-log(r)/(2 pi)" if kern == dmk.DMK_LAPLACE else "K_0(10 r)")),
-                   "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"],
+                   "levels": info["nlevels"], "boxes": info["nbox"], "leaves": info["nleaf"], "residual_candidate_pairs": info["npairs"],
                    "p": info["p"], "nf": info["nf"], "t_plan_s": round(t_plan, 3),
                    "end_to_end_points_per_s": n / (t_plan + ms_step * 1e-3),
                    "sampled_rel_l2_vs_direct": err, "stage_ms_per_step": stages,

@@ -39,7 +39,6 @@ namespace dmk {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int RLIST2 = 1024;  // longest residual list (checked at plan time)
 
 template <typename T>
 struct Dev2 {
@@ -595,6 +594,107 @@ __global__ void __launch_bounds__(TPB) k_leaf2(Dev2<T> D, const int32_t *anc, co
 //   R_l(r) = -log(r^2)/(4 pi) - l log(2)/(2 pi) - m(r/s_l)
 // and at r = 0 the far field's own share is removed:
 //   -(m(0) + l log(2)/(2 pi) + C_b) times the charge.
+// The residual's source staging, shared by the two kernels below.  The
+// running source counts of a leaf's gather list and the entries' first points
+// and levels sit in dynamic LDS (loff: L + 1 entries, then lbeg, llev: L each;
+// sized at launch to the plan's longest list), so that staging a source is one
+// dependent global load.  Only the sources that can reach the bounding box of
+// the chunk's targets are staged: the residual vanishes beyond the source box
+// side s, and a source farther than s from the box is farther than s from
+// every target (the box distance is formed with the same rounded operations
+// as the pair distances, so it is not larger than any pair's; the margin keeps
+// the comparison safe).
+
+// bounding box of the chunk's targets (wave 0 holds them all: tch <= 64):
+// bb = {xlo, ylo, xhi, yhi}
+template <typename T>
+__device__ __forceinline__ void target_box2(T xt, T yt, T *bb)
+{
+    if ((threadIdx.x >> 6) != 0) return;
+    T b[4] = {xt, yt, -xt, -yt};
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) b[k] = min(b[k], __shfl_xor(b[k], d));
+    if ((threadIdx.x & 63) == 0) {
+        bb[0] = b[0];
+        bb[1] = b[1];
+        bb[2] = -b[2];
+        bb[3] = -b[3];
+    }
+}
+
+// stage the next sources of the list, from `cursor` on, that can reach the box
+// (rounds of TPB entries while a whole round still fits); returns how many
+template <typename T, int RCAP>
+__device__ __forceinline__ int stage_sources2(const Dev2<T> &D, const int32_t *loff, const int32_t *lbeg,
+                                              const int32_t *llev, int L, int nsrc, int &cursor, double cx, double cy,
+                                              const T *bb, int *wtot, T *sx, T *sy, T *sq, T *sis2, T *slc)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int cnt = 0;
+    __syncthreads();
+    while (cursor < nsrc && cnt <= RCAP - TPB) {
+        const int g = cursor + threadIdx.x;
+        bool keep = false;
+        T ux = T(0), uy = T(0), uq = T(0), uis2 = T(0), ulc = T(0);
+        if (g < nsrc) {
+            int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (loff[mid] <= g) lo = mid; else hi = mid - 1;
+            }
+            const int64_t j = (int64_t)lbeg[lo] + (g - loff[lo]);
+            const int lev = llev[lo];
+            ux = (T)(D.X[j] - cx);
+            uy = (T)(D.Y[j] - cy);
+            uq = (T)D.qs[j];
+            uis2 = (T)ldexp(1.0, 2 * lev);
+            ulc = D.kern ? (T)lev : (T)(-lev * M_LN2 / (2.0 * M_PI));
+            const T ex = max(max(bb[0] - ux, T(0)), ux - bb[2]);
+            const T ey = max(max(bb[1] - uy, T(0)), uy - bb[3]);
+            const T d2 = ex * ex + ey * ey;
+            keep = d2 * uis2 < T(1.0001);
+        }
+        const uint64_t m = __ballot(keep);
+        if (lane == 0) wtot[wv] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < TPB / 64; ++k) {
+            const int c = wtot[k];
+            before += k < wv ? c : 0;
+            total += c;
+        }
+        if (keep) {
+            const int pos = cnt + before + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            sx[pos] = ux;
+            sy[pos] = uy;
+            sq[pos] = uq;
+            sis2[pos] = uis2;
+            slc[pos] = ulc;
+        }
+        cnt += total;
+        cursor += TPB;
+        __syncthreads();
+    }
+    return cnt;
+}
+
+// the list's running counts, first points and levels into dynamic LDS
+template <typename T>
+__device__ __forceinline__ void load_list2(const Dev2<T> &D, const int32_t *nl_src, const int32_t *nl_pre, int32_t l0,
+                                           int L, int32_t *loff, int32_t *lbeg, int32_t *llev)
+{
+    for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
+    for (int k = threadIdx.x; k < L; k += TPB) {
+        const int32_t Tb = nl_src[l0 + k];
+        lbeg[k] = D.pstart[Tb];
+        llev[k] = D.blevel[Tb];
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *leaves, const int32_t *nl_off,
                                                    const int32_t *nl_src, const int32_t *nl_pre)
@@ -602,7 +702,9 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
     constexpr int RCAP = sizeof(T) == 8 ? 768 : 1024;
     constexpr int YLEV = 32;  // levels of a K_0 problem's tables held in LDS
     __shared__ T sx[RCAP], sy[RCAP], sq[RCAP], sis2[RCAP], slc[RCAP];
-    __shared__ int32_t loff[RLIST2 + 1];
+    extern __shared__ __align__(16) int32_t loff[];  // then lbeg, llev (load_list2)
+    __shared__ int wtot[TPB / 64];
+    __shared__ T tbb[4];
     __shared__ T gc[48];
     __shared__ T yc[YLEV * 48];
     __shared__ T yself[YLEV];
@@ -620,7 +722,8 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
     } else {
         for (int t = threadIdx.x; t <= deg; t += TPB) gc[t] = D.gcheb[t];
     }
-    for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
+    int32_t *lbeg = loff + L + 1, *llev = lbeg + L;
+    load_list2(D, nl_src, nl_pre, l0, L, loff, lbeg, llev);
     __syncthreads();
     const int nsrc = loff[L];
     const double cx = D.bcenter[2 * (int64_t)B], cy = D.bcenter[2 * (int64_t)B + 1];
@@ -637,27 +740,11 @@ __global__ void __launch_bounds__(TPB) k_residual2(Dev2<T> D, const int32_t *lea
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
         const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy);
+        target_box2(xt, yt, tbb);
         double acc = 0.0;
-        for (int pb = 0; pb < nsrc; pb += RCAP) {
-            const int cnt = min(RCAP, nsrc - pb);
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < cnt; idx += TPB) {
-                const int g = pb + idx;
-                int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (loff[mid] <= g) lo = mid; else hi = mid - 1;
-                }
-                const int32_t Tb = nl_src[l0 + lo];
-                const int64_t j = D.pstart[Tb] + (g - loff[lo]);
-                const int lev = D.blevel[Tb];
-                sx[idx] = (T)(D.X[j] - cx);
-                sy[idx] = (T)(D.Y[j] - cy);
-                sq[idx] = (T)D.qs[j];
-                sis2[idx] = (T)ldexp(1.0, 2 * lev);
-                slc[idx] = D.kern ? (T)lev : (T)(-lev * M_LN2 / (2.0 * M_PI));
-            }
-            __syncthreads();
+        for (int cursor = 0; cursor < nsrc;) {
+            const int cnt =
+                stage_sources2<T, RCAP>(D, loff, lbeg, llev, L, nsrc, cursor, cx, cy, tbb, wtot, sx, sy, sq, sis2, slc);
             T pacc = T(0);
             if (D.kern) {
                 // K_0(lambda r) - M_l(r) for 0 < r < s_l; -M_l(0) at r = 0
@@ -744,7 +831,9 @@ __global__ void __launch_bounds__(TPB) k_residual2_log(Dev2<T> D, const int32_t 
     } stg;
     T *sx = stg.s.x, *sy = stg.s.y, *sq = stg.s.q, *sis2 = stg.s.is2, *slc = stg.s.lc;
     double *part = stg.part;
-    __shared__ int32_t loff[RLIST2 + 1];
+    extern __shared__ __align__(16) int32_t loff[];  // then lbeg, llev (load_list2)
+    __shared__ int wtot[TPB / 64];
+    __shared__ T tbb[4];
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.pstart[B];
     const int nt = D.pcount[B];
@@ -753,7 +842,8 @@ __global__ void __launch_bounds__(TPB) k_residual2_log(Dev2<T> D, const int32_t 
     T gm[DEG + 1];
 #pragma unroll
     for (int k = 0; k <= DEG; ++k) gm[k] = (k <= D.gdeg) ? D.gmono[k] : T(0);
-    for (int k = threadIdx.x; k <= L; k += TPB) loff[k] = nl_pre[l0 + blockIdx.x + k];
+    int32_t *lbeg = loff + L + 1, *llev = lbeg + L;
+    load_list2(D, nl_src, nl_pre, l0, L, loff, lbeg, llev);
     __syncthreads();
     const int nsrc = loff[L];
     const int32_t prob = D.bprob[B];
@@ -768,27 +858,11 @@ __global__ void __launch_bounds__(TPB) k_residual2_log(Dev2<T> D, const int32_t 
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
         const T xt = (T)(D.X[it] - cx), yt = (T)(D.Y[it] - cy);
+        target_box2(xt, yt, tbb);
         double acc = 0.0;
-        for (int pb = 0; pb < nsrc; pb += RCAP) {
-            const int cnt = min(RCAP, nsrc - pb);
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < cnt; idx += TPB) {
-                const int g = pb + idx;
-                int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (loff[mid] <= g) lo = mid; else hi = mid - 1;
-                }
-                const int32_t Tb = nl_src[l0 + lo];
-                const int64_t j = D.pstart[Tb] + (g - loff[lo]);
-                const int lev = D.blevel[Tb];
-                sx[idx] = (T)(D.X[j] - cx);
-                sy[idx] = (T)(D.Y[j] - cy);
-                sq[idx] = (T)D.qs[j];
-                sis2[idx] = (T)ldexp(1.0, 2 * lev);
-                slc[idx] = (T)(-lev * M_LN2 / (2.0 * M_PI));
-            }
-            __syncthreads();
+        for (int cursor = 0; cursor < nsrc;) {
+            const int cnt =
+                stage_sources2<T, RCAP>(D, loff, lbeg, llev, L, nsrc, cursor, cx, cy, tbb, wtot, sx, sy, sq, sis2, slc);
             T pacc = T(0);
             constexpr int RB = 4;
             for (int j0 = split; j0 < cnt && split < nsplit; j0 += RB * nsplit) {
@@ -835,8 +909,9 @@ template <typename T>
 static void launch_residual2(const Dev2<T> &D, Plan *Pl, hipStream_t s)
 {
     const dim3 g((unsigned)Pl->nleaf), b(TPB);
+    const size_t lds = sizeof(int32_t) * 3 * ((size_t)Pl->nl_max + 1);  // loff, lbeg, llev
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, g, b, 0, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
+        hipLaunchKernelGGL(kern, g, b, lds, s, D, Pl->l_leaf, Pl->nl_off, Pl->nl_src, Pl->nl_pre);
     };
     if (D.kern) go(k_residual2<T>);
     else if (D.gdeg <= 9) go(k_residual2_log<T, 9>);

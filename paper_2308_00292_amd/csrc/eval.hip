@@ -1295,6 +1295,9 @@ __global__ void __launch_bounds__(TPB) k_residual_y3(Dev<T> D, const int32_t *le
     T *sx = stg.s.x, *sy = stg.s.y, *sz = stg.s.z, *sq = stg.s.q, *sis = stg.s.is;
     double *part = stg.part;
     extern __shared__ __align__(16) int32_t loff[];
+    __shared__ int wtot[TPB / 64];
+    __shared__ T tbb[6];  // the target chunk's bounding box: low corner, high corner
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int32_t B = leaves[blockIdx.x];
     const int64_t t0 = D.tstart[B];  // the leaf's targets
     const int nt = D.tcount[B];
@@ -1323,27 +1326,74 @@ __global__ void __launch_bounds__(TPB) k_residual_y3(Dev<T> D, const int32_t *le
         const bool active = (tbase + tl) < nt;
         const int64_t it = t0 + tbase + (active ? tl : 0);
         const T xt = (T)(D.Xt[it] - cx), yt = (T)(D.Yt[it] - cy), zt = (T)(D.Zt[it] - cz);
-        double acc = 0.0;
-        for (int pb = 0; pb < nsrc; pb += RCAP) {
-            const int cnt = min(RCAP, nsrc - pb);
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < cnt; idx += TPB) {
-                const int g = pb + idx;
-                int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (loff[mid] <= g) lo = mid; else hi = mid - 1;
+        // the chunk's bounding box (wave 0 holds all its targets: tch <= 64)
+        if (wv == 0) {
+            T b[6] = {xt, yt, zt, -xt, -yt, -zt};
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) b[q] = min(b[q], __shfl_xor(b[q], d));
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    tbb[q] = b[q];
+                    tbb[3 + q] = -b[3 + q];
                 }
-                const int64_t j = (int64_t)lbeg[lo] + (g - loff[lo]);
-                const int lev = llev[lo];
-                sx[idx] = (T)(D.X[j] - cx);
-                sy[idx] = (T)(D.Y[j] - cy);
-                sz[idx] = (T)(D.Z[j] - cz);
-                sq[idx] = (T)D.qs[j];
-                sis[idx] = (T)ldexp(1.0, lev);
-                slev[idx] = (int8_t)lev;
             }
+        }
+        double acc = 0.0;
+        for (int cursor = 0; cursor < nsrc;) {
+            // stage the sources that can reach the box, as in k_residual
+            int cnt = 0;
             __syncthreads();
+            while (cursor < nsrc && cnt <= RCAP - TPB) {
+                const int g = cursor + threadIdx.x;
+                bool keep = false;
+                T ux = T(0), uy = T(0), uz = T(0), uq = T(0), uis = T(0);
+                int ulev = 0;
+                if (g < nsrc) {
+                    int lo = 0, hi = L - 1;  // entry k with loff[k] <= g < loff[k+1]
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (loff[mid] <= g) lo = mid; else hi = mid - 1;
+                    }
+                    const int64_t j = (int64_t)lbeg[lo] + (g - loff[lo]);
+                    ulev = llev[lo];
+                    ux = (T)(D.X[j] - cx);
+                    uy = (T)(D.Y[j] - cy);
+                    uz = (T)(D.Z[j] - cz);
+                    uq = (T)D.qs[j];
+                    uis = (T)ldexp(1.0, ulev);
+                    const T ex = max(max(tbb[0] - ux, T(0)), ux - tbb[3]);
+                    const T ey = max(max(tbb[1] - uy, T(0)), uy - tbb[4]);
+                    const T ez = max(max(tbb[2] - uz, T(0)), uz - tbb[5]);
+                    const T d2 = ex * ex + ey * ey + ez * ez;
+                    keep = d2 * uis * uis < T(1.0001);
+                }
+                const uint64_t m = __ballot(keep);
+                if (lane == 0) wtot[wv] = __popcll(m);
+                __syncthreads();
+                int before = 0, total = 0;
+#pragma unroll
+                for (int q = 0; q < TPB / 64; ++q) {
+                    const int c = wtot[q];
+                    before += q < wv ? c : 0;
+                    total += c;
+                }
+                if (keep) {
+                    const int pos = cnt + before + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+                    sx[pos] = ux;
+                    sy[pos] = uy;
+                    sz[pos] = uz;
+                    sq[pos] = uq;
+                    sis[pos] = uis;
+                    slev[pos] = (int8_t)ulev;
+                }
+                cnt += total;
+                cursor += TPB;
+                __syncthreads();
+            }
             T pacc = T(0);
             for (int j = split; j < cnt && split < nsplit; j += nsplit) {
                 const T dx = xt - sx[j], dy = yt - sy[j], dz = zt - sz[j];

@@ -87,11 +87,19 @@ struct Dev {
 };
 
 // ------------------------------------------------------------------ upward
-// points per anterpolation chunk: three Lagrange rows per point in the
-// kernel's work area of 2 p^3 values
-template <int P> constexpr int up_chunk()
+// x slabs of a child's proxy grid per round of the child -> parent mode
+// products: all p, except FP64 at p = 18, whose two p^3 work buffers (93 KB)
+// leave room for one block per CU, against two with 2 x 6 p^2 (at p = 15 and
+// 9 the registers, not the LDS, set the occupancy)
+template <typename T, int P> constexpr int up_slabs() { return sizeof(T) == 8 && P == 18 ? 6 : P; }
+
+// the upward kernel's work area (values): two buffers of up_slabs x p^2
+template <typename T, int P> constexpr int up_work() { return 2 * up_slabs<T, P>() * P * P; }
+
+// points per anterpolation chunk: three Lagrange rows per point in the work area
+template <typename T, int P> constexpr int up_chunk()
 {
-    return (2 * P * P * P) / (3 * P) < 128 ? (2 * P * P * P) / (3 * P) : 128;
+    return up_work<T, P>() / (3 * P) < 128 ? up_work<T, P>() / (3 * P) : 128;
 }
 
 // COH: the box's children were computed by the same launch (queue-fed)
@@ -99,14 +107,14 @@ template <typename T, int P, bool COH>
 __device__ __forceinline__ void upward_box(const Dev<T> &D, const int32_t Pb)
 {
     constexpr int P2 = P * P, P3 = P2 * P, RM = Tiles<P>::RM, RN = Tiles<P>::RN;
-    constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, CH = up_chunk<P>();
+    constexpr int ZM = Tiles<P>::ZM, ZN = Tiles<P>::ZN, CH = up_chunk<T, P>(), GS = up_slabs<T, P>();
     constexpr int MT = (P + RM - 1) / RM, NT = (P2 + RN - 1) / RN;  // tile grid of the p x p^2 accumulator
     extern __shared__ __align__(16) unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
     T *Am = sm;              // 2 p^2 child->parent matrices
     T *xc = Am + 2 * P2;     // nodes
     T *bw = xc + P;          // barycentric weights
-    T *w0 = bw + P;          // work area of 2 p^3
+    T *w0 = bw + P;          // work area of up_work values
     for (int t = threadIdx.x; t < 2 * P2; t += TPB) Am[t] = D.c2p[t];
     for (int t = threadIdx.x; t < P; t += TPB) { xc[t] = D.xcheb[t]; bw[t] = D.bary[t]; }
     T acc[RM][RN];
@@ -128,21 +136,25 @@ __device__ __forceinline__ void upward_box(const Dev<T> &D, const int32_t Pb)
         const int cnt = D.pcount[C];
         if (cnt == 0) continue;
         if (D.bflags[C] & 2) {
-            // c2p: three mode products with A_sigma (sigma from the child's position)
+            // c2p: three mode products with A_sigma (sigma from the child's
+            // position), GS x slabs (i0) at a time
             const T *src = D.proxy + (int64_t)D.proxy_slot[C] * P3;
-            T *t1 = w0, *t2 = w0 + P3;
+            T *t1 = w0, *t2 = w0 + GS * P2;
             const T *Ax = Am + ((k >> 2) & 1) * P2, *Ay = Am + ((k >> 1) & 1) * P2, *Az = Am + (k & 1) * P2;
-            __syncthreads();
-            copy_to_lds<COH, TPB>(t2, src, P3);
-            __syncthreads();
-            // z: t1[(i0 i1)][a2] = sum_i2 t2[(i0 i1)][i2] Az[a2][i2]
-            gemm<T, ZM, ZN, false>(1, P2, P, P, t2, 0, P, 1, Az, 0, 1, P, t1, 0, P, 1);
-            __syncthreads();
-            // y: t2[i0][a1][a2] = sum_i1 Ay[a1][i1] t1[i0][i1][a2]
-            gemm<T, ZM, ZN, false>(P, P, P, P, Ay, 0, P, 1, t1, P2, P, 1, t2, P2, P, 1);
-            __syncthreads();
-            // x: acc[a0][r] += sum_i0 Ax[a0][i0] t2[i0][r]
-            gemm_regs<T, RM, RN>(P, P2, P, Ax, P, 1, t2, P2, 1, acc);
+            for (int i00 = 0; i00 < P; i00 += GS) {
+                const int g = min(GS, P - i00);
+                __syncthreads();
+                copy_to_lds<COH, TPB>(t2, src + i00 * P2, g * P2);
+                __syncthreads();
+                // z: t1[(i0 i1)][a2] = sum_i2 t2[(i0 i1)][i2] Az[a2][i2]
+                gemm<T, ZM, ZN, false>(1, g * P, P, P, t2, 0, P, 1, Az, 0, 1, P, t1, 0, P, 1);
+                __syncthreads();
+                // y: t2[i0][a1][a2] = sum_i1 Ay[a1][i1] t1[i0][i1][a2]
+                gemm<T, ZM, ZN, false>(g, P, P, P, Ay, 0, P, 1, t1, P2, P, 1, t2, P2, P, 1);
+                __syncthreads();
+                // x: acc[a0][r] += sum_i0 Ax[a0][i0] t2[i0][r] over the round's slabs
+                gemm_regs<T, RM, RN>(P, P2, g, Ax + i00, P, 1, t2, P2, 1, acc);
+            }
         } else {
             if (threadIdx.x == 0) {
                 rlo[nr] = D.pstart[C];
@@ -1715,7 +1727,7 @@ __global__ void __launch_bounds__(TPB) k_leaf_mfma(Dev<T> D, const int32_t *anc,
 template <typename T, int P, int NF>
 struct Cfg {
     static constexpr int P2 = P * P, P3 = P2 * P, NN = 2 * NF + 1, NH = NF + 1;
-    static size_t lds_up() { return sizeof(T) * (2 * P2 + 2 * P + 2 * P3); }
+    static size_t lds_up() { return sizeof(T) * (2 * P2 + 2 * P + up_work<T, P>()); }
 };
 
 template <typename T>

@@ -79,7 +79,9 @@ class _Pow2(C.Structure):
 class VParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("q", C.c_int), ("sigma0", C.c_double), ("p", C.c_int), ("nf", C.c_int),
                 ("nw", C.c_int), ("hw", C.c_double), ("nleg", C.c_int), ("tau_a", C.c_double),
-                ("tpan_gl", C.c_int), ("tpan_w", C.c_double)]
+                ("tpan_gl", C.c_int), ("tpan_w", C.c_double), ("split", C.c_int), ("c", C.c_double),
+                ("theta1", C.c_double), ("nfit", C.c_int), ("fit_t", C.c_double * 32), ("fit_w", C.c_double * 32),
+                ("fit_err", C.c_double)]
 
 
 class _VTree(C.Structure):
@@ -205,6 +207,8 @@ def lib():
         L.orc_gsplit_w0_pw.restype = C.c_double
         L.orc_vsog.argtypes = [_P(VParams), C.c_double, C.c_double, _f64p, _f64p]
         L.orc_vsog_count.argtypes = [_P(VParams), C.c_double, C.c_double]
+        L.orc_vfit_target.argtypes = [_P(VParams), C.c_double]
+        L.orc_vfit_target.restype = C.c_double
         L.orc_vtree_build.argtypes = [_P(VParams), C.c_double, C.c_int, C.c_int, C.c_int, _f64p, DENSITY_FN,
                                       C.c_void_p, _P(_VTree)]
         L.orc_vtree_free.argtypes = [_P(_VTree)]
@@ -629,6 +633,15 @@ def vparams_for(tol: float = 1e-3, q: int = 8) -> VParams:
     if lib().orc_vparams_for(tol, q, C.byref(vp)) != 0:
         raise ValueError(f"unsupported volume parameters tol={tol} q={q}")
     return vp
+
+
+def vfit(vp: VParams):
+    """PSWF split (tol 1e-6): the fitted Gaussians (t s_L, w s_L) and the
+    function they stand for, h(x) = (erf(theta1 x) - Phi(x)) / x."""
+    n = vp.nfit
+    t = np.array(vp.fit_t[:n])
+    w = np.array(vp.fit_w[:n])
+    return t, w, np.vectorize(lambda x: lib().orc_vfit_target(C.byref(vp), float(x)))
 
 
 class GSplit:

@@ -248,6 +248,7 @@ void orc_direct2(int kern, double lam, int64_t n, const double *pts, const doubl
  * Volume potential u(x) = int_{B_0} rho(y)/(4 pi |x-y|) dy on the unit cube
  * B_0 = [-1/2,1/2]^3 with the Gaussian multilevel split (Sec. 3.2) and the
  * continuous-source modifications of Sec. 3.6 and Sec. 4.4; see vol.c. */
+#define ORC_VFIT_MAX 32
 typedef struct {
     double tol;
     int    q;        /* leaf grid: q Chebyshev nodes per axis               */
@@ -259,8 +260,20 @@ typedef struct {
     double tau_a;    /* t_a = tau_a / (target leaf side)                     */
     int    tpan_gl;  /* Gauss-Legendre nodes per panel in log t              */
     double tpan_w;   /* panel width in log t                                 */
+    /* tol 1e-6 takes the PSWF split of Sec. 3.7 (split = 1): D_l and W_0 of
+       the point code, and the residual R_L = (1 - Phi(r/s_L))/r as a sum of
+       Gaussians -- nfit fitted ones plus the t-quadrature from theta1/s_L */
+    int    split;    /* 0: Gaussian split (tol 1e-3); 1: PSWF split          */
+    double c;        /* PSWF bandwidth (split 1)                             */
+    double theta1;   /* quadrature in t from theta1 / s_L (split 1)          */
+    int    nfit;     /* fitted Gaussians (split 1)                           */
+    double fit_t[ORC_VFIT_MAX], fit_w[ORC_VFIT_MAX]; /* t s_L and w s_L      */
+    double fit_err;  /* max |error| of the fit on its sample grid, x 1/s_L   */
 } orc_vparams;
-int orc_vparams_for(double tol, int q, orc_vparams *vp);  /* tol 1e-3 */
+int orc_vparams_for(double tol, int q, orc_vparams *vp);  /* tol 1e-3 or 1e-6 */
+/* the part of R_L that the fitted Gaussians stand for, in units of s_L:
+   h(x) = (erf(theta1 x) - Phi(x)) / x */
+double orc_vfit_target(const orc_vparams *vp, double x);
 
 double orc_gsplit_m(const orc_vparams *vp, int l, double r);   /* erf(r/s_l)/r */
 double orc_gsplit_d(const orc_vparams *vp, int l, double r);   /* D_l          */

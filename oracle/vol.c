@@ -31,6 +31,17 @@
  *     the expansion rho + Delta rho/(4 t^2) + Delta^2 rho/(32 t^4) of the
  *     Gaussian convolution.
  *
+ *   - At tol 1e-6, the PSWF split of Sec. 3.7 instead (the remark closing
+ *     Sec. 3.6 proposes it, with Gaussians for the residual only): D_l and
+ *     the windowed W_0 of the point code (p = 18, n_f = 12); the residual
+ *     R_L = (1 - Phi(r/s_L))/r, in x = r/s_L, is
+ *       h(x) + (2/sqrt pi) int_{theta1}^{t_a s_L} e^{-x^2 t^2} dt + erfc(t_a r)/r,
+ *     h(x) = (erf(theta1 x) - Phi(x))/x: the integral is the same log-t
+ *     quadrature (half-width panels), the last term the same asymptotic
+ *     part, and h is a sum of nfit Gaussians fitted by least squares
+ *     (Sec. 3.6 asks for a sum of Gaussians and leaves its construction
+ *     open; see vfit below for the nodes and the sample grid).
+ *
  * Readings where the paper leaves a choice open (each is also a choice of
  * the GPU path, made independently there):
  *   - leaf nodes: first-kind Chebyshev points cos(pi (i + 1/2)/q) per axis;
@@ -71,23 +82,121 @@ typedef double complex cplx;
 #define VKB 21 /* key bits per axis */
 
 /* ------------------------------------------------------------- parameters */
+/* Least squares min |A w - b| by Householder QR (A is m x n, row-major,
+ * m >= n, overwritten); w gets the n unknowns. */
+static int lsq_householder(int m, int n, double *A, double *b, double *w)
+{
+    for (int k = 0; k < n; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < m; ++i) nrm += A[i * n + k] * A[i * n + k];
+        nrm = sqrt(nrm);
+        if (nrm == 0.0) return -1;
+        const double alpha = A[k * n + k] > 0 ? -nrm : nrm;
+        /* v = a_k - alpha e_k, stored in column k below the diagonal */
+        A[k * n + k] -= alpha;
+        double vv = 0.0;
+        for (int i = k; i < m; ++i) vv += A[i * n + k] * A[i * n + k];
+        for (int j = k + 1; j < n; ++j) {
+            double d = 0.0;
+            for (int i = k; i < m; ++i) d += A[i * n + k] * A[i * n + j];
+            d *= 2.0 / vv;
+            for (int i = k; i < m; ++i) A[i * n + j] -= d * A[i * n + k];
+        }
+        double d = 0.0;
+        for (int i = k; i < m; ++i) d += A[i * n + k] * b[i];
+        d *= 2.0 / vv;
+        for (int i = k; i < m; ++i) b[i] -= d * A[i * n + k];
+        A[k * n + k] = alpha; /* R's diagonal */
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = b[k];
+        for (int j = k + 1; j < n; ++j) s -= A[k * n + j] * w[j];
+        w[k] = s / A[k * n + k];
+    }
+    return 0;
+}
+
+/* Sec. 3.6 asks for a sum of Gaussians for the residual kernel on [eps_0, 1]
+ * and leaves the construction open.  With the PSWF split (Sec. 3.7) the
+ * residual of level L is R_L(r) = (1 - Phi(r/s_L))/r.  In x = r/s_L,
+ *   (1 - Phi(x))/x = h(x) + (2/sqrt pi) int_{theta1}^{tau} e^{-x^2 t^2} dt
+ *                  + erfc(tau x)/x,     h(x) = (erf(theta1 x) - Phi(x))/x,
+ * tau = t_a s_L: the last term is the asymptotic part (Sec. 4.4), the
+ * middle one the quadrature in log t, and h -- bounded, even, and zero to
+ * erfc(theta1) beyond x = 1 -- is fitted by nfit Gaussians e^{-x^2 t_i^2}
+ * with fixed t_i (geometric from 0.5 to 10) by least squares on 2200 equal
+ * steps of [0, 5.5] (the largest node distance of a near pair is below
+ * 3 sqrt 3 source sides). */
+static double fit_target(const orc_pswf *ps, const orc_vparams *vp, double x)
+{
+    if (x == 0.0) return 2.0 * vp->theta1 / sqrt(M_PI) - ps->psi0 / ps->c0;
+    return (erf(vp->theta1 * x) - orc_pswf_phi(ps, x)) / x;
+}
+
+double orc_vfit_target(const orc_vparams *vp, double x)
+{
+    orc_pswf ps;
+    if (vp->split != 1 || orc_pswf_init(vp->c, &ps) != 0) return NAN;
+    return fit_target(&ps, vp, x);
+}
+
+static int vfit(orc_vparams *vp)
+{
+    const int m = 2200, n = vp->nfit;
+    orc_pswf ps;
+    if (n < 2 || n > ORC_VFIT_MAX || orc_pswf_init(vp->c, &ps) != 0) return -1;
+    double *A = (double *)malloc((size_t)m * n * sizeof(double));
+    double *b = (double *)malloc((size_t)m * sizeof(double));
+    double *x = (double *)malloc((size_t)m * sizeof(double));
+    for (int i = 0; i < n; ++i) vp->fit_t[i] = 0.5 * pow(20.0, (double)i / (n - 1));
+    for (int j = 0; j < m; ++j) {
+        x[j] = 5.5 * j / (m - 1);
+        b[j] = fit_target(&ps, vp, x[j]);
+        for (int i = 0; i < n; ++i) A[j * n + i] = exp(-x[j] * x[j] * vp->fit_t[i] * vp->fit_t[i]);
+    }
+    int rc = lsq_householder(m, n, A, b, vp->fit_w);
+    vp->fit_err = 0.0;
+    for (int j = 0; j < m && rc == 0; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += vp->fit_w[i] * exp(-x[j] * x[j] * vp->fit_t[i] * vp->fit_t[i]);
+        double e = fabs(s - fit_target(&ps, vp, x[j]));
+        if (e > vp->fit_err) vp->fit_err = e;
+    }
+    free(A);
+    free(b);
+    free(x);
+    return rc;
+}
+
 int orc_vparams_for(double tol, int q, orc_vparams *vp)
 {
     memset(vp, 0, sizeof(*vp));
-    if (!(tol == 1e-3)) return -1;
+    if (!(tol == 1e-3 || tol == 1e-6)) return -1;
     if (q < 2 || q > 16) return -1;
     vp->tol = tol;
     vp->q = q;
     vp->sigma0 = 1.0 / sqrt(log(1.0 / tol));
     vp->p = 18;
     vp->nf = 12;
-    vp->nw = 14;
-    vp->hw = 2.0 * M_PI / (2.0 * sqrt(3.0) + 2.0);
     vp->nleg = 18;
     vp->tau_a = 2.0 * pow(tol, -1.0 / 6.0);
     vp->tpan_gl = 5;
-    vp->tpan_w = 1.0;
-    return 0;
+    if (tol == 1e-3) {
+        vp->nw = 14;
+        vp->hw = 2.0 * M_PI / (2.0 * sqrt(3.0) + 2.0);
+        vp->tpan_w = 1.0;
+        return 0;
+    }
+    orc_params pr;
+    if (orc_params_for(1e-6, &pr) != 0 || pr.p != 18 || pr.nf != 12) return -1;
+    vp->split = 1;
+    vp->c = pr.c;
+    vp->nw = pr.nw;
+    vp->hw = pr.hw;
+    vp->tpan_w = 0.5;
+    vp->theta1 = 5.0;
+    vp->nfit = 20;
+    return vfit(vp);
 }
 
 static double sig(const orc_vparams *vp, int l) { return ldexp(vp->sigma0, -l); }
@@ -680,6 +789,8 @@ int orc_vol_eval(const orc_vtree *t, const orc_vparams *vp, const double *rho, o
     res->utail = (double *)calloc((size_t)npt, sizeof(double));
     const double kappa = 1.0 / (4.0 * M_PI);
 
+    orc_pswf ps; /* PSWF split (tol 1e-6): D_l and W_0 of Sec. 3.7 */
+    if (vp->split == 1 && orc_pswf_init(vp->c, &ps) != 0) return -1;
     vboxes B;
     build_boxes(t, &B);
     cheb_t ch, chq;
@@ -741,7 +852,8 @@ int orc_vol_eval(const orc_vtree *t, const orc_vparams *vp, const double *rho, o
             for (int b = 0; b < nwn; ++b)
                 for (int c = 0; c < nwn; ++c) {
                     int k2 = (a - nw) * (a - nw) + (b - nw) * (b - nw) + (c - nw) * (c - nw);
-                    phi[(a * nwn + b) * nwn + c] *= fac * orc_gw0hat(vp, hw * sqrt((double)k2));
+                    const double k = hw * sqrt((double)k2);
+                    phi[(a * nwn + b) * nwn + c] *= fac * (vp->split ? orc_w0hat(&ps, k) : orc_gw0hat(vp, k));
                 }
         local[0] = (double *)calloc((size_t)p3, sizeof(double));
         v_pw_to_grid(&ch, phi, hw, 1.0, nw, local[0]);
@@ -789,7 +901,8 @@ int orc_vol_eval(const orc_vtree *t, const orc_vparams *vp, const double *rho, o
                 for (int bb = 0; bb < nn; ++bb)
                     for (int cc = 0; cc < nn; ++cc) {
                         int k2 = (a - nf) * (a - nf) + (bb - nf) * (bb - nf) + (cc - nf) * (cc - nf);
-                        psi[(a * nn + bb) * nn + cc] *= fac * orc_gdhat(vp, l, h * sqrt((double)k2));
+                        const double k = h * sqrt((double)k2);
+                        psi[(a * nn + bb) * nn + cc] *= fac * (vp->split ? orc_dhat(&ps, l, k) : orc_gdhat(vp, l, k));
                     }
             v_pw_to_grid(&ch, psi, h, s, nf, local[b]);
             free(psi);
@@ -823,7 +936,8 @@ int orc_vol_eval(const orc_vtree *t, const orc_vparams *vp, const double *rho, o
     free(phi);
 
     /* ---- near field: for each source leaf T, the Gaussians of R_{L_T} with
-       t in [1/sigma_{L_T}, t_a(target)] over the target leaves of its lists */
+       t in [1/sigma_{L_T}, t_a(target)] (PSWF split: [theta1/s_T, t_a] and
+       the fitted Gaussians) over the target leaves of its lists */
     const double sqL = sqrt(log(1.0 / vp->tol));
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t T = 0; T < B.nbox; ++T) {
@@ -883,7 +997,12 @@ int orc_vol_eval(const orc_vtree *t, const orc_vparams *vp, const double *rho, o
                 if (g > 0.0) gap2 += g * g;
             }
             if (gap2 >= sT * sT) continue;
-            const int ng = orc_vsog(vp, sqL / sT, vp->tau_a / sB, tn, wn);
+            const double t_lo = (vp->split ? vp->theta1 : sqL) / sT;
+            int ng = orc_vsog(vp, t_lo, vp->tau_a / sB, tn, wn);
+            for (int i = 0; i < vp->nfit; ++i, ++ng) { /* PSWF split: the fitted part of R_L */
+                tn[ng] = vp->fit_t[i] / sT;
+                wn[ng] = vp->fit_w[i] / sT;
+            }
             double *ub = res->unear + B.leafidx[Bx] * q3;
             double row[16];
             for (int j = 0; j < ng; ++j) {

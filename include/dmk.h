@@ -531,8 +531,16 @@ typedef void (*dmk_density_fn)(int64_t n, const double *xyz, double *out, void *
 /*
  * dmk_vol_plan -- build the tree (host, by calls of `density`), then the box
  * structures, lists and tables on the device.
- *  tol        1e-3 (p = 18 proxies, 25 plane waves per axis; else
- *             DMK_ERR_UNSUPPORTED).
+ *  tol        1e-3: the Gaussian split of Sec. 3.2 (p = 18 proxies, 25
+ *             plane waves per axis), the residual as a quadrature of
+ *             Gaussians in t (Sec. 3.6);
+ *             1e-6: the PSWF split of Sec. 3.7 (the point code's 1e-6 far
+ *             field, p = 18, 25 plane waves per axis), the residual
+ *             (1 - Phi(r/s_L))/r as Gaussians: a quadrature in t from 5/s_L
+ *             plus 20 Gaussians fitted to the rest by least squares at plan
+ *             time (Sec. 3.6 leaves the construction open), and the same
+ *             asymptotic part;
+ *             else DMK_ERR_UNSUPPORTED.
  *  q          8 (leaf grid order; else DMK_ERR_UNSUPPORTED).
  *  rho_scale  > 0, the density magnitude the refinement tolerance is
  *             relative to.

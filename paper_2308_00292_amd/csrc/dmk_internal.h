@@ -72,6 +72,7 @@ void build_tables(const Params &prm, Tables *t, int dim = 3, int kind = 0);
 
 // PSWF helpers exposed for the host-side self checks in the tests.
 double pswf_eval(const Tables &t, double x);  // any real x
+double pswf_phi(const Tables &t, double x);  // Phi(x) = (1/c_0) int_0^x psi, 1 beyond x = 1
 
 // ------------------------------------------------------------------- plan
 struct LevelLists {
@@ -87,8 +88,13 @@ struct VolData {
     int q = 0;
     int64_t nleaf = 0;
     std::vector<int32_t> level, ijk;     // host leaf list, Morton order
-    double tau_a = 0, sqL = 0, tpan_w = 1.0;
+    double tau_a = 0, sqL = 0, tpan_w = 1.0;  // sqL: lower end of the t-quadrature, x s_T
     int tpan_gl = 5;
+    int split = 0;                       // 0: Gaussian split; 1: PSWF split (tol 1e-6)
+    int nfit = 0;                        // PSWF split: fitted Gaussians of the residual
+    std::vector<double> fit;             // [2][nfit]: t s_T, then w s_T
+    double fit_err = 0;                  // max |fit error| on its sample grid, x 1/s_T
+    double *d_fit = nullptr;
     int32_t *d_level = nullptr, *d_ijk = nullptr;
     int32_t *box2v = nullptr;            // [nbox] volume leaf of a leaf box, -1 otherwise
     double *d_v1 = nullptr;              // [2][p][q] density -> parent proxy matrices

@@ -177,6 +177,8 @@ void lagrange_row(const Tables &t, double xi, double *out)
 
 }  // namespace
 
+double pswf_phi(const Tables &t, double x) { return x <= 0.0 ? 0.0 : phi_window(t, x); }
+
 double pswf_eval(const Tables &t, double x)
 {
     x = std::fabs(x);

@@ -554,7 +554,8 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
                                                   const double *egl, const double *eglw, int ngl, double tpan_w,
                                                   double tau_a, double sqL, int q, int64_t nk, const int32_t *kk,
                                                   const double *kd, const int32_t *kng, const int64_t *kbase,
-                                                  int64_t rows, double *gtab, double *gw)
+                                                  int nfit, const double *fit, int64_t rows, double *gtab,
+                                                  double *gw)
 {
     const int64_t r = blockIdx.x * (int64_t)TPB + threadIdx.x;
     if (r >= rows) return;
@@ -569,10 +570,11 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
     const int64_t c = lo;
     const int j = (int)(g - kbase[c]), k = kk[c];
     const double u0 = log(sqL), u1 = log(tau_a) + k * log(2.0);
-    const int npan = kng[c] / ngl;
+    const int npan = (kng[c] - nfit) / ngl;
     const double hp = (u1 - u0) / npan;
     const int pan = j / ngl, gi = j % ngl;
-    const double tj = exp(u0 + hp * (pan + 0.5 * (tgl[gi] + 1.0)));
+    const bool fitted = j >= npan * ngl;  // PSWF split: the fitted Gaussians follow the panels
+    const double tj = fitted ? fit[j - npan * ngl] : exp(u0 + hp * (pan + 0.5 * (tgl[gi] + 1.0)));
     const double tau = 0.5 * tj;
     const double xi = 2.0 * kd[c] + ldexp(1.0, -k) * xq[a];
     const double lo_ = fmax(-1.0, xi - 7.0 / tau), hi_ = fmin(1.0, xi + 7.0 / tau);
@@ -601,7 +603,7 @@ __global__ void __launch_bounds__(TPB) k_vol_gtab(const double *xq, const double
         for (int m = 1; m < q; ++m) s += 2.0 * cos(m * M_PI * (b + 0.5) / q) * cf[m];
         out[b] = 0.5 * s / q;
     }
-    if (a == 0) gw[g] = 2.0 / sqrt(M_PI) * tj * 0.5 * hp * tglw[gi];
+    if (a == 0) gw[g] = fitted ? fit[nfit + j - npan * ngl] : 2.0 / sqrt(M_PI) * tj * 0.5 * hp * tglw[gi];
 }
 
 __global__ void __launch_bounds__(TPB) k_vol_tof32(const double *src, float *dst, int64_t n)
@@ -863,9 +865,74 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
     DMK_HIP(hipGetLastError());
 }
 
+// PSWF split (tol 1e-6): the residual R_L(r) = (1 - Phi(r/s_L))/r of Sec. 3.7
+// as Gaussians for the near field of Sec. 3.6.  In x = r/s_L,
+//   (1 - Phi(x))/x = h(x) + (2/sqrt pi) int_{theta_1}^{tau} e^{-x^2 t^2} dt + erfc(tau x)/x,
+//   h(x) = (erf(theta_1 x) - Phi(x))/x,  tau = t_a s_L:
+// the integral is the log-t quadrature, erfc(tau x)/x the asymptotic part
+// (Sec. 4.4), and h -- bounded, and zero to erfc(theta_1) beyond x = 1 -- is
+// fitted here by n Gaussians e^{-x^2 t_i^2}, t_i geometric from 0.5 to 10,
+// by least squares over 2200 equal steps of [0, 5.5] (node distances of a
+// near pair stay below 3 sqrt 3 source sides), solved by Gram-Schmidt with
+// reorthogonalisation.  fit = [t_i..., w_i...]; returns the largest error on
+// the sample grid.
+double vol_sog_fit(const Tables &tb, double theta1, int n, std::vector<double> &fit)
+{
+    const int m = 2200;
+    fit.assign(2 * (size_t)n, 0.0);
+    std::vector<double> t(n), xs(m), b(m), Q((size_t)n * m), R((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) t[i] = 0.5 * std::pow(20.0, (double)i / (n - 1));
+    for (int j = 0; j < m; ++j) {
+        const double x = 5.5 * j / (m - 1);
+        xs[j] = x;
+        b[j] = x == 0.0 ? 2.0 * theta1 / std::sqrt(M_PI) - tb.psi0 / tb.c0
+                        : (std::erf(theta1 * x) - pswf_phi(tb, x)) / x;
+    }
+    for (int i = 0; i < n; ++i) {
+        double *qi = &Q[(size_t)i * m];
+        for (int j = 0; j < m; ++j) qi[j] = std::exp(-xs[j] * xs[j] * t[i] * t[i]);
+        for (int pass = 0; pass < 2; ++pass)
+            for (int k = 0; k < i; ++k) {
+                const double *qk = &Q[(size_t)k * m];
+                double d = 0.0;
+                for (int j = 0; j < m; ++j) d += qk[j] * qi[j];
+                R[(size_t)k * n + i] += d;
+                for (int j = 0; j < m; ++j) qi[j] -= d * qk[j];
+            }
+        double nr = 0.0;
+        for (int j = 0; j < m; ++j) nr += qi[j] * qi[j];
+        nr = std::sqrt(nr);
+        if (!(nr > 0.0)) throw Error{DMK_ERR_STATE, "sum-of-Gaussians fit: singular basis"};
+        R[(size_t)i * n + i] = nr;
+        for (int j = 0; j < m; ++j) qi[j] /= nr;
+    }
+    std::vector<double> y(n), r(b);
+    for (int i = 0; i < n; ++i) {  // y = Q^T b, one projection at a time
+        const double *qi = &Q[(size_t)i * m];
+        double d = 0.0;
+        for (int j = 0; j < m; ++j) d += qi[j] * r[j];
+        y[i] = d;
+        for (int j = 0; j < m; ++j) r[j] -= d * qi[j];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double sum = y[i];
+        for (int k = i + 1; k < n; ++k) sum -= R[(size_t)i * n + k] * fit[n + k];
+        fit[n + i] = sum / R[(size_t)i * n + i];
+    }
+    double err = 0.0;
+    for (int j = 0; j < m; ++j) {
+        double sum = 0.0;
+        for (int i = 0; i < n; ++i) sum += fit[n + i] * std::exp(-xs[j] * xs[j] * t[i] * t[i]);
+        err = std::max(err, std::fabs(sum - b[j]));
+    }
+    for (int i = 0; i < n; ++i) fit[i] = t[i];
+    return err;
+}
+
 // Gaussians of the near field of a pair whose target is 2^-k times the
 // source side: Gauss-Legendre panels of width <= tpan_w in log t from
-// sqrt(log(1/eps)) / s_T to tau_a / s_B
+// sqL / s_T (Gaussian split: sqL = sqrt(log(1/eps)); PSWF split: theta_1)
+// to tau_a / s_B; the PSWF split adds its nfit fitted Gaussians
 int vol_npan(const VolData &V, int k)
 {
     const double u0 = std::log(V.sqL), u1 = std::log(V.tau_a) + k * std::log(2.0);
@@ -942,7 +1009,7 @@ void vol_count_work(Plan *P, hipStream_t s)
                 pkey[3 * (size_t)e + d] = id;
             }
             V.n_pairs++;
-            V.n_gauss += (int64_t)vol_npan(V, k) * V.tpan_gl;
+            V.n_gauss += (int64_t)vol_npan(V, k) * V.tpan_gl + V.nfit;
         }
     }
     // order every target's entries by (z class, y class, x class), pruned
@@ -992,7 +1059,7 @@ void vol_count_work(Plan *P, hipStream_t s)
     std::vector<int64_t> kbase(std::max<int64_t>(nk, 1), 0);
     int64_t ng = 0;
     for (int64_t c = 0; c < nk; ++c) {
-        kng[c] = vol_npan(V, ck[c]) * V.tpan_gl;
+        kng[c] = vol_npan(V, ck[c]) * V.tpan_gl + V.nfit;
         kk[c] = ck[c];
         kbase[c] = ng;
         ng += kng[c];
@@ -1020,7 +1087,7 @@ void vol_count_work(Plan *P, hipStream_t s)
     if (rows > 0)
         hipLaunchKernelGGL(k_vol_gtab, dim3(vblk(rows)), dim3(TPB), 0, s, V.d_xq, V.d_tgl, V.d_tglw, V.d_egl,
                            V.d_eglw, V.tpan_gl, V.tpan_w, V.tau_a, V.sqL, q, nk, d_kk, d_cd, V.d_kng, V.d_kbase,
-                           rows, V.d_gtab, V.d_gw);
+                           V.nfit, V.d_fit, rows, V.d_gtab, V.d_gw);
     if (P->precision == DMK_MIXED) {
         // the mixed path's near field multiplies in FP32
         const int64_t nt = std::max<int64_t>(ng, 1) * q * q;
@@ -1038,7 +1105,9 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
                          int32_t nfeat, const double *feat, dmk_density_fn density, void *ctx, const dmk_opts *opts,
                          void *stream)
 {
-    if (!(tol == 1e-3)) throw Error{DMK_ERR_UNSUPPORTED, "volume plans are built for tol = 1e-3"};
+    const bool pswf = (tol == 1e-6);  // PSWF split; tol 1e-3 takes the Gaussian split
+    if (!(tol == 1e-3 || pswf))
+        throw Error{DMK_ERR_UNSUPPORTED, "volume plans are built for tol = 1e-3 (Gaussian split) or 1e-6 (PSWF split)"};
     if (q != VQ) throw Error{DMK_ERR_UNSUPPORTED, "volume plans are built for q = 8"};
     if (!(rho_scale > 0) || !std::isfinite(rho_scale)) throw Error{DMK_ERR_ARG, "rho_scale must be positive"};
     if (min_level < 1 || max_level > 19 || min_level > max_level)
@@ -1081,7 +1150,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         P->queued = queue_schedule(3, P->flags);
         P->n = n;
         build_tables(prm, &P->tab, 3);
-        gauss_tables(&P->tab, tol);
+        if (!pswf) gauss_tables(&P->tab, tol);
         P->p = P->tab.p;
         P->nf = P->tab.nf;
         P->nw = P->tab.nw;
@@ -1089,9 +1158,21 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         V.q = q;
         V.nleaf = nleaf;
         V.tau_a = 2.0 * std::pow(tol, -1.0 / 6.0);
-        V.sqL = std::sqrt(std::log(1.0 / tol));
         V.tpan_gl = 5;
-        V.tpan_w = 1.0;
+        if (pswf) {
+            // t-quadrature from theta_1 = 5 (erfc(5) = 1.5e-12 bounds h beyond
+            // x = 1) on half-width panels; 20 fitted Gaussians
+            V.split = 1;
+            V.sqL = 5.0;
+            V.tpan_w = 0.5;
+            V.nfit = 20;
+            if (V.nfit % VolLds<18, VQ>::JB) throw Error{DMK_ERR_STATE, "fitted Gaussians must fill whole passes"};
+            V.fit_err = vol_sog_fit(P->tab, V.sqL, V.nfit, V.fit);
+            if (!(V.fit_err < 2e-6)) throw Error{DMK_ERR_STATE, "sum-of-Gaussians fit of the residual failed"};
+        } else {
+            V.sqL = std::sqrt(std::log(1.0 / tol));
+            V.tpan_w = 1.0;
+        }
         V.level.resize(nleaf);
         V.ijk.resize(3 * nleaf);
         for (int64_t i = 0; i < nleaf; ++i) {
@@ -1111,6 +1192,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         P->d_poff = (int64_t *)dalloc(P, 2 * sizeof(int64_t));
         DMK_HIP(hipMemcpyAsync(P->d_poff, P->poff.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
         upload_tables(P, s);
+        if (V.nfit) V.d_fit = up64(V.fit);
         V.d_level = up32i(V.level);
         V.d_ijk = up32i(V.ijk);
         std::vector<double> xq(q), bq(q);

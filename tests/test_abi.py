@@ -69,7 +69,7 @@ def test_argument_errors_without_device():
     cb = dmk.DENSITY_FN(lambda n, x, out, ctx: calls.append(n))
     ok = np.array([[0.0, 0.0, 0.0, 0.1]])
     bad = np.array([[0.0, 0.0, 0.0, 0.0]])
-    assert L.dmk_vol_plan(1e-6, 8, 1.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -2  # tol
+    assert L.dmk_vol_plan(1e-4, 8, 1.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -2  # tol
     assert L.dmk_vol_plan(1e-3, 6, 1.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -2  # q
     assert L.dmk_vol_plan(1e-3, 8, 0.0, 1, 4, 0, None, cb, None, None, None, C.byref(h)) == -1  # rho_scale
     assert L.dmk_vol_plan(1e-3, 8, 1.0, 0, 4, 0, None, cb, None, None, None, C.byref(h)) == -1  # min_level

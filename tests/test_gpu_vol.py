@@ -123,7 +123,7 @@ def test_api_misuse(oracle_mod):
     import paper_2308_00292_amd as dmk
     f = lambda x: np.ones(len(x))
     with pytest.raises(dmk.DmkError):
-        dmk.VolPlan(f, tol=1e-6)
+        dmk.VolPlan(f, tol=1e-4)
     with pytest.raises(dmk.DmkError):
         dmk.VolPlan(f, q=6)
     with pytest.raises(dmk.DmkError):

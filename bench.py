@@ -50,16 +50,22 @@ WORKLOADS = {
     "cfg5_volume_8gauss": "3-D volume potential on [-1/2,1/2]^3 of rho = sum of 8 Gaussians exp(-|x-c|^2/s^2), "
                           "s = exp(U[ln 1e-3, ln 1e-1]), c ~ U[-0.3,0.3]^3; adaptive tree of 8^3 Chebyshev leaves "
                           "(density resolved to 3e-8 of its peak, leaves <= 4 s at each centre), 4.0e7 nodes; "
-                          "Gaussian split, tol 1e-3 (--precision: mixed = FP32 far-field transforms and near-field "
+                          "Gaussian split at tol 1e-3, PSWF split at 1e-6 (--vol-tol; same tree) (--precision: mixed = FP32 far-field transforms and near-field "
                           "products, FP64 asymptotic part and sums)",
 }
 METRIC_2D = "points/s, 2-D DMK batch of 512 problems at 1e-6 rel l2, 1 GPU"
-METRIC_VOL = "points/s, 3-D volume potential DMK (box code) at tol 1e-3, 1 GPU"
+METRIC_VOL = "points/s, 3-D volume potential DMK (box code) at tol {tol:g}, 1 GPU"
 STAGE_KERNEL_VOL = {"upward": "k_vol_upward", "root": "k_root_stage", "proxy2pw": "k_proxy2pw_mfma",
                     "pwshift": "k_pwshift", "pw2grid": "k_local_mfma_q", "leaf": "k_vol_leaf", "residual": "k_vol_near",
                     "finalize": "k_vol_finalize"}
-# volume workload: density, refinement and tree limits
+# volume workload: density, refinement and tree limits.  The tree refines
+# while a leaf's Chebyshev tail exceeds tol * rho_scale; the product is held
+# at 3e-8 for both tolerances, so tol 1e-3 and 1e-6 run on the same tree.
 VOL_SEED, VOL_RHO_SCALE, VOL_MAX_LEVEL = 5, 3e-5, 16
+
+
+def vol_rho_scale(tol):
+    return VOL_RHO_SCALE * 1e-3 / tol
 
 
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 PMC runs of
@@ -169,23 +175,24 @@ def cpu_baseline(pts, q, ns, tol, seed=7):
     return res
 
 
-def cpu_baseline_vol(sig, cen, amp, feat):
+def cpu_baseline_vol(sig, cen, amp, feat, tol):
     """The volume oracle (plain FP64 C, OpenMP) on the same density with the
-    tree cut at level 3 (same refinement rule otherwise): points/s of its
-    eval phase."""
+    tree cut at level 3 (tol 1e-3) or 2 (tol 1e-6; same refinement rule
+    otherwise): points/s of its eval phase."""
     import oracle
     import dmk_inputs
-    vp = oracle.vparams_for(1e-3, 8)
+    vp = oracle.vparams_for(tol, 8)
     f = lambda x: dmk_inputs.gaussian_mixture(x, sig, cen, amp)
-    T = oracle.VTree(vp, f, VOL_RHO_SCALE, 1, 3, features=feat)
+    cut = 3 if tol == 1e-3 else 2  # about 15 s of eval either way
+    T = oracle.VTree(vp, f, vol_rho_scale(tol), 1, cut, features=feat)
     rho = f(T.nodes())
     t0 = time.perf_counter()
     T.eval(rho)
     te = time.perf_counter() - t0
     n = T.nleaf * 512
     return {"value": n / te, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"same density, tree cut at level 3 ({T.nleaf} leaves, {n} nodes), eval phase {te:.2f} s, "
-                      f"tree excluded, FP64, tol 1e-3"}
+            "sample": f"same density, tree cut at level {cut} ({T.nleaf} leaves, {n} nodes), eval phase {te:.2f} s, "
+                      f"tree excluded, FP64, tol {tol:g}"}
 
 
 def run_volume(args):
@@ -203,7 +210,8 @@ def run_volume(args):
     log(f"[bench] volume plan ({args.precision})")
     t0 = time.perf_counter()
     lvl = dmk.DMK_FLAG_LEVEL_LAUNCHES if args.level_launches else 0
-    plan = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
+    vtol = args.vol_tol
+    plan = dmk.VolPlan(f, tol=vtol, q=8, rho_scale=vol_rho_scale(vtol), min_level=1, max_level=VOL_MAX_LEVEL,
                        features=feat, precision=prec, flags=lvl)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
@@ -266,7 +274,7 @@ def run_volume(args):
     plan.close()
     fp64 = None
     if not args.no_compare and prec != dmk.DMK_FP64:
-        p64 = dmk.VolPlan(f, tol=1e-3, q=8, rho_scale=VOL_RHO_SCALE, min_level=1, max_level=VOL_MAX_LEVEL,
+        p64 = dmk.VolPlan(f, tol=vtol, q=8, rho_scale=vol_rho_scale(vtol), min_level=1, max_level=VOL_MAX_LEVEL,
                           features=feat, precision=dmk.DMK_FP64, flags=lvl)
         out64 = torch.empty_like(rho)
         for _ in range(args.warmup):
@@ -287,16 +295,17 @@ def run_volume(args):
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (volume oracle)")
-        cpu = cpu_baseline_vol(sig, cen, amp, feat)
+        cpu = cpu_baseline_vol(sig, cen, amp, feat, vtol)
         log(f"[bench] cpu baseline {cpu['value']:.4g} points/s on {cpu['cores']} threads")
     res = {
-        "metric": METRIC_VOL, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC_VOL.format(tol=vtol), "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64" if prec == dmk.DMK_FP64 else "f32+f64", "data": "synthetic",
         "config": {"workload": WORKLOADS["cfg5_volume_8gauss"], "name": "cfg5_volume_8gauss", "n_points": n,
                    "precision": args.precision, "fp64": fp64,
                    "schedule": "per-level launches" if args.level_launches else "queue-fed over all levels",
-                   "leaves": plan.nleaf, "levels": np.bincount(lev).tolist(), "q": 8, "p": 18, "nf": 12, "tol": 1e-3,
+                   "leaves": plan.nleaf, "levels": np.bincount(lev).tolist(), "q": 8, "p": 18, "nf": 12, "tol": vtol,
+                   "split": "PSWF (residual: fitted Gaussians + log-t quadrature)" if vtol == 1e-6 else "Gaussian",
                    "t_plan_s": round(t_plan, 3), "sampled_rel_l2_vs_closed_form": err, "stage_ms_per_step": stages},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -318,6 +327,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain FP64 (eager) comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--vol-tol", type=float, default=1e-3, choices=[1e-3, 1e-6],
+                    help="volume workload: 1e-3 (Gaussian split) or 1e-6 (PSWF split), same tree")
     ap.add_argument("--sample-targets", type=int, default=200)
     ap.add_argument("--level-launches", action="store_true",
                     help="launch the upward and local stages one tree level at a time instead of the "

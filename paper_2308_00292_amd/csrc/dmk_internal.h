@@ -118,6 +118,7 @@ struct VolData {
     int64_t n_merge = 0;        // non-leaf children merged by the child->parent matrices
     int64_t n_pairs = 0;        // (source leaf, target leaf) pairs of the near field
     int64_t n_gauss = 0;        // Gaussians summed over those pairs
+    int64_t n_gauss_passes = 0; // near-field mode-product passes times their Gaussians
 };
 
 struct Plan {

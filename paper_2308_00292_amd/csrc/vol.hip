@@ -1049,6 +1049,21 @@ void vol_count_work(Plan *P, hipStream_t s)
             }
             for (size_t r = 0; r < ord.size(); ++r) src[off[i] + r] = s2[r];
         }
+        // passes of the near-field kernel, times Gaussians: per z group an x
+        // pass per entry, a y pass per (y, z) group and one z pass
+        V.n_gauss_passes = 0;
+        for (int64_t i = 0; i < nl; ++i) {
+            int64_t npass = 0;
+            for (int32_t e = off[i]; e < off[i + 1]; ++e) {
+                const int32_t *K = &pk4[4 * (size_t)e];
+                if (K[0] < 0) break;
+                npass += 1 + (K[3] & 1) + ((K[3] >> 1) & 1);
+                if (K[3] & 2) {
+                    V.n_gauss_passes += npass * (vol_npan(V, ck[K[2]]) * V.tpan_gl + V.nfit);
+                    npass = 0;
+                }
+            }
+        }
         if (ne > 0)
             DMK_HIP(hipMemcpy(P->nl_src, src.data(), (size_t)ne * sizeof(int32_t), hipMemcpyHostToDevice));
     }
@@ -1297,7 +1312,9 @@ void run_vol_eval(Plan *P, const double *rho, double *u, double *far_part, doubl
 //             6 p^4 per merged child; density read once, proxies written once
 //   far       as the point code (proxy->PW, translation, PW->grid, root)
 //   leaf      2 (p^3 q + p^2 q^2 + p q^3) per leaf; anchor grid read, q^3 written
-//   residual  6 q^4 per (pair, Gaussian) (three q x q mode products) and
+//   residual  2 q^4 per pass and Gaussian (one q x q mode product over a
+//             q^3 block): an x pass per kept pair, a y pass per (y, z) group
+//             and a z pass per z group of a target's sorted gather list; and
 //             12 q^4 per leaf (two Laplacians); density read, near part written
 void vol_stage_work(const Plan *P, double *F, double *Bt)
 {
@@ -1321,7 +1338,7 @@ void vol_stage_work(const Plan *P, double *F, double *Bt)
     Bt[DMK_STAGE_PW2GRID] = pwbytes * P->nfin + 2 * el * p3 * P->nanc;
     F[DMK_STAGE_LEAF] = 2 * (p3 * q + p * p * q * q + p * q3) * NL;
     Bt[DMK_STAGE_LEAF] = el * p3 * P->nanc + 8 * N;
-    F[DMK_STAGE_RESIDUAL] = 6 * q4 * (double)P->vol.n_gauss + 12 * q4 * NL;
+    F[DMK_STAGE_RESIDUAL] = 2 * q4 * (double)P->vol.n_gauss_passes + 12 * q4 * NL;
     Bt[DMK_STAGE_RESIDUAL] = 16 * N;
     Bt[DMK_STAGE_FINALIZE] = 24 * N;
 }

@@ -28,6 +28,8 @@ CASES = {
     "uniform_l2": (0.2, [0.1, -0.05, 0.0], 1e9, 2, 2, 2e-6),
     # one level-1 leaf among level-2 leaves: coarse-neighbour pairs both ways
     "two_level": (0.1, [0.2, 0.15, 0.25], 1.0, 1, 2, 2e-5),
+    # adaptive to level 3 (281 leaves on levels 2 and 3): 8e-8 in the oracle
+    "adaptive_l3": (0.1, [0.1, -0.05, 0.12], 1.0, 1, 3, 1e-6),
 }
 
 _ORACLE = {}

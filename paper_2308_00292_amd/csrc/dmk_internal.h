@@ -105,8 +105,10 @@ struct VolData {
     double *d_egl = nullptr, *d_eglw = nullptr;  // Gauss-Legendre rule of the 1-D Gaussian integrals
     double *ufar = nullptr, *unear = nullptr;    // [nleaf q^3], leaf-major
     // near-field tables: one q x q matrix per (per-axis offset class, Gaussian)
-    // for a unit source box; pkey[e][3] gives the class of each axis of
-    // gather-list entry e (-1: pair pruned)
+    // for a unit source box; d_pkey[e][4] holds, for gather-list entry e,
+    // the first table row (Gaussian) of each axis' class (-1: pair pruned),
+    // then flags: bit 0 ends a (y, z) group, bit 1 a z group, and the
+    // entry's Gaussian count sits above bit 1
     int32_t *d_pkey = nullptr;
     int32_t *d_kng = nullptr;            // [nkey] Gaussians of the class
     int64_t *d_kbase = nullptr;          // [nkey] first Gaussian of the class

@@ -636,8 +636,8 @@ constexpr int vol_near_threads = Q * Q * 5;  // q^2 rows times the Gaussians of 
 template <typename T, int Q>
 __global__ void __launch_bounds__(vol_near_threads<Q>)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
-               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pk, const int32_t *__restrict__ kng,
-               const int64_t *__restrict__ kbase, const T *__restrict__ gtab, const double *__restrict__ gw)
+               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pk, const T *__restrict__ gtab,
+               const double *__restrict__ gw)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NB = VolLds<18, Q>::NB, RS = Q + 1,
                   NT = JB * Q2;
@@ -667,10 +667,10 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
         }
         const int32_t kx0 = pk[4 * (int64_t)e], kzc = pk[4 * (int64_t)e + 2];
         const double sT = ldexp(1.0, -D.blevel[nl_src[e]]);
-        const int ng = kng[kx0];
+        const int ng = pk[4 * (int64_t)e + 3] >> 2;
         for (int j0 = 0; j0 < ng; j0 += JB) {
             const int64_t j = j0 + w;
-            const T wj = (T)(gw[kbase[kx0] + j] * sT * sT);
+            const T wj = (T)(gw[kx0 + j] * sT * sT);
             T xa[Q], ya[Q];  // lane (i1 i2): xa[a]; lane (a i2): ya[b]
 #pragma unroll
             for (int k = 0; k < Q; ++k) xa[k] = ya[k] = T(0);
@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
                 for (int sidx = 0; sidx < nb; ++sidx) {
                     const int64_t es = b0 + sidx;
                     // x: xa[a] += sum_i0 G_x[a][i0] rho[i0][(i1 i2)]
-                    const T *gx = gtab + (kbase[pk[4 * es]] + j) * Q2;
+                    const T *gx = gtab + (pk[4 * es] + j) * Q2;
                     const T *rs = slot + sidx * Q3;
                     T r[Q];
 #pragma unroll
@@ -699,7 +699,7 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
                     }
                     if (pk[4 * es + 3] & 1) {
                         // end of a (y, z) group: ya[b] += sum_i1 G_y[b][i1] X[a][i1][i2]
-                        const T *gy = gtab + (kbase[pk[4 * es + 1]] + j) * Q2;
+                        const T *gy = gtab + (pk[4 * es + 1] + j) * Q2;
 #pragma unroll
                         for (int a = 0; a < Q; ++a) buf[L * RS + a] = xa[a];
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -723,7 +723,7 @@ __global__ void __launch_bounds__(vol_near_threads<Q>)
                 }
             }
             // end of the z class: acc[c] += w_j sum_i2 G_z[c][i2] Y[a][b][i2]
-            const T *gz = gtab + (kbase[kzc] + j) * Q2;
+            const T *gz = gtab + (kzc + j) * Q2;
 #pragma unroll
             for (int bb = 0; bb < Q; ++bb) buf[L * RS + bb] = ya[bb];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -855,7 +855,7 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         const T *gtab = sizeof(T) == 8 ? (const T *)V.d_gtab : (const T *)V.f_gtab;
         const size_t lds_near = LD::near(sizeof(T));
         hipLaunchKernelGGL((k_vol_near<T, Q>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB), lds_near, s, D64,
-                           Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey, V.d_kng, V.d_kbase, gtab, V.d_gw);
+                           Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey, gtab, V.d_gw);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -1081,6 +1081,17 @@ void vol_count_work(Plan *P, hipStream_t s)
     }
     V.nkey = nk;
     V.ngauss_tab = ng;
+    if (ng >= (int64_t(1) << 31) / 4) throw Error{DMK_ERR_STATE, "near-field tables too large"};
+    // the near-field kernel reads table offsets, not class ids: each class
+    // becomes the index of its first Gaussian, and the flags word carries the
+    // entry's Gaussian count (its classes share one level difference) above bit 1
+    for (int64_t e = 0; e < ne; ++e) {
+        int32_t *K = &pkey[4 * (size_t)e];
+        if (K[0] < 0) continue;
+        const int32_t ngx = kng[K[0]];
+        for (int d = 0; d < 3; ++d) K[d] = (int32_t)kbase[K[d]];
+        K[3] |= ngx << 2;
+    }
     const int q = V.q;
     auto upi = [&](const std::vector<int32_t> &h) {
         int32_t *d = (int32_t *)dalloc(P, h.size() * sizeof(int32_t));

@@ -37,7 +37,7 @@
  *     R_L = (1 - Phi(r/s_L))/r, in x = r/s_L, is
  *       h(x) + (2/sqrt pi) int_{theta1}^{t_a s_L} e^{-x^2 t^2} dt + erfc(t_a r)/r,
  *     h(x) = (erf(theta1 x) - Phi(x))/x: the integral is the same log-t
- *     quadrature (half-width panels), the last term the same asymptotic
+ *     quadrature (10 nodes on panels of width <= 1.4), the last term the same asymptotic
  *     part, and h is a sum of nfit Gaussians fitted by least squares
  *     (Sec. 3.6 asks for a sum of Gaussians and leaves its construction
  *     open; see vfit below for the nodes and the sample grid).
@@ -193,7 +193,8 @@ int orc_vparams_for(double tol, int q, orc_vparams *vp)
     vp->c = pr.c;
     vp->nw = pr.nw;
     vp->hw = pr.hw;
-    vp->tpan_w = 0.5;
+    vp->tpan_gl = 10; /* one panel of 10 nodes covers [theta1, t_a s_L] = [5, 20] */
+    vp->tpan_w = 1.4;
     vp->theta1 = 5.0;
     vp->nfit = 20;
     return vfit(vp);

@@ -1187,12 +1187,15 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
         V.tpan_gl = 5;
         if (pswf) {
             // t-quadrature from theta_1 = 5 (erfc(5) = 1.5e-12 bounds h beyond
-            // x = 1) on half-width panels; 20 fitted Gaussians
+            // x = 1), 10 nodes per panel of width <= 1.4 in log t (one panel
+            // up to t_a s_T = 20); 20 fitted Gaussians
             V.split = 1;
             V.sqL = 5.0;
-            V.tpan_w = 0.5;
+            V.tpan_gl = 10;
+            V.tpan_w = 1.4;
             V.nfit = 20;
-            if (V.nfit % VolLds<18, VQ>::JB) throw Error{DMK_ERR_STATE, "fitted Gaussians must fill whole passes"};
+            if (V.nfit % VolLds<18, VQ>::JB || V.tpan_gl % VolLds<18, VQ>::JB)
+                throw Error{DMK_ERR_STATE, "near-field Gaussians must fill whole passes"};
             V.fit_err = vol_sog_fit(P->tab, V.sqL, V.nfit, V.fit);
             if (!(V.fit_err < 2e-6)) throw Error{DMK_ERR_STATE, "sum-of-Gaussians fit of the residual failed"};
         } else {

@@ -248,7 +248,7 @@ def test_pswf_params(vp6):
     pr = O.params_for(TOL6)
     assert vp6.split == 1 and (vp6.p, vp6.nf) == (pr.p, pr.nf) == (18, 12)
     assert (vp6.nw, vp6.hw, vp6.c) == (pr.nw, pr.hw, pr.c)
-    assert vp6.tau_a == pytest.approx(20.0) and vp6.tpan_w == 0.5 and vp6.theta1 == 5.0
+    assert vp6.tau_a == pytest.approx(20.0) and (vp6.tpan_gl, vp6.tpan_w, vp6.theta1) == (10, 1.4, 5.0)
     assert vp6.nfit == 20 and vp6.fit_err < 1e-6
     with pytest.raises(ValueError):
         O.vparams_for(1e-4, 8)

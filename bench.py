@@ -177,13 +177,13 @@ def cpu_baseline(pts, q, ns, tol, seed=7):
 
 def cpu_baseline_vol(sig, cen, amp, feat, tol):
     """The volume oracle (plain FP64 C, OpenMP) on the same density with the
-    tree cut at level 3 (tol 1e-3) or 2 (tol 1e-6; same refinement rule
+    tree cut at level 4 (tol 1e-3) or 3 (tol 1e-6; same refinement rule
     otherwise): points/s of its eval phase."""
     import oracle
     import dmk_inputs
     vp = oracle.vparams_for(tol, 8)
     f = lambda x: dmk_inputs.gaussian_mixture(x, sig, cen, amp)
-    cut = 3 if tol == 1e-3 else 2  # about 15 s of eval either way
+    cut = 4 if tol == 1e-3 else 3  # 10 to 30 s of eval on 16 threads either way
     T = oracle.VTree(vp, f, vol_rho_scale(tol), 1, cut, features=feat)
     rho = f(T.nodes())
     t0 = time.perf_counter()

@@ -403,13 +403,14 @@ struct VolLds {
     static constexpr int up_work = (2 * P3 > Q3 + Q * Q * P + Q * P2) ? 2 * P3 : Q3 + Q * Q * P + Q * P2;
     static size_t up(size_t el) { return el * (2 * P2 + 2 * P * Q + up_work); }
     static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
-    static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel)
+    static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel at tol 1e-3)
+    static constexpr int JB6 = 10;  // the same at tol 1e-6 (30 or 40 Gaussians per pair)
     static constexpr int NB = 6;  // source densities staged per batch
     // NB source blocks, then a [q^2][q+1] regrouping buffer per wave; the
     // epilogue reuses them for the partial sums and the Laplacians
-    static size_t near(size_t el)
+    static size_t near(size_t el, int jb = JB)
     {
-        const size_t main = el * (NB * Q3 + JB * Q * Q * (Q + 1)), epi = sizeof(double) * (JB * Q3 + 3 * Q3 + Q * Q);
+        const size_t main = el * (NB * Q3 + jb * Q * Q * (Q + 1)), epi = sizeof(double) * (jb * Q3 + 3 * Q3 + Q * Q);
         return main > epi ? main : epi;
     }
 };
@@ -628,20 +629,16 @@ __global__ void __launch_bounds__(TPB) k_vol_tof32(const double *src, float *dst
 // (rows (i1 i2), then (a i2), then (a b)); a wave-private LDS buffer
 // regroups between passes.  The sources' densities are staged in LDS in
 // batches of NB.
-template <int Q>
-constexpr int vol_near_threads = Q * Q * 5;  // q^2 rows times the Gaussians of one panel
-
 // T: precision of the factor products and their sums (FP64, or FP32 for
 // mixed-precision plans); the asymptotic part and the output stay FP64.
-template <typename T, int Q>
-__global__ void __launch_bounds__(vol_near_threads<Q>)
+template <typename T, int Q, int JB>
+__global__ void __launch_bounds__(Q * Q * JB)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
                const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pk, const T *__restrict__ gtab,
                const double *__restrict__ gw)
 {
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, JB = VolLds<18, Q>::JB, NB = VolLds<18, Q>::NB, RS = Q + 1,
-                  NT = JB * Q2;
-    static_assert(NT == vol_near_threads<Q> && Q2 == 64, "one wavefront per Gaussian, one lane per row");
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, NB = VolLds<18, Q>::NB, RS = Q + 1, NT = JB * Q2;
+    static_assert(Q2 == 64, "one wavefront per Gaussian, one lane per row");
     extern __shared__ __align__(16) double vsm[];
     T *slot = reinterpret_cast<T *>(vsm);  // [NB][q^3] source densities
     T *wb = slot + NB * Q3;                // per wave: [q^2][RS] regrouping buffer
@@ -820,7 +817,8 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         vol_allow_lds(k_vol_upward<T, P, Q>, LD::up(sizeof(T)));
         vol_allow_lds(k_vol_upward_q<T, P, Q>, LD::up(sizeof(T)));
         vol_allow_lds(k_vol_leaf<T, P, Q>, LD::leaf(sizeof(T)));
-        vol_allow_lds(k_vol_near<T, Q>, LD::near(sizeof(T)));
+        vol_allow_lds(k_vol_near<T, Q, LD::JB>, LD::near(sizeof(T)));
+        vol_allow_lds(k_vol_near<T, Q, LD::JB6>, LD::near(sizeof(T), LD::JB6));
         attrs = true;
     }
     VDev<T> D = make_vdev<T>(Pl);
@@ -853,9 +851,14 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         D64.rho = rho;
         const VolData &V = Pl->vol;
         const T *gtab = sizeof(T) == 8 ? (const T *)V.d_gtab : (const T *)V.f_gtab;
-        const size_t lds_near = LD::near(sizeof(T));
-        hipLaunchKernelGGL((k_vol_near<T, Q>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB), lds_near, s, D64,
-                           Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey, gtab, V.d_gw);
+        if (V.split)  // 30 or 40 Gaussians per pair: ten waves share each staging of the sources
+            hipLaunchKernelGGL((k_vol_near<T, Q, LD::JB6>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB6),
+                               LD::near(sizeof(T), LD::JB6), s, D64, Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey,
+                               gtab, V.d_gw);
+        else
+            hipLaunchKernelGGL((k_vol_near<T, Q, LD::JB>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB),
+                               LD::near(sizeof(T)), s, D64, Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey, gtab,
+                               V.d_gw);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -1194,7 +1197,7 @@ dmk_plan_t make_vol_plan(double tol, int32_t q, double rho_scale, int32_t min_le
             V.tpan_gl = 10;
             V.tpan_w = 1.4;
             V.nfit = 20;
-            if (V.nfit % VolLds<18, VQ>::JB || V.tpan_gl % VolLds<18, VQ>::JB)
+            if (V.nfit % VolLds<18, VQ>::JB6 || V.tpan_gl % VolLds<18, VQ>::JB6)
                 throw Error{DMK_ERR_STATE, "near-field Gaussians must fill whole passes"};
             V.fit_err = vol_sog_fit(P->tab, V.sqL, V.nfit, V.fit);
             if (!(V.fit_err < 2e-6)) throw Error{DMK_ERR_STATE, "sum-of-Gaussians fit of the residual failed"};

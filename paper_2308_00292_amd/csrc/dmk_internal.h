@@ -97,6 +97,7 @@ struct VolData {
     double *d_fit = nullptr;
     int32_t *d_level = nullptr, *d_ijk = nullptr;
     int32_t *box2v = nullptr;            // [nbox] volume leaf of a leaf box, -1 otherwise
+    int32_t *d_esrc = nullptr;           // [gather entries] volume leaf of each entry's source
     double *d_v1 = nullptr;              // [2][p][q] density -> parent proxy matrices
     float *f_v1 = nullptr;
     double *d_xq = nullptr, *d_bq = nullptr;     // leaf nodes and barycentric weights

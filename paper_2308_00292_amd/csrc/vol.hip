@@ -634,8 +634,8 @@ __global__ void __launch_bounds__(TPB) k_vol_tof32(const double *src, float *dst
 template <typename T, int Q, int JB>
 __global__ void __launch_bounds__(Q * Q * JB)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
-               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ pk, const T *__restrict__ gtab,
-               const double *__restrict__ gw)
+               const int32_t *__restrict__ nl_src, const int32_t *__restrict__ esrc, const int32_t *__restrict__ pk,
+               const T *__restrict__ gtab, const double *__restrict__ gw)
 {
     constexpr int Q2 = Q * Q, Q3 = Q2 * Q, NB = VolLds<18, Q>::NB, RS = Q + 1, NT = JB * Q2;
     static_assert(Q2 == 64, "one wavefront per Gaussian, one lane per row");
@@ -676,7 +676,7 @@ __global__ void __launch_bounds__(Q * Q * JB)
                 __syncthreads();
                 for (int t = tid; t < nb * Q3; t += NT) {
                     const int sidx = t / Q3;
-                    slot[t] = (T)D.rho[(int64_t)D.box2v[nl_src[b0 + sidx]] * Q3 + t % Q3];
+                    slot[t] = (T)D.rho[(int64_t)esrc[b0 + sidx] * Q3 + t % Q3];
                 }
                 __syncthreads();
                 for (int sidx = 0; sidx < nb; ++sidx) {
@@ -853,12 +853,12 @@ void run_vol_t(Plan *Pl, const double *rho, double *u, double *fp, double *np, h
         const T *gtab = sizeof(T) == 8 ? (const T *)V.d_gtab : (const T *)V.f_gtab;
         if (V.split)  // 30 or 40 Gaussians per pair: ten waves share each staging of the sources
             hipLaunchKernelGGL((k_vol_near<T, Q, LD::JB6>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB6),
-                               LD::near(sizeof(T), LD::JB6), s, D64, Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey,
-                               gtab, V.d_gw);
+                               LD::near(sizeof(T), LD::JB6), s, D64, Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_esrc,
+                               V.d_pkey, gtab, V.d_gw);
         else
             hipLaunchKernelGGL((k_vol_near<T, Q, LD::JB>), dim3((unsigned)Pl->nleaf), dim3(Q * Q * LD::JB),
-                               LD::near(sizeof(T)), s, D64, Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_pkey, gtab,
-                               V.d_gw);
+                               LD::near(sizeof(T)), s, D64, Pl->l_leaf, Pl->nl_off, Pl->nl_src, V.d_esrc, V.d_pkey,
+                               gtab, V.d_gw);
     }
     {
         StageScope t(Pl, s, DMK_STAGE_FINALIZE);
@@ -1102,6 +1102,13 @@ void vol_count_work(Plan *P, hipStream_t s)
         return d;
     };
     V.d_pkey = upi(pkey);
+    {  // volume leaf of each entry's source, in the sorted order
+        std::vector<int32_t> b2v(nb), esrc(std::max<int64_t>(ne, 1), 0);
+        DMK_HIP(hipMemcpy(b2v.data(), V.box2v, nb * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t e = 0; e < ne; ++e) esrc[e] = b2v[src[e]];
+        V.d_esrc = (int32_t *)dalloc(P, esrc.size() * sizeof(int32_t));
+        DMK_HIP(hipMemcpy(V.d_esrc, esrc.data(), esrc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     V.d_kng = upi(kng);
     int32_t *d_kk = upi(kk);
     V.d_kbase = (int64_t *)dalloc(P, kbase.size() * sizeof(int64_t));

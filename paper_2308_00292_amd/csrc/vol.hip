@@ -405,7 +405,7 @@ struct VolLds {
     static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
     static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel at tol 1e-3)
     static constexpr int JB6 = 10;  // the same at tol 1e-6 (30 or 40 Gaussians per pair)
-    static constexpr int NB = 6;  // source densities staged per batch
+    static constexpr int NB = 9;  // source densities staged per batch (a z group of 9 colleagues in one)
     // NB source blocks, then a [q^2][q+1] regrouping buffer per wave; the
     // epilogue reuses them for the partial sums and the Laplacians
     static size_t near(size_t el, int jb = JB)

@@ -631,8 +631,10 @@ __global__ void __launch_bounds__(TPB) k_vol_tof32(const double *src, float *dst
 // batches of NB.
 // T: precision of the factor products and their sums (FP64, or FP32 for
 // mixed-precision plans); the asymptotic part and the output stay FP64.
+// FP32 with five waves per block: registers capped for seven waves per SIMD
+// (69 VGPRs instead of 82, no spills), so five blocks fit a CU as its LDS allows
 template <typename T, int Q, int JB>
-__global__ void __launch_bounds__(Q * Q * JB)
+__global__ void __launch_bounds__(Q * Q * JB, (sizeof(T) == 4 && JB == 5) ? 7 : 1)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
                const int32_t *__restrict__ nl_src, const int32_t *__restrict__ esrc, const int32_t *__restrict__ pk,
                const T *__restrict__ gtab, const double *__restrict__ gw)

@@ -405,12 +405,14 @@ struct VolLds {
     static size_t leaf(size_t el) { return el * (P3 + P2 * Q + P * Q * Q + 3 * Q * P + 2 * P); }
     static constexpr int JB = 5;  // Gaussians per pass of the near-field kernel (one panel at tol 1e-3)
     static constexpr int JB6 = 10;  // the same at tol 1e-6 (30 or 40 Gaussians per pair)
-    static constexpr int NB = 9;  // source densities staged per batch (a z group of 9 colleagues in one)
+    // source densities staged per batch: seven with five waves (FP32: six
+    // blocks per CU), nine with ten (a z group of nine colleagues in one batch)
+    static constexpr int nb(int jb) { return jb == 5 ? 7 : 9; }
     // NB source blocks, then a [q^2][q+1] regrouping buffer per wave; the
     // epilogue reuses them for the partial sums and the Laplacians
     static size_t near(size_t el, int jb = JB)
     {
-        const size_t main = el * (NB * Q3 + jb * Q * Q * (Q + 1)), epi = sizeof(double) * (jb * Q3 + 3 * Q3 + Q * Q);
+        const size_t main = el * (nb(jb) * Q3 + jb * Q * Q * (Q + 1)), epi = sizeof(double) * (jb * Q3 + 3 * Q3 + Q * Q);
         return main > epi ? main : epi;
     }
 };
@@ -631,15 +633,15 @@ __global__ void __launch_bounds__(TPB) k_vol_tof32(const double *src, float *dst
 // batches of NB.
 // T: precision of the factor products and their sums (FP64, or FP32 for
 // mixed-precision plans); the asymptotic part and the output stay FP64.
-// FP32 with five waves per block: registers capped for seven waves per SIMD
-// (69 VGPRs instead of 82, no spills), so five blocks fit a CU as its LDS allows
+// FP32 with five waves per block: registers capped for eight waves per SIMD
+// (62 VGPRs instead of 82, no spills), so six blocks fit a CU as its LDS allows
 template <typename T, int Q, int JB>
-__global__ void __launch_bounds__(Q * Q * JB, (sizeof(T) == 4 && JB == 5) ? 7 : 1)
+__global__ void __launch_bounds__(Q * Q * JB, (sizeof(T) == 4 && JB == 5) ? 8 : 1)
     k_vol_near(VDev<double> D, const int32_t *__restrict__ leaves, const int32_t *__restrict__ nl_off,
                const int32_t *__restrict__ nl_src, const int32_t *__restrict__ esrc, const int32_t *__restrict__ pk,
                const T *__restrict__ gtab, const double *__restrict__ gw)
 {
-    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, NB = VolLds<18, Q>::NB, RS = Q + 1, NT = JB * Q2;
+    constexpr int Q2 = Q * Q, Q3 = Q2 * Q, NB = VolLds<18, Q>::nb(JB), RS = Q + 1, NT = JB * Q2;
     static_assert(Q2 == 64, "one wavefront per Gaussian, one lane per row");
     extern __shared__ __align__(16) double vsm[];
     T *slot = reinterpret_cast<T *>(vsm);  // [NB][q^3] source densities
